@@ -1,0 +1,216 @@
+/*
+ * sqngd.h - C ABI of libsqngd.so, the gfx950 hot path of SQNGD (joint design
+ * of Doppler-resilient unimodular discrete-phase MIMO radar waveforms and
+ * mismatched receive filters, arXiv 2604.25728).
+ *
+ * What the library computes (paper Sec. II and Sec. III-B/C):
+ *   - the discrete ambiguity function A_ml(tau, f) of every waveform s_m against
+ *     every receive filter h_l, m,l in [0,M), over all delays
+ *     tau in [-(N-1), N-1] and a uniform Doppler grid (Sec. II-A, eq. 6),
+ *     evaluated as a zero-padded FFT correlation per Doppler bin (eq. 33-36);
+ *   - the sidelobe loss over the delay-Doppler region of interest: auto pairs
+ *     exclude tau = 0, cross pairs keep every tau (eq. 7-9); the max of eq. 37
+ *     is replaced by the p-norm L_p = (sum a^p)^(1/p), a = |A|/N, while the
+ *     exact maxima are reported as PSL (eq. 48);
+ *   - the SNR-loss penalty L_SNRL = (1/M) sum_m (p_m - p_tar)^2 with
+ *     p_m = |h_m^H s_m| / N and p_tar = 10^(-mu/20) (eq. 38-41), and the total
+ *     loss L = w_psl * L_p + w_snrl * L_SNRL (eq. 42);
+ *   - the gradient of L with respect to the soft-quantisation logits and the
+ *     filters (the differentiable AF module of Sec. III-B);
+ *   - one outer iteration of the alternating optimiser of Sec. III-C /
+ *     Algorithm 1: Adam on the filters against the hard waveform followed by
+ *     the energy projection (eq. 31-32), then Adam on the logits against the
+ *     soft waveform.
+ *
+ * Transmit parameterisation. Each chip (m, n) carries L real logits z[m][n][:]
+ * (L is the paper's phase-alphabet size B). The hard waveform is
+ * x = exp(j 2 pi l* / L) with l* = argmax_l z (ties go to the lowest l), the
+ * discrete-phase set of eq. 5. The soft waveform uses pi = softmax(z / T):
+ *   SQNGD_SQ_PHASE_MEAN  (default): s = exp(j 2 pi (sum_l l pi_l) / L), which
+ *                         stays unimodular like the soft waveform of eq. 23;
+ *   SQNGD_SQ_PHASOR_MEAN:  s = sum_l pi_l exp(j 2 pi l / L) (not unimodular).
+ *
+ * Conventions.
+ *   - Indices are 0-based (the paper counts from 1; |A|, every loss and every
+ *     gradient are unchanged by the shift).
+ *   - Complex data is interleaved sqngd_c64 (re, im), layout-identical to a
+ *     HIP float2, 8-byte aligned.
+ *   - z is [M][N][L] with L fastest; waveforms, filters and their gradients
+ *     are [M][N]; an AF cube is [M][M][F][2N-1] with tau fastest at index
+ *     tau + N - 1.
+ *   - Gradients of the real loss with respect to a complex variable v are
+ *     packed as dL/dRe(v) + j dL/dIm(v), the pair that Adam on (H_Re, H_Im)
+ *     consumes (eq. 26-28).
+ *   - Doppler grid: nu_f = nu_min + f (nu_max - nu_min) / (F - 1) for
+ *     f in [0, F) (nu_f = nu_min when F = 1); the modulation is
+ *     exp(j 2 pi n nu_f / N) (eq. 33).
+ *   - Batches: the nprob problems of one call are packed back to back in
+ *     every buffer in problem order: problem i owns M_i*N_i*L_i floats of z
+ *     (and of grad_z), M_i*N_i complex values of h, s, x, grad_h, grad_s and
+ *     M_i*N_i int32 of idx, M_i*M_i*F_i*(2N_i-1) complex values of af_cube,
+ *     SQNGD_ADAM_FLOATS(M_i,N_i,L_i) floats of adam_state and one sqngd_stats
+ *     (two for sqngd_step, see there). sqngd_buffer_sizes() returns the totals.
+ *
+ * Ownership and memory. Every array argument is a DEVICE pointer owned by the
+ * caller; problem descriptors and options are HOST pointers read during the
+ * call. The library never allocates or frees memory and keeps no per-call
+ * state: scratch lives in the caller's workspace (size from
+ * sqngd_workspace_size, 256-byte aligned). Calls only enqueue work on
+ * `stream` (a hipStream_t passed as void*; NULL is the null stream), are
+ * asynchronous and stream-ordered, and issue no memset, so they can be
+ * captured in a HIP graph. Two calls that share a workspace must not overlap.
+ *
+ * Errors. Every argument is validated on the host before any HIP call, so a
+ * bad call returns a negative status without touching the device:
+ *   SQNGD_E_INVALID_ARG  shape, p, weight or mode out of range; NULL required
+ *                        pointer;
+ *   SQNGD_E_UNSUPPORTED  N above 1024 (the FFT length 2^ceil(log2(2N-1)) would
+ *                        exceed 2048), M above 16 or L above 64;
+ *   SQNGD_E_WORKSPACE    ws_bytes smaller than sqngd_workspace_size;
+ *   SQNGD_E_ALIGN        a pointer not aligned as stated above;
+ *   SQNGD_E_HIP          a HIP launch failed (sqngd_last_hip_error() keeps
+ *                        the hipError_t).
+ * Numerical trouble is not a status: a non-finite loss or gradient sets
+ * stats.nonfinite, and sqngd_step then skips that problem's update.
+ */
+#ifndef SQNGD_H
+#define SQNGD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SQNGD_OK 0
+#define SQNGD_E_INVALID_ARG (-1)
+#define SQNGD_E_UNSUPPORTED (-2)
+#define SQNGD_E_WORKSPACE (-3)
+#define SQNGD_E_ALIGN (-4)
+#define SQNGD_E_HIP (-5)
+
+/* waveform source for sqngd_af_forward / sqngd_af_backward */
+#define SQNGD_WAVE_SOFT 0  /* soft-quantised from z at problem.temperature */
+#define SQNGD_WAVE_HARD 1  /* hard-quantised from z (argmax)              */
+#define SQNGD_WAVE_GIVEN 2 /* s_given, any complex sequence              */
+
+/* soft quantiser */
+#define SQNGD_SQ_PHASE_MEAN 0
+#define SQNGD_SQ_PHASOR_MEAN 1
+
+/* sqngd_opt.flags */
+#define SQNGD_OPT_SGD 1      /* plain gradient descent instead of Adam       */
+#define SQNGD_OPT_FREEZE_H 2 /* skip step A: filters stay fixed (SQNAF mode) */
+
+/* floats of Adam state per problem: first and second moments of z (2*M*N*L)
+   and of (Re h, Im h) (4*M*N) */
+#define SQNGD_ADAM_FLOATS(M, N, L) (2 * (int64_t)(M) * (N) * (L) + 4 * (int64_t)(M) * (N))
+
+typedef struct {
+  float re, im;
+} sqngd_c64;
+
+/* One design problem: the inputs of Algorithm 1 (M, N, B, Doppler grid, ROI,
+   weighting, SNRL target) plus the p of the p-norm surrogate. 64 bytes. */
+typedef struct {
+  int32_t M;              /* waveforms = receive filters, 1..16                  */
+  int32_t N;              /* chips per waveform, 2..1024                         */
+  int32_t L;              /* phase levels (paper B), 2..64                       */
+  int32_t F;              /* Doppler bins, >= 1                                  */
+  float nu_min, nu_max;   /* Doppler span (normalised as in eq. 6), nu_min<=nu_max */
+  int32_t tau_lo, tau_hi; /* delay ROI, -(N-1) <= tau_lo <= tau_hi <= N-1        */
+  float p;                /* sidelobe exponent, 2 <= p <= 64                     */
+  float snrl_target_db;   /* mu of eq. 39, >= 0                                  */
+  float w_psl, w_snrl;    /* loss weights of eq. 42 (paper: eps, 1-eps), >= 0    */
+  float temperature;      /* softmax temperature T > 0 (SOFT mode)               */
+  int32_t sq_mode;        /* SQNGD_SQ_PHASE_MEAN | SQNGD_SQ_PHASOR_MEAN           */
+  int32_t reserved[2];    /* must be 0                                           */
+} sqngd_problem;
+
+/* Optimiser options of one outer iteration (Algorithm 1). */
+typedef struct {
+  float lr_z, lr_h;       /* step sizes of the logit and filter updates      */
+  float beta1, beta2, eps; /* Adam moments and denominator guard              */
+  int32_t n_h, n_x;       /* inner steps A and B per outer iteration, >= 0   */
+  float T0, T1;           /* temperature schedule T_t = T0 (T1/T0)^(t/(I-1)) */
+  int32_t total_iters;    /* I, >= 1                                          */
+  int32_t flags;          /* SQNGD_OPT_*                                      */
+} sqngd_opt;
+
+/* Per-problem statistics written by the device. 64 bytes. */
+typedef struct {
+  float loss;        /* w_psl * lp + w_snrl * l_snrl (eq. 42)                    */
+  float lp;          /* (sum over the ROI of a^p)^(1/p), a = |A|/N              */
+  float l_snrl;      /* eq. 41                                                   */
+  float psl_auto;    /* max |A| over auto pairs, tau != 0 (eq. 8, w = 1)         */
+  float psl_cross;   /* max |A| over cross pairs (eq. 9, w = 1)                  */
+  float pslr_db;     /* 20 log10(max(psl_auto, psl_cross) / N)  (eq. 48)         */
+  float snrl_db_max; /* max over m of 10 log10(|s|^2 |h|^2 / |h^H s|^2) (eq. 10) */
+  float p_min;       /* min over m of |h_m^H s_m| / N (eq. 38)                   */
+  int32_t arg_m, arg_l, arg_tau, arg_f; /* location of the larger PSL            */
+  uint32_t nonfinite; /* nonzero when a loss or gradient value was not finite    */
+  int32_t reserved[3];
+} sqngd_stats;
+
+/* Total element counts of the packed buffers of a batch (see Conventions).
+   Any output pointer may be NULL. Returns SQNGD_OK or SQNGD_E_INVALID_ARG. */
+int sqngd_buffer_sizes(const sqngd_problem* probs, int32_t nprob, int64_t* z_floats,
+                       int64_t* wave_c64, int64_t* adam_floats, int64_t* cube_c64);
+
+/* Workspace bytes every entry point needs for this batch. */
+int sqngd_workspace_size(const sqngd_problem* probs, int32_t nprob, size_t* bytes);
+
+/* Loss and statistics of one evaluation (Sec. III-B: eq. 33-36 for the AF,
+   eq. 37-42 for the loss, eq. 48 for PSLR).
+   z        logits, read for wave_mode SOFT/HARD (may be NULL for GIVEN);
+   s_given  waveforms, read for wave_mode GIVEN (may be NULL otherwise);
+   h        filters;
+   stats    nprob entries, written;
+   af_cube  NULL, or the full cube written for inspection (not on the hot path). */
+int sqngd_af_forward(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t wave_mode,
+                     const sqngd_c64* s_given, const sqngd_c64* h, sqngd_stats* stats,
+                     sqngd_c64* af_cube, void* ws, size_t ws_bytes, void* stream);
+
+/* Gradient of grad_loss[i] * loss_i (the differentiable AF module of
+   Sec. III-B) with respect to the logits (through the soft or hard waveform:
+   the hard waveform has zero gradient), the filters and the waveforms.
+   grad_loss  nprob floats on the device, or NULL for 1;
+   grad_z, grad_h, grad_s  outputs, each may be NULL when not wanted (grad_z
+              is only defined for SOFT mode; HARD writes zeros);
+   stats      nprob entries written as by sqngd_af_forward (may be NULL). */
+int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t wave_mode,
+                      const sqngd_c64* s_given, const sqngd_c64* h, const float* grad_loss,
+                      float* grad_z, sqngd_c64* grad_h, sqngd_c64* grad_s, sqngd_stats* stats,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* One outer iteration t of Algorithm 1 for every problem of the batch:
+   n_h times { hard waveform from z; loss and grad_h; Adam on (Re h, Im h);
+   h_m <- h_m sqrt(N / |h_m|^2) (eq. 32) }, then n_x times { soft waveform from
+   z at T_t; loss and grad_z; Adam on z }, then *step_counter += 1.
+   z, h, adam_state are updated in place; step_counter is ONE device int32
+   shared by the batch (t, starting at 0); stats holds 2*nprob entries: [i] is
+   the last step-A evaluation of problem i (hard waveform, filters before that
+   update) and [nprob + i] the last step-B evaluation (soft waveform). A problem
+   whose evaluation is not finite keeps its parameters for that inner step. */
+int sqngd_step(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, float* z,
+               sqngd_c64* h, float* adam_state, int32_t* step_counter, sqngd_stats* stats, void* ws,
+               size_t ws_bytes, void* stream);
+
+/* Hard quantisation (the final stage of Algorithm 1): idx[m][n] = argmax_l
+   z[m][n][l] with ties to the lowest l, and (if x is not NULL)
+   x = exp(j 2 pi idx / L). */
+int sqngd_hard_quantize(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t* idx,
+                        sqngd_c64* x, void* stream);
+
+/* Human-readable text of a status code. */
+const char* sqngd_status_string(int status);
+
+/* hipError_t of the last SQNGD_E_HIP (0 if none). */
+int sqngd_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SQNGD_H */

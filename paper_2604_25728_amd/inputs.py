@@ -1,0 +1,115 @@
+"""Seeded synthetic inputs and the workload presets.
+
+This module holds no arithmetic of the method: it only draws random numbers
+and states shapes and hyper-parameters. Both the GPU path and the oracle take
+their inputs from here.
+
+Workloads. The paper uses no dataset: its designs start from random phases
+(Algorithm 1, initialisation). The presets below are the five workloads this
+implementation is measured and checked on:
+
+  c1  M=2, N=64, L=4, F=33 over nu in [-0.5, 0.5], p=8, 200 iterations at
+      step 1e-2, temperature 1.0 (small enough for the oracle to run whole);
+  c2  M=4, N=256, L=8, F=129 over [-0.5, 0.5], p=16, SNRL target 0.5 dB,
+      temperature annealed 1.0 -> 0.05 over 2000 iterations, step 1e-2;
+  c3  64 designs with N in {128, 256, 512, 1024}, M in {2, 4, 8},
+      L in {4, 8, 16}, F=129, 8 random restarts each, c2's schedule;
+  c4  M=8, N=1024, L=16, F=257 over the wide span [-2.5, 2.5], p=16,
+      5000 iterations;
+  c5  M=4, N=512, L=8, F=129 over [-0.5, 0.5], p=16 (the warm-start
+      network's design size).
+
+Every delay is in the region of interest, SNRL target 0.5 dB, loss weights
+w_psl = w_snrl = 1, Adam with beta = (0.9, 0.999), eps = 1e-8 and one step A
+plus one step B per outer iteration, unless a preset says otherwise.
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+
+PHASE_MEAN = 0
+PHASOR_MEAN = 1
+
+
+def make_problem(M: int, N: int, L: int, F: int, nu_min: float = -0.5, nu_max: float = 0.5,
+                 p: float = 16.0, snrl_target_db: float = 0.5, w_psl: float = 1.0,
+                 w_snrl: float = 1.0, temperature: float = 1.0, sq_mode: int = PHASE_MEAN,
+                 tau_lo: int | None = None, tau_hi: int | None = None) -> dict:
+    """A problem dict with every delay in the region of interest by default."""
+    return {
+        "M": int(M), "N": int(N), "L": int(L), "F": int(F),
+        "nu_min": float(nu_min), "nu_max": float(nu_max),
+        "tau_lo": int(-(N - 1) if tau_lo is None else tau_lo),
+        "tau_hi": int((N - 1) if tau_hi is None else tau_hi),
+        "p": float(p), "snrl_target_db": float(snrl_target_db),
+        "w_psl": float(w_psl), "w_snrl": float(w_snrl),
+        "temperature": float(temperature), "sq_mode": int(sq_mode),
+    }
+
+
+def make_opt(lr_z: float = 1e-2, lr_h: float = 1e-2, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8, n_h: int = 1, n_x: int = 1, T0: float = 1.0, T1: float = 1.0,
+             total_iters: int = 1, flags: int = 0) -> dict:
+    return {"lr_z": float(lr_z), "lr_h": float(lr_h), "beta1": float(beta1),
+            "beta2": float(beta2), "eps": float(eps), "n_h": int(n_h), "n_x": int(n_x),
+            "T0": float(T0), "T1": float(T1), "total_iters": int(total_iters),
+            "flags": int(flags)}
+
+
+CONFIGS = {
+    "c1": {"problem": make_problem(2, 64, 4, 33, p=8.0),
+           "opt": make_opt(total_iters=200, T0=1.0, T1=1.0)},
+    "c2": {"problem": make_problem(4, 256, 8, 129, p=16.0),
+           "opt": make_opt(total_iters=2000, T0=1.0, T1=0.05)},
+    "c4": {"problem": make_problem(8, 1024, 16, 257, nu_min=-2.5, nu_max=2.5, p=16.0),
+           "opt": make_opt(total_iters=5000, T0=1.0, T1=0.05)},
+    "c5": {"problem": make_problem(4, 512, 8, 129, p=16.0),
+           "opt": make_opt(total_iters=2000, T0=1.0, T1=0.05)},
+}
+
+
+def config(name: str) -> dict:
+    """A deep copy of a preset: {"problem": ..., "opt": ...}."""
+    return copy.deepcopy(CONFIGS[name])
+
+
+def c3_designs(n_designs: int = 64, restarts: int = 8, draw_seed: int = 12345):
+    """The uneven batch: (problem, seed) for every design and restart. Shapes
+    come from their own generator; restart r of design d uses seed 1000 d + r."""
+    rng = np.random.default_rng(draw_seed)
+    out = []
+    for d in range(n_designs):
+        N = int(rng.choice([128, 256, 512, 1024]))
+        M = int(rng.choice([2, 4, 8]))
+        L = int(rng.choice([4, 8, 16]))
+        prob = make_problem(M, N, L, 129, p=16.0)
+        for r in range(restarts):
+            out.append((prob, 1000 * d + r))
+    return out
+
+
+def logits(M: int, N: int, L: int, seed: int) -> np.ndarray:
+    """z ~ N(0, 1) i.i.d., drawn in float64 in [M][N][L] order, rounded to float32."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((M, N, L)).astype(np.float32)
+
+
+def complex_gaussian(M: int, N: int, seed: int) -> np.ndarray:
+    """A complex [M][N] sequence with i.i.d. N(0, 1/2) parts, rounded to complex64."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((M, N, 2)) * np.sqrt(0.5)
+    return (a[..., 0] + 1j * a[..., 1]).astype(np.complex64)
+
+
+def unimodular(M: int, N: int, seed: int) -> np.ndarray:
+    """Random continuous phases e^{j 2 pi u}, u ~ U[0, 1), rounded to complex64."""
+    rng = np.random.default_rng(seed)
+    return np.exp(2j * np.pi * rng.random((M, N))).astype(np.complex64)
+
+
+def noise(M: int, N: int, seed: int) -> np.ndarray:
+    """The warm-start network's input noise, N(0, 1) [M][N] float32."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((M, N)).astype(np.float32)

@@ -53,11 +53,16 @@
  *
  * Ownership and memory. Every array argument is a DEVICE pointer owned by the
  * caller; problem descriptors and options are HOST pointers read during the
- * call. The library never allocates or frees memory and keeps no per-call
- * state: scratch lives in the caller's workspace (size from
- * sqngd_workspace_size, 256-byte aligned). Calls only enqueue work on
- * `stream` (a hipStream_t passed as void*; NULL is the null stream), are
- * asynchronous and stream-ordered, and issue no memset, so they can be
+ * call. The library never allocates device memory. Scratch lives in the
+ * caller's workspace (size from sqngd_workspace_size, 256-byte aligned), which
+ * sqngd_workspace_init prepares once per batch: it uploads the batch plan
+ * (problem descriptors, buffer offsets, work tables) into the workspace with
+ * one host-to-device copy from a host buffer the library keeps until the
+ * process ends. Every later call checks on the host that it names the same
+ * batch as the last initialisation of that workspace, and the caller must not
+ * write into the workspace meanwhile. Calls only enqueue work on `stream` (a
+ * hipStream_t passed as void*; NULL is the null stream), are asynchronous and
+ * stream-ordered, and issue no memset, so after the initialisation they can be
  * captured in a HIP graph. Two calls that share a workspace must not overlap.
  *
  * Errors. Every argument is validated on the host before any HIP call, so a
@@ -65,8 +70,10 @@
  *   SQNGD_E_INVALID_ARG  shape, p, weight or mode out of range; NULL required
  *                        pointer;
  *   SQNGD_E_UNSUPPORTED  N above 1024 (the FFT length 2^ceil(log2(2N-1)) would
- *                        exceed 2048), M above 16 or L above 64;
- *   SQNGD_E_WORKSPACE    ws_bytes smaller than sqngd_workspace_size;
+ *                        exceed 2048), M above 16, L above 64, F above 4096,
+ *                        or M*M*F*P >= 2^32 (P the FFT length);
+ *   SQNGD_E_WORKSPACE    ws_bytes smaller than sqngd_workspace_size, or the
+ *                        workspace was not initialised for this batch;
  *   SQNGD_E_ALIGN        a pointer not aligned as stated above;
  *   SQNGD_E_HIP          a HIP launch failed (sqngd_last_hip_error() keeps
  *                        the hipError_t).
@@ -161,6 +168,13 @@ int sqngd_buffer_sizes(const sqngd_problem* probs, int32_t nprob, int64_t* z_flo
 /* Workspace bytes every entry point needs for this batch. */
 int sqngd_workspace_size(const sqngd_problem* probs, int32_t nprob, size_t* bytes);
 
+/* Prepares ws for this batch (see Ownership and memory): enqueues the upload
+   of the batch plan and the reset of the step bookkeeping on stream. Required
+   before any other call that takes this workspace, and again after the batch
+   changes. */
+int sqngd_workspace_init(const sqngd_problem* probs, int32_t nprob, void* ws, size_t ws_bytes,
+                         void* stream);
+
 /* Loss and statistics of one evaluation (Sec. III-B: eq. 33-36 for the AF,
    eq. 37-42 for the loss, eq. 48 for PSLR).
    z        logits, read for wave_mode SOFT/HARD (may be NULL for GIVEN);
@@ -199,9 +213,9 @@ int sqngd_step(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, 
 
 /* Hard quantisation (the final stage of Algorithm 1): idx[m][n] = argmax_l
    z[m][n][l] with ties to the lowest l, and (if x is not NULL)
-   x = exp(j 2 pi idx / L). */
+   x = exp(j 2 pi idx / L). Either output may be NULL. */
 int sqngd_hard_quantize(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t* idx,
-                        sqngd_c64* x, void* stream);
+                        sqngd_c64* x, void* ws, size_t ws_bytes, void* stream);
 
 /* Human-readable text of a status code. */
 const char* sqngd_status_string(int status);

@@ -1,0 +1,594 @@
+// api.hip - host side of libsqngd.so: argument validation, the batch plan
+// kept in the caller's workspace, and the launch sequences of the C ABI
+// declared in include/sqngd.h.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.hip"
+
+using namespace sq;
+
+namespace {
+
+std::atomic<int> g_last_hip{0};
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int fft_len(int N) {
+  int P = 128;
+  while (P < 2 * N - 1) P *= 2;
+  return P;
+}
+int log2i(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+bool finite(float v) { return std::isfinite(v); }
+
+int validate_problem(const sqngd_problem& p) {
+  if (p.M < 1 || p.N < 2 || p.L < 2 || p.F < 1) return SQNGD_E_INVALID_ARG;
+  if (p.M > 16 || p.N > 1024 || p.L > 64 || p.F > 4096) return SQNGD_E_UNSUPPORTED;
+  const double P = fft_len(p.N);
+  if ((double)p.M * p.M * p.F * P >= 4294967296.0) return SQNGD_E_UNSUPPORTED;
+  if (!finite(p.nu_min) || !finite(p.nu_max) || p.nu_min > p.nu_max) return SQNGD_E_INVALID_ARG;
+  if (p.tau_lo < -(p.N - 1) || p.tau_hi > p.N - 1 || p.tau_lo > p.tau_hi) return SQNGD_E_INVALID_ARG;
+  if (!finite(p.p) || p.p < 2.0f || p.p > 64.0f) return SQNGD_E_INVALID_ARG;
+  if (!finite(p.snrl_target_db) || p.snrl_target_db < 0.0f) return SQNGD_E_INVALID_ARG;
+  if (!finite(p.w_psl) || !finite(p.w_snrl) || p.w_psl < 0.0f || p.w_snrl < 0.0f) return SQNGD_E_INVALID_ARG;
+  if (!finite(p.temperature) || p.temperature <= 0.0f) return SQNGD_E_INVALID_ARG;
+  if (p.sq_mode != SQNGD_SQ_PHASE_MEAN && p.sq_mode != SQNGD_SQ_PHASOR_MEAN) return SQNGD_E_INVALID_ARG;
+  if (p.reserved[0] != 0 || p.reserved[1] != 0) return SQNGD_E_INVALID_ARG;
+  return SQNGD_OK;
+}
+
+int validate_batch(const sqngd_problem* probs, int32_t nprob) {
+  if (probs == nullptr || nprob < 1 || nprob > (1 << 20)) return SQNGD_E_INVALID_ARG;
+  for (int i = 0; i < nprob; ++i) {
+    int rc = validate_problem(probs[i]);
+    if (rc != SQNGD_OK) return rc;
+  }
+  return SQNGD_OK;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// Host copy of a batch plan: the bytes uploaded to the start of the workspace.
+struct Plan {
+  WsHeader hdr{};
+  std::vector<char> bytes;  // [0, hdr.spec): header, plans, tables
+  std::vector<ProbPlan> plans;
+  int group_phlog[kNumPGroups];
+  uint64_t hash = 0;
+};
+
+uint64_t fnv1a(const void* data, size_t n) {
+  const unsigned char* c = (const unsigned char*)data;
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
+  auto pl = std::make_unique<Plan>();
+  WsHeader& H = pl->hdr;
+  H.magic = kWsMagic;
+  H.nprob = nprob;
+  pl->plans.resize(nprob);
+  std::vector<int> gprob[kNumPGroups];
+  int64_t off_z = 0, off_w = 0, off_state = 0, off_cube = 0, spec = 0, unit = 0, upart = 0;
+  int rows = 0;
+  for (int i = 0; i < nprob; ++i) {
+    const sqngd_problem& p = probs[i];
+    ProbPlan& q = pl->plans[i];
+    std::memset(&q, 0, sizeof(q));
+    q.M = p.M;
+    q.N = p.N;
+    q.L = p.L;
+    q.F = p.F;
+    q.P = fft_len(p.N);
+    q.logP = log2i(q.P);
+    q.tau_lo = p.tau_lo;
+    q.tau_hi = p.tau_hi;
+    q.nu_min = p.nu_min;
+    q.dnu = p.F > 1 ? (float)(((double)p.nu_max - (double)p.nu_min) / (double)(p.F - 1)) : 0.0f;
+    q.p = p.p;
+    q.p_tar = (float)std::pow(10.0, -(double)p.snrl_target_db / 20.0);
+    q.w_psl = p.w_psl;
+    q.w_snrl = p.w_snrl;
+    q.temperature = p.temperature;
+    q.inv_NP = (float)(1.0 / ((double)p.N * (double)q.P));
+    q.sq_mode = p.sq_mode;
+    q.ph_log = -1;
+    for (int k = 0; k <= 5; ++k)
+      if (p.p == 2.0f * (float)(1 << k)) q.ph_log = k;
+    q.units = p.M * p.F;
+    q.row0 = rows;
+    q.off_z = off_z;
+    q.off_w = off_w;
+    q.off_state = off_state;
+    q.off_cube = off_cube;
+    q.ws_spec = spec;
+    q.ws_unit = unit;
+    q.ws_upart = upart;
+    off_z += (int64_t)p.M * p.N * p.L;
+    off_w += (int64_t)p.M * p.N;
+    off_state += SQNGD_ADAM_FLOATS(p.M, p.N, p.L);
+    off_cube += (int64_t)p.M * p.M * p.F * (2 * p.N - 1);
+    spec += (int64_t)p.M * q.P;
+    unit += q.units;
+    upart += (int64_t)q.units * p.N;
+    rows += p.M;
+    gprob[q.logP - kMinLogP].push_back(i);
+  }
+  H.nrows = rows;
+  // table region
+  size_t off = align_up(sizeof(WsHeader));
+  H.plans = (int64_t)off;
+  off = align_up(off + sizeof(ProbPlan) * nprob);
+  std::vector<std::vector<int32_t>> wave(kNumPGroups), rwave(kNumPGroups);
+  for (int g = 0; g < kNumPGroups; ++g) {
+    const int P = 1 << (g + kMinLogP);
+    const int TF = P >= 512 ? 64 : P / 8;
+    const int slots = 64 / TF;
+    H.group_n[g] = (int32_t)gprob[g].size();
+    int wsum = 0, rsum = 0;
+    int phl = -2;
+    for (int id : gprob[g]) {
+      wave[g].push_back(wsum);
+      rwave[g].push_back(rsum);
+      wsum += (pl->plans[id].units + slots - 1) / slots;
+      rsum += (pl->plans[id].M + slots - 1) / slots;
+      phl = (phl == -2 || phl == pl->plans[id].ph_log) ? pl->plans[id].ph_log : -1;
+    }
+    wave[g].push_back(wsum);
+    rwave[g].push_back(rsum);
+    H.group_waves[g] = wsum;
+    H.group_rwaves[g] = rsum;
+    pl->group_phlog[g] = phl;
+    H.group_prob[g] = (int64_t)off;
+    off = align_up(off + 4 * gprob[g].size());
+    H.group_wave[g] = (int64_t)off;
+    off = align_up(off + 4 * wave[g].size());
+    H.group_rwave[g] = (int64_t)off;
+    off = align_up(off + 4 * rwave[g].size());
+  }
+  H.row_prob = (int64_t)off;
+  off = align_up(off + 4 * (size_t)rows);
+  H.counters = (int64_t)off;
+  off = align_up(off + 4 * kNumCounters);
+  const size_t table_bytes = off;
+  H.spec = (int64_t)off;
+  off = align_up(off + 8 * (size_t)spec);
+  H.wself = (int64_t)off;
+  off = align_up(off + 8 * (size_t)off_w);
+  H.wpart = (int64_t)off;
+  off = align_up(off + 8 * (size_t)off_w);
+  H.ustat = (int64_t)off;
+  off = align_up(off + sizeof(UnitStat) * (size_t)unit);
+  H.upart = (int64_t)off;
+  off = align_up(off + 8 * (size_t)upart);
+  H.snrl = (int64_t)off;
+  off = align_up(off + 16 * (size_t)rows);
+  H.total = (int64_t)off;
+
+  pl->bytes.assign(table_bytes, 0);
+  char* b = pl->bytes.data();
+  std::memcpy(b + H.plans, pl->plans.data(), sizeof(ProbPlan) * nprob);
+  for (int g = 0; g < kNumPGroups; ++g) {
+    if (!gprob[g].empty()) std::memcpy(b + H.group_prob[g], gprob[g].data(), 4 * gprob[g].size());
+    std::memcpy(b + H.group_wave[g], wave[g].data(), 4 * wave[g].size());
+    std::memcpy(b + H.group_rwave[g], rwave[g].data(), 4 * rwave[g].size());
+  }
+  std::vector<int32_t> rp(rows);
+  for (int i = 0; i < nprob; ++i)
+    for (int m = 0; m < probs[i].M; ++m) rp[pl->plans[i].row0 + m] = i;
+  std::memcpy(b + H.row_prob, rp.data(), 4 * rp.size());
+  std::memcpy(b, &H, sizeof(WsHeader));
+  pl->hash = fnv1a(b, table_bytes);
+  return pl;
+}
+
+// Workspace registry: which batch each workspace was last initialised for.
+// Plans are never freed, so an upload still in flight always reads live memory.
+std::mutex g_mu;
+std::vector<std::unique_ptr<Plan>> g_keep;
+std::unordered_map<const void*, Plan*> g_ws;
+
+int hip_fail(hipError_t e) {
+  g_last_hip.store((int)e);
+  return SQNGD_E_HIP;
+}
+
+int check_launch() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SQNGD_OK : hip_fail(e);
+}
+
+// Validates the batch and the workspace; on success *out is the plan the
+// workspace holds.
+int lookup(const sqngd_problem* probs, int32_t nprob, void* ws, size_t ws_bytes, const Plan** out) {
+  int rc = validate_batch(probs, nprob);
+  if (rc != SQNGD_OK) return rc;
+  if (ws == nullptr) return SQNGD_E_INVALID_ARG;
+  if (!aligned(ws, kAlign)) return SQNGD_E_ALIGN;
+  auto fresh = build_plan(probs, nprob);
+  if (ws_bytes < (size_t)fresh->hdr.total) return SQNGD_E_WORKSPACE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_ws.find(ws);
+  if (it == g_ws.end() || it->second->hash != fresh->hash ||
+      it->second->bytes.size() != fresh->bytes.size() ||
+      std::memcmp(it->second->bytes.data(), fresh->bytes.data(), fresh->bytes.size()) != 0)
+    return SQNGD_E_WORKSPACE;
+  *out = it->second;
+  return SQNGD_OK;
+}
+
+struct Ptrs {
+  char* base;
+  const ProbPlan* plans;
+  const int32_t* row_prob;
+  int32_t* counters;
+  float2* spec;
+  float2* wself;
+  float2* wpart;
+  UnitStat* ustat;
+  float2* upart;
+  float4* snrl;
+};
+
+Ptrs ptrs(const Plan& pl, void* ws) {
+  char* b = (char*)ws;
+  const WsHeader& H = pl.hdr;
+  return Ptrs{b,
+              (const ProbPlan*)(b + H.plans),
+              (const int32_t*)(b + H.row_prob),
+              (int32_t*)(b + H.counters),
+              (float2*)(b + H.spec),
+              (float2*)(b + H.wself),
+              (float2*)(b + H.wpart),
+              (UnitStat*)(b + H.ustat),
+              (float2*)(b + H.upart),
+              (float4*)(b + H.snrl)};
+}
+
+// ----------------------------------------------------------- launch helpers
+
+template <int P>
+void launch_prep_p(const PrepArgs& a, int waves, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep<P>, dim3(waves), dim3(64), 0, s, a);
+}
+
+void launch_prep(const Plan& pl, const Ptrs& w, PrepArgs a, hipStream_t s) {
+  a.plans = w.plans;
+  a.spec = w.spec;
+  a.wself = w.wself;
+  a.wpart = w.wpart;
+  a.snrl = w.snrl;
+  for (int g = 0; g < kNumPGroups; ++g) {
+    if (pl.hdr.group_n[g] == 0) continue;
+    a.gprob = (const int32_t*)(w.base + pl.hdr.group_prob[g]);
+    a.grwave = (const int32_t*)(w.base + pl.hdr.group_rwave[g]);
+    a.gn = pl.hdr.group_n[g];
+    const int waves = pl.hdr.group_rwaves[g];
+    switch (g) {
+      case 0: launch_prep_p<128>(a, waves, s); break;
+      case 1: launch_prep_p<256>(a, waves, s); break;
+      case 2: launch_prep_p<512>(a, waves, s); break;
+      case 3: launch_prep_p<1024>(a, waves, s); break;
+      default: launch_prep_p<2048>(a, waves, s); break;
+    }
+  }
+}
+
+template <int P>
+void launch_pass_p(const PassArgs& a, int phlog, int waves, hipStream_t s) {
+  if (phlog == 3) hipLaunchKernelGGL((k_pass<P, 3>), dim3(waves), dim3(64), 0, s, a);
+  else if (phlog == 2) hipLaunchKernelGGL((k_pass<P, 2>), dim3(waves), dim3(64), 0, s, a);
+  else hipLaunchKernelGGL((k_pass<P, -1>), dim3(waves), dim3(64), 0, s, a);
+}
+
+void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
+  a.plans = w.plans;
+  a.spec = w.spec;
+  a.ustat = w.ustat;
+  a.upart = w.upart;
+  for (int g = 0; g < kNumPGroups; ++g) {
+    if (pl.hdr.group_n[g] == 0) continue;
+    a.gprob = (const int32_t*)(w.base + pl.hdr.group_prob[g]);
+    a.gwave = (const int32_t*)(w.base + pl.hdr.group_wave[g]);
+    a.gn = pl.hdr.group_n[g];
+    const int waves = pl.hdr.group_waves[g];
+    const int phl = pl.group_phlog[g];
+    switch (g) {
+      case 0: launch_pass_p<128>(a, phl, waves, s); break;
+      case 1: launch_pass_p<256>(a, phl, waves, s); break;
+      case 2: launch_pass_p<512>(a, phl, waves, s); break;
+      case 3: launch_pass_p<1024>(a, phl, waves, s); break;
+      default: launch_pass_p<2048>(a, phl, waves, s); break;
+    }
+  }
+}
+
+void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
+  a.plans = w.plans;
+  a.row_prob = w.row_prob;
+  a.nrows = pl.hdr.nrows;
+  a.ustat = w.ustat;
+  a.upart = w.upart;
+  a.snrl = w.snrl;
+  a.done = w.counters;
+  hipLaunchKernelGGL(k_final, dim3(pl.hdr.nrows), dim3(kFinThreads), 0, s, a);
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+const char* sqngd_status_string(int status) {
+  switch (status) {
+    case SQNGD_OK: return "ok";
+    case SQNGD_E_INVALID_ARG: return "invalid argument";
+    case SQNGD_E_UNSUPPORTED: return "unsupported problem size";
+    case SQNGD_E_WORKSPACE: return "workspace too small or not initialised for this batch";
+    case SQNGD_E_ALIGN: return "misaligned pointer";
+    case SQNGD_E_HIP: return "HIP launch failure";
+    default: return "unknown status";
+  }
+}
+
+int sqngd_last_hip_error(void) { return g_last_hip.load(); }
+
+int sqngd_buffer_sizes(const sqngd_problem* probs, int32_t nprob, int64_t* z_floats, int64_t* wave_c64,
+                       int64_t* adam_floats, int64_t* cube_c64) {
+  int rc = validate_batch(probs, nprob);
+  if (rc != SQNGD_OK) return rc;
+  int64_t zf = 0, wc = 0, af = 0, cc = 0;
+  for (int i = 0; i < nprob; ++i) {
+    const sqngd_problem& p = probs[i];
+    zf += (int64_t)p.M * p.N * p.L;
+    wc += (int64_t)p.M * p.N;
+    af += SQNGD_ADAM_FLOATS(p.M, p.N, p.L);
+    cc += (int64_t)p.M * p.M * p.F * (2 * p.N - 1);
+  }
+  if (z_floats) *z_floats = zf;
+  if (wave_c64) *wave_c64 = wc;
+  if (adam_floats) *adam_floats = af;
+  if (cube_c64) *cube_c64 = cc;
+  return SQNGD_OK;
+}
+
+int sqngd_workspace_size(const sqngd_problem* probs, int32_t nprob, size_t* bytes) {
+  int rc = validate_batch(probs, nprob);
+  if (rc != SQNGD_OK) return rc;
+  if (bytes == nullptr) return SQNGD_E_INVALID_ARG;
+  *bytes = (size_t)build_plan(probs, nprob)->hdr.total;
+  return SQNGD_OK;
+}
+
+int sqngd_workspace_init(const sqngd_problem* probs, int32_t nprob, void* ws, size_t ws_bytes, void* stream) {
+  int rc = validate_batch(probs, nprob);
+  if (rc != SQNGD_OK) return rc;
+  if (ws == nullptr) return SQNGD_E_INVALID_ARG;
+  if (!aligned(ws, kAlign)) return SQNGD_E_ALIGN;
+  auto pl = build_plan(probs, nprob);
+  if (ws_bytes < (size_t)pl->hdr.total) return SQNGD_E_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  Plan* raw = pl.get();
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_keep.push_back(std::move(pl));
+    g_ws[ws] = raw;
+  }
+  hipError_t e = hipMemcpyAsync(ws, raw->bytes.data(), raw->bytes.size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int32_t*)((char*)ws + raw->hdr.counters),
+                     kNumCounters);
+  return check_launch();
+}
+
+int sqngd_af_forward(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t wave_mode,
+                     const sqngd_c64* s_given, const sqngd_c64* h, sqngd_stats* stats, sqngd_c64* af_cube,
+                     void* ws, size_t ws_bytes, void* stream) {
+  if (wave_mode < SQNGD_WAVE_SOFT || wave_mode > SQNGD_WAVE_GIVEN) return SQNGD_E_INVALID_ARG;
+  if (wave_mode != SQNGD_WAVE_GIVEN && z == nullptr) return SQNGD_E_INVALID_ARG;
+  if (wave_mode == SQNGD_WAVE_GIVEN && s_given == nullptr) return SQNGD_E_INVALID_ARG;
+  if (h == nullptr || stats == nullptr) return SQNGD_E_INVALID_ARG;
+  if (!aligned(z, 4) || !aligned(s_given, 8) || !aligned(h, 8) || !aligned(stats, 4) || !aligned(af_cube, 8))
+    return SQNGD_E_ALIGN;
+  const Plan* pl = nullptr;
+  int rc = lookup(probs, nprob, ws, ws_bytes, &pl);
+  if (rc != SQNGD_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Ptrs w = ptrs(*pl, ws);
+  PrepArgs pa{};
+  pa.mode = wave_mode == SQNGD_WAVE_SOFT ? PREP_B_SOFT : (wave_mode == SQNGD_WAVE_HARD ? PREP_B_HARD : PREP_B_GIVEN);
+  pa.z = z;
+  pa.s_given = (const float2*)s_given;
+  pa.h = (const float2*)h;
+  launch_prep(*pl, w, pa, s);
+  PassArgs ka{};
+  ka.orient = 0;
+  ka.want_grad = 0;
+  ka.self_w = w.wself;
+  ka.cube = (float2*)af_cube;
+  launch_pass(*pl, w, ka, s);
+  FinArgs fa{};
+  fa.orient = 0;
+  fa.mode = FIN_STATS;
+  fa.self_w = w.wself;
+  fa.part_w = (const float2*)h;
+  fa.stats = stats;
+  launch_final(*pl, w, fa, s);
+  return check_launch();
+}
+
+int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t wave_mode,
+                      const sqngd_c64* s_given, const sqngd_c64* h, const float* grad_loss, float* grad_z,
+                      sqngd_c64* grad_h, sqngd_c64* grad_s, sqngd_stats* stats, void* ws, size_t ws_bytes,
+                      void* stream) {
+  if (wave_mode < SQNGD_WAVE_SOFT || wave_mode > SQNGD_WAVE_GIVEN) return SQNGD_E_INVALID_ARG;
+  if (wave_mode != SQNGD_WAVE_GIVEN && z == nullptr) return SQNGD_E_INVALID_ARG;
+  if (wave_mode == SQNGD_WAVE_GIVEN && (s_given == nullptr || grad_z != nullptr)) return SQNGD_E_INVALID_ARG;
+  if (h == nullptr) return SQNGD_E_INVALID_ARG;
+  if (grad_z == nullptr && grad_h == nullptr && grad_s == nullptr && stats == nullptr) return SQNGD_E_INVALID_ARG;
+  if (!aligned(z, 4) || !aligned(s_given, 8) || !aligned(h, 8) || !aligned(grad_loss, 4) || !aligned(grad_z, 4) ||
+      !aligned(grad_h, 8) || !aligned(grad_s, 8) || !aligned(stats, 4))
+    return SQNGD_E_ALIGN;
+  const Plan* pl = nullptr;
+  int rc = lookup(probs, nprob, ws, ws_bytes, &pl);
+  if (rc != SQNGD_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Ptrs w = ptrs(*pl, ws);
+  PrepArgs pa{};
+  pa.mode = wave_mode == SQNGD_WAVE_SOFT ? PREP_B_SOFT : (wave_mode == SQNGD_WAVE_HARD ? PREP_B_HARD : PREP_B_GIVEN);
+  pa.z = z;
+  pa.s_given = (const float2*)s_given;
+  pa.h = (const float2*)h;
+  launch_prep(*pl, w, pa, s);
+  // waveform side (orientation 0)
+  PassArgs ka{};
+  ka.orient = 0;
+  ka.want_grad = 1;
+  ka.self_w = w.wself;
+  launch_pass(*pl, w, ka, s);
+  FinArgs fa{};
+  fa.orient = 0;
+  fa.mode = FIN_GRAD;
+  fa.wave_mode = wave_mode;
+  fa.self_w = w.wself;
+  fa.part_w = (const float2*)h;
+  fa.stats = stats;
+  fa.grad_loss = grad_loss;
+  fa.grad_w = (float2*)grad_s;
+  fa.grad_z = grad_z;
+  fa.z = const_cast<float*>(z);
+  launch_final(*pl, w, fa, s);
+  if (grad_h != nullptr) {
+    // filter side (orientation 1): self = h, partners = the waveforms of wself
+    PrepArgs pb{};
+    pb.mode = PREP_A_SELF;
+    pb.h = (const float2*)h;
+    launch_prep(*pl, w, pb, s);
+    PassArgs kb{};
+    kb.orient = 1;
+    kb.want_grad = 1;
+    kb.self_w = (const float2*)h;
+    launch_pass(*pl, w, kb, s);
+    FinArgs fb{};
+    fb.orient = 1;
+    fb.mode = FIN_GRAD;
+    fb.wave_mode = SQNGD_WAVE_GIVEN;
+    fb.self_w = (const float2*)h;
+    fb.part_w = w.wself;
+    fb.grad_loss = grad_loss;
+    fb.grad_w = (float2*)grad_h;
+    launch_final(*pl, w, fb, s);
+  }
+  return check_launch();
+}
+
+int sqngd_step(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, float* z, sqngd_c64* h,
+               float* adam_state, int32_t* step_counter, sqngd_stats* stats, void* ws, size_t ws_bytes,
+               void* stream) {
+  if (opt == nullptr || z == nullptr || h == nullptr || adam_state == nullptr || step_counter == nullptr)
+    return SQNGD_E_INVALID_ARG;
+  const sqngd_opt& o = *opt;
+  if (!finite(o.lr_z) || !finite(o.lr_h) || o.lr_z < 0.f || o.lr_h < 0.f) return SQNGD_E_INVALID_ARG;
+  if (!(o.beta1 >= 0.f && o.beta1 < 1.f && o.beta2 >= 0.f && o.beta2 < 1.f)) return SQNGD_E_INVALID_ARG;
+  if (!finite(o.eps) || o.eps <= 0.f) return SQNGD_E_INVALID_ARG;
+  if (o.n_h < 0 || o.n_x < 0 || o.n_h + o.n_x < 1 || o.n_h > 1000 || o.n_x > 1000) return SQNGD_E_INVALID_ARG;
+  if (!finite(o.T0) || !finite(o.T1) || o.T0 <= 0.f || o.T1 <= 0.f || o.total_iters < 1) return SQNGD_E_INVALID_ARG;
+  if ((o.flags & ~SQNGD_OPT_SGD) != 0) return SQNGD_E_INVALID_ARG;
+  if (!aligned(z, 4) || !aligned(h, 8) || !aligned(adam_state, 4) || !aligned(step_counter, 4) ||
+      !aligned(stats, 4))
+    return SQNGD_E_ALIGN;
+  const Plan* pl = nullptr;
+  int rc = lookup(probs, nprob, ws, ws_bytes, &pl);
+  if (rc != SQNGD_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  Ptrs w = ptrs(*pl, ws);
+  for (int i = 0; i < o.n_h; ++i) {
+    PrepArgs pa{};
+    pa.mode = PREP_A_HARD;
+    pa.z = z;
+    pa.h = (const float2*)h;
+    launch_prep(*pl, w, pa, s);
+    PassArgs ka{};
+    ka.orient = 1;
+    ka.want_grad = 1;
+    ka.self_w = (const float2*)h;
+    launch_pass(*pl, w, ka, s);
+    FinArgs fa{};
+    fa.orient = 1;
+    fa.mode = FIN_STEP_A;
+    fa.inner = i;
+    fa.count_step = (o.n_x == 0 && i == o.n_h - 1) ? 1 : 0;
+    fa.self_w = (const float2*)h;
+    fa.part_w = w.wpart;
+    fa.stats = stats;
+    fa.h = (float2*)h;
+    fa.adam = adam_state;
+    fa.counter = step_counter;
+    fa.opt = o;
+    launch_final(*pl, w, fa, s);
+  }
+  for (int j = 0; j < o.n_x; ++j) {
+    PrepArgs pa{};
+    pa.mode = PREP_B_SOFT;
+    pa.use_schedule = 1;
+    pa.opt = o;
+    pa.counter = step_counter;
+    pa.z = z;
+    pa.h = (const float2*)h;
+    launch_prep(*pl, w, pa, s);
+    PassArgs ka{};
+    ka.orient = 0;
+    ka.want_grad = 1;
+    ka.self_w = w.wself;
+    launch_pass(*pl, w, ka, s);
+    FinArgs fa{};
+    fa.orient = 0;
+    fa.mode = FIN_STEP_B;
+    fa.inner = j;
+    fa.count_step = (j == o.n_x - 1) ? 1 : 0;
+    fa.self_w = w.wself;
+    fa.part_w = (const float2*)h;
+    fa.stats = stats ? stats + nprob : nullptr;
+    fa.z = z;
+    fa.adam = adam_state;
+    fa.counter = step_counter;
+    fa.opt = o;
+    launch_final(*pl, w, fa, s);
+  }
+  return check_launch();
+}
+
+int sqngd_hard_quantize(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t* idx, sqngd_c64* x,
+                        void* ws, size_t ws_bytes, void* stream) {
+  if (z == nullptr || (idx == nullptr && x == nullptr)) return SQNGD_E_INVALID_ARG;
+  if (!aligned(z, 4) || !aligned(idx, 4) || !aligned(x, 8)) return SQNGD_E_ALIGN;
+  const Plan* pl = nullptr;
+  int rc = lookup(probs, nprob, ws, ws_bytes, &pl);
+  if (rc != SQNGD_OK) return rc;
+  Ptrs w = ptrs(*pl, ws);
+  HardArgs a{w.plans, w.row_prob, z, idx, (float2*)x};
+  hipLaunchKernelGGL(k_hardq, dim3(pl->hdr.nrows), dim3(256), 0, (hipStream_t)stream, a);
+  return check_launch();
+}
+
+}  // extern "C"

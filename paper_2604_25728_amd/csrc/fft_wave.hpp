@@ -1,0 +1,308 @@
+// fft_wave.hpp - wave-local complex64 FFTs of length P = 128 .. 2048 for gfx950.
+//
+// One FFT lives in TF lanes of a single 64-lane wave, E = P / TF elements per
+// lane in registers (TF = 64 for P >= 512, else P / 8, so E >= 8), and a wave
+// runs 64 / TF independent FFTs side by side ("slots"). Every exchange of data
+// between lanes stays inside the wave, so no workgroup barrier is ever needed:
+// an exchange is a write of the slot's elements to its private LDS region, a
+// wave-scope fence, and a read back in the next stage's order.
+//
+// Factorisation (Cooley-Tukey four-step, P = E * TF with TF = A * B):
+//   natural index n = t + TF * e            (lane t, register e)
+//   1. length-E DFT over the registers of each lane           -> k1
+//   2. twiddle W_P^(t k1)
+//   3a. LDS exchange, length-A DFTs over alpha (n2 = B alpha + beta)  -> gamma,
+//       twiddle W_TF^(beta gamma)
+//   3b. LDS exchange, length-B DFTs over beta                          -> delta
+//   output "spectral layout": lane t, register j2*B + delta holds bin
+//       k = k1 + E (gamma + A delta),  gamma = t % A,  k1 = j2*B + t / A.
+// The inverse transform runs the same stages mirrored, from the spectral
+// layout back to the natural layout, with conjugate twiddles. Neither
+// transform scales by 1/P.
+//
+// Products of two spectra are formed element by element in the spectral
+// layout, so a forward FFT, a pointwise product and an inverse FFT never
+// reorder data through memory beyond the four exchanges.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+namespace sq {
+
+// ----------------------------------------------------------------- utilities
+
+template <int... Is, class Fn>
+__device__ __forceinline__ void static_for_impl(std::integer_sequence<int, Is...>, Fn&& fn) {
+  (fn(std::integral_constant<int, Is>{}), ...);
+}
+template <int Count, class Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  static_for_impl(std::make_integer_sequence<int, Count>{}, static_cast<Fn&&>(fn));
+}
+
+// Compile-time sine and cosine (Taylor series after reduction to [-pi, pi]),
+// used only to form constant twiddles of the in-register DFTs.
+constexpr double cx_pi = 3.14159265358979323846264338327950288;
+constexpr double cx_sin(double x) {
+  while (x > cx_pi) x -= 2.0 * cx_pi;
+  while (x < -cx_pi) x += 2.0 * cx_pi;
+  double term = x, sum = x;
+  for (int i = 1; i < 30; ++i) {
+    term *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cx_cos(double x) { return cx_sin(x + 0.5 * cx_pi); }
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// Multiply by the constant W = exp(DIR * 2 pi i J / LEN), DIR = -1 forward, +1 inverse.
+template <int J, int LEN, int DIR>
+__device__ __forceinline__ float2 twiddle_const(float2 v) {
+  constexpr int j = ((J % LEN) + LEN) % LEN;
+  if constexpr (j == 0) {
+    return v;
+  } else if constexpr (4 * j == LEN) {  // W = DIR * i
+    return DIR < 0 ? make_float2(v.y, -v.x) : make_float2(-v.y, v.x);
+  } else if constexpr (2 * j == LEN) {
+    return make_float2(-v.x, -v.y);
+  } else if constexpr (4 * j == 3 * LEN) {  // W = -DIR * i
+    return DIR < 0 ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+  } else {
+    constexpr double ang = 2.0 * cx_pi * (double)j / (double)LEN;
+    constexpr float c = (float)cx_cos(ang);
+    constexpr float s = (float)(DIR * cx_sin(ang));
+    return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
+  }
+}
+
+constexpr int cx_log2(int v) { return v <= 1 ? 0 : 1 + cx_log2(v / 2); }
+constexpr int cx_bitrev(int v, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((v >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+// In-register DFT of length R on x[OFF .. OFF+R) (natural order in and out):
+// radix-2 decimation in time after a compile-time bit reversal (a register
+// renaming, free at run time).
+template <int R, int DIR, int OFF, int CAP>
+__device__ __forceinline__ void dft_reg(float2 (&x)[CAP]) {
+  if constexpr (R == 1) {
+    return;
+  } else {
+    constexpr int LB = cx_log2(R);
+    float2 y[R];
+    static_for<R>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      y[cx_bitrev(i, LB)] = x[OFF + i];
+    });
+    static_for<LB>([&](auto sc) {
+      constexpr int half = 1 << decltype(sc)::value;
+      constexpr int len = 2 * half;
+      static_for<R / len>([&](auto bc) {
+        constexpr int base = decltype(bc)::value * len;
+        static_for<half>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          float2 u = y[base + j];
+          float2 v = twiddle_const<j, len, DIR>(y[base + j + half]);
+          y[base + j] = cadd(u, v);
+          y[base + j + half] = csub(u, v);
+        });
+      });
+    });
+    static_for<R>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      x[OFF + i] = y[i];
+    });
+  }
+}
+
+// Wave-scope ordering of LDS traffic: every lane's earlier LDS accesses are
+// complete and visible to the wave before any later one starts.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------------ twiddles
+
+// W_2048^k = exp(-2 pi i k / 2048), k < 2048, rounded from double precision at
+// compile time. A length-P twiddle W_P^k is entry k * (2048 / P).
+struct TwiddleTable {
+  float2 w[2048];
+};
+constexpr TwiddleTable make_twiddles() {
+  TwiddleTable t{};
+  for (int k = 0; k < 2048; ++k) {
+    double a = 2.0 * cx_pi * (double)k / 2048.0;
+    t.w[k] = float2{(float)cx_cos(a), (float)(-cx_sin(a))};
+  }
+  return t;
+}
+__constant__ const TwiddleTable kTw = make_twiddles();
+
+template <int P>
+__device__ __forceinline__ float2 tw(int k) {  // W_P^k, any integer k >= 0
+  return kTw.w[(k & (P - 1)) * (2048 / P)];
+}
+
+// ------------------------------------------------------------------ geometry
+
+template <int P_>
+struct Geom {
+  static constexpr int P = P_;
+  static constexpr int TF = P >= 512 ? 64 : P / 8;  // lanes per FFT
+  static constexpr int E = P / TF;                   // elements per lane
+  static constexpr int A = TF >= 32 ? 8 : 4;
+  static constexpr int B = TF / A;
+  static constexpr int SLOTS = 64 / TF;              // FFTs per wave
+  static constexpr int LDS = 64 * E;                 // float2 per wave
+  static_assert(E % A == 0 && E % B == 0, "register blocks must tile E");
+  // spectral-layout bin of lane t, register e
+  __device__ static constexpr int spec_bin(int t, int e) {
+    int gamma = t % A, k1 = (e / B) * B + t / A, delta = e % B;
+    return k1 + E * (gamma + A * delta);
+  }
+};
+
+// Per-lane twiddles reused by every FFT of the wave.
+template <int P>
+struct WaveTwiddles {
+  using G = Geom<P>;
+  static constexpr int NLO = G::E < 8 ? G::E : 8;
+  static constexpr int NHI = G::E / NLO;
+  float2 lo[NLO];  // W_P^(t b),        b < NLO
+  float2 hi[NHI];  // W_P^(t NLO a),    a < NHI     (W_P^(t k1) = lo[k1 % NLO] hi[k1 / NLO])
+  float2 col[G::A];  // W_TF^(beta gamma), gamma < A, beta = t % B
+  __device__ __forceinline__ void init(int t) {
+    for (int b = 0; b < NLO; ++b) lo[b] = tw<P>(t * b);
+    for (int a = 0; a < NHI; ++a) hi[a] = tw<P>(t * NLO * a);
+    const int beta = t % G::B;
+    for (int g = 0; g < G::A; ++g) col[g] = tw<P>(beta * g * G::E);
+  }
+  template <int K1>
+  __device__ __forceinline__ float2 step2(float2 v, bool inverse) const {
+    constexpr int b = K1 % NLO, a = K1 / NLO;
+    float2 w = lo[b];
+    if constexpr (a > 0) w = cmul(w, hi[a]);
+    return inverse ? cmulc(v, w) : cmul(v, w);
+  }
+};
+
+// Forward FFT of one slot: x in natural layout -> x in spectral layout.
+// buf points at this slot's P-element LDS region; t is the lane within the slot.
+template <int P>
+__device__ __forceinline__ void fft_forward(float2 (&x)[Geom<P>::E], float2* buf, int t,
+                                            const WaveTwiddles<P>& W) {
+  using G = Geom<P>;
+  constexpr int E = G::E, TF = G::TF, A = G::A, B = G::B;
+  dft_reg<E, -1, 0>(x);
+  static_for<E>([&](auto kc) {
+    constexpr int k1 = decltype(kc)::value;
+    x[k1] = W.template step2<k1>(x[k1], false);
+  });
+  // exchange 1: [k1][n2]
+  wave_lds_sync();
+  static_for<E>([&](auto kc) {
+    constexpr int k1 = decltype(kc)::value;
+    buf[k1 * TF + t] = x[k1];
+  });
+  wave_lds_sync();
+  const int beta = t % B, q = t / B;
+  static_for<E / A>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    static_for<A>([&](auto ac) {
+      constexpr int al = decltype(ac)::value;
+      x[j * A + al] = buf[(j * A + q) * TF + B * al + beta];
+    });
+    dft_reg<A, -1, j * A>(x);
+    static_for<A>([&](auto gc) {
+      constexpr int g = decltype(gc)::value;
+      if constexpr (g > 0) x[j * A + g] = cmul(x[j * A + g], W.col[g]);
+    });
+  });
+  // exchange 2: [k1][gamma * B + beta]
+  wave_lds_sync();
+  static_for<E / A>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    static_for<A>([&](auto gc) {
+      constexpr int g = decltype(gc)::value;
+      buf[(j * A + q) * TF + g * B + beta] = x[j * A + g];
+    });
+  });
+  wave_lds_sync();
+  const int gamma = t % A, q2 = t / A;
+  static_for<E / B>([&](auto jc) {
+    constexpr int j2 = decltype(jc)::value;
+    static_for<B>([&](auto bc) {
+      constexpr int be = decltype(bc)::value;
+      x[j2 * B + be] = buf[(j2 * B + q2) * TF + gamma * B + be];
+    });
+    dft_reg<B, -1, j2 * B>(x);
+  });
+}
+
+// Inverse FFT of one slot (unscaled): x in spectral layout -> x in natural layout.
+template <int P>
+__device__ __forceinline__ void fft_inverse(float2 (&x)[Geom<P>::E], float2* buf, int t,
+                                            const WaveTwiddles<P>& W) {
+  using G = Geom<P>;
+  constexpr int E = G::E, TF = G::TF, A = G::A, B = G::B;
+  const int gamma = t % A, q2 = t / A;
+  static_for<E / B>([&](auto jc) {
+    constexpr int j2 = decltype(jc)::value;
+    dft_reg<B, +1, j2 * B>(x);
+  });
+  wave_lds_sync();
+  static_for<E / B>([&](auto jc) {
+    constexpr int j2 = decltype(jc)::value;
+    static_for<B>([&](auto bc) {
+      constexpr int be = decltype(bc)::value;
+      buf[(j2 * B + q2) * TF + gamma * B + be] = x[j2 * B + be];
+    });
+  });
+  wave_lds_sync();
+  const int beta = t % B, q = t / B;
+  static_for<E / A>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    static_for<A>([&](auto gc) {
+      constexpr int g = decltype(gc)::value;
+      float2 v = buf[(j * A + q) * TF + g * B + beta];
+      if constexpr (g > 0) v = cmulc(v, W.col[g]);
+      x[j * A + g] = v;
+    });
+    dft_reg<A, +1, j * A>(x);
+  });
+  wave_lds_sync();
+  static_for<E / A>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    static_for<A>([&](auto ac) {
+      constexpr int al = decltype(ac)::value;
+      buf[(j * A + q) * TF + B * al + beta] = x[j * A + al];
+    });
+  });
+  wave_lds_sync();
+  static_for<E>([&](auto kc) {
+    constexpr int k1 = decltype(kc)::value;
+    x[k1] = W.template step2<k1>(buf[k1 * TF + t], true);
+  });
+  dft_reg<E, +1, 0>(x);
+}
+
+}  // namespace sq

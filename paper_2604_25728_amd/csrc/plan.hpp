@@ -1,0 +1,65 @@
+// plan.hpp - device-side description of a batch, written into the caller's
+// workspace by sqngd_workspace_init and read by every kernel.
+#pragma once
+
+#include <cstdint>
+
+namespace sq {
+
+constexpr int kNumPGroups = 5;  // FFT lengths 128, 256, 512, 1024, 2048
+constexpr int kMinLogP = 7;
+
+// One problem of the batch. Offsets are element offsets: off_z into z-sized
+// arrays (floats), off_w into waveform-sized arrays (complex), off_state into
+// the Adam state (floats), off_cube into the AF cube (complex); ws_* are
+// offsets into the workspace regions of the same element type.
+struct ProbPlan {
+  int32_t M, N, L, F;
+  int32_t P, logP, tau_lo, tau_hi;
+  float nu_min, dnu, p, p_tar;
+  float w_psl, w_snrl, temperature, inv_NP;
+  int32_t sq_mode, ph_log;  // ph_log = log2(p/2) when p/2 is a power of two <= 32, else -1
+  int32_t units, row0;      // units = M*F; row0 = first row of this problem in the batch
+  int64_t off_z, off_w, off_state, off_cube;
+  int64_t ws_spec;   // complex: [M][P] spectra
+  int64_t ws_unit;   // UnitStat index and row index of upart ([units][N] complex, stride N)
+  int64_t ws_upart;  // complex offset of this problem's unit partials
+  int64_t pad;
+};
+static_assert(sizeof(ProbPlan) == 144, "ProbPlan layout");
+
+// Per-unit partial statistics of one fused pass. Keys pack the squared raw
+// magnitude (float bits, monotone for non-negative values) in the high word
+// and the complement of the cell index in the low word, so a max over keys
+// selects the largest cell and, among equal values, the lowest index.
+struct UnitStat {
+  float sigma;   // running scale: max raw |r| over the ROI cells of the unit
+  float S;       // sum over the unit's ROI cells of (|r| / sigma)^p
+  uint32_t pad0, pad1;
+  unsigned long long key_auto, key_cross;
+};
+static_assert(sizeof(UnitStat) == 32, "UnitStat layout");
+
+// Batch header at the start of the workspace.
+struct WsHeader {
+  uint32_t magic;
+  int32_t nprob, nrows, pad0;
+  int64_t plans;          // byte offset of ProbPlan[nprob]
+  int64_t group_prob[kNumPGroups];   // byte offset of int32 problem ids of each FFT-length group
+  int64_t group_wave[kNumPGroups];   // byte offset of int32 [n+1] wave prefix (fused pass)
+  int64_t group_rwave[kNumPGroups];  // byte offset of int32 [n+1] wave prefix (one slot per row)
+  int32_t group_n[kNumPGroups];
+  int32_t group_waves[kNumPGroups];
+  int32_t group_rwaves[kNumPGroups];
+  int32_t pad1;
+  int64_t row_prob;       // byte offset of int32 [nrows]: problem of each row
+  int64_t spec, wself, wpart, ustat, upart, snrl, counters;  // region byte offsets
+  int64_t total;
+};
+
+constexpr uint32_t kWsMagic = 0x53514e47u;  // "SQNG"
+
+// Number of 32-bit device counters at WsHeader::counters.
+constexpr int kNumCounters = 4;
+
+}  // namespace sq

@@ -1,0 +1,145 @@
+"""Host-side checks of the C ABI: exported symbols, struct layouts, and the
+argument validation that runs before any HIP call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2604_25728_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sqngd.h")
+
+
+@pytest.fixture(scope="module")
+def nat():
+    from paper_2604_25728_amd import native
+    if not os.path.exists(native.LIB_PATH):
+        from paper_2604_25728_amd import build
+        build.build()
+    native.load()
+    return native
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:const\s+)?\w+\*?\s+\**(sqngd_\w+)\(", text, flags=re.M)))
+
+
+def test_header_symbols_exported(nat):
+    names = _declared()
+    assert len(names) >= 9
+    lib = nat.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(nat.SYMBOLS) == names
+
+
+def test_struct_layouts(nat):
+    assert ctypes.sizeof(nat.Problem) == 64
+    assert ctypes.sizeof(nat.Opt) == 44
+    text = open(HEADER).read()
+    assert "} sqngd_problem;" in text and "} sqngd_stats;" in text
+
+
+def test_status_strings(nat):
+    assert nat.status_string(0) == "ok"
+    for rc in (-1, -2, -3, -4, -5):
+        assert nat.status_string(rc) != "unknown status"
+
+
+def _arr(nat, **over):
+    p = I.make_problem(2, 64, 4, 33, p=8.0)
+    p.update(over)
+    return nat.make_problems([p])
+
+
+def _ws_size(nat, arr, n=1):
+    b = ctypes.c_size_t()
+    rc = nat.load().sqngd_workspace_size(arr, n, ctypes.byref(b))
+    return rc, b.value
+
+
+def test_workspace_size_and_buffer_sizes(nat):
+    lib = nat.load()
+    rc, nb = _ws_size(nat, _arr(nat))
+    assert rc == 0 and nb > 0 and nb % 256 == 0
+    zf, wc, af, cc = (ctypes.c_int64() for _ in range(4))
+    probs = nat.make_problems([I.make_problem(2, 64, 4, 33), I.make_problem(3, 100, 8, 5)])
+    assert lib.sqngd_buffer_sizes(probs, 2, ctypes.byref(zf), ctypes.byref(wc), ctypes.byref(af),
+                                  ctypes.byref(cc)) == 0
+    assert zf.value == 2 * 64 * 4 + 3 * 100 * 8
+    assert wc.value == 2 * 64 + 3 * 100
+    assert af.value == (2 * 2 * 64 * 4 + 4 * 2 * 64) + (2 * 3 * 100 * 8 + 4 * 3 * 100)
+    assert cc.value == 4 * 33 * 127 + 9 * 5 * 199
+    # the workspace grows with the batch
+    rc2, nb2 = _ws_size(nat, probs, 2)
+    assert rc2 == 0 and nb2 > nb
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("M", 0, -1), ("M", 17, -2), ("N", 1, -1), ("N", 1025, -2), ("L", 1, -1), ("L", 65, -2),
+    ("F", 0, -1), ("F", 4097, -2), ("p", 1.5, -1), ("p", 65.0, -1), ("p", float("nan"), -1),
+    ("temperature", 0.0, -1), ("w_psl", -1.0, -1), ("snrl_target_db", -0.1, -1),
+    ("tau_lo", -64, -1), ("tau_hi", 64, -1), ("sq_mode", 2, -1), ("nu_min", 1.0, -1),
+])
+def test_problem_validation(nat, field, value, code):
+    rc, _ = _ws_size(nat, _arr(nat, **{field: value}))
+    assert rc == code, (field, value, rc)
+
+
+def test_reserved_and_pair_count_limits(nat):
+    arr = _arr(nat)
+    arr[0].reserved[0] = 1
+    assert _ws_size(nat, arr)[0] == -1
+    # the largest problem the limits allow still has cell indices below 2^32
+    assert _ws_size(nat, _arr(nat, M=16, N=1024, F=4096))[0] == 0
+
+
+def test_entry_points_reject_before_touching_the_device(nat):
+    lib = nat.load()
+    arr = _arr(nat)
+    fake = ctypes.c_void_p(0x100000)      # never dereferenced: validation fails first
+    odd = ctypes.c_void_p(0x100002)
+    ws = ctypes.c_void_p(0x200000)
+    _, nb = _ws_size(nat, arr)
+    stats = ctypes.c_void_p(0x300000)
+    # bad wave mode / missing pointers
+    assert lib.sqngd_af_forward(arr, 1, fake, 7, None, fake, stats, None, ws, nb, None) == -1
+    assert lib.sqngd_af_forward(arr, 1, None, 0, None, fake, stats, None, ws, nb, None) == -1
+    assert lib.sqngd_af_forward(arr, 1, fake, 2, None, fake, stats, None, ws, nb, None) == -1
+    assert lib.sqngd_af_forward(arr, 1, fake, 0, None, None, stats, None, ws, nb, None) == -1
+    # misalignment
+    assert lib.sqngd_af_forward(arr, 1, fake, 0, None, odd, stats, None, ws, nb, None) == -4
+    assert lib.sqngd_af_forward(arr, 1, fake, 0, None, fake, stats, None,
+                                ctypes.c_void_p(0x200010), nb, None) == -4
+    # workspace too small, then not initialised for this batch
+    assert lib.sqngd_af_forward(arr, 1, fake, 0, None, fake, stats, None, ws, nb - 256, None) == -3
+    assert lib.sqngd_af_forward(arr, 1, fake, 0, None, fake, stats, None, ws, nb, None) == -3
+    # backward: logits gradient is undefined for a given waveform
+    assert lib.sqngd_af_backward(arr, 1, None, 2, fake, fake, None, fake, None, None, None, ws, nb,
+                                 None) == -1
+    assert lib.sqngd_af_backward(arr, 1, fake, 0, None, fake, None, None, None, None, None, ws, nb,
+                                 None) == -1
+    # step options
+    opt = nat.make_opt(I.make_opt())
+    st = ctypes.c_void_p(0x400000)
+    assert lib.sqngd_step(arr, 1, ctypes.byref(opt), fake, fake, fake, st, None, ws, nb, None) == -3
+    for field, value in (("beta1", 1.0), ("eps", 0.0), ("lr_z", -1.0), ("n_h", -1), ("T0", 0.0),
+                         ("total_iters", 0), ("flags", 8)):
+        bad = nat.make_opt(I.make_opt())
+        setattr(bad, field, value)
+        assert lib.sqngd_step(arr, 1, ctypes.byref(bad), fake, fake, fake, st, None, ws, nb,
+                              None) == -1, field
+    zero = nat.make_opt(I.make_opt(n_h=0, n_x=0))
+    assert lib.sqngd_step(arr, 1, ctypes.byref(zero), fake, fake, fake, st, None, ws, nb, None) == -1
+    assert lib.sqngd_step(arr, 1, None, fake, fake, fake, st, None, ws, nb, None) == -1
+    # hard quantise
+    assert lib.sqngd_hard_quantize(arr, 1, fake, None, None, ws, nb, None) == -1
+    assert lib.sqngd_hard_quantize(arr, 1, fake, fake, None, ws, nb, None) == -3
+    # batch count
+    assert lib.sqngd_workspace_init(arr, 0, ws, nb, None) == -1
+    assert lib.sqngd_workspace_init(None, 1, ws, nb, None) == -1
+    assert lib.sqngd_workspace_init(arr, 1, ws, nb - 256, None) == -3
+    assert lib.sqngd_last_hip_error() == 0

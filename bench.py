@@ -1,0 +1,210 @@
+#!/usr/bin/env python
+"""Throughput of the SQNGD hot path on one MI355X.
+
+A step is one outer iteration of Algorithm 1 (sqngd_step with one filter
+update and one logit update, each a full AF loss + gradient evaluation:
+quantisation, fused FFT AF / loss / adjoint pass, reduction, optimiser),
+recorded once in a HIP graph and replayed. The default workload is one design
+of M=4 waveforms, N=256 chips, L=8 phase levels, F=129 Doppler bins over
+[-0.5, 0.5], every delay in the region of interest, p=16, temperature annealed
+1.0 -> 0.05. Inputs are seeded synthetic N(0,1) logits and the matched filter;
+they are resident in HBM before the timed region starts.
+
+Prints one JSON line with the metric, the roofline of the fused pass kernel
+and the oracle timed on the host cores.
+Diagnostics go to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+HBM_PEAK_GBPS = 8000.0            # MI355X published HBM3E bandwidth
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def fft_len(N: int) -> int:
+    P = 128
+    while P < 2 * N - 1:
+        P *= 2
+    return P
+
+
+def pass_flops(prob: dict) -> float:
+    """Algorithmic FP32 flops of one fused pass with gradient for one problem:
+    per unit (self row, Doppler bin) 2M+2 length-P FFTs at 5 P log2 P flops
+    each, plus about 30 flops per delay cell and partner for the products,
+    the magnitude, the p-norm terms and the adjoint accumulation."""
+    M, F, P = prob["M"], prob["F"], fft_len(prob["N"])
+    units = M * F
+    return units * ((2 * M + 2) * 5.0 * P * math.log2(P) + M * 30.0 * P)
+
+
+def cube_cells(prob: dict) -> int:
+    return prob["M"] ** 2 * prob["F"] * (2 * prob["N"] - 1)
+
+
+def time_graph(run, steps: int, warmup: int):
+    import torch
+    run.capture()
+    for _ in range(warmup):
+        run.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        run.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def kernel_durations(run, nat, steps: int):
+    """Durations (ms) of every fused-pass launch over `steps` eager steps."""
+    import torch
+    torch.cuda.synchronize()
+    nat.profile_enable(2 * steps)
+    for _ in range(steps):
+        run.step()
+    torch.cuda.synchronize()
+    d = nat.profile_read(2 * steps)
+    nat.profile_enable(0)
+    return d
+
+
+def cpu_baseline(prob: dict, opt: dict, budget_s: float) -> dict:
+    """The FP64 oracle's outer iteration, timed on the host cores."""
+    import numpy as np
+
+    from oracle import sqngd_ref as R
+    from paper_2604_25728_amd import inputs as I
+    R.build()
+    z = I.logits(prob["M"], prob["N"], prob["L"], 0).astype(np.float64)
+    h = R.matched_init(z)
+    state = R.new_state(prob["M"], prob["N"], prob["L"])
+    n = 0
+    t0 = time.perf_counter()
+    while n < 1 or time.perf_counter() - t0 < budget_s:
+        z, h, state, _, _ = R.step(prob, opt, z, h, state, n)
+        n += 1
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    return {"value": 2 * n / el, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} outer iterations (2 evaluations each: AF cube, loss and both gradients "
+                      f"by FP64 direct sums) of the same workload, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and copy probes")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the designs of a batch "
+              "are independent, and a multi-GPU run would shard them without communication",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2604_25728_amd import inputs as I
+    from paper_2604_25728_amd import native as nat
+    from paper_2604_25728_amd import optim
+
+    torch.cuda.set_device(0)
+    cfg = I.config("c2")
+    prob, opt = cfg["problem"], cfg["opt"]
+    log(f"device: {torch.cuda.get_device_name(0)}")
+
+    run = optim.SQNGD([prob], opt, seeds=[0])
+    ms_step, wall = time_graph(run, args.steps, args.warmup)
+    evals_per_s = 2.0 / (ms_step * 1e-3)
+    log(f"step {ms_step * 1e3:.2f} us ({args.steps} graph replays, wall {wall:.3f} s)")
+
+    kd = kernel_durations(run, nat, min(args.steps, 200))
+    kd_avg_ms = float(kd.mean())
+    flops = pass_flops(prob)
+    achieved = flops / (kd_avg_ms * 1e-3) / 1e12
+    log(f"fused pass: {kd.size} launches, mean {kd_avg_ms * 1e3:.2f} us, "
+        f"{achieved:.2f} TFLOP/s algorithmic")
+    cube_gbps = 16.0 * cube_cells(prob) / (kd_avg_ms * 1e-3) / 1e9
+
+    extras = {}
+    if not args.no_extras:
+        R = 64
+        runb = optim.SQNGD([prob] * R, opt, seeds=list(range(R)))
+        msb, _ = time_graph(runb, max(10, args.steps // 10), 5)
+        kdb = kernel_durations(runb, nat, 20)
+        extras["batched_restarts"] = {
+            "designs": R, "ms_per_step": msb, "evals_per_s": 2.0 * R / (msb * 1e-3),
+            "pass_kernel_us": float(kdb.mean() * 1e3),
+            "pass_tflops": R * flops / (kdb.mean() * 1e-3) / 1e12}
+        log(f"batched x{R}: step {msb * 1e3:.1f} us, {extras['batched_restarts']['evals_per_s']:.0f} evals/s")
+        del runb
+        n = 1 << 28
+        a = torch.empty(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        extras["hbm_copy_GBps"] = 10 * 2 * 4 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del a, b
+
+    out = {
+        "metric": "AF loss+grad evals/s",
+        "value": evals_per_s,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "one SQNGD design, M=4 N=256 L=8 F=129 nu in [-0.5,0.5], all 511 "
+                               "delays, p=16, one filter + one logit update per step, HIP graph",
+                   "M": prob["M"], "N": prob["N"], "L": prob["L"], "F": prob["F"],
+                   "p": prob["p"], "evals_per_step": 2},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "k_pass (fused AF + loss + adjoint)",
+                     "kernel_us": kd_avg_ms * 1e3, "flops_per_launch": flops},
+        "cube_equivalent": {"GBps": cube_gbps, "frac_of_hbm": cube_gbps / HBM_PEAK_GBPS,
+                            "bytes_per_launch": 16 * cube_cells(prob)},
+    }
+    if extras:
+        out["extras"] = extras
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, opt, args.cpu_seconds)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.3f} evals/s on {out['cpu_baseline']['cores']} cores")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

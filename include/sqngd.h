@@ -217,6 +217,16 @@ int sqngd_step(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, 
 int sqngd_hard_quantize(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t* idx,
                         sqngd_c64* x, void* ws, size_t ws_bytes, void* stream);
 
+/* Measurement hook. sqngd_profile_enable(n) (n > 0) makes the library
+   bracket each of the next n launches of its fused AF pass kernel with HIP
+   events recorded on the launch stream; sqngd_profile_enable(0) switches it
+   off. sqngd_profile_read waits for those events and writes the duration of
+   each recorded launch in milliseconds (at most capacity values, *count gets
+   the number recorded). Process-wide state, not thread-safe; calls captured in
+   a graph while enabled record nothing. */
+int sqngd_profile_enable(int32_t max_launches);
+int sqngd_profile_read(float* ms, int32_t capacity, int32_t* count);
+
 /* Human-readable text of a status code. */
 const char* sqngd_status_string(int status);
 

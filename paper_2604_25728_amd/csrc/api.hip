@@ -293,6 +293,18 @@ void launch_prep(const Plan& pl, const Ptrs& w, PrepArgs a, hipStream_t s) {
   }
 }
 
+// Measurement hook state (see sqngd_profile_enable).
+struct Profiler {
+  std::mutex mu;
+  std::vector<hipEvent_t> ev;  // 2 per launch
+  int max = 0, used = 0;
+} g_prof;
+
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
 template <int P>
 void launch_pass_p(const PassArgs& a, int phlog, int waves, hipStream_t s) {
   if (phlog == 3) hipLaunchKernelGGL((k_pass<P, 3>), dim3(waves), dim3(64), 0, s, a);
@@ -312,6 +324,12 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
     a.gn = pl.hdr.group_n[g];
     const int waves = pl.hdr.group_waves[g];
     const int phl = pl.group_phlog[g];
+    int slot = -1;
+    if (g_prof.max > 0 && !stream_capturing(s)) {
+      std::lock_guard<std::mutex> lk(g_prof.mu);
+      if (g_prof.used < g_prof.max) slot = g_prof.used++;
+    }
+    if (slot >= 0) hipEventRecord(g_prof.ev[2 * slot], s);
     switch (g) {
       case 0: launch_pass_p<128>(a, phl, waves, s); break;
       case 1: launch_pass_p<256>(a, phl, waves, s); break;
@@ -319,6 +337,7 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
       case 3: launch_pass_p<1024>(a, phl, waves, s); break;
       default: launch_pass_p<2048>(a, phl, waves, s); break;
     }
+    if (slot >= 0) hipEventRecord(g_prof.ev[2 * slot + 1], s);
   }
 }
 
@@ -352,6 +371,34 @@ const char* sqngd_status_string(int status) {
 }
 
 int sqngd_last_hip_error(void) { return g_last_hip.load(); }
+
+int sqngd_profile_enable(int32_t max_launches) {
+  if (max_launches < 0 || max_launches > (1 << 16)) return SQNGD_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  while ((int)g_prof.ev.size() < 2 * max_launches) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return hip_fail(err);
+    g_prof.ev.push_back(e);
+  }
+  g_prof.max = max_launches;
+  g_prof.used = 0;
+  return SQNGD_OK;
+}
+
+int sqngd_profile_read(float* ms, int32_t capacity, int32_t* count) {
+  if (count == nullptr || (ms == nullptr && capacity > 0) || capacity < 0) return SQNGD_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  const int n = g_prof.used < capacity ? g_prof.used : capacity;
+  for (int i = 0; i < n; ++i) {
+    hipError_t err = hipEventSynchronize(g_prof.ev[2 * i + 1]);
+    if (err != hipSuccess) return hip_fail(err);
+    err = hipEventElapsedTime(&ms[i], g_prof.ev[2 * i], g_prof.ev[2 * i + 1]);
+    if (err != hipSuccess) return hip_fail(err);
+  }
+  *count = g_prof.used;
+  return SQNGD_OK;
+}
 
 int sqngd_buffer_sizes(const sqngd_problem* probs, int32_t nprob, int64_t* z_floats, int64_t* wave_c64,
                        int64_t* adam_floats, int64_t* cube_c64) {

@@ -22,7 +22,7 @@ OPT_SGD = 1
 SYMBOLS = [
     "sqngd_buffer_sizes", "sqngd_workspace_size", "sqngd_workspace_init", "sqngd_af_forward",
     "sqngd_af_backward", "sqngd_step", "sqngd_hard_quantize", "sqngd_status_string",
-    "sqngd_last_hip_error",
+    "sqngd_last_hip_error", "sqngd_profile_enable", "sqngd_profile_read",
 ]
 
 
@@ -74,6 +74,8 @@ def load():
     lib.sqngd_status_string.argtypes = [ctypes.c_int]
     lib.sqngd_status_string.restype = ctypes.c_char_p
     lib.sqngd_last_hip_error.argtypes = []
+    lib.sqngd_profile_enable.argtypes = [i32]
+    lib.sqngd_profile_read.argtypes = [P, i32, P]
     for name in SYMBOLS:
         if name not in ("sqngd_status_string",):
             getattr(lib, name).restype = ctypes.c_int
@@ -89,6 +91,19 @@ def check(rc: int, what: str):
     if rc != OK:
         hip = load().sqngd_last_hip_error()
         raise SQNGDError(f"{what}: {status_string(rc)} (status {rc}, hip error {hip})")
+
+
+def profile_enable(max_launches: int):
+    """Bracket the next max_launches fused-pass launches with HIP events (0: off)."""
+    check(load().sqngd_profile_enable(int(max_launches)), "profile_enable")
+
+
+def profile_read(capacity: int = 65536) -> np.ndarray:
+    """Durations (ms) of the fused-pass launches recorded since profile_enable."""
+    buf = (ctypes.c_float * capacity)()
+    cnt = ctypes.c_int32()
+    check(load().sqngd_profile_read(buf, capacity, ctypes.byref(cnt)), "profile_read")
+    return np.array(buf[: min(cnt.value, capacity)], dtype=np.float64)
 
 
 def make_problems(probs) -> ctypes.Array:

@@ -1,0 +1,119 @@
+"""Driver of the alternating SQNGD iteration (Algorithm 1) on one GPU.
+
+Every outer iteration is one ``sqngd_step`` of the C ABI; the driver owns the
+device tensors (logits, filters, Adam state, step counter, statistics),
+optionally records one iteration in a HIP graph (``torch.cuda.CUDAGraph`` is
+hipGraph on ROCm) and replays it, and saves or restores the complete state.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import inputs as I
+from . import native as nat
+
+
+class SQNGD:
+    """A batch of independent designs optimised together.
+
+    probs: list of problem dicts (inputs.make_problem); opt: option dict
+    (inputs.make_opt); seeds: one seed per problem for the N(0,1) logits, or
+    z0: a list of [M][N][L] float32 arrays to start from instead."""
+
+    def __init__(self, probs, opt: dict, seeds=None, z0=None, device="cuda"):
+        self.batch = nat.Batch(probs, device=device)
+        self.probs = self.batch.probs
+        self.opt_dict = dict(opt)
+        self.opt = nat.make_opt(opt)
+        if z0 is None:
+            seeds = list(range(len(probs))) if seeds is None else list(seeds)
+            z0 = [I.logits(p["M"], p["N"], p["L"], s) for p, s in zip(self.probs, seeds)]
+        self.z = self.batch.pack_z(z0)
+        # filters start as the matched filter of the hard starting waveform
+        # (Algorithm 1's initialisation); |x_m|^2 = N, so the projection of
+        # eq. 32 leaves them unchanged.
+        _, x = self.batch.hard_quantize(self.z, want_idx=False)
+        self.h = x.clone()
+        dev = self.batch.device
+        self.adam = torch.zeros(self.batch.adam_floats, dtype=torch.float32, device=dev)
+        self.counter = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.stats = self.batch.new_stats(2 * self.batch.n)
+        self.graph = None
+
+    # ------------------------------------------------------------------ steps
+    def step(self):
+        """Enqueue one outer iteration on the current stream."""
+        self.batch.step(self.opt, self.z, self.h, self.adam, self.counter, self.stats)
+
+    def capture(self):
+        """Record one outer iteration in a HIP graph; replay() then runs it."""
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    def run(self, iters: int, use_graph: bool = True):
+        if use_graph and self.graph is None:
+            self.capture()
+        for _ in range(iters):
+            if use_graph:
+                self.graph.replay()
+            else:
+                self.step()
+
+    # ------------------------------------------------------------- inspection
+    @property
+    def t(self) -> int:
+        return int(self.counter.item())
+
+    def step_stats(self):
+        """(step A stats, step B stats) of the last iteration, per problem."""
+        st = nat.decode_stats(self.stats.cpu().numpy())
+        n = self.batch.n
+        return st[:n], st[n:]
+
+    def hard_stats(self):
+        """Statistics of the hard-quantised designs with the current filters."""
+        stats = self.batch.af_forward(self.z, self.h, nat.WAVE_HARD)
+        return nat.decode_stats(stats.cpu().numpy())
+
+    def hard_indices(self):
+        idx, _ = self.batch.hard_quantize(self.z, want_x=False)
+        return [self.batch.unpack_w(idx, i).cpu().numpy() for i in range(self.batch.n)]
+
+    # ------------------------------------------------------------- checkpoint
+    def state_dict(self) -> dict:
+        return {"z": self.z.detach().cpu().clone(), "h": self.h.detach().cpu().clone(),
+                "adam": self.adam.detach().cpu().clone(), "counter": self.counter.cpu().clone(),
+                "probs": [dict(p) for p in self.probs], "opt": dict(self.opt_dict)}
+
+    def load_state_dict(self, sd: dict):
+        if [dict(p) for p in sd["probs"]] != self.probs:
+            raise ValueError("checkpoint belongs to another batch")
+        self.z.copy_(sd["z"].to(self.z.device))
+        self.h.copy_(sd["h"].to(self.h.device))
+        self.adam.copy_(sd["adam"].to(self.adam.device))
+        self.counter.copy_(sd["counter"].to(self.counter.device))
+
+    def numpy_state(self, i: int = 0) -> dict:
+        """Problem i's state as float64 / complex128 arrays (oracle layout)."""
+        p = self.probs[i]
+        M, N, L = p["M"], p["N"], p["L"]
+        z = self.batch.unpack_z(self.z, i).cpu().numpy().astype(np.float64)
+        h = self.batch.unpack_w(self.h, i).cpu().numpy().astype(np.complex128)
+        off = 0
+        for j in range(i):
+            q = self.probs[j]
+            off += 2 * q["M"] * q["N"] * q["L"] + 4 * q["M"] * q["N"]
+        a = self.adam[off: off + 2 * M * N * L + 4 * M * N].cpu().numpy().astype(np.float64)
+        mnl = M * N * L
+        state = {"mz": a[:mnl].reshape(M, N, L), "vz": a[mnl:2 * mnl].reshape(M, N, L),
+                 "mh": a[2 * mnl: 2 * mnl + 2 * M * N].reshape(M, N, 2),
+                 "vh": a[2 * mnl + 2 * M * N:].reshape(M, N, 2)}
+        return {"z": z, "h": h, "state": state, "t": self.t}

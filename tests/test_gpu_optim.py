@@ -1,0 +1,198 @@
+"""The alternating iteration on the GPU against the oracle, HIP-graph replays,
+finite differences of the FP32 loss, autograd, non-finite handling and
+checkpoint / resume."""
+import numpy as np
+import pytest
+
+from paper_2604_25728_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_25728_amd import autograd, native, optim
+    native.load()
+    return native, optim, autograd
+
+
+def _rel(a, b):
+    a, b = np.asarray(a).reshape(-1), np.asarray(b).reshape(-1)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("cfg,warm", [("c1", 3), ("c2", 2)])
+def test_step_teacher_forced(ref, mods, cfg, warm):
+    """From the GPU state at iteration t, one oracle iteration matches the GPU's."""
+    nat, optim, _ = mods
+    c = I.config(cfg)
+    prob, opt = c["problem"], c["opt"]
+    print(f"[gpu] teacher-forced step {cfg}", flush=True)
+    run = optim.SQNGD([prob], opt, seeds=[0])
+    for _ in range(warm):
+        run.step()
+    torch.cuda.synchronize()
+    s0 = run.numpy_state(0)
+    run.step()
+    torch.cuda.synchronize()
+    s1 = run.numpy_state(0)
+    sa, sb = run.step_stats()
+    z, h, state, sta, stb = ref.step(prob, opt, s0["z"], s0["h"], s0["state"], s0["t"])
+    assert s1["t"] == s0["t"] + 1
+    assert _rel(s1["h"], h) <= 1e-4
+    assert _rel(s1["z"], z) <= 1e-4
+    assert _rel(s1["state"]["vz"], state["vz"]) <= 1e-3
+    assert abs(sa[0]["loss"] - sta["loss"]) <= 1e-4 * sta["loss"]
+    assert abs(sb[0]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"]
+    assert abs(sa[0]["pslr_db"] - sta["pslr_db"]) <= 0.05
+    np.testing.assert_allclose((np.abs(s1["h"]) ** 2).sum(axis=1), prob["N"], rtol=1e-5)
+
+
+def test_c1_run_matches_oracle_where_margins_are_clear(ref, mods):
+    """The full 200-iteration c1 design: final hard indices equal the oracle's
+    wherever the oracle's top-2 logit margin exceeds 1e-3; final PSL agrees."""
+    nat, optim, _ = mods
+    c = I.config("c1")
+    prob, opt = c["problem"], c["opt"]
+    print("[gpu] c1 full run", flush=True)
+    run = optim.SQNGD([prob], opt, seeds=[0])
+    run.run(opt["total_iters"], use_graph=True)
+    torch.cuda.synchronize()
+    z0 = I.logits(prob["M"], prob["N"], prob["L"], 0).astype(np.float64)
+    z, h = z0, ref.matched_init(z0)
+    state = ref.new_state(prob["M"], prob["N"], prob["L"])
+    for t in range(opt["total_iters"]):
+        z, h, state, _, _ = ref.step(prob, opt, z, h, state, t)
+    srt = np.sort(z, axis=-1)
+    clear = (srt[..., -1] - srt[..., -2]) > 1e-3
+    got = run.hard_indices()[0]
+    want = ref.hard_indices(z)
+    agree = (got == want)[clear].mean()
+    print(f"c1 final: {clear.mean():.3f} of chips clear, agreement {agree:.4f}")
+    assert agree >= 0.99
+    st_gpu = run.hard_stats()[0]
+    st_ref = ref.evaluate(ref.hard_waveform(z), h, prob, False)[0]
+    print("c1 final PSLR gpu", st_gpu["pslr_db"], "oracle", st_ref["pslr_db"])
+    st0 = ref.evaluate(ref.hard_waveform(z0), ref.matched_init(z0), prob, False)[0]
+    assert st_gpu["loss"] < st0["loss"]
+
+
+def test_graph_replay_matches_eager(mods):
+    nat, optim, _ = mods
+    c = I.config("c2")
+    print("[gpu] graph replay vs eager", flush=True)
+    a = optim.SQNGD([c["problem"]], c["opt"], seeds=[1])
+    b = optim.SQNGD([c["problem"]], c["opt"], seeds=[1])
+    a.capture()
+    for i in range(4):
+        a.replay()
+        b.step()
+        torch.cuda.synchronize()
+        _ = (a.z * 2).sum().item()  # eager work between replays
+        assert torch.equal(a.z, b.z) and torch.equal(a.h, b.h), i
+        assert torch.equal(a.counter, b.counter)
+    assert a.t == 4
+
+
+def test_checkpoint_resume_bitwise(mods, tmp_path):
+    nat, optim, _ = mods
+    c = I.config("c1")
+    print("[gpu] checkpoint resume", flush=True)
+    a = optim.SQNGD([c["problem"]], c["opt"], seeds=[2])
+    a.run(5, use_graph=False)
+    path = tmp_path / "ck.pt"
+    torch.save(a.state_dict(), path)
+    a.run(5, use_graph=False)
+    b = optim.SQNGD([c["problem"]], c["opt"], seeds=[99])
+    b.load_state_dict(torch.load(path, weights_only=True))
+    b.run(5, use_graph=False)
+    torch.cuda.synchronize()
+    assert torch.equal(a.z, b.z) and torch.equal(a.h, b.h) and a.t == b.t == 10
+
+
+def test_nonfinite_skips_update(mods):
+    nat, optim, _ = mods
+    c = I.config("c1")
+    print("[gpu] non-finite", flush=True)
+    run = optim.SQNGD([c["problem"]], c["opt"], seeds=[3])
+    run.z[5] = float("nan")   # chip (0, 1): its soft waveform, hence the step-B loss, is NaN
+    z_before = run.z.clone()
+    run.step()
+    torch.cuda.synchronize()
+    sa, sb = run.step_stats()
+    assert sb[0]["nonfinite"] == 1
+    assert sa[0]["nonfinite"] == 0      # the hard waveform ignores the NaN logit
+    same = torch.equal(torch.nan_to_num(run.z, nan=7.0), torch.nan_to_num(z_before, nan=7.0))
+    assert same                          # logits were not updated
+    assert torch.isfinite(run.h).all()
+
+
+def test_finite_differences_c2(mods):
+    """Central differences (step 1e-3) of the FP32 loss on 32 random coordinates."""
+    nat, _, _ = mods
+    prob = I.config("c2")["problem"]
+    M, N, L = prob["M"], prob["N"], prob["L"]
+    print("[gpu] finite differences c2", flush=True)
+    b = nat.Batch([prob])
+    z = b.pack_z([I.logits(M, N, L, 4)])
+    h = b.pack_w([I.complex_gaussian(M, N, 5) * 0.9 + I.unimodular(M, N, 6)])
+    gz, gh, _ = b.af_backward(z, h, nat.WAVE_SOFT)
+    torch.cuda.synchronize()
+    gz, gh = gz.cpu().numpy(), gh.cpu().numpy()
+    rng = np.random.default_rng(7)
+
+    def loss(zz, hh):
+        st = b.af_forward(zz, hh, nat.WAVE_SOFT)
+        return float(st.view(torch.float32)[0, 0].item())
+
+    step = 1e-3
+    gmax_z, gmax_h = np.abs(gz).max(), np.abs(gh).max()
+    for k in range(32):
+        if k % 2 == 0:
+            i = int(rng.integers(gz.size))
+            zp, zm = z.clone(), z.clone()
+            zp[i] += step
+            zm[i] -= step
+            fd = (loss(zp, h) - loss(zm, h)) / (2 * step)
+            an, floor = gz[i], 1e-4 * gmax_z
+        else:
+            i = int(rng.integers(gh.size))
+            part = complex(1, 0) if k % 4 == 1 else complex(0, 1)
+            hp, hm = h.clone(), h.clone()
+            hp[i] += step * part
+            hm[i] -= step * part
+            fd = (loss(z, hp) - loss(z, hm)) / (2 * step)
+            an, floor = (gh[i].real if part.real else gh[i].imag), 1e-4 * gmax_h
+        tol = max(1e-3 * abs(an), floor, 2e-7 / step)
+        assert abs(fd - an) <= tol, (k, i, fd, an, tol)
+
+
+def test_autograd_function(ref, mods):
+    nat, _, ag = mods
+    prob = I.make_problem(2, 48, 4, 5, p=8.0, nu_min=-0.7, nu_max=0.7)
+    print("[gpu] autograd", flush=True)
+    b = nat.Batch([prob])
+    z0 = I.logits(2, 48, 4, 8)
+    h0 = I.complex_gaussian(2, 48, 9)
+    z = b.pack_z([z0]).requires_grad_(True)
+    h = b.pack_w([h0]).requires_grad_(True)
+    loss = ag.af_loss(z, h, b, nat.WAVE_SOFT)
+    (3.0 * loss.sum()).backward()
+    s = ref.soft_waveform(z0.astype(np.float64), 1.0)
+    st, gs, gh = ref.evaluate(s, h0.astype(np.complex128), prob)
+    gz = ref.logit_grad(z0.astype(np.float64), 1.0, gs)
+    assert abs(loss.item() - st["loss"]) <= 1e-4 * st["loss"]
+    assert _rel(z.grad.cpu().numpy(), 3.0 * gz) <= 1e-4
+    assert _rel(h.grad.cpu().numpy(), 3.0 * gh) <= 1e-4
+    # given waveform: gradient with respect to s itself
+    sg = b.pack_w([I.unimodular(2, 48, 10)]).requires_grad_(True)
+    h2 = h.detach().clone().requires_grad_(True)
+    l2 = ag.af_loss(None, h2, b, nat.WAVE_GIVEN, sg)
+    l2.sum().backward()
+    st2, gs2, gh2 = ref.evaluate(sg.detach().cpu().numpy().astype(np.complex128).reshape(2, 48),
+                                 h0.astype(np.complex128), prob)
+    assert _rel(sg.grad.cpu().numpy(), gs2) <= 1e-4
+    assert _rel(h2.grad.cpu().numpy(), gh2) <= 1e-4

@@ -56,22 +56,25 @@ def cube_cells(prob: dict) -> int:
     return prob["M"] ** 2 * prob["F"] * (2 * prob["N"] - 1)
 
 
-def time_graph(run, steps: int, warmup: int):
+def time_graph(run, steps: int, warmup: int, per_graph: int):
+    """ms per outer iteration over `steps` iterations run as graph replays of
+    `per_graph` iterations each (steps is rounded up to a multiple)."""
     import torch
-    run.capture()
-    for _ in range(warmup):
+    run.capture(per_graph)
+    for _ in range(max(1, warmup // per_graph)):
         run.replay()
     torch.cuda.synchronize()
+    reps = max(1, -(-steps // per_graph))
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
-    for _ in range(steps):
+    for _ in range(reps):
         run.replay()
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / steps, wall
+    return e0.elapsed_time(e1) / (reps * per_graph), wall, reps * per_graph
 
 
 def kernel_durations(run, nat, steps: int):
@@ -114,6 +117,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--iters-per-graph", type=int, default=10,
+                    help="outer iterations recorded in one HIP graph (one sqngd_run call)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and copy probes")
@@ -136,9 +141,10 @@ def main():
     log(f"device: {torch.cuda.get_device_name(0)}")
 
     run = optim.SQNGD([prob], opt, seeds=[0])
-    ms_step, wall = time_graph(run, args.steps, args.warmup)
+    ms_step, wall, steps = time_graph(run, args.steps, args.warmup, args.iters_per_graph)
     evals_per_s = 2.0 / (ms_step * 1e-3)
-    log(f"step {ms_step * 1e3:.2f} us ({args.steps} graph replays, wall {wall:.3f} s)")
+    log(f"step {ms_step * 1e3:.2f} us ({steps} iterations in graphs of {args.iters_per_graph}, "
+        f"wall {wall:.3f} s)")
 
     kd = kernel_durations(run, nat, min(args.steps, 200))
     kd_avg_ms = float(kd.mean())
@@ -152,7 +158,7 @@ def main():
     if not args.no_extras:
         R = 64
         runb = optim.SQNGD([prob] * R, opt, seeds=list(range(R)))
-        msb, _ = time_graph(runb, max(10, args.steps // 10), 5)
+        msb, _, _ = time_graph(runb, max(10, args.steps // 10), 5, args.iters_per_graph)
         kdb = kernel_durations(runb, nat, 20)
         extras["batched_restarts"] = {
             "designs": R, "ms_per_step": msb, "evals_per_s": 2.0 * R / (msb * 1e-3),
@@ -179,7 +185,7 @@ def main():
         "value": evals_per_s,
         "unit": "evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
@@ -188,7 +194,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "one SQNGD design, M=4 N=256 L=8 F=129 nu in [-0.5,0.5], all 511 "
-                               "delays, p=16, one filter + one logit update per step, HIP graph",
+                               "delays, p=16, one filter + one logit update per step, HIP graphs of "
+                               f"{args.iters_per_graph} steps",
                    "M": prob["M"], "N": prob["N"], "L": prob["L"], "F": prob["F"],
                    "p": prob["p"], "evals_per_step": 2},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,

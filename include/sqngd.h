@@ -211,6 +211,15 @@ int sqngd_step(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, 
                sqngd_c64* h, float* adam_state, int32_t* step_counter, sqngd_stats* stats, void* ws,
                size_t ws_bytes, void* stream);
 
+/* n_iters consecutive outer iterations, equal to n_iters calls of sqngd_step
+   with the same arguments. Within the call the kernel that applies one update
+   also prepares the inputs of the next evaluation (quantised waveform, partner
+   spectra, mainlobe inner products), so each further iteration costs fewer
+   launches than a separate call. 1 <= n_iters <= 100000. */
+int sqngd_run(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, int32_t n_iters,
+              float* z, sqngd_c64* h, float* adam_state, int32_t* step_counter, sqngd_stats* stats,
+              void* ws, size_t ws_bytes, void* stream);
+
 /* Hard quantisation (the final stage of Algorithm 1): idx[m][n] = argmax_l
    z[m][n][l] with ties to the lowest l, and (if x is not NULL)
    x = exp(j 2 pi idx / L). Either output may be NULL. */

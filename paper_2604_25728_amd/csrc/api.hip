@@ -35,6 +35,10 @@ int log2i(int v) {
 
 bool finite(float v) { return std::isfinite(v); }
 
+// waves per block of the latency variant of the fused pass
+constexpr int split_waves(int P) { return P == 512 ? 8 : 8; }
+constexpr double kSplitMaxWaves = 8192.0;
+
 int validate_problem(const sqngd_problem& p) {
   if (p.M < 1 || p.N < 2 || p.L < 2 || p.F < 1) return SQNGD_E_INVALID_ARG;
   if (p.M > 16 || p.N > 1024 || p.L > 64 || p.F > 4096) return SQNGD_E_UNSUPPORTED;
@@ -68,6 +72,8 @@ struct Plan {
   std::vector<char> bytes;  // [0, hdr.spec): header, plans, tables
   std::vector<ProbPlan> plans;
   int group_phlog[kNumPGroups];
+  int maxN = 0;
+  bool split = false;  // the fused pass runs as k_pass_split (small batches)
   uint64_t hash = 0;
 };
 
@@ -88,6 +94,17 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
   H.nprob = nprob;
   pl->plans.resize(nprob);
   std::vector<int> gprob[kNumPGroups];
+  // Small batches of P = 512 or 1024 problems run the latency variant of the
+  // fused pass (one wave per Doppler bin and partner).
+  bool split = true;
+  double pair_waves = 0.0;
+  for (int i = 0; i < nprob; ++i) {
+    const int P = fft_len(probs[i].N);
+    if ((P != 512 && P != 1024) || probs[i].M > split_waves(P)) split = false;
+    pair_waves += (double)probs[i].M * probs[i].M * probs[i].F;
+  }
+  if (pair_waves > kSplitMaxWaves) split = false;
+  pl->split = split;
   int64_t off_z = 0, off_w = 0, off_state = 0, off_cube = 0, spec = 0, unit = 0, upart = 0;
   int rows = 0;
   for (int i = 0; i < nprob; ++i) {
@@ -116,6 +133,17 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
       if (p.p == 2.0f * (float)(1 << k)) q.ph_log = k;
     q.units = p.M * p.F;
     q.row0 = rows;
+    {
+      int upb;  // Doppler bins per fused-pass block
+      if (split) {
+        upb = split_waves(q.P) / p.M;
+      } else {
+        const int TF = q.P >= 512 ? 64 : q.P / 8;
+        upb = kPassWaves * (64 / TF);
+      }
+      q.wpr = (p.F + upb - 1) / upb;
+    }
+    q.units = p.M * q.wpr;
     q.off_z = off_z;
     q.off_w = off_w;
     q.off_state = off_state;
@@ -129,7 +157,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     off_cube += (int64_t)p.M * p.M * p.F * (2 * p.N - 1);
     spec += (int64_t)p.M * q.P;
     unit += q.units;
-    upart += (int64_t)q.units * p.N;
+    upart += (int64_t)q.units * p.N;  // one partial row per fused-pass block
     rows += p.M;
     gprob[q.logP - kMinLogP].push_back(i);
   }
@@ -149,7 +177,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     for (int id : gprob[g]) {
       wave[g].push_back(wsum);
       rwave[g].push_back(rsum);
-      wsum += (pl->plans[id].units + slots - 1) / slots;
+      wsum += pl->plans[id].M * pl->plans[id].wpr;
       rsum += (pl->plans[id].M + slots - 1) / slots;
       phl = (phl == -2 || phl == pl->plans[id].ph_log) ? pl->plans[id].ph_log : -1;
     }
@@ -164,9 +192,15 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     off = align_up(off + 4 * wave[g].size());
     H.group_rwave[g] = (int64_t)off;
     off = align_up(off + 4 * rwave[g].size());
+    int nr = 0;
+    for (int id : gprob[g]) nr += pl->plans[id].M;
+    H.group_nrows[g] = nr;
+    H.group_rows[g] = (int64_t)off;
+    off = align_up(off + 4 * (size_t)nr);
   }
   H.row_prob = (int64_t)off;
   off = align_up(off + 4 * (size_t)rows);
+  // counters live in the uploaded table region, so the upload zeroes them
   H.counters = (int64_t)off;
   off = align_up(off + 4 * kNumCounters);
   const size_t table_bytes = off;
@@ -181,8 +215,11 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
   H.upart = (int64_t)off;
   off = align_up(off + 8 * (size_t)upart);
   H.snrl = (int64_t)off;
-  off = align_up(off + 16 * (size_t)rows);
+  off = align_up(off + 2 * 16 * (size_t)rows);
   H.total = (int64_t)off;
+  int maxN = 0;
+  for (int i = 0; i < nprob; ++i) maxN = probs[i].N > maxN ? probs[i].N : maxN;
+  pl->maxN = maxN;
 
   pl->bytes.assign(table_bytes, 0);
   char* b = pl->bytes.data();
@@ -191,6 +228,10 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     if (!gprob[g].empty()) std::memcpy(b + H.group_prob[g], gprob[g].data(), 4 * gprob[g].size());
     std::memcpy(b + H.group_wave[g], wave[g].data(), 4 * wave[g].size());
     std::memcpy(b + H.group_rwave[g], rwave[g].data(), 4 * rwave[g].size());
+    std::vector<int32_t> gr;
+    for (int id : gprob[g])
+      for (int m = 0; m < pl->plans[id].M; ++m) gr.push_back(pl->plans[id].row0 + m);
+    if (!gr.empty()) std::memcpy(b + H.group_rows[g], gr.data(), 4 * gr.size());
   }
   std::vector<int32_t> rp(rows);
   for (int i = 0; i < nprob; ++i)
@@ -276,7 +317,9 @@ void launch_prep(const Plan& pl, const Ptrs& w, PrepArgs a, hipStream_t s) {
   a.spec = w.spec;
   a.wself = w.wself;
   a.wpart = w.wpart;
-  a.snrl = w.snrl;
+  if (a.snrl == nullptr) a.snrl = w.snrl;
+  a.single = pl.hdr.nprob == 1;
+  a.one = pl.plans[0];
   for (int g = 0; g < kNumPGroups; ++g) {
     if (pl.hdr.group_n[g] == 0) continue;
     a.gprob = (const int32_t*)(w.base + pl.hdr.group_prob[g]);
@@ -306,10 +349,20 @@ bool stream_capturing(hipStream_t s) {
 }
 
 template <int P>
+void launch_split_p(const PassArgs& a, int phlog, int blocks, hipStream_t s) {
+  constexpr int WV = split_waves(P);
+  const dim3 block(64 * WV);
+  if (phlog == 3) hipLaunchKernelGGL((k_pass_split<P, 3, WV>), dim3(blocks), block, 0, s, a);
+  else if (phlog == 2) hipLaunchKernelGGL((k_pass_split<P, 2, WV>), dim3(blocks), block, 0, s, a);
+  else hipLaunchKernelGGL((k_pass_split<P, -1, WV>), dim3(blocks), block, 0, s, a);
+}
+
+template <int P>
 void launch_pass_p(const PassArgs& a, int phlog, int waves, hipStream_t s) {
-  if (phlog == 3) hipLaunchKernelGGL((k_pass<P, 3>), dim3(waves), dim3(64), 0, s, a);
-  else if (phlog == 2) hipLaunchKernelGGL((k_pass<P, 2>), dim3(waves), dim3(64), 0, s, a);
-  else hipLaunchKernelGGL((k_pass<P, -1>), dim3(waves), dim3(64), 0, s, a);
+  const dim3 block(64 * kPassWaves);
+  if (phlog == 3) hipLaunchKernelGGL((k_pass<P, 3>), dim3(waves), block, 0, s, a);
+  else if (phlog == 2) hipLaunchKernelGGL((k_pass<P, 2>), dim3(waves), block, 0, s, a);
+  else hipLaunchKernelGGL((k_pass<P, -1>), dim3(waves), block, 0, s, a);
 }
 
 void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
@@ -317,6 +370,8 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
   a.spec = w.spec;
   a.ustat = w.ustat;
   a.upart = w.upart;
+  a.single = pl.hdr.nprob == 1;
+  a.one = pl.plans[0];
   for (int g = 0; g < kNumPGroups; ++g) {
     if (pl.hdr.group_n[g] == 0) continue;
     a.gprob = (const int32_t*)(w.base + pl.hdr.group_prob[g]);
@@ -330,12 +385,17 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
       if (g_prof.used < g_prof.max) slot = g_prof.used++;
     }
     if (slot >= 0) hipEventRecord(g_prof.ev[2 * slot], s);
-    switch (g) {
-      case 0: launch_pass_p<128>(a, phl, waves, s); break;
-      case 1: launch_pass_p<256>(a, phl, waves, s); break;
-      case 2: launch_pass_p<512>(a, phl, waves, s); break;
-      case 3: launch_pass_p<1024>(a, phl, waves, s); break;
-      default: launch_pass_p<2048>(a, phl, waves, s); break;
+    if (pl.split) {
+      if (g == 2) launch_split_p<512>(a, phl, waves, s);
+      else launch_split_p<1024>(a, phl, waves, s);
+    } else {
+      switch (g) {
+        case 0: launch_pass_p<128>(a, phl, waves, s); break;
+        case 1: launch_pass_p<256>(a, phl, waves, s); break;
+        case 2: launch_pass_p<512>(a, phl, waves, s); break;
+        case 3: launch_pass_p<1024>(a, phl, waves, s); break;
+        default: launch_pass_p<2048>(a, phl, waves, s); break;
+      }
     }
     if (slot >= 0) hipEventRecord(g_prof.ev[2 * slot + 1], s);
   }
@@ -344,12 +404,27 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
 void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
   a.plans = w.plans;
   a.row_prob = w.row_prob;
-  a.nrows = pl.hdr.nrows;
+  a.nrows_total = pl.hdr.nrows;
   a.ustat = w.ustat;
   a.upart = w.upart;
-  a.snrl = w.snrl;
+  a.wself = w.wself;
+  a.wpart = w.wpart;
+  a.spec = w.spec;
   a.done = w.counters;
-  hipLaunchKernelGGL(k_final, dim3(pl.hdr.nrows), dim3(kFinThreads), 0, s, a);
+  a.single = pl.hdr.nprob == 1;
+  a.one = pl.plans[0];
+  for (int g = 0; g < kNumPGroups; ++g) {
+    if (pl.hdr.group_nrows[g] == 0) continue;
+    a.rows = (const int32_t*)(w.base + pl.hdr.group_rows[g]);
+    const dim3 grid(pl.hdr.group_nrows[g]), block(kFinThreads);
+    switch (g) {
+      case 0: hipLaunchKernelGGL(k_final<128>, grid, block, 0, s, a); break;
+      case 1: hipLaunchKernelGGL(k_final<256>, grid, block, 0, s, a); break;
+      case 2: hipLaunchKernelGGL(k_final<512>, grid, block, 0, s, a); break;
+      case 3: hipLaunchKernelGGL(k_final<1024>, grid, block, 0, s, a); break;
+      default: hipLaunchKernelGGL(k_final<2048>, grid, block, 0, s, a); break;
+    }
+  }
 }
 
 }  // namespace
@@ -443,9 +518,7 @@ int sqngd_workspace_init(const sqngd_problem* probs, int32_t nprob, void* ws, si
   }
   hipError_t e = hipMemcpyAsync(ws, raw->bytes.data(), raw->bytes.size(), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e);
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, (int32_t*)((char*)ws + raw->hdr.counters),
-                     kNumCounters);
-  return check_launch();
+  return SQNGD_OK;
 }
 
 int sqngd_af_forward(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t wave_mode,
@@ -477,8 +550,7 @@ int sqngd_af_forward(const sqngd_problem* probs, int32_t nprob, const float* z, 
   FinArgs fa{};
   fa.orient = 0;
   fa.mode = FIN_STATS;
-  fa.self_w = w.wself;
-  fa.part_w = (const float2*)h;
+  fa.snrl = w.snrl;
   fa.stats = stats;
   launch_final(*pl, w, fa, s);
   return check_launch();
@@ -501,11 +573,14 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
   if (rc != SQNGD_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
   Ptrs w = ptrs(*pl, ws);
+  float4* snrl0 = w.snrl;
+  float4* snrl1 = w.snrl + pl->hdr.nrows;
   PrepArgs pa{};
   pa.mode = wave_mode == SQNGD_WAVE_SOFT ? PREP_B_SOFT : (wave_mode == SQNGD_WAVE_HARD ? PREP_B_HARD : PREP_B_GIVEN);
   pa.z = z;
   pa.s_given = (const float2*)s_given;
   pa.h = (const float2*)h;
+  pa.snrl = snrl0;
   launch_prep(*pl, w, pa, s);
   // waveform side (orientation 0)
   PassArgs ka{};
@@ -519,6 +594,7 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
   fa.wave_mode = wave_mode;
   fa.self_w = w.wself;
   fa.part_w = (const float2*)h;
+  fa.snrl = snrl0;
   fa.stats = stats;
   fa.grad_loss = grad_loss;
   fa.grad_w = (float2*)grad_s;
@@ -530,6 +606,7 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
     PrepArgs pb{};
     pb.mode = PREP_A_SELF;
     pb.h = (const float2*)h;
+    pb.snrl = snrl1;
     launch_prep(*pl, w, pb, s);
     PassArgs kb{};
     kb.orient = 1;
@@ -542,6 +619,7 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
     fb.wave_mode = SQNGD_WAVE_GIVEN;
     fb.self_w = (const float2*)h;
     fb.part_w = w.wself;
+    fb.snrl = snrl1;
     fb.grad_loss = grad_loss;
     fb.grad_w = (float2*)grad_h;
     launch_final(*pl, w, fb, s);
@@ -549,11 +627,8 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
   return check_launch();
 }
 
-int sqngd_step(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, float* z, sqngd_c64* h,
-               float* adam_state, int32_t* step_counter, sqngd_stats* stats, void* ws, size_t ws_bytes,
-               void* stream) {
-  if (opt == nullptr || z == nullptr || h == nullptr || adam_state == nullptr || step_counter == nullptr)
-    return SQNGD_E_INVALID_ARG;
+static int validate_opt(const sqngd_opt* opt) {
+  if (opt == nullptr) return SQNGD_E_INVALID_ARG;
   const sqngd_opt& o = *opt;
   if (!finite(o.lr_z) || !finite(o.lr_h) || o.lr_z < 0.f || o.lr_h < 0.f) return SQNGD_E_INVALID_ARG;
   if (!(o.beta1 >= 0.f && o.beta1 < 1.f && o.beta2 >= 0.f && o.beta2 < 1.f)) return SQNGD_E_INVALID_ARG;
@@ -561,68 +636,100 @@ int sqngd_step(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, 
   if (o.n_h < 0 || o.n_x < 0 || o.n_h + o.n_x < 1 || o.n_h > 1000 || o.n_x > 1000) return SQNGD_E_INVALID_ARG;
   if (!finite(o.T0) || !finite(o.T1) || o.T0 <= 0.f || o.T1 <= 0.f || o.total_iters < 1) return SQNGD_E_INVALID_ARG;
   if ((o.flags & ~SQNGD_OPT_SGD) != 0) return SQNGD_E_INVALID_ARG;
+  return SQNGD_OK;
+}
+
+int sqngd_run(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, int32_t n_iters, float* z,
+              sqngd_c64* h, float* adam_state, int32_t* step_counter, sqngd_stats* stats, void* ws,
+              size_t ws_bytes, void* stream) {
+  int rc = validate_opt(opt);
+  if (rc != SQNGD_OK) return rc;
+  if (n_iters < 1 || n_iters > 100000) return SQNGD_E_INVALID_ARG;
+  if (z == nullptr || h == nullptr || adam_state == nullptr || step_counter == nullptr) return SQNGD_E_INVALID_ARG;
   if (!aligned(z, 4) || !aligned(h, 8) || !aligned(adam_state, 4) || !aligned(step_counter, 4) ||
       !aligned(stats, 4))
     return SQNGD_E_ALIGN;
   const Plan* pl = nullptr;
-  int rc = lookup(probs, nprob, ws, ws_bytes, &pl);
+  rc = lookup(probs, nprob, ws, ws_bytes, &pl);
   if (rc != SQNGD_OK) return rc;
+  const sqngd_opt& o = *opt;
   hipStream_t s = (hipStream_t)stream;
   Ptrs w = ptrs(*pl, ws);
-  for (int i = 0; i < o.n_h; ++i) {
-    PrepArgs pa{};
-    pa.mode = PREP_A_HARD;
-    pa.z = z;
-    pa.h = (const float2*)h;
-    launch_prep(*pl, w, pa, s);
-    PassArgs ka{};
-    ka.orient = 1;
-    ka.want_grad = 1;
-    ka.self_w = (const float2*)h;
-    launch_pass(*pl, w, ka, s);
-    FinArgs fa{};
-    fa.orient = 1;
-    fa.mode = FIN_STEP_A;
-    fa.inner = i;
-    fa.count_step = (o.n_x == 0 && i == o.n_h - 1) ? 1 : 0;
-    fa.self_w = (const float2*)h;
-    fa.part_w = w.wpart;
-    fa.stats = stats;
-    fa.h = (float2*)h;
-    fa.adam = adam_state;
-    fa.counter = step_counter;
-    fa.opt = o;
-    launch_final(*pl, w, fa, s);
-  }
-  for (int j = 0; j < o.n_x; ++j) {
-    PrepArgs pa{};
-    pa.mode = PREP_B_SOFT;
-    pa.use_schedule = 1;
-    pa.opt = o;
-    pa.counter = step_counter;
-    pa.z = z;
-    pa.h = (const float2*)h;
-    launch_prep(*pl, w, pa, s);
-    PassArgs ka{};
-    ka.orient = 0;
-    ka.want_grad = 1;
-    ka.self_w = w.wself;
-    launch_pass(*pl, w, ka, s);
-    FinArgs fa{};
-    fa.orient = 0;
-    fa.mode = FIN_STEP_B;
-    fa.inner = j;
-    fa.count_step = (j == o.n_x - 1) ? 1 : 0;
-    fa.self_w = w.wself;
-    fa.part_w = (const float2*)h;
-    fa.stats = stats ? stats + nprob : nullptr;
-    fa.z = z;
-    fa.adam = adam_state;
-    fa.counter = step_counter;
-    fa.opt = o;
-    launch_final(*pl, w, fa, s);
+  float4* snrl_buf[2] = {w.snrl, w.snrl + pl->hdr.nrows};
+  int q = 0;  // pass index within the call: pass q reads snrl_buf[q & 1]
+  // inputs of the first pass
+  PrepArgs pa{};
+  pa.mode = o.n_h > 0 ? PREP_A_HARD : PREP_B_SOFT;
+  pa.use_schedule = 1;
+  pa.opt = o;
+  pa.counter = step_counter;
+  pa.z = z;
+  pa.h = (const float2*)h;
+  pa.snrl = snrl_buf[0];
+  launch_prep(*pl, w, pa, s);
+  for (int it = 0; it < n_iters; ++it) {
+    const bool more = it + 1 < n_iters;
+    for (int i = 0; i < o.n_h; ++i, ++q) {
+      PassArgs ka{};
+      ka.orient = 1;
+      ka.want_grad = 1;
+      ka.self_w = (const float2*)h;
+      launch_pass(*pl, w, ka, s);
+      FinArgs fa{};
+      fa.orient = 1;
+      fa.mode = FIN_STEP_A;
+      fa.inner = i;
+      fa.count_step = (o.n_x == 0 && i == o.n_h - 1) ? 1 : 0;
+      fa.next = i + 1 < o.n_h ? NEXT_A_SNRL : (o.n_x > 0 ? NEXT_B_FULL : (more ? NEXT_A_SNRL : NEXT_NONE));
+      fa.self_w = (const float2*)h;
+      fa.part_w = w.wpart;
+      fa.snrl = snrl_buf[q & 1];
+      fa.snrl_next = snrl_buf[(q + 1) & 1];
+      fa.stats = stats;
+      fa.z = z;
+      fa.h = (float2*)h;
+      fa.adam = adam_state;
+      fa.counter = step_counter;
+      fa.opt = o;
+      launch_final(*pl, w, fa, s);
+    }
+    for (int j = 0; j < o.n_x; ++j, ++q) {
+      PassArgs ka{};
+      ka.orient = 0;
+      ka.want_grad = 1;
+      ka.self_w = w.wself;
+      launch_pass(*pl, w, ka, s);
+      FinArgs fa{};
+      fa.orient = 0;
+      fa.mode = FIN_STEP_B;
+      fa.inner = j;
+      fa.count_step = (j == o.n_x - 1) ? 1 : 0;
+      if (j + 1 < o.n_x) {
+        fa.next = NEXT_B_SOFT;
+      } else if (more) {
+        fa.next = o.n_h > 0 ? NEXT_A_FULL : NEXT_B_SOFT;
+        fa.next_t_offset = 1;
+      }
+      fa.self_w = w.wself;
+      fa.part_w = (const float2*)h;
+      fa.snrl = snrl_buf[q & 1];
+      fa.snrl_next = snrl_buf[(q + 1) & 1];
+      fa.stats = stats ? stats + nprob : nullptr;
+      fa.z = z;
+      fa.h = (float2*)h;
+      fa.adam = adam_state;
+      fa.counter = step_counter;
+      fa.opt = o;
+      launch_final(*pl, w, fa, s);
+    }
   }
   return check_launch();
+}
+
+int sqngd_step(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, float* z, sqngd_c64* h,
+               float* adam_state, int32_t* step_counter, sqngd_stats* stats, void* ws, size_t ws_bytes,
+               void* stream) {
+  return sqngd_run(probs, nprob, opt, 1, z, h, adam_state, step_counter, stats, ws, ws_bytes, stream);
 }
 
 int sqngd_hard_quantize(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t* idx, sqngd_c64* x,

@@ -132,6 +132,34 @@ __device__ __forceinline__ void dft_reg(float2 (&x)[CAP]) {
   }
 }
 
+// Reductions over the TF lanes of a slot with DPP row operations (VALU
+// speed); the result is returned in every lane of the slot.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float old, float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
+}
+template <int TF, class Op>
+__device__ __forceinline__ float slot_reduce(float v, float ident, Op op) {
+  v = op(v, dpp_f<0x111, 0xF>(ident, v));  // row_shr:1
+  v = op(v, dpp_f<0x112, 0xF>(ident, v));  // row_shr:2
+  v = op(v, dpp_f<0x114, 0xF>(ident, v));  // row_shr:4
+  v = op(v, dpp_f<0x118, 0xF>(ident, v));  // row_shr:8  -> lane 15 of each row holds the row
+  if constexpr (TF >= 32) v = op(v, dpp_f<0x142, 0xA>(ident, v));  // row_bcast:15 -> lanes 31, 63
+  if constexpr (TF >= 64) {
+    v = op(v, dpp_f<0x143, 0xC>(ident, v));  // row_bcast:31 -> lane 63
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+  } else {
+    const int lane = __lane_id();
+    return __shfl(v, (lane & ~(TF - 1)) + TF - 1);
+  }
+}
+struct OpMax {
+  __device__ __forceinline__ float operator()(float a, float b) const { return fmaxf(a, b); }
+};
+struct OpAdd {
+  __device__ __forceinline__ float operator()(float a, float b) const { return a + b; }
+};
+
 // Wave-scope ordering of LDS traffic: every lane's earlier LDS accesses are
 // complete and visible to the wave before any later one starts.
 __device__ __forceinline__ void wave_lds_sync() {
@@ -141,26 +169,6 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // ------------------------------------------------------------------ twiddles
-
-// W_2048^k = exp(-2 pi i k / 2048), k < 2048, rounded from double precision at
-// compile time. A length-P twiddle W_P^k is entry k * (2048 / P).
-struct TwiddleTable {
-  float2 w[2048];
-};
-constexpr TwiddleTable make_twiddles() {
-  TwiddleTable t{};
-  for (int k = 0; k < 2048; ++k) {
-    double a = 2.0 * cx_pi * (double)k / 2048.0;
-    t.w[k] = float2{(float)cx_cos(a), (float)(-cx_sin(a))};
-  }
-  return t;
-}
-__constant__ const TwiddleTable kTw = make_twiddles();
-
-template <int P>
-__device__ __forceinline__ float2 tw(int k) {  // W_P^k, any integer k >= 0
-  return kTw.w[(k & (P - 1)) * (2048 / P)];
-}
 
 // ------------------------------------------------------------------ geometry
 
@@ -181,7 +189,17 @@ struct Geom {
   }
 };
 
-// Per-lane twiddles reused by every FFT of the wave.
+// exp(-2 pi i k / P) for an integer k, from one sincospi of the reduced angle.
+template <int P>
+__device__ __forceinline__ float2 tw_exact(int k) {
+  float s, c;
+  sincospif(2.0f * (float)(k & (P - 1)) / (float)P, &s, &c);
+  return make_float2(c, -s);
+}
+
+// Per-lane twiddles reused by every FFT of the wave. A few are evaluated with
+// sincospi and the rest formed as products of at most two of them (error a
+// few ulp), so no table is read from memory at kernel start.
 template <int P>
 struct WaveTwiddles {
   using G = Geom<P>;
@@ -191,10 +209,30 @@ struct WaveTwiddles {
   float2 hi[NHI];  // W_P^(t NLO a),    a < NHI     (W_P^(t k1) = lo[k1 % NLO] hi[k1 / NLO])
   float2 col[G::A];  // W_TF^(beta gamma), gamma < A, beta = t % B
   __device__ __forceinline__ void init(int t) {
-    for (int b = 0; b < NLO; ++b) lo[b] = tw<P>(t * b);
-    for (int a = 0; a < NHI; ++a) hi[a] = tw<P>(t * NLO * a);
+    // lo: powers 1, 2, 4 exact; 3, 5, 6, 7 as products
+    lo[0] = make_float2(1.f, 0.f);
+    if constexpr (NLO > 1) lo[1] = tw_exact<P>(t);
+    if constexpr (NLO > 2) lo[2] = tw_exact<P>(2 * t);
+    if constexpr (NLO > 3) lo[3] = cmul(lo[2], lo[1]);
+    if constexpr (NLO > 4) {
+      lo[4] = tw_exact<P>(4 * t);
+      lo[5] = cmul(lo[4], lo[1]);
+      lo[6] = cmul(lo[4], lo[2]);
+      lo[7] = cmul(lo[4], lo[3]);
+    }
+    hi[0] = make_float2(1.f, 0.f);
+    for (int a = 1; a < NHI; ++a) hi[a] = tw_exact<P>(t * NLO * a);
     const int beta = t % G::B;
-    for (int g = 0; g < G::A; ++g) col[g] = tw<P>(beta * g * G::E);
+    col[0] = make_float2(1.f, 0.f);
+    if constexpr (G::A > 1) col[1] = tw_exact<P>(beta * G::E);
+    if constexpr (G::A > 2) col[2] = tw_exact<P>(2 * beta * G::E);
+    if constexpr (G::A > 3) col[3] = cmul(col[2], col[1]);
+    if constexpr (G::A > 4) {
+      col[4] = tw_exact<P>(4 * beta * G::E);
+      col[5] = cmul(col[4], col[1]);
+      col[6] = cmul(col[4], col[2]);
+      col[7] = cmul(col[4], col[3]);
+    }
   }
   template <int K1>
   __device__ __forceinline__ float2 step2(float2 v, bool inverse) const {

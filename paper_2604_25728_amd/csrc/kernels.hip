@@ -170,6 +170,8 @@ struct PrepArgs {
   float2* wpart;
   float2* spec;
   float4* snrl;  // per row: (Re, Im) of sum_n conj(part(n)) self(n), |self|^2, |part|^2
+  int32_t single;  // one problem: its plan is `one`, no table lookups
+  ProbPlan one;
 };
 
 template <int P>
@@ -178,9 +180,16 @@ __global__ __launch_bounds__(64) void k_prep(PrepArgs a) {
   constexpr int E = G::E, TF = G::TF, EH = E / 2;
   __shared__ float2 lds[G::LDS];
   const int lane = threadIdx.x, slot = lane / TF, t = lane % TF;
-  const int entry = find_entry(a.grwave, a.gn, blockIdx.x);
-  const ProbPlan pl = a.plans[a.gprob[entry]];
-  const int row = (blockIdx.x - a.grwave[entry]) * G::SLOTS + slot;
+  int base = 0;
+  ProbPlan pl;
+  if (a.single) {
+    pl = a.one;
+  } else {
+    const int entry = find_entry(a.grwave, a.gn, blockIdx.x);
+    pl = a.plans[a.gprob[entry]];
+    base = a.grwave[entry];
+  }
+  const int row = (blockIdx.x - base) * G::SLOTS + slot;
   const bool active = row < pl.M;
   const int g = active ? row : pl.M - 1;
   const int N = pl.N, L = pl.L;
@@ -259,22 +268,42 @@ struct PassArgs {
   UnitStat* ustat;
   float2* upart;
   float2* cube;  // orientation 0 only, may be null
+  int32_t single;  // one problem: its plan is `one`, no table lookups
+  ProbPlan one;
 };
 
+constexpr int kPassWaves = 4;  // waves per block of the fused pass
+
 template <int P, int PHLOG>
-__global__ __launch_bounds__(64) void k_pass(PassArgs a) {
+__global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
   using G = Geom<P>;
-  constexpr int E = G::E, TF = G::TF, EH = E / 2;
-  __shared__ float2 lds[G::LDS];
-  const int lane = threadIdx.x, slot = lane / TF, t = lane % TF;
-  float2* buf = lds + slot * P;
-  const int entry = find_entry(a.gwave, a.gn, blockIdx.x);
-  const ProbPlan pl = a.plans[a.gprob[entry]];
+  constexpr int E = G::E, TF = G::TF, EH = E / 2, SL = G::SLOTS;
+  constexpr int UPB = kPassWaves * SL;  // units (Doppler bins of one row) per block
+  __shared__ float2 lds[kPassWaves * G::LDS];
+  __shared__ float u_sig[UPB], u_S[UPB];
+  __shared__ unsigned long long u_ka[UPB], u_kc[UPB];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, slot = lane / TF, t = lane % TF;
+  float2* buf = lds + wv * G::LDS + slot * P;
+  int base = 0;
+  ProbPlan pl;
+  if (a.single) {
+    pl = a.one;
+  } else {
+    const int entry = find_entry(a.gwave, a.gn, blockIdx.x);
+    pl = a.plans[a.gprob[entry]];
+    base = a.gwave[entry];
+  }
   const int M = pl.M, N = pl.N, F = pl.F;
-  const int unit = (blockIdx.x - a.gwave[entry]) * G::SLOTS + slot;
-  const bool active = unit < pl.units;
-  const int u = active ? unit : pl.units - 1;
-  const int w = u / F, f = u - w * F;
+  // blocks of a problem: wpr per row, rows in order; a block covers UPB
+  // consecutive Doppler bins of one row, one per slot
+  const int lb = blockIdx.x - base;
+  const int w = lb / pl.wpr;
+  const int grp = lb - w * pl.wpr;
+  const int uslot = wv * SL + slot;
+  const int fs = grp * UPB + uslot;
+  const bool active = fs < F;
+  const int f = active ? fs : F - 1;
+  const int u = w * F + f;
   const float invN = 1.0f / (float)N;
   const float nu = (a.orient ? -1.0f : 1.0f) * (pl.nu_min + (float)f * pl.dnu);
   const int wlo = a.orient ? -pl.tau_hi : pl.tau_lo;
@@ -285,40 +314,76 @@ __global__ __launch_bounds__(64) void k_pass(PassArgs a) {
   WaveTwiddles<P> W;
   W.init(t);
 
-  // Doppler-modulated self sequence, zero-padded to P (eq. 33, 35), and its FFT.
-  float2 X[E];
-  const float2* sw = a.self_w + pl.off_w + (int64_t)w * N;
-  static_for<E>([&](auto ec) {
-    constexpr int e = decltype(ec)::value;
-    X[e] = make_float2(0.f, 0.f);
-    if constexpr (e < EH) {
-      const int n = t + TF * e;
-      if (n < N) X[e] = cmul(sw[n], phasor(n, nu, invN));
-    }
-  });
-  fft_forward<P>(X, buf, t, W);
-
-  float2 U[E];
-  static_for<E>([&](auto ec) { U[decltype(ec)::value] = make_float2(0.f, 0.f); });
-  float sigma = 0.f, S = 0.f;
-  unsigned long long kauto = 0, kcross = 0;
+  // The pass is a sequence of 2M+2 transforms (M+1 without the gradient):
+  //   SELF  forward FFT of the Doppler-modulated self sequence (eq. 33, 35)
+  //   PAIR  inverse FFT of X conj(H_g): the AF row of partner g (eq. 36)
+  //   ADJ   forward FFT of the scaled adjoint of that row
+  //   UINV  inverse FFT of the accumulated adjoint spectra
+  // run as one loop over a single forward and a single inverse transform, so
+  // the code each wave streams through the instruction cache stays small.
+  enum Op { OP_SELF, OP_PAIR, OP_ADJ, OP_UINV };
+  constexpr bool kKeepSG = E <= 8;  // the partner spectrum stays in registers for both uses
   const float2* spec = a.spec + pl.ws_spec;
+  const float2* sw = a.self_w + pl.off_w + (int64_t)w * N;
   float2* cube = a.cube ? a.cube + pl.off_cube : nullptr;
   const float invP = 1.0f / (float)P;
   const int T2 = 2 * N - 1;
-
-  for (int g = 0; g < M; ++g) {
-    const float2* sg = spec + (int64_t)g * P;
-    float2 R[E];
+  float2 X[E], U[E], R[E], SG[kKeepSG ? E : 1];
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    R[e] = make_float2(0.f, 0.f);
+    U[e] = make_float2(0.f, 0.f);
+    if constexpr (e < EH) {
+      const int n = t + TF * e;
+      if (n < N) R[e] = cmul(sw[n], phasor(n, nu, invN));
+    }
+  });
+  float sigma = 0.f, S = 0.f;
+  unsigned long long kauto = 0, kcross = 0;  // per lane; reduced once per unit
+  int g = 0;
+  const float2* sg = spec;
+  auto start_pair = [&]() {  // R = X conj(H_g)
+    sg = spec + (int64_t)g * P;
     static_for<E>([&](auto ec) {
       constexpr int e = decltype(ec)::value;
-      R[e] = cmulc(X[e], sg[e * TF + t]);
+      if constexpr (kKeepSG) {
+        SG[e] = sg[e * TF + t];
+        R[e] = cmulc(X[e], SG[e]);
+      } else {
+        R[e] = cmulc(X[e], sg[e * TF + t]);
+      }
     });
-    fft_inverse<P>(R, buf, t, W);  // R[e] = P * A(tau') at r-index k = t + TF e
-
-    // ROI cells: r-index k holds tau' = -k (k < N) or P - k (k > P - N).
+  };
+  for (int op = OP_SELF;;) {
+    if (op == OP_PAIR || op == OP_UINV) fft_inverse<P>(R, buf, t, W);
+    else fft_forward<P>(R, buf, t, W);
+    if (op == OP_UINV) break;
+    if (op == OP_SELF) {
+      static_for<E>([&](auto ec) { X[decltype(ec)::value] = R[decltype(ec)::value]; });
+      start_pair();
+      op = OP_PAIR;
+      continue;
+    }
+    if (op == OP_ADJ) {
+      static_for<E>([&](auto ec) {
+        constexpr int e = decltype(ec)::value;
+        if constexpr (kKeepSG) U[e] = cadd(U[e], cmul(R[e], SG[e]));
+        else U[e] = cadd(U[e], cmul(R[e], sg[e * TF + t]));
+      });
+      if (++g < M) {
+        start_pair();
+        op = OP_PAIR;
+      } else {
+        static_for<E>([&](auto ec) { R[decltype(ec)::value] = U[decltype(ec)::value]; });
+        op = OP_UINV;
+      }
+      continue;
+    }
+    // OP_PAIR: R[e] = P * A(tau') at r-index k = t + TF e; ROI cells hold
+    // tau' = -k (k < N) or P - k (k > P - N).
     uint32_t vmask = 0;
-    unsigned long long key = 0;
+    float qmax = 0.f;
+    int kbest = 0;
     static_for<E>([&](auto ec) {
       constexpr int e = decltype(ec)::value;
       const int k = t + TF * e;
@@ -335,24 +400,27 @@ __global__ __launch_bounds__(64) void k_pass(PassArgs a) {
       if (valid) {
         vmask |= 1u << e;
         const float q = R[e].x * R[e].x + R[e].y * R[e].y;
-        key = umax64(key, make_key(q, (uint32_t)(((int64_t)u * M + g) * P + k)));
+        if (q > qmax) {
+          qmax = q;
+          kbest = k;
+        }
       }
       if (cube != nullptr && active && inr)
         cube[((int64_t)(w * M + g) * F + f) * T2 + tp + N - 1] = cscale(R[e], invP);
     });
-    key = slot_max_key<TF>(key);
+    // this lane's largest cell of the pair (lowest index among equal values)
+    const unsigned long long key = vmask ? make_key(qmax, (uint32_t)(((int64_t)u * M + g) * P + kbest)) : 0ull;
     if (g == w) kauto = umax64(kauto, key);
     else kcross = umax64(kcross, key);
-    const float mu = sqrtf(key_q(key));
+    qmax = slot_reduce<TF>(qmax, 0.0f, OpMax());
+    const float mu = sqrtf(qmax);
     if (mu > sigma) {  // new running scale: rescale the partial sums (online max)
       const float c = sigma / mu;
       float cm1, cp;
       pow_ph<PHLOG>(c * c, phm1, cm1, cp);  // (c^2)^(p/2 - 1), (c^2)^(p/2)
       S *= cp;
-      if (grad) {
-        const float cpm1 = cm1 * c;  // c^(p-1)
-        static_for<E>([&](auto ec) { U[decltype(ec)::value] = cscale(U[decltype(ec)::value], cpm1); });
-      }
+      const float cpm1 = cm1 * c;  // c^(p-1)
+      static_for<E>([&](auto ec) { U[decltype(ec)::value] = cscale(U[decltype(ec)::value], cpm1); });
       sigma = mu;
     }
     const float inv_s = sigma > 0.f ? 1.0f / sigma : 0.f;
@@ -371,60 +439,134 @@ __global__ __launch_bounds__(64) void k_pass(PassArgs a) {
       }
     });
     if (grad) {
-      fft_forward<P>(R, buf, t, W);
-      static_for<E>([&](auto ec) {
-        constexpr int e = decltype(ec)::value;
-        U[e] = cadd(U[e], cmul(R[e], sg[e * TF + t]));
-      });
+      op = OP_ADJ;
+    } else if (++g < M) {
+      start_pair();
+    } else {
+      break;
     }
   }
 
-  if (grad) {
-    fft_inverse<P>(U, buf, t, W);
-    if (active) {
-      float2* up = a.upart + pl.ws_upart + (int64_t)u * N;
-      static_for<EH>([&](auto ec) {
-        constexpr int e = decltype(ec)::value;
-        const int n = t + TF * e;
-        if (n < N) up[n] = cmulc(U[e], phasor(n, nu, invN));
-      });
-    }
+  // Unit results: statistics to the block's tables, the demodulated gradient
+  // partial into this slot's LDS region (unscaled, with the unit scale sigma).
+  S = slot_reduce<TF>(S, 0.0f, OpAdd());
+  kauto = slot_max_key<TF>(kauto);
+  kcross = slot_max_key<TF>(kcross);
+  if (t == 0) {
+    u_sig[uslot] = active ? sigma : 0.f;
+    u_S[uslot] = active ? S : 0.f;
+    u_ka[uslot] = active ? kauto : 0ull;
+    u_kc[uslot] = active ? kcross : 0ull;
   }
-  S = slot_sum<TF>(S);
-  if (active && t == 0) {
+  if (grad) {
+    wave_lds_sync();
+    static_for<EH>([&](auto ec) {
+      constexpr int e = decltype(ec)::value;
+      const int n = t + TF * e;
+      if (n < N) buf[n] = active ? cmulc(R[e], phasor(n, nu, invN)) : make_float2(0.f, 0.f);
+    });
+  }
+  __syncthreads();
+
+  // Block combine: one statistics entry and one partial per block, both
+  // relative to the block's largest unit scale (unit order fixed).
+  float sb = 0.f;
+  for (int j = 0; j < UPB; ++j) sb = fmaxf(sb, u_sig[j]);
+  const float inv_b = sb > 0.f ? 1.0f / sb : 0.f;
+  const int64_t ent = (int64_t)w * pl.wpr + grp;
+  if (threadIdx.x == 0) {
+    float Sb = 0.f;
+    unsigned long long ka = 0, kc = 0;
+    for (int j = 0; j < UPB; ++j) {
+      const float c = u_sig[j] * inv_b;
+      float cm1, cp;
+      pow_ph<PHLOG>(c * c, phm1, cm1, cp);
+      Sb += cp * u_S[j];
+      ka = umax64(ka, u_ka[j]);
+      kc = umax64(kc, u_kc[j]);
+    }
     UnitStat st;
-    st.sigma = sigma;
-    st.S = S;
+    st.sigma = sb;
+    st.S = Sb;
     st.pad0 = st.pad1 = 0;
-    st.key_auto = kauto;
-    st.key_cross = kcross;
-    a.ustat[pl.ws_unit + u] = st;
+    st.key_auto = ka;
+    st.key_cross = kc;
+    a.ustat[pl.ws_unit + ent] = st;
+  }
+  if (grad) {
+    float fac[UPB];
+#pragma unroll
+    for (int j = 0; j < UPB; ++j) {
+      const float c = u_sig[j] * inv_b;
+      float cm1, cp;
+      pow_ph<PHLOG>(c * c, phm1, cm1, cp);
+      fac[j] = cm1 * c;  // (sigma_j / sigma_block)^(p-1)
+    }
+    float2* up = a.upart + pl.ws_upart + ent * N;
+    for (int n = threadIdx.x; n < N; n += 64 * kPassWaves) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int j = 0; j < UPB; ++j) {
+        const float2 v = lds[(j / SL) * G::LDS + (j % SL) * P + n];
+        acc.x += fac[j] * v.x;
+        acc.y += fac[j] * v.y;
+      }
+      up[n] = acc;
+    }
   }
 }
 
 // ------------------------------------------------------------------ k_final
 
+// x^p and x^(p-1) for 0 <= x <= 1: exact repeated squaring when p/2 is a
+// power of two (ph_log >= 0), powf otherwise.
+__device__ __forceinline__ float pow_p(float x, const ProbPlan& pl) {
+  if (pl.ph_log >= 0) {
+    float y = x * x;
+    for (int i = 0; i < pl.ph_log; ++i) y *= y;
+    return y;
+  }
+  return powf(x, pl.p);
+}
+__device__ __forceinline__ float pow_pm1(float x, const ProbPlan& pl) {
+  if (pl.ph_log >= 0) return x > 0.f ? pow_p(x, pl) / x : (pl.ph_log == 0 ? 1.0f : 0.0f);
+  return powf(x, pl.p - 1.0f);
+}
+
 enum FinMode : int32_t {
-  FIN_STATS = 0,   // statistics only
+  FIN_STATS = 0,   // statistics only (the first row of each problem works)
   FIN_GRAD = 1,    // statistics and gradient outputs (scaled by grad_loss)
   FIN_STEP_A = 2,  // Adam on the filters, then the energy projection
   FIN_STEP_B = 3,  // chain rule to the logits, Adam on the logits
 };
 
+// What k_final prepares for the pass that follows it.
+enum NextPrep : int32_t {
+  NEXT_NONE = 0,
+  NEXT_B_FULL = 1,  // after a filter update: soft waveform, filter spectrum, mainlobe products
+  NEXT_A_SNRL = 2,  // after a filter update, another filter step: mainlobe products only
+  NEXT_A_FULL = 3,  // after a logit update: hard waveform, its spectrum, mainlobe products
+  NEXT_B_SOFT = 4,  // after a logit update, another logit step: soft waveform, mainlobe products
+};
+
 struct FinArgs {
   const ProbPlan* plans;
-  const int32_t* row_prob;
-  int32_t nrows;
+  const int32_t* rows;      // batch rows of this launch, one block each
+  const int32_t* row_prob;  // problem of every batch row
+  int32_t nrows_total;      // rows of the whole batch (blocks of all launches of one step)
   int32_t orient;
   int32_t mode;
-  int32_t inner;        // index of the inner step (Adam step count t * n + inner + 1)
-  int32_t count_step;   // this launch ends the outer iteration: advance *counter
-  int32_t wave_mode;    // SOFT / HARD / GIVEN for the logit chain of FIN_GRAD
+  int32_t inner;            // index of the inner step (Adam step count t * n + inner + 1)
+  int32_t count_step;       // this launch ends the outer iteration: advance *counter
+  int32_t wave_mode;        // SOFT / HARD / GIVEN for the logit chain of FIN_GRAD
+  int32_t next;             // NextPrep
+  int32_t next_t_offset;    // temperature of NEXT_B_SOFT at step t + offset
   const float2* self_w;
   const float2* part_w;
   const UnitStat* ustat;
   const float2* upart;
-  const float4* snrl;
+  const float4* snrl;       // mainlobe inner products of the pass just run
+  float4* snrl_next;        // ... of the prepared pass
   sqngd_stats* stats;
   const float* grad_loss;
   float2* grad_w;
@@ -432,323 +574,746 @@ struct FinArgs {
   float* z;     // logits: read for the chain, updated by FIN_STEP_B
   float2* h;    // filters updated by FIN_STEP_A
   float* adam;
+  float2* wself;  // prepared soft waveforms
+  float2* wpart;  // prepared hard waveforms
+  float2* spec;   // prepared partner spectra
   int32_t* counter;
   int32_t* done;
   sqngd_opt opt;
+  int32_t single;  // one problem: its plan is `one`, rows are the block indices
+  ProbPlan one;
 };
 
-constexpr int kFinThreads = 256;
+constexpr int kFinThreads = 1024;
+constexpr int kFinWaves = kFinThreads / 64;
 
-template <class T, class Op>
-__device__ __forceinline__ T block_reduce(T v, T* sh, Op op) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off));
+__device__ __forceinline__ float wave_max(float v) { return slot_reduce<64>(v, 0.0f, OpMax()); }
+__device__ __forceinline__ float wave_sum(float v) { return slot_reduce<64>(v, 0.0f, OpAdd()); }
+__device__ __forceinline__ float block_max(float v, float* sh) {
+  v = wave_max(v);
   __syncthreads();
-  if ((tid & 63) == 0) sh[tid >> 6] = v;
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  T r = sh[0];
-  for (int i = 1; i < kFinThreads / 64; ++i) r = op(r, sh[i]);
+  float r = sh[0];
+  for (int i = 1; i < kFinWaves; ++i) r = fmaxf(r, sh[i]);
   return r;
 }
-
-__device__ __forceinline__ unsigned long long block_max_key(unsigned long long v, unsigned long long* sh) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    uint32_t lo = __shfl_xor((uint32_t)v, off), hi = __shfl_xor((uint32_t)(v >> 32), off);
-    v = umax64(v, ((unsigned long long)hi << 32) | lo);
-  }
+__device__ __forceinline__ float block_sum(float v, float* sh) {
+  v = wave_sum(v);
   __syncthreads();
-  if ((tid & 63) == 0) sh[tid >> 6] = v;
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = sh[0];
+  for (int i = 1; i < kFinWaves; ++i) r += sh[i];
+  return r;
+}
+__device__ __forceinline__ unsigned long long block_max_key(unsigned long long v, unsigned long long* sh) {
+  v = slot_max_key<64>(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
   unsigned long long r = sh[0];
-  for (int i = 1; i < kFinThreads / 64; ++i) r = umax64(r, sh[i]);
+  for (int i = 1; i < kFinWaves; ++i) r = umax64(r, sh[i]);
   return r;
 }
 
-struct FMax {
-  __device__ float operator()(float a, float b) const { return fmaxf(a, b); }
-};
-struct FSum {
-  __device__ float operator()(float a, float b) const { return a + b; }
-};
-struct IOr {
-  __device__ int operator()(int a, int b) const { return a | b; }
-};
+// dL/dz of one chip from the packed waveform gradient g by the chain rule
+// through the soft quantiser at temperature T; fn(l, dL/dz_l) is called in
+// order l = 0 .. L-1 after the softmax statistics have been read.
+template <class Fn>
+__device__ __forceinline__ void logit_chain(const float* zc, int L, float T, int mode, float2 s, float2 g,
+                                            Fn&& fn) {
+  float zm = zc[0];
+  for (int l = 1; l < L; ++l) zm = fmaxf(zm, zc[l]);
+  const float invT = 1.0f / T;
+  float sum = 0.f, ybar = 0.f;
+  for (int l = 0; l < L; ++l) {
+    const float e = expf((zc[l] - zm) * invT);
+    sum += e;
+    ybar += (float)l * e;
+  }
+  const float inv = 1.0f / sum;
+  ybar *= inv;
+  if (mode == SQNGD_SQ_PHASE_MEAN) {
+    const float dphi = g.y * s.x - g.x * s.y;  // Im(g conj(s)) = dL/dphi
+    const float c = dphi * 2.0f * 3.14159265358979f / (float)L * invT;
+    for (int l = 0; l < L; ++l) fn(l, c * expf((zc[l] - zm) * invT) * inv * ((float)l - ybar));
+  } else {
+    for (int l = 0; l < L; ++l) {
+      const float2 ul = level_phasor(l, L);
+      fn(l, expf((zc[l] - zm) * invT) * inv * invT * (g.x * (ul.x - s.x) + g.y * (ul.y - s.y)));
+    }
+  }
+}
 
-__global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
-  __shared__ float shf[kFinThreads / 64];
-  __shared__ int shi[kFinThreads / 64];
-  __shared__ unsigned long long shk[kFinThreads / 64];
-  __shared__ float fac[4096];
-  __shared__ float2 csnrl[16];
-  __shared__ float pm_sh[16];
+// Spectrum of one row (value v of chip n; threads n >= N pass zero) in the
+// spectral layout of the fused pass, computed by wave 0 of the block; fbuf
+// holds the staged row and then serves as that wave's exchange buffer.
+template <int P>
+__device__ __forceinline__ void row_spectrum(float2 v, int N, float2* fbuf, float2* out) {
+  using G = Geom<P>;
+  constexpr int E = G::E, TF = G::TF;
   const int tid = threadIdx.x;
-  const int r = blockIdx.x;
-  const int pid = a.row_prob[r];
-  const ProbPlan pl = a.plans[pid];
-  const int M = pl.M, N = pl.N, F = pl.F, L = pl.L, P = pl.P;
+  for (int i = tid; i < P; i += kFinThreads) fbuf[i] = make_float2(0.f, 0.f);
+  __syncthreads();
+  if (tid < N) fbuf[tid] = v;
+  __syncthreads();
+  if (tid < 64) {
+    const int slot = tid / TF, t = tid % TF;
+    float2 X[E];
+    static_for<E>([&](auto ec) {
+      constexpr int e = decltype(ec)::value;
+      X[e] = slot == 0 ? fbuf[t + TF * e] : make_float2(0.f, 0.f);
+    });
+    WaveTwiddles<P> W;
+    W.init(t);
+    fft_forward<P>(X, fbuf + slot * P, t, W);
+    if (slot == 0) {
+      static_for<E>([&](auto ec) {
+        constexpr int e = decltype(ec)::value;
+        out[e * TF + t] = X[e];
+      });
+    }
+  }
+}
+
+// Mainlobe inner product c' = sum_n conj(part(n)) self(n) and the two
+// energies (eq. 10, 38) of one row, written by thread 0 (one LDS round).
+__device__ __forceinline__ void row_snrl(float2 self, float2 part, float* sh, float4* out) {
+  float v[4] = {part.x * self.x + part.y * self.y, part.x * self.y - part.y * self.x,
+                self.x * self.x + self.y * self.y, part.x * part.x + part.y * part.y};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+    for (int i = 0; i < 4; ++i) sh[i * kFinWaves + (threadIdx.x >> 6)] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float r[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < 4; ++i)
+      for (int w = 0; w < kFinWaves; ++w) r[i] += sh[i * kFinWaves + w];
+    *out = make_float4(r[0], r[1], r[2], r[3]);
+  }
+}
+
+// Segmented reductions over aligned groups of LP lanes (LP a power of two <= 64).
+__device__ __forceinline__ float seg_max(float v, int LP) {
+  for (int off = LP >> 1; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ float seg_sum(float v, int LP) {
+  for (int off = LP >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+// largest value and its lowest index
+__device__ __forceinline__ void seg_argmax(float& v, int& idx, int LP) {
+  for (int off = LP >> 1; off > 0; off >>= 1) {
+    const float ov = __shfl_xor(v, off);
+    const int oi = __shfl_xor(idx, off);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+}
+
+// One block per row of the batch. The block
+//  1. issues every load that does not wait for a reduction;
+//  2. reduces the problem's unit statistics to L_p (every row of a problem
+//     does the same, in the same order) and the SNRL penalty;
+//  3. sums the row's per-block gradient partials over the Doppler bins (in
+//     bin order within each of FS interleaved splits, then over the splits);
+//  4. applies the filter update (one thread per chip), or writes the gradient;
+//  5. runs the logit side one thread per (chip, level): the chain rule through
+//     the soft quantiser, the logit update and the quantisation that prepares
+//     the next pass, with per-chip softmax statistics from lane shuffles;
+//  6. forms the next pass's mainlobe products and partner spectrum;
+//  7. writes the statistics record.
+template <int P>
+__global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
+  __shared__ float shf[kFinWaves * 4];
+  __shared__ unsigned long long shk[kFinWaves * 2];
+  __shared__ float fac[4096];
+  __shared__ float2 part[kFinThreads];
+  __shared__ float2 gsh[1024];    // row gradient of each chip
+  __shared__ float2 nsh[1024];    // quantised waveform of each chip for the next pass
+  __shared__ float4 snrl_sh[16];
+  __shared__ float2 fbuf[Geom<P>::LDS];
+  const int tid = threadIdx.x;
+  int r, pid;
+  ProbPlan pl;
+  if (a.single) {
+    r = blockIdx.x;
+    pid = 0;
+    pl = a.one;
+  } else {
+    r = a.rows[blockIdx.x];
+    pid = a.row_prob[r];
+    pl = a.plans[pid];
+  }
+  const int M = pl.M, N = pl.N, F = pl.F, L = pl.L;
   const int m = r - pl.row0;
   if (a.mode == FIN_STATS && m != 0) return;
   const UnitStat* us = a.ustat + pl.ws_unit;
   const float p = pl.p;
-
-  // L_p = (sum over units of sigma_u^p S_u)^(1/p), evaluated relative to the largest sigma.
-  float smax = 0.f;
-  unsigned long long ka = 0, kc = 0;
-  for (int i = tid; i < pl.units; i += kFinThreads) {
-    smax = fmaxf(smax, us[i].sigma);
-    ka = umax64(ka, us[i].key_auto);
-    kc = umax64(kc, us[i].key_cross);
+  const int n = tid;
+  const bool on = n < N;
+  const bool upd = a.mode != FIN_STATS;
+  const int64_t wrow = pl.off_w + (int64_t)m * N;
+  const int64_t crow = (int64_t)m * N;
+  const int NE = pl.wpr;  // statistics entries / partials per row (one per fused-pass block)
+  const bool chain_out = a.mode == FIN_GRAD && a.grad_z != nullptr && a.orient == 0;
+  const bool zstep = a.mode == FIN_STEP_B;
+  const bool next_soft = a.next == NEXT_B_FULL || a.next == NEXT_B_SOFT;
+  const bool next_hard = a.next == NEXT_A_FULL;
+  const bool elem = chain_out || zstep || next_soft || next_hard;
+  int LP = 1, lg = 0;
+  while (LP < L) {
+    LP <<= 1;
+    ++lg;
   }
-  smax = block_reduce(smax, shf, FMax());
-  ka = block_max_key(ka, shk);
-  kc = block_max_key(kc, shk);
-  float acc = 0.f;
-  if (smax > 0.f)
-    for (int i = tid; i < pl.units; i += kFinThreads) acc += powf(us[i].sigma / smax, p) * us[i].S;
-  acc = block_reduce(acc, shf, FSum());
-  const float lp_raw = smax > 0.f ? smax * powf(acc, 1.0f / p) : 0.f;
-  const float lp = lp_raw * pl.inv_NP;
 
-  // SNRL penalty (eq. 38-41): c'_k = sum_n conj(part_k(n)) self_k(n).
-  float l_snrl = 0.f, snrl_max = -INFINITY, p_min = INFINITY;
-  for (int k = 0; k < M; ++k) {
-    const float4 c4 = a.snrl[pl.row0 + k];
-    const float mag = sqrtf(c4.x * c4.x + c4.y * c4.y);
-    const float pk = mag / (float)N;
-    l_snrl += (pk - pl.p_tar) * (pk - pl.p_tar) / (float)M;
-    snrl_max = fmaxf(snrl_max, 10.0f * log10f(c4.z * c4.w / (mag * mag)));
-    p_min = fminf(p_min, pk);
-    if (tid == 0) {
-      csnrl[k] = make_float2(c4.x, c4.y);
-      pm_sh[k] = pk;
+  // ---- 1. loads
+  float2 pw = make_float2(0.f, 0.f), hv = make_float2(0.f, 0.f);
+  float4 mvh = make_float4(0.f, 0.f, 0.f, 0.f);
+  float* mh = a.adam + pl.off_state + 2 * (int64_t)M * N * L + 2 * crow;
+  float* vh = mh + 2 * (int64_t)M * N;
+  if (upd && on) {
+    pw = a.part_w[wrow + n];
+    if (a.mode == FIN_STEP_A || a.mode == FIN_STEP_B) hv = a.h[wrow + n];
+    if (a.mode == FIN_STEP_A) {
+      const float2 m2 = *(const float2*)(mh + 2 * n), v2 = *(const float2*)(vh + 2 * n);
+      mvh = make_float4(m2.x, m2.y, v2.x, v2.y);
     }
   }
-  const float loss = pl.w_psl * lp + pl.w_snrl * l_snrl;
+  const float fsig = upd && tid < NE ? us[m * NE + tid].sigma : 0.f;
+  const float4 sn = tid < M ? a.snrl[pl.row0 + tid] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const int tstep = (a.mode == FIN_STEP_A || a.mode == FIN_STEP_B) ? *a.counter : 0;
+  constexpr int kBatch = 8;
+  const int Nc = (N + 63) & ~63;
+  const int FS = kFinThreads / Nc;
+  const int nn = tid % Nc, fsi = tid / Nc;
+  const bool red = upd && fsi < FS && nn < N;
+  const float2* up = a.upart + pl.ws_upart + (int64_t)m * NE * N + nn;
+  float2 v[kBatch];
+#pragma unroll
+  for (int j = 0; j < kBatch; ++j) {
+    const int ff = fsi + j * FS;
+    v[j] = red && ff < NE ? up[(int64_t)ff * N] : make_float2(0.f, 0.f);
+  }
+  // this thread's first logit element (chip i >> lg, level i & (LP-1))
+  float zv0 = 0.f, m0 = 0.f, v0 = 0.f;
+  float2 s0 = make_float2(0.f, 0.f);
+  {
+    const int en = tid >> lg, el = tid & (LP - 1);
+    if (elem && en < N && el < L) {
+      zv0 = a.z[pl.off_z + (crow + en) * L + el];
+      if (zstep) {
+        m0 = a.adam[pl.off_state + (crow + en) * L + el];
+        v0 = a.adam[pl.off_state + (int64_t)M * N * L + (crow + en) * L + el];
+      }
+      if (zstep || chain_out) s0 = a.self_w[wrow + en];
+    }
+  }
+  // online (max, rescaled sum) of this thread's unit statistics
+  float mx = 0.f, sx = 0.f;
+  unsigned long long ka = 0, kc = 0;
+  for (int i = tid; i < pl.units; i += kFinThreads) {
+    const UnitStat u = us[i];
+    ka = umax64(ka, u.key_auto);
+    kc = umax64(kc, u.key_cross);
+    if (u.sigma > mx) {
+      sx = (mx > 0.f ? sx * pow_p(mx / u.sigma, pl) : 0.f) + u.S;
+      mx = u.sigma;
+    } else if (u.sigma > 0.f) {
+      sx += u.S * pow_p(u.sigma / mx, pl);
+    }
+  }
+  if (tid < NE) fac[tid] = fsig;
+  for (int j = tid + kFinThreads; upd && j < NE; j += kFinThreads) fac[j] = us[m * NE + j].sigma;
+  if (tid < M) snrl_sh[tid] = sn;
+
+  // ---- 2. L_p and the SNRL penalty
+  {
+    const float wm = wave_max(mx);
+    float s = mx > 0.f ? sx * pow_p(mx / wm, pl) : 0.f;
+    s = wave_sum(s);
+    ka = slot_max_key<64>(ka);
+    kc = slot_max_key<64>(kc);
+    if ((tid & 63) == 0) {
+      shf[tid >> 6] = wm;
+      shf[kFinWaves + (tid >> 6)] = s;
+      shk[tid >> 6] = ka;
+      shk[kFinWaves + (tid >> 6)] = kc;
+    }
+  }
+  __syncthreads();
+  float smax = 0.f;
+  for (int w = 0; w < kFinWaves; ++w) {
+    smax = fmaxf(smax, shf[w]);
+    ka = umax64(ka, shk[w]);
+    kc = umax64(kc, shk[kFinWaves + w]);
+  }
+  float acc = 0.f;
+  for (int w = 0; w < kFinWaves; ++w)
+    if (shf[w] > 0.f) acc += shf[kFinWaves + w] * pow_p(shf[w] / smax, pl);
+  const float lp_raw = smax > 0.f ? smax * powf(acc, 1.0f / p) : 0.f;
+  float l_snrl = 0.f;
+  for (int k = 0; k < M; ++k) {
+    const float4 c4 = snrl_sh[k];
+    const float pk = sqrtf(c4.x * c4.x + c4.y * c4.y) / (float)N;
+    l_snrl += (pk - pl.p_tar) * (pk - pl.p_tar) / (float)M;
+  }
+  const float loss = pl.w_psl * lp_raw * pl.inv_NP + pl.w_snrl * l_snrl;
   const bool bad = !isfinite(loss);
 
+  float2 g = make_float2(0.f, 0.f);
+  bool skip = true;
+  if (upd) {
+    // ---- 3. row gradient: sum_f (w_psl/(N P)) (sigma_u/lp_raw)^(p-1) partial_u + G'_S part_m
+    for (int j = tid; j < NE; j += kFinThreads)
+      fac[j] = lp_raw > 0.f ? pl.w_psl / ((float)N * (float)pl.P) * pow_pm1(fac[j] / lp_raw, pl) : 0.f;
+    __syncthreads();
+    {
+      float2 gp = make_float2(0.f, 0.f);
+      if (red) {
+        for (int f0 = fsi;; f0 += kBatch * FS) {
+#pragma unroll
+          for (int j = 0; j < kBatch; ++j) {
+            const int ff = f0 + j * FS;
+            const float c = ff < NE ? fac[ff] : 0.f;
+            gp.x += c * v[j].x;
+            gp.y += c * v[j].y;
+          }
+          const int f1 = f0 + kBatch * FS;
+          if (f1 >= NE) break;
+#pragma unroll
+          for (int j = 0; j < kBatch; ++j) {
+            const int ff = f1 + j * FS;
+            v[j] = ff < NE ? up[(int64_t)ff * N] : make_float2(0.f, 0.f);
+          }
+        }
+      }
+      part[tid] = gp;
+    }
+    __syncthreads();
+    const float gl = a.grad_loss ? a.grad_loss[pid] : 1.0f;
+    const float4 cm = snrl_sh[m];
+    const float magm = sqrtf(cm.x * cm.x + cm.y * cm.y);
+    float2 gS = make_float2(0.f, 0.f);
+    if (magm > 0.f)
+      gS = cscale(make_float2(cm.x, cm.y),
+                  pl.w_snrl * (2.0f / (float)M) * (magm / (float)N - pl.p_tar) / ((float)N * magm));
+    if (on) {
+      for (int s = 0; s < FS; ++s) g = cadd(g, part[s * Nc + n]);
+      g = cscale(cadd(g, cmul(gS, pw)), gl);
+      gsh[n] = g;
+    }
+    const int rowbad = __syncthreads_or(on && (!isfinite(g.x) || !isfinite(g.y)));
+    skip = bad || rowbad;
+
+    // ---- 4. per chip
+    if (a.mode == FIN_GRAD && on && a.grad_w) a.grad_w[wrow + n] = g;
+    if (a.mode == FIN_STEP_A) {
+      // Adam on (Re h, Im h), then h <- h sqrt(N / |h|^2) (eq. 32)
+      const int k = tstep * a.opt.n_h + a.inner + 1;
+      const float b1 = a.opt.beta1, b2 = a.opt.beta2;
+      const float bc1 = 1.0f - powf(b1, (float)k), bc2 = 1.0f - powf(b2, (float)k);
+      if (on && !skip) {
+        if (a.opt.flags & SQNGD_OPT_SGD) {
+          hv.x -= a.opt.lr_h * g.x;
+          hv.y -= a.opt.lr_h * g.y;
+        } else {
+          const float mx2 = b1 * mvh.x + (1.0f - b1) * g.x, my2 = b1 * mvh.y + (1.0f - b1) * g.y;
+          const float vx = b2 * mvh.z + (1.0f - b2) * g.x * g.x, vy = b2 * mvh.w + (1.0f - b2) * g.y * g.y;
+          *(float2*)(mh + 2 * n) = make_float2(mx2, my2);
+          *(float2*)(vh + 2 * n) = make_float2(vx, vy);
+          hv.x -= a.opt.lr_h * (mx2 / bc1) / (sqrtf(vx / bc2) + a.opt.eps);
+          hv.y -= a.opt.lr_h * (my2 / bc1) / (sqrtf(vy / bc2) + a.opt.eps);
+        }
+      }
+      const float e2 = block_sum(hv.x * hv.x + hv.y * hv.y, shf);
+      hv = cscale(hv, skip ? 1.0f : sqrtf((float)N / e2));
+      if (on) a.h[wrow + n] = hv;
+    }
+
+    // ---- 5. logit side, one thread per (chip, level)
+    if (elem) {
+      const bool zupd = zstep && !skip;
+      const int kz = tstep * a.opt.n_x + a.inner + 1;
+      const float b1 = a.opt.beta1, b2 = a.opt.beta2;
+      const float bc1 = zupd ? 1.0f - powf(b1, (float)kz) : 1.0f;
+      const float bc2 = zupd ? 1.0f - powf(b2, (float)kz) : 1.0f;
+      const float Tc = zstep ? temperature_at(a.opt, tstep) : pl.temperature;
+      const float Tn = temperature_at(a.opt, tstep + (a.next == NEXT_B_SOFT ? a.next_t_offset : 0));
+      const bool soft_grad = chain_out ? a.wave_mode == SQNGD_WAVE_SOFT : zupd;
+      const float tw = 2.0f * 3.14159265358979f / (float)L;
+      for (int base = 0; base < N * LP; base += kFinThreads) {
+        const int i = base + tid, en = i >> lg, el = i & (LP - 1);
+        const bool ok = en < N && el < L;
+        float zv = zv0, mm = m0, vv = v0;
+        float2 s = s0;
+        const int64_t zi = pl.off_z + (crow + en) * L + el;
+        if (base > 0 && ok) {
+          zv = a.z[zi];
+          if (zstep) {
+            mm = a.adam[pl.off_state + (crow + en) * L + el];
+            vv = a.adam[pl.off_state + (int64_t)M * N * L + (crow + en) * L + el];
+          }
+          if (zstep || chain_out) s = a.self_w[wrow + en];
+        }
+        if (chain_out || zupd) {
+          // dL/dz through the soft quantiser at Tc (chip softmax from the L lanes)
+          const float zm = seg_max(ok ? zv : -INFINITY, LP);
+          const float e = ok ? expf((zv - zm) / Tc) : 0.f;
+          const float sum = seg_sum(e, LP);
+          const float yb = seg_sum((float)el * e, LP) / sum;
+          const float2 gc = ok ? gsh[en] : make_float2(0.f, 0.f);
+          const float pi = e / sum;
+          float gv;
+          if (pl.sq_mode == SQNGD_SQ_PHASE_MEAN) {
+            gv = (gc.y * s.x - gc.x * s.y) * tw / Tc * pi * ((float)el - yb);
+          } else {
+            const float2 ul = level_phasor(el, L);
+            gv = pi / Tc * (gc.x * (ul.x - s.x) + gc.y * (ul.y - s.y));
+          }
+          if (!soft_grad) gv = 0.f;
+          if (chain_out && ok) a.grad_z[zi] = gv;
+          if (zupd && ok) {
+            if (a.opt.flags & SQNGD_OPT_SGD) {
+              zv -= a.opt.lr_z * gv;
+            } else {
+              mm = b1 * mm + (1.0f - b1) * gv;
+              vv = b2 * vv + (1.0f - b2) * gv * gv;
+              a.adam[pl.off_state + (crow + en) * L + el] = mm;
+              a.adam[pl.off_state + (int64_t)M * N * L + (crow + en) * L + el] = vv;
+              zv -= a.opt.lr_z * (mm / bc1) / (sqrtf(vv / bc2) + a.opt.eps);
+            }
+            a.z[zi] = zv;
+          }
+        }
+        if (next_soft) {  // soft waveform of the next pass at Tn
+          const float zm = seg_max(ok ? zv : -INFINITY, LP);
+          const float e = ok ? expf((zv - zm) / Tn) : 0.f;
+          const float sum = seg_sum(e, LP);
+          float2 sq;
+          if (pl.sq_mode == SQNGD_SQ_PHASE_MEAN) {
+            const float yb = seg_sum((float)el * e, LP) / sum;
+            float sn_, cs_;
+            sincospif(2.0f * yb / (float)L, &sn_, &cs_);
+            sq = make_float2(cs_, sn_);
+          } else {
+            const float2 ul = level_phasor(el, L);
+            sq = make_float2(seg_sum(e * ul.x, LP) / sum, seg_sum(e * ul.y, LP) / sum);
+          }
+          if (el == 0 && en < N) nsh[en] = sq;
+        } else if (next_hard) {  // hard waveform of the next pass
+          float bv = ok ? zv : -INFINITY;
+          int bi = el;
+          seg_argmax(bv, bi, LP);
+          if (el == 0 && en < N) nsh[en] = level_phasor(bi, L);
+        }
+      }
+    }
+  }
+
+  // ---- 6. inputs of the next pass
+  if (a.next != NEXT_NONE) {
+    __syncthreads();
+    float2 self = hv, prt = hv, sp = hv;
+    if (next_soft) {
+      self = on ? nsh[n] : make_float2(0.f, 0.f);
+      if (on) a.wself[wrow + n] = self;
+    } else if (next_hard) {
+      prt = on ? nsh[n] : make_float2(0.f, 0.f);
+      sp = prt;
+      if (on) a.wpart[wrow + n] = prt;
+    } else {  // NEXT_A_SNRL
+      prt = on ? a.wpart[wrow + n] : make_float2(0.f, 0.f);
+    }
+    row_snrl(self, prt, shf, a.snrl_next + r);
+    if (a.next == NEXT_B_FULL || next_hard) row_spectrum<P>(sp, N, fbuf, a.spec + pl.ws_spec + (int64_t)m * P);
+  }
+
+  // ---- 7. statistics record
   if (m == 0 && tid == 0 && a.stats != nullptr) {
+    const int Pl = pl.P;
+    float snrl_max = -INFINITY, p_min = INFINITY;
+    for (int k = 0; k < M; ++k) {
+      const float4 c4 = snrl_sh[k];
+      const float mag = sqrtf(c4.x * c4.x + c4.y * c4.y);
+      snrl_max = fmaxf(snrl_max, 10.0f * log10f(c4.z * c4.w / (mag * mag)));
+      p_min = fminf(p_min, mag / (float)N);
+    }
     sqngd_stats st;
     st.loss = loss;
-    st.lp = lp;
+    st.lp = lp_raw * pl.inv_NP;
     st.l_snrl = l_snrl;
-    const float invP = 1.0f / (float)P;
+    const float invP = 1.0f / (float)Pl;
     st.psl_auto = sqrtf(key_q(ka)) * invP;
     st.psl_cross = sqrtf(key_q(kc)) * invP;
-    const float psl = fmaxf(st.psl_auto, st.psl_cross);
-    st.pslr_db = 20.0f * log10f(psl / (float)N);
+    st.pslr_db = 20.0f * log10f(fmaxf(st.psl_auto, st.psl_cross) / (float)N);
     st.snrl_db_max = snrl_max;
     st.p_min = p_min;
     const unsigned long long kb = key_q(ka) >= key_q(kc) ? ka : kc;
     const uint32_t cell = key_cell(kb);
-    const int kk = (int)(cell % (uint32_t)P);
-    const uint32_t rest = cell / (uint32_t)P;
+    const int kk = (int)(cell % (uint32_t)Pl);
+    const uint32_t rest = cell / (uint32_t)Pl;
     const int gg = (int)(rest % (uint32_t)M);
     const int uu = (int)(rest / (uint32_t)M);
     const int ww = uu / F, ff = uu % F;
-    const int tp = kk <= N - 1 ? -kk : P - kk;
-    if (a.orient == 0) {
-      st.arg_m = ww;
-      st.arg_l = gg;
-      st.arg_tau = tp;
-    } else {
-      st.arg_m = gg;
-      st.arg_l = ww;
-      st.arg_tau = -tp;
-    }
+    const int tp = kk <= N - 1 ? -kk : Pl - kk;
+    st.arg_m = a.orient == 0 ? ww : gg;
+    st.arg_l = a.orient == 0 ? gg : ww;
+    st.arg_tau = a.orient == 0 ? tp : -tp;
     st.arg_f = ff;
     st.nonfinite = bad ? 1u : 0u;
     st.reserved[0] = st.reserved[1] = st.reserved[2] = 0;
     a.stats[pid] = st;
   }
   if (a.mode == FIN_STATS) return;
-  __syncthreads();
-
-  // Gradient of row m of the self sequence:
-  //   sum_f (w_psl / (N P)) (sigma_u / lp_raw)^(p-1) partial_u  +  G'_S part_m
-  for (int ff = tid; ff < F; ff += kFinThreads) {
-    const float su = us[m * F + ff].sigma;
-    fac[ff] = lp_raw > 0.f ? pl.w_psl / ((float)N * (float)P) * powf(su / lp_raw, p - 1.0f) : 0.f;
-  }
-  __syncthreads();
-  const float gl = a.grad_loss ? a.grad_loss[pid] : 1.0f;
-  const float2 cm = csnrl[m];
-  const float magm = sqrtf(cm.x * cm.x + cm.y * cm.y);
-  float2 gS = make_float2(0.f, 0.f);
-  if (magm > 0.f) gS = cscale(cm, pl.w_snrl * (2.0f / (float)M) * (pm_sh[m] - pl.p_tar) / ((float)N * magm));
-  constexpr int kMaxPer = 1024 / kFinThreads;
-  float2 gr[kMaxPer];
-  int rowbad = 0;
-  const float2* up = a.upart + pl.ws_upart + (int64_t)m * F * N;
-  const float2* pw = a.part_w + pl.off_w + (int64_t)m * N;
-#pragma unroll
-  for (int i = 0; i < kMaxPer; ++i) {
-    const int n = tid + i * kFinThreads;
-    float2 g = make_float2(0.f, 0.f);
-    if (n < N) {
-      for (int ff = 0; ff < F; ++ff) {
-        const float2 v = up[(int64_t)ff * N + n];
-        g.x += fac[ff] * v.x;
-        g.y += fac[ff] * v.y;
-      }
-      g = cadd(g, cmul(gS, pw[n]));
-      g = cscale(g, gl);
-      if (!isfinite(g.x) || !isfinite(g.y)) rowbad = 1;
-    }
-    gr[i] = g;
-  }
-  rowbad = block_reduce(rowbad, shi, IOr());
-  const bool skip = bad || rowbad;
-
-  const int64_t wrow = pl.off_w + (int64_t)m * N;
-  if (a.mode == FIN_GRAD) {
-    if (a.grad_w) {
-#pragma unroll
-      for (int i = 0; i < kMaxPer; ++i) {
-        const int n = tid + i * kFinThreads;
-        if (n < N) a.grad_w[wrow + n] = gr[i];
-      }
-    }
-    if (a.grad_z && a.orient == 0) {
-      const float T = pl.temperature;
-#pragma unroll
-      for (int i = 0; i < kMaxPer; ++i) {
-        const int n = tid + i * kFinThreads;
-        if (n >= N) continue;
-        float* gz = a.grad_z + pl.off_z + (wrow - pl.off_w + n) * L;
-        const float* zc = a.z + pl.off_z + (wrow - pl.off_w + n) * L;
-        if (a.wave_mode != SQNGD_WAVE_SOFT) {
-          for (int l = 0; l < L; ++l) gz[l] = 0.f;
-          continue;
-        }
-        float zm = zc[0];
-        for (int l = 1; l < L; ++l) zm = fmaxf(zm, zc[l]);
-        float sum = 0.f, ybar = 0.f;
-        for (int l = 0; l < L; ++l) {
-          float e = expf((zc[l] - zm) / T);
-          sum += e;
-          ybar += (float)l * e;
-        }
-        ybar /= sum;
-        const float2 s = a.self_w[wrow + n];
-        const float2 g = gr[i];
-        if (pl.sq_mode == SQNGD_SQ_PHASE_MEAN) {
-          const float dphi = g.y * s.x - g.x * s.y;  // Im(g conj(s))
-          const float c = dphi * 2.0f * 3.14159265358979f / ((float)L * T);
-          for (int l = 0; l < L; ++l) gz[l] = c * (expf((zc[l] - zm) / T) / sum) * ((float)l - ybar);
-        } else {
-          for (int l = 0; l < L; ++l) {
-            const float pi_l = expf((zc[l] - zm) / T) / sum;
-            const float2 ul = level_phasor(l, L);
-            gz[l] = pi_l / T * (g.x * (ul.x - s.x) + g.y * (ul.y - s.y));
-          }
-        }
-      }
-    }
-  } else if (a.mode == FIN_STEP_A) {
-    const int tstep = *a.counter;
-    const int k = tstep * a.opt.n_h + a.inner + 1;
-    const float b1 = a.opt.beta1, b2 = a.opt.beta2;
-    const float bc1 = 1.0f - powf(b1, (float)k), bc2 = 1.0f - powf(b2, (float)k);
-    const bool sgd = (a.opt.flags & SQNGD_OPT_SGD) != 0;
-    float* mh = a.adam + pl.off_state + 2 * (int64_t)M * N * L + 2 * (wrow - pl.off_w);
-    float* vh = mh + 2 * (int64_t)M * N;
-    float2 hn[kMaxPer];
-    float e2 = 0.f;
-#pragma unroll
-    for (int i = 0; i < kMaxPer; ++i) {
-      const int n = tid + i * kFinThreads;
-      hn[i] = make_float2(0.f, 0.f);
-      if (n >= N) continue;
-      float2 hv = a.h[wrow + n];
-      if (!skip) {
-        const float g2[2] = {gr[i].x, gr[i].y};
-        float hv2[2] = {hv.x, hv.y};
-        for (int c = 0; c < 2; ++c) {
-          if (sgd) {
-            hv2[c] -= a.opt.lr_h * g2[c];
-          } else {
-            float mm = b1 * mh[2 * n + c] + (1.0f - b1) * g2[c];
-            float vv = b2 * vh[2 * n + c] + (1.0f - b2) * g2[c] * g2[c];
-            mh[2 * n + c] = mm;
-            vh[2 * n + c] = vv;
-            hv2[c] -= a.opt.lr_h * (mm / bc1) / (sqrtf(vv / bc2) + a.opt.eps);
-          }
-        }
-        hv = make_float2(hv2[0], hv2[1]);
-      }
-      hn[i] = hv;
-      e2 += hv.x * hv.x + hv.y * hv.y;
-    }
-    e2 = block_reduce(e2, shf, FSum());
-    const float sc = skip ? 1.0f : sqrtf((float)N / e2);  // eq. 32
-#pragma unroll
-    for (int i = 0; i < kMaxPer; ++i) {
-      const int n = tid + i * kFinThreads;
-      if (n < N) a.h[wrow + n] = cscale(hn[i], sc);
-    }
-  } else if (a.mode == FIN_STEP_B) {
-    const int tstep = *a.counter;
-    const int k = tstep * a.opt.n_x + a.inner + 1;
-    const float b1 = a.opt.beta1, b2 = a.opt.beta2;
-    const float bc1 = 1.0f - powf(b1, (float)k), bc2 = 1.0f - powf(b2, (float)k);
-    const bool sgd = (a.opt.flags & SQNGD_OPT_SGD) != 0;
-    const float T = temperature_at(a.opt, tstep);
-    float* mz = a.adam + pl.off_state;
-    float* vz = mz + (int64_t)M * N * L;
-#pragma unroll
-    for (int i = 0; i < kMaxPer; ++i) {
-      const int n = tid + i * kFinThreads;
-      if (n >= N || skip) continue;
-      const int64_t zoff = pl.off_z + (wrow - pl.off_w + n) * L;
-      const int64_t soff = (wrow - pl.off_w + n) * L;
-      float* zc = a.z + zoff;
-      float zm = zc[0];
-      for (int l = 1; l < L; ++l) zm = fmaxf(zm, zc[l]);
-      float sum = 0.f, ybar = 0.f;
-      for (int l = 0; l < L; ++l) {
-        float e = expf((zc[l] - zm) / T);
-        sum += e;
-        ybar += (float)l * e;
-      }
-      ybar /= sum;
-      const float2 s = a.self_w[wrow + n];
-      const float2 g = gr[i];
-      const float dphi = g.y * s.x - g.x * s.y;
-      const float c = dphi * 2.0f * 3.14159265358979f / ((float)L * T);
-      for (int l = 0; l < L; ++l) {
-        const float pi_l = expf((zc[l] - zm) / T) / sum;
-        float gv;
-        if (pl.sq_mode == SQNGD_SQ_PHASE_MEAN) {
-          gv = c * pi_l * ((float)l - ybar);
-        } else {
-          const float2 ul = level_phasor(l, L);
-          gv = pi_l / T * (g.x * (ul.x - s.x) + g.y * (ul.y - s.y));
-        }
-        if (sgd) {
-          zc[l] -= a.opt.lr_z * gv;
-        } else {
-          float mm = b1 * mz[soff + l] + (1.0f - b1) * gv;
-          float vv = b2 * vz[soff + l] + (1.0f - b2) * gv * gv;
-          mz[soff + l] = mm;
-          vz[soff + l] = vv;
-          zc[l] -= a.opt.lr_z * (mm / bc1) / (sqrtf(vv / bc2) + a.opt.eps);
-        }
-      }
-    }
-  }
 
   if (a.count_step) {
     __syncthreads();
     if (tid == 0) {
       __threadfence();
       const int old = atomicAdd(a.done, 1);
-      if (old == a.nrows - 1) {
+      if (old == a.nrows_total - 1) {
         atomicExch(a.done, 0);
         atomicAdd(a.counter, 1);
       }
+    }
+  }
+}
+
+// ------------------------------------------------------------ k_pass_split
+
+// Latency variant of the fused pass for small batches: one wave per
+// (Doppler bin, partner) pair instead of one wave per Doppler bin looping
+// over the partners. A block holds UB = WV / M units of one row, all M
+// partners of each; the partners' adjoint spectra and statistics are
+// combined per unit in LDS (relative to the unit's largest pair scale), then
+// the units per block as in k_pass. Every wave computes its unit's modulated
+// spectrum itself. Needs one FFT per wave (P >= 512) and M <= WV.
+template <int P, int PHLOG, int WV>
+__global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
+  using G = Geom<P>;
+  static_assert(G::TF == 64, "one FFT per wave");
+  constexpr int E = G::E, EH = E / 2;
+  __shared__ float2 lds[WV * P];
+  __shared__ float g_sig[WV], g_S[WV];
+  __shared__ unsigned long long g_ka[WV], g_kc[WV];
+  __shared__ float u_sig[WV], u_S[WV];
+  __shared__ unsigned long long u_ka[WV], u_kc[WV];
+  const int wv = threadIdx.x >> 6, t = threadIdx.x & 63;
+  float2* buf = lds + wv * P;
+  int base = 0;
+  ProbPlan pl;
+  if (a.single) {
+    pl = a.one;
+  } else {
+    const int entry = find_entry(a.gwave, a.gn, blockIdx.x);
+    pl = a.plans[a.gprob[entry]];
+    base = a.gwave[entry];
+  }
+  const int M = pl.M, N = pl.N, F = pl.F;
+  const int UB = WV / M;
+  const int j = wv / M, g = wv - (wv / M) * M;
+  const bool wave_on = j < UB;
+  const int lb = blockIdx.x - base;
+  const int w = lb / pl.wpr;
+  const int grp = lb - w * pl.wpr;
+  const int fs = grp * UB + j;
+  const bool active = wave_on && fs < F;
+  const int f = fs < F ? fs : F - 1;
+  const int u = w * F + f;
+  const float invN = 1.0f / (float)N;
+  const float nu = (a.orient ? -1.0f : 1.0f) * (pl.nu_min + (float)f * pl.dnu);
+  const int wlo = a.orient ? -pl.tau_hi : pl.tau_lo;
+  const int whi = a.orient ? -pl.tau_lo : pl.tau_hi;
+  const float phm1 = 0.5f * pl.p - 1.0f;
+  const bool grad = a.want_grad != 0;
+
+  // global loads first, then the arithmetic that hides their latency
+  const float2* sg = a.spec + pl.ws_spec + (int64_t)(wave_on ? g : 0) * P;
+  const float2* sw = a.self_w + pl.off_w + (int64_t)w * N;
+  float2 SG[E], X[E];
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    SG[e] = sg[e * 64 + t];
+    X[e] = make_float2(0.f, 0.f);
+    if constexpr (e < EH) {
+      const int n = t + 64 * e;
+      if (n < N) X[e] = sw[n];
+    }
+  });
+  WaveTwiddles<P> W;
+  W.init(t);
+  static_for<EH>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    X[e] = cmul(X[e], phasor(t + 64 * e, nu, invN));
+  });
+  fft_forward<P>(X, buf, t, W);
+
+  // this wave's pair (unit j, partner g)
+  float2 R[E];
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    R[e] = cmulc(X[e], SG[e]);
+  });
+  fft_inverse<P>(R, buf, t, W);
+  uint32_t vmask = 0;
+  float qmax = 0.f;
+  int kbest = 0;
+  float2* cube = a.cube ? a.cube + pl.off_cube : nullptr;
+  const float invP = 1.0f / (float)P;
+  const int T2 = 2 * N - 1;
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    const int k = t + 64 * e;
+    int tp = 0;
+    bool inr = false;
+    if (k <= N - 1) {
+      tp = -k;
+      inr = true;
+    } else if (k >= P - N + 1) {
+      tp = P - k;
+      inr = true;
+    }
+    const bool valid = inr && tp >= wlo && tp <= whi && !(g == w && tp == 0);
+    if (valid) {
+      vmask |= 1u << e;
+      const float q = R[e].x * R[e].x + R[e].y * R[e].y;
+      if (q > qmax) {
+        qmax = q;
+        kbest = k;
+      }
+    }
+    if (cube != nullptr && active && inr)
+      cube[((int64_t)(w * M + g) * F + f) * T2 + tp + N - 1] = cscale(R[e], invP);
+  });
+  // wave maximum, and its cell from the lowest lane that holds it
+  const float qw = wave_max(qmax);
+  const unsigned long long holders = __ballot(vmask != 0 && qmax == qw);
+  const int src = holders ? __ffsll((long long)holders) - 1 : 0;
+  const int kb = __builtin_amdgcn_readlane(kbest, src);
+  const unsigned long long key = holders ? make_key(qw, (uint32_t)(((int64_t)u * M + g) * P + kb)) : 0ull;
+  const float sigma = sqrtf(qw);
+  const float inv_s = sigma > 0.f ? 1.0f / sigma : 0.f;
+  const float inv_s2 = inv_s * inv_s;
+  float S = 0.f;
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    if (vmask & (1u << e)) {
+      const float x = (R[e].x * R[e].x + R[e].y * R[e].y) * inv_s2;
+      float ym1, y;
+      pow_ph<PHLOG>(x, phm1, ym1, y);
+      S += y;
+      R[e] = cscale(R[e], ym1 * inv_s);
+    } else {
+      R[e] = make_float2(0.f, 0.f);
+    }
+  });
+  S = wave_sum(S);
+  if (t == 0) {
+    g_sig[wv] = active ? sigma : 0.f;
+    g_S[wv] = active ? S : 0.f;
+    g_ka[wv] = active && g == w ? key : 0ull;
+    g_kc[wv] = active && g != w ? key : 0ull;
+  }
+  if (grad) {
+    fft_forward<P>(R, buf, t, W);
+    wave_lds_sync();
+    static_for<E>([&](auto ec) {
+      constexpr int e = decltype(ec)::value;
+      buf[e * 64 + t] = cmul(R[e], SG[e]);
+    });
+  }
+  __syncthreads();
+
+  // per unit: the partner waves combined by the unit's first wave
+  if (wave_on && g == 0) {
+    float su = 0.f;
+    for (int gg = 0; gg < M; ++gg) su = fmaxf(su, g_sig[j * M + gg]);
+    const float inv_u = su > 0.f ? 1.0f / su : 0.f;
+    float Su = 0.f;
+    unsigned long long ka = 0, kc = 0;
+    float2 U[E];
+    static_for<E>([&](auto ec) { U[decltype(ec)::value] = make_float2(0.f, 0.f); });
+    for (int gg = 0; gg < M; ++gg) {
+      const int src = j * M + gg;
+      const float c = g_sig[src] * inv_u;
+      float cm1, cp;
+      pow_ph<PHLOG>(c * c, phm1, cm1, cp);
+      Su += cp * g_S[src];
+      ka = umax64(ka, g_ka[src]);
+      kc = umax64(kc, g_kc[src]);
+      if (grad) {
+        const float fc = cm1 * c;  // (sigma_g / sigma_u)^(p-1)
+        static_for<E>([&](auto ec) {
+          constexpr int e = decltype(ec)::value;
+          const float2 v = lds[src * P + e * 64 + t];
+          U[e].x += fc * v.x;
+          U[e].y += fc * v.y;
+        });
+      }
+    }
+    if (t == 0) {
+      u_sig[j] = su;
+      u_S[j] = Su;
+      u_ka[j] = ka;
+      u_kc[j] = kc;
+    }
+    if (grad) {
+      fft_inverse<P>(U, buf, t, W);
+      wave_lds_sync();
+      static_for<EH>([&](auto ec) {
+        constexpr int e = decltype(ec)::value;
+        const int n = t + 64 * e;
+        if (n < N) buf[n] = active ? cmulc(U[e], phasor(n, nu, invN)) : make_float2(0.f, 0.f);
+      });
+    }
+  }
+  __syncthreads();
+
+  // block combine over the UB units (unit order fixed)
+  float sb = 0.f;
+  for (int jj = 0; jj < UB; ++jj) sb = fmaxf(sb, u_sig[jj]);
+  const float inv_b = sb > 0.f ? 1.0f / sb : 0.f;
+  const int64_t ent = (int64_t)w * pl.wpr + grp;
+  if (threadIdx.x == 0) {
+    float Sb = 0.f;
+    unsigned long long ka = 0, kc = 0;
+    for (int jj = 0; jj < UB; ++jj) {
+      const float c = u_sig[jj] * inv_b;
+      float cm1, cp;
+      pow_ph<PHLOG>(c * c, phm1, cm1, cp);
+      Sb += cp * u_S[jj];
+      ka = umax64(ka, u_ka[jj]);
+      kc = umax64(kc, u_kc[jj]);
+    }
+    UnitStat st;
+    st.sigma = sb;
+    st.S = Sb;
+    st.pad0 = st.pad1 = 0;
+    st.key_auto = ka;
+    st.key_cross = kc;
+    a.ustat[pl.ws_unit + ent] = st;
+  }
+  if (grad) {
+    float2* up = a.upart + pl.ws_upart + ent * N;
+    for (int n = threadIdx.x; n < N; n += 64 * WV) {
+      float2 acc = make_float2(0.f, 0.f);
+      for (int jj = 0; jj < UB; ++jj) {
+        const float c = u_sig[jj] * inv_b;
+        float cm1, cp;
+        pow_ph<PHLOG>(c * c, phm1, cm1, cp);
+        const float fc = cm1 * c;
+        const float2 v = lds[(jj * M) * P + n];
+        acc.x += fc * v.x;
+        acc.y += fc * v.y;
+      }
+      up[n] = acc;
     }
   }
 }
@@ -773,10 +1338,6 @@ __global__ __launch_bounds__(256) void k_hardq(HardArgs a) {
     if (a.idx) a.idx[pl.off_w + c] = l;
     if (a.x) a.x[pl.off_w + c] = level_phasor(l, pl.L);
   }
-}
-
-__global__ void k_zero_i32(int32_t* p, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
 }  // namespace sq

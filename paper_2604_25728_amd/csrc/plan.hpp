@@ -19,14 +19,16 @@ struct ProbPlan {
   float nu_min, dnu, p, p_tar;
   float w_psl, w_snrl, temperature, inv_NP;
   int32_t sq_mode, ph_log;  // ph_log = log2(p/2) when p/2 is a power of two <= 32, else -1
-  int32_t units, row0;      // units = M*F; row0 = first row of this problem in the batch
+  int32_t units, row0;      // units = M*wpr statistics entries; row0 = first row in the batch
+  int32_t wpr, pad0;        // fused-pass blocks per row (ceil(F / Doppler bins per block))
   int64_t off_z, off_w, off_state, off_cube;
   int64_t ws_spec;   // complex: [M][P] spectra
   int64_t ws_unit;   // UnitStat index and row index of upart ([units][N] complex, stride N)
   int64_t ws_upart;  // complex offset of this problem's unit partials
   int64_t pad;
 };
-static_assert(sizeof(ProbPlan) == 144, "ProbPlan layout");
+static_assert(sizeof(ProbPlan) == 152, "ProbPlan layout");
+
 
 // Per-unit partial statistics of one fused pass. Keys pack the squared raw
 // magnitude (float bits, monotone for non-negative values) in the high word
@@ -48,12 +50,14 @@ struct WsHeader {
   int64_t group_prob[kNumPGroups];   // byte offset of int32 problem ids of each FFT-length group
   int64_t group_wave[kNumPGroups];   // byte offset of int32 [n+1] wave prefix (fused pass)
   int64_t group_rwave[kNumPGroups];  // byte offset of int32 [n+1] wave prefix (one slot per row)
+  int64_t group_rows[kNumPGroups];   // byte offset of int32 batch rows of each group
   int32_t group_n[kNumPGroups];
   int32_t group_waves[kNumPGroups];
   int32_t group_rwaves[kNumPGroups];
-  int32_t pad1;
+  int32_t group_nrows[kNumPGroups];
   int64_t row_prob;       // byte offset of int32 [nrows]: problem of each row
-  int64_t spec, wself, wpart, ustat, upart, snrl, counters;  // region byte offsets
+  int64_t spec, wself, wpart, ustat, upart, counters;  // region byte offsets
+  int64_t snrl;  // float4 [2][rows]: mainlobe products, double-buffered by pass parity
   int64_t total;
 };
 

@@ -21,7 +21,7 @@ OPT_SGD = 1
 
 SYMBOLS = [
     "sqngd_buffer_sizes", "sqngd_workspace_size", "sqngd_workspace_init", "sqngd_af_forward",
-    "sqngd_af_backward", "sqngd_step", "sqngd_hard_quantize", "sqngd_status_string",
+    "sqngd_af_backward", "sqngd_step", "sqngd_run", "sqngd_hard_quantize", "sqngd_status_string",
     "sqngd_last_hip_error", "sqngd_profile_enable", "sqngd_profile_read",
 ]
 
@@ -70,6 +70,7 @@ def load():
     lib.sqngd_af_forward.argtypes = [P, i32, P, i32, P, P, P, P, P, sz, P]
     lib.sqngd_af_backward.argtypes = [P, i32, P, i32, P, P, P, P, P, P, P, P, sz, P]
     lib.sqngd_step.argtypes = [P, i32, P, P, P, P, P, P, P, sz, P]
+    lib.sqngd_run.argtypes = [P, i32, P, i32, P, P, P, P, P, P, sz, P]
     lib.sqngd_hard_quantize.argtypes = [P, i32, P, P, P, P, sz, P]
     lib.sqngd_status_string.argtypes = [ctypes.c_int]
     lib.sqngd_status_string.restype = ctypes.c_char_p
@@ -241,6 +242,11 @@ class Batch:
         check(self.lib.sqngd_step(self._arr, self.n, ctypes.byref(opt), _ptr(z), _ptr(h), _ptr(adam),
                                   _ptr(counter), _ptr(stats), self._ws_ptr, self.ws_bytes,
                                   _stream()), "step")
+
+    def run(self, opt: Opt, n_iters: int, z, h, adam, counter, stats=None):
+        check(self.lib.sqngd_run(self._arr, self.n, ctypes.byref(opt), int(n_iters), _ptr(z), _ptr(h),
+                                 _ptr(adam), _ptr(counter), _ptr(stats), self._ws_ptr, self.ws_bytes,
+                                 _stream()), "run")
 
     def hard_quantize(self, z, want_idx=True, want_x=True):
         import torch

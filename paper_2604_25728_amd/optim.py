@@ -40,32 +40,44 @@ class SQNGD:
         self.counter = torch.zeros(1, dtype=torch.int32, device=dev)
         self.stats = self.batch.new_stats(2 * self.batch.n)
         self.graph = None
+        self.graph_iters = 0
 
     # ------------------------------------------------------------------ steps
-    def step(self):
-        """Enqueue one outer iteration on the current stream."""
-        self.batch.step(self.opt, self.z, self.h, self.adam, self.counter, self.stats)
+    def step(self, n_iters: int = 1):
+        """Enqueue n_iters outer iterations (one sqngd_run call) on the current stream."""
+        if n_iters == 1:
+            self.batch.step(self.opt, self.z, self.h, self.adam, self.counter, self.stats)
+        else:
+            self.batch.run(self.opt, n_iters, self.z, self.h, self.adam, self.counter, self.stats)
 
-    def capture(self):
-        """Record one outer iteration in a HIP graph; replay() then runs it."""
+    def capture(self, iters_per_graph: int = 1):
+        """Record iters_per_graph outer iterations in a HIP graph; replay() runs them."""
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.step()
+            self.step(iters_per_graph)
         self.graph = g
+        self.graph_iters = iters_per_graph
         return g
 
     def replay(self):
         self.graph.replay()
 
-    def run(self, iters: int, use_graph: bool = True):
-        if use_graph and self.graph is None:
-            self.capture()
-        for _ in range(iters):
-            if use_graph:
-                self.graph.replay()
-            else:
-                self.step()
+    def run(self, iters: int, use_graph: bool = True, iters_per_graph: int = 10):
+        """iters outer iterations: graph replays of iters_per_graph iterations, then the rest eagerly."""
+        if not use_graph:
+            done = 0
+            while done < iters:
+                k = min(iters_per_graph, iters - done)
+                self.step(k)
+                done += k
+            return
+        if self.graph is None or self.graph_iters != iters_per_graph:
+            self.capture(iters_per_graph)
+        for _ in range(iters // iters_per_graph):
+            self.graph.replay()
+        if iters % iters_per_graph:
+            self.step(iters % iters_per_graph)
 
     # ------------------------------------------------------------- inspection
     @property

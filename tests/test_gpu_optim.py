@@ -196,3 +196,46 @@ def test_autograd_function(ref, mods):
                                  h0.astype(np.complex128), prob)
     assert _rel(sg.grad.cpu().numpy(), gs2) <= 1e-4
     assert _rel(h2.grad.cpu().numpy(), gh2) <= 1e-4
+
+
+@pytest.mark.parametrize("n_h,n_x", [(1, 1), (2, 2), (0, 1), (1, 0)])
+def test_chained_run_matches_oracle(ref, mods, n_h, n_x):
+    """sqngd_run over several iterations (updates prepare the next evaluation
+    inside the finalize kernel) against the oracle's iterations from the same
+    start, for every combination of inner-step counts the chaining handles."""
+    nat, optim, _ = mods
+    prob = I.config("c1")["problem"]
+    opt = I.make_opt(n_h=n_h, n_x=n_x, total_iters=20, T0=1.0, T1=0.3)
+    print(f"[gpu] chained run n_h={n_h} n_x={n_x}", flush=True)
+    run = optim.SQNGD([prob], opt, seeds=[11])
+    s0 = run.numpy_state(0)
+    iters = 3
+    run.step(iters)
+    torch.cuda.synchronize()
+    s1 = run.numpy_state(0)
+    z, h, state = s0["z"], s0["h"], s0["state"]
+    for t in range(iters):
+        z, h, state, sta, stb = ref.step(prob, opt, z, h, state, t)
+    assert s1["t"] == iters
+    assert _rel(s1["h"], h) <= 1e-4, _rel(s1["h"], h)
+    assert _rel(s1["z"], z) <= 1e-4, _rel(s1["z"], z)
+    sa, sb = run.step_stats()
+    if n_h:
+        assert abs(sa[0]["loss"] - sta["loss"]) <= 1e-4 * sta["loss"]
+    if n_x:
+        assert abs(sb[0]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"]
+
+
+def test_chained_graph_matches_eager_run(mods):
+    nat, optim, _ = mods
+    c = I.config("c2")
+    print("[gpu] chained graph vs eager run", flush=True)
+    a = optim.SQNGD([c["problem"]], c["opt"], seeds=[3])
+    b = optim.SQNGD([c["problem"]], c["opt"], seeds=[3])
+    a.capture(5)
+    for i in range(3):
+        a.replay()
+        b.step(5)
+        torch.cuda.synchronize()
+        assert torch.equal(a.z, b.z) and torch.equal(a.h, b.h), i
+    assert a.t == b.t == 15

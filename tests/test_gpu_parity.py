@@ -70,6 +70,8 @@ SHAPES = {
     "phasor": I.make_problem(2, 40, 6, 9, p=16.0, sq_mode=I.PHASOR_MEAN, temperature=0.8),
     "n512": I.make_problem(2, 512, 4, 5, nu_min=-0.5, nu_max=0.5, p=16.0),
     "n1024": I.make_problem(2, 1024, 4, 3, nu_min=-2.5, nu_max=2.5, p=16.0),
+    "m3n256": I.make_problem(3, 256, 4, 11, nu_min=-0.4, nu_max=0.6, p=16.0, tau_lo=-200, tau_hi=150),
+    "m5n300": I.make_problem(5, 300, 8, 7, p=8.0),
 }
 
 
@@ -183,3 +185,26 @@ def test_deterministic(nat):
     torch.cuda.synchronize()
     for a, c in zip(r1, r2):
         assert torch.equal(a, c)
+
+
+def test_latency_and_throughput_variants_agree(ref, nat):
+    """A single small design runs the per-(bin, partner) variant of the fused
+    pass; the same design inside a large batch runs the per-bin variant. Both
+    must give the same statistics and gradients to FP32 rounding."""
+    prob = I.config("c2")["problem"]
+    M, N, L = prob["M"], prob["N"], prob["L"]
+    print("[gpu] split vs throughput variants", flush=True)
+    zs = [I.logits(M, N, L, 30 + i) for i in range(8)]
+    hs = [I.complex_gaussian(M, N, 50 + i) for i in range(8)]
+    one = nat.Batch([prob])
+    many = nat.Batch([prob] * 8)
+    s1, s8 = one.new_stats(), many.new_stats()
+    g1 = one.af_backward(one.pack_z(zs[:1]), one.pack_w(hs[:1]), nat.WAVE_SOFT, want_s=True, stats=s1)
+    g8 = many.af_backward(many.pack_z(zs), many.pack_w(hs), nat.WAVE_SOFT, want_s=True, stats=s8)
+    torch.cuda.synchronize()
+    a, b = nat.decode_stats(s1.cpu().numpy())[0], nat.decode_stats(s8.cpu().numpy())[0]
+    assert abs(a["loss"] - b["loss"]) <= 1e-5 * a["loss"]
+    assert a["psl_auto"] == pytest.approx(b["psl_auto"], rel=1e-5)
+    for x, y in zip(g1, g8):
+        n = x.numel()
+        assert _rel(x.cpu().numpy(), y[:n].cpu().numpy()) <= 1e-5

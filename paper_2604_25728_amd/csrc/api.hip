@@ -3,6 +3,7 @@
 // declared in include/sqngd.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -72,6 +73,10 @@ struct Plan {
   std::vector<char> bytes;  // [0, hdr.spec): header, plans, tables
   std::vector<ProbPlan> plans;
   int group_phlog[kNumPGroups];
+  // finalize of the optimiser steps: 0 = k_final, else k_step with this
+  // bound on the logit levels per lane
+  int group_step[kNumPGroups];
+  bool all_step = true;  // every group runs k_step: the step counter advances in the next pass
   int maxN = 0;
   bool split = false;  // the fused pass runs as k_pass_split (small batches)
   uint64_t hash = 0;
@@ -186,6 +191,15 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     H.group_waves[g] = wsum;
     H.group_rwaves[g] = rsum;
     pl->group_phlog[g] = phl;
+    {
+      const int tpc = P > 2 * kStepThreads ? 1 : (P >= 256 ? 2 * kStepThreads / P : 8);
+      int lv = 0;
+      for (int id : gprob[g]) lv = std::max(lv, (pl->plans[id].L + tpc - 1) / tpc);
+      int mode = lv <= 4 ? 4 : (lv <= 16 ? 16 : 0);
+      if (P > 2 * kStepThreads) mode = 0;
+      pl->group_step[g] = mode;
+      if (!gprob[g].empty() && mode == 0) pl->all_step = false;
+    }
     H.group_prob[g] = (int64_t)off;
     off = align_up(off + 4 * gprob[g].size());
     H.group_wave[g] = (int64_t)off;
@@ -216,6 +230,10 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
   off = align_up(off + 8 * (size_t)upart);
   H.snrl = (int64_t)off;
   off = align_up(off + 2 * 16 * (size_t)rows);
+  H.gbuf = (int64_t)off;
+  off = align_up(off + 8 * (size_t)off_w);
+  H.pflag = (int64_t)off;
+  off = align_up(off + 4 * (size_t)nprob);
   H.total = (int64_t)off;
   int maxN = 0;
   for (int i = 0; i < nprob; ++i) maxN = probs[i].N > maxN ? probs[i].N : maxN;
@@ -288,6 +306,8 @@ struct Ptrs {
   UnitStat* ustat;
   float2* upart;
   float4* snrl;
+  float2* gbuf;
+  int32_t* pflag;
 };
 
 Ptrs ptrs(const Plan& pl, void* ws) {
@@ -302,7 +322,9 @@ Ptrs ptrs(const Plan& pl, void* ws) {
               (float2*)(b + H.wpart),
               (UnitStat*)(b + H.ustat),
               (float2*)(b + H.upart),
-              (float4*)(b + H.snrl)};
+              (float4*)(b + H.snrl),
+              (float2*)(b + H.gbuf),
+              (int32_t*)(b + H.pflag)};
 }
 
 // ----------------------------------------------------------- launch helpers
@@ -398,6 +420,19 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
       }
     }
     if (slot >= 0) hipEventRecord(g_prof.ev[2 * slot + 1], s);
+    a.bump = nullptr;  // the first kernel of the pass advances the counter
+  }
+}
+
+template <int P>
+void launch_step_p(const FinArgs& a, int lv, dim3 grid, hipStream_t s) {
+  const dim3 block(kStepThreads);
+  if (a.mode == FIN_STEP_A) {
+    if (lv == 4) hipLaunchKernelGGL((k_step<P, FIN_STEP_A, 4>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step<P, FIN_STEP_A, 16>), grid, block, 0, s, a);
+  } else {
+    if (lv == 4) hipLaunchKernelGGL((k_step<P, FIN_STEP_B, 4>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step<P, FIN_STEP_B, 16>), grid, block, 0, s, a);
   }
 }
 
@@ -411,12 +446,27 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
   a.wpart = w.wpart;
   a.spec = w.spec;
   a.done = w.counters;
+  a.gbuf = w.gbuf;
+  a.pflag = w.pflag;
   a.single = pl.hdr.nprob == 1;
   a.one = pl.plans[0];
   for (int g = 0; g < kNumPGroups; ++g) {
     if (pl.hdr.group_nrows[g] == 0) continue;
     a.rows = (const int32_t*)(w.base + pl.hdr.group_rows[g]);
     const dim3 grid(pl.hdr.group_nrows[g]), block(kFinThreads);
+    if ((a.mode == FIN_STEP_A || a.mode == FIN_STEP_B) && pl.group_step[g] != 0) {
+      const int lv = pl.group_step[g];
+      // gradient rows: N <= P/2 chips per row in blocks of kGradChips
+      a.grad_chunks = (1 << (g + kMinLogP)) / (2 * kGradChips);
+      hipLaunchKernelGGL(k_grad, dim3(pl.hdr.group_nrows[g] * a.grad_chunks), dim3(kGradThreads), 0, s, a);
+      switch (g) {
+        case 0: launch_step_p<128>(a, lv, grid, s); break;
+        case 1: launch_step_p<256>(a, lv, grid, s); break;
+        case 2: launch_step_p<512>(a, lv, grid, s); break;
+        default: launch_step_p<1024>(a, lv, grid, s); break;
+      }
+      continue;
+    }
     switch (g) {
       case 0: hipLaunchKernelGGL(k_final<128>, grid, block, 0, s, a); break;
       case 1: hipLaunchKernelGGL(k_final<256>, grid, block, 0, s, a); break;
@@ -657,6 +707,11 @@ int sqngd_run(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, i
   Ptrs w = ptrs(*pl, ws);
   float4* snrl_buf[2] = {w.snrl, w.snrl + pl->hdr.nrows};
   int q = 0;  // pass index within the call: pass q reads snrl_buf[q & 1]
+  // With k_step on every group, the finalize that ends an outer iteration
+  // leaves the step counter to the first kernel of the next pass (which does
+  // not read it), saving the last-block atomics; the last iteration of the
+  // call advances it itself.
+  int32_t* bump = nullptr;
   // inputs of the first pass
   PrepArgs pa{};
   pa.mode = o.n_h > 0 ? PREP_A_HARD : PREP_B_SOFT;
@@ -674,6 +729,8 @@ int sqngd_run(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, i
       ka.orient = 1;
       ka.want_grad = 1;
       ka.self_w = (const float2*)h;
+      ka.bump = bump;
+      bump = nullptr;
       launch_pass(*pl, w, ka, s);
       FinArgs fa{};
       fa.orient = 1;
@@ -691,6 +748,10 @@ int sqngd_run(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, i
       fa.adam = adam_state;
       fa.counter = step_counter;
       fa.opt = o;
+      if (fa.count_step && fa.next != NEXT_NONE && pl->all_step) {
+        fa.count_step = 0;
+        bump = step_counter;
+      }
       launch_final(*pl, w, fa, s);
     }
     for (int j = 0; j < o.n_x; ++j, ++q) {
@@ -698,6 +759,8 @@ int sqngd_run(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, i
       ka.orient = 0;
       ka.want_grad = 1;
       ka.self_w = w.wself;
+      ka.bump = bump;
+      bump = nullptr;
       launch_pass(*pl, w, ka, s);
       FinArgs fa{};
       fa.orient = 0;
@@ -720,6 +783,10 @@ int sqngd_run(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, i
       fa.adam = adam_state;
       fa.counter = step_counter;
       fa.opt = o;
+      if (fa.count_step && fa.next != NEXT_NONE && pl->all_step) {
+        fa.count_step = 0;
+        bump = step_counter;
+      }
       launch_final(*pl, w, fa, s);
     }
   }

@@ -86,8 +86,11 @@ __device__ __forceinline__ void pow_ph(float x, float phm1, float& y_m1, float& 
 __device__ __forceinline__ float temperature_at(const sqngd_opt& o, int t) {
   if (o.total_iters <= 1) return o.T0;
   float frac = fminf((float)t, (float)(o.total_iters - 1)) / (float)(o.total_iters - 1);
-  return o.T0 * powf(o.T1 / o.T0, frac);
+  return o.T0 * exp2f(frac * log2f(o.T1 / o.T0));
 }
+
+// 1 - b^k for the Adam bias corrections (0 < b < 1, k >= 1).
+__device__ __forceinline__ float bias_corr(float b, int k) { return 1.0f - exp2f((float)k * log2f(b)); }
 
 // Soft-quantised chip from its L logits (softmax at temperature T).
 __device__ __forceinline__ float2 soft_chip(const float* zc, int L, float T, int mode) {
@@ -263,6 +266,7 @@ struct PassArgs {
   int32_t orient;
   int32_t want_grad;
   int32_t pad;
+  int32_t* bump;  // if set, block 0 advances this step counter (deferred by the previous finalize)
   const float2* self_w;
   const float2* spec;
   UnitStat* ustat;
@@ -283,6 +287,7 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
   __shared__ float u_sig[UPB], u_S[UPB];
   __shared__ unsigned long long u_ka[UPB], u_kc[UPB];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, slot = lane / TF, t = lane % TF;
+  if (a.bump != nullptr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.bump, 1);
   float2* buf = lds + wv * G::LDS + slot * P;
   int base = 0;
   ProbPlan pl;
@@ -580,6 +585,9 @@ struct FinArgs {
   int32_t* counter;
   int32_t* done;
   sqngd_opt opt;
+  float2* gbuf;         // gradient rows (k_grad -> k_step)
+  int32_t* pflag;       // per problem: the loss is not finite (k_grad -> k_step)
+  int32_t grad_chunks;  // k_grad blocks per row
   int32_t single;  // one problem: its plan is `one`, rows are the block indices
   ProbPlan one;
 };
@@ -715,6 +723,48 @@ __device__ __forceinline__ void seg_argmax(float& v, int& idx, int LP) {
       idx = oi;
     }
   }
+}
+
+
+// Statistics record of one problem (eq. 8-10, 48): loss terms, the auto and
+// cross PSL with the cell that holds the peak, the PSLR and the SNRL of the
+// worst waveform, from the reduced maximum keys and the mainlobe products of
+// the problem's M rows.
+__device__ __forceinline__ void stats_record(sqngd_stats* out, const ProbPlan& pl, int orient, float loss,
+                                          float lp_raw, float l_snrl, unsigned long long ka,
+                                          unsigned long long kc, const float4* snrl_rows, bool bad) {
+  const int M = pl.M, N = pl.N, F = pl.F, Pl = pl.P;
+  float snrl_max = -INFINITY, p_min = INFINITY;
+  for (int k = 0; k < M; ++k) {
+    const float4 c4 = snrl_rows[k];
+    const float mag = sqrtf(c4.x * c4.x + c4.y * c4.y);
+    snrl_max = fmaxf(snrl_max, 10.0f * log10f(c4.z * c4.w / (mag * mag)));
+    p_min = fminf(p_min, mag / (float)N);
+  }
+  sqngd_stats& st = *out;
+  st.loss = loss;
+  st.lp = lp_raw * pl.inv_NP;
+  st.l_snrl = l_snrl;
+  const float invP = 1.0f / (float)Pl;
+  st.psl_auto = sqrtf(key_q(ka)) * invP;
+  st.psl_cross = sqrtf(key_q(kc)) * invP;
+  st.pslr_db = 20.0f * log10f(fmaxf(st.psl_auto, st.psl_cross) / (float)N);
+  st.snrl_db_max = snrl_max;
+  st.p_min = p_min;
+  const unsigned long long kb = key_q(ka) >= key_q(kc) ? ka : kc;
+  const uint32_t cell = key_cell(kb);
+  const int kk = (int)(cell % (uint32_t)Pl);
+  const uint32_t rest = cell / (uint32_t)Pl;
+  const int gg = (int)(rest % (uint32_t)M);
+  const int uu = (int)(rest / (uint32_t)M);
+  const int ww = uu / F, ff = uu % F;
+  const int tp = kk <= N - 1 ? -kk : Pl - kk;
+  st.arg_m = orient == 0 ? ww : gg;
+  st.arg_l = orient == 0 ? gg : ww;
+  st.arg_tau = orient == 0 ? tp : -tp;
+  st.arg_f = ff;
+  st.nonfinite = bad ? 1u : 0u;
+  st.reserved[0] = st.reserved[1] = st.reserved[2] = 0;
 }
 
 // One block per row of the batch. The block
@@ -1036,42 +1086,539 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
   }
 
   // ---- 7. statistics record
-  if (m == 0 && tid == 0 && a.stats != nullptr) {
-    const int Pl = pl.P;
-    float snrl_max = -INFINITY, p_min = INFINITY;
-    for (int k = 0; k < M; ++k) {
-      const float4 c4 = snrl_sh[k];
-      const float mag = sqrtf(c4.x * c4.x + c4.y * c4.y);
-      snrl_max = fmaxf(snrl_max, 10.0f * log10f(c4.z * c4.w / (mag * mag)));
-      p_min = fminf(p_min, mag / (float)N);
-    }
-    sqngd_stats st;
-    st.loss = loss;
-    st.lp = lp_raw * pl.inv_NP;
-    st.l_snrl = l_snrl;
-    const float invP = 1.0f / (float)Pl;
-    st.psl_auto = sqrtf(key_q(ka)) * invP;
-    st.psl_cross = sqrtf(key_q(kc)) * invP;
-    st.pslr_db = 20.0f * log10f(fmaxf(st.psl_auto, st.psl_cross) / (float)N);
-    st.snrl_db_max = snrl_max;
-    st.p_min = p_min;
-    const unsigned long long kb = key_q(ka) >= key_q(kc) ? ka : kc;
-    const uint32_t cell = key_cell(kb);
-    const int kk = (int)(cell % (uint32_t)Pl);
-    const uint32_t rest = cell / (uint32_t)Pl;
-    const int gg = (int)(rest % (uint32_t)M);
-    const int uu = (int)(rest / (uint32_t)M);
-    const int ww = uu / F, ff = uu % F;
-    const int tp = kk <= N - 1 ? -kk : Pl - kk;
-    st.arg_m = a.orient == 0 ? ww : gg;
-    st.arg_l = a.orient == 0 ? gg : ww;
-    st.arg_tau = a.orient == 0 ? tp : -tp;
-    st.arg_f = ff;
-    st.nonfinite = bad ? 1u : 0u;
-    st.reserved[0] = st.reserved[1] = st.reserved[2] = 0;
-    a.stats[pid] = st;
-  }
+  if (m == 0 && tid == 0 && a.stats != nullptr)
+    stats_record(a.stats + pid, pl, a.orient, loss, lp_raw, l_snrl, ka, kc, snrl_sh, bad);
   if (a.mode == FIN_STATS) return;
+
+  if (a.count_step) {
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      const int old = atomicAdd(a.done, 1);
+      if (old == a.nrows_total - 1) {
+        atomicExch(a.done, 0);
+        atomicAdd(a.counter, 1);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ k_grad / k_step
+
+// The finalize of an optimiser step (Algorithm 1; step A: filter update and
+// projection, eq. 31-32; step B: chain rule through the soft quantiser and
+// logit update) for problems with P <= 1024 runs as two latency-oriented
+// kernels instead of k_final's one block per row:
+//   k_grad  many blocks per row: every block reduces the problem's unit
+//           statistics to L_p and the loss (all in the same order, so all
+//           agree), then the gradient of its chips: the Doppler partials
+//           scaled by (w_psl / (N P)) (sigma_u / L_p)^(p-1), 16 lanes per
+//           chip, plus the SNRL term. The row's partials are read by many
+//           compute units at once instead of one.
+//   k_step  one block per row: the update, the next pass's waveform samples,
+//           their energy and mainlobe sums, the partner spectrum. TPC
+//           consecutive lanes own one chip (quad DPP between them), so the
+//           chain rule's per-chip softmax, the Adam updates and the
+//           quantisation stay in the chip's lanes; one block barrier for the
+//           row sums. The projection scale of eq. 32 is known only after it,
+//           so it is applied to the sums and, by linearity, to the spectrum
+//           of the unscaled row. A non-finite loss or gradient (rare) is
+//           handled after the barrier by redoing the next-pass inputs from
+//           the unchanged state.
+
+constexpr int kStepThreads = 512;
+constexpr int kStepWaves = kStepThreads / 64;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+// Sums / maxima over the TPC lanes of a chip (aligned groups of TPC lanes);
+// every lane of the group gets the same value.
+template <int TPC>
+__device__ __forceinline__ float chip_sum(float v) {
+  if constexpr (TPC >= 2) v += dpp_f<0xB1, 0xF>(0.f, v);  // quad_perm [1,0,3,2]
+  if constexpr (TPC >= 4) v += dpp_f<0x4E, 0xF>(0.f, v);  // quad_perm [2,3,0,1]
+  if constexpr (TPC >= 8) v += __shfl_xor(v, 4);
+  return v;
+}
+template <int TPC>
+__device__ __forceinline__ float chip_max(float v) {
+  if constexpr (TPC >= 2) v = fmaxf(v, dpp_f<0xB1, 0xF>(0.f, v));
+  if constexpr (TPC >= 4) v = fmaxf(v, dpp_f<0x4E, 0xF>(0.f, v));
+  if constexpr (TPC >= 8) v = fmaxf(v, __shfl_xor(v, 4));
+  return v;
+}
+// largest value, lowest level among equal values
+__device__ __forceinline__ void argmax_merge(float& v, int& l, float ov, int ol) {
+  if (ov > v || (ov == v && ol < l)) {
+    v = ov;
+    l = ol;
+  }
+}
+template <int TPC>
+__device__ __forceinline__ void chip_argmax(float& v, int& l) {
+  if constexpr (TPC >= 2) argmax_merge(v, l, dpp_f<0xB1, 0xF>(0.f, v), dpp_i<0xB1>(l));
+  if constexpr (TPC >= 4) argmax_merge(v, l, dpp_f<0x4E, 0xF>(0.f, v), dpp_i<0x4E>(l));
+  if constexpr (TPC >= 8) argmax_merge(v, l, __shfl_xor(v, 4), __shfl_xor(l, 4));
+}
+
+// Next-pass waveform sample of one chip from its logits zc (levels
+// sub + TPC k, invalid ones -inf): soft at temperature T or hard.
+template <int TPC, int LVMAX>
+__device__ __forceinline__ float2 chip_quantise(const float (&zc)[LVMAX], int sub, int L, bool hard, float T,
+                                                int sq_mode) {
+  if (hard) {
+    float bv = -INFINITY;
+    int bl = 0x7FFFFFFF;
+#pragma unroll
+    for (int k = 0; k < LVMAX; ++k) argmax_merge(bv, bl, zc[k], sub + TPC * k);
+    chip_argmax<TPC>(bv, bl);
+    return level_phasor(bl < L ? bl : 0, L);
+  }
+  float zm = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < LVMAX; ++k) zm = fmaxf(zm, zc[k]);
+  zm = chip_max<TPC>(zm);
+  const float invT = 1.0f / T;
+  float se = 0.f, sy = 0.f, sc = 0.f, ss = 0.f;
+#pragma unroll
+  for (int k = 0; k < LVMAX; ++k) {
+    const int l = sub + TPC * k;
+    const float e = l < L ? expf((zc[k] - zm) * invT) : 0.f;
+    se += e;
+    if (sq_mode == SQNGD_SQ_PHASE_MEAN) {
+      sy += (float)l * e;
+    } else if (l < L) {
+      const float2 u = level_phasor(l, L);
+      sc += e * u.x;
+      ss += e * u.y;
+    }
+  }
+  se = chip_sum<TPC>(se);
+  if (sq_mode == SQNGD_SQ_PHASE_MEAN) {
+    sy = chip_sum<TPC>(sy);
+    float sn, cs;
+    sincospif(2.0f * (sy / se) / (float)L, &sn, &cs);
+    return make_float2(cs, sn);
+  }
+  sc = chip_sum<TPC>(sc);
+  ss = chip_sum<TPC>(ss);
+  return make_float2(sc / se, ss / se);
+}
+
+// Block sums of four products and a flag, in wave order (the same in every
+// thread); sh holds 5 * kStepWaves floats.
+__device__ __forceinline__ void block_sum5(float (&v)[5], float* sh) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) v[i] = wave_sum(v[i]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) sh[i * kStepWaves + (threadIdx.x >> 6)] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    float r = 0.f;
+    for (int w = 0; w < kStepWaves; ++w) r += sh[i * kStepWaves + w];
+    v[i] = r;
+  }
+}
+
+constexpr int kGradChips = 16;                    // chips per k_grad block
+constexpr int kGradThreads = 16 * kGradChips;     // 16 lanes per chip
+constexpr int kGradWaves = kGradThreads / 64;
+constexpr int kGradK = 8;                         // Doppler partials per lane and load round
+
+__global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
+  __shared__ float shw[2 * kGradWaves];
+  __shared__ unsigned long long shk[2 * kGradWaves];
+  __shared__ float4 snrl_sh[16];
+  const int tid = threadIdx.x;
+  const int rb = blockIdx.x / a.grad_chunks, chunk = blockIdx.x % a.grad_chunks;
+  int r, pid;
+  ProbPlan pl;
+  if (a.single) {
+    r = rb;
+    pid = 0;
+    pl = a.one;
+  } else {
+    r = a.rows[rb];
+    pid = a.row_prob[r];
+    pl = a.plans[pid];
+  }
+  const int M = pl.M, N = pl.N, NE = pl.wpr;
+  const int m = r - pl.row0;
+  if (chunk * kGradChips >= N) return;  // whole block beyond the row
+  const int n = chunk * kGradChips + (tid >> 4), sub = tid & 15;
+  const bool on = n < N;
+  const bool first = m == 0 && chunk == 0;  // writes the statistics record and the flag
+  const int64_t wrow = pl.off_w + (int64_t)m * N;
+
+  // ---- loads
+  const UnitStat* us = a.ustat + pl.ws_unit;
+  const float2* up = a.upart + pl.ws_upart + (int64_t)m * NE * N + n;
+  float sj[kGradK];
+  float2 v[kGradK];
+#pragma unroll
+  for (int k = 0; k < kGradK; ++k) {
+    const int j = sub + 16 * k;
+    const bool ok = on && j < NE;
+    sj[k] = ok ? us[m * NE + j].sigma : 0.f;
+    v[k] = ok ? up[(int64_t)j * N] : make_float2(0.f, 0.f);
+  }
+  const float2 pw = on ? a.part_w[wrow + n] : make_float2(0.f, 0.f);
+  if (tid < M) snrl_sh[tid] = a.snrl[pl.row0 + tid];
+  float mx = 0.f, sx = 0.f;
+  unsigned long long ka = 0, kc = 0;
+  for (int i = tid; i < pl.units; i += kGradThreads) {
+    const UnitStat u = us[i];
+    if (first) {
+      ka = umax64(ka, u.key_auto);
+      kc = umax64(kc, u.key_cross);
+    }
+    if (u.sigma > mx) {
+      sx = (mx > 0.f ? sx * pow_p(mx / u.sigma, pl) : 0.f) + u.S;
+      mx = u.sigma;
+    } else if (u.sigma > 0.f) {
+      sx += u.S * pow_p(u.sigma / mx, pl);
+    }
+  }
+
+  // ---- L_p, the SNRL penalty and the loss (eq. 37-42)
+  {
+    const float wm = wave_max(mx);
+    float s = mx > 0.f ? sx * pow_p(mx / wm, pl) : 0.f;
+    s = wave_sum(s);
+    if ((tid & 63) == 0) {
+      shw[tid >> 6] = wm;
+      shw[kGradWaves + (tid >> 6)] = s;
+    }
+    if (first) {
+      ka = slot_max_key<64>(ka);
+      kc = slot_max_key<64>(kc);
+      if ((tid & 63) == 0) {
+        shk[tid >> 6] = ka;
+        shk[kGradWaves + (tid >> 6)] = kc;
+      }
+    }
+  }
+  __syncthreads();
+  float smax = 0.f;
+  for (int w = 0; w < kGradWaves; ++w) smax = fmaxf(smax, shw[w]);
+  float acc = 0.f;
+  for (int w = 0; w < kGradWaves; ++w)
+    if (shw[w] > 0.f) acc += shw[kGradWaves + w] * pow_p(shw[w] / smax, pl);
+  const float lp_raw = smax > 0.f ? smax * exp2f(log2f(acc) / pl.p) : 0.f;
+  float l_snrl = 0.f;
+  for (int k = 0; k < M; ++k) {
+    const float4 c4 = snrl_sh[k];
+    const float pk = sqrtf(c4.x * c4.x + c4.y * c4.y) / (float)N;
+    l_snrl += (pk - pl.p_tar) * (pk - pl.p_tar) / (float)M;
+  }
+  const float loss = pl.w_psl * lp_raw * pl.inv_NP + pl.w_snrl * l_snrl;
+  const bool bad = !isfinite(loss);
+  if (first && tid == 0) {
+    for (int w = 0; w < kGradWaves; ++w) {
+      ka = umax64(ka, shk[w]);
+      kc = umax64(kc, shk[kGradWaves + w]);
+    }
+    if (a.stats != nullptr) stats_record(a.stats + pid, pl, a.orient, loss, lp_raw, l_snrl, ka, kc, snrl_sh, bad);
+    a.pflag[pid] = bad ? 1 : 0;
+  }
+
+  // ---- gradient of the chip
+  float2 g = make_float2(0.f, 0.f);
+  if (lp_raw > 0.f) {
+    const float cfac = pl.w_psl / ((float)N * (float)pl.P);
+    const float inv_lp = 1.0f / lp_raw;
+#pragma unroll
+    for (int k = 0; k < kGradK; ++k) {
+      const float f = sj[k] > 0.f ? cfac * pow_pm1(sj[k] * inv_lp, pl) : 0.f;
+      g.x += f * v[k].x;
+      g.y += f * v[k].y;
+    }
+    for (int j0 = 16 * kGradK; j0 < NE; j0 += 16 * kGradK) {
+#pragma unroll
+      for (int k = 0; k < kGradK; ++k) {
+        const int j = j0 + sub + 16 * k;
+        const bool ok = on && j < NE;
+        sj[k] = ok ? us[m * NE + j].sigma : 0.f;
+        v[k] = ok ? up[(int64_t)j * N] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int k = 0; k < kGradK; ++k) {
+        const float f = sj[k] > 0.f ? cfac * pow_pm1(sj[k] * inv_lp, pl) : 0.f;
+        g.x += f * v[k].x;
+        g.y += f * v[k].y;
+      }
+    }
+  }
+  g.x = slot_reduce<16>(g.x, 0.0f, OpAdd());
+  g.y = slot_reduce<16>(g.y, 0.0f, OpAdd());
+  const float4 cm = snrl_sh[m];
+  const float magm = sqrtf(cm.x * cm.x + cm.y * cm.y);
+  if (magm > 0.f) {
+    const float2 gS = cscale(make_float2(cm.x, cm.y),
+                             pl.w_snrl * (2.0f / (float)M) * (magm / (float)N - pl.p_tar) / ((float)N * magm));
+    g = cadd(g, cmul(gS, pw));
+  }
+  if (on && sub == 0) a.gbuf[wrow + n] = g;
+}
+
+template <int P, int MODE, int LVMAX>
+__global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
+  constexpr int TPC = P >= 256 ? 2 * kStepThreads / P : 8;  // lanes per chip: N <= P/2 chips fill the block
+  constexpr bool kA = MODE == FIN_STEP_A;
+  using G = Geom<P>;
+  __shared__ float shr[2 * 5 * kStepWaves];
+  __shared__ float2 rowbuf[P];
+  __shared__ float2 fbuf[G::LDS];
+  const int tid = threadIdx.x;
+  int r, pid;
+  ProbPlan pl;
+  if (a.single) {
+    r = blockIdx.x;
+    pid = 0;
+    pl = a.one;
+  } else {
+    r = a.rows[blockIdx.x];
+    pid = a.row_prob[r];
+    pl = a.plans[pid];
+  }
+  const int M = pl.M, N = pl.N, L = pl.L;
+  const int m = r - pl.row0;
+  const int n = tid / TPC, sub = tid % TPC;
+  const bool on = n < N, lead = on && sub == 0;
+  const int64_t wrow = pl.off_w + (int64_t)m * N;
+  const int64_t crow = (int64_t)m * N;
+  const int next = a.next;
+  const bool want_spec = next == NEXT_B_FULL || next == NEXT_A_FULL;
+  const bool want_soft = next == NEXT_B_FULL || next == NEXT_B_SOFT;
+  const bool need_z = !kA || want_soft;
+  const bool sgd = (a.opt.flags & SQNGD_OPT_SGD) != 0;
+  const float2 zero2 = make_float2(0.f, 0.f);
+
+  // ---- loads
+  const int tstep = *a.counter;
+  const bool bad = a.pflag[pid] != 0;
+  const float2 g = on ? a.gbuf[wrow + n] : zero2;
+  float2 hv = zero2, sv = zero2, xv = zero2;
+  float4 mvh = make_float4(0.f, 0.f, 0.f, 0.f);
+  float* mh = a.adam + pl.off_state + 2 * (int64_t)M * N * L + 2 * crow;
+  float* vh = mh + 2 * (int64_t)M * N;
+  if (lead) {
+    hv = a.h[wrow + n];
+    if (kA && !sgd) {
+      const float2 m2 = *(const float2*)(mh + 2 * n), v2 = *(const float2*)(vh + 2 * n);
+      mvh = make_float4(m2.x, m2.y, v2.x, v2.y);
+    }
+    if (kA && next == NEXT_A_SNRL) xv = a.wpart[wrow + n];
+  }
+  if (!kA && on) sv = a.self_w[wrow + n];
+  const int64_t zrow = pl.off_z + (crow + n) * L;
+  float* amz = a.adam + pl.off_state + (crow + n) * L;
+  float* avz = amz + (int64_t)M * N * L;
+  float zl[LVMAX], mz[LVMAX], vz[LVMAX];
+#pragma unroll
+  for (int k = 0; k < LVMAX; ++k) {
+    const int l = sub + TPC * k;
+    const bool ok = on && l < L && need_z;
+    zl[k] = ok ? a.z[zrow + l] : -INFINITY;
+    mz[k] = ok && !kA && !sgd ? amz[l] : 0.f;
+    vz[k] = ok && !kA && !sgd ? avz[l] : 0.f;
+  }
+  if (want_spec)
+    for (int i = N + tid; i < P; i += kStepThreads) rowbuf[i] = zero2;
+  const float flag = lead && !(isfinite(g.x) && isfinite(g.y)) ? 1.0f : 0.0f;
+  const float b1 = a.opt.beta1, b2 = a.opt.beta2;
+
+  // ---- the update candidate and the next pass's waveform sample
+  float2 hu = hv;   // step A: updated, unprojected filter chip (lead lanes)
+  float2 nx = zero2;  // next pass: soft self sample or hard partner sample
+  float4 mvn = mvh;
+  if constexpr (kA) {
+    if (lead && !bad) {
+      if (sgd) {
+        hu.x -= a.opt.lr_h * g.x;
+        hu.y -= a.opt.lr_h * g.y;
+      } else {
+        const int k = tstep * a.opt.n_h + a.inner + 1;
+        const float bc1 = bias_corr(b1, k), bc2 = bias_corr(b2, k);
+        mvn.x = b1 * mvh.x + (1.0f - b1) * g.x;
+        mvn.y = b1 * mvh.y + (1.0f - b1) * g.y;
+        mvn.z = b2 * mvh.z + (1.0f - b2) * g.x * g.x;
+        mvn.w = b2 * mvh.w + (1.0f - b2) * g.y * g.y;
+        hu.x -= a.opt.lr_h * (mvn.x / bc1) / (sqrtf(mvn.z / bc2) + a.opt.eps);
+        hu.y -= a.opt.lr_h * (mvn.y / bc1) / (sqrtf(mvn.w / bc2) + a.opt.eps);
+      }
+    }
+    if (next == NEXT_B_FULL) nx = chip_quantise<TPC, LVMAX>(zl, sub, L, false, temperature_at(a.opt, tstep), pl.sq_mode);
+  } else {
+    // dL/dz through the soft quantiser at the temperature of this step, then Adam
+    const float Tc = temperature_at(a.opt, tstep);
+    const float invT = 1.0f / Tc;
+    float zm = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < LVMAX; ++k) zm = fmaxf(zm, zl[k]);
+    zm = chip_max<TPC>(zm);
+    float e[LVMAX];
+    float se = 0.f, sy = 0.f;
+#pragma unroll
+    for (int k = 0; k < LVMAX; ++k) {
+      const int l = sub + TPC * k;
+      e[k] = on && l < L ? expf((zl[k] - zm) * invT) : 0.f;
+      se += e[k];
+      sy += (float)l * e[k];
+    }
+    se = chip_sum<TPC>(se);
+    sy = chip_sum<TPC>(sy);
+    const float yb = sy / se;
+    const int kz = tstep * a.opt.n_x + a.inner + 1;
+    const float bc1 = sgd ? 1.0f : bias_corr(b1, kz), bc2 = sgd ? 1.0f : bias_corr(b2, kz);
+    const float dphi = (g.y * sv.x - g.x * sv.y) * (2.0f * 3.14159265358979f / (float)L) * invT;
+    const bool upd = !bad;
+#pragma unroll
+    for (int k = 0; k < LVMAX; ++k) {
+      const int l = sub + TPC * k;
+      if (!(on && l < L) || !upd) continue;
+      const float pi = e[k] / se;
+      float gv;
+      if (pl.sq_mode == SQNGD_SQ_PHASE_MEAN) {
+        gv = dphi * pi * ((float)l - yb);
+      } else {
+        const float2 ul = level_phasor(l, L);
+        gv = pi * invT * (g.x * (ul.x - sv.x) + g.y * (ul.y - sv.y));
+      }
+      if (sgd) {
+        e[k] = zl[k] - a.opt.lr_z * gv;
+      } else {
+        mz[k] = b1 * mz[k] + (1.0f - b1) * gv;
+        vz[k] = b2 * vz[k] + (1.0f - b2) * gv * gv;
+        e[k] = zl[k] - a.opt.lr_z * (mz[k] / bc1) / (sqrtf(vz[k] / bc2) + a.opt.eps);
+      }
+    }
+    // e[] now holds the updated logits of the valid levels
+#pragma unroll
+    for (int k = 0; k < LVMAX; ++k) {
+      const int l = sub + TPC * k;
+      if (!(on && l < L)) e[k] = -INFINITY;
+      else if (!upd) e[k] = zl[k];
+    }
+    if (next == NEXT_A_FULL || next == NEXT_B_SOFT)
+      nx = chip_quantise<TPC, LVMAX>(e, sub, L, next == NEXT_A_FULL,
+                                     temperature_at(a.opt, tstep + (next == NEXT_B_SOFT ? a.next_t_offset : 0)),
+                                     pl.sq_mode);
+    // keep the updated logits in zl for the writes after the barrier; the
+    // unchanged ones are reloaded if the step is skipped
+#pragma unroll
+    for (int k = 0; k < LVMAX; ++k) zl[k] = e[k];
+  }
+
+  // ---- energy and mainlobe products of the next pass (eq. 10, 32, 38),
+  // summed over the row together with the count of non-finite gradient
+  // chips: slots 0-1 Re, Im of sum conj(partner) self; 2 |self|^2;
+  // 3 |partner|^2; 4 the count. In step A the filter chips are the
+  // unprojected hcur, whose energy is slot 2 or 3 (slot 3 without a next pass).
+  auto products = [&](float2 hcur, float2 nxt, float* sh, float4& prod, float& nbad) {
+    float q[5] = {0.f, 0.f, 0.f, 0.f, flag};
+    float2 self, part;
+    if (kA) {
+      self = next == NEXT_B_FULL ? nxt : hcur;
+      part = next == NEXT_B_FULL ? hcur : (next == NEXT_A_SNRL ? xv : hcur);
+    } else {
+      self = next == NEXT_A_FULL ? hv : nxt;
+      part = next == NEXT_A_FULL ? nxt : hv;
+    }
+    if (lead) {
+      q[0] = part.x * self.x + part.y * self.y;
+      q[1] = part.x * self.y - part.y * self.x;
+      q[2] = self.x * self.x + self.y * self.y;
+      q[3] = part.x * part.x + part.y * part.y;
+    }
+    block_sum5(q, sh);
+    prod = make_float4(q[0], q[1], q[2], q[3]);
+    nbad = q[4];
+  };
+  if (want_spec && lead) rowbuf[n] = kA ? hu : nx;
+  float4 prod;
+  float nbad;
+  products(hu, nx, shr, prod, nbad);
+  const bool skip = bad || nbad > 0.f;
+  float cs = 1.0f;  // scale of the prepared spectrum
+
+  // ---- writes
+  if (!skip) {
+    if constexpr (kA) {
+      const float e2 = next == NEXT_A_SNRL ? prod.z : prod.w;
+      const float c = sqrtf((float)N / e2);
+      if (lead) {
+        if (!sgd) {
+          *(float2*)(mh + 2 * n) = make_float2(mvn.x, mvn.y);
+          *(float2*)(vh + 2 * n) = make_float2(mvn.z, mvn.w);
+        }
+        a.h[wrow + n] = cscale(hu, c);
+      }
+      if (next == NEXT_B_FULL) prod = make_float4(c * prod.x, c * prod.y, prod.z, c * c * prod.w);
+      if (next == NEXT_A_SNRL) prod = make_float4(c * prod.x, c * prod.y, c * c * prod.z, prod.w);
+      cs = c;
+    } else {
+#pragma unroll
+      for (int k = 0; k < LVMAX; ++k) {
+        const int l = sub + TPC * k;
+        if (on && l < L) {
+          a.z[zrow + l] = zl[k];
+          if (!sgd) {
+            amz[l] = mz[k];
+            avz[l] = vz[k];
+          }
+        }
+      }
+    }
+  } else {
+    // no update: the next pass is prepared from the unchanged state
+    if constexpr (kA) {
+      hu = hv;
+    } else {
+#pragma unroll
+      for (int k = 0; k < LVMAX; ++k) {
+        const int l = sub + TPC * k;
+        zl[k] = on && l < L ? a.z[zrow + l] : -INFINITY;
+      }
+      if (next == NEXT_A_FULL || next == NEXT_B_SOFT)
+        nx = chip_quantise<TPC, LVMAX>(zl, sub, L, next == NEXT_A_FULL,
+                                       temperature_at(a.opt, tstep + (next == NEXT_B_SOFT ? a.next_t_offset : 0)),
+                                       pl.sq_mode);
+    }
+    if (want_spec && lead) rowbuf[n] = kA ? hu : nx;
+    products(hu, nx, shr + 5 * kStepWaves, prod, nbad);
+  }
+  if (lead) {
+    if (next == NEXT_B_FULL || next == NEXT_B_SOFT) a.wself[wrow + n] = nx;
+    if (next == NEXT_A_FULL) a.wpart[wrow + n] = nx;
+  }
+  if (tid == 0 && next != NEXT_NONE) a.snrl_next[r] = prod;
+
+  // ---- spectrum of the next pass's partner row (wave 0)
+  if (want_spec && tid < 64) {
+    constexpr int E = G::E, TF = G::TF;
+    const int slot = tid / TF, t = tid % TF;
+    float2 X[E];
+    static_for<E>([&](auto ec) {
+      constexpr int e = decltype(ec)::value;
+      X[e] = slot == 0 ? rowbuf[t + TF * e] : zero2;
+    });
+    WaveTwiddles<P> W;
+    W.init(t);
+    fft_forward<P>(X, fbuf + slot * P, t, W);
+    if (slot == 0) {
+      float2* out = a.spec + pl.ws_spec + (int64_t)m * P;
+      static_for<E>([&](auto ec) {
+        constexpr int e = decltype(ec)::value;
+        out[e * TF + t] = cscale(X[e], cs);
+      });
+    }
+  }
 
   if (a.count_step) {
     __syncthreads();
@@ -1106,6 +1653,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   __shared__ float u_sig[WV], u_S[WV];
   __shared__ unsigned long long u_ka[WV], u_kc[WV];
   const int wv = threadIdx.x >> 6, t = threadIdx.x & 63;
+  if (a.bump != nullptr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.bump, 1);
   float2* buf = lds + wv * P;
   int base = 0;
   ProbPlan pl;

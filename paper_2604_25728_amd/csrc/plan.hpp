@@ -58,6 +58,8 @@ struct WsHeader {
   int64_t row_prob;       // byte offset of int32 [nrows]: problem of each row
   int64_t spec, wself, wpart, ustat, upart, counters;  // region byte offsets
   int64_t snrl;  // float4 [2][rows]: mainlobe products, double-buffered by pass parity
+  int64_t gbuf;   // float2 [sum M N]: gradient rows of an optimiser step (packed waveform layout)
+  int64_t pflag;  // int32 [nprob]: non-finite loss of the step's evaluation
   int64_t total;
 };
 

@@ -458,7 +458,10 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
       const int lv = pl.group_step[g];
       // gradient rows: N <= P/2 chips per row in blocks of kGradChips
       a.grad_chunks = (1 << (g + kMinLogP)) / (2 * kGradChips);
-      hipLaunchKernelGGL(k_grad, dim3(pl.hdr.group_nrows[g] * a.grad_chunks), dim3(kGradThreads), 0, s, a);
+      a.grad_nprob = pl.hdr.group_n[g];
+      a.gprob = (const int32_t*)(w.base + pl.hdr.group_prob[g]);
+      hipLaunchKernelGGL(k_grad, dim3(pl.hdr.group_nrows[g] * a.grad_chunks + a.grad_nprob), dim3(kGradThreads), 0,
+                         s, a);
       switch (g) {
         case 0: launch_step_p<128>(a, lv, grid, s); break;
         case 1: launch_step_p<256>(a, lv, grid, s); break;

@@ -39,6 +39,7 @@ __device__ __forceinline__ float2 phasor(int n, float nu, float invN) {
   return make_float2(c, s);
 }
 
+
 __device__ __forceinline__ unsigned long long make_key(float q, uint32_t cell) {
   return ((unsigned long long)__float_as_uint(q) << 32) | (unsigned long long)(0xFFFFFFFFu - cell);
 }
@@ -91,6 +92,73 @@ __device__ __forceinline__ float temperature_at(const sqngd_opt& o, int t) {
 
 // 1 - b^k for the Adam bias corrections (0 < b < 1, k >= 1).
 __device__ __forceinline__ float bias_corr(float b, int k) { return 1.0f - exp2f((float)k * log2f(b)); }
+
+// phasor(n, nu, invN) for n = t + TF e, e < EH: one sincospi for n = t, one
+// for the step TF, then products (the step's rounding grows by one ulp per e).
+template <int EH, int TF>
+__device__ __forceinline__ void phasor_row(int t, float nu, float invN, float2 (&ph)[EH]) {
+  ph[0] = phasor(t, nu, invN);
+  if constexpr (EH > 1) {
+    const float2 st = phasor(TF, nu, invN);
+    static_for<EH - 1>([&](auto ec) {
+      constexpr int e = decltype(ec)::value + 1;
+      ph[e] = cmul(ph[e - 1], st);
+    });
+  }
+}
+
+// In-ROI scan of one AF row held as R[e] = P A(tau') at r-index k = t + TF e
+// (ROI cells: tau' = -k for k < N, P - k for k > P - N, inside [wlo, whi],
+// without tau' = 0 on an auto pair): the valid-cell mask and the lane's
+// largest |r|^2 with its lowest index.
+template <int P, int TF, int E>
+__device__ __forceinline__ void roi_scan(const float2 (&R)[E], int t, int N, int wlo, int whi, bool auto_pair,
+                                         uint32_t& vmask, float& qmax, int& kbest) {
+  vmask = 0;
+  qmax = 0.f;
+  kbest = 0;
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    const int k = t + TF * e;
+    const bool lo = k <= N - 1, hi = k >= P - N + 1;
+    const int tp = lo ? -k : P - k;
+    const bool valid = (lo || hi) && tp >= wlo && tp <= whi && !(auto_pair && tp == 0);
+    const float q = valid ? R[e].x * R[e].x + R[e].y * R[e].y : 0.f;
+    const bool better = q > qmax;
+    qmax = better ? q : qmax;
+    kbest = better ? k : kbest;
+    vmask |= valid ? (1u << e) : 0u;
+  });
+}
+
+// S += sum over valid cells of x^(p/2), x = |r|^2 / sigma^2, and the scaled
+// adjoint r <- x^(p/2 - 1) r / sigma on valid cells, 0 elsewhere.
+template <int PHLOG, int E>
+__device__ __forceinline__ void roi_scale(float2 (&R)[E], uint32_t vmask, float inv_s, float phm1, float& S) {
+  const float inv_s2 = inv_s * inv_s;
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    const bool valid = (vmask >> e) & 1u;
+    const float x = valid ? (R[e].x * R[e].x + R[e].y * R[e].y) * inv_s2 : 0.f;
+    float ym1, y;
+    pow_ph<PHLOG>(x, phm1, ym1, y);
+    S += valid ? y : 0.f;
+    const float sc = valid ? ym1 * inv_s : 0.f;
+    R[e] = cscale(R[e], sc);
+  });
+}
+
+// AF cells of one row into the cube [w][g][f][tau + N - 1] (scaled by 1/P).
+template <int P, int TF, int E>
+__device__ __forceinline__ void cube_store(const float2 (&R)[E], int t, int N, float2* row) {
+  const float invP = 1.0f / (float)P;
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    const int k = t + TF * e;
+    if (k <= N - 1) row[N - 1 - k] = cscale(R[e], invP);
+    else if (k >= P - N + 1) row[P - k + N - 1] = cscale(R[e], invP);
+  });
+}
 
 // Soft-quantised chip from its L logits (softmax at temperature T).
 __device__ __forceinline__ float2 soft_chip(const float* zc, int L, float T, int mode) {
@@ -331,18 +399,21 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
   const float2* spec = a.spec + pl.ws_spec;
   const float2* sw = a.self_w + pl.off_w + (int64_t)w * N;
   float2* cube = a.cube ? a.cube + pl.off_cube : nullptr;
-  const float invP = 1.0f / (float)P;
   const int T2 = 2 * N - 1;
   float2 X[E], U[E], R[E], SG[kKeepSG ? E : 1];
-  static_for<E>([&](auto ec) {
-    constexpr int e = decltype(ec)::value;
-    R[e] = make_float2(0.f, 0.f);
-    U[e] = make_float2(0.f, 0.f);
-    if constexpr (e < EH) {
-      const int n = t + TF * e;
-      if (n < N) R[e] = cmul(sw[n], phasor(n, nu, invN));
-    }
-  });
+  {
+    float2 ph[EH];
+    phasor_row<EH, TF>(t, nu, invN, ph);
+    static_for<E>([&](auto ec) {
+      constexpr int e = decltype(ec)::value;
+      R[e] = make_float2(0.f, 0.f);
+      U[e] = make_float2(0.f, 0.f);
+      if constexpr (e < EH) {
+        const int n = t + TF * e;
+        if (n < N) R[e] = cmul(sw[n], ph[e]);
+      }
+    });
+  }
   float sigma = 0.f, S = 0.f;
   unsigned long long kauto = 0, kcross = 0;  // per lane; reduced once per unit
   int g = 0;
@@ -386,33 +457,11 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
     }
     // OP_PAIR: R[e] = P * A(tau') at r-index k = t + TF e; ROI cells hold
     // tau' = -k (k < N) or P - k (k > P - N).
-    uint32_t vmask = 0;
-    float qmax = 0.f;
-    int kbest = 0;
-    static_for<E>([&](auto ec) {
-      constexpr int e = decltype(ec)::value;
-      const int k = t + TF * e;
-      int tp = 0;
-      bool inr = false;
-      if (k <= N - 1) {
-        tp = -k;
-        inr = true;
-      } else if (k >= P - N + 1) {
-        tp = P - k;
-        inr = true;
-      }
-      const bool valid = inr && tp >= wlo && tp <= whi && !(g == w && tp == 0);
-      if (valid) {
-        vmask |= 1u << e;
-        const float q = R[e].x * R[e].x + R[e].y * R[e].y;
-        if (q > qmax) {
-          qmax = q;
-          kbest = k;
-        }
-      }
-      if (cube != nullptr && active && inr)
-        cube[((int64_t)(w * M + g) * F + f) * T2 + tp + N - 1] = cscale(R[e], invP);
-    });
+    uint32_t vmask;
+    float qmax;
+    int kbest;
+    roi_scan<P, TF, E>(R, t, N, wlo, whi, g == w, vmask, qmax, kbest);
+    if (cube != nullptr && active) cube_store<P, TF, E>(R, t, N, cube + ((int64_t)(w * M + g) * F + f) * T2);
     // this lane's largest cell of the pair (lowest index among equal values)
     const unsigned long long key = vmask ? make_key(qmax, (uint32_t)(((int64_t)u * M + g) * P + kbest)) : 0ull;
     if (g == w) kauto = umax64(kauto, key);
@@ -428,21 +477,8 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
       static_for<E>([&](auto ec) { U[decltype(ec)::value] = cscale(U[decltype(ec)::value], cpm1); });
       sigma = mu;
     }
-    const float inv_s = sigma > 0.f ? 1.0f / sigma : 0.f;
-    const float inv_s2 = inv_s * inv_s;
     // a/sigma = x^(1/2), x = |r|^2 / sigma^2:  S += x^(p/2);  G~ = x^(p/2 - 1) r / sigma
-    static_for<E>([&](auto ec) {
-      constexpr int e = decltype(ec)::value;
-      if (vmask & (1u << e)) {
-        const float x = (R[e].x * R[e].x + R[e].y * R[e].y) * inv_s2;
-        float ym1, y;
-        pow_ph<PHLOG>(x, phm1, ym1, y);
-        S += y;
-        R[e] = cscale(R[e], ym1 * inv_s);
-      } else {
-        R[e] = make_float2(0.f, 0.f);
-      }
-    });
+    roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? 1.0f / sigma : 0.f, phm1, S);
     if (grad) {
       op = OP_ADJ;
     } else if (++g < M) {
@@ -464,11 +500,13 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
     u_kc[uslot] = active ? kcross : 0ull;
   }
   if (grad) {
+    float2 ph[EH];
+    phasor_row<EH, TF>(t, nu, invN, ph);
     wave_lds_sync();
     static_for<EH>([&](auto ec) {
       constexpr int e = decltype(ec)::value;
       const int n = t + TF * e;
-      if (n < N) buf[n] = active ? cmulc(R[e], phasor(n, nu, invN)) : make_float2(0.f, 0.f);
+      if (n < N) buf[n] = active ? cmulc(R[e], ph[e]) : make_float2(0.f, 0.f);
     });
   }
   __syncthreads();
@@ -524,18 +562,25 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
 // ------------------------------------------------------------------ k_final
 
 // x^p and x^(p-1) for 0 <= x <= 1: exact repeated squaring when p/2 is a
-// power of two (ph_log >= 0), powf otherwise.
+// power of two (ph_log >= 0), exp2 / log2 otherwise.
 __device__ __forceinline__ float pow_p(float x, const ProbPlan& pl) {
   if (pl.ph_log >= 0) {
     float y = x * x;
     for (int i = 0; i < pl.ph_log; ++i) y *= y;
     return y;
   }
-  return powf(x, pl.p);
+  return x > 0.f ? exp2f(pl.p * log2f(x)) : 0.f;
 }
 __device__ __forceinline__ float pow_pm1(float x, const ProbPlan& pl) {
-  if (pl.ph_log >= 0) return x > 0.f ? pow_p(x, pl) / x : (pl.ph_log == 0 ? 1.0f : 0.0f);
-  return powf(x, pl.p - 1.0f);
+  if (pl.ph_log >= 0) {
+    float a = 1.0f, s = x * x;  // a = x^(p-2) after the loop
+    for (int i = 0; i < pl.ph_log; ++i) {
+      a *= s;
+      s *= s;
+    }
+    return a * x;
+  }
+  return x > 0.f ? exp2f((pl.p - 1.0f) * log2f(x)) : 0.f;
 }
 
 enum FinMode : int32_t {
@@ -588,6 +633,8 @@ struct FinArgs {
   float2* gbuf;         // gradient rows (k_grad -> k_step)
   int32_t* pflag;       // per problem: the loss is not finite (k_grad -> k_step)
   int32_t grad_chunks;  // k_grad blocks per row
+  int32_t grad_nprob;   // problems of the launch (one statistics block each)
+  const int32_t* gprob; // their ids
   int32_t single;  // one problem: its plan is `one`, rows are the block indices
   ProbPlan one;
 };
@@ -1230,29 +1277,70 @@ constexpr int kGradThreads = 16 * kGradChips;     // 16 lanes per chip
 constexpr int kGradWaves = kGradThreads / 64;
 constexpr int kGradK = 8;                         // Doppler partials per lane and load round
 
+// Per problem of the launch, after the row blocks: one statistics block
+// (L_p, maxima, loss, the record and the non-finite flag).
+__device__ __forceinline__ void grad_units(const ProbPlan& pl, const UnitStat* us, bool keys, float& mx, float& sx,
+                                           unsigned long long& ka, unsigned long long& kc) {
+  // four units per thread and round, loads first
+  for (int i0 = threadIdx.x; i0 < pl.units; i0 += 4 * kGradThreads) {
+    UnitStat u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + q * kGradThreads;
+      if (i < pl.units) {
+        u[q] = us[i];
+      } else {
+        u[q].sigma = 0.f;
+        u[q].S = 0.f;
+        u[q].key_auto = u[q].key_cross = 0ull;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (keys) {
+        ka = umax64(ka, u[q].key_auto);
+        kc = umax64(kc, u[q].key_cross);
+      }
+      if (u[q].sigma > mx) {
+        sx = (mx > 0.f ? sx * pow_p(mx / u[q].sigma, pl) : 0.f) + u[q].S;
+        mx = u[q].sigma;
+      } else if (u[q].sigma > 0.f) {
+        sx += u[q].S * pow_p(u[q].sigma / mx, pl);
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
   __shared__ float shw[2 * kGradWaves];
   __shared__ unsigned long long shk[2 * kGradWaves];
   __shared__ float4 snrl_sh[16];
   const int tid = threadIdx.x;
-  const int rb = blockIdx.x / a.grad_chunks, chunk = blockIdx.x % a.grad_chunks;
-  int r, pid;
+  const int nrb = gridDim.x - a.grad_nprob;  // row blocks
+  const bool stat_block = (int)blockIdx.x >= nrb;
+  int r = 0, pid, chunk = 0;
   ProbPlan pl;
-  if (a.single) {
-    r = rb;
-    pid = 0;
-    pl = a.one;
+  if (stat_block) {
+    pid = a.single ? 0 : a.gprob[blockIdx.x - nrb];
+    pl = a.single ? a.one : a.plans[pid];
   } else {
-    r = a.rows[rb];
-    pid = a.row_prob[r];
-    pl = a.plans[pid];
+    const int rb = blockIdx.x / a.grad_chunks;
+    chunk = blockIdx.x - rb * a.grad_chunks;
+    if (a.single) {
+      r = rb;
+      pid = 0;
+      pl = a.one;
+    } else {
+      r = a.rows[rb];
+      pid = a.row_prob[r];
+      pl = a.plans[pid];
+    }
   }
   const int M = pl.M, N = pl.N, NE = pl.wpr;
-  const int m = r - pl.row0;
-  if (chunk * kGradChips >= N) return;  // whole block beyond the row
+  const int m = stat_block ? 0 : r - pl.row0;
+  if (!stat_block && chunk * kGradChips >= N) return;  // whole block beyond the row
   const int n = chunk * kGradChips + (tid >> 4), sub = tid & 15;
-  const bool on = n < N;
-  const bool first = m == 0 && chunk == 0;  // writes the statistics record and the flag
+  const bool on = !stat_block && n < N;
   const int64_t wrow = pl.off_w + (int64_t)m * N;
 
   // ---- loads
@@ -1271,19 +1359,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
   if (tid < M) snrl_sh[tid] = a.snrl[pl.row0 + tid];
   float mx = 0.f, sx = 0.f;
   unsigned long long ka = 0, kc = 0;
-  for (int i = tid; i < pl.units; i += kGradThreads) {
-    const UnitStat u = us[i];
-    if (first) {
-      ka = umax64(ka, u.key_auto);
-      kc = umax64(kc, u.key_cross);
-    }
-    if (u.sigma > mx) {
-      sx = (mx > 0.f ? sx * pow_p(mx / u.sigma, pl) : 0.f) + u.S;
-      mx = u.sigma;
-    } else if (u.sigma > 0.f) {
-      sx += u.S * pow_p(u.sigma / mx, pl);
-    }
-  }
+  grad_units(pl, us, stat_block, mx, sx, ka, kc);
 
   // ---- L_p, the SNRL penalty and the loss (eq. 37-42)
   {
@@ -1294,7 +1370,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
       shw[tid >> 6] = wm;
       shw[kGradWaves + (tid >> 6)] = s;
     }
-    if (first) {
+    if (stat_block) {
       ka = slot_max_key<64>(ka);
       kc = slot_max_key<64>(kc);
       if ((tid & 63) == 0) {
@@ -1310,21 +1386,24 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
   for (int w = 0; w < kGradWaves; ++w)
     if (shw[w] > 0.f) acc += shw[kGradWaves + w] * pow_p(shw[w] / smax, pl);
   const float lp_raw = smax > 0.f ? smax * exp2f(log2f(acc) / pl.p) : 0.f;
-  float l_snrl = 0.f;
-  for (int k = 0; k < M; ++k) {
-    const float4 c4 = snrl_sh[k];
-    const float pk = sqrtf(c4.x * c4.x + c4.y * c4.y) / (float)N;
-    l_snrl += (pk - pl.p_tar) * (pk - pl.p_tar) / (float)M;
-  }
-  const float loss = pl.w_psl * lp_raw * pl.inv_NP + pl.w_snrl * l_snrl;
-  const bool bad = !isfinite(loss);
-  if (first && tid == 0) {
-    for (int w = 0; w < kGradWaves; ++w) {
-      ka = umax64(ka, shk[w]);
-      kc = umax64(kc, shk[kGradWaves + w]);
+  if (stat_block) {
+    if (tid == 0) {
+      float l_snrl = 0.f;
+      for (int k = 0; k < M; ++k) {
+        const float4 c4 = snrl_sh[k];
+        const float pk = sqrtf(c4.x * c4.x + c4.y * c4.y) / (float)N;
+        l_snrl += (pk - pl.p_tar) * (pk - pl.p_tar) / (float)M;
+      }
+      const float loss = pl.w_psl * lp_raw * pl.inv_NP + pl.w_snrl * l_snrl;
+      const bool bad = !isfinite(loss);
+      for (int w = 0; w < kGradWaves; ++w) {
+        ka = umax64(ka, shk[w]);
+        kc = umax64(kc, shk[kGradWaves + w]);
+      }
+      if (a.stats != nullptr) stats_record(a.stats + pid, pl, a.orient, loss, lp_raw, l_snrl, ka, kc, snrl_sh, bad);
+      a.pflag[pid] = bad ? 1 : 0;
     }
-    if (a.stats != nullptr) stats_record(a.stats + pid, pl, a.orient, loss, lp_raw, l_snrl, ka, kc, snrl_sh, bad);
-    a.pflag[pid] = bad ? 1 : 0;
+    return;
   }
 
   // ---- gradient of the chip
@@ -1334,7 +1413,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
     const float inv_lp = 1.0f / lp_raw;
 #pragma unroll
     for (int k = 0; k < kGradK; ++k) {
-      const float f = sj[k] > 0.f ? cfac * pow_pm1(sj[k] * inv_lp, pl) : 0.f;
+      const float f = cfac * pow_pm1(sj[k] * inv_lp, pl);
       g.x += f * v[k].x;
       g.y += f * v[k].y;
     }
@@ -1348,7 +1427,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
       }
 #pragma unroll
       for (int k = 0; k < kGradK; ++k) {
-        const float f = sj[k] > 0.f ? cfac * pow_pm1(sj[k] * inv_lp, pl) : 0.f;
+        const float f = cfac * pow_pm1(sj[k] * inv_lp, pl);
         g.x += f * v[k].x;
         g.y += f * v[k].y;
       }
@@ -1697,10 +1776,14 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   });
   WaveTwiddles<P> W;
   W.init(t);
-  static_for<EH>([&](auto ec) {
-    constexpr int e = decltype(ec)::value;
-    X[e] = cmul(X[e], phasor(t + 64 * e, nu, invN));
-  });
+  {
+    float2 ph[EH];
+    phasor_row<EH, 64>(t, nu, invN, ph);
+    static_for<EH>([&](auto ec) {
+      constexpr int e = decltype(ec)::value;
+      X[e] = cmul(X[e], ph[e]);
+    });
+  }
   fft_forward<P>(X, buf, t, W);
 
   // this wave's pair (unit j, partner g)
@@ -1710,36 +1793,12 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
     R[e] = cmulc(X[e], SG[e]);
   });
   fft_inverse<P>(R, buf, t, W);
-  uint32_t vmask = 0;
-  float qmax = 0.f;
-  int kbest = 0;
-  float2* cube = a.cube ? a.cube + pl.off_cube : nullptr;
-  const float invP = 1.0f / (float)P;
-  const int T2 = 2 * N - 1;
-  static_for<E>([&](auto ec) {
-    constexpr int e = decltype(ec)::value;
-    const int k = t + 64 * e;
-    int tp = 0;
-    bool inr = false;
-    if (k <= N - 1) {
-      tp = -k;
-      inr = true;
-    } else if (k >= P - N + 1) {
-      tp = P - k;
-      inr = true;
-    }
-    const bool valid = inr && tp >= wlo && tp <= whi && !(g == w && tp == 0);
-    if (valid) {
-      vmask |= 1u << e;
-      const float q = R[e].x * R[e].x + R[e].y * R[e].y;
-      if (q > qmax) {
-        qmax = q;
-        kbest = k;
-      }
-    }
-    if (cube != nullptr && active && inr)
-      cube[((int64_t)(w * M + g) * F + f) * T2 + tp + N - 1] = cscale(R[e], invP);
-  });
+  uint32_t vmask;
+  float qmax;
+  int kbest;
+  roi_scan<P, 64, E>(R, t, N, wlo, whi, g == w, vmask, qmax, kbest);
+  if (a.cube != nullptr && active)
+    cube_store<P, 64, E>(R, t, N, a.cube + pl.off_cube + ((int64_t)(w * M + g) * F + f) * (2 * N - 1));
   // wave maximum, and its cell from the lowest lane that holds it
   const float qw = wave_max(qmax);
   const unsigned long long holders = __ballot(vmask != 0 && qmax == qw);
@@ -1747,21 +1806,8 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   const int kb = __builtin_amdgcn_readlane(kbest, src);
   const unsigned long long key = holders ? make_key(qw, (uint32_t)(((int64_t)u * M + g) * P + kb)) : 0ull;
   const float sigma = sqrtf(qw);
-  const float inv_s = sigma > 0.f ? 1.0f / sigma : 0.f;
-  const float inv_s2 = inv_s * inv_s;
   float S = 0.f;
-  static_for<E>([&](auto ec) {
-    constexpr int e = decltype(ec)::value;
-    if (vmask & (1u << e)) {
-      const float x = (R[e].x * R[e].x + R[e].y * R[e].y) * inv_s2;
-      float ym1, y;
-      pow_ph<PHLOG>(x, phm1, ym1, y);
-      S += y;
-      R[e] = cscale(R[e], ym1 * inv_s);
-    } else {
-      R[e] = make_float2(0.f, 0.f);
-    }
-  });
+  roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? 1.0f / sigma : 0.f, phm1, S);
   S = wave_sum(S);
   if (t == 0) {
     g_sig[wv] = active ? sigma : 0.f;
@@ -1814,11 +1860,13 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
     }
     if (grad) {
       fft_inverse<P>(U, buf, t, W);
+      float2 ph[EH];
+      phasor_row<EH, 64>(t, nu, invN, ph);
       wave_lds_sync();
       static_for<EH>([&](auto ec) {
         constexpr int e = decltype(ec)::value;
         const int n = t + 64 * e;
-        if (n < N) buf[n] = active ? cmulc(U[e], phasor(n, nu, invN)) : make_float2(0.f, 0.f);
+        if (n < N) buf[n] = active ? cmulc(U[e], ph[e]) : make_float2(0.f, 0.f);
       });
     }
   }

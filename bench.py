@@ -29,6 +29,8 @@ if ROOT not in sys.path:
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 HBM_PEAK_GBPS = 8000.0            # MI355X published HBM3E bandwidth
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_split_c2_traffic.md")
+COPY_BYTES = 1 << 28              # calibration copy of the counter runs: 256 MiB read, 256 MiB written
 
 
 def log(*a):
@@ -77,17 +79,66 @@ def time_graph(run, steps: int, warmup: int, per_graph: int):
     return e0.elapsed_time(e1) / (reps * per_graph), wall, reps * per_graph
 
 
-def kernel_durations(run, nat, steps: int):
-    """Durations (ms) of every fused-pass launch over `steps` eager steps."""
+def kernel_durations(run, nat, steps: int, repeat: int = 20):
+    """Per-launch durations (ms) of the fused pass over `steps` eager steps: HIP
+    events on the launch stream around `repeat` back-to-back launches of each
+    pass (identical inputs and outputs), divided by `repeat`."""
     import torch
     torch.cuda.synchronize()
-    nat.profile_enable(2 * steps)
+    nat.profile_enable(2 * steps, repeat)
     for _ in range(steps):
         run.step()
     torch.cuda.synchronize()
     d = nat.profile_read(2 * steps)
-    nat.profile_enable(0)
+    nat.profile_enable(0, 1)
     return d
+
+
+def source_hash() -> str:
+    """sha256 over the device sources (kernels, FFT, plan layout): a stored
+    traffic figure is used only while the kernels it was measured on are
+    unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2604_25728_amd", "csrc")
+    for name in ("fft_wave.hpp", "kernels.hip", "plan.hpp"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per fused-pass launch from the committed counter summary, or
+    None when the summary is missing or was taken on other sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            txt = f.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        if line.startswith("traffic_bytes_per_launch:") or line.startswith("source_hash:"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != source_hash() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def counter_run(run, steps: int):
+    """Workload for the rocprofv3 --pmc passes: `steps` eager iterations (every
+    kernel a separate dispatch), then a plain device copy of COPY_BYTES that
+    calibrates FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    for _ in range(steps):
+        run.step()
+    torch.cuda.synchronize()
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"counter run: {steps} eager iterations, then one copy of {COPY_BYTES} bytes")
 
 
 def cpu_baseline(prob: dict, opt: dict, budget_s: float) -> dict:
@@ -122,6 +173,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and copy probes")
+    ap.add_argument("--counters", action="store_true",
+                    help="run the workload for rocprofv3 --pmc (eager iterations + calibration copy) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the designs of a batch "
@@ -141,6 +194,9 @@ def main():
     log(f"device: {torch.cuda.get_device_name(0)}")
 
     run = optim.SQNGD([prob], opt, seeds=[0])
+    if args.counters:
+        counter_run(run, args.steps)
+        return
     ms_step, wall, steps = time_graph(run, args.steps, args.warmup, args.iters_per_graph)
     evals_per_s = 2.0 / (ms_step * 1e-3)
     log(f"step {ms_step * 1e3:.2f} us ({steps} iterations in graphs of {args.iters_per_graph}, "
@@ -148,6 +204,7 @@ def main():
 
     kd = kernel_durations(run, nat, min(args.steps, 200))
     kd_avg_ms = float(kd.mean())
+    traffic = stored_traffic()
     flops = pass_flops(prob)
     achieved = flops / (kd_avg_ms * 1e-3) / 1e12
     log(f"fused pass: {kd.size} launches, mean {kd_avg_ms * 1e3:.2f} us, "
@@ -200,8 +257,9 @@ def main():
                    "p": prob["p"], "evals_per_step": 2},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "k_pass (fused AF + loss + adjoint)",
-                     "kernel_us": kd_avg_ms * 1e3, "flops_per_launch": flops},
+                     "traffic": traffic, "kernel": "k_pass_split (fused AF + loss + adjoint)",
+                     "kernel_us": kd_avg_ms * 1e3, "flops_per_launch": flops,
+                     "traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT) if traffic else None},
         "cube_equivalent": {"GBps": cube_gbps, "frac_of_hbm": cube_gbps / HBM_PEAK_GBPS,
                             "bytes_per_launch": 16 * cube_cells(prob)},
     }

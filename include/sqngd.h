@@ -226,14 +226,17 @@ int sqngd_run(const sqngd_problem* probs, int32_t nprob, const sqngd_opt* opt, i
 int sqngd_hard_quantize(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t* idx,
                         sqngd_c64* x, void* ws, size_t ws_bytes, void* stream);
 
-/* Measurement hook. sqngd_profile_enable(n) (n > 0) makes the library
-   bracket each of the next n launches of its fused AF pass kernel with HIP
-   events recorded on the launch stream; sqngd_profile_enable(0) switches it
-   off. sqngd_profile_read waits for those events and writes the duration of
-   each recorded launch in milliseconds (at most capacity values, *count gets
-   the number recorded). Process-wide state, not thread-safe; calls captured in
-   a graph while enabled record nothing. */
-int sqngd_profile_enable(int32_t max_launches);
+/* Measurement hook. sqngd_profile_enable(n, r) (n > 0, 1 <= r <= 1000) makes
+   the library bracket each of the next n launches of its fused AF pass kernel
+   with HIP events recorded on the launch stream, and issue that launch r times
+   back to back inside the bracket (the pass reads only prepared inputs and
+   rewrites the same outputs, so the repeats change nothing; a deferred step
+   counter advance happens once). sqngd_profile_enable(0, 1) switches it off.
+   sqngd_profile_read waits for the events and writes, per recorded launch, the
+   bracketed time divided by r in milliseconds (at most capacity values,
+   *count gets the number recorded). Process-wide state, not thread-safe;
+   calls captured in a graph while enabled record nothing. */
+int sqngd_profile_enable(int32_t max_launches, int32_t repeat);
 int sqngd_profile_read(float* ms, int32_t capacity, int32_t* count);
 
 /* Human-readable text of a status code. */

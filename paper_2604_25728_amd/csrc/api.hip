@@ -362,7 +362,7 @@ void launch_prep(const Plan& pl, const Ptrs& w, PrepArgs a, hipStream_t s) {
 struct Profiler {
   std::mutex mu;
   std::vector<hipEvent_t> ev;  // 2 per launch
-  int max = 0, used = 0;
+  int max = 0, used = 0, repeat = 1;
 } g_prof;
 
 bool stream_capturing(hipStream_t s) {
@@ -407,16 +407,19 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
       if (g_prof.used < g_prof.max) slot = g_prof.used++;
     }
     if (slot >= 0) hipEventRecord(g_prof.ev[2 * slot], s);
-    if (pl.split) {
-      if (g == 2) launch_split_p<512>(a, phl, waves, s);
-      else launch_split_p<1024>(a, phl, waves, s);
-    } else {
-      switch (g) {
-        case 0: launch_pass_p<128>(a, phl, waves, s); break;
-        case 1: launch_pass_p<256>(a, phl, waves, s); break;
-        case 2: launch_pass_p<512>(a, phl, waves, s); break;
-        case 3: launch_pass_p<1024>(a, phl, waves, s); break;
-        default: launch_pass_p<2048>(a, phl, waves, s); break;
+    const int reps = slot >= 0 ? g_prof.repeat : 1;
+    for (int rep = 0; rep < reps; ++rep, a.bump = nullptr) {
+      if (pl.split) {
+        if (g == 2) launch_split_p<512>(a, phl, waves, s);
+        else launch_split_p<1024>(a, phl, waves, s);
+      } else {
+        switch (g) {
+          case 0: launch_pass_p<128>(a, phl, waves, s); break;
+          case 1: launch_pass_p<256>(a, phl, waves, s); break;
+          case 2: launch_pass_p<512>(a, phl, waves, s); break;
+          case 3: launch_pass_p<1024>(a, phl, waves, s); break;
+          default: launch_pass_p<2048>(a, phl, waves, s); break;
+        }
       }
     }
     if (slot >= 0) hipEventRecord(g_prof.ev[2 * slot + 1], s);
@@ -500,8 +503,8 @@ const char* sqngd_status_string(int status) {
 
 int sqngd_last_hip_error(void) { return g_last_hip.load(); }
 
-int sqngd_profile_enable(int32_t max_launches) {
-  if (max_launches < 0 || max_launches > (1 << 16)) return SQNGD_E_INVALID_ARG;
+int sqngd_profile_enable(int32_t max_launches, int32_t repeat) {
+  if (max_launches < 0 || max_launches > (1 << 16) || repeat < 1 || repeat > 1000) return SQNGD_E_INVALID_ARG;
   std::lock_guard<std::mutex> lk(g_prof.mu);
   while ((int)g_prof.ev.size() < 2 * max_launches) {
     hipEvent_t e;
@@ -511,6 +514,7 @@ int sqngd_profile_enable(int32_t max_launches) {
   }
   g_prof.max = max_launches;
   g_prof.used = 0;
+  g_prof.repeat = repeat;
   return SQNGD_OK;
 }
 
@@ -523,6 +527,7 @@ int sqngd_profile_read(float* ms, int32_t capacity, int32_t* count) {
     if (err != hipSuccess) return hip_fail(err);
     err = hipEventElapsedTime(&ms[i], g_prof.ev[2 * i], g_prof.ev[2 * i + 1]);
     if (err != hipSuccess) return hip_fail(err);
+    ms[i] /= (float)g_prof.repeat;
   }
   *count = g_prof.used;
   return SQNGD_OK;

@@ -75,7 +75,7 @@ def load():
     lib.sqngd_status_string.argtypes = [ctypes.c_int]
     lib.sqngd_status_string.restype = ctypes.c_char_p
     lib.sqngd_last_hip_error.argtypes = []
-    lib.sqngd_profile_enable.argtypes = [i32]
+    lib.sqngd_profile_enable.argtypes = [i32, i32]
     lib.sqngd_profile_read.argtypes = [P, i32, P]
     for name in SYMBOLS:
         if name not in ("sqngd_status_string",):
@@ -94,9 +94,10 @@ def check(rc: int, what: str):
         raise SQNGDError(f"{what}: {status_string(rc)} (status {rc}, hip error {hip})")
 
 
-def profile_enable(max_launches: int):
-    """Bracket the next max_launches fused-pass launches with HIP events (0: off)."""
-    check(load().sqngd_profile_enable(int(max_launches)), "profile_enable")
+def profile_enable(max_launches: int, repeat: int = 1):
+    """Bracket the next max_launches fused-pass launches with HIP events (0: off),
+    each issued `repeat` times back to back inside its bracket."""
+    check(load().sqngd_profile_enable(int(max_launches), int(repeat)), "profile_enable")
 
 
 def profile_read(capacity: int = 65536) -> np.ndarray:

@@ -143,3 +143,17 @@ def test_entry_points_reject_before_touching_the_device(nat):
     assert lib.sqngd_workspace_init(None, 1, ws, nb, None) == -1
     assert lib.sqngd_workspace_init(arr, 1, ws, nb - 256, None) == -3
     assert lib.sqngd_last_hip_error() == 0
+
+
+def test_profile_hook_validation(nat):
+    """The profiling switch validates its arguments on the host; switching it
+    off needs no device."""
+    lib = nat.load()
+    assert lib.sqngd_profile_enable(-1, 1) == -1
+    assert lib.sqngd_profile_enable(1, 0) == -1
+    assert lib.sqngd_profile_enable(1, 1001) == -1
+    assert lib.sqngd_profile_enable(1 << 17, 1) == -1
+    assert lib.sqngd_profile_enable(0, 1) == 0
+    cnt = ctypes.c_int32(-1)
+    assert lib.sqngd_profile_read(None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 0
+    assert lib.sqngd_profile_read(None, 0, None) == -1

@@ -113,3 +113,45 @@ def noise(M: int, N: int, seed: int) -> np.ndarray:
     """The warm-start network's input noise, N(0, 1) [M][N] float32."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((M, N)).astype(np.float32)
+
+
+# ---------------------------------------------------------------- warm-start network
+
+NET_CHANNELS = 64   # hidden channels
+NET_TAPS = 5        # kernel width (zero padding of 2 on each side, output length N)
+
+
+def net_layers(M: int, L: int) -> list:
+    """(input channels, output channels) of the four conv layers: M noise rows
+    plus two conditioning rows in, 64 hidden channels, M*L logits out (channel
+    m*L + l is level l of waveform m)."""
+    C = NET_CHANNELS
+    return [(M + 2, C), (C, C), (C, C), (C, M * L)]
+
+
+def net_param_count(M: int, L: int) -> int:
+    return sum(co * NET_TAPS * ci + co for ci, co in net_layers(M, L))
+
+
+def net_init(M: int, L: int, seed: int) -> np.ndarray:
+    """Flat float32 parameters, per layer W[cout][tap][cin] then b[cout]:
+    uniform in +-sqrt(6 / fan_in) for W (fan_in = 5 cin), zero bias."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for ci, co in net_layers(M, L):
+        bound = np.sqrt(6.0 / (NET_TAPS * ci))
+        out.append(rng.uniform(-bound, bound, size=co * NET_TAPS * ci))
+        out.append(np.zeros(co))
+    return np.concatenate(out).astype(np.float32)
+
+
+def net_noise(B: int, M: int, N: int, seed: int) -> np.ndarray:
+    """A batch of network inputs, N(0, 1) [B][M][N] float32."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((B, M, N)).astype(np.float32)
+
+
+def net_targets(B: int, M: int, N: int, L: int, seed: int) -> np.ndarray:
+    """Random level indices [B][M][N] int32 (for tests of the loss)."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, L, size=(B, M, N)).astype(np.int32)

@@ -821,3 +821,6 @@ int sqngd_hard_quantize(const sqngd_problem* probs, int32_t nprob, const float* 
 }
 
 }  // extern "C"
+
+// the warm-start network (same translation unit: it uses the helpers above)
+#include "net.hip"

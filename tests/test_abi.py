@@ -10,6 +10,7 @@ from paper_2604_25728_amd import inputs as I
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "sqngd.h")
+NET_HEADER = os.path.join(ROOT, "include", "sqngd_net.h")
 
 
 @pytest.fixture(scope="module")
@@ -22,8 +23,8 @@ def nat():
     return native
 
 
-def _declared():
-    text = open(HEADER).read()
+def _declared(path=HEADER):
+    text = open(path).read()
     return sorted(set(re.findall(r"^(?:const\s+)?\w+\*?\s+\**(sqngd_\w+)\(", text, flags=re.M)))
 
 
@@ -34,6 +35,16 @@ def test_header_symbols_exported(nat):
     for n in names:
         assert hasattr(lib, n), n
     assert sorted(nat.SYMBOLS) == names
+
+
+def test_every_header_in_include_is_exported(nat):
+    from paper_2604_25728_amd import netnative
+    lib = nat.load()
+    inc = os.path.join(ROOT, "include")
+    for h in sorted(os.listdir(inc)):
+        for n in _declared(os.path.join(inc, h)):
+            assert hasattr(lib, n), (h, n)
+    assert sorted(netnative.SYMBOLS) == _declared(NET_HEADER)
 
 
 def test_struct_layouts(nat):
@@ -157,3 +168,28 @@ def test_profile_hook_validation(nat):
     cnt = ctypes.c_int32(-1)
     assert lib.sqngd_profile_read(None, 0, ctypes.byref(cnt)) == 0 and cnt.value == 0
     assert lib.sqngd_profile_read(None, 0, None) == -1
+
+
+def test_net_validation(nat):
+    """Network shape checks run on the host; counts follow the layer table."""
+    from paper_2604_25728_amd import netnative as NN
+    lib = NN.lib()
+    n = ctypes.c_int64()
+    b = ctypes.c_size_t()
+    ok = NN.shape(4, 512, 8, 16)
+    assert lib.sqngd_net_param_count(ctypes.byref(ok), ctypes.byref(n)) == 0
+    assert n.value == I.net_param_count(4, 8)
+    assert lib.sqngd_net_workspace_size(ctypes.byref(ok), ctypes.byref(b)) == 0 and b.value > 0
+    for args, code in (((7, 512, 8, 16), -2), ((4, 500, 8, 16), -2), ((4, 512, 6, 16), -2),
+                       ((3, 512, 4, 16), -2), ((4, 512, 8, 0), -1), ((0, 512, 8, 4), -1)):
+        s = NN.shape(*args)
+        assert lib.sqngd_net_param_count(ctypes.byref(s), ctypes.byref(n)) == code, args
+    bad = NN.shape(4, 512, 8, 16, cond=(float("nan"), 1.0))
+    assert lib.sqngd_net_workspace_size(ctypes.byref(bad), ctypes.byref(b)) == -1
+    # entry points reject before touching the device
+    assert lib.sqngd_net_forward(ctypes.byref(ok), None, None, None, None, 0, None) == -1
+    dummy = ctypes.c_void_p(256)
+    assert lib.sqngd_net_forward(ctypes.byref(ok), dummy, dummy, dummy, dummy, 16, None) == -3
+    assert lib.sqngd_net_backward(ctypes.byref(ok), None, None, None, dummy, None, dummy, 1 << 40, None) == -1
+    o = NN.NetOpt(1e-3, 0.9, 0.999, 1e-8)
+    assert lib.sqngd_net_adam(ctypes.byref(ok), ctypes.byref(o), 0, dummy, dummy, dummy, None) == -1

@@ -1,0 +1,45 @@
+"""The warm-start pipeline end to end at a small size: converged-run data from
+paired starts, training on the MFMA network, time to target against random
+starts (mechanics and invariants; the measured A/B at the M=4 N=512 size is
+produced by `python -m paper_2604_25728_amd.warmstart`)."""
+import numpy as np
+import pytest
+
+from paper_2604_25728_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def WS():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_25728_amd import native, warmstart
+    native.load()
+    return warmstart
+
+
+def test_paired_logits_peak_at_the_noise_quantile(WS):
+    eps = np.array([[-3.0, 0.0, 0.3]])
+    z = WS.paired_logits(eps, 8)
+    assert z.shape == (1, 3, 8)
+    assert np.argmax(z[0, 1]) == 4  # Phi(0) = 1/2 -> level L/2
+    assert np.allclose(z.max(axis=-1), np.cos(2 * np.pi * np.min(np.abs(
+        np.arange(8)[None, :] / 8 - np.array([[0.0013499], [0.5], [0.6179114]])), axis=-1)), atol=1e-3)
+
+
+def test_pipeline_small(WS):
+    prob = I.make_problem(4, 64, 4, 9, p=8.0)
+    opt = I.make_opt(total_iters=40, T0=1.0, T1=0.2)
+    print("[gpu] warm-start pipeline small", flush=True)
+    data = WS.generate(prob, opt, range(500, 508), batch=4, iters=40)
+    assert data["idx"].shape == (8, 4, 64) and data["idx"].max() < 4
+    net, hist = WS.train(prob, data, epochs=3, batch=4, lr=3e-3)
+    assert len(hist) == 3 and all(np.isfinite(hist))
+    res = WS.time_to_target(prob, opt, net.params, range(4), iters=40, check_every=10)
+    assert res["seeds"] == 4 and 0.0 <= res["fraction_reached"] <= 1.0
+    for p in res["per_seed"]:
+        # the random arm reaches its own final PSL by the last checkpoint at the latest
+        assert p["random_iters"] is not None and p["random_iters"] <= 40
+        assert p["warm_iters"] is None or p["warm_iters"] <= 40

@@ -223,6 +223,23 @@ def main():
             "pass_tflops": R * flops / (kdb.mean() * 1e-3) / 1e12}
         log(f"batched x{R}: step {msb * 1e3:.1f} us, {extras['batched_restarts']['evals_per_s']:.0f} evals/s")
         del runb
+        # the other workloads: one wide-span design, the network's design size
+        # batched, and the uneven 64-design x 8-restart batch
+        for name, count in (("c4", 1), ("c5", 64)):
+            c = I.config(name)
+            r = optim.SQNGD([c["problem"]] * count, c["opt"], seeds=list(range(count)))
+            ms_c, _, _ = time_graph(r, 20, 10, 10)
+            extras[f"{name}_x{count}"] = {"ms_per_step": ms_c, "evals_per_s": 2.0 * count / (ms_c * 1e-3),
+                                          "shape": {k: c["problem"][k] for k in ("M", "N", "L", "F")}}
+            log(f"{name} x{count}: step {ms_c * 1e3:.1f} us")
+            del r
+        designs = I.c3_designs()
+        r = optim.SQNGD([p for p, _ in designs], I.config("c2")["opt"], seeds=[sd for _, sd in designs])
+        ms_c, _, _ = time_graph(r, 10, 10, 10)
+        extras["c3_uneven_512"] = {"ms_per_step": ms_c, "evals_per_s": 2.0 * len(designs) / (ms_c * 1e-3),
+                                   "designs": 64, "restarts": 8}
+        log(f"c3 uneven x{len(designs)}: step {ms_c * 1e3:.1f} us")
+        del r
         n = 1 << 28
         a = torch.empty(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

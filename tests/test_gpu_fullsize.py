@@ -1,0 +1,107 @@
+"""Full-size parity of the hot path: the wide-span M=8 N=1024 L=16 F=257
+design, the M=4 N=512 L=8 F=129 design, and an uneven slice of the 64-design
+workload in one batch, each against the FP64 oracle (statistics and both
+gradients in full; AF cells on sampled rows computed one by one by direct sum)
+and against properties that hold at any size (the statistics recomputed from
+the AF cube the kernels wrote). Tolerances as in test_gpu_parity."""
+import numpy as np
+import pytest
+
+from paper_2604_25728_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def nat():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_25728_amd import native
+    native.load()
+    return native
+
+
+def _rel(a, b):
+    a, b = np.asarray(a).reshape(-1), np.asarray(b).reshape(-1)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _db(v):
+    return 20 * np.log10(v)
+
+
+def _cube_stats(cube, prob):
+    """PSL and L_p from a device cube [M][M][F][2N-1] (float64 on the GPU)."""
+    M, N = prob["M"], prob["N"]
+    a = cube.abs().double() / N
+    tau = torch.arange(-(N - 1), N, device=a.device)
+    roi = (tau >= prob["tau_lo"]) & (tau <= prob["tau_hi"])
+    eye = torch.eye(M, dtype=torch.bool, device=a.device)[:, :, None, None]
+    auto = eye & roi & (tau != 0)
+    cross = (~eye) & roi
+    psl_a = (a * auto).amax().item() * N
+    psl_c = (a * cross).amax().item() * N if M > 1 else 0.0
+    mask = auto | cross
+    amax = (a * mask).amax()
+    lp = (amax * (((a / amax) ** prob["p"]) * mask).sum() ** (1.0 / prob["p"])).item()
+    return psl_a, psl_c, lp
+
+
+def _check(ref, nat, b, probs, zs, hs, rows_per_problem=4):
+    zt, ht = b.pack_z(zs), b.pack_w(hs)
+    stats, cube = b.af_forward(zt, ht, nat.WAVE_SOFT, cube=True)
+    stats_b = b.new_stats()
+    gz, gh, gs = b.af_backward(zt, ht, nat.WAVE_SOFT, want_s=True, stats=stats_b)
+    torch.cuda.synchronize()
+    sts = nat.decode_stats(stats.cpu().numpy())
+    rng = np.random.default_rng(0)
+    for i, p in enumerate(probs):
+        M, N, F = p["M"], p["N"], p["F"]
+        c = b.unpack_cube(cube, i)
+        # properties: the statistics against the cube the kernels wrote
+        psl_a, psl_c, lp = _cube_stats(c, p)
+        st = sts[i]
+        assert abs(_db(st["psl_auto"]) - _db(psl_a)) <= 0.01, (i, st["psl_auto"], psl_a)
+        if M > 1:
+            assert abs(_db(st["psl_cross"]) - _db(psl_c)) <= 0.01, (i, st["psl_cross"], psl_c)
+        assert abs(st["lp"] - lp) <= 1e-4 * lp, (i, st["lp"], lp)
+        # the oracle: sampled rows by direct sum, statistics and gradients in full
+        s = ref.soft_waveform(zs[i].astype(np.float64), p["temperature"])
+        h = hs[i].astype(np.complex128)
+        amax = float(c.abs().max().item())
+        for _ in range(rows_per_problem):
+            m, l, f = int(rng.integers(M)), int(rng.integers(M)), int(rng.integers(F))
+            row = ref.af_row(s, h, F, p["nu_min"], p["nu_max"], m, l, f)
+            got = c[m, l, f].cpu().numpy()
+            assert np.abs(got - row).max() <= 1e-4 * amax, (i, m, l, f)
+        st_ref, gs_ref, gh_ref = ref.evaluate(s, h, p)
+        assert abs(st["loss"] - st_ref["loss"]) <= 1e-4 * st_ref["loss"]
+        assert abs(st["pslr_db"] - st_ref["pslr_db"]) <= 0.05
+        assert abs(st["snrl_db_max"] - st_ref["snrl_db_max"]) <= 0.05
+        assert _rel(b.unpack_w(gs, i).cpu().numpy(), gs_ref) <= 1e-4, i
+        assert _rel(b.unpack_w(gh, i).cpu().numpy(), gh_ref) <= 1e-4, i
+        gz_ref = ref.logit_grad(zs[i].astype(np.float64), p["temperature"], gs_ref)
+        assert _rel(b.unpack_z(gz, i).cpu().numpy(), gz_ref) <= 1e-4, i
+
+
+@pytest.mark.parametrize("name", ["c4", "c5"])
+def test_single_design_full_size(ref, nat, name):
+    prob = I.config(name)["problem"]
+    M, N, L = prob["M"], prob["N"], prob["L"]
+    print(f"[gpu] full size {name}", flush=True)
+    b = nat.Batch([prob])
+    z = I.logits(M, N, L, 21)
+    h = ref.matched_init(z.astype(np.float64)).astype(np.complex64) + 0.1 * I.complex_gaussian(M, N, 22)
+    _check(ref, nat, b, [prob], [z], [h])
+
+
+def test_uneven_batch_slice(ref, nat):
+    """Eight designs of the 64-design workload (first restart each) in one batch."""
+    designs = I.c3_designs(n_designs=8, restarts=1)
+    probs = [p for p, _ in designs]
+    print("[gpu] uneven batch " + ", ".join(f"M{p['M']}N{p['N']}L{p['L']}" for p in probs), flush=True)
+    zs = [I.logits(p["M"], p["N"], p["L"], s) for p, s in designs]
+    hs = [I.complex_gaussian(p["M"], p["N"], s + 7) for p, s in designs]
+    b = nat.Batch(probs)
+    _check(ref, nat, b, probs, zs, hs, rows_per_problem=2)

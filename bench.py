@@ -95,13 +95,13 @@ def kernel_durations(run, nat, steps: int, repeat: int = 20):
 
 
 def source_hash() -> str:
-    """sha256 over the device sources (kernels, FFT, plan layout): a stored
-    traffic figure is used only while the kernels it was measured on are
-    unchanged."""
+    """sha256 over the device sources and their launch code (kernels, FFT,
+    plan layout, launcher): a stored traffic figure is used only while the
+    kernels and launch shapes it was measured on are unchanged."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2604_25728_amd", "csrc")
-    for name in ("fft_wave.hpp", "kernels.hip", "plan.hpp"):
+    for name in ("api.hip", "fft_wave.hpp", "kernels.hip", "plan.hpp"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]

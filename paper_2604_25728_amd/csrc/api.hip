@@ -37,8 +37,41 @@ int log2i(int v) {
 bool finite(float v) { return std::isfinite(v); }
 
 // waves per block of the latency variant of the fused pass
-constexpr int split_waves(int P) { return P == 512 ? 8 : 8; }
+// Latency variant of the fused pass: waves per block (M partners x units per
+// block) are chosen per FFT length among the compiled shapes; the LDS of a
+// block holds one P-point exchange buffer per wave (<= 64 KiB).
+constexpr int kSplitShapes512[] = {8, 12, 16};
+constexpr int kSplitShapes1024[] = {8};
+constexpr int kMaxSplitWaves = 16;
 constexpr double kSplitMaxWaves = 8192.0;
+constexpr int kNumCUs = 256;  // MI355X compute units: one block per CU is the aim
+
+// Waves per split block for the problems of one FFT length: the compiled
+// shape minimising (rounds of kNumCUs blocks) x (waves per block), i.e. the
+// per-SIMD wave count of the slowest compute unit; ties go to fewer waves.
+int choose_split_waves(int P, const sqngd_problem* probs, const std::vector<int>& ids) {
+  const int* shapes = P == 512 ? kSplitShapes512 : kSplitShapes1024;
+  const int nshapes = P == 512 ? 3 : 1;
+  int best = 0;
+  double best_cost = 0.0;
+  for (int k = 0; k < nshapes; ++k) {
+    const int wv = shapes[k];
+    int64_t blocks = 0;
+    bool fits = true;
+    for (int id : ids) {
+      const int M = probs[id].M;
+      if (M > wv) fits = false;
+      else blocks += (int64_t)M * ((probs[id].F + wv / M - 1) / (wv / M));
+    }
+    if (!fits) continue;
+    const double cost = (double)((blocks + kNumCUs - 1) / kNumCUs) * wv;
+    if (best == 0 || cost < best_cost) {
+      best = wv;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
 
 int validate_problem(const sqngd_problem& p) {
   if (p.M < 1 || p.N < 2 || p.L < 2 || p.F < 1) return SQNGD_E_INVALID_ARG;
@@ -73,6 +106,7 @@ struct Plan {
   std::vector<char> bytes;  // [0, hdr.spec): header, plans, tables
   std::vector<ProbPlan> plans;
   int group_phlog[kNumPGroups];
+  int group_wv[kNumPGroups];  // waves per block of the latency variant (split batches)
   // finalize of the optimiser steps: 0 = k_final, else k_step with this
   // bound on the logit levels per lane
   int group_step[kNumPGroups];
@@ -103,12 +137,21 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
   // fused pass (one wave per Doppler bin and partner).
   bool split = true;
   double pair_waves = 0.0;
+  std::vector<int> ids_p[kNumPGroups];
   for (int i = 0; i < nprob; ++i) {
     const int P = fft_len(probs[i].N);
-    if ((P != 512 && P != 1024) || probs[i].M > split_waves(P)) split = false;
+    if ((P != 512 && P != 1024) || probs[i].M > kMaxSplitWaves) split = false;
     pair_waves += (double)probs[i].M * probs[i].M * probs[i].F;
+    ids_p[log2i(P) - kMinLogP].push_back(i);
   }
   if (pair_waves > kSplitMaxWaves) split = false;
+  for (int g = 0; g < kNumPGroups; ++g) {
+    pl->group_wv[g] = 0;
+    if (split && !ids_p[g].empty()) {
+      pl->group_wv[g] = choose_split_waves(1 << (g + kMinLogP), probs, ids_p[g]);
+      if (pl->group_wv[g] == 0) split = false;
+    }
+  }
   pl->split = split;
   int64_t off_z = 0, off_w = 0, off_state = 0, off_cube = 0, spec = 0, unit = 0, upart = 0;
   int rows = 0;
@@ -141,7 +184,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     {
       int upb;  // Doppler bins per fused-pass block
       if (split) {
-        upb = split_waves(q.P) / p.M;
+        upb = pl->group_wv[q.logP - kMinLogP] / p.M;
       } else {
         const int TF = q.P >= 512 ? 64 : q.P / 8;
         upb = kPassWaves * (64 / TF);
@@ -370,13 +413,19 @@ bool stream_capturing(hipStream_t s) {
   return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
 }
 
-template <int P>
-void launch_split_p(const PassArgs& a, int phlog, int blocks, hipStream_t s) {
-  constexpr int WV = split_waves(P);
+template <int P, int WV>
+void launch_split_wv(const PassArgs& a, int phlog, int blocks, hipStream_t s) {
   const dim3 block(64 * WV);
   if (phlog == 3) hipLaunchKernelGGL((k_pass_split<P, 3, WV>), dim3(blocks), block, 0, s, a);
   else if (phlog == 2) hipLaunchKernelGGL((k_pass_split<P, 2, WV>), dim3(blocks), block, 0, s, a);
   else hipLaunchKernelGGL((k_pass_split<P, -1, WV>), dim3(blocks), block, 0, s, a);
+}
+
+void launch_split(int P, int wv, const PassArgs& a, int phlog, int blocks, hipStream_t s) {
+  if (P == 1024) launch_split_wv<1024, 8>(a, phlog, blocks, s);
+  else if (wv == 12) launch_split_wv<512, 12>(a, phlog, blocks, s);
+  else if (wv == 16) launch_split_wv<512, 16>(a, phlog, blocks, s);
+  else launch_split_wv<512, 8>(a, phlog, blocks, s);
 }
 
 template <int P>
@@ -410,8 +459,7 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
     const int reps = slot >= 0 ? g_prof.repeat : 1;
     for (int rep = 0; rep < reps; ++rep, a.bump = nullptr) {
       if (pl.split) {
-        if (g == 2) launch_split_p<512>(a, phl, waves, s);
-        else launch_split_p<1024>(a, phl, waves, s);
+        launch_split(1 << (g + kMinLogP), pl.group_wv[g], a, phl, waves, s);
       } else {
         switch (g) {
           case 0: launch_pass_p<128>(a, phl, waves, s); break;

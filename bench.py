@@ -107,9 +107,10 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic():
+def stored_traffic(schedule: int):
     """HBM bytes per fused-pass launch from the committed counter summary, or
-    None when the summary is missing or was taken on other sources."""
+    None when the summary is missing or was taken on other sources or under
+    another schedule."""
     try:
         with open(TRAFFIC_FILE) as f:
             txt = f.read()
@@ -117,10 +118,12 @@ def stored_traffic():
         return None
     vals = {}
     for line in txt.splitlines():
-        if line.startswith("traffic_bytes_per_launch:") or line.startswith("source_hash:"):
+        if line.startswith(("traffic_bytes_per_launch:", "source_hash:", "schedule:")):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("source_hash") != source_hash() or "traffic_bytes_per_launch" not in vals:
+        return None
+    if int(vals.get("schedule", "-1")) != int(schedule):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -173,6 +176,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and copy probes")
+    ap.add_argument("--schedule", type=int, default=12,
+                    help="fused-pass schedule hint of the --counters run (the timed run tunes it)")
     ap.add_argument("--counters", action="store_true",
                     help="run the workload for rocprofv3 --pmc (eager iterations + calibration copy) and exit")
     args = ap.parse_args()
@@ -193,10 +198,15 @@ def main():
     prob, opt = cfg["problem"], cfg["opt"]
     log(f"device: {torch.cuda.get_device_name(0)}")
 
-    run = optim.SQNGD([prob], opt, seeds=[0])
     if args.counters:
+        run = optim.SQNGD([prob], opt, seeds=[0], schedule=args.schedule)
         counter_run(run, args.steps)
         return
+    from paper_2604_25728_amd import tune
+    sched, sched_ms = tune.tune([prob], opt, steps=40)
+    log("schedule tuning (ms per step): " + ", ".join(f"{k}: {v * 1e3:.1f} us" for k, v in sched_ms.items())
+        + f" -> {sched}")
+    run = optim.SQNGD([prob], opt, seeds=[0], schedule=sched)
     ms_step, wall, steps = time_graph(run, args.steps, args.warmup, args.iters_per_graph)
     evals_per_s = 2.0 / (ms_step * 1e-3)
     log(f"step {ms_step * 1e3:.2f} us ({steps} iterations in graphs of {args.iters_per_graph}, "
@@ -204,7 +214,7 @@ def main():
 
     kd = kernel_durations(run, nat, min(args.steps, 200))
     kd_avg_ms = float(kd.mean())
-    traffic = stored_traffic()
+    traffic = stored_traffic(sched)
     flops = pass_flops(prob)
     achieved = flops / (kd_avg_ms * 1e-3) / 1e12
     log(f"fused pass: {kd.size} launches, mean {kd_avg_ms * 1e3:.2f} us, "
@@ -271,7 +281,7 @@ def main():
                                "delays, p=16, one filter + one logit update per step, HIP graphs of "
                                f"{args.iters_per_graph} steps",
                    "M": prob["M"], "N": prob["N"], "L": prob["L"], "F": prob["F"],
-                   "p": prob["p"], "evals_per_step": 2},
+                   "p": prob["p"], "evals_per_step": 2, "schedule": int(sched)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
                      "traffic": traffic, "kernel": "k_pass_split (fused AF + loss + adjoint)",

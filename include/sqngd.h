@@ -132,8 +132,27 @@ typedef struct {
   float w_psl, w_snrl;    /* loss weights of eq. 42 (paper: eps, 1-eps), >= 0    */
   float temperature;      /* softmax temperature T > 0 (SOFT mode)               */
   int32_t sq_mode;        /* SQNGD_SQ_PHASE_MEAN | SQNGD_SQ_PHASOR_MEAN           */
-  int32_t reserved[2];    /* must be 0                                           */
+  int32_t schedule;       /* fused-pass schedule hint, SQNGD_SCHED_* (0: automatic) */
+  int32_t reserved;       /* must be 0                                           */
 } sqngd_problem;
+
+/* Schedule of the fused AF pass (an implementation choice; every schedule
+   computes the same results to rounding). AUTO: the library's rule (the
+   per-(Doppler bin, partner) latency variant for small single batches of
+   FFT length 512 or 1024, its block shape minimising the slowest compute
+   unit's wave count). THROUGHPUT: one wavefront per Doppler bin looping over
+   the partners. SPLIT8/12/16: the latency variant with that many waves per
+   block (8, 12 or 16 at FFT length 512; 8 at 1024). A hint that does not
+   apply to the batch (another FFT length, M above the waves per block, a
+   batch too large for the latency variant) falls back to AUTO. The first
+   non-AUTO hint in problem order decides for the whole batch. The
+   project's autotuner (paper_2604_25728_amd/tune.py) times the candidates
+   on the device and returns the best hint. */
+#define SQNGD_SCHED_AUTO 0
+#define SQNGD_SCHED_THROUGHPUT 1
+#define SQNGD_SCHED_SPLIT8 8
+#define SQNGD_SCHED_SPLIT12 12
+#define SQNGD_SCHED_SPLIT16 16
 
 /* Optimiser options of one outer iteration (Algorithm 1). */
 typedef struct {

@@ -49,13 +49,14 @@ constexpr int kNumCUs = 256;  // MI355X compute units: one block per CU is the a
 // Waves per split block for the problems of one FFT length: the compiled
 // shape minimising (rounds of kNumCUs blocks) x (waves per block), i.e. the
 // per-SIMD wave count of the slowest compute unit; ties go to fewer waves.
-int choose_split_waves(int P, const sqngd_problem* probs, const std::vector<int>& ids) {
+int choose_split_waves(int P, const sqngd_problem* probs, const std::vector<int>& ids, int forced) {
   const int* shapes = P == 512 ? kSplitShapes512 : kSplitShapes1024;
   const int nshapes = P == 512 ? 3 : 1;
   int best = 0;
   double best_cost = 0.0;
   for (int k = 0; k < nshapes; ++k) {
     const int wv = shapes[k];
+    if (forced != 0 && wv != forced) continue;
     int64_t blocks = 0;
     bool fits = true;
     for (int id : ids) {
@@ -85,7 +86,10 @@ int validate_problem(const sqngd_problem& p) {
   if (!finite(p.w_psl) || !finite(p.w_snrl) || p.w_psl < 0.0f || p.w_snrl < 0.0f) return SQNGD_E_INVALID_ARG;
   if (!finite(p.temperature) || p.temperature <= 0.0f) return SQNGD_E_INVALID_ARG;
   if (p.sq_mode != SQNGD_SQ_PHASE_MEAN && p.sq_mode != SQNGD_SQ_PHASOR_MEAN) return SQNGD_E_INVALID_ARG;
-  if (p.reserved[0] != 0 || p.reserved[1] != 0) return SQNGD_E_INVALID_ARG;
+  if (p.reserved != 0) return SQNGD_E_INVALID_ARG;
+  if (p.schedule != SQNGD_SCHED_AUTO && p.schedule != SQNGD_SCHED_THROUGHPUT && p.schedule != SQNGD_SCHED_SPLIT8 &&
+      p.schedule != SQNGD_SCHED_SPLIT12 && p.schedule != SQNGD_SCHED_SPLIT16)
+    return SQNGD_E_INVALID_ARG;
   return SQNGD_OK;
 }
 
@@ -145,11 +149,22 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     ids_p[log2i(P) - kMinLogP].push_back(i);
   }
   if (pair_waves > kSplitMaxWaves) split = false;
-  for (int g = 0; g < kNumPGroups; ++g) {
-    pl->group_wv[g] = 0;
-    if (split && !ids_p[g].empty()) {
-      pl->group_wv[g] = choose_split_waves(1 << (g + kMinLogP), probs, ids_p[g]);
-      if (pl->group_wv[g] == 0) split = false;
+  int hint = SQNGD_SCHED_AUTO;
+  for (int i = 0; i < nprob && hint == SQNGD_SCHED_AUTO; ++i) hint = probs[i].schedule;
+  if (hint == SQNGD_SCHED_THROUGHPUT) split = false;
+  const int forced = hint >= SQNGD_SCHED_SPLIT8 ? hint : 0;
+  for (int pass = 0; pass < 2; ++pass) {  // a forced shape that does not apply falls back to the rule
+    bool ok = split;
+    for (int g = 0; g < kNumPGroups; ++g) {
+      pl->group_wv[g] = 0;
+      if (ok && !ids_p[g].empty()) {
+        pl->group_wv[g] = choose_split_waves(1 << (g + kMinLogP), probs, ids_p[g], pass == 0 ? forced : 0);
+        if (pl->group_wv[g] == 0) ok = false;
+      }
+    }
+    if (ok || pass == 1) {
+      split = ok;
+      break;
     }
   }
   pl->split = split;

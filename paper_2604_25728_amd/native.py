@@ -18,6 +18,7 @@ OK = 0
 WAVE_SOFT, WAVE_HARD, WAVE_GIVEN = 0, 1, 2
 SQ_PHASE_MEAN, SQ_PHASOR_MEAN = 0, 1
 OPT_SGD = 1
+SCHED_AUTO, SCHED_THROUGHPUT, SCHED_SPLIT8, SCHED_SPLIT12, SCHED_SPLIT16 = 0, 1, 8, 12, 16
 
 SYMBOLS = [
     "sqngd_buffer_sizes", "sqngd_workspace_size", "sqngd_workspace_init", "sqngd_af_forward",
@@ -32,7 +33,7 @@ class Problem(ctypes.Structure):
                 ("tau_lo", ctypes.c_int32), ("tau_hi", ctypes.c_int32), ("p", ctypes.c_float),
                 ("snrl_target_db", ctypes.c_float), ("w_psl", ctypes.c_float),
                 ("w_snrl", ctypes.c_float), ("temperature", ctypes.c_float),
-                ("sq_mode", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("sq_mode", ctypes.c_int32), ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Opt(ctypes.Structure):
@@ -115,6 +116,7 @@ def make_problems(probs) -> ctypes.Array:
         p = arr[i]
         for k in ("M", "N", "L", "F", "tau_lo", "tau_hi", "sq_mode"):
             setattr(p, k, int(d[k]))
+        p.schedule = int(d.get("schedule", SCHED_AUTO))
         for k in ("nu_min", "nu_max", "p", "snrl_target_db", "w_psl", "w_snrl", "temperature"):
             setattr(p, k, float(d[k]))
     return arr

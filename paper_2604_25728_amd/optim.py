@@ -21,7 +21,16 @@ class SQNGD:
     (inputs.make_opt); seeds: one seed per problem for the N(0,1) logits, or
     z0: a list of [M][N][L] float32 arrays to start from instead."""
 
-    def __init__(self, probs, opt: dict, seeds=None, z0=None, device="cuda"):
+    def __init__(self, probs, opt: dict, seeds=None, z0=None, device="cuda", schedule=None):
+        """schedule: None keeps each problem's hint (default automatic), an
+        int applies that SQNGD_SCHED_* hint to every problem, "tune" times the
+        candidates first (tune.tune) and applies the fastest."""
+        if schedule == "tune":
+            from . import tune
+            schedule, _ = tune.tune(probs, opt)
+        if schedule is not None:
+            probs = [dict(p, schedule=int(schedule)) for p in probs]
+        self.schedule = schedule
         self.batch = nat.Batch(probs, device=device)
         self.probs = self.batch.probs
         self.opt_dict = dict(opt)

@@ -102,8 +102,12 @@ def test_problem_validation(nat, field, value, code):
 
 def test_reserved_and_pair_count_limits(nat):
     arr = _arr(nat)
-    arr[0].reserved[0] = 1
+    arr[0].reserved = 1
     assert _ws_size(nat, arr)[0] == -1
+    for sched, code in ((2, -1), (-1, -1), (0, 0), (1, 0), (8, 0), (12, 0), (16, 0)):
+        arr = _arr(nat)
+        arr[0].schedule = sched
+        assert _ws_size(nat, arr)[0] == code, sched
     # the largest problem the limits allow still has cell indices below 2^32
     assert _ws_size(nat, _arr(nat, M=16, N=1024, F=4096))[0] == 0
 

@@ -208,3 +208,37 @@ def test_latency_and_throughput_variants_agree(ref, nat):
     for x, y in zip(g1, g8):
         n = x.numel()
         assert _rel(x.cpu().numpy(), y[:n].cpu().numpy()) <= 1e-5
+
+
+@pytest.mark.parametrize("sched", [1, 8, 12, 16])
+def test_every_schedule_gives_the_same_results(ref, nat, sched):
+    """Each fused-pass schedule hint (throughput variant, latency variant with
+    8 / 12 / 16 waves per block) against the automatic choice and the oracle."""
+    prob = I.config("c2")["problem"]
+    M, N, L = prob["M"], prob["N"], prob["L"]
+    print(f"[gpu] schedule {sched}", flush=True)
+    z, h = I.logits(M, N, L, 40), I.complex_gaussian(M, N, 41)
+    out = {}
+    for s_ in (0, sched):
+        b = nat.Batch([dict(prob, schedule=s_)])
+        st = b.new_stats()
+        gz, gh, gs = b.af_backward(b.pack_z([z]), b.pack_w([h]), nat.WAVE_SOFT, want_s=True, stats=st)
+        torch.cuda.synchronize()
+        out[s_] = (nat.decode_stats(st.cpu().numpy())[0], gz.cpu().numpy(), gh.cpu().numpy())
+    a, c = out[0], out[sched]
+    assert abs(a[0]["loss"] - c[0]["loss"]) <= 1e-5 * a[0]["loss"]
+    assert _rel(c[1], a[1]) <= 1e-5 and _rel(c[2], a[2]) <= 1e-5
+    st_ref, gs_ref, gh_ref = ref.evaluate(ref.soft_waveform(z.astype(np.float64), prob["temperature"]),
+                                          h.astype(np.complex128), prob)
+    _check_stats(c[0], st_ref, N, sched)
+    assert _rel(c[2], gh_ref) <= 1e-4
+
+
+def test_autotuner_picks_a_candidate(nat):
+    from paper_2604_25728_amd import tune
+    c = I.config("c2")
+    print("[gpu] autotuner", flush=True)
+    best, times = tune.tune([c["problem"]], c["opt"], steps=20)
+    assert best in tune.CANDIDATES and set(times) == set(tune.CANDIDATES)
+    assert times[best] == min(times.values()) and all(t > 0 for t in times.values())
+    print("tuned", best, times)

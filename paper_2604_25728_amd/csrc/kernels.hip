@@ -352,6 +352,11 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
   constexpr int E = G::E, TF = G::TF, EH = E / 2, SL = G::SLOTS;
   constexpr int UPB = kPassWaves * SL;  // units (Doppler bins of one row) per block
   __shared__ float2 lds[kPassWaves * G::LDS];
+  // Long transforms keep the accumulated adjoint spectra U in the wave's LDS
+  // slice instead of registers (three E-element arrays per lane do not fit
+  // two waves per SIMD at P >= 1024).
+  constexpr bool kUL = E >= 16;
+  __shared__ float2 ulds[kUL ? kPassWaves * P : 1];
   __shared__ float u_sig[UPB], u_S[UPB];
   __shared__ unsigned long long u_ka[UPB], u_kc[UPB];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, slot = lane / TF, t = lane % TF;
@@ -400,14 +405,16 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
   const float2* sw = a.self_w + pl.off_w + (int64_t)w * N;
   float2* cube = a.cube ? a.cube + pl.off_cube : nullptr;
   const int T2 = 2 * N - 1;
-  float2 X[E], U[E], R[E], SG[kKeepSG ? E : 1];
+  float2 X[E], U[kUL ? 1 : E], R[E], SG[kKeepSG ? E : 1];
+  float2* ub = ulds + (kUL ? wv * P : 0);
   {
     float2 ph[EH];
     phasor_row<EH, TF>(t, nu, invN, ph);
     static_for<E>([&](auto ec) {
       constexpr int e = decltype(ec)::value;
       R[e] = make_float2(0.f, 0.f);
-      U[e] = make_float2(0.f, 0.f);
+      if constexpr (kUL) ub[e * TF + t] = make_float2(0.f, 0.f);
+      else U[e] = make_float2(0.f, 0.f);
       if constexpr (e < EH) {
         const int n = t + TF * e;
         if (n < N) R[e] = cmul(sw[n], ph[e]);
@@ -443,14 +450,19 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
     if (op == OP_ADJ) {
       static_for<E>([&](auto ec) {
         constexpr int e = decltype(ec)::value;
-        if constexpr (kKeepSG) U[e] = cadd(U[e], cmul(R[e], SG[e]));
+        if constexpr (kUL) ub[e * TF + t] = cadd(ub[e * TF + t], cmul(R[e], sg[e * TF + t]));
+        else if constexpr (kKeepSG) U[e] = cadd(U[e], cmul(R[e], SG[e]));
         else U[e] = cadd(U[e], cmul(R[e], sg[e * TF + t]));
       });
       if (++g < M) {
         start_pair();
         op = OP_PAIR;
       } else {
-        static_for<E>([&](auto ec) { R[decltype(ec)::value] = U[decltype(ec)::value]; });
+        static_for<E>([&](auto ec) {
+          constexpr int e = decltype(ec)::value;
+          if constexpr (kUL) R[e] = ub[e * TF + t];
+          else R[e] = U[e];
+        });
         op = OP_UINV;
       }
       continue;
@@ -474,7 +486,11 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
       pow_ph<PHLOG>(c * c, phm1, cm1, cp);  // (c^2)^(p/2 - 1), (c^2)^(p/2)
       S *= cp;
       const float cpm1 = cm1 * c;  // c^(p-1)
-      static_for<E>([&](auto ec) { U[decltype(ec)::value] = cscale(U[decltype(ec)::value], cpm1); });
+      static_for<E>([&](auto ec) {
+        constexpr int e = decltype(ec)::value;
+        if constexpr (kUL) ub[e * TF + t] = cscale(ub[e * TF + t], cpm1);
+        else U[e] = cscale(U[e], cpm1);
+      });
       sigma = mu;
     }
     // a/sigma = x^(1/2), x = |r|^2 / sigma^2:  S += x^(p/2);  G~ = x^(p/2 - 1) r / sigma

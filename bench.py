@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 HBM_PEAK_GBPS = 8000.0            # MI355X published HBM3E bandwidth
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_split_c2_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_split_m4n256_traffic.md")
 COPY_BYTES = 1 << 28              # calibration copy of the counter runs: 256 MiB read, 256 MiB written
 
 
@@ -194,7 +194,7 @@ def main():
     from paper_2604_25728_amd import optim
 
     torch.cuda.set_device(0)
-    cfg = I.config("c2")
+    cfg = I.config("m4n256")
     prob, opt = cfg["problem"], cfg["opt"]
     log(f"device: {torch.cuda.get_device_name(0)}")
 
@@ -235,7 +235,7 @@ def main():
         del runb
         # the other workloads: one wide-span design, the network's design size
         # batched, and the uneven 64-design x 8-restart batch
-        for name, count in (("c4", 1), ("c5", 64)):
+        for name, count in (("wide_m8n1024", 1), ("m4n512", 64)):
             c = I.config(name)
             r = optim.SQNGD([c["problem"]] * count, c["opt"], seeds=list(range(count)))
             ms_c, _, _ = time_graph(r, 20, 10, 10)
@@ -243,12 +243,12 @@ def main():
                                           "shape": {k: c["problem"][k] for k in ("M", "N", "L", "F")}}
             log(f"{name} x{count}: step {ms_c * 1e3:.1f} us")
             del r
-        designs = I.c3_designs()
-        r = optim.SQNGD([p for p, _ in designs], I.config("c2")["opt"], seeds=[sd for _, sd in designs])
+        designs = I.uneven_designs()
+        r = optim.SQNGD([p for p, _ in designs], I.config("m4n256")["opt"], seeds=[sd for _, sd in designs])
         ms_c, _, _ = time_graph(r, 10, 10, 10)
-        extras["c3_uneven_512"] = {"ms_per_step": ms_c, "evals_per_s": 2.0 * len(designs) / (ms_c * 1e-3),
+        extras["uneven_64x8"] = {"ms_per_step": ms_c, "evals_per_s": 2.0 * len(designs) / (ms_c * 1e-3),
                                    "designs": 64, "restarts": 8}
-        log(f"c3 uneven x{len(designs)}: step {ms_c * 1e3:.1f} us")
+        log(f"uneven x{len(designs)}: step {ms_c * 1e3:.1f} us")
         del r
         n = 1 << 28
         a = torch.empty(n, dtype=torch.float32, device="cuda")

@@ -8,16 +8,19 @@ Workloads. The paper uses no dataset: its designs start from random phases
 (Algorithm 1, initialisation). The presets below are the five workloads this
 implementation is measured and checked on:
 
-  c1  M=2, N=64, L=4, F=33 over nu in [-0.5, 0.5], p=8, 200 iterations at
-      step 1e-2, temperature 1.0 (small enough for the oracle to run whole);
-  c2  M=4, N=256, L=8, F=129 over [-0.5, 0.5], p=16, SNRL target 0.5 dB,
-      temperature annealed 1.0 -> 0.05 over 2000 iterations, step 1e-2;
-  c3  64 designs with N in {128, 256, 512, 1024}, M in {2, 4, 8},
-      L in {4, 8, 16}, F=129, 8 random restarts each, c2's schedule;
-  c4  M=8, N=1024, L=16, F=257 over the wide span [-2.5, 2.5], p=16,
-      5000 iterations;
-  c5  M=4, N=512, L=8, F=129 over [-0.5, 0.5], p=16 (the warm-start
-      network's design size).
+  small_m2n64   M=2, N=64, L=4, F=33 over nu in [-0.5, 0.5], p=8, 200
+                iterations at step 1e-2, temperature 1.0 (small enough for
+                the oracle to run whole);
+  m4n256        M=4, N=256, L=8, F=129 over [-0.5, 0.5], p=16, SNRL target
+                0.5 dB, temperature annealed 1.0 -> 0.05 over 2000
+                iterations, step 1e-2;
+  uneven        (uneven_designs) 64 designs with N in {128, 256, 512, 1024},
+                M in {2, 4, 8}, L in {4, 8, 16}, F=129, 8 random restarts
+                each, the m4n256 schedule;
+  wide_m8n1024  M=8, N=1024, L=16, F=257 over the wide span [-2.5, 2.5],
+                p=16, 5000 iterations;
+  m4n512        M=4, N=512, L=8, F=129 over [-0.5, 0.5], p=16 (the
+                warm-start network's design size).
 
 Every delay is in the region of interest, SNRL target 0.5 dB, loss weights
 w_psl = w_snrl = 1, Adam with beta = (0.9, 0.999), eps = 1e-8 and one step A
@@ -59,13 +62,13 @@ def make_opt(lr_z: float = 1e-2, lr_h: float = 1e-2, beta1: float = 0.9, beta2: 
 
 
 CONFIGS = {
-    "c1": {"problem": make_problem(2, 64, 4, 33, p=8.0),
+    "m2n64": {"problem": make_problem(2, 64, 4, 33, p=8.0),
            "opt": make_opt(total_iters=200, T0=1.0, T1=1.0)},
-    "c2": {"problem": make_problem(4, 256, 8, 129, p=16.0),
+    "m4n256": {"problem": make_problem(4, 256, 8, 129, p=16.0),
            "opt": make_opt(total_iters=2000, T0=1.0, T1=0.05)},
-    "c4": {"problem": make_problem(8, 1024, 16, 257, nu_min=-2.5, nu_max=2.5, p=16.0),
+    "wide_m8n1024": {"problem": make_problem(8, 1024, 16, 257, nu_min=-2.5, nu_max=2.5, p=16.0),
            "opt": make_opt(total_iters=5000, T0=1.0, T1=0.05)},
-    "c5": {"problem": make_problem(4, 512, 8, 129, p=16.0),
+    "m4n512": {"problem": make_problem(4, 512, 8, 129, p=16.0),
            "opt": make_opt(total_iters=2000, T0=1.0, T1=0.05)},
 }
 
@@ -75,7 +78,7 @@ def config(name: str) -> dict:
     return copy.deepcopy(CONFIGS[name])
 
 
-def c3_designs(n_designs: int = 64, restarts: int = 8, draw_seed: int = 12345):
+def uneven_designs(n_designs: int = 64, restarts: int = 8, draw_seed: int = 12345):
     """The uneven batch: (problem, seed) for every design and restart. Shapes
     come from their own generator; restart r of design d uses seed 1000 d + r."""
     rng = np.random.default_rng(draw_seed)

@@ -199,7 +199,7 @@ def main():
     t.add_argument("--check-every", type=int, default=50)
     t.add_argument("--out", required=True)
     args = ap.parse_args()
-    cfg = I.config("c5")
+    cfg = I.config("m4n512")
     prob, opt = cfg["problem"], dict(cfg["opt"])
     if args.cmd == "generate":
         opt["total_iters"] = args.iters

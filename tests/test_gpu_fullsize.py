@@ -85,7 +85,7 @@ def _check(ref, nat, b, probs, zs, hs, rows_per_problem=4):
         assert _rel(b.unpack_z(gz, i).cpu().numpy(), gz_ref) <= 1e-4, i
 
 
-@pytest.mark.parametrize("name", ["c4", "c5"])
+@pytest.mark.parametrize("name", ["wide_m8n1024", "m4n512"])
 def test_single_design_full_size(ref, nat, name):
     prob = I.config(name)["problem"]
     M, N, L = prob["M"], prob["N"], prob["L"]
@@ -98,7 +98,7 @@ def test_single_design_full_size(ref, nat, name):
 
 def test_uneven_batch_slice(ref, nat):
     """Eight designs of the 64-design workload (first restart each) in one batch."""
-    designs = I.c3_designs(n_designs=8, restarts=1)
+    designs = I.uneven_designs(n_designs=8, restarts=1)
     probs = [p for p, _ in designs]
     print("[gpu] uneven batch " + ", ".join(f"M{p['M']}N{p['N']}L{p['L']}" for p in probs), flush=True)
     zs = [I.logits(p["M"], p["N"], p["L"], s) for p, s in designs]

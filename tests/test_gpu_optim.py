@@ -24,7 +24,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-@pytest.mark.parametrize("cfg,warm", [("c1", 3), ("c2", 2)])
+@pytest.mark.parametrize("cfg,warm", [("m2n64", 3), ("m4n256", 2)])
 def test_step_teacher_forced(ref, mods, cfg, warm):
     """From the GPU state at iteration t, one oracle iteration matches the GPU's."""
     nat, optim, _ = mods
@@ -52,12 +52,12 @@ def test_step_teacher_forced(ref, mods, cfg, warm):
 
 
 def test_c1_run_matches_oracle_where_margins_are_clear(ref, mods):
-    """The full 200-iteration c1 design: final hard indices equal the oracle's
+    """The full 200-iteration M=2 N=64 design: final hard indices equal the oracle's
     wherever the oracle's top-2 logit margin exceeds 1e-3; final PSL agrees."""
     nat, optim, _ = mods
-    c = I.config("c1")
+    c = I.config("m2n64")
     prob, opt = c["problem"], c["opt"]
-    print("[gpu] c1 full run", flush=True)
+    print("[gpu] M=2 N=64 full run", flush=True)
     run = optim.SQNGD([prob], opt, seeds=[0])
     run.run(opt["total_iters"], use_graph=True)
     torch.cuda.synchronize()
@@ -71,18 +71,18 @@ def test_c1_run_matches_oracle_where_margins_are_clear(ref, mods):
     got = run.hard_indices()[0]
     want = ref.hard_indices(z)
     agree = (got == want)[clear].mean()
-    print(f"c1 final: {clear.mean():.3f} of chips clear, agreement {agree:.4f}")
+    print(f"M=2 N=64 final: {clear.mean():.3f} of chips clear, agreement {agree:.4f}")
     assert agree >= 0.99
     st_gpu = run.hard_stats()[0]
     st_ref = ref.evaluate(ref.hard_waveform(z), h, prob, False)[0]
-    print("c1 final PSLR gpu", st_gpu["pslr_db"], "oracle", st_ref["pslr_db"])
+    print("final PSLR gpu", st_gpu["pslr_db"], "oracle", st_ref["pslr_db"])
     st0 = ref.evaluate(ref.hard_waveform(z0), ref.matched_init(z0), prob, False)[0]
     assert st_gpu["loss"] < st0["loss"]
 
 
 def test_graph_replay_matches_eager(mods):
     nat, optim, _ = mods
-    c = I.config("c2")
+    c = I.config("m4n256")
     print("[gpu] graph replay vs eager", flush=True)
     a = optim.SQNGD([c["problem"]], c["opt"], seeds=[1])
     b = optim.SQNGD([c["problem"]], c["opt"], seeds=[1])
@@ -99,7 +99,7 @@ def test_graph_replay_matches_eager(mods):
 
 def test_checkpoint_resume_bitwise(mods, tmp_path):
     nat, optim, _ = mods
-    c = I.config("c1")
+    c = I.config("m2n64")
     print("[gpu] checkpoint resume", flush=True)
     a = optim.SQNGD([c["problem"]], c["opt"], seeds=[2])
     a.run(5, use_graph=False)
@@ -115,7 +115,7 @@ def test_checkpoint_resume_bitwise(mods, tmp_path):
 
 def test_nonfinite_skips_update(mods):
     nat, optim, _ = mods
-    c = I.config("c1")
+    c = I.config("m2n64")
     print("[gpu] non-finite", flush=True)
     run = optim.SQNGD([c["problem"]], c["opt"], seeds=[3])
     run.z[5] = float("nan")   # chip (0, 1): its soft waveform, hence the step-B loss, is NaN
@@ -133,9 +133,9 @@ def test_nonfinite_skips_update(mods):
 def test_finite_differences_c2(mods):
     """Central differences (step 1e-3) of the FP32 loss on 32 random coordinates."""
     nat, _, _ = mods
-    prob = I.config("c2")["problem"]
+    prob = I.config("m4n256")["problem"]
     M, N, L = prob["M"], prob["N"], prob["L"]
-    print("[gpu] finite differences c2", flush=True)
+    print("[gpu] finite differences M=4 N=256", flush=True)
     b = nat.Batch([prob])
     z = b.pack_z([I.logits(M, N, L, 4)])
     h = b.pack_w([I.complex_gaussian(M, N, 5) * 0.9 + I.unimodular(M, N, 6)])
@@ -204,7 +204,7 @@ def test_chained_run_matches_oracle(ref, mods, n_h, n_x):
     inside the finalize kernel) against the oracle's iterations from the same
     start, for every combination of inner-step counts the chaining handles."""
     nat, optim, _ = mods
-    prob = I.config("c1")["problem"]
+    prob = I.config("m2n64")["problem"]
     opt = I.make_opt(n_h=n_h, n_x=n_x, total_iters=20, T0=1.0, T1=0.3)
     print(f"[gpu] chained run n_h={n_h} n_x={n_x}", flush=True)
     run = optim.SQNGD([prob], opt, seeds=[11])
@@ -228,7 +228,7 @@ def test_chained_run_matches_oracle(ref, mods, n_h, n_x):
 
 def test_chained_graph_matches_eager_run(mods):
     nat, optim, _ = mods
-    c = I.config("c2")
+    c = I.config("m4n256")
     print("[gpu] chained graph vs eager run", flush=True)
     a = optim.SQNGD([c["problem"]], c["opt"], seeds=[3])
     b = optim.SQNGD([c["problem"]], c["opt"], seeds=[3])

@@ -63,7 +63,7 @@ def _ref_waveform(R, prob, z, s, mode):
 
 
 SHAPES = {
-    "c1": I.config("c1")["problem"],
+    "m2n64": I.config("m2n64")["problem"],
     "ragged": I.make_problem(3, 100, 5, 7, nu_min=-1.3, nu_max=0.7, p=6.0, tau_lo=-40, tau_hi=30,
                              w_psl=0.8, w_snrl=1.7, temperature=0.6),
     "m1f1": I.make_problem(1, 64, 4, 1, nu_min=0.0, nu_max=0.0, p=8.0),
@@ -121,7 +121,7 @@ def test_backward_gradients(ref, nat, name, mode):
 
 
 def test_grad_loss_scaling_and_hard_mode(ref, nat):
-    prob = SHAPES["c1"]
+    prob = SHAPES["m2n64"]
     z, h, _ = _problem_inputs(prob, 7, 1)
     print("[gpu] grad_loss scaling / hard mode", flush=True)
     b = nat.Batch([prob])
@@ -135,7 +135,7 @@ def test_grad_loss_scaling_and_hard_mode(ref, nat):
 
 
 def test_hard_quantize_bit_exact(ref, nat):
-    probs = [I.config("c1")["problem"], I.make_problem(3, 300, 16, 4), I.make_problem(2, 1024, 64, 2)]
+    probs = [I.config("m2n64")["problem"], I.make_problem(3, 300, 16, 4), I.make_problem(2, 1024, 64, 2)]
     zs = [I.logits(p["M"], p["N"], p["L"], 11 + i) for i, p in enumerate(probs)]
     zs[0][0, 0, :] = 0.25        # full tie -> level 0
     zs[1][1, 7, [3, 9]] = 50.0   # two-way tie -> level 3
@@ -191,7 +191,7 @@ def test_latency_and_throughput_variants_agree(ref, nat):
     """A single small design runs the per-(bin, partner) variant of the fused
     pass; the same design inside a large batch runs the per-bin variant. Both
     must give the same statistics and gradients to FP32 rounding."""
-    prob = I.config("c2")["problem"]
+    prob = I.config("m4n256")["problem"]
     M, N, L = prob["M"], prob["N"], prob["L"]
     print("[gpu] split vs throughput variants", flush=True)
     zs = [I.logits(M, N, L, 30 + i) for i in range(8)]
@@ -214,7 +214,7 @@ def test_latency_and_throughput_variants_agree(ref, nat):
 def test_every_schedule_gives_the_same_results(ref, nat, sched):
     """Each fused-pass schedule hint (throughput variant, latency variant with
     8 / 12 / 16 waves per block) against the automatic choice and the oracle."""
-    prob = I.config("c2")["problem"]
+    prob = I.config("m4n256")["problem"]
     M, N, L = prob["M"], prob["N"], prob["L"]
     print(f"[gpu] schedule {sched}", flush=True)
     z, h = I.logits(M, N, L, 40), I.complex_gaussian(M, N, 41)
@@ -236,7 +236,7 @@ def test_every_schedule_gives_the_same_results(ref, nat, sched):
 
 def test_autotuner_picks_a_candidate(nat):
     from paper_2604_25728_amd import tune
-    c = I.config("c2")
+    c = I.config("m4n256")
     print("[gpu] autotuner", flush=True)
     best, times = tune.tune([c["problem"]], c["opt"], steps=20)
     assert best in tune.CANDIDATES and set(times) == set(tune.CANDIDATES)

@@ -388,8 +388,8 @@ def test_temperature_schedule(ref):
 
 
 def test_step_invariants_and_improvement(ref):
-    """Filters stay on the energy sphere (eq. 31-32); a short c1-sized run lowers the loss."""
-    cfg = I.config("c1")
+    """Filters stay on the energy sphere (eq. 31-32); a short M=2 N=64 run lowers the loss."""
+    cfg = I.config("m2n64")
     prob, opt = cfg["problem"], cfg["opt"]
     z = I.logits(prob["M"], prob["N"], prob["L"], 0).astype(np.float64)
     h = ref.matched_init(z)

@@ -352,11 +352,14 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
   constexpr int E = G::E, TF = G::TF, EH = E / 2, SL = G::SLOTS;
   constexpr int UPB = kPassWaves * SL;  // units (Doppler bins of one row) per block
   __shared__ float2 lds[kPassWaves * G::LDS];
-  // Long transforms keep the accumulated adjoint spectra U in the wave's LDS
-  // slice instead of registers (three E-element arrays per lane do not fit
-  // two waves per SIMD at P >= 1024).
-  constexpr bool kUL = E >= 16;
-  __shared__ float2 ulds[kUL ? kPassWaves * P : 1];
+  // The accumulated adjoint spectra U, and for P <= 512 the self spectrum X,
+  // live in the slot's LDS slice instead of registers: three E-element arrays
+  // per lane plus the partner spectrum would cap the occupancy (two waves per
+  // SIMD at P = 512, one at P >= 1024).
+  constexpr bool kUL = true;
+  constexpr bool kXL = P <= 512;
+  __shared__ float2 ulds[kPassWaves * SL * P];
+  __shared__ float2 xlds[kXL ? kPassWaves * SL * P : 1];
   __shared__ float u_sig[UPB], u_S[UPB];
   __shared__ unsigned long long u_ka[UPB], u_kc[UPB];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, slot = lane / TF, t = lane % TF;
@@ -400,13 +403,14 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
   // run as one loop over a single forward and a single inverse transform, so
   // the code each wave streams through the instruction cache stays small.
   enum Op { OP_SELF, OP_PAIR, OP_ADJ, OP_UINV };
-  constexpr bool kKeepSG = E <= 8;  // the partner spectrum stays in registers for both uses
+  constexpr bool kKeepSG = E <= 8 && !kXL;  // the partner spectrum stays in registers for both uses
   const float2* spec = a.spec + pl.ws_spec;
   const float2* sw = a.self_w + pl.off_w + (int64_t)w * N;
   float2* cube = a.cube ? a.cube + pl.off_cube : nullptr;
   const int T2 = 2 * N - 1;
-  float2 X[E], U[kUL ? 1 : E], R[E], SG[kKeepSG ? E : 1];
-  float2* ub = ulds + (kUL ? wv * P : 0);
+  float2 X[kXL ? 1 : E], U[kUL ? 1 : E], R[E], SG[kKeepSG ? E : 1];
+  float2* ub = ulds + (wv * SL + slot) * P;
+  float2* xb = xlds + (kXL ? (wv * SL + slot) * P : 0);
   {
     float2 ph[EH];
     phasor_row<EH, TF>(t, nu, invN, ph);
@@ -429,11 +433,12 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
     sg = spec + (int64_t)g * P;
     static_for<E>([&](auto ec) {
       constexpr int e = decltype(ec)::value;
+      const float2 xe = kXL ? xb[e * TF + t] : X[kXL ? 0 : e];
       if constexpr (kKeepSG) {
         SG[e] = sg[e * TF + t];
-        R[e] = cmulc(X[e], SG[e]);
+        R[e] = cmulc(xe, SG[e]);
       } else {
-        R[e] = cmulc(X[e], sg[e * TF + t]);
+        R[e] = cmulc(xe, sg[e * TF + t]);
       }
     });
   };
@@ -442,7 +447,11 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
     else fft_forward<P>(R, buf, t, W);
     if (op == OP_UINV) break;
     if (op == OP_SELF) {
-      static_for<E>([&](auto ec) { X[decltype(ec)::value] = R[decltype(ec)::value]; });
+      static_for<E>([&](auto ec) {
+        constexpr int e = decltype(ec)::value;
+        if constexpr (kXL) xb[e * TF + t] = R[e];
+        else X[e] = R[e];
+      });
       start_pair();
       op = OP_PAIR;
       continue;

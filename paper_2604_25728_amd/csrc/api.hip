@@ -202,7 +202,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
         upb = pl->group_wv[q.logP - kMinLogP] / p.M;
       } else {
         const int TF = q.P >= 512 ? 64 : q.P / 8;
-        upb = kPassWaves * (64 / TF);
+        upb = pass_waves(q.P) * (64 / TF);
       }
       q.wpr = (p.F + upb - 1) / upb;
     }
@@ -445,7 +445,7 @@ void launch_split(int P, int wv, const PassArgs& a, int phlog, int blocks, hipSt
 
 template <int P>
 void launch_pass_p(const PassArgs& a, int phlog, int waves, hipStream_t s) {
-  const dim3 block(64 * kPassWaves);
+  const dim3 block(64 * pass_waves(P));
   if (phlog == 3) hipLaunchKernelGGL((k_pass<P, 3>), dim3(waves), block, 0, s, a);
   else if (phlog == 2) hipLaunchKernelGGL((k_pass<P, 2>), dim3(waves), block, 0, s, a);
   else hipLaunchKernelGGL((k_pass<P, -1>), dim3(waves), block, 0, s, a);

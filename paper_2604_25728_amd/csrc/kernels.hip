@@ -344,11 +344,14 @@ struct PassArgs {
   ProbPlan one;
 };
 
-constexpr int kPassWaves = 4;  // waves per block of the fused pass
+// Waves per block of the throughput pass: four at P <= 512, two at longer
+// transforms (whose per-wave LDS slices would otherwise allow one block per CU).
+__host__ __device__ constexpr int pass_waves(int P) { return P >= 1024 ? 2 : 4; }
 
 template <int P, int PHLOG>
-__global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
+__global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
   using G = Geom<P>;
+  constexpr int kPassWaves = pass_waves(P);
   constexpr int E = G::E, TF = G::TF, EH = E / 2, SL = G::SLOTS;
   constexpr int UPB = kPassWaves * SL;  // units (Doppler bins of one row) per block
   __shared__ float2 lds[kPassWaves * G::LDS];
@@ -357,7 +360,7 @@ __global__ __launch_bounds__(64 * kPassWaves) void k_pass(PassArgs a) {
   // per lane plus the partner spectrum would cap the occupancy (two waves per
   // SIMD at P = 512, one at P >= 1024).
   constexpr bool kUL = true;
-  constexpr bool kXL = P <= 512;
+  constexpr bool kXL = P <= 1024;
   __shared__ float2 ulds[kPassWaves * SL * P];
   __shared__ float2 xlds[kXL ? kPassWaves * SL * P : 1];
   __shared__ float u_sig[UPB], u_S[UPB];

@@ -536,12 +536,22 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
       }
       continue;
     }
+    FinArgs af = a;
+    if (a.mode == FIN_STEP_A || a.mode == FIN_STEP_B) {
+      // gradient rows by the wide kernel first; k_final then skips the partial sums
+      af.grad_chunks = (1 << (g + kMinLogP)) / (2 * kGradChips);
+      af.grad_nprob = pl.hdr.group_n[g];
+      af.gprob = (const int32_t*)(w.base + pl.hdr.group_prob[g]);
+      hipLaunchKernelGGL(k_grad, dim3(pl.hdr.group_nrows[g] * af.grad_chunks + af.grad_nprob), dim3(kGradThreads),
+                         0, s, af);
+      af.grad_in = w.gbuf;
+    }
     switch (g) {
-      case 0: hipLaunchKernelGGL(k_final<128>, grid, block, 0, s, a); break;
-      case 1: hipLaunchKernelGGL(k_final<256>, grid, block, 0, s, a); break;
-      case 2: hipLaunchKernelGGL(k_final<512>, grid, block, 0, s, a); break;
-      case 3: hipLaunchKernelGGL(k_final<1024>, grid, block, 0, s, a); break;
-      default: hipLaunchKernelGGL(k_final<2048>, grid, block, 0, s, a); break;
+      case 0: hipLaunchKernelGGL(k_final<128>, grid, block, 0, s, af); break;
+      case 1: hipLaunchKernelGGL(k_final<256>, grid, block, 0, s, af); break;
+      case 2: hipLaunchKernelGGL(k_final<512>, grid, block, 0, s, af); break;
+      case 3: hipLaunchKernelGGL(k_final<1024>, grid, block, 0, s, af); break;
+      default: hipLaunchKernelGGL(k_final<2048>, grid, block, 0, s, af); break;
     }
   }
 }

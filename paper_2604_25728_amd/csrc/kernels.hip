@@ -659,6 +659,7 @@ struct FinArgs {
   int32_t* done;
   sqngd_opt opt;
   float2* gbuf;         // gradient rows (k_grad -> k_step)
+  const float2* grad_in;  // k_final: gradient rows already reduced by k_grad (skips the partial sums)
   int32_t* pflag;       // per problem: the loss is not finite (k_grad -> k_step)
   int32_t grad_chunks;  // k_grad blocks per row
   int32_t grad_nprob;   // problems of the launch (one statistics block each)
@@ -918,7 +919,7 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
   const int Nc = (N + 63) & ~63;
   const int FS = kFinThreads / Nc;
   const int nn = tid % Nc, fsi = tid / Nc;
-  const bool red = upd && fsi < FS && nn < N;
+  const bool red = upd && fsi < FS && nn < N && a.grad_in == nullptr;
   const float2* up = a.upart + pl.ws_upart + (int64_t)m * NE * N + nn;
   float2 v[kBatch];
 #pragma unroll
@@ -996,6 +997,14 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
   bool skip = true;
   if (upd) {
     // ---- 3. row gradient: sum_f (w_psl/(N P)) (sigma_u/lp_raw)^(p-1) partial_u + G'_S part_m
+    // (or the rows k_grad reduced already, SNRL term included)
+    if (a.grad_in != nullptr) {
+      const float gl = a.grad_loss ? a.grad_loss[pid] : 1.0f;
+      if (on) {
+        g = cscale(a.grad_in[wrow + n], gl);
+        gsh[n] = g;
+      }
+    } else {
     for (int j = tid; j < NE; j += kFinThreads)
       fac[j] = lp_raw > 0.f ? pl.w_psl / ((float)N * (float)pl.P) * pow_pm1(fac[j] / lp_raw, pl) : 0.f;
     __syncthreads();
@@ -1033,6 +1042,7 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
       for (int s = 0; s < FS; ++s) g = cadd(g, part[s * Nc + n]);
       g = cscale(cadd(g, cmul(gS, pw)), gl);
       gsh[n] = g;
+    }
     }
     const int rowbad = __syncthreads_or(on && (!isfinite(g.x) || !isfinite(g.y)));
     skip = bad || rowbad;

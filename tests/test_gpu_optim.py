@@ -239,3 +239,28 @@ def test_chained_graph_matches_eager_run(mods):
         torch.cuda.synchronize()
         assert torch.equal(a.z, b.z) and torch.equal(a.h, b.h), i
     assert a.t == b.t == 15
+
+
+@pytest.mark.parametrize("shape", [(2, 1024, 4, 3), (2, 300, 64, 5)])
+def test_fallback_finalize_steps_match_oracle(ref, mods, shape):
+    """Steps whose finalize runs in k_final (FFT length 2048, or more logit
+    levels per lane than the latency finalize holds) against the oracle."""
+    nat, optim, _ = mods
+    M, N, L, F = shape
+    prob = I.make_problem(M, N, L, F, p=16.0)
+    opt = I.make_opt(total_iters=10, T0=1.0, T1=0.5)
+    print(f"[gpu] fallback finalize M={M} N={N} L={L} F={F}", flush=True)
+    run = optim.SQNGD([prob], opt, seeds=[5])
+    s0 = run.numpy_state(0)
+    run.step(2)
+    torch.cuda.synchronize()
+    s1 = run.numpy_state(0)
+    z, h, state = s0["z"], s0["h"], s0["state"]
+    for t in range(2):
+        z, h, state, sta, stb = ref.step(prob, opt, z, h, state, t)
+    assert s1["t"] == 2
+    assert _rel(s1["h"], h) <= 1e-4, _rel(s1["h"], h)
+    assert _rel(s1["z"], z) <= 1e-4, _rel(s1["z"], z)
+    sa, sb = run.step_stats()
+    assert abs(sa[0]["loss"] - sta["loss"]) <= 1e-4 * sta["loss"]
+    assert abs(sb[0]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"]

@@ -264,3 +264,26 @@ def test_fallback_finalize_steps_match_oracle(ref, mods, shape):
     sa, sb = run.step_stats()
     assert abs(sa[0]["loss"] - sta["loss"]) <= 1e-4 * sta["loss"]
     assert abs(sb[0]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"]
+
+
+def test_mixed_batch_steps_match_oracle(ref, mods):
+    """One batch whose FFT-length groups finalize in different kernels (k_step
+    for the short ones, k_final for the length-2048 one), several problems per
+    group: every problem's two iterations against the oracle's."""
+    nat, optim, _ = mods
+    probs = [I.make_problem(2, 64, 4, 5, p=8.0), I.make_problem(3, 200, 8, 3, p=16.0),
+             I.make_problem(2, 1024, 4, 2, p=16.0), I.make_problem(2, 60, 8, 4, p=8.0, sq_mode=I.PHASOR_MEAN)]
+    opt = I.make_opt(total_iters=10, T0=1.0, T1=0.5)
+    print("[gpu] mixed batch steps", flush=True)
+    run = optim.SQNGD(probs, opt, seeds=[31, 32, 33, 34])
+    s0 = [run.numpy_state(i) for i in range(len(probs))]
+    run.step(2)
+    torch.cuda.synchronize()
+    assert run.t == 2
+    for i, prob in enumerate(probs):
+        s1 = run.numpy_state(i)
+        z, h, state = s0[i]["z"], s0[i]["h"], s0[i]["state"]
+        for t in range(2):
+            z, h, state, _, _ = ref.step(prob, opt, z, h, state, t)
+        assert _rel(s1["h"], h) <= 1e-4, (i, _rel(s1["h"], h))
+        assert _rel(s1["z"], z) <= 1e-4, (i, _rel(s1["z"], z))

@@ -57,6 +57,15 @@ def cond_of(prob: dict):
     return (prob["L"] / 8.0, prob["nu_max"] - prob["nu_min"])
 
 
+PARAMS_M4N512 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warmstart_m4n512.npy")
+
+
+def trained_params(path: str = PARAMS_M4N512) -> np.ndarray:
+    """Parameters of the network trained on converged M=4 N=512 L=8 F=129 runs
+    (written by `train-eval --save-params`), float32."""
+    return np.load(path, allow_pickle=False)
+
+
 def generate(prob: dict, opt: dict, seeds, batch: int, iters: int) -> dict:
     """Converged runs from the paired starts: hard indices and final stats."""
     M, N, L = prob["M"], prob["N"], prob["L"]
@@ -198,6 +207,7 @@ def main():
     t.add_argument("--iters", type=int, default=2000)
     t.add_argument("--check-every", type=int, default=50)
     t.add_argument("--out", required=True)
+    t.add_argument("--save-params", default=None, help="write the trained parameters (.npy, float32)")
     args = ap.parse_args()
     cfg = I.config("m4n512")
     prob, opt = cfg["problem"], dict(cfg["opt"])
@@ -211,6 +221,8 @@ def main():
     data = {k: d[k] for k in d.files}
     opt["total_iters"] = args.iters
     net, hist = train(prob, data, args.epochs, args.batch, args.lr)
+    if args.save_params:
+        np.save(args.save_params, net.params.cpu().numpy().astype(np.float32), allow_pickle=False)
     res = time_to_target(prob, opt, net.params, range(args.eval_seeds), args.iters, args.check_every)
     res["train_loss"] = hist
     res["train_runs"] = int(len(data["seeds"]))

@@ -43,3 +43,18 @@ def test_pipeline_small(WS):
         # the random arm reaches its own final PSL by the last checkpoint at the latest
         assert p["random_iters"] is not None and p["random_iters"] <= 40
         assert p["warm_iters"] is None or p["warm_iters"] <= 40
+
+
+def test_trained_network_reaches_the_random_start_target_sooner(WS):
+    """What the trained network gains over the method without it, at the size it
+    was trained for (M=4 N=512 L=8 F=129, 2000 iterations): on 32 held-out seeds
+    the warm start reaches the random start's final hard PSL (SNRL within the
+    same bound) on most seeds, in far fewer iterations."""
+    prob, opt = I.config("m4n512")["problem"], I.config("m4n512")["opt"]
+    params = torch.tensor(WS.trained_params(), device="cuda")
+    print("[gpu] warm start A/B on 32 held-out seeds", flush=True)
+    res = WS.time_to_target(prob, opt, params, range(32), iters=opt["total_iters"], check_every=50)
+    print({k: v for k, v in res.items() if k != "per_seed"})
+    assert res["fraction_reached"] >= 0.8
+    assert res["median_ratio_iters"] <= 0.5
+    assert res["median_warm_final_psl_db"] <= res["median_target_psl_db"]

@@ -242,3 +242,39 @@ def test_autotuner_picks_a_candidate(nat):
     assert best in tune.CANDIDATES and set(times) == set(tune.CANDIDATES)
     assert times[best] == min(times.values()) and all(t > 0 for t in times.values())
     print("tuned", best, times)
+
+
+EDGE = {
+    # the largest shapes the limits allow in M, N and L (FFT length 2048), two Doppler bins
+    "max_m16_n1024_l64": I.make_problem(16, 1024, 64, 2, nu_min=-0.25, nu_max=0.25, p=16.0),
+    # the shortest sequences
+    "n2": I.make_problem(2, 2, 2, 3, p=8.0),
+    # a region of interest that holds only tau = 0: auto pairs contribute nothing, cross pairs their zero lag
+    "tau0_only": I.make_problem(3, 40, 4, 5, p=8.0, tau_lo=0, tau_hi=0),
+    # one waveform, one Doppler bin, tau window on one side
+    "m1_onesided": I.make_problem(1, 77, 4, 1, nu_min=0.2, nu_max=0.2, p=4.0, tau_lo=3, tau_hi=60),
+}
+
+
+@pytest.mark.parametrize("name", list(EDGE))
+def test_edge_shapes(ref, nat, name):
+    prob = EDGE[name]
+    M, N, L = prob["M"], prob["N"], prob["L"]
+    print(f"[gpu] edge {name}", flush=True)
+    z, h, _ = _problem_inputs(prob, 13, 0)
+    b = nat.Batch([prob])
+    zt, ht = b.pack_z([z]), b.pack_w([h])
+    stats = b.new_stats()
+    gz, gh, gs = b.af_backward(zt, ht, nat.WAVE_SOFT, want_s=True, stats=stats)
+    torch.cuda.synchronize()
+    st = nat.decode_stats(stats.cpu().numpy())[0]
+    s = ref.soft_waveform(z.astype(np.float64), prob["temperature"])
+    st_ref, gs_ref, gh_ref = ref.evaluate(s, h.astype(np.complex128), prob)
+    assert abs(st["loss"] - st_ref["loss"]) <= 1e-4 * abs(st_ref["loss"]) + 1e-12, (st, st_ref)
+    assert abs(st["lp"] - st_ref["lp"]) <= 1e-4 * st_ref["lp"] + 1e-12
+    for k in ("psl_auto", "psl_cross"):
+        if st_ref[k] > 0:
+            assert abs(_db(st[k]) - _db(st_ref[k])) <= 0.05, (k, st[k], st_ref[k])
+        else:
+            assert st[k] == 0.0, (k, st[k])
+    assert _rel(gs.cpu().numpy(), gs_ref) <= 1e-4 and _rel(gh.cpu().numpy(), gh_ref) <= 1e-4

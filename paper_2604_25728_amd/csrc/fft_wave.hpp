@@ -234,6 +234,17 @@ struct WaveTwiddles {
       col[7] = cmul(col[4], col[3]);
     }
   }
+  // The same twiddles read from a table tab[k] = W_P^k, k < P (a block
+  // computes the table once instead of every wave its own sincospi values).
+  __device__ __forceinline__ void init_table(int t, const float2* tab) {
+    lo[0] = make_float2(1.f, 0.f);
+    for (int b = 1; b < NLO; ++b) lo[b] = tab[(t * b) & (P - 1)];
+    hi[0] = make_float2(1.f, 0.f);
+    for (int a = 1; a < NHI; ++a) hi[a] = tab[(t * NLO * a) & (P - 1)];
+    const int beta = t % G::B;
+    col[0] = make_float2(1.f, 0.f);
+    for (int g = 1; g < G::A; ++g) col[g] = tab[(g * beta * G::E) & (P - 1)];
+  }
   template <int K1>
   __device__ __forceinline__ float2 step2(float2 v, bool inverse) const {
     constexpr int b = K1 % NLO, a = K1 / NLO;

@@ -1765,6 +1765,10 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   static_assert(G::TF == 64, "one FFT per wave");
   constexpr int E = G::E, EH = E / 2;
   __shared__ float2 lds[WV * P];
+  // tables the block computes once: W_P^k, and per unit exp(j 2 pi t nu / N)
+  // for t < 64 with the step t = 64 in the last column
+  __shared__ float2 tw_tab[P];
+  __shared__ float2 ph_tab[WV][65];
   __shared__ float g_sig[WV], g_S[WV];
   __shared__ unsigned long long g_ka[WV], g_kc[WV];
   __shared__ float u_sig[WV], u_S[WV];
@@ -1812,11 +1816,27 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
       if (n < N) X[e] = sw[n];
     }
   });
+  for (int i = threadIdx.x; i < P; i += 64 * WV) tw_tab[i] = tw_exact<P>(i);
+  for (int i = threadIdx.x; i < UB * 65; i += 64 * WV) {
+    const int jj = i / 65, tt = i - jj * 65;
+    const int fj = min(grp * UB + jj, F - 1);
+    const float nuj = (a.orient ? -1.0f : 1.0f) * (pl.nu_min + (float)fj * pl.dnu);
+    ph_tab[jj][tt] = phasor(tt, nuj, invN);
+  }
+  __syncthreads();
   WaveTwiddles<P> W;
-  W.init(t);
+  W.init_table(t, tw_tab);
+  auto phasor_row_tab = [&](float2 (&ph)[EH]) {
+    ph[0] = ph_tab[wave_on ? j : 0][t];
+    const float2 st = ph_tab[wave_on ? j : 0][64];
+    static_for<EH - 1>([&](auto ec) {
+      constexpr int e = decltype(ec)::value + 1;
+      ph[e] = cmul(ph[e - 1], st);
+    });
+  };
   {
     float2 ph[EH];
-    phasor_row<EH, 64>(t, nu, invN, ph);
+    phasor_row_tab(ph);
     static_for<EH>([&](auto ec) {
       constexpr int e = decltype(ec)::value;
       X[e] = cmul(X[e], ph[e]);
@@ -1899,7 +1919,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
     if (grad) {
       fft_inverse<P>(U, buf, t, W);
       float2 ph[EH];
-      phasor_row<EH, 64>(t, nu, invN, ph);
+      phasor_row_tab(ph);
       wave_lds_sync();
       static_for<EH>([&](auto ec) {
         constexpr int e = decltype(ec)::value;

@@ -58,6 +58,18 @@ def cube_cells(prob: dict) -> int:
     return prob["M"] ** 2 * prob["F"] * (2 * prob["N"] - 1)
 
 
+# Cube-equivalent bytes of one evaluation: what a pipeline that materialises
+# the AF cube would move per cell (complex64 A written and read back for the
+# loss, complex64 adjoint G written and read back for the gradient).
+CUBE_BYTES_PER_CELL = 32
+
+
+def cube_frac(cells: int, evals_per_cell_set: float, ms: float) -> float:
+    """Cube-equivalent bandwidth of `evals_per_cell_set` evaluations of
+    `cells` cells in `ms` milliseconds, as a fraction of the HBM peak."""
+    return CUBE_BYTES_PER_CELL * cells * evals_per_cell_set / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS
+
+
 def time_graph(run, steps: int, warmup: int, per_graph: int):
     """ms per outer iteration over `steps` iterations run as graph replays of
     `per_graph` iterations each (steps is rounded up to a multiple)."""
@@ -219,7 +231,8 @@ def main():
     achieved = flops / (kd_avg_ms * 1e-3) / 1e12
     log(f"fused pass: {kd.size} launches, mean {kd_avg_ms * 1e3:.2f} us, "
         f"{achieved:.2f} TFLOP/s algorithmic")
-    cube_gbps = 16.0 * cube_cells(prob) / (kd_avg_ms * 1e-3) / 1e9
+    cube_gbps = CUBE_BYTES_PER_CELL * cube_cells(prob) / (kd_avg_ms * 1e-3) / 1e9
+    cube_step_gbps = 2 * CUBE_BYTES_PER_CELL * cube_cells(prob) / (ms_step * 1e-3) / 1e9
 
     extras = {}
     if not args.no_extras:
@@ -229,6 +242,7 @@ def main():
         kdb = kernel_durations(runb, nat, 20)
         extras["batched_restarts"] = {
             "designs": R, "ms_per_step": msb, "evals_per_s": 2.0 * R / (msb * 1e-3),
+            "cube_equiv_frac_of_hbm": cube_frac(R * cube_cells(prob), 2, msb),
             "pass_kernel_us": float(kdb.mean() * 1e3),
             "pass_tflops": R * flops / (kdb.mean() * 1e-3) / 1e12}
         log(f"batched x{R}: step {msb * 1e3:.1f} us, {extras['batched_restarts']['evals_per_s']:.0f} evals/s")
@@ -240,6 +254,8 @@ def main():
             r = optim.SQNGD([c["problem"]] * count, c["opt"], seeds=list(range(count)))
             ms_c, _, _ = time_graph(r, 20, 10, 10)
             extras[f"{name}_x{count}"] = {"ms_per_step": ms_c, "evals_per_s": 2.0 * count / (ms_c * 1e-3),
+                                          "cube_equiv_frac_of_hbm": cube_frac(count * cube_cells(c["problem"]),
+                                                                              2, ms_c),
                                           "shape": {k: c["problem"][k] for k in ("M", "N", "L", "F")}}
             log(f"{name} x{count}: step {ms_c * 1e3:.1f} us")
             del r
@@ -247,6 +263,8 @@ def main():
         r = optim.SQNGD([p for p, _ in designs], I.config("m4n256")["opt"], seeds=[sd for _, sd in designs])
         ms_c, _, _ = time_graph(r, 10, 10, 10)
         extras["uneven_64x8"] = {"ms_per_step": ms_c, "evals_per_s": 2.0 * len(designs) / (ms_c * 1e-3),
+                                   "cube_equiv_frac_of_hbm": cube_frac(sum(cube_cells(p) for p, _ in designs),
+                                                                       2, ms_c),
                                    "designs": 64, "restarts": 8}
         log(f"uneven x{len(designs)}: step {ms_c * 1e3:.1f} us")
         del r
@@ -288,7 +306,8 @@ def main():
                      "kernel_us": kd_avg_ms * 1e3, "flops_per_launch": flops,
                      "traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT) if traffic else None},
         "cube_equivalent": {"GBps": cube_gbps, "frac_of_hbm": cube_gbps / HBM_PEAK_GBPS,
-                            "bytes_per_launch": 16 * cube_cells(prob)},
+                            "bytes_per_eval": CUBE_BYTES_PER_CELL * cube_cells(prob),
+                            "step_GBps": cube_step_gbps, "step_frac_of_hbm": cube_step_gbps / HBM_PEAK_GBPS},
     }
     if extras:
         out["extras"] = extras

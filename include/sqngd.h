@@ -107,8 +107,7 @@ extern "C" {
 #define SQNGD_SQ_PHASOR_MEAN 1
 
 /* sqngd_opt.flags */
-#define SQNGD_OPT_SGD 1      /* plain gradient descent instead of Adam       */
-#define SQNGD_OPT_FREEZE_H 2 /* skip step A: filters stay fixed (SQNAF mode) */
+#define SQNGD_OPT_SGD 1 /* plain gradient descent instead of Adam (fixed filters: n_h = 0) */
 
 /* floats of Adam state per problem: first and second moments of z (2*M*N*L)
    and of (Re h, Im h) (4*M*N) */

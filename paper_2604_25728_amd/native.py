@@ -180,15 +180,17 @@ class Batch:
         check(self.lib.sqngd_workspace_init(self._arr, self.n, self._ws_ptr, self.ws_bytes,
                                             _stream()), "workspace_init")
         # element offsets of each problem in the packed buffers
-        self.off_z, self.off_w, self.off_cube = [], [], []
-        oz = ow = oc = 0
+        self.off_z, self.off_w, self.off_cube, self.off_adam = [], [], [], []
+        oz = ow = oc = oa = 0
         for p in self.probs:
             self.off_z.append(oz)
             self.off_w.append(ow)
             self.off_cube.append(oc)
+            self.off_adam.append(oa)
             oz += p["M"] * p["N"] * p["L"]
             ow += p["M"] * p["N"]
             oc += p["M"] * p["M"] * p["F"] * (2 * p["N"] - 1)
+            oa += 2 * p["M"] * p["N"] * p["L"] + 4 * p["M"] * p["N"]
 
     # -------------------------------------------------------------- packing
     def pack_z(self, zs):
@@ -209,6 +211,11 @@ class Batch:
         p = self.probs[i]
         return t[self.off_z[i]: self.off_z[i] + p["M"] * p["N"] * p["L"]].reshape(
             p["M"], p["N"], p["L"])
+
+    def unpack_adam(self, t, i):
+        """Problem i's Adam state (flat: m_z, v_z, m_h, v_h as in SQNGD_ADAM_FLOATS)."""
+        p = self.probs[i]
+        return t[self.off_adam[i]: self.off_adam[i] + 2 * p["M"] * p["N"] * p["L"] + 4 * p["M"] * p["N"]]
 
     def unpack_cube(self, t, i):
         p = self.probs[i]

@@ -88,6 +88,26 @@ class SQNGD:
         if iters % iters_per_graph:
             self.step(iters % iters_per_graph)
 
+    def subset(self, keep) -> "SQNGD":
+        """A new driver over the problems `keep` (indices into this batch) that
+        continues from their current state: logits, filters, Adam moments and
+        the shared iteration counter t (so the temperature schedule goes on)."""
+        keep = [int(i) for i in keep]
+        new = SQNGD.__new__(SQNGD)
+        new.schedule = self.schedule
+        new.batch = nat.Batch([self.probs[i] for i in keep], device=self.batch.device)
+        new.probs = new.batch.probs
+        new.opt_dict = dict(self.opt_dict)
+        new.opt = nat.make_opt(self.opt_dict)
+        new.z = torch.cat([self.batch.unpack_z(self.z, i).reshape(-1) for i in keep])
+        new.h = torch.cat([self.batch.unpack_w(self.h, i).reshape(-1) for i in keep])
+        new.adam = torch.cat([self.batch.unpack_adam(self.adam, i) for i in keep])
+        new.counter = self.counter.clone()
+        new.stats = new.batch.new_stats(2 * new.batch.n)
+        new.graph = None
+        new.graph_iters = 0
+        return new
+
     # ------------------------------------------------------------- inspection
     @property
     def t(self) -> int:
@@ -128,13 +148,94 @@ class SQNGD:
         M, N, L = p["M"], p["N"], p["L"]
         z = self.batch.unpack_z(self.z, i).cpu().numpy().astype(np.float64)
         h = self.batch.unpack_w(self.h, i).cpu().numpy().astype(np.complex128)
-        off = 0
-        for j in range(i):
-            q = self.probs[j]
-            off += 2 * q["M"] * q["N"] * q["L"] + 4 * q["M"] * q["N"]
-        a = self.adam[off: off + 2 * M * N * L + 4 * M * N].cpu().numpy().astype(np.float64)
+        a = self.batch.unpack_adam(self.adam, i).cpu().numpy().astype(np.float64)
         mnl = M * N * L
         state = {"mz": a[:mnl].reshape(M, N, L), "vz": a[mnl:2 * mnl].reshape(M, N, L),
                  "mh": a[2 * mnl: 2 * mnl + 2 * M * N].reshape(M, N, 2),
                  "vh": a[2 * mnl + 2 * M * N:].reshape(M, N, 2)}
         return {"z": z, "h": h, "state": state, "t": self.t}
+
+
+class StopRule:
+    """The stopping criterion of Algorithm 1, per design.
+
+    The paper ends a run when lowering the loss no longer improves the WPSL of
+    the hard-quantised design, or after T outer iterations. Read here as: at
+    every checkpoint the hard WPSL (dB) is compared with the best seen so far;
+    a checkpoint that does not lower it by more than `min_gain_db` counts as a
+    stall, and a design stops after `patience` consecutive stalls."""
+
+    def __init__(self, n: int, patience: int = 4, min_gain_db: float = 0.0):
+        if patience < 1:
+            raise ValueError("patience must be >= 1")
+        self.patience = int(patience)
+        self.min_gain_db = float(min_gain_db)
+        self.best = np.full(n, np.inf)
+        self.stall = np.zeros(n, dtype=np.int64)
+        self.stopped = np.zeros(n, dtype=bool)
+
+    def update(self, ids, wpsl_db) -> list:
+        """Record the checkpoint WPSL of the running designs `ids`; returns the
+        ids that stop at this checkpoint."""
+        out = []
+        for i, w in zip(ids, wpsl_db):
+            if self.stopped[i]:
+                raise ValueError(f"design {i} has already stopped")
+            if w < self.best[i] - self.min_gain_db:
+                self.best[i] = w
+                self.stall[i] = 0
+            else:
+                self.stall[i] += 1
+                if self.stall[i] >= self.patience:
+                    self.stopped[i] = True
+                    out.append(int(i))
+        return out
+
+
+def optimise(probs, opt: dict, seeds=None, z0=None, max_iters: int | None = None, check_every: int = 50,
+             patience: int = 4, min_gain_db: float = 0.0, iters_per_graph: int = 10, schedule=None) -> dict:
+    """Algorithm 1 for a batch of designs, with its stopping criterion.
+
+    Every `check_every` outer iterations the hard-quantised WPSL of each running
+    design is measured (one forward evaluation of the batch) and fed to a
+    StopRule; a design that stops keeps the state it has at that checkpoint,
+    and the running designs continue as a smaller batch (SQNGD.subset), so
+    stopped designs cost nothing further. Returns, per design, the iteration at
+    which it stopped (max_iters if it never did), its hard phase indices,
+    filters, logits, final hard statistics and its WPSL history."""
+    max_iters = int(opt["total_iters"] if max_iters is None else max_iters)
+    run = SQNGD(probs, opt, seeds=seeds, z0=z0, schedule=schedule)
+    n = run.batch.n
+    rule = StopRule(n, patience, min_gain_db)
+    ids = list(range(n))  # original index of each problem of `run`
+    res = [None] * n
+    hist = [[] for _ in range(n)]
+    it = 0
+    while ids:
+        k = min(check_every, max_iters - it)
+        if k > 0:
+            run.run(k, use_graph=True, iters_per_graph=min(iters_per_graph, k))
+            it += k
+        sts = run.hard_stats()
+        for j, st in enumerate(sts):
+            hist[ids[j]].append(st["pslr_db"])
+        stopping = set(rule.update(ids, [st["pslr_db"] for st in sts]))
+        if it >= max_iters:
+            stopping = set(ids)
+        if not stopping:
+            continue
+        idx_all = run.hard_indices()
+        keep = []
+        for j, i in enumerate(ids):
+            if i in stopping:
+                res[i] = {"stop_iter": it, "stats": sts[j], "idx": idx_all[j],
+                          "h": run.batch.unpack_w(run.h, j).cpu().numpy(),
+                          "z": run.batch.unpack_z(run.z, j).cpu().numpy()}
+            else:
+                keep.append(j)
+        if keep:
+            run = run.subset(keep)
+        ids = [ids[j] for j in keep]
+    for i in range(n):
+        res[i]["wpsl_db_history"] = hist[i]
+    return {"designs": res, "check_every": check_every, "patience": patience, "max_iters": max_iters}

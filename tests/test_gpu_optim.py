@@ -287,3 +287,58 @@ def test_mixed_batch_steps_match_oracle(ref, mods):
             z, h, state, _, _ = ref.step(prob, opt, z, h, state, t)
         assert _rel(s1["h"], h) <= 1e-4, (i, _rel(s1["h"], h))
         assert _rel(s1["z"], z) <= 1e-4, (i, _rel(s1["z"], z))
+
+
+def test_subset_continues_bitwise(mods):
+    """A sub-batch built from a running batch continues exactly as the batch
+    does when both make the same calls (a call's first evaluation is prepared
+    by k_prep, later ones by the finalize kernel, whose sums run in another
+    order, so only equal call structures are bitwise comparable)."""
+    nat, optim, _ = mods
+    c = I.config("m2n64")
+    print("[gpu] subset continuation", flush=True)
+    a = optim.SQNGD([c["problem"]] * 3, c["opt"], seeds=[5, 6, 7], schedule=nat.SCHED_THROUGHPUT)
+    a.run(6, use_graph=False)
+    sub = a.subset([0, 2])
+    a.run(6, use_graph=False)
+    sub.run(6, use_graph=False)
+    torch.cuda.synchronize()
+    assert sub.t == a.t == 12
+    for j, i in enumerate([0, 2]):
+        assert torch.equal(sub.batch.unpack_z(sub.z, j), a.batch.unpack_z(a.z, i)), i
+        assert torch.equal(sub.batch.unpack_w(sub.h, j), a.batch.unpack_w(a.h, i)), i
+        assert torch.equal(sub.batch.unpack_adam(sub.adam, j), a.batch.unpack_adam(a.adam, i)), i
+
+
+def test_stopping_rule_run(ref, mods):
+    """optimise() with the stopping rule: each design stops where its own WPSL
+    history says, its returned state is the state a plain run reaches at that
+    iteration, and its hard statistics match the oracle's."""
+    nat, optim, _ = mods
+    c = I.config("m2n64")
+    prob, opt = c["problem"], c["opt"]
+    seeds = [11, 12, 13, 14]
+    print("[gpu] stopping rule, 4 designs M=2 N=64", flush=True)
+    res = optim.optimise([prob] * 4, opt, seeds=seeds, max_iters=120, check_every=10, patience=1,
+                         min_gain_db=1.0, schedule=nat.SCHED_THROUGHPUT)
+    stops = [d["stop_iter"] for d in res["designs"]]
+    print("stop iterations", stops)
+    assert any(s < 120 for s in stops)
+    for i, d in enumerate(res["designs"]):
+        hist = d["wpsl_db_history"]
+        assert len(hist) == -(-d["stop_iter"] // 10)
+        rule = optim.StopRule(1, patience=1, min_gain_db=1.0)
+        fired = [bool(rule.update([0], [w])) for w in hist]
+        assert fired[-1] or d["stop_iter"] == 120
+        assert not any(fired[:-1])
+        assert d["stats"]["pslr_db"] == hist[-1]
+        # the same design alone, run for the same number of iterations
+        plain = optim.SQNGD([prob], opt, seeds=[seeds[i]], schedule=nat.SCHED_THROUGHPUT)
+        plain.run(d["stop_iter"], use_graph=False)
+        torch.cuda.synchronize()
+        assert np.array_equal(plain.batch.unpack_z(plain.z, 0).cpu().numpy(), d["z"]), i
+        assert np.array_equal(plain.batch.unpack_w(plain.h, 0).cpu().numpy(), d["h"]), i
+        assert np.array_equal(d["idx"], ref.hard_indices(d["z"].astype(np.float64)))
+        st = ref.evaluate(ref.hard_waveform(d["z"].astype(np.float64)), d["h"].astype(np.complex128),
+                          prob, False)[0]
+        assert abs(d["stats"]["pslr_db"] - st["pslr_db"]) <= 0.05

@@ -45,6 +45,10 @@ constexpr int kSplitShapes1024[] = {8};
 constexpr int kMaxSplitWaves = 16;
 constexpr double kSplitMaxWaves = 8192.0;
 constexpr int kNumCUs = 256;  // MI355X compute units: one block per CU is the aim
+// the gradient reduction moves into k_step for groups of at least this many
+// rows, or whose rows hold at most this many bytes of Doppler partials
+constexpr int kFuseRows = kNumCUs / 2;
+constexpr int64_t kFuseRowBytes = 16384;
 
 // Waves per split block for the problems of one FFT length: the compiled
 // shape minimising (rounds of kNumCUs blocks) x (waves per block), i.e. the
@@ -114,6 +118,7 @@ struct Plan {
   // finalize of the optimiser steps: 0 = k_final, else k_step with this
   // bound on the logit levels per lane
   int group_step[kNumPGroups];
+  bool group_fuse[kNumPGroups];  // k_step reduces the gradient rows itself (no k_grad launch)
   bool all_step = true;  // every group runs k_step: the step counter advances in the next pass
   int maxN = 0;
   bool split = false;  // the fused pass runs as k_pass_split (small batches)
@@ -257,6 +262,20 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
       if (P > 2 * kStepThreads) mode = 0;
       pl->group_step[g] = mode;
       if (!gprob[g].empty() && mode == 0) pl->all_step = false;
+      // k_step reduces the rows' Doppler partials itself when that takes at
+      // most two load rounds per lane and either the rows alone fill half the
+      // chip or a row's partials are small (one block reading a large row is
+      // slower than k_grad's many blocks reading it together)
+      int ne = 0, nr = 0;
+      int64_t row_bytes = 0;
+      for (int id : gprob[g]) {
+        const ProbPlan& q = pl->plans[id];
+        ne = std::max(ne, q.wpr);
+        nr += q.M;
+        row_bytes = std::max(row_bytes, (int64_t)8 * q.wpr * q.N);
+      }
+      pl->group_fuse[g] = mode != 0 && ne <= 2 * step_tpc(P) * step_fg_loads(P) &&
+                          (nr >= kFuseRows || row_bytes <= kFuseRowBytes);
     }
     H.group_prob[g] = (int64_t)off;
     off = align_up(off + 4 * gprob[g].size());
@@ -490,16 +509,21 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
   }
 }
 
-template <int P>
-void launch_step_p(const FinArgs& a, int lv, dim3 grid, hipStream_t s) {
+template <int P, bool FG>
+void launch_step_pf(const FinArgs& a, int lv, dim3 grid, hipStream_t s) {
   const dim3 block(kStepThreads);
   if (a.mode == FIN_STEP_A) {
-    if (lv == 4) hipLaunchKernelGGL((k_step<P, FIN_STEP_A, 4>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_step<P, FIN_STEP_A, 16>), grid, block, 0, s, a);
+    if (lv == 4) hipLaunchKernelGGL((k_step<P, FIN_STEP_A, 4, FG>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step<P, FIN_STEP_A, 16, FG>), grid, block, 0, s, a);
   } else {
-    if (lv == 4) hipLaunchKernelGGL((k_step<P, FIN_STEP_B, 4>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_step<P, FIN_STEP_B, 16>), grid, block, 0, s, a);
+    if (lv == 4) hipLaunchKernelGGL((k_step<P, FIN_STEP_B, 4, FG>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step<P, FIN_STEP_B, 16, FG>), grid, block, 0, s, a);
   }
+}
+template <int P>
+void launch_step_p(const FinArgs& a, int lv, bool fuse, dim3 grid, hipStream_t s) {
+  if (fuse) launch_step_pf<P, true>(a, lv, grid, s);
+  else launch_step_pf<P, false>(a, lv, grid, s);
 }
 
 void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
@@ -522,17 +546,20 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
     const dim3 grid(pl.hdr.group_nrows[g]), block(kFinThreads);
     if ((a.mode == FIN_STEP_A || a.mode == FIN_STEP_B) && pl.group_step[g] != 0) {
       const int lv = pl.group_step[g];
-      // gradient rows: N <= P/2 chips per row in blocks of kGradChips
-      a.grad_chunks = (1 << (g + kMinLogP)) / (2 * kGradChips);
-      a.grad_nprob = pl.hdr.group_n[g];
-      a.gprob = (const int32_t*)(w.base + pl.hdr.group_prob[g]);
-      hipLaunchKernelGGL(k_grad, dim3(pl.hdr.group_nrows[g] * a.grad_chunks + a.grad_nprob), dim3(kGradThreads), 0,
-                         s, a);
+      const bool fuse = pl.group_fuse[g];
+      if (!fuse) {
+        // gradient rows: N <= P/2 chips per row in blocks of kGradChips
+        a.grad_chunks = (1 << (g + kMinLogP)) / (2 * kGradChips);
+        a.grad_nprob = pl.hdr.group_n[g];
+        a.gprob = (const int32_t*)(w.base + pl.hdr.group_prob[g]);
+        hipLaunchKernelGGL(k_grad, dim3(pl.hdr.group_nrows[g] * a.grad_chunks + a.grad_nprob), dim3(kGradThreads),
+                           0, s, a);
+      }
       switch (g) {
-        case 0: launch_step_p<128>(a, lv, grid, s); break;
-        case 1: launch_step_p<256>(a, lv, grid, s); break;
-        case 2: launch_step_p<512>(a, lv, grid, s); break;
-        default: launch_step_p<1024>(a, lv, grid, s); break;
+        case 0: launch_step_p<128>(a, lv, fuse, grid, s); break;
+        case 1: launch_step_p<256>(a, lv, fuse, grid, s); break;
+        case 2: launch_step_p<512>(a, lv, fuse, grid, s); break;
+        default: launch_step_p<1024>(a, lv, fuse, grid, s); break;
       }
       continue;
     }

@@ -1317,14 +1317,15 @@ constexpr int kGradK = 8;                         // Doppler partials per lane a
 
 // Per problem of the launch, after the row blocks: one statistics block
 // (L_p, maxima, loss, the record and the non-finite flag).
+template <int NT>
 __device__ __forceinline__ void grad_units(const ProbPlan& pl, const UnitStat* us, bool keys, float& mx, float& sx,
                                            unsigned long long& ka, unsigned long long& kc) {
   // four units per thread and round, loads first
-  for (int i0 = threadIdx.x; i0 < pl.units; i0 += 4 * kGradThreads) {
+  for (int i0 = threadIdx.x; i0 < pl.units; i0 += 4 * NT) {
     UnitStat u[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = i0 + q * kGradThreads;
+      const int i = i0 + q * NT;
       if (i < pl.units) {
         u[q] = us[i];
       } else {
@@ -1397,7 +1398,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
   if (tid < M) snrl_sh[tid] = a.snrl[pl.row0 + tid];
   float mx = 0.f, sx = 0.f;
   unsigned long long ka = 0, kc = 0;
-  grad_units(pl, us, stat_block, mx, sx, ka, kc);
+  grad_units<kGradThreads>(pl, us, stat_block, mx, sx, ka, kc);
 
   // ---- L_p, the SNRL penalty and the loss (eq. 37-42)
   {
@@ -1483,14 +1484,29 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
   if (on && sub == 0) a.gbuf[wrow + n] = g;
 }
 
-template <int P, int MODE, int LVMAX>
+// Lanes per chip in k_step, and the Doppler partials a lane loads per round
+// when k_step reduces the gradient rows itself (FG).
+__host__ __device__ constexpr int step_tpc(int P) { return P >= 256 ? 2 * kStepThreads / P : 8; }
+__host__ __device__ constexpr int step_fg_loads(int P) {
+  return 48 / step_tpc(P) < 32 ? 48 / step_tpc(P) : 32;
+}
+
+// FG: the block also does k_grad's work for its row (the problem's L_p and
+// loss from the unit statistics, in every block in the same order; the
+// record by the problem's first row; the chip gradients from the Doppler
+// partials, TPC lanes per chip), so one kernel ends the inner step. Used
+// when a row's partials take at most two load rounds per lane.
+template <int P, int MODE, int LVMAX, bool FG>
 __global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
-  constexpr int TPC = P >= 256 ? 2 * kStepThreads / P : 8;  // lanes per chip: N <= P/2 chips fill the block
+  constexpr int TPC = step_tpc(P);  // lanes per chip: N <= P/2 chips fill the block
   constexpr bool kA = MODE == FIN_STEP_A;
   using G = Geom<P>;
   __shared__ float shr[2 * 5 * kStepWaves];
   __shared__ float2 rowbuf[P];
   __shared__ float2 fbuf[G::LDS];
+  __shared__ float shw[FG ? 2 * kStepWaves : 1];
+  __shared__ unsigned long long shk[FG ? 2 * kStepWaves : 1];
+  __shared__ float4 snrl_sh[FG ? 16 : 1];
   const int tid = threadIdx.x;
   int r, pid;
   ProbPlan pl;
@@ -1518,8 +1534,25 @@ __global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
 
   // ---- loads
   const int tstep = *a.counter;
-  const bool bad = a.pflag[pid] != 0;
-  const float2 g = on ? a.gbuf[wrow + n] : zero2;
+  constexpr int KL = FG ? step_fg_loads(P) : 1;
+  const int NE = pl.wpr;
+  const UnitStat* us = a.ustat + pl.ws_unit;
+  const float2* up = a.upart + pl.ws_upart + (int64_t)m * NE * N + n;
+  float sj[KL];
+  float2 vj[KL];
+  float2 pw = zero2;
+  if constexpr (FG) {
+    // first round of the chip's Doppler partials: lane sub takes sub + TPC k
+#pragma unroll
+    for (int k = 0; k < KL; ++k) {
+      const int j = sub + TPC * k;
+      const bool ok = on && j < NE;
+      sj[k] = ok ? us[m * NE + j].sigma : 0.f;
+      vj[k] = ok ? up[(int64_t)j * N] : zero2;
+    }
+    pw = on ? a.part_w[wrow + n] : zero2;
+    if (tid < M) snrl_sh[tid] = a.snrl[pl.row0 + tid];
+  }
   float2 hv = zero2, sv = zero2, xv = zero2;
   float4 mvh = make_float4(0.f, 0.f, 0.f, 0.f);
   float* mh = a.adam + pl.off_state + 2 * (int64_t)M * N * L + 2 * crow;
@@ -1547,6 +1580,96 @@ __global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
   }
   if (want_spec)
     for (int i = N + tid; i < P; i += kStepThreads) rowbuf[i] = zero2;
+
+  bool bad;
+  float2 g;
+  if constexpr (FG) {
+    // ---- L_p, the SNRL penalty and the loss (eq. 37-42), as in k_grad
+    float mx = 0.f, sx = 0.f;
+    unsigned long long ka = 0, kc = 0;
+    const bool keys = m == 0;
+    grad_units<kStepThreads>(pl, us, keys, mx, sx, ka, kc);
+    {
+      const float wm = wave_max(mx);
+      float sw = mx > 0.f ? sx * pow_p(mx / wm, pl) : 0.f;
+      sw = wave_sum(sw);
+      if ((tid & 63) == 0) {
+        shw[tid >> 6] = wm;
+        shw[kStepWaves + (tid >> 6)] = sw;
+      }
+      if (keys) {
+        ka = slot_max_key<64>(ka);
+        kc = slot_max_key<64>(kc);
+        if ((tid & 63) == 0) {
+          shk[tid >> 6] = ka;
+          shk[kStepWaves + (tid >> 6)] = kc;
+        }
+      }
+    }
+    __syncthreads();
+    float smax = 0.f;
+    for (int w = 0; w < kStepWaves; ++w) smax = fmaxf(smax, shw[w]);
+    float acc = 0.f;
+    for (int w = 0; w < kStepWaves; ++w)
+      if (shw[w] > 0.f) acc += shw[kStepWaves + w] * pow_p(shw[w] / smax, pl);
+    const float lp_raw = smax > 0.f ? smax * exp2f(log2f(acc) / pl.p) : 0.f;
+    float l_snrl = 0.f;
+    for (int k = 0; k < M; ++k) {
+      const float4 c4 = snrl_sh[k];
+      const float pk = sqrtf(c4.x * c4.x + c4.y * c4.y) / (float)N;
+      l_snrl += (pk - pl.p_tar) * (pk - pl.p_tar) / (float)M;
+    }
+    const float loss = pl.w_psl * lp_raw * pl.inv_NP + pl.w_snrl * l_snrl;
+    bad = !isfinite(loss);
+    if (keys && tid == 0 && a.stats != nullptr) {
+      for (int w = 0; w < kStepWaves; ++w) {
+        ka = umax64(ka, shk[w]);
+        kc = umax64(kc, shk[kStepWaves + w]);
+      }
+      stats_record(a.stats + pid, pl, a.orient, loss, lp_raw, l_snrl, ka, kc, snrl_sh, bad);
+    }
+    // ---- gradient of the chip: Doppler partials scaled by
+    // (w_psl / (N P)) (sigma_u / L_p)^(p-1), then the SNRL term
+    g = zero2;
+    if (lp_raw > 0.f) {
+      const float cfac = pl.w_psl / ((float)N * (float)pl.P);
+      const float inv_lp = 1.0f / lp_raw;
+#pragma unroll
+      for (int k = 0; k < KL; ++k) {
+        const float f = cfac * pow_pm1(sj[k] * inv_lp, pl);
+        g.x += f * vj[k].x;
+        g.y += f * vj[k].y;
+      }
+      for (int j0 = TPC * KL; j0 < NE; j0 += TPC * KL) {
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {
+          const int j = j0 + sub + TPC * k;
+          const bool ok = on && j < NE;
+          sj[k] = ok ? us[m * NE + j].sigma : 0.f;
+          vj[k] = ok ? up[(int64_t)j * N] : zero2;
+        }
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {
+          const float f = cfac * pow_pm1(sj[k] * inv_lp, pl);
+          g.x += f * vj[k].x;
+          g.y += f * vj[k].y;
+        }
+      }
+    }
+    g.x = chip_sum<TPC>(g.x);
+    g.y = chip_sum<TPC>(g.y);
+    const float4 cm = snrl_sh[m];
+    const float magm = sqrtf(cm.x * cm.x + cm.y * cm.y);
+    if (magm > 0.f) {
+      const float2 gS = cscale(make_float2(cm.x, cm.y),
+                               pl.w_snrl * (2.0f / (float)M) * (magm / (float)N - pl.p_tar) / ((float)N * magm));
+      g = cadd(g, cmul(gS, pw));
+    }
+    if (!on) g = zero2;
+  } else {
+    bad = a.pflag[pid] != 0;
+    g = on ? a.gbuf[wrow + n] : zero2;
+  }
   const float flag = lead && !(isfinite(g.x) && isfinite(g.y)) ? 1.0f : 0.0f;
   const float b1 = a.opt.beta1, b2 = a.opt.beta2;
 

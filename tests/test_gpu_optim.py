@@ -342,3 +342,30 @@ def test_stopping_rule_run(ref, mods):
         st = ref.evaluate(ref.hard_waveform(d["z"].astype(np.float64)), d["h"].astype(np.complex128),
                           prob, False)[0]
         assert abs(d["stats"]["pslr_db"] - st["pslr_db"]) <= 0.05
+
+
+@pytest.mark.parametrize("F", [129, 200])
+def test_fused_finalize_steps_match_oracle(ref, mods, F):
+    """A batch of 32 M=4 N=256 designs (128 rows: k_step reduces the gradient
+    rows itself, in one load round per lane at F=129 and two at F=200):
+    two iterations of its first and last design against the oracle's."""
+    nat, optim, _ = mods
+    prob = I.make_problem(4, 256, 8, F, p=16.0)
+    opt = I.make_opt(total_iters=10, T0=1.0, T1=0.5)
+    print(f"[gpu] fused finalize 32 x M=4 N=256 F={F}", flush=True)
+    run = optim.SQNGD([prob] * 32, opt, seeds=list(range(40, 72)), schedule=nat.SCHED_THROUGHPUT)
+    s0 = [run.numpy_state(i) for i in (0, 31)]
+    run.step(2)
+    torch.cuda.synchronize()
+    assert run.t == 2
+    sa, sb = run.step_stats()
+    for k, i in enumerate((0, 31)):
+        s1 = run.numpy_state(i)
+        z, h, state = s0[k]["z"], s0[k]["h"], s0[k]["state"]
+        for t in range(2):
+            z, h, state, sta, stb = ref.step(prob, opt, z, h, state, t)
+        assert _rel(s1["h"], h) <= 1e-4, (i, _rel(s1["h"], h))
+        assert _rel(s1["z"], z) <= 1e-4, (i, _rel(s1["z"], z))
+        assert abs(sa[i]["loss"] - sta["loss"]) <= 1e-4 * sta["loss"]
+        assert abs(sb[i]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"]
+        assert abs(sb[i]["pslr_db"] - stb["pslr_db"]) <= 0.05

@@ -206,8 +206,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
       if (split) {
         upb = pl->group_wv[q.logP - kMinLogP] / p.M;
       } else {
-        const int TF = q.P >= 512 ? 64 : q.P / 8;
-        upb = pass_waves(q.P) * (64 / TF);
+        upb = pass_upb(q.P);
       }
       q.wpr = (p.F + upb - 1) / upb;
     }

@@ -1,11 +1,14 @@
 // fft_wave.hpp - wave-local complex64 FFTs of length P = 128 .. 2048 for gfx950.
 //
-// One FFT lives in TF lanes of a single 64-lane wave, E = P / TF elements per
-// lane in registers (TF = 64 for P >= 512, else P / 8, so E >= 8), and a wave
-// runs 64 / TF independent FFTs side by side ("slots"). Every exchange of data
-// between lanes stays inside the wave, so no workgroup barrier is ever needed:
-// an exchange is a write of the slot's elements to its private LDS region, a
-// wave-scope fence, and a read back in the next stage's order.
+// One FFT lives in TF lanes, E = P / TF elements per lane in registers. The
+// default geometry (Geom) keeps it inside one 64-lane wave (TF = 64 for
+// P >= 512, else P / 8, so E >= 8), and a wave runs 64 / TF independent FFTs
+// side by side ("slots"); every exchange of data between lanes stays inside
+// the wave, so no workgroup barrier is needed: an exchange is a write of the
+// slot's elements to its private LDS region, a wave-scope fence, and a read
+// back in the next stage's order. A geometry with TF = 128 spreads one FFT
+// over two waves of a workgroup (half the registers per lane); its exchanges
+// synchronise the workgroup instead.
 //
 // Factorisation (Cooley-Tukey four-step, P = E * TF with TF = A * B):
 //   natural index n = t + TF * e            (lane t, register e)
@@ -172,22 +175,39 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // ------------------------------------------------------------------ geometry
 
-template <int P_>
-struct Geom {
+template <int P_, int TF_>
+struct GeomT {
   static constexpr int P = P_;
-  static constexpr int TF = P >= 512 ? 64 : P / 8;  // lanes per FFT
+  static constexpr int TF = TF_;                     // lanes per FFT
   static constexpr int E = P / TF;                   // elements per lane
   static constexpr int A = TF >= 32 ? 8 : 4;
   static constexpr int B = TF / A;
-  static constexpr int SLOTS = 64 / TF;              // FFTs per wave
+  static constexpr int SLOTS = TF <= 64 ? 64 / TF : 1;  // FFTs per wave
+  static constexpr int WAVES = TF > 64 ? TF / 64 : 1;   // waves per FFT
   static constexpr int LDS = 64 * E;                 // float2 per wave
   static_assert(E % A == 0 && E % B == 0, "register blocks must tile E");
+  static_assert(TF <= 64 ? 64 % TF == 0 : TF % 64 == 0, "an FFT fills whole waves or divides one");
   // spectral-layout bin of lane t, register e
   __device__ static constexpr int spec_bin(int t, int e) {
     int gamma = t % A, k1 = (e / B) * B + t / A, delta = e % B;
     return k1 + E * (gamma + A * delta);
   }
+  // the inverse: storage index e * TF + t of bin k
+  __device__ static constexpr int spec_index(int k) {
+    const int k1 = k % E, r = k / E, gamma = r % A, delta = r / A;
+    return ((k1 / B) * B + delta) * TF + (k1 % B) * A + gamma;
+  }
 };
+template <int P>
+using Geom = GeomT<P, (P >= 512 ? 64 : P / 8)>;
+
+// LDS ordering between the stages of one FFT: the wave for a wave-local
+// geometry, the workgroup for one spread over several waves.
+template <class G>
+__device__ __forceinline__ void fft_sync() {
+  if constexpr (G::WAVES > 1) __syncthreads();
+  else wave_lds_sync();
+}
 
 // exp(-2 pi i k / P) for an integer k, from one sincospi of the reduced angle.
 template <int P>
@@ -200,9 +220,10 @@ __device__ __forceinline__ float2 tw_exact(int k) {
 // Per-lane twiddles reused by every FFT of the wave. A few are evaluated with
 // sincospi and the rest formed as products of at most two of them (error a
 // few ulp), so no table is read from memory at kernel start.
-template <int P>
-struct WaveTwiddles {
-  using G = Geom<P>;
+template <class G_>
+struct TwiddlesG {
+  using G = G_;
+  static constexpr int P = G::P;
   static constexpr int NLO = G::E < 8 ? G::E : 8;
   static constexpr int NHI = G::E / NLO;
   float2 lo[NLO];  // W_P^(t b),        b < NLO
@@ -254,12 +275,13 @@ struct WaveTwiddles {
   }
 };
 
+template <int P>
+using WaveTwiddles = TwiddlesG<Geom<P>>;
+
 // Forward FFT of one slot: x in natural layout -> x in spectral layout.
 // buf points at this slot's P-element LDS region; t is the lane within the slot.
-template <int P>
-__device__ __forceinline__ void fft_forward(float2 (&x)[Geom<P>::E], float2* buf, int t,
-                                            const WaveTwiddles<P>& W) {
-  using G = Geom<P>;
+template <class G>
+__device__ __forceinline__ void fft_forward_g(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
   constexpr int E = G::E, TF = G::TF, A = G::A, B = G::B;
   dft_reg<E, -1, 0>(x);
   static_for<E>([&](auto kc) {
@@ -267,12 +289,12 @@ __device__ __forceinline__ void fft_forward(float2 (&x)[Geom<P>::E], float2* buf
     x[k1] = W.template step2<k1>(x[k1], false);
   });
   // exchange 1: [k1][n2]
-  wave_lds_sync();
+  fft_sync<G>();
   static_for<E>([&](auto kc) {
     constexpr int k1 = decltype(kc)::value;
     buf[k1 * TF + t] = x[k1];
   });
-  wave_lds_sync();
+  fft_sync<G>();
   const int beta = t % B, q = t / B;
   static_for<E / A>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
@@ -287,7 +309,7 @@ __device__ __forceinline__ void fft_forward(float2 (&x)[Geom<P>::E], float2* buf
     });
   });
   // exchange 2: [k1][gamma * B + beta]
-  wave_lds_sync();
+  fft_sync<G>();
   static_for<E / A>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
     static_for<A>([&](auto gc) {
@@ -295,7 +317,7 @@ __device__ __forceinline__ void fft_forward(float2 (&x)[Geom<P>::E], float2* buf
       buf[(j * A + q) * TF + g * B + beta] = x[j * A + g];
     });
   });
-  wave_lds_sync();
+  fft_sync<G>();
   const int gamma = t % A, q2 = t / A;
   static_for<E / B>([&](auto jc) {
     constexpr int j2 = decltype(jc)::value;
@@ -308,17 +330,15 @@ __device__ __forceinline__ void fft_forward(float2 (&x)[Geom<P>::E], float2* buf
 }
 
 // Inverse FFT of one slot (unscaled): x in spectral layout -> x in natural layout.
-template <int P>
-__device__ __forceinline__ void fft_inverse(float2 (&x)[Geom<P>::E], float2* buf, int t,
-                                            const WaveTwiddles<P>& W) {
-  using G = Geom<P>;
+template <class G>
+__device__ __forceinline__ void fft_inverse_g(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
   constexpr int E = G::E, TF = G::TF, A = G::A, B = G::B;
   const int gamma = t % A, q2 = t / A;
   static_for<E / B>([&](auto jc) {
     constexpr int j2 = decltype(jc)::value;
     dft_reg<B, +1, j2 * B>(x);
   });
-  wave_lds_sync();
+  fft_sync<G>();
   static_for<E / B>([&](auto jc) {
     constexpr int j2 = decltype(jc)::value;
     static_for<B>([&](auto bc) {
@@ -326,7 +346,7 @@ __device__ __forceinline__ void fft_inverse(float2 (&x)[Geom<P>::E], float2* buf
       buf[(j2 * B + q2) * TF + gamma * B + be] = x[j2 * B + be];
     });
   });
-  wave_lds_sync();
+  fft_sync<G>();
   const int beta = t % B, q = t / B;
   static_for<E / A>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
@@ -338,7 +358,7 @@ __device__ __forceinline__ void fft_inverse(float2 (&x)[Geom<P>::E], float2* buf
     });
     dft_reg<A, +1, j * A>(x);
   });
-  wave_lds_sync();
+  fft_sync<G>();
   static_for<E / A>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
     static_for<A>([&](auto ac) {
@@ -346,12 +366,21 @@ __device__ __forceinline__ void fft_inverse(float2 (&x)[Geom<P>::E], float2* buf
       buf[(j * A + q) * TF + B * al + beta] = x[j * A + al];
     });
   });
-  wave_lds_sync();
+  fft_sync<G>();
   static_for<E>([&](auto kc) {
     constexpr int k1 = decltype(kc)::value;
     x[k1] = W.template step2<k1>(buf[k1 * TF + t], true);
   });
   dft_reg<E, +1, 0>(x);
+}
+
+template <int P>
+__device__ __forceinline__ void fft_forward(float2 (&x)[Geom<P>::E], float2* buf, int t, const WaveTwiddles<P>& W) {
+  fft_forward_g<Geom<P>>(x, buf, t, W);
+}
+template <int P>
+__device__ __forceinline__ void fft_inverse(float2 (&x)[Geom<P>::E], float2* buf, int t, const WaveTwiddles<P>& W) {
+  fft_inverse_g<Geom<P>>(x, buf, t, W);
 }
 
 }  // namespace sq

@@ -214,6 +214,70 @@ __device__ __forceinline__ int find_entry(const int32_t* base, int n, int wave) 
   return lo;
 }
 
+// Waves per block of the throughput pass: four at P <= 512, two at longer
+// transforms (whose per-wave LDS slices would otherwise allow one block per CU).
+__host__ __device__ constexpr int pass_waves(int P) { return P >= 1024 ? 2 : 4; }
+// FFT geometry of the throughput pass: wave-local up to P = 1024; at P = 2048
+// one transform spans the block's two waves (16 elements per lane instead of
+// 32), which keeps the pass's three spectra in registers without spilling.
+template <int P>
+struct PassGeomSel {
+  using type = Geom<P>;
+};
+template <>
+struct PassGeomSel<2048> {
+  using type = GeomT<2048, 128>;
+};
+template <int P>
+using PassGeom = typename PassGeomSel<P>::type;
+// Doppler bins (units) per throughput-pass block
+__host__ __device__ constexpr int pass_upb(int P) {
+  return P >= 2048 ? pass_waves(P) * 64 / 128 : pass_waves(P) * (P >= 512 ? 1 : 64 / (P / 8));
+}
+// Where a producer's spectral bin k lands in the partner-spectrum rows the
+// pass reads (the pass's own layout).
+template <int P>
+__device__ __forceinline__ int pass_spec_slot(int t, int e) {
+  using GP = Geom<P>;
+  using GC = PassGeom<P>;
+  if constexpr (GP::TF == GC::TF) return e * GP::TF + t;
+  else return GC::spec_index(GP::spec_bin(t, e));
+}
+
+// Reductions over the lanes of one FFT of geometry G, the result in all of
+// them; a transform spread over several waves combines the waves' values
+// through red[] (one entry per wave of the block) in wave order.
+template <class G, class Op>
+__device__ __forceinline__ float fft_lanes_reduce(float v, float ident, Op op, float* red) {
+  if constexpr (G::WAVES == 1) {
+    return slot_reduce<G::TF>(v, ident, op);
+  } else {
+    v = slot_reduce<64>(v, ident, op);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const int w0 = (threadIdx.x / G::TF) * G::WAVES;
+    float r = red[w0];
+    for (int i = 1; i < G::WAVES; ++i) r = op(r, red[w0 + i]);
+    return r;
+  }
+}
+template <class G>
+__device__ __forceinline__ unsigned long long fft_lanes_max_key(unsigned long long v, unsigned long long* red) {
+  if constexpr (G::WAVES == 1) {
+    return slot_max_key<G::TF>(v);
+  } else {
+    v = slot_max_key<64>(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const int w0 = (threadIdx.x / G::TF) * G::WAVES;
+    unsigned long long r = red[w0];
+    for (int i = 1; i < G::WAVES; ++i) r = umax64(r, red[w0 + i]);
+    return r;
+  }
+}
+
 // ------------------------------------------------------------------ k_prep
 
 enum PrepMode : int32_t {
@@ -319,7 +383,7 @@ __global__ __launch_bounds__(64) void k_prep(PrepArgs a) {
     float2* sp = a.spec + pl.ws_spec + (int64_t)g * P;
     static_for<E>([&](auto ec) {
       constexpr int e = decltype(ec)::value;
-      sp[e * TF + t] = X[e];
+      sp[pass_spec_slot<P>(t, e)] = X[e];
     });
   }
 }
@@ -344,30 +408,31 @@ struct PassArgs {
   ProbPlan one;
 };
 
-// Waves per block of the throughput pass: four at P <= 512, two at longer
-// transforms (whose per-wave LDS slices would otherwise allow one block per CU).
-__host__ __device__ constexpr int pass_waves(int P) { return P >= 1024 ? 2 : 4; }
 
 template <int P, int PHLOG>
 __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
-  using G = Geom<P>;
+  using G = PassGeom<P>;
   constexpr int kPassWaves = pass_waves(P);
-  constexpr int E = G::E, TF = G::TF, EH = E / 2, SL = G::SLOTS;
-  constexpr int UPB = kPassWaves * SL;  // units (Doppler bins of one row) per block
-  __shared__ float2 lds[kPassWaves * G::LDS];
-  // The accumulated adjoint spectra U, and for P <= 512 the self spectrum X,
-  // live in the slot's LDS slice instead of registers: three E-element arrays
-  // per lane plus the partner spectrum would cap the occupancy (two waves per
-  // SIMD at P = 512, one at P >= 1024).
+  constexpr int E = G::E, TF = G::TF, EH = E / 2;
+  constexpr int UPB = pass_upb(P);  // units (Doppler bins of one row) per block
+  static_assert(UPB * TF == 64 * kPassWaves, "the units fill the block");
+  __shared__ float2 lds[UPB * P];
+  // The accumulated adjoint spectra U and the self spectrum X live in the
+  // slot's LDS slice instead of registers: three E-element arrays per lane
+  // plus the partner spectrum would cap the occupancy (two waves per SIMD at
+  // P = 512, one at P >= 1024).
   constexpr bool kUL = true;
-  constexpr bool kXL = P <= 1024;
-  __shared__ float2 ulds[kPassWaves * SL * P];
-  __shared__ float2 xlds[kXL ? kPassWaves * SL * P : 1];
+  constexpr bool kXL = true;
+  __shared__ float2 ulds[UPB * P];
+  __shared__ float2 xlds[kXL ? UPB * P : 1];
   __shared__ float u_sig[UPB], u_S[UPB];
   __shared__ unsigned long long u_ka[UPB], u_kc[UPB];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, slot = lane / TF, t = lane % TF;
+  __shared__ float red_f[kPassWaves];
+  __shared__ unsigned long long red_k[kPassWaves];
+  // uslot: the block's unit this lane works on; t: its lane within the FFT
+  const int uslot = threadIdx.x / TF, t = threadIdx.x % TF;
   if (a.bump != nullptr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.bump, 1);
-  float2* buf = lds + wv * G::LDS + slot * P;
+  float2* buf = lds + uslot * P;
   int base = 0;
   ProbPlan pl;
   if (a.single) {
@@ -383,7 +448,6 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
   const int lb = blockIdx.x - base;
   const int w = lb / pl.wpr;
   const int grp = lb - w * pl.wpr;
-  const int uslot = wv * SL + slot;
   const int fs = grp * UPB + uslot;
   const bool active = fs < F;
   const int f = active ? fs : F - 1;
@@ -395,7 +459,7 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
   const float phm1 = 0.5f * pl.p - 1.0f;
   const bool grad = a.want_grad != 0;
 
-  WaveTwiddles<P> W;
+  TwiddlesG<G> W;
   W.init(t);
 
   // The pass is a sequence of 2M+2 transforms (M+1 without the gradient):
@@ -412,8 +476,8 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
   float2* cube = a.cube ? a.cube + pl.off_cube : nullptr;
   const int T2 = 2 * N - 1;
   float2 X[kXL ? 1 : E], U[kUL ? 1 : E], R[E], SG[kKeepSG ? E : 1];
-  float2* ub = ulds + (wv * SL + slot) * P;
-  float2* xb = xlds + (kXL ? (wv * SL + slot) * P : 0);
+  float2* ub = ulds + uslot * P;
+  float2* xb = xlds + (kXL ? uslot * P : 0);
   {
     float2 ph[EH];
     phasor_row<EH, TF>(t, nu, invN, ph);
@@ -446,8 +510,8 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
     });
   };
   for (int op = OP_SELF;;) {
-    if (op == OP_PAIR || op == OP_UINV) fft_inverse<P>(R, buf, t, W);
-    else fft_forward<P>(R, buf, t, W);
+    if (op == OP_PAIR || op == OP_UINV) fft_inverse_g<G>(R, buf, t, W);
+    else fft_forward_g<G>(R, buf, t, W);
     if (op == OP_UINV) break;
     if (op == OP_SELF) {
       static_for<E>([&](auto ec) {
@@ -490,7 +554,7 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
     const unsigned long long key = vmask ? make_key(qmax, (uint32_t)(((int64_t)u * M + g) * P + kbest)) : 0ull;
     if (g == w) kauto = umax64(kauto, key);
     else kcross = umax64(kcross, key);
-    qmax = slot_reduce<TF>(qmax, 0.0f, OpMax());
+    qmax = fft_lanes_reduce<G>(qmax, 0.0f, OpMax(), red_f);
     const float mu = sqrtf(qmax);
     if (mu > sigma) {  // new running scale: rescale the partial sums (online max)
       const float c = sigma / mu;
@@ -518,9 +582,9 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
 
   // Unit results: statistics to the block's tables, the demodulated gradient
   // partial into this slot's LDS region (unscaled, with the unit scale sigma).
-  S = slot_reduce<TF>(S, 0.0f, OpAdd());
-  kauto = slot_max_key<TF>(kauto);
-  kcross = slot_max_key<TF>(kcross);
+  S = fft_lanes_reduce<G>(S, 0.0f, OpAdd(), red_f);
+  kauto = fft_lanes_max_key<G>(kauto, red_k);
+  kcross = fft_lanes_max_key<G>(kcross, red_k);
   if (t == 0) {
     u_sig[uslot] = active ? sigma : 0.f;
     u_S[uslot] = active ? S : 0.f;
@@ -530,7 +594,7 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
   if (grad) {
     float2 ph[EH];
     phasor_row<EH, TF>(t, nu, invN, ph);
-    wave_lds_sync();
+    fft_sync<G>();
     static_for<EH>([&](auto ec) {
       constexpr int e = decltype(ec)::value;
       const int n = t + TF * e;
@@ -578,7 +642,7 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
       float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
       for (int j = 0; j < UPB; ++j) {
-        const float2 v = lds[(j / SL) * G::LDS + (j % SL) * P + n];
+        const float2 v = lds[j * P + n];
         acc.x += fac[j] * v.x;
         acc.y += fac[j] * v.y;
       }
@@ -755,7 +819,7 @@ __device__ __forceinline__ void row_spectrum(float2 v, int N, float2* fbuf, floa
     if (slot == 0) {
       static_for<E>([&](auto ec) {
         constexpr int e = decltype(ec)::value;
-        out[e * TF + t] = X[e];
+        out[pass_spec_slot<P>(t, e)] = X[e];
       });
     }
   }

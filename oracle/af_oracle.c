@@ -88,22 +88,27 @@ void sqngd_ref_af_row(int M, int N, int F, double nu_min, double nu_max, const d
   free(xh);
 }
 
-/* Region of interest (eq. 7-9 with w = 1 inside the delay window): a cell
-   (m, l, tau, f) counts when tau_lo <= tau <= tau_hi, except the tau = 0 cut
-   of an auto pair (eq. 8 excludes tau = 0 for m1 = m2; eq. 9 keeps every tau
-   for m1 != m2). */
+/* Region of interest (eq. 7-9): a cell (m, l, tau, f) counts when
+   tau_lo <= tau <= tau_hi, except the tau = 0 cut of an auto pair (eq. 8
+   excludes tau = 0 for m1 = m2; eq. 9 keeps every tau for m1 != m2). Inside it
+   a cell carries the weight w(tau, f) of eq. 8-9: wt[f][tau + N - 1] when a
+   table is given, else 1. */
 static int in_roi(int m, int l, int tau, int tau_lo, int tau_hi) {
   if (tau < tau_lo || tau > tau_hi) return 0;
   if (m == l && tau == 0) return 0;
   return 1;
 }
+static double roi_weight(const double* wt, int N, int f, int tau) {
+  return wt ? wt[(size_t)f * (2 * N - 1) + tau + N - 1] : 1.0;
+}
 
-/* Loss and statistics from a cube.
+/* Loss and statistics from a cube (wt: the weights w(tau, f) of eq. 8-9 as
+   [F][2N-1], or NULL for w = 1).
    out[0] loss = w_psl * lp + w_snrl * l_snrl             (eq. 42, p-norm for the max)
-   out[1] lp = (sum over the ROI of a^p)^(1/p), a = |A|/N  (p-norm of eq. 37's max)
+   out[1] lp = (sum over the ROI of a^p)^(1/p), a = w |A|/N (p-norm of eq. 37's max)
    out[2] l_snrl = (1/M) sum_m (p_m - p_tar)^2             (eq. 41)
-   out[3] psl_auto = max |A| over auto cells               (eq. 8)
-   out[4] psl_cross = max |A| over cross cells             (eq. 9)
+   out[3] psl_auto = max w |A| over auto cells             (eq. 8)
+   out[4] psl_cross = max w |A| over cross cells           (eq. 9)
    out[5] pslr_db = 20 log10(max(out[3], out[4]) / N)      (eq. 48)
    out[6] max over m of SNRL_m in dB                       (eq. 10)
    out[7] min over m of p_m = |h_m^H s_m| / N              (eq. 38)
@@ -112,8 +117,8 @@ static int in_roi(int m, int l, int tau, int tau_lo, int tau_hi) {
    SNRL_m and p_m. lp is evaluated as amax (sum (a/amax)^p)^(1/p), which equals
    the definition and does not overflow. */
 void sqngd_ref_loss(int M, int N, int F, const double* A_in, const double* s_in, const double* h_in,
-                    int tau_lo, int tau_hi, double p, double mu_db, double w_psl, double w_snrl,
-                    double* out, int* arg, double* snrl_db, double* pm) {
+                    int tau_lo, int tau_hi, const double* wt, double p, double mu_db, double w_psl,
+                    double w_snrl, double* out, int* arg, double* snrl_db, double* pm) {
   const cplx* A = (const cplx*)A_in;
   const cplx* s = (const cplx*)s_in;
   const cplx* h = (const cplx*)h_in;
@@ -126,7 +131,7 @@ void sqngd_ref_loss(int M, int N, int F, const double* A_in, const double* s_in,
       for (int f = 0; f < F; ++f)
         for (int tau = -(N - 1); tau <= N - 1; ++tau) {
           if (!in_roi(m, l, tau, tau_lo, tau_hi)) continue;
-          double v = cabs(A[(((size_t)m * M + l) * F + f) * T + tau + N - 1]);
+          double v = roi_weight(wt, N, f, tau) * cabs(A[(((size_t)m * M + l) * F + f) * T + tau + N - 1]);
           if (m == l) {
             if (v > psl_auto) psl_auto = v;
           } else if (v > psl_cross) {
@@ -145,7 +150,7 @@ void sqngd_ref_loss(int M, int N, int F, const double* A_in, const double* s_in,
         for (int f = 0; f < F; ++f)
           for (int tau = -(N - 1); tau <= N - 1; ++tau) {
             if (!in_roi(m, l, tau, tau_lo, tau_hi)) continue;
-            double a = cabs(A[(((size_t)m * M + l) * F + f) * T + tau + N - 1]) / N;
+            double a = roi_weight(wt, N, f, tau) * cabs(A[(((size_t)m * M + l) * F + f) * T + tau + N - 1]) / N;
             acc += pow(a / amax, p);
           }
   }
@@ -184,9 +189,10 @@ void sqngd_ref_loss(int M, int N, int F, const double* A_in, const double* s_in,
 /* Gradients of the loss of sqngd_ref_loss with respect to the waveforms and
    the filters, packed as dL/dRe + j dL/dIm.
 
-   With a = |A|/N on the ROI, dlp/da = lp^(1-p) a^(p-1) and the packed
-   derivative of a with respect to A is A / (N |A|), so the sidelobe term has
-   packed gradient G = w_psl lp^(1-p) a^(p-2) A / N^2 on the ROI, 0 elsewhere.
+   With a = w |A|/N on the ROI, dlp/da = lp^(1-p) a^(p-1) and the packed
+   derivative of a with respect to A is w A / (N |A|), so the sidelobe term
+   has packed gradient G = w_psl lp^(1-p) a^(p-2) w^2 A / N^2 on the ROI, 0
+   elsewhere.
    A is linear in s_m and conjugate-linear in h_l (eq. 6), which gives
      grad_s_m(n) = sum_{l,f,tau} e^{-j 2 pi n nu_f / N} G_ml(tau,f) h_l(n + tau)
      grad_h_l(k) = sum_{m,f,tau} conj(G_ml(tau,f)) s_m(k - tau) e^{j 2 pi (k - tau) nu_f / N}.
@@ -195,8 +201,9 @@ void sqngd_ref_loss(int M, int N, int F, const double* A_in, const double* s_in,
      grad_s_m += G_S h_m,  grad_h_m += conj(G_S) s_m.
    Requires the cube of sqngd_ref_af_cube for the same inputs. */
 void sqngd_ref_grads(int M, int N, int F, double nu_min, double nu_max, const double* s_in,
-                     const double* h_in, const double* A_in, int tau_lo, int tau_hi, double p,
-                     double mu_db, double w_psl, double w_snrl, double* gs_out, double* gh_out) {
+                     const double* h_in, const double* A_in, int tau_lo, int tau_hi, const double* wt,
+                     double p, double mu_db, double w_psl, double w_snrl, double* gs_out,
+                     double* gh_out) {
   const cplx* s = (const cplx*)s_in;
   const cplx* h = (const cplx*)h_in;
   const cplx* A = (const cplx*)A_in;
@@ -204,7 +211,7 @@ void sqngd_ref_grads(int M, int N, int F, double nu_min, double nu_max, const do
   cplx* gh = (cplx*)gh_out;
   const int T = 2 * N - 1;
   double stats[8];
-  sqngd_ref_loss(M, N, F, A_in, s_in, h_in, tau_lo, tau_hi, p, mu_db, w_psl, w_snrl, stats, NULL,
+  sqngd_ref_loss(M, N, F, A_in, s_in, h_in, tau_lo, tau_hi, wt, p, mu_db, w_psl, w_snrl, stats, NULL,
                  NULL, NULL);
   const double lp = stats[1];
   const size_t ncell = (size_t)M * M * F * T;
@@ -216,8 +223,9 @@ void sqngd_ref_grads(int M, int N, int F, double nu_min, double nu_max, const do
           for (int tau = -(N - 1); tau <= N - 1; ++tau) {
             if (!in_roi(m, l, tau, tau_lo, tau_hi)) continue;
             size_t i = (((size_t)m * M + l) * F + f) * T + tau + N - 1;
-            double a = cabs(A[i]) / N;
-            G[i] = w_psl * pow(lp, 1.0 - p) * pow(a, p - 2.0) * A[i] / ((double)N * N);
+            double w = roi_weight(wt, N, f, tau);
+            double a = w * cabs(A[i]) / N;
+            G[i] = w_psl * pow(lp, 1.0 - p) * pow(a, p - 2.0) * w * w * A[i] / ((double)N * N);
           }
   }
 #pragma omp parallel for collapse(2) schedule(dynamic)

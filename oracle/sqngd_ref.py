@@ -26,7 +26,8 @@ design notes of the repository):
 
 A problem is a plain dict with the keys M, N, L, F, nu_min, nu_max, tau_lo,
 tau_hi, p, snrl_target_db, w_psl, w_snrl, temperature, sq_mode (0 phase-mean,
-1 phasor-mean). Options of an outer iteration are a dict with lr_z, lr_h,
+1 phasor-mean), and optionally roi_w: the weights w(tau, f) of eq. 8-9 as an
+[F][2N-1] array (tau + N - 1 fastest; absent or None means w = 1). Options of an outer iteration are a dict with lr_z, lr_h,
 beta1, beta2, eps, n_h, n_x, T0, T1, total_iters, flags (1 = plain gradient
 descent).
 """
@@ -69,9 +70,9 @@ def _load():
         lib.sqngd_ref_af_row.restype = None
         lib.sqngd_ref_af_row.argtypes = [i, i, i, d, d, P, P, i, i, i, P]
         lib.sqngd_ref_loss.restype = None
-        lib.sqngd_ref_loss.argtypes = [i, i, i, P, P, P, i, i, d, d, d, d, P, P, P, P]
+        lib.sqngd_ref_loss.argtypes = [i, i, i, P, P, P, i, i, P, d, d, d, d, P, P, P, P]
         lib.sqngd_ref_grads.restype = None
-        lib.sqngd_ref_grads.argtypes = [i, i, i, d, d, P, P, P, i, i, d, d, d, d, P, P]
+        lib.sqngd_ref_grads.argtypes = [i, i, i, d, d, P, P, P, i, i, P, d, d, d, d, P, P]
         _lib = lib
     return _lib
 
@@ -80,8 +81,8 @@ def _c128(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
 
 
-def _ptr(a: np.ndarray):
-    return a.ctypes.data_as(ctypes.c_void_p)
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
 # ---------------------------------------------------------------------------
@@ -114,6 +115,16 @@ def af_row(s, h, F: int, nu_min: float, nu_max: float, m: int, l: int, f: int) -
     return out
 
 
+def _weights(prob: dict, N: int, F: int):
+    """The weight table w(tau, f) of eq. 8-9 as contiguous float64 [F][2N-1], or None."""
+    wt = prob.get("roi_w")
+    if wt is None:
+        return None
+    wt = np.ascontiguousarray(wt, dtype=np.float64)
+    assert wt.shape == (F, 2 * N - 1), wt.shape
+    return wt
+
+
 def loss_stats(cube: np.ndarray, s, h, prob: dict) -> dict:
     """Loss, p-norm, SNRL penalty, PSLs and SNRLs of one evaluation (eq. 7-10, 37-42, 48)."""
     s, h = _c128(s), _c128(h)
@@ -124,8 +135,9 @@ def loss_stats(cube: np.ndarray, s, h, prob: dict) -> dict:
     arg = np.zeros(4, dtype=np.int32)
     snrl = np.zeros(M)
     pm = np.zeros(M)
+    wt = _weights(prob, N, F)
     _load().sqngd_ref_loss(M, N, F, _ptr(cube), _ptr(s), _ptr(h), int(prob["tau_lo"]),
-                           int(prob["tau_hi"]), float(prob["p"]), float(prob["snrl_target_db"]),
+                           int(prob["tau_hi"]), _ptr(wt), float(prob["p"]), float(prob["snrl_target_db"]),
                            float(prob["w_psl"]), float(prob["w_snrl"]), _ptr(out), _ptr(arg),
                            _ptr(snrl), _ptr(pm))
     keys = ["loss", "lp", "l_snrl", "psl_auto", "psl_cross", "pslr_db", "snrl_db_max", "p_min"]
@@ -146,8 +158,9 @@ def grads(s, h, prob: dict, cube: np.ndarray | None = None):
     cube = _c128(cube)
     gs = np.zeros((M, N), dtype=np.complex128)
     gh = np.zeros((M, N), dtype=np.complex128)
+    wt = _weights(prob, N, F)
     _load().sqngd_ref_grads(M, N, F, float(prob["nu_min"]), float(prob["nu_max"]), _ptr(s), _ptr(h),
-                            _ptr(cube), int(prob["tau_lo"]), int(prob["tau_hi"]), float(prob["p"]),
+                            _ptr(cube), int(prob["tau_lo"]), int(prob["tau_hi"]), _ptr(wt), float(prob["p"]),
                             float(prob["snrl_target_db"]), float(prob["w_psl"]),
                             float(prob["w_snrl"]), _ptr(gs), _ptr(gh))
     return gs, gh

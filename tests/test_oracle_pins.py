@@ -401,3 +401,71 @@ def test_step_invariants_and_improvement(ref):
     st1 = ref.evaluate(ref.hard_waveform(z), h, prob, False)[0]
     assert st1["loss"] < st0["loss"]
     assert sa is not None and sb is not None
+
+
+# ------------------------------------------------- ROI weights w(tau, f) (eq. 8-9)
+
+def _weights(F, N, seed, lo=0.3, hi=2.0):
+    return np.random.default_rng(seed).uniform(lo, hi, size=(F, 2 * N - 1))
+
+
+def test_weights_of_one_and_indicator_windows(ref):
+    """w = 1 gives the unweighted statistics; a 0/1 table equal to a delay
+    window gives the window's statistics (the window is eq. 8-9 with an
+    indicator weight)."""
+    M, N, F = 2, 12, 4
+    s, h = _rand_c((M, N), 41), _rand_c((M, N), 42)
+    cube = ref.af_cube(s, h, F, -0.5, 0.5)
+    base = I.make_problem(M, N, 4, F, p=6.0)
+    st0 = ref.loss_stats(cube, s, h, base)
+    st1 = ref.loss_stats(cube, s, h, dict(base, roi_w=np.ones((F, 2 * N - 1))))
+    for k in ("loss", "lp", "psl_auto", "psl_cross"):
+        assert st1[k] == st0[k], k
+    tau = np.arange(-(N - 1), N)
+    ind = np.tile(((tau >= -4) & (tau <= 7)).astype(float), (F, 1))
+    stw = ref.loss_stats(cube, s, h, dict(base, roi_w=ind))
+    stn = ref.loss_stats(cube, s, h, dict(base, tau_lo=-4, tau_hi=7))
+    for k in ("lp", "psl_auto", "psl_cross"):
+        assert abs(stw[k] - stn[k]) <= 1e-12 * stn[k], k
+
+
+def test_weighted_psl_and_norm_by_brute_force(ref):
+    """PSL and L_p with random weights against a numpy scan of the cube."""
+    M, N, F, p = 3, 9, 5, 5.0
+    s, h = _rand_c((M, N), 43), _rand_c((M, N), 44)
+    cube = ref.af_cube(s, h, F, -0.7, 0.3)
+    wt = _weights(F, N, 45)
+    st = ref.loss_stats(cube, s, h, dict(I.make_problem(M, N, 4, F, p=p), roi_w=wt))
+    aw = np.abs(cube) * wt[None, None]
+    auto_mask = np.ones(2 * N - 1, bool)
+    auto_mask[N - 1] = False
+    auto = max(aw[m, m][:, auto_mask].max() for m in range(M))
+    cross = max(aw[m, l].max() for m in range(M) for l in range(M) if m != l)
+    cells = [aw[m, l][:, auto_mask] if m == l else aw[m, l] for m in range(M) for l in range(M)]
+    lp = (sum(((c / N) ** p).sum() for c in cells)) ** (1 / p)
+    assert abs(st["psl_auto"] - auto) < 1e-12 * auto and abs(st["psl_cross"] - cross) < 1e-12 * cross
+    assert abs(st["lp"] - lp) < 1e-12 * lp
+
+
+def test_weight_scaling(ref):
+    """w -> c w scales L_p and both PSLs by c and the sidelobe part of the gradient by c."""
+    M, N, F = 2, 10, 3
+    s, h = _rand_c((M, N), 46), _rand_c((M, N), 47)
+    wt = _weights(F, N, 48)
+    prob = dict(I.make_problem(M, N, 4, F, p=8.0, w_snrl=0.0), roi_w=wt)
+    st, gs, gh = ref.evaluate(s, h, prob)
+    st3, gs3, gh3 = ref.evaluate(s, h, dict(prob, roi_w=3.0 * wt))
+    for k in ("lp", "psl_auto", "psl_cross"):
+        assert abs(st3[k] - 3.0 * st[k]) <= 1e-12 * st3[k], k
+    assert np.abs(gs3 - 3.0 * gs).max() <= 1e-12 * np.abs(gs3).max()
+    assert np.abs(gh3 - 3.0 * gh).max() <= 1e-12 * np.abs(gh3).max()
+
+
+def test_weighted_gradients_central_differences(ref):
+    M, N, F = 2, 8, 4
+    s, h = _rand_c((M, N), 49), _rand_c((M, N), 50)
+    prob = dict(I.make_problem(M, N, 4, F, nu_min=-0.4, nu_max=0.6, p=6.0, w_snrl=0.8, tau_lo=-6, tau_hi=5),
+                roi_w=_weights(F, N, 51))
+    rng = np.random.default_rng(52)
+    coords = [(w, int(rng.integers(M)), int(rng.integers(N))) for w in ("s", "h") for _ in range(6)]
+    _fd_check(ref, s, h, prob, coords)

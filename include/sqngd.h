@@ -193,6 +193,22 @@ int sqngd_workspace_size(const sqngd_problem* probs, int32_t nprob, size_t* byte
 int sqngd_workspace_init(const sqngd_problem* probs, int32_t nprob, void* ws, size_t ws_bytes,
                          void* stream);
 
+/* Attaches the weights w(tau, f) of eq. 8-9 (Algorithm 1's ROI weights) to
+   the workspace initialised for this batch. weights is a DEVICE array of
+   floats, per problem [F][2N-1] (tau + N - 1 fastest), problems packed back to
+   back in batch order (sum of F*(2N-1) floats), 4-byte aligned; NULL returns
+   to w = 1. Inside the delay window [tau_lo, tau_hi] a cell then enters the
+   statistics and the loss as a = w |A| / N: the PSLs become WAPSL and WCPSL of
+   eq. 8-9, L_p sums (w |A| / N)^p, and the gradients follow. Values must be
+   finite and non-negative (not checked). The caller keeps the array alive
+   and unchanged while calls run that use this workspace; the pointer is read
+   when each call enqueues its kernels, so a graph captured earlier keeps the
+   weights it was captured with. sqngd_workspace_init resets to w = 1.
+   Returns SQNGD_OK, SQNGD_E_ALIGN, or the lookup errors of the other calls
+   (SQNGD_E_INVALID_ARG, SQNGD_E_WORKSPACE). */
+int sqngd_set_roi_weights(const sqngd_problem* probs, int32_t nprob, const float* weights, void* ws,
+                          size_t ws_bytes);
+
 /* Loss and statistics of one evaluation (Sec. III-B: eq. 33-36 for the AF,
    eq. 37-42 for the loss, eq. 48 for PSLR).
    z        logits, read for wave_mode SOFT/HARD (may be NULL for GIVEN);

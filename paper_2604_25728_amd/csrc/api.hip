@@ -123,6 +123,9 @@ struct Plan {
   int maxN = 0;
   bool split = false;  // the fused pass runs as k_pass_split (small batches)
   uint64_t hash = 0;
+  // ROI weights attached by sqngd_set_roi_weights (device, packed per
+  // problem), or null for w = 1; read when a pass is enqueued
+  mutable const float* roi_w = nullptr;
 };
 
 uint64_t fnv1a(const void* data, size_t n) {
@@ -173,7 +176,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     }
   }
   pl->split = split;
-  int64_t off_z = 0, off_w = 0, off_state = 0, off_cube = 0, spec = 0, unit = 0, upart = 0;
+  int64_t off_z = 0, off_w = 0, off_state = 0, off_cube = 0, off_rw = 0, spec = 0, unit = 0, upart = 0;
   int rows = 0;
   for (int i = 0; i < nprob; ++i) {
     const sqngd_problem& p = probs[i];
@@ -215,6 +218,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     q.off_w = off_w;
     q.off_state = off_state;
     q.off_cube = off_cube;
+    q.off_rw = off_rw;
     q.ws_spec = spec;
     q.ws_unit = unit;
     q.ws_upart = upart;
@@ -222,6 +226,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     off_w += (int64_t)p.M * p.N;
     off_state += SQNGD_ADAM_FLOATS(p.M, p.N, p.L);
     off_cube += (int64_t)p.M * p.M * p.F * (2 * p.N - 1);
+    off_rw += (int64_t)p.F * (2 * p.N - 1);
     spec += (int64_t)p.M * q.P;
     unit += q.units;
     upart += (int64_t)q.units * p.N;  // one partial row per fused-pass block
@@ -446,12 +451,14 @@ bool stream_capturing(hipStream_t s) {
   return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
 }
 
+// Weighted launches (ROI weights attached) take the general-p instantiation.
 template <int P, int WV>
 void launch_split_wv(const PassArgs& a, int phlog, int blocks, hipStream_t s) {
   const dim3 block(64 * WV);
-  if (phlog == 3) hipLaunchKernelGGL((k_pass_split<P, 3, WV>), dim3(blocks), block, 0, s, a);
-  else if (phlog == 2) hipLaunchKernelGGL((k_pass_split<P, 2, WV>), dim3(blocks), block, 0, s, a);
-  else hipLaunchKernelGGL((k_pass_split<P, -1, WV>), dim3(blocks), block, 0, s, a);
+  if (a.roi_w != nullptr) hipLaunchKernelGGL((k_pass_split<P, -1, WV, true>), dim3(blocks), block, 0, s, a);
+  else if (phlog == 3) hipLaunchKernelGGL((k_pass_split<P, 3, WV, false>), dim3(blocks), block, 0, s, a);
+  else if (phlog == 2) hipLaunchKernelGGL((k_pass_split<P, 2, WV, false>), dim3(blocks), block, 0, s, a);
+  else hipLaunchKernelGGL((k_pass_split<P, -1, WV, false>), dim3(blocks), block, 0, s, a);
 }
 
 void launch_split(int P, int wv, const PassArgs& a, int phlog, int blocks, hipStream_t s) {
@@ -464,13 +471,15 @@ void launch_split(int P, int wv, const PassArgs& a, int phlog, int blocks, hipSt
 template <int P>
 void launch_pass_p(const PassArgs& a, int phlog, int waves, hipStream_t s) {
   const dim3 block(64 * pass_waves(P));
-  if (phlog == 3) hipLaunchKernelGGL((k_pass<P, 3>), dim3(waves), block, 0, s, a);
-  else if (phlog == 2) hipLaunchKernelGGL((k_pass<P, 2>), dim3(waves), block, 0, s, a);
-  else hipLaunchKernelGGL((k_pass<P, -1>), dim3(waves), block, 0, s, a);
+  if (a.roi_w != nullptr) hipLaunchKernelGGL((k_pass<P, -1, true>), dim3(waves), block, 0, s, a);
+  else if (phlog == 3) hipLaunchKernelGGL((k_pass<P, 3, false>), dim3(waves), block, 0, s, a);
+  else if (phlog == 2) hipLaunchKernelGGL((k_pass<P, 2, false>), dim3(waves), block, 0, s, a);
+  else hipLaunchKernelGGL((k_pass<P, -1, false>), dim3(waves), block, 0, s, a);
 }
 
 void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
   a.plans = w.plans;
+  a.roi_w = pl.roi_w;
   a.spec = w.spec;
   a.ustat = w.ustat;
   a.upart = w.upart;
@@ -656,6 +665,17 @@ int sqngd_workspace_size(const sqngd_problem* probs, int32_t nprob, size_t* byte
   if (rc != SQNGD_OK) return rc;
   if (bytes == nullptr) return SQNGD_E_INVALID_ARG;
   *bytes = (size_t)build_plan(probs, nprob)->hdr.total;
+  return SQNGD_OK;
+}
+
+int sqngd_set_roi_weights(const sqngd_problem* probs, int32_t nprob, const float* weights, void* ws,
+                          size_t ws_bytes) {
+  if (!aligned(weights, 4)) return SQNGD_E_ALIGN;
+  const Plan* pl = nullptr;
+  int rc = lookup(probs, nprob, ws, ws_bytes, &pl);
+  if (rc != SQNGD_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  pl->roi_w = weights;
   return SQNGD_OK;
 }
 

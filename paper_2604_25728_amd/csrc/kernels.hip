@@ -148,6 +148,24 @@ __device__ __forceinline__ void roi_scale(float2 (&R)[E], uint32_t vmask, float 
   });
 }
 
+// ROI weights w(tau, f) of eq. 8-9 applied to a row held as R[e] (r-index
+// k = t + TF e holds tau' = -k or P - k of the pass's orientation; the table
+// row wrow = w(., f) is indexed by the original delay tau + N - 1, with
+// tau = tau' in orientation 0 and -tau' in the role-swapped orientation 1).
+// Cells that hold no delay get 0.
+template <int P, int TF, int E>
+__device__ __forceinline__ void roi_weigh(float2 (&R)[E], int t, int N, int orient, const float* wrow) {
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    const int k = t + TF * e;
+    const bool lo = k <= N - 1, hi = k >= P - N + 1;
+    const int tp = lo ? -k : P - k;
+    const int tau = orient ? -tp : tp;
+    const float wv = (lo || hi) ? wrow[tau + N - 1] : 0.f;
+    R[e] = cscale(R[e], wv);
+  });
+}
+
 // AF cells of one row into the cube [w][g][f][tau + N - 1] (scaled by 1/P).
 template <int P, int TF, int E>
 __device__ __forceinline__ void cube_store(const float2 (&R)[E], int t, int N, float2* row) {
@@ -399,6 +417,7 @@ struct PassArgs {
   int32_t want_grad;
   int32_t pad;
   int32_t* bump;  // if set, block 0 advances this step counter (deferred by the previous finalize)
+  const float* roi_w;  // ROI weights [F][2N-1] per problem (plan offset off_rw), or null for w = 1
   const float2* self_w;
   const float2* spec;
   UnitStat* ustat;
@@ -409,7 +428,9 @@ struct PassArgs {
 };
 
 
-template <int P, int PHLOG>
+// WT: the launch carries ROI weights (a separate instantiation, so that the
+// unweighted pass keeps its registers).
+template <int P, int PHLOG, bool WT>
 __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
   using G = PassGeom<P>;
   constexpr int kPassWaves = pass_waves(P);
@@ -458,6 +479,7 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
   const int whi = a.orient ? -pl.tau_lo : pl.tau_hi;
   const float phm1 = 0.5f * pl.p - 1.0f;
   const bool grad = a.want_grad != 0;
+  const float* wrow = WT ? a.roi_w + pl.off_rw + (int64_t)f * (2 * N - 1) : nullptr;
 
   TwiddlesG<G> W;
   W.init(t);
@@ -548,8 +570,9 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
     uint32_t vmask;
     float qmax;
     int kbest;
-    roi_scan<P, TF, E>(R, t, N, wlo, whi, g == w, vmask, qmax, kbest);
     if (cube != nullptr && active) cube_store<P, TF, E>(R, t, N, cube + ((int64_t)(w * M + g) * F + f) * T2);
+    if constexpr (WT) roi_weigh<P, TF, E>(R, t, N, a.orient, wrow);  // a = w |A| / N from here on
+    roi_scan<P, TF, E>(R, t, N, wlo, whi, g == w, vmask, qmax, kbest);
     // this lane's largest cell of the pair (lowest index among equal values)
     const unsigned long long key = vmask ? make_key(qmax, (uint32_t)(((int64_t)u * M + g) * P + kbest)) : 0ull;
     if (g == w) kauto = umax64(kauto, key);
@@ -571,6 +594,7 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
     }
     // a/sigma = x^(1/2), x = |r|^2 / sigma^2:  S += x^(p/2);  G~ = x^(p/2 - 1) r / sigma
     roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? 1.0f / sigma : 0.f, phm1, S);
+    if constexpr (WT) roi_weigh<P, TF, E>(R, t, N, a.orient, wrow);  // d(w|r|)^p / dr carries w^2
     if (grad) {
       op = OP_ADJ;
     } else if (++g < M) {
@@ -1946,7 +1970,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
 // combined per unit in LDS (relative to the unit's largest pair scale), then
 // the units per block as in k_pass. Every wave computes its unit's modulated
 // spectrum itself. Needs one FFT per wave (P >= 512) and M <= WV.
-template <int P, int PHLOG, int WV>
+template <int P, int PHLOG, int WV, bool WT>
 __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   using G = Geom<P>;
   static_assert(G::TF == 64, "one FFT per wave");
@@ -1989,6 +2013,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   const int whi = a.orient ? -pl.tau_lo : pl.tau_hi;
   const float phm1 = 0.5f * pl.p - 1.0f;
   const bool grad = a.want_grad != 0;
+  const float* wrow = WT ? a.roi_w + pl.off_rw + (int64_t)f * (2 * N - 1) : nullptr;
 
   // global loads first, then the arithmetic that hides their latency
   const float2* sg = a.spec + pl.ws_spec + (int64_t)(wave_on ? g : 0) * P;
@@ -2041,9 +2066,10 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   uint32_t vmask;
   float qmax;
   int kbest;
-  roi_scan<P, 64, E>(R, t, N, wlo, whi, g == w, vmask, qmax, kbest);
   if (a.cube != nullptr && active)
     cube_store<P, 64, E>(R, t, N, a.cube + pl.off_cube + ((int64_t)(w * M + g) * F + f) * (2 * N - 1));
+  if constexpr (WT) roi_weigh<P, 64, E>(R, t, N, a.orient, wrow);  // a = w |A| / N from here on
+  roi_scan<P, 64, E>(R, t, N, wlo, whi, g == w, vmask, qmax, kbest);
   // wave maximum, and its cell from the lowest lane that holds it
   const float qw = wave_max(qmax);
   const unsigned long long holders = __ballot(vmask != 0 && qmax == qw);
@@ -2053,6 +2079,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   const float sigma = sqrtf(qw);
   float S = 0.f;
   roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? 1.0f / sigma : 0.f, phm1, S);
+  if constexpr (WT) roi_weigh<P, 64, E>(R, t, N, a.orient, wrow);  // d(w|r|)^p / dr carries w^2
   S = wave_sum(S);
   if (t == 0) {
     g_sig[wv] = active ? sigma : 0.f;

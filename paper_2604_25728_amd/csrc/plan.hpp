@@ -25,7 +25,7 @@ struct ProbPlan {
   int64_t ws_spec;   // complex: [M][P] spectra
   int64_t ws_unit;   // UnitStat index and row index of upart ([units][N] complex, stride N)
   int64_t ws_upart;  // complex offset of this problem's unit partials
-  int64_t pad;
+  int64_t off_rw;    // float offset of this problem's ROI weights [F][2N-1]
 };
 static_assert(sizeof(ProbPlan) == 152, "ProbPlan layout");
 

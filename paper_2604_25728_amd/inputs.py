@@ -112,6 +112,21 @@ def unimodular(M: int, N: int, seed: int) -> np.ndarray:
     return np.exp(2j * np.pi * rng.random((M, N))).astype(np.complex64)
 
 
+def roi_weights(prob: dict, seed: int, lo: float = 0.25, hi: float = 2.0) -> np.ndarray:
+    """Weights w(tau, f) of eq. 8-9 for a problem: i.i.d. U[lo, hi) as float32
+    [F][2N-1] (tau + N - 1 fastest), so that every cell of the delay-Doppler
+    grid carries its own weight."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=(prob["F"], 2 * prob["N"] - 1)).astype(np.float32)
+
+
+def roi_window_weights(prob: dict, half_width: int) -> np.ndarray:
+    """0/1 weights of a delay window |tau| <= half_width at every Doppler bin
+    (the paper's fixed ROI tau in [-50, 50] is half_width = 50), float32 [F][2N-1]."""
+    tau = np.arange(-(prob["N"] - 1), prob["N"])
+    return np.tile((np.abs(tau) <= half_width).astype(np.float32), (prob["F"], 1))
+
+
 def noise(M: int, N: int, seed: int) -> np.ndarray:
     """The warm-start network's input noise, N(0, 1) [M][N] float32."""
     rng = np.random.default_rng(seed)

@@ -23,7 +23,7 @@ SCHED_AUTO, SCHED_THROUGHPUT, SCHED_SPLIT8, SCHED_SPLIT12, SCHED_SPLIT16 = 0, 1,
 SYMBOLS = [
     "sqngd_buffer_sizes", "sqngd_workspace_size", "sqngd_workspace_init", "sqngd_af_forward",
     "sqngd_af_backward", "sqngd_step", "sqngd_run", "sqngd_hard_quantize", "sqngd_status_string",
-    "sqngd_last_hip_error", "sqngd_profile_enable", "sqngd_profile_read",
+    "sqngd_last_hip_error", "sqngd_profile_enable", "sqngd_profile_read", "sqngd_set_roi_weights",
 ]
 
 
@@ -68,6 +68,7 @@ def load():
     lib.sqngd_buffer_sizes.argtypes = [P, i32, P, P, P, P]
     lib.sqngd_workspace_size.argtypes = [P, i32, P]
     lib.sqngd_workspace_init.argtypes = [P, i32, P, sz, P]
+    lib.sqngd_set_roi_weights.argtypes = [P, i32, P, P, sz]
     lib.sqngd_af_forward.argtypes = [P, i32, P, i32, P, P, P, P, P, sz, P]
     lib.sqngd_af_backward.argtypes = [P, i32, P, i32, P, P, P, P, P, P, P, P, sz, P]
     lib.sqngd_step.argtypes = [P, i32, P, P, P, P, P, P, P, sz, P]
@@ -179,6 +180,7 @@ class Batch:
         self._ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
         check(self.lib.sqngd_workspace_init(self._arr, self.n, self._ws_ptr, self.ws_bytes,
                                             _stream()), "workspace_init")
+        self.roi_w = None
         # element offsets of each problem in the packed buffers
         self.off_z, self.off_w, self.off_cube, self.off_adam = [], [], [], []
         oz = ow = oc = oa = 0
@@ -191,6 +193,25 @@ class Batch:
             ow += p["M"] * p["N"]
             oc += p["M"] * p["M"] * p["F"] * (2 * p["N"] - 1)
             oa += 2 * p["M"] * p["N"] * p["L"] + 4 * p["M"] * p["N"]
+
+    def set_roi_weights(self, ws=None):
+        """Attach the ROI weights w(tau, f) of eq. 8-9: a list of [F][2N-1]
+        arrays (one per problem, None entries meaning w = 1) or None for w = 1
+        everywhere. The packed device copy is kept by the batch."""
+        import torch
+        if ws is None or all(w is None for w in ws):
+            self.roi_w = None
+        else:
+            parts = []
+            for p, w in zip(self.probs, ws):
+                shape = (p["F"], 2 * p["N"] - 1)
+                w = np.ones(shape, np.float32) if w is None else np.asarray(w, np.float32)
+                if w.shape != shape:
+                    raise ValueError(f"ROI weights of shape {w.shape}, expected {shape}")
+                parts.append(torch.as_tensor(w).reshape(-1))
+            self.roi_w = torch.cat(parts).to(self.device)
+        check(self.lib.sqngd_set_roi_weights(self._arr, self.n, _ptr(self.roi_w), self._ws_ptr, self.ws_bytes),
+              "set_roi_weights")
 
     # -------------------------------------------------------------- packing
     def pack_z(self, zs):
@@ -216,6 +237,12 @@ class Batch:
         """Problem i's Adam state (flat: m_z, v_z, m_h, v_h as in SQNGD_ADAM_FLOATS)."""
         p = self.probs[i]
         return t[self.off_adam[i]: self.off_adam[i] + 2 * p["M"] * p["N"] * p["L"] + 4 * p["M"] * p["N"]]
+
+    def unpack_roi(self, i):
+        """Problem i's attached ROI weights [F][2N-1] (a view of the packed copy)."""
+        off = sum(q["F"] * (2 * q["N"] - 1) for q in self.probs[:i])
+        p = self.probs[i]
+        return self.roi_w[off: off + p["F"] * (2 * p["N"] - 1)].reshape(p["F"], 2 * p["N"] - 1)
 
     def unpack_cube(self, t, i):
         p = self.probs[i]

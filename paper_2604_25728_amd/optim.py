@@ -21,10 +21,11 @@ class SQNGD:
     (inputs.make_opt); seeds: one seed per problem for the N(0,1) logits, or
     z0: a list of [M][N][L] float32 arrays to start from instead."""
 
-    def __init__(self, probs, opt: dict, seeds=None, z0=None, device="cuda", schedule=None):
+    def __init__(self, probs, opt: dict, seeds=None, z0=None, device="cuda", schedule=None, roi_weights=None):
         """schedule: None keeps each problem's hint (default automatic), an
         int applies that SQNGD_SCHED_* hint to every problem, "tune" times the
-        candidates first (tune.tune) and applies the fastest."""
+        candidates first (tune.tune) and applies the fastest. roi_weights: one
+        [F][2N-1] array (or None) per problem, the w(tau, f) of eq. 8-9."""
         if schedule == "tune":
             from . import tune
             schedule, _ = tune.tune(probs, opt)
@@ -32,6 +33,8 @@ class SQNGD:
             probs = [dict(p, schedule=int(schedule)) for p in probs]
         self.schedule = schedule
         self.batch = nat.Batch(probs, device=device)
+        if roi_weights is not None:
+            self.batch.set_roi_weights(roi_weights)
         self.probs = self.batch.probs
         self.opt_dict = dict(opt)
         self.opt = nat.make_opt(opt)
@@ -96,6 +99,8 @@ class SQNGD:
         new = SQNGD.__new__(SQNGD)
         new.schedule = self.schedule
         new.batch = nat.Batch([self.probs[i] for i in keep], device=self.batch.device)
+        if self.batch.roi_w is not None:
+            new.batch.set_roi_weights([self.batch.unpack_roi(i).cpu().numpy() for i in keep])
         new.probs = new.batch.probs
         new.opt_dict = dict(self.opt_dict)
         new.opt = nat.make_opt(self.opt_dict)

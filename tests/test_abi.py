@@ -197,3 +197,18 @@ def test_net_validation(nat):
     assert lib.sqngd_net_backward(ctypes.byref(ok), None, None, None, dummy, None, dummy, 1 << 40, None) == -1
     o = NN.NetOpt(1e-3, 0.9, 0.999, 1e-8)
     assert lib.sqngd_net_adam(ctypes.byref(ok), ctypes.byref(o), 0, dummy, dummy, dummy, None) == -1
+
+
+def test_set_roi_weights_validation(nat):
+    """Argument checks of sqngd_set_roi_weights run before any HIP call."""
+    import ctypes
+    lib = nat.load()
+    probs = nat.make_problems([I.config("m2n64")["problem"]])
+    ws = ctypes.create_string_buffer(1 << 16)
+    base = (ctypes.addressof(ws) + 255) // 256 * 256
+    # a misaligned weight pointer
+    assert lib.sqngd_set_roi_weights(probs, 1, ctypes.c_void_p(base + 2), ctypes.c_void_p(base), 1 << 15) == -4
+    # no problems
+    assert lib.sqngd_set_roi_weights(None, 1, None, ctypes.c_void_p(base), 1 << 15) == -1
+    # a workspace that was never initialised for this batch
+    assert lib.sqngd_set_roi_weights(probs, 1, None, ctypes.c_void_p(base), 1 << 15) in (-3,)

@@ -69,8 +69,8 @@
  * bad call returns a negative status without touching the device:
  *   SQNGD_E_INVALID_ARG  shape, p, weight or mode out of range; NULL required
  *                        pointer;
- *   SQNGD_E_UNSUPPORTED  N above 1024 (the FFT length 2^ceil(log2(2N-1)) would
- *                        exceed 2048), M above 16, L above 64, F above 4096,
+ *   SQNGD_E_UNSUPPORTED  N above 2048 (the FFT length 2^ceil(log2(2N-1)) would
+ *                        exceed 4096), M above 16, L above 64, F above 4096,
  *                        or M*M*F*P >= 2^32 (P the FFT length);
  *   SQNGD_E_WORKSPACE    ws_bytes smaller than sqngd_workspace_size, or the
  *                        workspace was not initialised for this batch;
@@ -121,7 +121,7 @@ typedef struct {
    weighting, SNRL target) plus the p of the p-norm surrogate. 64 bytes. */
 typedef struct {
   int32_t M;              /* waveforms = receive filters, 1..16                  */
-  int32_t N;              /* chips per waveform, 2..1024                         */
+  int32_t N;              /* chips per waveform, 2..2048                         */
   int32_t L;              /* phase levels (paper B), 2..64                       */
   int32_t F;              /* Doppler bins, >= 1                                  */
   float nu_min, nu_max;   /* Doppler span (normalised as in eq. 6), nu_min<=nu_max */

@@ -80,7 +80,7 @@ int choose_split_waves(int P, const sqngd_problem* probs, const std::vector<int>
 
 int validate_problem(const sqngd_problem& p) {
   if (p.M < 1 || p.N < 2 || p.L < 2 || p.F < 1) return SQNGD_E_INVALID_ARG;
-  if (p.M > 16 || p.N > 1024 || p.L > 64 || p.F > 4096) return SQNGD_E_UNSUPPORTED;
+  if (p.M > 16 || p.N > 2048 || p.L > 64 || p.F > 4096) return SQNGD_E_UNSUPPORTED;
   const double P = fft_len(p.N);
   if ((double)p.M * p.M * p.F * P >= 4294967296.0) return SQNGD_E_UNSUPPORTED;
   if (!finite(p.nu_min) || !finite(p.nu_max) || p.nu_min > p.nu_max) return SQNGD_E_INVALID_ARG;
@@ -434,7 +434,8 @@ void launch_prep(const Plan& pl, const Ptrs& w, PrepArgs a, hipStream_t s) {
       case 1: launch_prep_p<256>(a, waves, s); break;
       case 2: launch_prep_p<512>(a, waves, s); break;
       case 3: launch_prep_p<1024>(a, waves, s); break;
-      default: launch_prep_p<2048>(a, waves, s); break;
+      case 4: launch_prep_p<2048>(a, waves, s); break;
+      default: launch_prep_p<4096>(a, waves, s); break;
     }
   }
 }
@@ -508,7 +509,8 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
           case 1: launch_pass_p<256>(a, phl, waves, s); break;
           case 2: launch_pass_p<512>(a, phl, waves, s); break;
           case 3: launch_pass_p<1024>(a, phl, waves, s); break;
-          default: launch_pass_p<2048>(a, phl, waves, s); break;
+          case 4: launch_pass_p<2048>(a, phl, waves, s); break;
+          default: launch_pass_p<4096>(a, phl, waves, s); break;
         }
       }
     }
@@ -572,7 +574,9 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
       continue;
     }
     FinArgs af = a;
-    if (a.mode == FIN_STEP_A || a.mode == FIN_STEP_B) {
+    // k_final at P = 4096 holds two chips per thread and always takes its
+    // gradient rows from k_grad
+    if (a.mode == FIN_STEP_A || a.mode == FIN_STEP_B || (a.mode == FIN_GRAD && g + kMinLogP >= 12)) {
       // gradient rows by the wide kernel first; k_final then skips the partial sums
       af.grad_chunks = (1 << (g + kMinLogP)) / (2 * kGradChips);
       af.grad_nprob = pl.hdr.group_n[g];
@@ -586,7 +590,8 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
       case 1: hipLaunchKernelGGL(k_final<256>, grid, block, 0, s, af); break;
       case 2: hipLaunchKernelGGL(k_final<512>, grid, block, 0, s, af); break;
       case 3: hipLaunchKernelGGL(k_final<1024>, grid, block, 0, s, af); break;
-      default: hipLaunchKernelGGL(k_final<2048>, grid, block, 0, s, af); break;
+      case 4: hipLaunchKernelGGL(k_final<2048>, grid, block, 0, s, af); break;
+      default: hipLaunchKernelGGL(k_final<4096>, grid, block, 0, s, af); break;
     }
   }
 }

@@ -181,21 +181,40 @@ struct GeomT {
   static constexpr int TF = TF_;                     // lanes per FFT
   static constexpr int E = P / TF;                   // elements per lane
   static constexpr int A = TF >= 32 ? 8 : 4;
-  static constexpr int B = TF / A;
+  // The length-TF DFT over the lanes runs as radix-A then radix-B stages
+  // (two LDS exchanges) when every lane's E elements tile both radices, else
+  // as radix-A, radix-B = E and radix-C stages (three exchanges).
+  static constexpr bool THREE = E % (TF / A) != 0;
+  static constexpr int B = THREE ? E : TF / A;
+  static constexpr int C = THREE ? TF / (A * B) : 1;
+  static constexpr int BC = B * C;
   static constexpr int SLOTS = TF <= 64 ? 64 / TF : 1;  // FFTs per wave
   static constexpr int WAVES = TF > 64 ? TF / 64 : 1;   // waves per FFT
   static constexpr int LDS = 64 * E;                 // float2 per wave
-  static_assert(E % A == 0 && E % B == 0, "register blocks must tile E");
+  static_assert(A * B * C == TF, "the lane radices factor TF");
+  static_assert(E % A == 0 && E % B == 0 && E % C == 0, "register blocks must tile E");
   static_assert(TF <= 64 ? 64 % TF == 0 : TF % 64 == 0, "an FFT fills whole waves or divides one");
   // spectral-layout bin of lane t, register e
   __device__ static constexpr int spec_bin(int t, int e) {
-    int gamma = t % A, k1 = (e / B) * B + t / A, delta = e % B;
-    return k1 + E * (gamma + A * delta);
+    if constexpr (!THREE) {
+      int gamma = t % A, k1 = (e / B) * B + t / A, delta = e % B;
+      return k1 + E * (gamma + A * delta);
+    } else {
+      const int q3 = t / (A * B), gamma = (t % (A * B)) / B, zeta = t % B;
+      const int k1 = (e / C) * C + q3, eta = e % C;
+      return k1 + E * (gamma + A * (zeta + B * eta));
+    }
   }
   // the inverse: storage index e * TF + t of bin k
   __device__ static constexpr int spec_index(int k) {
-    const int k1 = k % E, r = k / E, gamma = r % A, delta = r / A;
-    return ((k1 / B) * B + delta) * TF + (k1 % B) * A + gamma;
+    const int k1 = k % E, r = k / E, gamma = r % A;
+    if constexpr (!THREE) {
+      const int delta = r / A;
+      return ((k1 / B) * B + delta) * TF + (k1 % B) * A + gamma;
+    } else {
+      const int r2 = r / A, zeta = r2 % B, eta = r2 / B;
+      return ((k1 / C) * C + eta) * TF + (k1 % C) * (A * B) + gamma * B + zeta;
+    }
   }
 };
 template <int P>
@@ -228,7 +247,8 @@ struct TwiddlesG {
   static constexpr int NHI = G::E / NLO;
   float2 lo[NLO];  // W_P^(t b),        b < NLO
   float2 hi[NHI];  // W_P^(t NLO a),    a < NHI     (W_P^(t k1) = lo[k1 % NLO] hi[k1 / NLO])
-  float2 col[G::A];  // W_TF^(beta gamma), gamma < A, beta = t % B
+  float2 col[G::A];  // W_TF^(beta gamma), gamma < A, beta = t % (B C)
+  float2 col2[G::THREE ? G::B : 1];  // three stages: W_(B C)^(c zeta), zeta < B, c = t % C
   __device__ __forceinline__ void init(int t) {
     // lo: powers 1, 2, 4 exact; 3, 5, 6, 7 as products
     lo[0] = make_float2(1.f, 0.f);
@@ -243,7 +263,7 @@ struct TwiddlesG {
     }
     hi[0] = make_float2(1.f, 0.f);
     for (int a = 1; a < NHI; ++a) hi[a] = tw_exact<P>(t * NLO * a);
-    const int beta = t % G::B;
+    const int beta = t % G::BC;
     col[0] = make_float2(1.f, 0.f);
     if constexpr (G::A > 1) col[1] = tw_exact<P>(beta * G::E);
     if constexpr (G::A > 2) col[2] = tw_exact<P>(2 * beta * G::E);
@@ -254,6 +274,11 @@ struct TwiddlesG {
       col[6] = cmul(col[4], col[2]);
       col[7] = cmul(col[4], col[3]);
     }
+    if constexpr (G::THREE) {
+      const int c = t % G::C;
+      col2[0] = make_float2(1.f, 0.f);
+      for (int z = 1; z < G::B; ++z) col2[z] = tw_exact<P>(c * z * G::E * G::A);
+    }
   }
   // The same twiddles read from a table tab[k] = W_P^k, k < P (a block
   // computes the table once instead of every wave its own sincospi values).
@@ -262,9 +287,14 @@ struct TwiddlesG {
     for (int b = 1; b < NLO; ++b) lo[b] = tab[(t * b) & (P - 1)];
     hi[0] = make_float2(1.f, 0.f);
     for (int a = 1; a < NHI; ++a) hi[a] = tab[(t * NLO * a) & (P - 1)];
-    const int beta = t % G::B;
+    const int beta = t % G::BC;
     col[0] = make_float2(1.f, 0.f);
     for (int g = 1; g < G::A; ++g) col[g] = tab[(g * beta * G::E) & (P - 1)];
+    if constexpr (G::THREE) {
+      const int c = t % G::C;
+      col2[0] = make_float2(1.f, 0.f);
+      for (int z = 1; z < G::B; ++z) col2[z] = tab[(c * z * G::E * G::A) & (P - 1)];
+    }
   }
   template <int K1>
   __device__ __forceinline__ float2 step2(float2 v, bool inverse) const {
@@ -278,10 +308,168 @@ struct TwiddlesG {
 template <int P>
 using WaveTwiddles = TwiddlesG<Geom<P>>;
 
-// Forward FFT of one slot: x in natural layout -> x in spectral layout.
-// buf points at this slot's P-element LDS region; t is the lane within the slot.
+// Three-exchange forms (G::THREE): the lane index t = BC alpha + tau with
+// tau = C beta + c; radix-A DFT over alpha (-> gamma), twiddle W_TF^(tau
+// gamma); radix-B DFT over beta (-> zeta), twiddle W_BC^(c zeta); radix-C
+// DFT over c (-> eta). Spectral layout: lane t = q3 A B + gamma B + zeta,
+// register j3 C + eta holds bin k1 + E (gamma + A (zeta + B eta)) with
+// k1 = j3 C + q3.
 template <class G>
-__device__ __forceinline__ void fft_forward_g(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
+__device__ __forceinline__ void fft3_forward(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
+  constexpr int E = G::E, TF = G::TF, A = G::A, B = G::B, C = G::C, BC = G::BC;
+  dft_reg<E, -1, 0>(x);
+  static_for<E>([&](auto kc) {
+    constexpr int k1 = decltype(kc)::value;
+    x[k1] = W.template step2<k1>(x[k1], false);
+  });
+  fft_sync<G>();
+  static_for<E>([&](auto kc) {
+    constexpr int k1 = decltype(kc)::value;
+    buf[k1 * TF + t] = x[k1];
+  });
+  fft_sync<G>();
+  {  // radix A over alpha: lane (q, tau), k1 = j A + q
+    const int tau = t % BC, q = t / BC;
+    static_for<E / A>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      static_for<A>([&](auto ac) {
+        constexpr int al = decltype(ac)::value;
+        x[j * A + al] = buf[(j * A + q) * TF + BC * al + tau];
+      });
+      dft_reg<A, -1, j * A>(x);
+      static_for<A>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        if constexpr (g > 0) x[j * A + g] = cmul(x[j * A + g], W.col[g]);
+      });
+    });
+    fft_sync<G>();
+    static_for<E / A>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      static_for<A>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        buf[(j * A + q) * TF + g * BC + tau] = x[j * A + g];
+      });
+    });
+    fft_sync<G>();
+  }
+  {  // radix B over beta: lane (q2, gamma, c), k1 = j2 B + q2
+    const int q2 = t / (A * C), gamma = (t % (A * C)) / C, c = t % C;
+    static_for<E / B>([&](auto jc) {
+      constexpr int j2 = decltype(jc)::value;
+      const int k1 = j2 * B + q2;
+      static_for<B>([&](auto bc) {
+        constexpr int be = decltype(bc)::value;
+        x[j2 * B + be] = buf[k1 * TF + gamma * BC + C * be + c];
+      });
+      dft_reg<B, -1, j2 * B>(x);
+      static_for<B>([&](auto zc) {
+        constexpr int z = decltype(zc)::value;
+        if constexpr (z > 0) x[j2 * B + z] = cmul(x[j2 * B + z], W.col2[z]);
+      });
+    });
+    fft_sync<G>();
+    static_for<E / B>([&](auto jc) {
+      constexpr int j2 = decltype(jc)::value;
+      const int k1 = j2 * B + q2;
+      static_for<B>([&](auto zc) {
+        constexpr int z = decltype(zc)::value;
+        buf[k1 * TF + gamma * BC + z * C + c] = x[j2 * B + z];
+      });
+    });
+    fft_sync<G>();
+  }
+  {  // radix C over c: lane (q3, gamma, zeta), k1 = j3 C + q3
+    const int q3 = t / (A * B), gamma = (t % (A * B)) / B, zeta = t % B;
+    static_for<E / C>([&](auto jc) {
+      constexpr int j3 = decltype(jc)::value;
+      const int k1 = j3 * C + q3;
+      static_for<C>([&](auto cc) {
+        constexpr int ci = decltype(cc)::value;
+        x[j3 * C + ci] = buf[k1 * TF + gamma * BC + zeta * C + ci];
+      });
+      dft_reg<C, -1, j3 * C>(x);
+    });
+  }
+}
+
+template <class G>
+__device__ __forceinline__ void fft3_inverse(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
+  constexpr int E = G::E, TF = G::TF, A = G::A, B = G::B, C = G::C, BC = G::BC;
+  {  // radix C over eta -> c
+    const int q3 = t / (A * B), gamma = (t % (A * B)) / B, zeta = t % B;
+    static_for<E / C>([&](auto jc) {
+      constexpr int j3 = decltype(jc)::value;
+      dft_reg<C, +1, j3 * C>(x);
+    });
+    fft_sync<G>();
+    static_for<E / C>([&](auto jc) {
+      constexpr int j3 = decltype(jc)::value;
+      const int k1 = j3 * C + q3;
+      static_for<C>([&](auto cc) {
+        constexpr int ci = decltype(cc)::value;
+        buf[k1 * TF + gamma * BC + zeta * C + ci] = x[j3 * C + ci];
+      });
+    });
+    fft_sync<G>();
+  }
+  {  // radix B over zeta -> beta
+    const int q2 = t / (A * C), gamma = (t % (A * C)) / C, c = t % C;
+    static_for<E / B>([&](auto jc) {
+      constexpr int j2 = decltype(jc)::value;
+      const int k1 = j2 * B + q2;
+      static_for<B>([&](auto zc) {
+        constexpr int z = decltype(zc)::value;
+        float2 v = buf[k1 * TF + gamma * BC + z * C + c];
+        if constexpr (z > 0) v = cmulc(v, W.col2[z]);
+        x[j2 * B + z] = v;
+      });
+      dft_reg<B, +1, j2 * B>(x);
+    });
+    fft_sync<G>();
+    static_for<E / B>([&](auto jc) {
+      constexpr int j2 = decltype(jc)::value;
+      const int k1 = j2 * B + q2;
+      static_for<B>([&](auto bc) {
+        constexpr int be = decltype(bc)::value;
+        buf[k1 * TF + gamma * BC + C * be + c] = x[j2 * B + be];
+      });
+    });
+    fft_sync<G>();
+  }
+  {  // radix A over gamma -> alpha
+    const int tau = t % BC, q = t / BC;
+    static_for<E / A>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      static_for<A>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        float2 v = buf[(j * A + q) * TF + g * BC + tau];
+        if constexpr (g > 0) v = cmulc(v, W.col[g]);
+        x[j * A + g] = v;
+      });
+      dft_reg<A, +1, j * A>(x);
+    });
+    fft_sync<G>();
+    static_for<E / A>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      static_for<A>([&](auto ac) {
+        constexpr int al = decltype(ac)::value;
+        buf[(j * A + q) * TF + BC * al + tau] = x[j * A + al];
+      });
+    });
+    fft_sync<G>();
+  }
+  static_for<E>([&](auto kc) {
+    constexpr int k1 = decltype(kc)::value;
+    x[k1] = W.template step2<k1>(buf[k1 * TF + t], true);
+  });
+  dft_reg<E, +1, 0>(x);
+}
+
+// Forward FFT of one slot, two exchanges: x in natural layout -> x in spectral
+// layout. buf points at this slot's P-element LDS region; t is the lane within
+// the slot.
+template <class G>
+__device__ __forceinline__ void fft2_forward(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
   constexpr int E = G::E, TF = G::TF, A = G::A, B = G::B;
   dft_reg<E, -1, 0>(x);
   static_for<E>([&](auto kc) {
@@ -329,9 +517,10 @@ __device__ __forceinline__ void fft_forward_g(float2 (&x)[G::E], float2* buf, in
   });
 }
 
-// Inverse FFT of one slot (unscaled): x in spectral layout -> x in natural layout.
+// Inverse FFT of one slot, two exchanges (unscaled): x in spectral layout -> x
+// in natural layout.
 template <class G>
-__device__ __forceinline__ void fft_inverse_g(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
+__device__ __forceinline__ void fft2_inverse(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
   constexpr int E = G::E, TF = G::TF, A = G::A, B = G::B;
   const int gamma = t % A, q2 = t / A;
   static_for<E / B>([&](auto jc) {
@@ -372,6 +561,17 @@ __device__ __forceinline__ void fft_inverse_g(float2 (&x)[G::E], float2* buf, in
     x[k1] = W.template step2<k1>(buf[k1 * TF + t], true);
   });
   dft_reg<E, +1, 0>(x);
+}
+
+template <class G>
+__device__ __forceinline__ void fft_forward_g(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
+  if constexpr (G::THREE) fft3_forward<G>(x, buf, t, W);
+  else fft2_forward<G>(x, buf, t, W);
+}
+template <class G>
+__device__ __forceinline__ void fft_inverse_g(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
+  if constexpr (G::THREE) fft3_inverse<G>(x, buf, t, W);
+  else fft2_inverse<G>(x, buf, t, W);
 }
 
 template <int P>

@@ -232,26 +232,21 @@ __device__ __forceinline__ int find_entry(const int32_t* base, int n, int wave) 
   return lo;
 }
 
-// Waves per block of the throughput pass: four at P <= 512, two at longer
-// transforms (whose per-wave LDS slices would otherwise allow one block per CU).
-__host__ __device__ constexpr int pass_waves(int P) { return P >= 1024 ? 2 : 4; }
+// Waves per block of the throughput pass: four at P <= 512, two at 1024 and
+// 2048 (whose per-wave LDS slices would otherwise allow one block per CU),
+// four at 4096 (all four share one unit).
+__host__ __device__ constexpr int pass_waves(int P) { return P >= 4096 ? 4 : (P >= 1024 ? 2 : 4); }
 // FFT geometry of the throughput pass: wave-local up to P = 1024; at P = 2048
 // one transform spans the block's two waves (16 elements per lane instead of
-// 32), which keeps the pass's three spectra in registers without spilling.
-template <int P>
-struct PassGeomSel {
-  using type = Geom<P>;
-};
-template <>
-struct PassGeomSel<2048> {
-  using type = GeomT<2048, 128>;
-};
-template <int P>
-using PassGeom = typename PassGeomSel<P>::type;
-// Doppler bins (units) per throughput-pass block
-__host__ __device__ constexpr int pass_upb(int P) {
-  return P >= 2048 ? pass_waves(P) * 64 / 128 : pass_waves(P) * (P >= 512 ? 1 : 64 / (P / 8));
+// 32), which keeps the pass's three spectra in registers without spilling;
+// at P = 4096 it spans four waves (16 elements per lane, three exchanges).
+__host__ __device__ constexpr int pass_tf(int P) {
+  return P >= 4096 ? 256 : (P >= 2048 ? 128 : (P >= 512 ? 64 : P / 8));
 }
+template <int P>
+using PassGeom = GeomT<P, pass_tf(P)>;
+// Doppler bins (units) per throughput-pass block
+__host__ __device__ constexpr int pass_upb(int P) { return pass_waves(P) * 64 / pass_tf(P); }
 // Where a producer's spectral bin k lands in the partner-spectrum rows the
 // pass reads (the pass's own layout).
 template <int P>
@@ -821,14 +816,15 @@ __device__ __forceinline__ void logit_chain(const float* zc, int L, float T, int
 // Spectrum of one row (value v of chip n; threads n >= N pass zero) in the
 // spectral layout of the fused pass, computed by wave 0 of the block; fbuf
 // holds the staged row and then serves as that wave's exchange buffer.
-template <int P>
-__device__ __forceinline__ void row_spectrum(float2 v, int N, float2* fbuf, float2* out) {
+template <int P, int CH>
+__device__ __forceinline__ void row_spectrum(const float2 (&v)[CH], int N, float2* fbuf, float2* out) {
   using G = Geom<P>;
   constexpr int E = G::E, TF = G::TF;
   const int tid = threadIdx.x;
   for (int i = tid; i < P; i += kFinThreads) fbuf[i] = make_float2(0.f, 0.f);
   __syncthreads();
-  if (tid < N) fbuf[tid] = v;
+  for (int c = 0; c < CH; ++c)
+    if (tid + c * kFinThreads < N) fbuf[tid + c * kFinThreads] = v[c];
   __syncthreads();
   if (tid < 64) {
     const int slot = tid / TF, t = tid % TF;
@@ -850,10 +846,17 @@ __device__ __forceinline__ void row_spectrum(float2 v, int N, float2* fbuf, floa
 }
 
 // Mainlobe inner product c' = sum_n conj(part(n)) self(n) and the two
-// energies (eq. 10, 38) of one row, written by thread 0 (one LDS round).
-__device__ __forceinline__ void row_snrl(float2 self, float2 part, float* sh, float4* out) {
-  float v[4] = {part.x * self.x + part.y * self.y, part.x * self.y - part.y * self.x,
-                self.x * self.x + self.y * self.y, part.x * part.x + part.y * part.y};
+// energies (eq. 10, 38) of one row (CH chips per thread), written by thread 0
+// (one LDS round).
+template <int CH>
+__device__ __forceinline__ void row_snrl(const float2 (&self)[CH], const float2 (&part)[CH], float* sh, float4* out) {
+  float v[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < CH; ++c) {
+    v[0] += part[c].x * self[c].x + part[c].y * self[c].y;
+    v[1] += part[c].x * self[c].y - part[c].y * self[c].x;
+    v[2] += self[c].x * self[c].x + self[c].y * self[c].y;
+    v[3] += part[c].x * part[c].x + part[c].y * part[c].y;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
   __syncthreads();
@@ -943,14 +946,17 @@ __device__ __forceinline__ void stats_record(sqngd_stats* out, const ProbPlan& p
 //     the next pass, with per-chip softmax statistics from lane shuffles;
 //  6. forms the next pass's mainlobe products and partner spectrum;
 //  7. writes the statistics record.
+// CH chips per thread: two at P = 4096 (N up to 2048), where the gradient
+// rows always come reduced from k_grad (grad_in).
 template <int P>
 __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
+  constexpr int CH = P >= 4096 ? 2 : 1;
   __shared__ float shf[kFinWaves * 4];
   __shared__ unsigned long long shk[kFinWaves * 2];
   __shared__ float fac[4096];
   __shared__ float2 part[kFinThreads];
-  __shared__ float2 gsh[1024];    // row gradient of each chip
-  __shared__ float2 nsh[1024];    // quantised waveform of each chip for the next pass
+  __shared__ float2 gsh[CH * kFinThreads];  // row gradient of each chip
+  __shared__ float2 nsh[CH * kFinThreads];  // quantised waveform of each chip for the next pass
   __shared__ float4 snrl_sh[16];
   __shared__ float2 fbuf[Geom<P>::LDS];
   const int tid = threadIdx.x;
@@ -970,7 +976,7 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
   if (a.mode == FIN_STATS && m != 0) return;
   const UnitStat* us = a.ustat + pl.ws_unit;
   const float p = pl.p;
-  const int n = tid;
+  const int n = tid;  // chip of slot c: n + c * kFinThreads
   const bool on = n < N;
   const bool upd = a.mode != FIN_STATS;
   const int64_t wrow = pl.off_w + (int64_t)m * N;
@@ -988,16 +994,21 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
   }
 
   // ---- 1. loads
-  float2 pw = make_float2(0.f, 0.f), hv = make_float2(0.f, 0.f);
-  float4 mvh = make_float4(0.f, 0.f, 0.f, 0.f);
+  float2 pw = make_float2(0.f, 0.f), hv[CH];
+  float4 mvh[CH];
   float* mh = a.adam + pl.off_state + 2 * (int64_t)M * N * L + 2 * crow;
   float* vh = mh + 2 * (int64_t)M * N;
-  if (upd && on) {
-    pw = a.part_w[wrow + n];
-    if (a.mode == FIN_STEP_A || a.mode == FIN_STEP_B) hv = a.h[wrow + n];
-    if (a.mode == FIN_STEP_A) {
-      const float2 m2 = *(const float2*)(mh + 2 * n), v2 = *(const float2*)(vh + 2 * n);
-      mvh = make_float4(m2.x, m2.y, v2.x, v2.y);
+  if (upd && on) pw = a.part_w[wrow + n];
+  for (int c = 0; c < CH; ++c) {
+    const int nc = n + c * kFinThreads;
+    hv[c] = make_float2(0.f, 0.f);
+    mvh[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (upd && nc < N) {
+      if (a.mode == FIN_STEP_A || a.mode == FIN_STEP_B) hv[c] = a.h[wrow + nc];
+      if (a.mode == FIN_STEP_A) {
+        const float2 m2 = *(const float2*)(mh + 2 * nc), v2 = *(const float2*)(vh + 2 * nc);
+        mvh[c] = make_float4(m2.x, m2.y, v2.x, v2.y);
+      }
     }
   }
   const float fsig = upd && tid < NE ? us[m * NE + tid].sigma : 0.f;
@@ -1081,16 +1092,20 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
   const float loss = pl.w_psl * lp_raw * pl.inv_NP + pl.w_snrl * l_snrl;
   const bool bad = !isfinite(loss);
 
-  float2 g = make_float2(0.f, 0.f);
+  float2 g[CH];
+  for (int c = 0; c < CH; ++c) g[c] = make_float2(0.f, 0.f);
   bool skip = true;
   if (upd) {
     // ---- 3. row gradient: sum_f (w_psl/(N P)) (sigma_u/lp_raw)^(p-1) partial_u + G'_S part_m
     // (or the rows k_grad reduced already, SNRL term included)
     if (a.grad_in != nullptr) {
       const float gl = a.grad_loss ? a.grad_loss[pid] : 1.0f;
-      if (on) {
-        g = cscale(a.grad_in[wrow + n], gl);
-        gsh[n] = g;
+      for (int c = 0; c < CH; ++c) {
+        const int nc = n + c * kFinThreads;
+        if (nc < N) {
+          g[c] = cscale(a.grad_in[wrow + nc], gl);
+          gsh[nc] = g[c];
+        }
       }
     } else {
     for (int j = tid; j < NE; j += kFinThreads)
@@ -1127,37 +1142,49 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
       gS = cscale(make_float2(cm.x, cm.y),
                   pl.w_snrl * (2.0f / (float)M) * (magm / (float)N - pl.p_tar) / ((float)N * magm));
     if (on) {
-      for (int s = 0; s < FS; ++s) g = cadd(g, part[s * Nc + n]);
-      g = cscale(cadd(g, cmul(gS, pw)), gl);
-      gsh[n] = g;
+      for (int s = 0; s < FS; ++s) g[0] = cadd(g[0], part[s * Nc + n]);
+      g[0] = cscale(cadd(g[0], cmul(gS, pw)), gl);
+      gsh[n] = g[0];
     }
     }
-    const int rowbad = __syncthreads_or(on && (!isfinite(g.x) || !isfinite(g.y)));
+    bool chipbad = false;
+    for (int c = 0; c < CH; ++c)
+      chipbad |= n + c * kFinThreads < N && (!isfinite(g[c].x) || !isfinite(g[c].y));
+    const int rowbad = __syncthreads_or(chipbad);
     skip = bad || rowbad;
 
     // ---- 4. per chip
-    if (a.mode == FIN_GRAD && on && a.grad_w) a.grad_w[wrow + n] = g;
+    for (int c = 0; c < CH; ++c)
+      if (a.mode == FIN_GRAD && n + c * kFinThreads < N && a.grad_w) a.grad_w[wrow + n + c * kFinThreads] = g[c];
     if (a.mode == FIN_STEP_A) {
       // Adam on (Re h, Im h), then h <- h sqrt(N / |h|^2) (eq. 32)
       const int k = tstep * a.opt.n_h + a.inner + 1;
       const float b1 = a.opt.beta1, b2 = a.opt.beta2;
       const float bc1 = 1.0f - powf(b1, (float)k), bc2 = 1.0f - powf(b2, (float)k);
-      if (on && !skip) {
-        if (a.opt.flags & SQNGD_OPT_SGD) {
-          hv.x -= a.opt.lr_h * g.x;
-          hv.y -= a.opt.lr_h * g.y;
-        } else {
-          const float mx2 = b1 * mvh.x + (1.0f - b1) * g.x, my2 = b1 * mvh.y + (1.0f - b1) * g.y;
-          const float vx = b2 * mvh.z + (1.0f - b2) * g.x * g.x, vy = b2 * mvh.w + (1.0f - b2) * g.y * g.y;
-          *(float2*)(mh + 2 * n) = make_float2(mx2, my2);
-          *(float2*)(vh + 2 * n) = make_float2(vx, vy);
-          hv.x -= a.opt.lr_h * (mx2 / bc1) / (sqrtf(vx / bc2) + a.opt.eps);
-          hv.y -= a.opt.lr_h * (my2 / bc1) / (sqrtf(vy / bc2) + a.opt.eps);
+      float esum = 0.f;
+      for (int c = 0; c < CH; ++c) {
+        const int nc = n + c * kFinThreads;
+        if (nc < N && !skip) {
+          if (a.opt.flags & SQNGD_OPT_SGD) {
+            hv[c].x -= a.opt.lr_h * g[c].x;
+            hv[c].y -= a.opt.lr_h * g[c].y;
+          } else {
+            const float mx2 = b1 * mvh[c].x + (1.0f - b1) * g[c].x, my2 = b1 * mvh[c].y + (1.0f - b1) * g[c].y;
+            const float vx = b2 * mvh[c].z + (1.0f - b2) * g[c].x * g[c].x;
+            const float vy = b2 * mvh[c].w + (1.0f - b2) * g[c].y * g[c].y;
+            *(float2*)(mh + 2 * nc) = make_float2(mx2, my2);
+            *(float2*)(vh + 2 * nc) = make_float2(vx, vy);
+            hv[c].x -= a.opt.lr_h * (mx2 / bc1) / (sqrtf(vx / bc2) + a.opt.eps);
+            hv[c].y -= a.opt.lr_h * (my2 / bc1) / (sqrtf(vy / bc2) + a.opt.eps);
+          }
         }
+        esum += hv[c].x * hv[c].x + hv[c].y * hv[c].y;
       }
-      const float e2 = block_sum(hv.x * hv.x + hv.y * hv.y, shf);
-      hv = cscale(hv, skip ? 1.0f : sqrtf((float)N / e2));
-      if (on) a.h[wrow + n] = hv;
+      const float e2 = block_sum(esum, shf);
+      for (int c = 0; c < CH; ++c) {
+        hv[c] = cscale(hv[c], skip ? 1.0f : sqrtf((float)N / e2));
+        if (n + c * kFinThreads < N) a.h[wrow + n + c * kFinThreads] = hv[c];
+      }
     }
 
     // ---- 5. logit side, one thread per (chip, level)
@@ -1243,19 +1270,25 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
   // ---- 6. inputs of the next pass
   if (a.next != NEXT_NONE) {
     __syncthreads();
-    float2 self = hv, prt = hv, sp = hv;
-    if (next_soft) {
-      self = on ? nsh[n] : make_float2(0.f, 0.f);
-      if (on) a.wself[wrow + n] = self;
-    } else if (next_hard) {
-      prt = on ? nsh[n] : make_float2(0.f, 0.f);
-      sp = prt;
-      if (on) a.wpart[wrow + n] = prt;
-    } else {  // NEXT_A_SNRL
-      prt = on ? a.wpart[wrow + n] : make_float2(0.f, 0.f);
+    float2 self[CH], prt[CH], sp[CH];
+    for (int c = 0; c < CH; ++c) {
+      const int nc = n + c * kFinThreads;
+      const bool onc = nc < N;
+      self[c] = prt[c] = sp[c] = hv[c];
+      if (next_soft) {
+        self[c] = onc ? nsh[nc] : make_float2(0.f, 0.f);
+        if (onc) a.wself[wrow + nc] = self[c];
+      } else if (next_hard) {
+        prt[c] = onc ? nsh[nc] : make_float2(0.f, 0.f);
+        sp[c] = prt[c];
+        if (onc) a.wpart[wrow + nc] = prt[c];
+      } else {  // NEXT_A_SNRL
+        prt[c] = onc ? a.wpart[wrow + nc] : make_float2(0.f, 0.f);
+      }
     }
-    row_snrl(self, prt, shf, a.snrl_next + r);
-    if (a.next == NEXT_B_FULL || next_hard) row_spectrum<P>(sp, N, fbuf, a.spec + pl.ws_spec + (int64_t)m * P);
+    row_snrl<CH>(self, prt, shf, a.snrl_next + r);
+    if (a.next == NEXT_B_FULL || next_hard)
+      row_spectrum<P, CH>(sp, N, fbuf, a.spec + pl.ws_spec + (int64_t)m * P);
   }
 
   // ---- 7. statistics record
@@ -1576,7 +1609,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
 // when k_step reduces the gradient rows itself (FG).
 __host__ __device__ constexpr int step_tpc(int P) { return P >= 256 ? 2 * kStepThreads / P : 8; }
 __host__ __device__ constexpr int step_fg_loads(int P) {
-  return 48 / step_tpc(P) < 32 ? 48 / step_tpc(P) : 32;
+  return step_tpc(P) < 1 ? 0 : (48 / step_tpc(P) < 32 ? 48 / step_tpc(P) : 32);
 }
 
 // FG: the block also does k_grad's work for its row (the problem's L_p and

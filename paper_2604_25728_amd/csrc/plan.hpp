@@ -6,7 +6,7 @@
 
 namespace sq {
 
-constexpr int kNumPGroups = 5;  // FFT lengths 128, 256, 512, 1024, 2048
+constexpr int kNumPGroups = 6;  // FFT lengths 128, 256, 512, 1024, 2048, 4096
 constexpr int kMinLogP = 7;
 
 // One problem of the batch. Offsets are element offsets: off_z into z-sized

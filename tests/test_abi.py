@@ -90,7 +90,7 @@ def test_workspace_size_and_buffer_sizes(nat):
 
 
 @pytest.mark.parametrize("field,value,code", [
-    ("M", 0, -1), ("M", 17, -2), ("N", 1, -1), ("N", 1025, -2), ("L", 1, -1), ("L", 65, -2),
+    ("M", 0, -1), ("M", 17, -2), ("N", 1, -1), ("N", 2049, -2), ("L", 1, -1), ("L", 65, -2),
     ("F", 0, -1), ("F", 4097, -2), ("p", 1.5, -1), ("p", 65.0, -1), ("p", float("nan"), -1),
     ("temperature", 0.0, -1), ("w_psl", -1.0, -1), ("snrl_target_db", -0.1, -1),
     ("tau_lo", -64, -1), ("tau_hi", 64, -1), ("sq_mode", 2, -1), ("nu_min", 1.0, -1),

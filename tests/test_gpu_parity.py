@@ -245,8 +245,10 @@ def test_autotuner_picks_a_candidate(nat):
 
 
 EDGE = {
-    # the largest shapes the limits allow in M, N and L (FFT length 2048), two Doppler bins
+    # the largest M and L at N = 1024 (FFT length 2048), two Doppler bins
     "max_m16_n1024_l64": I.make_problem(16, 1024, 64, 2, nu_min=-0.25, nu_max=0.25, p=16.0),
+    # the largest N (FFT length 4096)
+    "max_n2048": I.make_problem(2, 2048, 4, 2, nu_min=-0.5, nu_max=0.5, p=16.0),
     # the shortest sequences
     "n2": I.make_problem(2, 2, 2, 3, p=8.0),
     # a region of interest that holds only tau = 0: auto pairs contribute nothing, cross pairs their zero lag

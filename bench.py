@@ -268,6 +268,20 @@ def main():
                                    "designs": 64, "restarts": 8}
         log(f"uneven x{len(designs)}: step {ms_c * 1e3:.1f} us")
         del r
+        # the paper's own shapes: N = 1200 (FFT length 4096), M = 2, B = 16 phase
+        # levels, 129 Doppler bins in [-0.5, 0.5], the fixed ROI |tau| <= 50 as 0/1
+        # weights w(tau, f) (eq. 8-9), one design and 64 restarts
+        pp = I.make_problem(2, 1200, 16, 129, p=16.0)
+        ww = I.roi_window_weights(pp, 50)
+        for count in (1, 64):
+            r = optim.SQNGD([pp] * count, opt, seeds=list(range(count)), roi_weights=[ww] * count)
+            ms_c, _, _ = time_graph(r, 20 if count == 1 else 10, 10, 10)
+            extras[f"paper_m2n1200_roi50_x{count}"] = {
+                "ms_per_step": ms_c, "evals_per_s": 2.0 * count / (ms_c * 1e-3),
+                "cube_equiv_frac_of_hbm": cube_frac(count * cube_cells(pp), 2, ms_c),
+                "shape": {"M": 2, "N": 1200, "L": 16, "F": 129, "roi": "|tau| <= 50 as weights"}}
+            log(f"M=2 N=1200 |tau|<=50 x{count}: step {ms_c * 1e3:.1f} us")
+            del r
         n = 1 << 28
         a = torch.empty(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

@@ -291,6 +291,58 @@ __device__ __forceinline__ unsigned long long fft_lanes_max_key(unsigned long lo
   }
 }
 
+// At P = 4096 the partner spectra are computed by k_rowspec (the pass's own
+// four-wave transform) after the kernel that writes their rows, instead of by
+// one wave of k_prep / k_final (64 elements per lane).
+__host__ __device__ constexpr bool spec_by_rowspec(int P) { return P >= 4096; }
+
+struct RowSpecArgs {
+  const ProbPlan* plans;
+  const int32_t* rows;      // batch rows of this launch, one block each
+  const int32_t* row_prob;  // problem of every batch row
+  const float2* src;        // rows [off_w + m N .. + N) to transform
+  float2* spec;             // partner spectra, the pass's layout
+  int32_t single;
+  ProbPlan one;
+};
+
+// Spectrum of one row of src (zero-padded to P) in the throughput pass's
+// layout, one block of the pass's transform width per row.
+template <int P>
+__global__ __launch_bounds__(64 * PassGeom<P>::WAVES) void k_rowspec(RowSpecArgs a) {
+  using G = PassGeom<P>;
+  constexpr int E = G::E, TF = G::TF;
+  __shared__ float2 buf[P];
+  int r, pid;
+  ProbPlan pl;
+  if (a.single) {
+    r = a.rows[blockIdx.x];
+    pid = 0;
+    pl = a.one;
+  } else {
+    r = a.rows[blockIdx.x];
+    pid = a.row_prob[r];
+    pl = a.plans[pid];
+  }
+  (void)pid;
+  const int m = r - pl.row0, N = pl.N, t = threadIdx.x;
+  const float2* row = a.src + pl.off_w + (int64_t)m * N;
+  float2 X[E];
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    const int n = t + TF * e;
+    X[e] = n < N ? row[n] : make_float2(0.f, 0.f);
+  });
+  TwiddlesG<G> W;
+  W.init(t);
+  fft_forward_g<G>(X, buf, t, W);
+  float2* out = a.spec + pl.ws_spec + (int64_t)m * P;
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    out[e * TF + t] = X[e];
+  });
+}
+
 // ------------------------------------------------------------------ k_prep
 
 enum PrepMode : int32_t {
@@ -389,15 +441,17 @@ __global__ __launch_bounds__(64) void k_prep(PrepArgs a) {
   es = slot_sum<TF>(es);
   ep = slot_sum<TF>(ep);
   if (active && t == 0) a.snrl[pl.row0 + g] = make_float4(cr, ci, es, ep);
-  WaveTwiddles<P> W;
-  W.init(t);
-  fft_forward<P>(X, lds + slot * P, t, W);
-  if (active) {
-    float2* sp = a.spec + pl.ws_spec + (int64_t)g * P;
-    static_for<E>([&](auto ec) {
-      constexpr int e = decltype(ec)::value;
-      sp[pass_spec_slot<P>(t, e)] = X[e];
-    });
+  if constexpr (!spec_by_rowspec(P)) {
+    WaveTwiddles<P> W;
+    W.init(t);
+    fft_forward<P>(X, lds + slot * P, t, W);
+    if (active) {
+      float2* sp = a.spec + pl.ws_spec + (int64_t)g * P;
+      static_for<E>([&](auto ec) {
+        constexpr int e = decltype(ec)::value;
+        sp[pass_spec_slot<P>(t, e)] = X[e];
+      });
+    }
   }
 }
 
@@ -1287,8 +1341,9 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
       }
     }
     row_snrl<CH>(self, prt, shf, a.snrl_next + r);
-    if (a.next == NEXT_B_FULL || next_hard)
-      row_spectrum<P, CH>(sp, N, fbuf, a.spec + pl.ws_spec + (int64_t)m * P);
+    if constexpr (!spec_by_rowspec(P))
+      if (a.next == NEXT_B_FULL || next_hard)
+        row_spectrum<P, CH>(sp, N, fbuf, a.spec + pl.ws_spec + (int64_t)m * P);
   }
 
   // ---- 7. statistics record

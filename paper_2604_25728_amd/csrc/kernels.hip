@@ -234,14 +234,15 @@ __device__ __forceinline__ int find_entry(const int32_t* base, int n, int wave) 
 
 // Waves per block of the throughput pass: four at P <= 512, two at 1024 and
 // 2048 (whose per-wave LDS slices would otherwise allow one block per CU),
-// four at 4096 (all four share one unit).
-__host__ __device__ constexpr int pass_waves(int P) { return P >= 4096 ? 4 : (P >= 1024 ? 2 : 4); }
+// eight at 4096 (all eight share one unit).
+__host__ __device__ constexpr int pass_waves(int P) { return P >= 4096 ? 8 : (P >= 1024 ? 2 : 4); }
 // FFT geometry of the throughput pass: wave-local up to P = 1024; at P = 2048
 // one transform spans the block's two waves (16 elements per lane instead of
 // 32), which keeps the pass's three spectra in registers without spilling;
-// at P = 4096 it spans four waves (16 elements per lane, three exchanges).
+// at P = 4096 it spans eight waves (8 elements per lane, three exchanges:
+// 190 VGPRs, against 256 plus spills with four waves and 16 per lane).
 __host__ __device__ constexpr int pass_tf(int P) {
-  return P >= 4096 ? 256 : (P >= 2048 ? 128 : (P >= 512 ? 64 : P / 8));
+  return P >= 4096 ? 512 : (P >= 2048 ? 128 : (P >= 512 ? 64 : P / 8));
 }
 template <int P>
 using PassGeom = GeomT<P, pass_tf(P)>;
@@ -292,7 +293,7 @@ __device__ __forceinline__ unsigned long long fft_lanes_max_key(unsigned long lo
 }
 
 // At P = 4096 the partner spectra are computed by k_rowspec (the pass's own
-// four-wave transform) after the kernel that writes their rows, instead of by
+// eight-wave transform) after the kernel that writes their rows, instead of by
 // one wave of k_prep / k_final (64 elements per lane).
 __host__ __device__ constexpr bool spec_by_rowspec(int P) { return P >= 4096; }
 

@@ -1,5 +1,5 @@
 """The paper's sequence length N = 1200 (FFT length 4096: the throughput pass
-spreads one transform over four waves with three LDS exchanges) against the
+spreads one transform over eight waves with three LDS exchanges) against the
 FP64 oracle: statistics, AF rows, both gradients, with and without ROI
 weights, and two optimiser iterations (whose finalize runs in k_final).
 Tolerances as in test_gpu_parity."""

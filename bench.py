@@ -178,6 +178,72 @@ def cpu_baseline(prob: dict, opt: dict, budget_s: float) -> dict:
                       f"by FP64 direct sums) of the same workload, {el:.1f} s"}
 
 
+def fft_route_eval(s, h, prob: dict, workers: int = 1) -> tuple:
+    """One evaluation by the paper's FFT route (eq. 33-36) in complex128 with
+    scipy's pocketfft, vectorised over (m, l, f): loss, and the packed
+    gradients with respect to the waveforms and the filters (the adjoint of
+    every linear step: the delay selection, the inverse FFT, the product with
+    the conjugate filter spectra, the zero-padded forward FFTs and the Doppler
+    modulation), plus the SNRL term. A CPU baseline of the GPU path's own
+    algorithm, not a reference: its values are checked against the oracle."""
+    import numpy as np
+    import scipy.fft as sf
+    s, h = np.asarray(s, np.complex128), np.asarray(h, np.complex128)
+    M, N = s.shape
+    F, P = prob["F"], fft_len(N)
+    nu = prob["nu_min"] + np.arange(F) * ((prob["nu_max"] - prob["nu_min"]) / (F - 1) if F > 1 else 0.0)
+    n = np.arange(N)
+    mod = np.exp(2j * np.pi * np.outer(nu, n) / N)                       # [F][N]
+    X = sf.fft(s[:, None, :] * mod[None], n=P, axis=-1, workers=workers)  # [M][F][P]
+    H = sf.fft(h, n=P, axis=-1, workers=workers)                          # [M][P]
+    r = sf.ifft(X[:, None] * np.conj(H)[None, :, None], axis=-1, workers=workers)  # [M][M][F][P]
+    tau = np.arange(-(N - 1), N)
+    k = (-tau) % P
+    A = r[..., k]                                                         # [M][M][F][2N-1]
+    mask = (tau >= prob["tau_lo"]) & (tau <= prob["tau_hi"])
+    mask = np.broadcast_to(mask, A.shape).copy()
+    for m in range(M):
+        mask[m, m, :, N - 1] = False
+    a = np.abs(A) / N * mask
+    amax = a.max()
+    p = prob["p"]
+    lp = amax * ((a / amax) ** p).sum() ** (1.0 / p)
+    c = (np.conj(h) * s).sum(axis=1)
+    p_tar = 10 ** (-prob["snrl_target_db"] / 20)
+    pm = np.abs(c) / N
+    loss = prob["w_psl"] * lp + prob["w_snrl"] * ((pm - p_tar) ** 2).mean()
+    with np.errstate(divide="ignore", invalid="ignore"):
+        G = np.where(mask, prob["w_psl"] * lp ** (1 - p) * a ** (p - 2) * A / N ** 2, 0.0)
+    gr = np.zeros(r.shape, np.complex128)
+    gr[..., k] = G                                                        # adjoint of the selection
+    gy = sf.fft(gr, axis=-1, workers=workers) / P                         # adjoint of the inverse FFT
+    gX = (H[None, :, None] * gy).sum(axis=1)                              # [M][F][P]
+    gs = (np.conj(mod)[None] * (P * sf.ifft(gX, axis=-1, workers=workers)[..., :N])).sum(axis=1)
+    gH = (X[:, None] * np.conj(gy)).sum(axis=(0, 2))                      # [M][P]
+    gh = P * sf.ifft(gH, axis=-1, workers=workers)[..., :N]
+    gS = prob["w_snrl"] * (2.0 / M) * (pm - p_tar) * c / (N * np.abs(c))
+    gs = gs + gS[:, None] * h
+    gh = gh + np.conj(gS)[:, None] * s
+    return loss, gs, gh
+
+
+def cpu_fft_route(prob: dict, budget_s: float) -> dict:
+    """The FFT route of fft_route_eval timed on the host cores (scipy workers)."""
+    import numpy as np
+    from paper_2604_25728_amd import inputs as I
+    cores = len(os.sched_getaffinity(0))
+    s = np.exp(2j * np.pi * np.random.default_rng(0).random((prob["M"], prob["N"])))
+    h = I.complex_gaussian(prob["M"], prob["N"], 1).astype(np.complex128)
+    n = 0
+    t0 = time.perf_counter()
+    while n < 1 or time.perf_counter() - t0 < budget_s:
+        fft_route_eval(s, h, prob, workers=cores)
+        n += 1
+    el = time.perf_counter() - t0
+    return {"value": n / el, "unit": "evals/s", "cores": cores, "kind": "fft_route_numpy",
+            "sample": f"{n} evaluations (loss, both gradients) by the FFT route in complex128, {el:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +392,8 @@ def main():
     if extras:
         out["extras"] = extras
     if not args.no_cpu_baseline:
+        out["cpu_fft_route"] = cpu_fft_route(prob, min(10.0, args.cpu_seconds))
+        log(f"cpu FFT route: {out['cpu_fft_route']['value']:.1f} evals/s on {out['cpu_fft_route']['cores']} cores")
         out["cpu_baseline"] = cpu_baseline(prob, opt, args.cpu_seconds)
         log(f"cpu baseline: {out['cpu_baseline']['value']:.3f} evals/s on {out['cpu_baseline']['cores']} cores")
     print(json.dumps(out), flush=True)

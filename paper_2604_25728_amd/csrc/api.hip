@@ -415,8 +415,9 @@ void launch_prep_p(const PrepArgs& a, int waves, hipStream_t s) {
   hipLaunchKernelGGL(k_prep<P>, dim3(waves), dim3(64), 0, s, a);
 }
 
-// Partner spectra of a group whose spectra k_rowspec computes (P = 4096).
-void launch_rowspec(const Plan& pl, const Ptrs& w, int g, const float2* src, hipStream_t s) {
+// Partner spectra of a group whose spectra k_rowspec computes (P >= 2048).
+template <int P>
+void launch_rowspec_p(const Plan& pl, const Ptrs& w, int g, const float2* src, hipStream_t s) {
   RowSpecArgs r{};
   r.plans = w.plans;
   r.rows = (const int32_t*)(w.base + pl.hdr.group_rows[g]);
@@ -425,7 +426,11 @@ void launch_rowspec(const Plan& pl, const Ptrs& w, int g, const float2* src, hip
   r.spec = w.spec;
   r.single = pl.hdr.nprob == 1;
   r.one = pl.plans[0];
-  hipLaunchKernelGGL(k_rowspec<4096>, dim3(pl.hdr.group_nrows[g]), dim3(64 * PassGeom<4096>::WAVES), 0, s, r);
+  hipLaunchKernelGGL(k_rowspec<P>, dim3(pl.hdr.group_nrows[g]), dim3(64 * PassGeom<P>::WAVES), 0, s, r);
+}
+void launch_rowspec(const Plan& pl, const Ptrs& w, int g, const float2* src, hipStream_t s) {
+  if (g + kMinLogP == 11) launch_rowspec_p<2048>(pl, w, g, src, s);
+  else launch_rowspec_p<4096>(pl, w, g, src, s);
 }
 
 void launch_prep(const Plan& pl, const Ptrs& w, PrepArgs a, hipStream_t s) {
@@ -448,15 +453,10 @@ void launch_prep(const Plan& pl, const Ptrs& w, PrepArgs a, hipStream_t s) {
       case 2: launch_prep_p<512>(a, waves, s); break;
       case 3: launch_prep_p<1024>(a, waves, s); break;
       case 4: launch_prep_p<2048>(a, waves, s); break;
-      default:
-        launch_prep_p<4096>(a, waves, s);
-        launch_rowspec(pl, w, g,
-                       a.mode == PREP_A_HARD ? w.wpart
-                       : a.mode == PREP_A_SELF ? w.wself
-                                               : a.h,
-                       s);
-        break;
+      default: launch_prep_p<4096>(a, waves, s); break;
     }
+    if (g + kMinLogP >= 11)
+      launch_rowspec(pl, w, g, a.mode == PREP_A_HARD ? w.wpart : a.mode == PREP_A_SELF ? w.wself : a.h, s);
   }
 }
 
@@ -611,11 +611,11 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
       case 2: hipLaunchKernelGGL(k_final<512>, grid, block, 0, s, af); break;
       case 3: hipLaunchKernelGGL(k_final<1024>, grid, block, 0, s, af); break;
       case 4: hipLaunchKernelGGL(k_final<2048>, grid, block, 0, s, af); break;
-      default:
-        hipLaunchKernelGGL(k_final<4096>, grid, block, 0, s, af);
-        if (af.next == NEXT_B_FULL) launch_rowspec(pl, w, g, af.h, s);
-        if (af.next == NEXT_A_FULL) launch_rowspec(pl, w, g, w.wpart, s);
-        break;
+      default: hipLaunchKernelGGL(k_final<4096>, grid, block, 0, s, af); break;
+    }
+    if (g + kMinLogP >= 11) {
+      if (af.next == NEXT_B_FULL) launch_rowspec(pl, w, g, af.h, s);
+      if (af.next == NEXT_A_FULL) launch_rowspec(pl, w, g, w.wpart, s);
     }
   }
 }

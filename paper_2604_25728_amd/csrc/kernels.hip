@@ -292,10 +292,10 @@ __device__ __forceinline__ unsigned long long fft_lanes_max_key(unsigned long lo
   }
 }
 
-// At P = 4096 the partner spectra are computed by k_rowspec (the pass's own
-// eight-wave transform) after the kernel that writes their rows, instead of by
-// one wave of k_prep / k_final (64 elements per lane).
-__host__ __device__ constexpr bool spec_by_rowspec(int P) { return P >= 4096; }
+// At P >= 2048 the partner spectra are computed by k_rowspec (the pass's own
+// two- or eight-wave transform) after the kernel that writes their rows,
+// instead of by one wave of k_prep / k_final (32 or 64 elements per lane).
+__host__ __device__ constexpr bool spec_by_rowspec(int P) { return P >= 2048; }
 
 struct RowSpecArgs {
   const ProbPlan* plans;

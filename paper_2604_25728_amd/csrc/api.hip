@@ -259,11 +259,12 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     H.group_rwaves[g] = rsum;
     pl->group_phlog[g] = phl;
     {
-      const int tpc = P > 2 * kStepThreads ? 1 : (P >= 256 ? 2 * kStepThreads / P : 8);
+      // k_step holds N <= P / 2 chips with tpc lanes each (P <= 2048); the
+      // rest, and rows with more than 16 logit levels per lane, use k_final
+      const int tpc = step_tpc(P);
       int lv = 0;
-      for (int id : gprob[g]) lv = std::max(lv, (pl->plans[id].L + tpc - 1) / tpc);
-      int mode = lv <= 4 ? 4 : (lv <= 16 ? 16 : 0);
-      if (P > 2 * kStepThreads) mode = 0;
+      for (int id : gprob[g]) lv = std::max(lv, tpc > 0 ? (pl->plans[id].L + tpc - 1) / tpc : 1 << 30);
+      const int mode = tpc < 1 ? 0 : (lv <= 4 ? 4 : (lv <= 16 ? 16 : 0));
       pl->group_step[g] = mode;
       if (!gprob[g].empty() && mode == 0) pl->all_step = false;
       // k_step reduces the rows' Doppler partials itself when that takes at
@@ -278,7 +279,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
         nr += q.M;
         row_bytes = std::max(row_bytes, (int64_t)8 * q.wpr * q.N);
       }
-      pl->group_fuse[g] = mode != 0 && ne <= 2 * step_tpc(P) * step_fg_loads(P) &&
+      pl->group_fuse[g] = mode != 0 && P <= 1024 && ne <= 2 * step_tpc(P) * step_fg_loads(P) &&
                           (nr >= kFuseRows || row_bytes <= kFuseRowBytes);
     }
     H.group_prob[g] = (int64_t)off;
@@ -541,7 +542,7 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
 
 template <int P, bool FG>
 void launch_step_pf(const FinArgs& a, int lv, dim3 grid, hipStream_t s) {
-  const dim3 block(kStepThreads);
+  const dim3 block(step_threads(P));
   if (a.mode == FIN_STEP_A) {
     if (lv == 4) hipLaunchKernelGGL((k_step<P, FIN_STEP_A, 4, FG>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_step<P, FIN_STEP_A, 16, FG>), grid, block, 0, s, a);
@@ -552,8 +553,13 @@ void launch_step_pf(const FinArgs& a, int lv, dim3 grid, hipStream_t s) {
 }
 template <int P>
 void launch_step_p(const FinArgs& a, int lv, bool fuse, dim3 grid, hipStream_t s) {
-  if (fuse) launch_step_pf<P, true>(a, lv, grid, s);
-  else launch_step_pf<P, false>(a, lv, grid, s);
+  if constexpr (P <= 1024) {
+    if (fuse) {
+      launch_step_pf<P, true>(a, lv, grid, s);
+      return;
+    }
+  }
+  launch_step_pf<P, false>(a, lv, grid, s);
 }
 
 void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
@@ -589,7 +595,12 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
         case 0: launch_step_p<128>(a, lv, fuse, grid, s); break;
         case 1: launch_step_p<256>(a, lv, fuse, grid, s); break;
         case 2: launch_step_p<512>(a, lv, fuse, grid, s); break;
-        default: launch_step_p<1024>(a, lv, fuse, grid, s); break;
+        case 3: launch_step_p<1024>(a, lv, fuse, grid, s); break;
+        default: launch_step_p<2048>(a, lv, fuse, grid, s); break;
+      }
+      if (g + kMinLogP >= 11) {  // partner spectra of the next pass
+        if (a.next == NEXT_B_FULL) launch_rowspec(pl, w, g, a.h, s);
+        if (a.next == NEXT_A_FULL) launch_rowspec(pl, w, g, w.wpart, s);
       }
       continue;
     }

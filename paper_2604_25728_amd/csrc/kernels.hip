@@ -1388,8 +1388,10 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
 //           handled after the barrier by redoing the next-pass inputs from
 //           the unchanged state.
 
-constexpr int kStepThreads = 512;
+constexpr int kStepThreads = 512;  // below P = 2048
 constexpr int kStepWaves = kStepThreads / 64;
+// threads of a k_step block: 512, or 1024 at P = 2048 (one lane per chip)
+__host__ __device__ constexpr int step_threads(int P) { return P >= 2048 ? 2 * kStepThreads : kStepThreads; }
 
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int x) {
@@ -1470,19 +1472,20 @@ __device__ __forceinline__ float2 chip_quantise(const float (&zc)[LVMAX], int su
 }
 
 // Block sums of four products and a flag, in wave order (the same in every
-// thread); sh holds 5 * kStepWaves floats.
+// thread) over NW waves; sh holds 5 * NW floats.
+template <int NW>
 __device__ __forceinline__ void block_sum5(float (&v)[5], float* sh) {
 #pragma unroll
   for (int i = 0; i < 5; ++i) v[i] = wave_sum(v[i]);
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int i = 0; i < 5; ++i) sh[i * kStepWaves + (threadIdx.x >> 6)] = v[i];
+    for (int i = 0; i < 5; ++i) sh[i * NW + (threadIdx.x >> 6)] = v[i];
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     float r = 0.f;
-    for (int w = 0; w < kStepWaves; ++w) r += sh[i * kStepWaves + w];
+    for (int w = 0; w < NW; ++w) r += sh[i * NW + w];
     v[i] = r;
   }
 }
@@ -1663,7 +1666,7 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
 
 // Lanes per chip in k_step, and the Doppler partials a lane loads per round
 // when k_step reduces the gradient rows itself (FG).
-__host__ __device__ constexpr int step_tpc(int P) { return P >= 256 ? 2 * kStepThreads / P : 8; }
+__host__ __device__ constexpr int step_tpc(int P) { return P >= 256 ? 2 * step_threads(P) / P : 8; }
 __host__ __device__ constexpr int step_fg_loads(int P) {
   return step_tpc(P) < 1 ? 0 : (48 / step_tpc(P) < 32 ? 48 / step_tpc(P) : 32);
 }
@@ -1674,15 +1677,16 @@ __host__ __device__ constexpr int step_fg_loads(int P) {
 // partials, TPC lanes per chip), so one kernel ends the inner step. Used
 // when a row's partials take at most two load rounds per lane.
 template <int P, int MODE, int LVMAX, bool FG>
-__global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
+__global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
+  constexpr int NT = step_threads(P), NW = NT / 64;
   constexpr int TPC = step_tpc(P);  // lanes per chip: N <= P/2 chips fill the block
   constexpr bool kA = MODE == FIN_STEP_A;
   using G = Geom<P>;
-  __shared__ float shr[2 * 5 * kStepWaves];
+  __shared__ float shr[2 * 5 * NW];
   __shared__ float2 rowbuf[P];
   __shared__ float2 fbuf[G::LDS];
-  __shared__ float shw[FG ? 2 * kStepWaves : 1];
-  __shared__ unsigned long long shk[FG ? 2 * kStepWaves : 1];
+  __shared__ float shw[FG ? 2 * NW : 1];
+  __shared__ unsigned long long shk[FG ? 2 * NW : 1];
   __shared__ float4 snrl_sh[FG ? 16 : 1];
   const int tid = threadIdx.x;
   int r, pid;
@@ -1756,7 +1760,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
     vz[k] = ok && !kA && !sgd ? avz[l] : 0.f;
   }
   if (want_spec)
-    for (int i = N + tid; i < P; i += kStepThreads) rowbuf[i] = zero2;
+    for (int i = N + tid; i < P; i += NT) rowbuf[i] = zero2;
 
   bool bad;
   float2 g;
@@ -1765,30 +1769,30 @@ __global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
     float mx = 0.f, sx = 0.f;
     unsigned long long ka = 0, kc = 0;
     const bool keys = m == 0;
-    grad_units<kStepThreads>(pl, us, keys, mx, sx, ka, kc);
+    grad_units<NT>(pl, us, keys, mx, sx, ka, kc);
     {
       const float wm = wave_max(mx);
       float sw = mx > 0.f ? sx * pow_p(mx / wm, pl) : 0.f;
       sw = wave_sum(sw);
       if ((tid & 63) == 0) {
         shw[tid >> 6] = wm;
-        shw[kStepWaves + (tid >> 6)] = sw;
+        shw[NW + (tid >> 6)] = sw;
       }
       if (keys) {
         ka = slot_max_key<64>(ka);
         kc = slot_max_key<64>(kc);
         if ((tid & 63) == 0) {
           shk[tid >> 6] = ka;
-          shk[kStepWaves + (tid >> 6)] = kc;
+          shk[NW + (tid >> 6)] = kc;
         }
       }
     }
     __syncthreads();
     float smax = 0.f;
-    for (int w = 0; w < kStepWaves; ++w) smax = fmaxf(smax, shw[w]);
+    for (int w = 0; w < NW; ++w) smax = fmaxf(smax, shw[w]);
     float acc = 0.f;
-    for (int w = 0; w < kStepWaves; ++w)
-      if (shw[w] > 0.f) acc += shw[kStepWaves + w] * pow_p(shw[w] / smax, pl);
+    for (int w = 0; w < NW; ++w)
+      if (shw[w] > 0.f) acc += shw[NW + w] * pow_p(shw[w] / smax, pl);
     const float lp_raw = smax > 0.f ? smax * exp2f(log2f(acc) / pl.p) : 0.f;
     float l_snrl = 0.f;
     for (int k = 0; k < M; ++k) {
@@ -1799,9 +1803,9 @@ __global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
     const float loss = pl.w_psl * lp_raw * pl.inv_NP + pl.w_snrl * l_snrl;
     bad = !isfinite(loss);
     if (keys && tid == 0 && a.stats != nullptr) {
-      for (int w = 0; w < kStepWaves; ++w) {
+      for (int w = 0; w < NW; ++w) {
         ka = umax64(ka, shk[w]);
-        kc = umax64(kc, shk[kStepWaves + w]);
+        kc = umax64(kc, shk[NW + w]);
       }
       stats_record(a.stats + pid, pl, a.orient, loss, lp_raw, l_snrl, ka, kc, snrl_sh, bad);
     }
@@ -1953,7 +1957,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
       q[2] = self.x * self.x + self.y * self.y;
       q[3] = part.x * part.x + part.y * part.y;
     }
-    block_sum5(q, sh);
+    block_sum5<NW>(q, sh);
     prod = make_float4(q[0], q[1], q[2], q[3]);
     nbad = q[4];
   };
@@ -2008,7 +2012,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
                                        pl.sq_mode);
     }
     if (want_spec && lead) rowbuf[n] = kA ? hu : nx;
-    products(hu, nx, shr + 5 * kStepWaves, prod, nbad);
+    products(hu, nx, shr + 5 * NW, prod, nbad);
   }
   if (lead) {
     if (next == NEXT_B_FULL || next == NEXT_B_SOFT) a.wself[wrow + n] = nx;
@@ -2016,7 +2020,8 @@ __global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
   }
   if (tid == 0 && next != NEXT_NONE) a.snrl_next[r] = prod;
 
-  // ---- spectrum of the next pass's partner row (wave 0)
+  // ---- spectrum of the next pass's partner row (wave 0; k_rowspec at P >= 2048)
+  if constexpr (!spec_by_rowspec(P)) {
   if (want_spec && tid < 64) {
     constexpr int E = G::E, TF = G::TF;
     const int slot = tid / TF, t = tid % TF;
@@ -2035,6 +2040,7 @@ __global__ __launch_bounds__(kStepThreads) void k_step(FinArgs a) {
         out[e * TF + t] = cscale(X[e], cs);
       });
     }
+  }
   }
 
   if (a.count_step) {

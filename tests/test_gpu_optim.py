@@ -241,10 +241,12 @@ def test_chained_graph_matches_eager_run(mods):
     assert a.t == b.t == 15
 
 
-@pytest.mark.parametrize("shape", [(2, 1024, 4, 3), (2, 300, 64, 5)])
+@pytest.mark.parametrize("shape", [(2, 1024, 4, 3), (3, 1000, 16, 3), (2, 1100, 8, 2), (2, 300, 64, 5)])
 def test_fallback_finalize_steps_match_oracle(ref, mods, shape):
-    """Steps whose finalize runs in k_final (FFT length 2048, or more logit
-    levels per lane than the latency finalize holds) against the oracle."""
+    """Steps at FFT length 2048 (k_step with 1024 threads, one lane per chip,
+    4 and 16 logit levels per lane, partner spectra by k_rowspec), at 4096
+    (k_final with two chips per thread) and with more logit levels per lane
+    than k_step holds (k_final) against the oracle."""
     nat, optim, _ = mods
     M, N, L, F = shape
     prob = I.make_problem(M, N, L, F, p=16.0)

@@ -173,3 +173,46 @@ def net_targets(B: int, M: int, N: int, L: int, seed: int) -> np.ndarray:
     """Random level indices [B][M][N] int32 (for tests of the loss)."""
     rng = np.random.default_rng(seed)
     return rng.integers(0, L, size=(B, M, N)).astype(np.int32)
+
+
+# ------------------------------------- the paper's transmit network (Sec. III-A)
+
+SQN_WIDTH = 128     # hidden width of the ResNet
+SQN_BLOCKS = 5      # residual blocks
+
+
+def sqn_layers(D: int) -> list:
+    """(input, output) widths of the dense layers, in parameter order: the input
+    layer, two per residual block, the output layer (D = M N inputs and outputs)."""
+    H = SQN_WIDTH
+    return [(D, H)] + [(H, H)] * (2 * SQN_BLOCKS) + [(H, D)]
+
+
+def sqn_param_count(D: int) -> int:
+    return sum(o * i + o for i, o in sqn_layers(D))
+
+
+def sqn_init(D: int, seed: int) -> np.ndarray:
+    """Flat float32 parameters, per layer W[out][in] then b[out], uniform in
+    +-1/sqrt(in) (weights and biases)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, o in sqn_layers(D):
+        bound = 1.0 / np.sqrt(i)
+        out.append(rng.uniform(-bound, bound, size=o * i))
+        out.append(rng.uniform(-bound, bound, size=o))
+    return np.concatenate(out).astype(np.float32)
+
+
+def sqn_thresholds(B: int, copies: int) -> np.ndarray:
+    """The B * copies ordered thresholds rho_i = (i + 1/2) / (B copies) of the
+    copied staircase, float32."""
+    K = B * copies
+    return ((np.arange(K) + 0.5) / K).astype(np.float32)
+
+
+def sqn_input(M: int, N: int, seed: int) -> np.ndarray:
+    """The network input y0 = vec(Y0): random normalised phases U[0, 1),
+    float32 [M N] (waveform m's chips at m N .. m N + N - 1)."""
+    rng = np.random.default_rng(seed)
+    return rng.random(M * N).astype(np.float32)

@@ -1,0 +1,111 @@
+"""Pins of the FP64 oracle of the paper's transmit parameterisation (ResNet,
+copied tanh staircase, hard quantiser) to torch float64 autograd, central
+differences, the staircase's limits and the paper's quad-phase example."""
+import numpy as np
+import pytest
+
+from paper_2604_25728_amd import inputs as I
+
+
+@pytest.fixture(scope="module")
+def S():
+    from oracle import sqn_ref
+    return sqn_ref
+
+
+def test_resnet_against_torch_autograd(S):
+    torch = pytest.importorskip("torch")
+    M, N = 2, 12
+    D = M * N
+    theta = I.sqn_init(D, 3).astype(np.float64)
+    y0 = I.sqn_input(M, N, 4).astype(np.float64)
+    z, cache = S.forward(theta, y0)
+    dz = np.random.default_rng(5).standard_normal(D)
+    g = S.backward(cache, dz)
+    th = torch.tensor(theta, requires_grad=True)
+    x = torch.tensor(y0)
+    off = 0
+    Ws = []
+    for i, o in I.sqn_layers(D):
+        W = th[off: off + o * i].reshape(o, i)
+        off += o * i
+        b = th[off: off + o]
+        off += o
+        Ws.append((W, b))
+    h = torch.tanh(Ws[0][0] @ x + Ws[0][1])
+    for k in range(I.SQN_BLOCKS):
+        W1, b1 = Ws[1 + 2 * k]
+        W2, b2 = Ws[2 + 2 * k]
+        h = h + torch.tanh(W2 @ torch.tanh(W1 @ h + b1) + b2)
+    zt = torch.sigmoid(Ws[-1][0] @ h + Ws[-1][1])
+    (zt * torch.tensor(dz)).sum().backward()
+    assert np.abs(zt.detach().numpy() - z).max() < 1e-14
+    assert np.abs(th.grad.numpy() - g).max() <= 1e-12 * np.abs(g).max()
+
+
+def test_resnet_central_differences(S):
+    M, N = 1, 8
+    D = M * N
+    theta = I.sqn_init(D, 6).astype(np.float64)
+    y0 = I.sqn_input(M, N, 7).astype(np.float64)
+    w = np.random.default_rng(8).standard_normal(D)
+    z, cache = S.forward(theta, y0)
+    g = S.backward(cache, w)
+    rng = np.random.default_rng(9)
+    for j in rng.integers(0, theta.size, size=12):
+        e = np.zeros_like(theta)
+        e[j] = 1e-6
+        fd = (w @ S.forward(theta + e, y0)[0] - w @ S.forward(theta - e, y0)[0]) / 2e-6
+        assert abs(fd - g[j]) <= 1e-7 * max(1.0, abs(g[j])), (j, fd, g[j])
+
+
+def test_staircase_limit_and_paper_example(S):
+    """For large c, Q_A is the step count / B away from the thresholds; with
+    B = 4 and r_n = 3 the hard values run over k / 4, k = 0..12 (the paper's
+    quad-phase example), and the waveforms are quad-phase."""
+    B, r = 4, 3
+    rho = I.sqn_thresholds(B, r).astype(np.float64)
+    z = np.linspace(0.0, 0.999, 5000)
+    z = z[np.min(np.abs(z[:, None] - rho[None, :]), axis=1) > 1e-3]
+    k = S.hard_levels(z, rho)
+    assert set(k.tolist()) == set(range(B * r + 1))
+    assert np.abs(S.soft_quantise(z, rho, B, 1e6) - k / B).max() < 1e-9
+    idx, x = S.hard_waveform(z[:12], rho, B, 3, 4)
+    assert np.allclose(np.abs(x), 1.0) and set(np.unique(idx)).issubset(set(range(B)))
+    assert np.allclose(x, np.exp(2j * np.pi * (k[:12] / B)).reshape(3, 4))
+
+
+def test_staircase_gradients_central_differences(S):
+    B, r, c = 4, 5, 30.0
+    rho = I.sqn_thresholds(B, r).astype(np.float64) + np.random.default_rng(10).normal(0, 1e-3, B * r)
+    z = np.random.default_rng(11).random(9)
+    dy = np.random.default_rng(12).standard_normal(9)
+    gz, grho = S.soft_quantise_grad(z, rho, B, c, dy)
+    eps = 1e-7
+    for j in range(9):
+        e = np.zeros(9)
+        e[j] = eps
+        fd = dy @ (S.soft_quantise(z + e, rho, B, c) - S.soft_quantise(z - e, rho, B, c)) / (2 * eps)
+        assert abs(fd - gz[j]) <= 1e-6 * max(1.0, abs(gz[j]))
+    for i in (0, 7, 19):
+        e = np.zeros(B * r)
+        e[i] = eps
+        fd = dy @ (S.soft_quantise(z, rho + e, B, c) - S.soft_quantise(z, rho - e, B, c)) / (2 * eps)
+        assert abs(fd - grho[i]) <= 1e-6 * max(1.0, abs(grho[i]))
+
+
+def test_waveform_chain_central_differences(S, ref):
+    """dL/dy1 = 2 pi Im(grad_s conj(s)) against central differences of the AF loss in y1."""
+    M, N, F = 2, 10, 3
+    prob = I.make_problem(M, N, 4, F, p=8.0)
+    y1 = np.random.default_rng(13).random(M * N) * 3
+    h = I.complex_gaussian(M, N, 14).astype(np.complex128)
+    s = S.soft_waveform(y1, M, N)
+    st, gs, _ = ref.evaluate(s, h, prob)
+    dy = S.waveform_chain(gs, s)
+    for j in (0, 7, 13, 19):
+        e = np.zeros(M * N)
+        e[j] = 1e-6
+        lp = ref.evaluate(S.soft_waveform(y1 + e, M, N), h, prob, want_grads=False)[0]["loss"]
+        lm = ref.evaluate(S.soft_waveform(y1 - e, M, N), h, prob, want_grads=False)[0]["loss"]
+        assert abs((lp - lm) / 2e-6 - dy[j]) <= 1e-6 * max(1.0, abs(dy[j]))

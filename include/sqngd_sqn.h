@@ -1,0 +1,103 @@
+/*
+ * sqngd_sqn.h - C ABI of the paper's transmit parameterisation in libsqngd.so
+ * (Sec. III-A): the ResNet f_theta that maps the fixed input y0 = vec(Y0)
+ * (normalised random phases, eq. 15-16) to continuous variables z (eq. 17),
+ * the copied tanh staircase Q_A with trainable ordered thresholds rho (eq. 24)
+ * that gives the soft waveform s = exp(j 2 pi Q_A(z)) (eq. 25-26), and the
+ * hard quantiser (eq. 46) read as the staircase's limit: the number of
+ * thresholds at or below z, mod B, as the phase index.
+ *
+ * Network (D = M N inputs and outputs, width 128, 5 residual blocks):
+ *   h_0 = tanh(W_in y0 + b_in),
+ *   h_k = h_{k-1} + tanh(W2_k tanh(W1_k h_{k-1} + b1_k) + b2_k), k = 1..5,
+ *   z   = sigmoid(W_out h_5 + b_out).
+ * Parameters: one flat FP32 array theta, per dense layer W[out][in] then
+ * b[out], in the order W_in, (W1_1, W2_1), ..., (W1_5, W2_5), W_out;
+ * sqngd_sqn_param_count gives its length. Staircase: K = B * copies
+ * thresholds rho (FP32, kept sorted), every transition of height 1/B and
+ * steepness c: Q_A(z) = sum_i (tanh(c (z - rho_i)) + 1) / (2B).
+ *
+ * The AF, the loss and the waveform / filter gradients come from
+ * sqngd_af_forward / sqngd_af_backward with wave_mode SQNGD_WAVE_GIVEN; these
+ * calls carry the waveform gradient back to (theta, rho) and update them.
+ *
+ * Ownership: every array is a DEVICE pointer owned by the caller; the shape is
+ * a HOST pointer read during the call. The network's activations live in the
+ * caller's workspace (size from sqngd_sqn_workspace_size, 256-byte aligned):
+ * sqngd_sqn_backward uses those the last sqngd_sqn_forward on the same
+ * workspace left there. Calls only enqueue on `stream` (a hipStream_t passed
+ * as void*), allocate nothing and issue no memset.
+ *
+ * Errors (checked on the host before any HIP call): SQNGD_E_INVALID_ARG for a
+ * NULL required pointer, a non-positive size or a non-finite / non-positive
+ * c; SQNGD_E_UNSUPPORTED unless M N <= 4096, 2 <= B <= 64 and
+ * B * copies <= 4096; SQNGD_E_WORKSPACE for a short workspace; SQNGD_E_ALIGN
+ * for a misaligned pointer; SQNGD_E_HIP for a failed launch.
+ */
+#ifndef SQNGD_SQN_H
+#define SQNGD_SQN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "sqngd.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t M, N;       /* waveforms and chips: D = M N network inputs and outputs */
+  int32_t B;          /* phase levels (the problem's L)                         */
+  int32_t copies;     /* r_n of the copying mechanism: K = B * copies thresholds */
+  float c;            /* staircase steepness                                    */
+  int32_t reserved[3]; /* must be 0                                              */
+} sqngd_sqn_shape;
+
+/* Length of theta for D = M N inputs. */
+int sqngd_sqn_param_count(int32_t D, int64_t* count);
+
+/* Workspace bytes of sqngd_sqn_forward / sqngd_sqn_backward. */
+int sqngd_sqn_workspace_size(const sqngd_sqn_shape* shape, size_t* bytes);
+
+/* z = f_theta(y0) (eq. 17); y0 and z are [M N] (waveform m at m N .. m N + N - 1). */
+int sqngd_sqn_forward(const sqngd_sqn_shape* shape, const float* theta, const float* y0, float* z, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Soft waveform s[m][n] = exp(j 2 pi Q_A(z[m N + n])) (eq. 24-26). */
+int sqngd_sqn_soft(const sqngd_sqn_shape* shape, const float* z, const float* rho, sqngd_c64* s, void* stream);
+
+/* Hard waveform (eq. 46): idx = #{i : rho_i <= z} mod B, x = exp(j 2 pi idx / B).
+   Either output may be NULL. */
+int sqngd_sqn_hard(const sqngd_sqn_shape* shape, const float* z, const float* rho, int32_t* idx, sqngd_c64* x,
+                   void* stream);
+
+/* Gradients of the loss with respect to theta and rho from the packed waveform
+   gradient grad_s (dL/dRe + j dL/dIm, from sqngd_af_backward in mode GIVEN) at
+   the soft waveform s of z: dL/dy1 = 2 pi Im(grad_s conj(s)), through Q_A to z
+   and rho, then through the network (whose activations the last
+   sqngd_sqn_forward on ws left there; y0 is the input of that forward).
+   grad_theta and grad_rho are written. */
+int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const float* y0, const float* z,
+                       const float* rho, const sqngd_c64* s, const sqngd_c64* grad_s, float* grad_theta,
+                       float* grad_rho, void* ws, size_t ws_bytes, void* stream);
+
+/* One bias-corrected Adam step (step count t >= 1) on n floats: p -= lr mhat /
+   (sqrt(vhat) + eps), with the moments m, v updated in place. Used for theta,
+   rho and the filters (as 2 M N floats, Re and Im interleaved). */
+int sqngd_sqn_adam(float* p, const float* g, float* m, float* v, int64_t n, int32_t t, float lr, float beta1,
+                   float beta2, float eps, void* stream);
+
+/* The projection of the thresholds onto an ordered set: sorts rho[0..K) in
+   place (ascending), K <= 4096. */
+int sqngd_sqn_sort(float* rho, int32_t K, void* stream);
+
+/* Energy projection of the filters (eq. 32): h_m <- h_m sqrt(N / |h_m|^2),
+   rows of N complex values. */
+int sqngd_sqn_project(int32_t M, int32_t N, sqngd_c64* h, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

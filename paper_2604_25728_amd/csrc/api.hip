@@ -983,3 +983,5 @@ int sqngd_hard_quantize(const sqngd_problem* probs, int32_t nprob, const float* 
 
 // the warm-start network (same translation unit: it uses the helpers above)
 #include "net.hip"
+// the paper's transmit parameterisation (same translation unit)
+#include "sqn.hip"

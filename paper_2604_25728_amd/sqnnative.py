@@ -1,0 +1,180 @@
+"""ctypes binding of the paper's transmit parameterisation (include/sqngd_sqn.h)
+and the driver of Algorithm 1 with it.
+
+Argument marshalling only: the network, the staircase, the hard quantiser,
+Adam, the threshold sort and the filter projection run in the library's
+gfx950 kernels, the AF, the loss and the waveform / filter gradients in the
+fused pass (sqngd_af_backward with the waveform given); torch provides device
+memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import inputs as I
+from . import native as nat
+
+SYMBOLS = ["sqngd_sqn_param_count", "sqngd_sqn_workspace_size", "sqngd_sqn_forward", "sqngd_sqn_soft",
+           "sqngd_sqn_hard", "sqngd_sqn_backward", "sqngd_sqn_adam", "sqngd_sqn_sort", "sqngd_sqn_project"]
+
+
+class SqnShape(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("N", ctypes.c_int32), ("B", ctypes.c_int32), ("copies", ctypes.c_int32),
+                ("c", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
+
+
+_ready = False
+
+
+def lib():
+    global _ready
+    L = nat.load()
+    if not _ready:
+        P, i32, i64, f, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_size_t
+        L.sqngd_sqn_param_count.argtypes = [i32, P]
+        L.sqngd_sqn_workspace_size.argtypes = [P, P]
+        L.sqngd_sqn_forward.argtypes = [P, P, P, P, P, sz, P]
+        L.sqngd_sqn_soft.argtypes = [P, P, P, P, P]
+        L.sqngd_sqn_hard.argtypes = [P, P, P, P, P, P]
+        L.sqngd_sqn_backward.argtypes = [P, P, P, P, P, P, P, P, P, P, sz, P]
+        L.sqngd_sqn_adam.argtypes = [P, P, P, P, i64, i32, f, f, f, f, P]
+        L.sqngd_sqn_sort.argtypes = [P, i32, P]
+        L.sqngd_sqn_project.argtypes = [i32, i32, P, P]
+        for n in SYMBOLS:
+            getattr(L, n).restype = ctypes.c_int
+        _ready = True
+    return L
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def adam(p, g, m, v, t: int, lr: float, beta1: float, beta2: float, eps: float):
+    nat.check(lib().sqngd_sqn_adam(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), int(t), float(lr), float(beta1),
+                                   float(beta2), float(eps), _stream()), "sqn_adam")
+
+
+class SQN:
+    """One design's transmit network and staircase on the GPU: shape, workspace."""
+
+    def __init__(self, M: int, N: int, B: int, copies: int, c: float, device="cuda"):
+        self.M, self.N, self.B, self.copies, self.c = M, N, B, copies, float(c)
+        self.D, self.K = M * N, B * copies
+        self.shape = SqnShape(M, N, B, copies, float(c), (ctypes.c_int32 * 3)(0, 0, 0))
+        n = ctypes.c_int64()
+        nat.check(lib().sqngd_sqn_param_count(self.D, ctypes.byref(n)), "sqn_param_count")
+        self.count = n.value
+        b = ctypes.c_size_t()
+        nat.check(lib().sqngd_sqn_workspace_size(ctypes.byref(self.shape), ctypes.byref(b)), "sqn_workspace_size")
+        self.ws = torch.empty(b.value + 256, dtype=torch.uint8, device=device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_view = self.ws[off: off + b.value]
+        self.device = torch.device(device)
+
+    def forward(self, theta, y0, z=None):
+        z = torch.empty(self.D, dtype=torch.float32, device=self.device) if z is None else z
+        nat.check(lib().sqngd_sqn_forward(ctypes.byref(self.shape), _ptr(theta), _ptr(y0), _ptr(z), _ptr(self.ws_view),
+                                          self.ws_view.numel(), _stream()), "sqn_forward")
+        return z
+
+    def soft(self, z, rho, s=None):
+        s = torch.empty(self.D, dtype=torch.complex64, device=self.device) if s is None else s
+        nat.check(lib().sqngd_sqn_soft(ctypes.byref(self.shape), _ptr(z), _ptr(rho), _ptr(s), _stream()), "sqn_soft")
+        return s
+
+    def hard(self, z, rho, want_idx=True, want_x=True):
+        idx = torch.empty(self.D, dtype=torch.int32, device=self.device) if want_idx else None
+        x = torch.empty(self.D, dtype=torch.complex64, device=self.device) if want_x else None
+        nat.check(lib().sqngd_sqn_hard(ctypes.byref(self.shape), _ptr(z), _ptr(rho), _ptr(idx), _ptr(x), _stream()),
+                  "sqn_hard")
+        return idx, x
+
+    def backward(self, theta, y0, z, rho, s, grad_s):
+        gt = torch.empty(self.count, dtype=torch.float32, device=self.device)
+        gr = torch.empty(self.K, dtype=torch.float32, device=self.device)
+        nat.check(lib().sqngd_sqn_backward(ctypes.byref(self.shape), _ptr(theta), _ptr(y0), _ptr(z), _ptr(rho),
+                                           _ptr(s), _ptr(grad_s), _ptr(gt), _ptr(gr), _ptr(self.ws_view),
+                                           self.ws_view.numel(), _stream()), "sqn_backward")
+        return gt, gr
+
+    def sort(self, rho):
+        nat.check(lib().sqngd_sqn_sort(_ptr(rho), self.K, _stream()), "sqn_sort")
+
+    def project(self, h):
+        nat.check(lib().sqngd_sqn_project(self.M, self.N, _ptr(h), _stream()), "sqn_project")
+
+
+class SQNDesign:
+    """Algorithm 1 with the paper's transmit side for one design: the ResNet
+    parameters theta and thresholds rho (step B, Adam with lr_z, thresholds
+    sorted after each update) and the filters h (step A, Adam with lr_h and
+    the energy projection), from the fixed network input y0. The filters
+    start as the matched filter of the first hard waveform (h0 = x0)."""
+
+    def __init__(self, prob: dict, opt: dict, copies: int, c: float, seed: int = 0, theta=None, rho=None,
+                 y0=None, h=None, device="cuda"):
+        self.prob, self.opt = dict(prob), dict(opt)
+        M, N, B = prob["M"], prob["N"], prob["L"]
+        self.sqn = SQN(M, N, B, copies, c, device)
+        self.batch = nat.Batch([dict(prob, schedule=prob.get("schedule", nat.SCHED_AUTO))], device=device)
+        dev = self.sqn.device
+        f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32)).to(dev).contiguous()
+        self.theta = f32(I.sqn_init(M * N, seed) if theta is None else theta)
+        self.rho = f32(I.sqn_thresholds(B, copies) if rho is None else rho)
+        self.y0 = f32(I.sqn_input(M, N, seed + 1) if y0 is None else y0)
+        self.z = self.sqn.forward(self.theta, self.y0)
+        if h is None:
+            _, x = self.sqn.hard(self.z, self.rho, want_idx=False)
+            self.h = x.clone()
+            self.sqn.project(self.h)
+        else:
+            self.h = torch.as_tensor(np.asarray(h, np.complex64)).to(dev).reshape(-1).contiguous()
+        zeros = lambda n: torch.zeros(n, dtype=torch.float32, device=dev)
+        self.mt, self.vt = zeros(self.sqn.count), zeros(self.sqn.count)
+        self.mr, self.vr = zeros(self.sqn.K), zeros(self.sqn.K)
+        self.mh, self.vh = zeros(2 * M * N), zeros(2 * M * N)
+        self.t = 0
+        self.stats_a = self.batch.new_stats()
+        self.stats_b = self.batch.new_stats()
+
+    def iteration(self):
+        o = self.opt
+        b1, b2, eps = o["beta1"], o["beta2"], o["eps"]
+        self.z = self.sqn.forward(self.theta, self.y0, self.z)
+        _, x = self.sqn.hard(self.z, self.rho, want_idx=False)
+        hv = torch.view_as_real(self.h).reshape(-1)
+        for i in range(int(o["n_h"])):
+            _, gh, _ = self.batch.af_backward(None, self.h, nat.WAVE_GIVEN, s_given=x, want_z=False, want_h=True,
+                                              stats=self.stats_a)
+            adam(hv, torch.view_as_real(gh).reshape(-1), self.mh, self.vh, self.t * int(o["n_h"]) + i + 1,
+                 o["lr_h"], b1, b2, eps)
+            self.sqn.project(self.h)
+        for j in range(int(o["n_x"])):
+            self.z = self.sqn.forward(self.theta, self.y0, self.z)
+            s = self.sqn.soft(self.z, self.rho)
+            _, _, gs = self.batch.af_backward(None, self.h, nat.WAVE_GIVEN, s_given=s, want_z=False, want_h=False,
+                                              want_s=True, stats=self.stats_b)
+            gt, gr = self.sqn.backward(self.theta, self.y0, self.z, self.rho, s, gs)
+            k = self.t * int(o["n_x"]) + j + 1
+            adam(self.theta, gt, self.mt, self.vt, k, o["lr_z"], b1, b2, eps)
+            adam(self.rho, gr, self.mr, self.vr, k, o["lr_z"], b1, b2, eps)
+            self.sqn.sort(self.rho)
+        self.t += 1
+
+    def hard_stats(self):
+        z = self.sqn.forward(self.theta, self.y0)
+        _, x = self.sqn.hard(z, self.rho, want_idx=False)
+        return nat.decode_stats(self.batch.af_forward(None, self.h, nat.WAVE_GIVEN, s_given=x).cpu().numpy())[0]
+
+    def hard_indices(self):
+        z = self.sqn.forward(self.theta, self.y0)
+        idx, _ = self.sqn.hard(z, self.rho, want_x=False)
+        return idx.cpu().numpy().reshape(self.prob["M"], self.prob["N"])

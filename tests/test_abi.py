@@ -45,6 +45,8 @@ def test_every_header_in_include_is_exported(nat):
         for n in _declared(os.path.join(inc, h)):
             assert hasattr(lib, n), (h, n)
     assert sorted(netnative.SYMBOLS) == _declared(NET_HEADER)
+    from paper_2604_25728_amd import sqnnative
+    assert sorted(sqnnative.SYMBOLS) == _declared(os.path.join(inc, "sqngd_sqn.h"))
 
 
 def test_struct_layouts(nat):
@@ -212,3 +214,26 @@ def test_set_roi_weights_validation(nat):
     assert lib.sqngd_set_roi_weights(None, 1, None, ctypes.c_void_p(base), 1 << 15) == -1
     # a workspace that was never initialised for this batch
     assert lib.sqngd_set_roi_weights(probs, 1, None, ctypes.c_void_p(base), 1 << 15) in (-3,)
+
+
+def test_sqn_validation(nat):
+    """Argument checks of the transmit-network entry points (no HIP call)."""
+    import ctypes
+    from paper_2604_25728_amd import sqnnative as SN
+    lib = SN.lib()
+    n = ctypes.c_int64()
+    assert lib.sqngd_sqn_param_count(0, ctypes.byref(n)) == -1
+    assert lib.sqngd_sqn_param_count(4097, ctypes.byref(n)) == -2
+    assert lib.sqngd_sqn_param_count(32, ctypes.byref(n)) == 0
+    assert n.value == I.sqn_param_count(32)
+    b = ctypes.c_size_t()
+    good = SN.SqnShape(2, 16, 4, 3, 30.0, (ctypes.c_int32 * 3)(0, 0, 0))
+    assert lib.sqngd_sqn_workspace_size(ctypes.byref(good), ctypes.byref(b)) == 0 and b.value > 0
+    for bad, rc in (((2, 16, 1, 3, 30.0), -1), ((2, 16, 4, 3, -1.0), -1), ((2, 16, 65, 3, 30.0), -2),
+                    ((2, 16, 4, 2000, 30.0), -2), ((64, 128, 4, 3, 30.0), -2)):
+        sh = SN.SqnShape(*bad, (ctypes.c_int32 * 3)(0, 0, 0))
+        assert lib.sqngd_sqn_workspace_size(ctypes.byref(sh), ctypes.byref(b)) == rc, bad
+    assert lib.sqngd_sqn_sort(None, 4, None) == -1
+    assert lib.sqngd_sqn_sort(ctypes.c_void_p(16), 5000, None) == -2
+    assert lib.sqngd_sqn_adam(None, None, None, None, 4, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert lib.sqngd_sqn_project(0, 4, ctypes.c_void_p(16), None) == -1

@@ -1,0 +1,131 @@
+"""The paper's transmit parameterisation on the GPU (include/sqngd_sqn.h)
+against its FP64 oracle: the ResNet forward and backward, the copied tanh
+staircase and its gradients, the hard quantiser (bit-exact away from the
+thresholds), Adam, the threshold sort, the filter projection, and two outer
+iterations of Algorithm 1 with this transmit side.
+
+Tolerances: the network and the staircase run in FP32 against FP64; outputs
+within 1e-5 relative normwise, gradients within 1e-4 (the staircase sums
+K tanh terms); the iteration as in test_gpu_optim (1e-4)."""
+import numpy as np
+import pytest
+
+from paper_2604_25728_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def SN():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_25728_amd import native, sqnnative
+    native.load()
+    return sqnnative
+
+
+@pytest.fixture(scope="module")
+def S():
+    from oracle import sqn_ref
+    return sqn_ref
+
+
+def _rel(a, b):
+    a, b = np.asarray(a).reshape(-1), np.asarray(b).reshape(-1)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _t(a, dtype=torch.float32):
+    return torch.as_tensor(np.asarray(a)).to(dtype).cuda().contiguous()
+
+
+@pytest.mark.parametrize("M,N,B,copies,c", [(2, 64, 4, 3, 30.0), (3, 100, 16, 10, 100.0), (2, 512, 4, 100, 300.0)])
+def test_network_and_staircase(SN, S, M, N, B, copies, c):
+    D = M * N
+    print(f"[gpu] sqn M={M} N={N} B={B} copies={copies}", flush=True)
+    q = SN.SQN(M, N, B, copies, c)
+    theta = I.sqn_init(D, 20)
+    y0 = I.sqn_input(M, N, 21)
+    rho = I.sqn_thresholds(B, copies) + np.random.default_rng(22).normal(0, 1e-4, B * copies).astype(np.float32)
+    rho = np.sort(rho).astype(np.float32)
+    th, y, r = _t(theta), _t(y0), _t(rho)
+    z = q.forward(th, y)
+    s = q.soft(z, r)
+    idx, x = q.hard(z, r)
+    torch.cuda.synchronize()
+    zr, cache = S.forward(theta.astype(np.float64), y0.astype(np.float64))
+    assert _rel(z.cpu().numpy(), zr) <= 1e-5
+    # the staircase on the GPU's own z (the FP32 network's rounding stays out of this check)
+    zg = z.cpu().numpy().astype(np.float64)
+    y1 = S.soft_quantise(zg, rho.astype(np.float64), B, c)
+    assert np.abs(np.angle(s.cpu().numpy() * np.conj(np.exp(2j * np.pi * y1)))).max() <= 2e-4 * copies
+    k_ref = S.hard_levels(zg, rho.astype(np.float64)) % B
+    far = np.min(np.abs(zg[:, None] - rho[None, :].astype(np.float64)), axis=1) > 1e-6
+    assert np.array_equal(idx.cpu().numpy()[far], k_ref[far])
+    assert np.allclose(x.cpu().numpy(), np.exp(2j * np.pi * idx.cpu().numpy() / B), atol=1e-6)
+    # backward from a given waveform gradient
+    gs = (np.random.default_rng(23).standard_normal(D) + 1j * np.random.default_rng(24).standard_normal(D))
+    gt, gr = q.backward(th, y, z, r, s, _t(gs, torch.complex64))
+    torch.cuda.synchronize()
+    sg = s.cpu().numpy().astype(np.complex128)
+    dy = S.waveform_chain(gs.astype(np.complex64).astype(np.complex128), sg)
+    dz, drho = S.soft_quantise_grad(zg, rho.astype(np.float64), B, c, dy)
+    _, cache_g = S.forward(theta.astype(np.float64), y0.astype(np.float64))
+    cache_g["z"] = zg
+    dth = S.backward(cache_g, dz)
+    assert _rel(gr.cpu().numpy(), drho) <= 1e-4, _rel(gr.cpu().numpy(), drho)
+    assert _rel(gt.cpu().numpy(), dth) <= 1e-4, _rel(gt.cpu().numpy(), dth)
+
+
+def test_adam_sort_project(SN, S):
+    from oracle import sqngd_ref as R
+    rng = np.random.default_rng(30)
+    p0, g = rng.standard_normal(1000).astype(np.float32), rng.standard_normal(1000).astype(np.float32)
+    p, m, v = _t(p0), torch.zeros(1000, device="cuda"), torch.zeros(1000, device="cuda")
+    pr, mr, vr = p0.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    for t in (1, 2, 3):
+        SN.adam(p, _t(g), m, v, t, 1e-2, 0.9, 0.999, 1e-8)
+        pr, mr, vr = R.adam(pr, g.astype(np.float64), mr, vr, t, 1e-2, 0.9, 0.999, 1e-8)
+    q = SN.SQN(2, 8, 4, 700, 30.0)   # K = 2800 thresholds (padded to 4096 in the sort)
+    rho = rng.random(2800).astype(np.float32)
+    r = _t(rho)
+    q.sort(r)
+    h = (rng.standard_normal((2, 8)) + 1j * rng.standard_normal((2, 8))).astype(np.complex64)
+    ht = _t(h, torch.complex64).reshape(-1)
+    q.project(ht)
+    torch.cuda.synchronize()
+    assert _rel(p.cpu().numpy(), pr) <= 1e-6
+    assert np.array_equal(r.cpu().numpy(), np.sort(rho))
+    assert _rel(ht.cpu().numpy().reshape(2, 8), R.project(h.astype(np.complex128))) <= 1e-6
+
+
+def test_two_iterations_match_oracle(SN, S):
+    """Two outer iterations (n_h = n_x = 1) from the same state: filters,
+    network parameters and thresholds against the oracle's. A gentle
+    staircase (c = 4) keeps every threshold's gradient far above FP32
+    resolution: Adam's step is about lr times the sign of a gradient, so a
+    threshold whose gradient underflows in FP32 (tanh saturates) would move
+    by lr in the oracle and not at all on the GPU."""
+    prob = I.make_problem(2, 64, 4, 5, p=8.0)
+    opt = I.make_opt(lr_z=1e-3, lr_h=1e-2)
+    copies, c = 3, 4.0
+    print("[gpu] sqn iterations", flush=True)
+    d = SN.SQNDesign(prob, opt, copies, c, seed=40)
+    theta0 = d.theta.cpu().numpy().astype(np.float64)
+    rho0 = d.rho.cpu().numpy().astype(np.float64)
+    y0 = d.y0.cpu().numpy().astype(np.float64)
+    h0 = d.h.cpu().numpy().reshape(2, 64).astype(np.complex128)
+    for _ in range(2):
+        d.iteration()
+    torch.cuda.synchronize()
+    th, rho, h, st = theta0, rho0, h0, S.new_state(2 * 64, 4 * copies, 2, 64)
+    for t in range(2):
+        th, rho, h, st, sa, sb = S.iteration(prob, opt, {"c": c, "copies": copies}, th, rho, h, y0, st, t)
+    assert _rel(d.h.cpu().numpy().reshape(2, 64), h) <= 1e-4, _rel(d.h.cpu().numpy().reshape(2, 64), h)
+    assert _rel(d.theta.cpu().numpy(), th) <= 1e-4, _rel(d.theta.cpu().numpy(), th)
+    assert _rel(d.rho.cpu().numpy(), rho) <= 1e-4
+    assert np.all(np.diff(d.rho.cpu().numpy()) >= 0)
+    from paper_2604_25728_amd import native as nat
+    stb = nat.decode_stats(d.stats_b.cpu().numpy())[0]
+    assert abs(stb["loss"] - sb["loss"]) <= 1e-4 * sb["loss"]

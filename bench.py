@@ -357,12 +357,13 @@ def main():
         os_ = I.make_opt(lr_z=1e-5, lr_h=5e-2, n_h=10, n_x=10, total_iters=2000)
         d = SN.SQNDesign(ps, os_, copies=100, c=300.0, seed=0)
         d.batch.set_roi_weights([I.roi_window_weights(ps, 50)])
-        d.iteration()
+        d.capture()              # one outer iteration as a HIP graph
+        d.graph.replay()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(5):
-            d.iteration()
+            d.graph.replay()
         e1.record()
         torch.cuda.synchronize()
         ms_it = e0.elapsed_time(e1) / 5

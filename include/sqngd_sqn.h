@@ -82,11 +82,17 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
                        const float* rho, const sqngd_c64* s, const sqngd_c64* grad_s, float* grad_theta,
                        float* grad_rho, void* ws, size_t ws_bytes, void* stream);
 
-/* One bias-corrected Adam step (step count t >= 1) on n floats: p -= lr mhat /
-   (sqrt(vhat) + eps), with the moments m, v updated in place. Used for theta,
-   rho and the filters (as 2 M N floats, Re and Im interleaved). */
-int sqngd_sqn_adam(float* p, const float* g, float* m, float* v, int64_t n, int32_t t, float lr, float beta1,
-                   float beta2, float eps, void* stream);
+/* One bias-corrected Adam step on n floats: p -= lr mhat / (sqrt(vhat) + eps),
+   with the moments m, v updated in place; used for theta, rho and the filters
+   (as 2 M N floats, Re and Im interleaved). The step count is
+   t = step_mul * (*step) + step_add, read on the device when step (a device
+   int32, e.g. the outer-iteration counter) is given, so that a captured graph
+   replays with the current count; else t = step_add (>= 1). */
+int sqngd_sqn_adam(float* p, const float* g, float* m, float* v, int64_t n, const int32_t* step, int32_t step_mul,
+                   int32_t step_add, float lr, float beta1, float beta2, float eps, void* stream);
+
+/* *step += 1 on the device (the outer-iteration counter of the driver). */
+int sqngd_sqn_count(int32_t* step, void* stream);
 
 /* The projection of the thresholds onto an ordered set: sorts rho[0..K) in
    place (ascending), K <= 4096. */

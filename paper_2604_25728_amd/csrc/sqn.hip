@@ -63,48 +63,66 @@ __global__ __launch_bounds__(kThreads) void k_dense_bwd_w(const float* __restric
   if (i < O) db[i] = d_act[i] * act_grad(act, a[i]);
 }
 
-// din[k] = base[k] + sum_o W[o][k] dp[o] (o in order), dp as above.
-__global__ __launch_bounds__(kThreads) void k_dense_bwd_in(const float* __restrict__ W,
-                                                            const float* __restrict__ d_act,
-                                                            const float* __restrict__ a, int act, int K, int O,
-                                                            const float* __restrict__ base, float* din) {
-  const int k = blockIdx.x * kThreads + threadIdx.x;
-  if (k >= K) return;
+// din[k] = base[k] + sum_o W[o][k] dp[o], dp as above: a block owns 64
+// inputs (one per lane); its 16 waves take the outputs o = w (mod 16) and
+// their partial sums are added in wave order.
+constexpr int kBwdWaves = 16;
+__global__ __launch_bounds__(64 * kBwdWaves) void k_dense_bwd_in(const float* __restrict__ W,
+                                                                  const float* __restrict__ d_act,
+                                                                  const float* __restrict__ a, int act, int K, int O,
+                                                                  const float* __restrict__ base, float* din) {
+  __shared__ float part[kBwdWaves][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + lane;
   float acc = 0.f;
-  for (int o = 0; o < O; ++o) acc += W[(int64_t)o * K + k] * (d_act[o] * act_grad(act, a[o]));
-  din[k] = (base ? base[k] : 0.f) + acc;
+  if (k < K)
+    for (int o = wv; o < O; o += kBwdWaves) acc += W[(int64_t)o * K + k] * (d_act[o] * act_grad(act, a[o]));
+  part[wv][lane] = acc;
+  __syncthreads();
+  if (wv == 0 && k < K) {
+    float tot = base ? base[k] : 0.f;
+    for (int w = 0; w < kBwdWaves; ++w) tot += part[w][lane];
+    din[k] = tot;
+  }
 }
 
-// y1 = sum_i (tanh(c (z - rho_i)) + 1) / (2B); s = exp(j 2 pi y1).
+// One wave per chip, the K thresholds split over its lanes (sums in lane
+// order). y1 = sum_i (tanh(c (z - rho_i)) + 1) / (2B); s = exp(j 2 pi y1).
 __global__ __launch_bounds__(kThreads) void k_soft(const float* __restrict__ z, const float* __restrict__ rho,
                                                     int D, int K, int B, float c, float2* s) {
-  const int n = blockIdx.x * kThreads + threadIdx.x;
+  const int n = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (n >= D) return;
   const float zn = z[n];
   float acc = 0.f;
-  for (int i = 0; i < K; ++i) acc += tanhf(c * (zn - rho[i])) + 1.0f;
-  const float y1 = acc / (2.0f * (float)B);
-  float sn, cs;
-  sincospif(2.0f * y1, &sn, &cs);
-  s[n] = make_float2(cs, sn);
+  for (int i = lane; i < K; i += 64) acc += tanhf(c * (zn - rho[i])) + 1.0f;
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const float y1 = acc / (2.0f * (float)B);
+    float sn, cs;
+    sincospif(2.0f * y1, &sn, &cs);
+    s[n] = make_float2(cs, sn);
+  }
 }
 
-// dy = 2 pi Im(grad_s conj(s)); dz = dy sum_i c (1 - t_i^2) / (2B).
+// dy = 2 pi Im(grad_s conj(s)); dz = dy sum_i c (1 - t_i^2) / (2B); one wave per chip.
 __global__ __launch_bounds__(kThreads) void k_chain(const float* __restrict__ z, const float* __restrict__ rho,
                                                      const float2* __restrict__ s, const float2* __restrict__ gs,
                                                      int D, int K, int B, float c, float* dy_out, float* dz_out) {
-  const int n = blockIdx.x * kThreads + threadIdx.x;
+  const int n = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (n >= D) return;
-  const float2 g = gs[n], sv = s[n];
-  const float dy = 2.0f * 3.14159265358979f * (g.y * sv.x - g.x * sv.y);
   const float zn = z[n];
   float d = 0.f;
-  for (int i = 0; i < K; ++i) {
+  for (int i = lane; i < K; i += 64) {
     const float t = tanhf(c * (zn - rho[i]));
     d += 1.0f - t * t;
   }
-  dy_out[n] = dy;
-  dz_out[n] = dy * d * c / (2.0f * (float)B);
+  d = wave_sum(d);
+  if (lane == 0) {
+    const float2 g = gs[n], sv = s[n];
+    const float dy = 2.0f * 3.14159265358979f * (g.y * sv.x - g.x * sv.y);
+    dy_out[n] = dy;
+    dz_out[n] = dy * d * c / (2.0f * (float)B);
+  }
 }
 
 // drho_i = -sum_n dy_n c (1 - tanh(c (z_n - rho_i))^2) / (2B): one block per
@@ -130,33 +148,46 @@ __global__ __launch_bounds__(kThreads) void k_drho(const float* __restrict__ z, 
   }
 }
 
+// One wave per chip: the count of thresholds at or below z, mod B.
 __global__ __launch_bounds__(kThreads) void k_hard(const float* __restrict__ z, const float* __restrict__ rho,
                                                     int D, int K, int B, int32_t* idx, float2* x) {
-  const int n = blockIdx.x * kThreads + threadIdx.x;
+  const int n = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (n >= D) return;
   const float zn = z[n];
   int cnt = 0;
-  for (int i = 0; i < K; ++i) cnt += rho[i] <= zn ? 1 : 0;
-  const int k = cnt % B;
-  if (idx) idx[n] = k;
-  if (x) {
-    float sn, cs;
-    sincospif(2.0f * (float)k / (float)B, &sn, &cs);
-    x[n] = make_float2(cs, sn);
+  for (int i = lane; i < K; i += 64) cnt += rho[i] <= zn ? 1 : 0;
+  cnt = (int)wave_sum((float)cnt);  // exact: counts <= 4096
+  if (lane == 0) {
+    const int k = cnt % B;
+    if (idx) idx[n] = k;
+    if (x) {
+      float sn, cs;
+      sincospif(2.0f * (float)k / (float)B, &sn, &cs);
+      x[n] = make_float2(cs, sn);
+    }
   }
 }
 
+// Step count t = step_mul * (*step) + step_add when step is given (a device
+// counter, so that a captured graph replays with the current count), else
+// step_add.
 __global__ __launch_bounds__(kThreads) void k_adam(float* p, const float* __restrict__ g, float* m, float* v,
                                                     int64_t n, float lr, float b1, float b2, float eps,
-                                                    float bc1, float bc2) {
+                                                    const int32_t* step, int32_t step_mul, int32_t step_add) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
+  const float t = (float)((step ? step_mul * *step : 0) + step_add);
+  const float bc1 = 1.0f - powf(b1, t), bc2 = 1.0f - powf(b2, t);
   const float gi = g[i];
   const float mi = b1 * m[i] + (1.0f - b1) * gi;
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
   p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+__global__ void k_count(int32_t* step) {
+  if (threadIdx.x == 0) *step += 1;
 }
 
 // Ascending bitonic sort of K <= 4096 values in LDS (padded with +inf).
@@ -307,7 +338,7 @@ int sqngd_sqn_soft(const sqngd_sqn_shape* shape, const float* z, const float* rh
   if (z == nullptr || rho == nullptr || sw == nullptr) return SQNGD_E_INVALID_ARG;
   if (!aligned(z, 4) || !aligned(rho, 4) || !aligned(sw, 8)) return SQNGD_E_ALIGN;
   const int D = shape->M * shape->N, K = shape->B * shape->copies;
-  hipLaunchKernelGGL(k_soft, dim3(blocks_for(D)), dim3(kThreads), 0, (hipStream_t)stream, z, rho, D, K, shape->B,
+  hipLaunchKernelGGL(k_soft, dim3(blocks_for(64 * (int64_t)D)), dim3(kThreads), 0, (hipStream_t)stream, z, rho, D, K, shape->B,
                      shape->c, (float2*)sw);
   return check_launch();
 }
@@ -320,7 +351,7 @@ int sqngd_sqn_hard(const sqngd_sqn_shape* shape, const float* z, const float* rh
   if (z == nullptr || rho == nullptr || (idx == nullptr && x == nullptr)) return SQNGD_E_INVALID_ARG;
   if (!aligned(z, 4) || !aligned(rho, 4) || !aligned(idx, 4) || !aligned(x, 8)) return SQNGD_E_ALIGN;
   const int D = shape->M * shape->N, K = shape->B * shape->copies;
-  hipLaunchKernelGGL(k_hard, dim3(blocks_for(D)), dim3(kThreads), 0, (hipStream_t)stream, z, rho, D, K, shape->B,
+  hipLaunchKernelGGL(k_hard, dim3(blocks_for(64 * (int64_t)D)), dim3(kThreads), 0, (hipStream_t)stream, z, rho, D, K, shape->B,
                      idx, (float2*)x);
   return check_launch();
 }
@@ -350,7 +381,7 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
   float* dh[2] = {f + L.dh, f + L.dh + kH};
   float* du = f + L.du;
   // staircase: dL/dy1, dL/dz and dL/drho
-  hipLaunchKernelGGL(k_chain, dim3(blocks_for(D)), dim3(kThreads), 0, s, z, rho, (const float2*)sw,
+  hipLaunchKernelGGL(k_chain, dim3(blocks_for(64 * (int64_t)D)), dim3(kThreads), 0, s, z, rho, (const float2*)sw,
                      (const float2*)grad_s, D, K, B, shape->c, dy, dz);
   hipLaunchKernelGGL(k_drho, dim3(K), dim3(kThreads), 0, s, z, rho, (const float*)dy, D, B, shape->c, grad_rho);
   // output layer: a = z (sigmoid), input h_5
@@ -358,7 +389,7 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
   hipLaunchKernelGGL(k_dense_bwd_w, dim3(blocks_for((int64_t)D * kH)), dim3(kThreads), 0, s, (const float*)dz, z,
                      (int)ACT_SIGMOID, (const float*)(h + (int64_t)kBlocks * kH), kH, D, grad_theta + Y.w[lo],
                      grad_theta + Y.b[lo]);
-  hipLaunchKernelGGL(k_dense_bwd_in, dim3(blocks_for(kH)), dim3(kThreads), 0, s, theta + Y.w[lo], (const float*)dz, z,
+  hipLaunchKernelGGL(k_dense_bwd_in, dim3((kH + 63) / 64), dim3(64 * kBwdWaves), 0, s, theta + Y.w[lo], (const float*)dz, z,
                      (int)ACT_SIGMOID, kH, D, (const float*)nullptr, dh[0]);
   int cur = 0;
   for (int k = kBlocks - 1; k >= 0; --k) {
@@ -368,13 +399,13 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
     // residual branch, second layer: a = v, input u, upstream dh
     hipLaunchKernelGGL(k_dense_bwd_w, dim3(blocks_for((int64_t)kH * kH)), dim3(kThreads), 0, s,
                        (const float*)dh[cur], v, (int)ACT_TANH, u, kH, kH, grad_theta + Y.w[l2], grad_theta + Y.b[l2]);
-    hipLaunchKernelGGL(k_dense_bwd_in, dim3(blocks_for(kH)), dim3(kThreads), 0, s, theta + Y.w[l2],
+    hipLaunchKernelGGL(k_dense_bwd_in, dim3((kH + 63) / 64), dim3(64 * kBwdWaves), 0, s, theta + Y.w[l2],
                        (const float*)dh[cur], v, (int)ACT_TANH, kH, kH, (const float*)nullptr, du);
     // first layer: a = u, input h_{k}, upstream du; dh_new = dh + W1^T dp
     hipLaunchKernelGGL(k_dense_bwd_w, dim3(blocks_for((int64_t)kH * kH)), dim3(kThreads), 0, s, (const float*)du, u,
                        (int)ACT_TANH, (const float*)(h + (int64_t)k * kH), kH, kH, grad_theta + Y.w[l1],
                        grad_theta + Y.b[l1]);
-    hipLaunchKernelGGL(k_dense_bwd_in, dim3(blocks_for(kH)), dim3(kThreads), 0, s, theta + Y.w[l1], (const float*)du,
+    hipLaunchKernelGGL(k_dense_bwd_in, dim3((kH + 63) / 64), dim3(64 * kBwdWaves), 0, s, theta + Y.w[l1], (const float*)du,
                        u, (int)ACT_TANH, kH, kH, (const float*)dh[cur], dh[cur ^ 1]);
     cur ^= 1;
   }
@@ -384,18 +415,25 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
   return check_launch();
 }
 
-int sqngd_sqn_adam(float* p, const float* g, float* m, float* v, int64_t n, int32_t t, float lr, float beta1,
-                   float beta2, float eps, void* stream) {
+int sqngd_sqn_adam(float* p, const float* g, float* m, float* v, int64_t n, const int32_t* step, int32_t step_mul,
+                   int32_t step_add, float lr, float beta1, float beta2, float eps, void* stream) {
   using namespace sqsqn;
-  if (p == nullptr || g == nullptr || m == nullptr || v == nullptr || n < 1 || t < 1) return SQNGD_E_INVALID_ARG;
+  if (p == nullptr || g == nullptr || m == nullptr || v == nullptr || n < 1) return SQNGD_E_INVALID_ARG;
+  if (step_mul < 0 || step_add < 0 || (step == nullptr && step_add < 1)) return SQNGD_E_INVALID_ARG;
   if (!std::isfinite(lr) || lr < 0.f || !(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f) ||
       !std::isfinite(eps) || eps <= 0.f)
     return SQNGD_E_INVALID_ARG;
-  if (!aligned(p, 4) || !aligned(g, 4) || !aligned(m, 4) || !aligned(v, 4)) return SQNGD_E_ALIGN;
-  const float bc1 = (float)(1.0 - std::pow((double)beta1, (double)t));
-  const float bc2 = (float)(1.0 - std::pow((double)beta2, (double)t));
+  if (!aligned(p, 4) || !aligned(g, 4) || !aligned(m, 4) || !aligned(v, 4) || !aligned(step, 4)) return SQNGD_E_ALIGN;
   hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(kThreads), 0, (hipStream_t)stream, p, g, m, v, n, lr, beta1,
-                     beta2, eps, bc1, bc2);
+                     beta2, eps, step, step_mul, step_add);
+  return check_launch();
+}
+
+int sqngd_sqn_count(int32_t* step, void* stream) {
+  using namespace sqsqn;
+  if (step == nullptr) return SQNGD_E_INVALID_ARG;
+  if (!aligned(step, 4)) return SQNGD_E_ALIGN;
+  hipLaunchKernelGGL(k_count, dim3(1), dim3(64), 0, (hipStream_t)stream, step);
   return check_launch();
 }
 

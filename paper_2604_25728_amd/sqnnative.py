@@ -18,7 +18,8 @@ from . import inputs as I
 from . import native as nat
 
 SYMBOLS = ["sqngd_sqn_param_count", "sqngd_sqn_workspace_size", "sqngd_sqn_forward", "sqngd_sqn_soft",
-           "sqngd_sqn_hard", "sqngd_sqn_backward", "sqngd_sqn_adam", "sqngd_sqn_sort", "sqngd_sqn_project"]
+           "sqngd_sqn_hard", "sqngd_sqn_backward", "sqngd_sqn_adam", "sqngd_sqn_count", "sqngd_sqn_sort",
+           "sqngd_sqn_project"]
 
 
 class SqnShape(ctypes.Structure):
@@ -40,7 +41,8 @@ def lib():
         L.sqngd_sqn_soft.argtypes = [P, P, P, P, P]
         L.sqngd_sqn_hard.argtypes = [P, P, P, P, P, P]
         L.sqngd_sqn_backward.argtypes = [P, P, P, P, P, P, P, P, P, P, sz, P]
-        L.sqngd_sqn_adam.argtypes = [P, P, P, P, i64, i32, f, f, f, f, P]
+        L.sqngd_sqn_adam.argtypes = [P, P, P, P, i64, P, i32, i32, f, f, f, f, P]
+        L.sqngd_sqn_count.argtypes = [P, P]
         L.sqngd_sqn_sort.argtypes = [P, i32, P]
         L.sqngd_sqn_project.argtypes = [i32, i32, P, P]
         for n in SYMBOLS:
@@ -57,9 +59,10 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def adam(p, g, m, v, t: int, lr: float, beta1: float, beta2: float, eps: float):
-    nat.check(lib().sqngd_sqn_adam(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), int(t), float(lr), float(beta1),
-                                   float(beta2), float(eps), _stream()), "sqn_adam")
+def adam(p, g, m, v, t: int, lr: float, beta1: float, beta2: float, eps: float, step=None, step_mul: int = 0):
+    """Adam with step count t, or step_mul * step[0] + t with a device counter."""
+    nat.check(lib().sqngd_sqn_adam(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), _ptr(step), int(step_mul), int(t),
+                                   float(lr), float(beta1), float(beta2), float(eps), _stream()), "sqn_adam")
 
 
 class SQN:
@@ -141,21 +144,28 @@ class SQNDesign:
         self.mt, self.vt = zeros(self.sqn.count), zeros(self.sqn.count)
         self.mr, self.vr = zeros(self.sqn.K), zeros(self.sqn.K)
         self.mh, self.vh = zeros(2 * M * N), zeros(2 * M * N)
-        self.t = 0
+        self.counter = torch.zeros(1, dtype=torch.int32, device=dev)  # outer iterations done
         self.stats_a = self.batch.new_stats()
         self.stats_b = self.batch.new_stats()
+        self.graph = None
+
+    @property
+    def t(self) -> int:
+        return int(self.counter.item())
 
     def iteration(self):
+        """Enqueue one outer iteration (Adam step counts from the device counter)."""
         o = self.opt
         b1, b2, eps = o["beta1"], o["beta2"], o["eps"]
+        nh, nx = int(o["n_h"]), int(o["n_x"])
         self.z = self.sqn.forward(self.theta, self.y0, self.z)
         _, x = self.sqn.hard(self.z, self.rho, want_idx=False)
         hv = torch.view_as_real(self.h).reshape(-1)
         for i in range(int(o["n_h"])):
             _, gh, _ = self.batch.af_backward(None, self.h, nat.WAVE_GIVEN, s_given=x, want_z=False, want_h=True,
                                               stats=self.stats_a)
-            adam(hv, torch.view_as_real(gh).reshape(-1), self.mh, self.vh, self.t * int(o["n_h"]) + i + 1,
-                 o["lr_h"], b1, b2, eps)
+            adam(hv, torch.view_as_real(gh).reshape(-1), self.mh, self.vh, i + 1, o["lr_h"], b1, b2, eps,
+                 step=self.counter, step_mul=nh)
             self.sqn.project(self.h)
         for j in range(int(o["n_x"])):
             self.z = self.sqn.forward(self.theta, self.y0, self.z)
@@ -163,11 +173,29 @@ class SQNDesign:
             _, _, gs = self.batch.af_backward(None, self.h, nat.WAVE_GIVEN, s_given=s, want_z=False, want_h=False,
                                               want_s=True, stats=self.stats_b)
             gt, gr = self.sqn.backward(self.theta, self.y0, self.z, self.rho, s, gs)
-            k = self.t * int(o["n_x"]) + j + 1
-            adam(self.theta, gt, self.mt, self.vt, k, o["lr_z"], b1, b2, eps)
-            adam(self.rho, gr, self.mr, self.vr, k, o["lr_z"], b1, b2, eps)
+            adam(self.theta, gt, self.mt, self.vt, j + 1, o["lr_z"], b1, b2, eps, step=self.counter, step_mul=nx)
+            adam(self.rho, gr, self.mr, self.vr, j + 1, o["lr_z"], b1, b2, eps, step=self.counter, step_mul=nx)
             self.sqn.sort(self.rho)
-        self.t += 1
+        nat.check(lib().sqngd_sqn_count(_ptr(self.counter), _stream()), "sqn_count")
+
+    def capture(self):
+        """Record one outer iteration in a HIP graph; run() replays it."""
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.iteration()
+        self.graph = g
+        return g
+
+    def run(self, iters: int, use_graph: bool = True):
+        if not use_graph:
+            for _ in range(iters):
+                self.iteration()
+            return
+        if self.graph is None:
+            self.capture()
+        for _ in range(iters):
+            self.graph.replay()
 
     def hard_stats(self):
         z = self.sqn.forward(self.theta, self.y0)

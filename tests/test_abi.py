@@ -235,5 +235,8 @@ def test_sqn_validation(nat):
         assert lib.sqngd_sqn_workspace_size(ctypes.byref(sh), ctypes.byref(b)) == rc, bad
     assert lib.sqngd_sqn_sort(None, 4, None) == -1
     assert lib.sqngd_sqn_sort(ctypes.c_void_p(16), 5000, None) == -2
-    assert lib.sqngd_sqn_adam(None, None, None, None, 4, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert lib.sqngd_sqn_adam(None, None, None, None, 4, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    v = ctypes.c_void_p(256)
+    assert lib.sqngd_sqn_adam(v, v, v, v, 4, None, 0, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1  # t = 0
+    assert lib.sqngd_sqn_count(None, None) == -1
     assert lib.sqngd_sqn_project(0, 4, ctypes.c_void_p(16), None) == -1

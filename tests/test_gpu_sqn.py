@@ -84,8 +84,10 @@ def test_adam_sort_project(SN, S):
     p0, g = rng.standard_normal(1000).astype(np.float32), rng.standard_normal(1000).astype(np.float32)
     p, m, v = _t(p0), torch.zeros(1000, device="cuda"), torch.zeros(1000, device="cuda")
     pr, mr, vr = p0.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
     for t in (1, 2, 3):
-        SN.adam(p, _t(g), m, v, t, 1e-2, 0.9, 0.999, 1e-8)
+        SN.adam(p, _t(g), m, v, 1, 1e-2, 0.9, 0.999, 1e-8, step=cnt, step_mul=1)  # t from the device counter
+        SN.lib().sqngd_sqn_count(SN._ptr(cnt), SN._stream())
         pr, mr, vr = R.adam(pr, g.astype(np.float64), mr, vr, t, 1e-2, 0.9, 0.999, 1e-8)
     q = SN.SQN(2, 8, 4, 700, 30.0)   # K = 2800 thresholds (padded to 4096 in the sort)
     rho = rng.random(2800).astype(np.float32)
@@ -129,3 +131,21 @@ def test_two_iterations_match_oracle(SN, S):
     from paper_2604_25728_amd import native as nat
     stb = nat.decode_stats(d.stats_b.cpu().numpy())[0]
     assert abs(stb["loss"] - sb["loss"]) <= 1e-4 * sb["loss"]
+
+
+def test_graph_replay_matches_eager(SN):
+    """Replays of a captured outer iteration (step counts from the device
+    counter) equal eager iterations, with eager work between the replays."""
+    prob = I.make_problem(2, 64, 4, 5, p=8.0)
+    opt = I.make_opt(lr_z=1e-3, lr_h=1e-2)
+    print("[gpu] sqn graph replay", flush=True)
+    a = SN.SQNDesign(prob, opt, 3, 30.0, seed=50)
+    b = SN.SQNDesign(prob, opt, 3, 30.0, seed=50)
+    a.capture()
+    for i in range(3):
+        a.graph.replay()
+        b.iteration()
+        torch.cuda.synchronize()
+        _ = (a.theta * 2).sum().item()
+        assert torch.equal(a.theta, b.theta) and torch.equal(a.h, b.h) and torch.equal(a.rho, b.rho), i
+    assert a.t == b.t == 3

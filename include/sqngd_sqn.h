@@ -23,7 +23,9 @@
  *
  * Ownership: every array is a DEVICE pointer owned by the caller; the shape is
  * a HOST pointer read during the call. The network's activations live in the
- * caller's workspace (size from sqngd_sqn_workspace_size, 256-byte aligned):
+ * caller's workspace (size from sqngd_sqn_workspace_size, 256-byte aligned;
+ * sqngd_sqn_forward also wants theta 16-byte aligned, as it reads the
+ * hidden layers in 16-byte pieces):
  * sqngd_sqn_backward uses those the last sqngd_sqn_forward on the same
  * workspace left there. Calls only enqueue on `stream` (a hipStream_t passed
  * as void*), allocate nothing and issue no memset.

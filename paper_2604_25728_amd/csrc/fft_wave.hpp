@@ -143,6 +143,7 @@ __device__ __forceinline__ float dpp_f(float old, float x) {
 }
 template <int TF, class Op>
 __device__ __forceinline__ float slot_reduce(float v, float ident, Op op) {
+  static_assert(TF == 16 || TF == 32 || TF == 64, "slot_reduce spans whole 16-lane rows");
   v = op(v, dpp_f<0x111, 0xF>(ident, v));  // row_shr:1
   v = op(v, dpp_f<0x112, 0xF>(ident, v));  // row_shr:2
   v = op(v, dpp_f<0x114, 0xF>(ident, v));  // row_shr:4

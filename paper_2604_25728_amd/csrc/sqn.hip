@@ -3,14 +3,16 @@
 // its host helpers (one translation unit).
 //
 // The network runs on a single input vector, so every dense layer is a
-// matrix-vector product bound by reading its weights once: one wavefront per
-// output (lanes stride over the inputs, a DPP sum in lane order, so results
-// are the same run to run). The backward pass mirrors the forward layer by
-// layer: an outer-product kernel for the weight and bias gradients and a
-// transposed product (one thread per input, outputs summed in order) for the
-// gradient of the layer's input. The staircase, its gradient, the hard
-// quantiser, Adam, the ordered projection of the thresholds (a bitonic sort in
-// LDS) and the filters' energy projection are element- or row-wise kernels.
+// matrix-vector product bound by reading its weights once. The wide input
+// and output layers spread over the chip (one wavefront per output, lanes
+// stride over the inputs, a DPP sum in lane order, so results are the same
+// run to run); the ten 128 x 128 hidden layers run in one workgroup that
+// keeps the activations in LDS, forward and backward, instead of twenty
+// dependent launches. The weight and bias gradients of all layers are outer
+// products, written by one launch over theta's layout. The staircase, its
+// gradient and the hard quantiser take one wave per chip with the thresholds
+// over the lanes; Adam, the ordered projection of the thresholds (a bitonic
+// sort in LDS) and the filters' energy projection are element- or row-wise.
 #include "../../include/sqngd_sqn.h"
 
 namespace sqsqn {
@@ -23,7 +25,7 @@ constexpr int kThreads = 256;
 constexpr int kMaxD = 4096;
 constexpr int kMaxK = 4096;
 
-enum Act : int { ACT_TANH = 0, ACT_SIGMOID = 1 };
+enum Act : int { ACT_TANH = 0, ACT_SIGMOID = 1, ACT_NONE = 2 };
 
 // a[o] = act(W[o][:] . in + b[o]); out[o] = res[o] + a[o] when res is given.
 template <int ACT>
@@ -46,43 +48,247 @@ __global__ __launch_bounds__(kThreads) void k_dense_fwd(const float* __restrict_
 }
 
 __device__ __forceinline__ float act_grad(int act, float a) {
-  return act == ACT_TANH ? 1.0f - a * a : a * (1.0f - a);
+  return act == ACT_TANH ? 1.0f - a * a : (act == ACT_SIGMOID ? a * (1.0f - a) : 1.0f);
 }
 
-// dW[o][k] = dp[o] in[k], db[o] = dp[o], dp[o] = d_act[o] act'(a[o]).
-__global__ __launch_bounds__(kThreads) void k_dense_bwd_w(const float* __restrict__ d_act,
-                                                           const float* __restrict__ a, int act,
-                                                           const float* __restrict__ in, int K, int O,
-                                                           float* dW, float* db) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t n = (int64_t)O * K;
-  if (i < n) {
-    const int o = (int)(i / K), k = (int)(i - (int64_t)o * K);
-    dW[i] = d_act[o] * act_grad(act, a[o]) * in[k];
+// The ten hidden layers (five residual blocks) in one workgroup: activations
+// stay in LDS, each layer's 128 x 128 weights stream from L2 once, and a wave
+// owns 8 outputs (the same lane-strided dot product and DPP sum as
+// k_dense_fwd). th points at the first hidden layer's weights; layers follow
+// at kHidStride floats. h[0] holds the input-layer activation; h[1..5], u, v
+// are written for the backward pass.
+constexpr int kStackThreads = 1024;
+constexpr int kStackWaves = kStackThreads / 64;
+constexpr int kOutPerWave = kH / kStackWaves;
+constexpr int64_t kHidStride = (int64_t)kH * kH + kH;
+static_assert(kH == 128 && kOutPerWave * kStackWaves == kH, "hidden-stack tiling");
+
+// A wave owns the 8 outputs o = 8 wv + j; lane 8 j + c computes the partial
+// dot product of row o over the 16 inputs [16 c, 16 c + 16) (in order) and
+// the 8 partials of a row are added by a DPP sum within the lane group, so a
+// layer costs one short reduction per wave instead of one per output. The
+// weights do not depend on the activations, so they are loaded kAhead - 1
+// layers ahead of their use.
+constexpr int kAhead = 5;
+constexpr int kSeg = kH / 8;  // inputs per lane
+struct StackW {
+  float4 w[kSeg / 4];
+  float b;
+};
+__device__ __forceinline__ StackW stack_load(const float* __restrict__ W, int wv, int lane) {
+  StackW r;
+  const int o = wv * kOutPerWave + (lane >> 3), c = lane & 7;
+  const float4* row = (const float4*)(W + (int64_t)o * kH + c * kSeg);
+#pragma unroll
+  for (int q = 0; q < kSeg / 4; ++q) r.w[q] = row[q];
+  r.b = W[(int64_t)kH * kH + o];
+  return r;
+}
+
+__device__ __forceinline__ void stack_layer(const StackW& L, const float* in, int wv, int lane, float* res,
+                                            float* a_lds, float* a_glob) {
+  const int o = wv * kOutPerWave + (lane >> 3), c = lane & 7;
+  const float4* x = (const float4*)(in + c * kSeg);
+  float acc = 0.f;
+#pragma unroll
+  for (int q = 0; q < kSeg / 4; ++q) {
+    const float4 xv = x[q];
+    acc += L.w[q].x * xv.x;
+    acc += L.w[q].y * xv.y;
+    acc += L.w[q].z * xv.z;
+    acc += L.w[q].w * xv.w;
   }
-  if (i < O) db[i] = d_act[i] * act_grad(act, a[i]);
+  // sum over the lane group 8 j .. 8 j + 7: after row_shr 1, 2, 4 its last
+  // lane holds lanes 8 j .. 8 j + 7 (lanes shifted in from outside the row add 0)
+  acc += sq::dpp_f<0x111, 0xF>(0.f, acc);
+  acc += sq::dpp_f<0x112, 0xF>(0.f, acc);
+  acc += sq::dpp_f<0x114, 0xF>(0.f, acc);
+  acc = __shfl(acc, (lane & ~7) + 7);
+  if (c == 0) {
+    const float a = tanhf(acc + L.b);
+    a_lds[o] = a;
+    a_glob[o] = a;
+    if (res) res[o] += a;
+  }
 }
 
-// din[k] = base[k] + sum_o W[o][k] dp[o], dp as above: a block owns 64
-// inputs (one per lane); its 16 waves take the outputs o = w (mod 16) and
-// their partial sums are added in wave order.
+__global__ __launch_bounds__(kStackThreads) void k_res_fwd(const float* __restrict__ th, float* h, float* u,
+                                                            float* v) {
+  __shared__ __align__(16) float xs[kH];
+  __shared__ __align__(16) float us[kH];
+  __shared__ float vs[kH];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  StackW buf[kAhead];
+#pragma unroll
+  for (int l = 0; l + 1 < kAhead; ++l) buf[l] = stack_load(th + l * kHidStride, wv, lane);
+  if (threadIdx.x < kH) xs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+#pragma unroll
+  for (int l = 0; l < 2 * kBlocks; ++l) {
+    if (l + kAhead - 1 < 2 * kBlocks)
+      buf[(l + kAhead - 1) % kAhead] = stack_load(th + (l + kAhead - 1) * kHidStride, wv, lane);
+    const int k = l >> 1;
+    if ((l & 1) == 0) {
+      stack_layer(buf[l % kAhead], xs, wv, lane, nullptr, us, u + k * kH);
+      __syncthreads();
+    } else {
+      stack_layer(buf[l % kAhead], us, wv, lane, xs, vs, v + k * kH);
+      __syncthreads();
+      if (threadIdx.x < kH) h[(k + 1) * kH + threadIdx.x] = xs[threadIdx.x];
+    }
+  }
+}
+
+// out[k] = sum_o W[o][k] d[o] over the hidden width, 16 waves: wave w takes
+// the inputs k = 64 (w & 1) + lane and the outputs o in [16 (w >> 1), +16);
+// the eight partial sums per input are added in order by the caller. The
+// weights are loaded kAhead - 1 layers ahead (stack_tload) like the forward's.
+struct StackT {
+  float w[16];
+};
+__device__ __forceinline__ StackT stack_tload(const float* __restrict__ W, int wv, int lane) {
+  StackT r;
+  const int kk = (wv & 1) * 64 + lane, g = wv >> 1;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) r.w[j] = W[(int64_t)(g * 16 + j) * kH + kk];
+  return r;
+}
+__device__ __forceinline__ void stack_transposed(const StackT& T, const float* d, int wv, int lane,
+                                                 float (*red)[kH]) {
+  const int kk = (wv & 1) * 64 + lane, g = wv >> 1;
+  float acc = 0.f;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc += T.w[j] * d[g * 16 + j];
+  red[g][kk] = acc;
+}
+
+// Backward through the hidden stack in one workgroup. The gradient into h_5
+// arrives as S partial sums [S][H] (from k_dense_bwd_part); dp[l][:] receives
+// the pre-activation gradient of layer l = 0..10 (layer 0 is the input layer)
+// for k_dw_all.
+__global__ __launch_bounds__(kStackThreads) void k_res_bwd(const float* __restrict__ th,
+                                                            const float* __restrict__ part, int S,
+                                                            const float* __restrict__ h, const float* __restrict__ u,
+                                                            const float* __restrict__ v, float* dp) {
+  __shared__ float dh[kH], ds[kH];
+  __shared__ float red[8][kH];
+  __shared__ float us[kBlocks * kH], vs[kBlocks * kH];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  // the forward's activations are staged in LDS so the chain below waits on
+  // no global load but the (prefetched) weights
+  for (int i = t; i < kBlocks * kH; i += kStackThreads) {
+    us[i] = u[i];
+    vs[i] = v[i];
+  }
+  const float h0 = t < kH ? h[t] : 0.f;
+  if (t < kH) {
+    float acc = 0.f;
+    for (int i = 0; i < S; ++i) acc += part[i * kH + t];
+    dh[t] = acc;
+  }
+  __syncthreads();
+  // hidden layers from the last (10) down to 1; buffer i holds layer 10 - i
+  StackT buf[kAhead];
+#pragma unroll
+  for (int i = 0; i + 1 < kAhead; ++i) buf[i] = stack_tload(th + (2 * kBlocks - 1 - i) * kHidStride, wv, lane);
+#pragma unroll
+  for (int i = 0; i < 2 * kBlocks; ++i) {
+    const int l = 2 * kBlocks - i, k = (l - 1) >> 1;
+    if (i + kAhead - 1 < 2 * kBlocks)
+      buf[(i + kAhead - 1) % kAhead] = stack_tload(th + (l - kAhead) * kHidStride, wv, lane);
+    if (t < kH) {
+      // second layer of block k (a = v_k, upstream dh) or first (a = u_k, upstream du)
+      float d;
+      if ((l & 1) == 0) {
+        d = dh[t] * act_grad(ACT_TANH, vs[k * kH + t]);
+      } else {
+        float du = 0.f;
+        for (int g = 0; g < 8; ++g) du += red[g][t];
+        d = du * act_grad(ACT_TANH, us[k * kH + t]);
+      }
+      ds[t] = d;
+      dp[l * kH + t] = d;
+    }
+    __syncthreads();
+    stack_transposed(buf[i % kAhead], ds, wv, lane, red);
+    __syncthreads();
+    if ((l & 1) == 1) {
+      // dh_k = dh_{k+1} + W1^T dp1
+      if (t < kH) {
+        float acc = dh[t];
+        for (int g = 0; g < 8; ++g) acc += red[g][t];
+        dh[t] = acc;
+      }
+      __syncthreads();
+    }
+  }
+  if (t < kH) dp[t] = dh[t] * act_grad(ACT_TANH, h0);
+}
+
+// part[s][k] = sum over o in chunk s of W[o][k] dp[o], dp[o] = d_act[o]
+// act'(a[o]): blocks (input tile of 64, chunk s); the block's 16 waves stride
+// over the chunk's outputs and are added in wave order.
 constexpr int kBwdWaves = 16;
-__global__ __launch_bounds__(64 * kBwdWaves) void k_dense_bwd_in(const float* __restrict__ W,
-                                                                  const float* __restrict__ d_act,
-                                                                  const float* __restrict__ a, int act, int K, int O,
-                                                                  const float* __restrict__ base, float* din) {
-  __shared__ float part[kBwdWaves][64];
+constexpr int kBwdSplit = 16;
+__global__ __launch_bounds__(64 * kBwdWaves) void k_dense_bwd_part(const float* __restrict__ W,
+                                                                    const float* __restrict__ d_act,
+                                                                    const float* __restrict__ a, int act, int K,
+                                                                    int O, float* part) {
+  __shared__ float sh[kBwdWaves][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int k = blockIdx.x * 64 + lane;
+  const int chunk = (O + kBwdSplit - 1) / kBwdSplit;
+  const int o0 = blockIdx.y * chunk, o1 = min(O, o0 + chunk);
   float acc = 0.f;
   if (k < K)
-    for (int o = wv; o < O; o += kBwdWaves) acc += W[(int64_t)o * K + k] * (d_act[o] * act_grad(act, a[o]));
-  part[wv][lane] = acc;
+    for (int o = o0 + wv; o < o1; o += kBwdWaves) acc += W[(int64_t)o * K + k] * (d_act[o] * act_grad(act, a[o]));
+  sh[wv][lane] = acc;
   __syncthreads();
   if (wv == 0 && k < K) {
-    float tot = base ? base[k] : 0.f;
-    for (int w = 0; w < kBwdWaves; ++w) tot += part[w][lane];
-    din[k] = tot;
+    float tot = 0.f;
+    for (int w = 0; w < kBwdWaves; ++w) tot += sh[w][lane];
+    part[(int64_t)blockIdx.y * K + k] = tot;
+  }
+}
+
+// Weight and bias gradients of every layer in one launch over theta's
+// layout: dW[o][k] = dp[o] x[k], db[o] = dp[o], with dp[o] = d[o] act'(a[o])
+// (act = ACT_NONE when d already is the pre-activation gradient).
+constexpr int kLayers = 2 * kBlocks + 2;
+struct DwArgs {
+  int64_t w[kLayers], b[kLayers];
+  const float* d[kLayers];
+  const float* a[kLayers];
+  const float* x[kLayers];
+  int in[kLayers], act[kLayers];
+  float* g;
+  int64_t total;
+};
+
+__global__ __launch_bounds__(kThreads) void k_dw_all(DwArgs A) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= A.total) return;
+  int64_t w = A.w[0], b = A.b[0];
+  const float *d = A.d[0], *a = A.a[0], *x = A.x[0];
+  int in = A.in[0], act = A.act[0];
+#pragma unroll
+  for (int l = 1; l < kLayers; ++l)
+    if (i >= A.w[l]) {
+      w = A.w[l];
+      b = A.b[l];
+      d = A.d[l];
+      a = A.a[l];
+      x = A.x[l];
+      in = A.in[l];
+      act = A.act[l];
+    }
+  if (i < b) {
+    const int64_t e = i - w;
+    const int o = (int)(e / in), k = (int)(e - (int64_t)o * in);
+    A.g[i] = d[o] * act_grad(act, a ? a[o] : 0.f) * x[k];
+  } else {
+    const int o = (int)(i - b);
+    A.g[i] = d[o] * act_grad(act, a ? a[o] : 0.f);
   }
 }
 
@@ -190,7 +396,9 @@ __global__ void k_count(int32_t* step) {
   if (threadIdx.x == 0) *step += 1;
 }
 
-// Ascending bitonic sort of K <= 4096 values in LDS (padded with +inf).
+// Ascending bitonic sort of K <= 4096 values in LDS (padded with +inf). A
+// rank sort (each value placed by counting smaller keys) measured slower at
+// the paper's K = 400: its K^2 comparisons run on the one CU.
 __global__ __launch_bounds__(1024) void k_sort(float* rho, int K) {
   __shared__ float v[kMaxK];
   int Kp = 1;
@@ -250,18 +458,20 @@ struct Layers {
   }
 };
 
-// Workspace (floats): h[0..5][H], u[1..5][H], v[1..5][H], dh[2][H], du[H], dy[D], dz[D].
+// Workspace (floats): h[0..5][H], u[1..5][H], v[1..5][H], dy[D], dz[D],
+// dp[11][H] (pre-activation gradients of the input and hidden layers) and
+// part[kBwdSplit][H] (split sums of the output layer's transposed product).
 struct WsLayout {
-  int64_t h, u, v, dh, du, dy, dz, total;
+  int64_t h, u, v, dy, dz, dp, part, total;
   explicit WsLayout(int D) {
     h = 0;
     u = h + (int64_t)(kBlocks + 1) * kH;
     v = u + (int64_t)kBlocks * kH;
-    dh = v + (int64_t)kBlocks * kH;
-    du = dh + 2 * kH;
-    dy = du + kH;
+    dy = v + (int64_t)kBlocks * kH;
     dz = dy + D;
-    total = dz + D;
+    dp = dz + D;
+    part = dp + (int64_t)(2 * kBlocks + 1) * kH;
+    total = part + (int64_t)kBwdSplit * kH;
   }
 };
 
@@ -301,7 +511,7 @@ int sqngd_sqn_forward(const sqngd_sqn_shape* shape, const float* theta, const fl
   int rc = validate(shape);
   if (rc != SQNGD_OK) return rc;
   if (theta == nullptr || y0 == nullptr || z == nullptr || ws == nullptr) return SQNGD_E_INVALID_ARG;
-  if (!aligned(theta, 4) || !aligned(y0, 4) || !aligned(z, 4) || !aligned(ws, kAlign))
+  if (!aligned(theta, 16) || !aligned(y0, 4) || !aligned(z, 4) || !aligned(ws, kAlign))
     return SQNGD_E_ALIGN;
   const int D = shape->M * shape->N;
   const WsLayout L(D);
@@ -313,17 +523,7 @@ int sqngd_sqn_forward(const sqngd_sqn_shape* shape, const float* theta, const fl
   const int wb = kThreads / 64;
   hipLaunchKernelGGL(k_dense_fwd<ACT_TANH>, dim3((kH + wb - 1) / wb), dim3(kThreads), 0, s, y0, D, theta + Y.w[0],
                      theta + Y.b[0], kH, (const float*)nullptr, (float*)nullptr, h);
-  for (int k = 0; k < kBlocks; ++k) {
-    const int l1 = 1 + 2 * k, l2 = 2 + 2 * k;
-    float* u = f + L.u + (int64_t)k * kH;
-    float* v = f + L.v + (int64_t)k * kH;
-    hipLaunchKernelGGL(k_dense_fwd<ACT_TANH>, dim3((kH + wb - 1) / wb), dim3(kThreads), 0, s,
-                       (const float*)(h + (int64_t)k * kH), kH, theta + Y.w[l1], theta + Y.b[l1], kH,
-                       (const float*)nullptr, u, (float*)nullptr);
-    hipLaunchKernelGGL(k_dense_fwd<ACT_TANH>, dim3((kH + wb - 1) / wb), dim3(kThreads), 0, s, (const float*)u, kH,
-                       theta + Y.w[l2], theta + Y.b[l2], kH, (const float*)(h + (int64_t)k * kH), v,
-                       h + (int64_t)(k + 1) * kH);
-  }
+  hipLaunchKernelGGL(k_res_fwd, dim3(1), dim3(kStackThreads), 0, s, theta + Y.w[1], h, f + L.u, f + L.v);
   const int lo = 2 * kBlocks + 1;
   hipLaunchKernelGGL(k_dense_fwd<ACT_SIGMOID>, dim3((D + wb - 1) / wb), dim3(kThreads), 0, s,
                      (const float*)(h + (int64_t)kBlocks * kH), kH, theta + Y.w[lo], theta + Y.b[lo], D,
@@ -378,40 +578,44 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
   float* h = f + L.h;
   float* dy = f + L.dy;
   float* dz = f + L.dz;
-  float* dh[2] = {f + L.dh, f + L.dh + kH};
-  float* du = f + L.du;
+  float* dp = f + L.dp;
+  float* part = f + L.part;
   // staircase: dL/dy1, dL/dz and dL/drho
   hipLaunchKernelGGL(k_chain, dim3(blocks_for(64 * (int64_t)D)), dim3(kThreads), 0, s, z, rho, (const float2*)sw,
                      (const float2*)grad_s, D, K, B, shape->c, dy, dz);
   hipLaunchKernelGGL(k_drho, dim3(K), dim3(kThreads), 0, s, z, rho, (const float*)dy, D, B, shape->c, grad_rho);
-  // output layer: a = z (sigmoid), input h_5
+  // output layer (a = z, sigmoid): gradient into h_5 as split sums
   const int lo = 2 * kBlocks + 1;
-  hipLaunchKernelGGL(k_dense_bwd_w, dim3(blocks_for((int64_t)D * kH)), dim3(kThreads), 0, s, (const float*)dz, z,
-                     (int)ACT_SIGMOID, (const float*)(h + (int64_t)kBlocks * kH), kH, D, grad_theta + Y.w[lo],
-                     grad_theta + Y.b[lo]);
-  hipLaunchKernelGGL(k_dense_bwd_in, dim3((kH + 63) / 64), dim3(64 * kBwdWaves), 0, s, theta + Y.w[lo], (const float*)dz, z,
-                     (int)ACT_SIGMOID, kH, D, (const float*)nullptr, dh[0]);
-  int cur = 0;
-  for (int k = kBlocks - 1; k >= 0; --k) {
-    const int l1 = 1 + 2 * k, l2 = 2 + 2 * k;
-    const float* u = f + L.u + (int64_t)k * kH;
-    const float* v = f + L.v + (int64_t)k * kH;
-    // residual branch, second layer: a = v, input u, upstream dh
-    hipLaunchKernelGGL(k_dense_bwd_w, dim3(blocks_for((int64_t)kH * kH)), dim3(kThreads), 0, s,
-                       (const float*)dh[cur], v, (int)ACT_TANH, u, kH, kH, grad_theta + Y.w[l2], grad_theta + Y.b[l2]);
-    hipLaunchKernelGGL(k_dense_bwd_in, dim3((kH + 63) / 64), dim3(64 * kBwdWaves), 0, s, theta + Y.w[l2],
-                       (const float*)dh[cur], v, (int)ACT_TANH, kH, kH, (const float*)nullptr, du);
-    // first layer: a = u, input h_{k}, upstream du; dh_new = dh + W1^T dp
-    hipLaunchKernelGGL(k_dense_bwd_w, dim3(blocks_for((int64_t)kH * kH)), dim3(kThreads), 0, s, (const float*)du, u,
-                       (int)ACT_TANH, (const float*)(h + (int64_t)k * kH), kH, kH, grad_theta + Y.w[l1],
-                       grad_theta + Y.b[l1]);
-    hipLaunchKernelGGL(k_dense_bwd_in, dim3((kH + 63) / 64), dim3(64 * kBwdWaves), 0, s, theta + Y.w[l1], (const float*)du,
-                       u, (int)ACT_TANH, kH, kH, (const float*)dh[cur], dh[cur ^ 1]);
-    cur ^= 1;
+  hipLaunchKernelGGL(k_dense_bwd_part, dim3((kH + 63) / 64, kBwdSplit), dim3(64 * kBwdWaves), 0, s, theta + Y.w[lo],
+                     (const float*)dz, z, (int)ACT_SIGMOID, kH, D, part);
+  // hidden stack and input layer: pre-activation gradients dp[0..10]
+  hipLaunchKernelGGL(k_res_bwd, dim3(1), dim3(kStackThreads), 0, s, theta + Y.w[1], (const float*)part, kBwdSplit,
+                     (const float*)h, (const float*)(f + L.u), (const float*)(f + L.v), dp);
+  // weight and bias gradients of all layers
+  DwArgs A{};
+  for (int l = 0; l < kLayers; ++l) {
+    A.w[l] = Y.w[l];
+    A.b[l] = Y.b[l];
+    A.in[l] = Y.in[l];
+    if (l == lo) {
+      A.d[l] = dz;
+      A.a[l] = z;
+      A.act[l] = ACT_SIGMOID;
+    } else {
+      A.d[l] = dp + (int64_t)l * kH;
+      A.a[l] = nullptr;
+      A.act[l] = ACT_NONE;
+    }
+    // inputs: y0 for layer 0, u_k for the second layer of block k, h_k for
+    // the first, h_5 for the output layer
+    if (l == 0) A.x[l] = y0;
+    else if (l == lo) A.x[l] = h + (int64_t)kBlocks * kH;
+    else if (l % 2 == 1) A.x[l] = h + (int64_t)((l - 1) / 2) * kH;
+    else A.x[l] = f + L.u + (int64_t)((l - 2) / 2) * kH;
   }
-  // input layer: a = h_0, input y0 (its own gradient is not needed)
-  hipLaunchKernelGGL(k_dense_bwd_w, dim3(blocks_for((int64_t)kH * D)), dim3(kThreads), 0, s, (const float*)dh[cur],
-                     (const float*)h, (int)ACT_TANH, y0, D, kH, grad_theta + Y.w[0], grad_theta + Y.b[0]);
+  A.g = grad_theta;
+  A.total = Y.total;
+  hipLaunchKernelGGL(k_dw_all, dim3(blocks_for(Y.total)), dim3(kThreads), 0, s, A);
   return check_launch();
 }
 

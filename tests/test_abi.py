@@ -240,3 +240,7 @@ def test_sqn_validation(nat):
     assert lib.sqngd_sqn_adam(v, v, v, v, 4, None, 0, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1  # t = 0
     assert lib.sqngd_sqn_count(None, None) == -1
     assert lib.sqngd_sqn_project(0, 4, ctypes.c_void_p(16), None) == -1
+    # forward reads theta in 16-byte pieces; a 4-byte-aligned theta is refused
+    ws = ctypes.c_void_p(4096)
+    assert lib.sqngd_sqn_forward(ctypes.byref(good), ctypes.c_void_p(260), v, v, ws, b.value, None) == -4
+    assert lib.sqngd_sqn_forward(ctypes.byref(good), v, v, v, ws, b.value - 4, None) == -3

@@ -93,12 +93,24 @@ def test_adam_sort_project(SN, S):
     rho = rng.random(2800).astype(np.float32)
     r = _t(rho)
     q.sort(r)
+    # rank path (K <= 1024): ties, signed zeros and infinities
+    q2 = SN.SQN(2, 8, 4, 100, 30.0)   # K = 400
+    rho2 = np.round(rng.standard_normal(400) * 4).astype(np.float32)
+    rho2[:3] = [np.inf, -np.inf, -0.0]
+    r2 = _t(rho2)
+    q2.sort(r2)
+    q3 = SN.SQN(2, 8, 4, 256, 30.0)   # K = 1024, the rank path's largest
+    rho3 = rng.random(1024).astype(np.float32)
+    r3 = _t(rho3)
+    q3.sort(r3)
     h = (rng.standard_normal((2, 8)) + 1j * rng.standard_normal((2, 8))).astype(np.complex64)
     ht = _t(h, torch.complex64).reshape(-1)
     q.project(ht)
     torch.cuda.synchronize()
     assert _rel(p.cpu().numpy(), pr) <= 1e-6
     assert np.array_equal(r.cpu().numpy(), np.sort(rho))
+    assert np.array_equal(r2.cpu().numpy(), np.sort(rho2))
+    assert np.array_equal(r3.cpu().numpy(), np.sort(rho3))
     assert _rel(ht.cpu().numpy().reshape(2, 8), R.project(h.astype(np.complex128))) <= 1e-6
 
 

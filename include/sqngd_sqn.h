@@ -76,13 +76,17 @@ int sqngd_sqn_hard(const sqngd_sqn_shape* shape, const float* z, const float* rh
 
 /* Gradients of the loss with respect to theta and rho from the packed waveform
    gradient grad_s (dL/dRe + j dL/dIm, from sqngd_af_backward in mode GIVEN) at
-   the soft waveform s of z: dL/dy1 = 2 pi Im(grad_s conj(s)), through Q_A to z
+   the soft waveform s of z: dL/dy1 = 2 pi Im(g conj(s)), through Q_A to z
    and rho, then through the network (whose activations the last
    sqngd_sqn_forward on ws left there; y0 is the input of that forward).
-   grad_theta and grad_rho are written. */
+   g = grad_s, or grad_s + grad_h when grad_h (the packed filter gradient of
+   the same sqngd_af_backward call) is given: matched filtering, the filters
+   being the soft waveform itself, as in the AF extension of SQN the paper
+   compares against (Sec. IV, no receive-filter optimisation). grad_theta and
+   grad_rho are written. */
 int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const float* y0, const float* z,
-                       const float* rho, const sqngd_c64* s, const sqngd_c64* grad_s, float* grad_theta,
-                       float* grad_rho, void* ws, size_t ws_bytes, void* stream);
+                       const float* rho, const sqngd_c64* s, const sqngd_c64* grad_s, const sqngd_c64* grad_h,
+                       float* grad_theta, float* grad_rho, void* ws, size_t ws_bytes, void* stream);
 
 /* One bias-corrected Adam step on n floats: p -= lr mhat / (sqrt(vhat) + eps),
    with the moments m, v updated in place; used for theta, rho and the filters

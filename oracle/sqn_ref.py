@@ -139,13 +139,19 @@ def new_state(D: int, K: int, M: int, N: int) -> dict:
             "mh": np.zeros((M, N, 2)), "vh": np.zeros((M, N, 2))}
 
 
-def iteration(prob: dict, opt: dict, sqn: dict, theta, rho, h, y0, state: dict, t: int):
+def iteration(prob: dict, opt: dict, sqn: dict, theta, rho, h, y0, state: dict, t: int,
+              matched: bool = False):
     """One outer iteration t of Algorithm 1 with the paper's transmit side:
     step A (n_h times) on the filters with the hard waveform Q_R(f_theta(y0)),
     Adam on (Re h, Im h) with lr_h and the energy projection; step B (n_x
     times) on (theta, rho) with the soft waveform Q_A(f_theta(y0)), Adam with
     lr_z on both, then the thresholds sorted. sqn holds B (= prob["L"]),
-    copies and c. Returns (theta, rho, h, state, stats_A, stats_B)."""
+    copies and c. Returns (theta, rho, h, state, stats_A, stats_B).
+
+    matched=True: the AF extension of SQN that the paper compares against
+    (Sec. IV) -- no step A, and in step B the filters are the soft waveform
+    itself, so the waveform gradient is the sum of the gradients of L(s, h)
+    in its two arguments at h = s (h is returned unchanged)."""
     from oracle import sqngd_ref as R
     M, N = prob["M"], prob["N"]
     B, c = int(prob["L"]), float(sqn["c"])
@@ -157,7 +163,7 @@ def iteration(prob: dict, opt: dict, sqn: dict, theta, rho, h, y0, state: dict, 
     stats_a = stats_b = None
     z, _ = forward(theta, y0)
     _, x = hard_waveform(z, rho, B, M, N)
-    for i in range(int(opt["n_h"])):
+    for i in range(0 if matched else int(opt["n_h"])):
         stats_a, _, gh = R.evaluate(x, h, prob)
         k = t * int(opt["n_h"]) + i + 1
         hr, state["mh"], state["vh"] = R.adam(R._c2r(h), R._c2r(gh), state["mh"], state["vh"], k,
@@ -166,7 +172,11 @@ def iteration(prob: dict, opt: dict, sqn: dict, theta, rho, h, y0, state: dict, 
     for j in range(int(opt["n_x"])):
         z, cache = forward(theta, y0)
         s = soft_waveform(soft_quantise(z, rho, B, c), M, N)
-        stats_b, gs, _ = R.evaluate(s, h, prob)
+        if matched:
+            stats_b, gs, gh = R.evaluate(s, s, prob)
+            gs = gs + gh
+        else:
+            stats_b, gs, _ = R.evaluate(s, h, prob)
         dz, drho = soft_quantise_grad(z, rho, B, c, waveform_chain(gs, s))
         dtheta = backward(cache, dz)
         k = t * int(opt["n_x"]) + j + 1

@@ -310,10 +310,12 @@ __global__ __launch_bounds__(kThreads) void k_soft(const float* __restrict__ z, 
   }
 }
 
-// dy = 2 pi Im(grad_s conj(s)); dz = dy sum_i c (1 - t_i^2) / (2B); one wave per chip.
+// dy = 2 pi Im(g conj(s)) with g = gs (+ gh when given); dz = dy sum_i c
+// (1 - t_i^2) / (2B); one wave per chip.
 __global__ __launch_bounds__(kThreads) void k_chain(const float* __restrict__ z, const float* __restrict__ rho,
                                                      const float2* __restrict__ s, const float2* __restrict__ gs,
-                                                     int D, int K, int B, float c, float* dy_out, float* dz_out) {
+                                                     const float2* __restrict__ gh, int D, int K, int B, float c,
+                                                     float* dy_out, float* dz_out) {
   const int n = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (n >= D) return;
   const float zn = z[n];
@@ -324,7 +326,9 @@ __global__ __launch_bounds__(kThreads) void k_chain(const float* __restrict__ z,
   }
   d = wave_sum(d);
   if (lane == 0) {
-    const float2 g = gs[n], sv = s[n];
+    float2 g = gs[n];
+    if (gh) g = make_float2(g.x + gh[n].x, g.y + gh[n].y);
+    const float2 sv = s[n];
     const float dy = 2.0f * 3.14159265358979f * (g.y * sv.x - g.x * sv.y);
     dy_out[n] = dy;
     dz_out[n] = dy * d * c / (2.0f * (float)B);
@@ -557,8 +561,8 @@ int sqngd_sqn_hard(const sqngd_sqn_shape* shape, const float* z, const float* rh
 }
 
 int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const float* y0, const float* z,
-                       const float* rho, const sqngd_c64* sw, const sqngd_c64* grad_s, float* grad_theta,
-                       float* grad_rho, void* ws, size_t ws_bytes, void* stream) {
+                       const float* rho, const sqngd_c64* sw, const sqngd_c64* grad_s, const sqngd_c64* grad_h,
+                       float* grad_theta, float* grad_rho, void* ws, size_t ws_bytes, void* stream) {
   using namespace sqsqn;
   int rc = validate(shape);
   if (rc != SQNGD_OK) return rc;
@@ -566,7 +570,7 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
       grad_theta == nullptr || grad_rho == nullptr || ws == nullptr)
     return SQNGD_E_INVALID_ARG;
   if (!aligned(theta, 4) || !aligned(y0, 4) || !aligned(z, 4) || !aligned(rho, 4) || !aligned(sw, 8) ||
-      !aligned(grad_s, 8) || !aligned(grad_theta, 4) || !aligned(grad_rho, 4) ||
+      !aligned(grad_s, 8) || !aligned(grad_h, 8) || !aligned(grad_theta, 4) || !aligned(grad_rho, 4) ||
       !aligned(ws, kAlign))
     return SQNGD_E_ALIGN;
   const int D = shape->M * shape->N, K = shape->B * shape->copies, B = shape->B;
@@ -582,7 +586,7 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
   float* part = f + L.part;
   // staircase: dL/dy1, dL/dz and dL/drho
   hipLaunchKernelGGL(k_chain, dim3(blocks_for(64 * (int64_t)D)), dim3(kThreads), 0, s, z, rho, (const float2*)sw,
-                     (const float2*)grad_s, D, K, B, shape->c, dy, dz);
+                     (const float2*)grad_s, (const float2*)grad_h, D, K, B, shape->c, dy, dz);
   hipLaunchKernelGGL(k_drho, dim3(K), dim3(kThreads), 0, s, z, rho, (const float*)dy, D, B, shape->c, grad_rho);
   // output layer (a = z, sigmoid): gradient into h_5 as split sums
   const int lo = 2 * kBlocks + 1;

@@ -40,7 +40,7 @@ def lib():
         L.sqngd_sqn_forward.argtypes = [P, P, P, P, P, sz, P]
         L.sqngd_sqn_soft.argtypes = [P, P, P, P, P]
         L.sqngd_sqn_hard.argtypes = [P, P, P, P, P, P]
-        L.sqngd_sqn_backward.argtypes = [P, P, P, P, P, P, P, P, P, P, sz, P]
+        L.sqngd_sqn_backward.argtypes = [P, P, P, P, P, P, P, P, P, P, P, sz, P]
         L.sqngd_sqn_adam.argtypes = [P, P, P, P, i64, P, i32, i32, f, f, f, f, P]
         L.sqngd_sqn_count.argtypes = [P, P]
         L.sqngd_sqn_sort.argtypes = [P, i32, P]
@@ -100,11 +100,14 @@ class SQN:
                   "sqn_hard")
         return idx, x
 
-    def backward(self, theta, y0, z, rho, s, grad_s):
+    def backward(self, theta, y0, z, rho, s, grad_s, grad_h=None):
+        """grad_h (optional): the filter gradient of the same evaluation when the
+        filters are the soft waveform itself (matched filtering); it adds to grad_s."""
         gt = torch.empty(self.count, dtype=torch.float32, device=self.device)
         gr = torch.empty(self.K, dtype=torch.float32, device=self.device)
         nat.check(lib().sqngd_sqn_backward(ctypes.byref(self.shape), _ptr(theta), _ptr(y0), _ptr(z), _ptr(rho),
-                                           _ptr(s), _ptr(grad_s), _ptr(gt), _ptr(gr), _ptr(self.ws_view),
+                                           _ptr(s), _ptr(grad_s), _ptr(grad_h), _ptr(gt), _ptr(gr),
+                                           _ptr(self.ws_view),
                                            self.ws_view.numel(), _stream()), "sqn_backward")
         return gt, gr
 
@@ -120,11 +123,17 @@ class SQNDesign:
     parameters theta and thresholds rho (step B, Adam with lr_z, thresholds
     sorted after each update) and the filters h (step A, Adam with lr_h and
     the energy projection), from the fixed network input y0. The filters
-    start as the matched filter of the first hard waveform (h0 = x0)."""
+    start as the matched filter of the first hard waveform (h0 = x0).
+
+    matched=True is the AF extension of SQN the paper compares against
+    (Sec. IV): no receive-filter optimisation, the filters are the waveform
+    itself (the soft one in step B, whose loss then depends on it through
+    both roles, the hard one when evaluated); step A is skipped."""
 
     def __init__(self, prob: dict, opt: dict, copies: int, c: float, seed: int = 0, theta=None, rho=None,
-                 y0=None, h=None, device="cuda"):
+                 y0=None, h=None, device="cuda", matched: bool = False):
         self.prob, self.opt = dict(prob), dict(opt)
+        self.matched = bool(matched)
         M, N, B = prob["M"], prob["N"], prob["L"]
         self.sqn = SQN(M, N, B, copies, c, device)
         self.batch = nat.Batch([dict(prob, schedule=prob.get("schedule", nat.SCHED_AUTO))], device=device)
@@ -161,7 +170,7 @@ class SQNDesign:
         self.z = self.sqn.forward(self.theta, self.y0, self.z)
         _, x = self.sqn.hard(self.z, self.rho, want_idx=False)
         hv = torch.view_as_real(self.h).reshape(-1)
-        for i in range(int(o["n_h"])):
+        for i in range(0 if self.matched else int(o["n_h"])):
             _, gh, _ = self.batch.af_backward(None, self.h, nat.WAVE_GIVEN, s_given=x, want_z=False, want_h=True,
                                               stats=self.stats_a)
             adam(hv, torch.view_as_real(gh).reshape(-1), self.mh, self.vh, i + 1, o["lr_h"], b1, b2, eps,
@@ -170,9 +179,9 @@ class SQNDesign:
         for j in range(int(o["n_x"])):
             self.z = self.sqn.forward(self.theta, self.y0, self.z)
             s = self.sqn.soft(self.z, self.rho)
-            _, _, gs = self.batch.af_backward(None, self.h, nat.WAVE_GIVEN, s_given=s, want_z=False, want_h=False,
-                                              want_s=True, stats=self.stats_b)
-            gt, gr = self.sqn.backward(self.theta, self.y0, self.z, self.rho, s, gs)
+            _, gh, gs = self.batch.af_backward(None, s if self.matched else self.h, nat.WAVE_GIVEN, s_given=s,
+                                               want_z=False, want_h=self.matched, want_s=True, stats=self.stats_b)
+            gt, gr = self.sqn.backward(self.theta, self.y0, self.z, self.rho, s, gs, gh)
             adam(self.theta, gt, self.mt, self.vt, j + 1, o["lr_z"], b1, b2, eps, step=self.counter, step_mul=nx)
             adam(self.rho, gr, self.mr, self.vr, j + 1, o["lr_z"], b1, b2, eps, step=self.counter, step_mul=nx)
             self.sqn.sort(self.rho)
@@ -200,7 +209,8 @@ class SQNDesign:
     def hard_stats(self):
         z = self.sqn.forward(self.theta, self.y0)
         _, x = self.sqn.hard(z, self.rho, want_idx=False)
-        return nat.decode_stats(self.batch.af_forward(None, self.h, nat.WAVE_GIVEN, s_given=x).cpu().numpy())[0]
+        h = x if self.matched else self.h
+        return nat.decode_stats(self.batch.af_forward(None, h, nat.WAVE_GIVEN, s_given=x).cpu().numpy())[0]
 
     def hard_indices(self):
         z = self.sqn.forward(self.theta, self.y0)

@@ -268,6 +268,27 @@ def test_fallback_finalize_steps_match_oracle(ref, mods, shape):
     assert abs(sb[0]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"]
 
 
+def test_correlation_only_steps_match_oracle(ref, mods):
+    """Correlation-only design (one Doppler bin at nu = 0, the paper's
+    correlation experiments): two steps of a batch of two M=3 N=200 designs
+    against the oracle."""
+    nat, optim, _ = mods
+    prob = I.make_problem(3, 200, 4, 1, nu_min=0.0, nu_max=0.0, p=16.0)
+    opt = I.make_opt(total_iters=10, T0=1.0, T1=0.5)
+    print("[gpu] correlation-only M=3 N=200 F=1", flush=True)
+    run = optim.SQNGD([prob, prob], opt, seeds=[6, 7])
+    s0 = [run.numpy_state(i) for i in range(2)]
+    run.step(2)
+    torch.cuda.synchronize()
+    for i in range(2):
+        s1 = run.numpy_state(i)
+        z, h, state = s0[i]["z"], s0[i]["h"], s0[i]["state"]
+        for t in range(2):
+            z, h, state, sta, stb = ref.step(prob, opt, z, h, state, t)
+        assert _rel(s1["h"], h) <= 1e-4, (i, _rel(s1["h"], h))
+        assert _rel(s1["z"], z) <= 1e-4, (i, _rel(s1["z"], z))
+
+
 def test_mixed_batch_steps_match_oracle(ref, mods):
     """One batch whose FFT-length groups finalize in different kernels (k_step
     for the short ones, k_final for the length-2048 one), several problems per

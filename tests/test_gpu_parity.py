@@ -67,6 +67,9 @@ SHAPES = {
     "ragged": I.make_problem(3, 100, 5, 7, nu_min=-1.3, nu_max=0.7, p=6.0, tau_lo=-40, tau_hi=30,
                              w_psl=0.8, w_snrl=1.7, temperature=0.6),
     "m1f1": I.make_problem(1, 64, 4, 1, nu_min=0.0, nu_max=0.0, p=8.0),
+    # correlation-only MIMO design (one Doppler bin at nu = 0: the AF is the
+    # aperiodic auto / cross correlation), the paper's correlation experiments
+    "corr_m3f1": I.make_problem(3, 200, 4, 1, nu_min=0.0, nu_max=0.0, p=16.0),
     "phasor": I.make_problem(2, 40, 6, 9, p=16.0, sq_mode=I.PHASOR_MEAN, temperature=0.8),
     "n512": I.make_problem(2, 512, 4, 5, nu_min=-0.5, nu_max=0.5, p=16.0),
     "n1024": I.make_problem(2, 1024, 4, 3, nu_min=-2.5, nu_max=2.5, p=16.0),

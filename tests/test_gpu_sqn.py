@@ -76,6 +76,14 @@ def test_network_and_staircase(SN, S, M, N, B, copies, c):
     dth = S.backward(cache_g, dz)
     assert _rel(gr.cpu().numpy(), drho) <= 1e-4, _rel(gr.cpu().numpy(), drho)
     assert _rel(gt.cpu().numpy(), dth) <= 1e-4, _rel(gt.cpu().numpy(), dth)
+    # with a filter gradient (matched filtering): the two add before the chain
+    gh = np.random.default_rng(25).standard_normal(D) - 0.5j * np.random.default_rng(26).standard_normal(D)
+    gt2, gr2 = q.backward(th, y, z, r, s, _t(gs, torch.complex64), _t(gh, torch.complex64))
+    torch.cuda.synchronize()
+    g2 = gs.astype(np.complex64).astype(np.complex128) + gh.astype(np.complex64).astype(np.complex128)
+    dz2, drho2 = S.soft_quantise_grad(zg, rho.astype(np.float64), B, c, S.waveform_chain(g2, sg))
+    assert _rel(gr2.cpu().numpy(), drho2) <= 1e-4, _rel(gr2.cpu().numpy(), drho2)
+    assert _rel(gt2.cpu().numpy(), S.backward(cache_g, dz2)) <= 1e-4
 
 
 def test_adam_sort_project(SN, S):
@@ -143,6 +151,44 @@ def test_two_iterations_match_oracle(SN, S):
     from paper_2604_25728_amd import native as nat
     stb = nat.decode_stats(d.stats_b.cpu().numpy())[0]
     assert abs(stb["loss"] - sb["loss"]) <= 1e-4 * sb["loss"]
+
+
+def test_matched_filter_mode_matches_oracle(SN, S):
+    """The AF extension of SQN (no filter optimisation, the filters are the
+    waveform): two outer iterations with n_x = 2 against the oracle's matched
+    mode; the filter gradient of the same evaluation adds to the waveform's
+    inside sqngd_sqn_backward. The hard evaluation uses h = x."""
+    prob = I.make_problem(2, 64, 4, 5, p=8.0, snrl_target_db=0.0)
+    opt = I.make_opt(lr_z=1e-3, lr_h=1e-2, n_h=3, n_x=2)
+    copies, c = 3, 4.0
+    print("[gpu] sqn matched-filter iterations", flush=True)
+    d = SN.SQNDesign(prob, opt, copies, c, seed=41, matched=True)
+    theta0 = d.theta.cpu().numpy().astype(np.float64)
+    rho0 = d.rho.cpu().numpy().astype(np.float64)
+    y0 = d.y0.cpu().numpy().astype(np.float64)
+    h0 = d.h.cpu().numpy().reshape(2, 64).astype(np.complex128)
+    for _ in range(2):
+        d.iteration()
+    torch.cuda.synchronize()
+    th, rho, h, st = theta0, rho0, h0, S.new_state(2 * 64, 4 * copies, 2, 64)
+    for t in range(2):
+        th, rho, h, st, sa, sb = S.iteration(prob, opt, {"c": c, "copies": copies}, th, rho, h, y0, st, t,
+                                             matched=True)
+    assert sa is None
+    assert _rel(d.theta.cpu().numpy(), th) <= 1e-4, _rel(d.theta.cpu().numpy(), th)
+    assert _rel(d.rho.cpu().numpy(), rho) <= 1e-4
+    from paper_2604_25728_amd import native as nat
+    stb = nat.decode_stats(d.stats_b.cpu().numpy())[0]
+    assert abs(stb["loss"] - sb["loss"]) <= 1e-4 * sb["loss"]
+    # hard evaluation with matched filtering: SNRL 0 dB (h = x)
+    hs = d.hard_stats()
+    assert abs(hs["snrl_db_max"]) <= 1e-4
+    # the oracle evaluates the GPU's own hard levels (a level at a threshold
+    # could flip between FP32 and FP64 parameters)
+    x = np.exp(2j * np.pi * d.hard_indices() / 4)
+    from oracle import sqngd_ref as R
+    ref_st = R.evaluate(x, x, prob, want_grads=False)[0]
+    assert abs(hs["psl_auto"] - ref_st["psl_auto"]) <= 1e-4 * ref_st["psl_auto"]
 
 
 def test_graph_replay_matches_eager(SN):

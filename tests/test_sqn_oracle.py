@@ -109,3 +109,32 @@ def test_waveform_chain_central_differences(S, ref):
         lp = ref.evaluate(S.soft_waveform(y1 + e, M, N), h, prob, want_grads=False)[0]["loss"]
         lm = ref.evaluate(S.soft_waveform(y1 - e, M, N), h, prob, want_grads=False)[0]["loss"]
         assert abs((lp - lm) / 2e-6 - dy[j]) <= 1e-6 * max(1.0, abs(dy[j]))
+
+
+def test_matched_filter_gradient_central_differences(S, ref):
+    """Matched filtering (the filters are the waveform): the summed packed
+    gradient gs + gh of L(s, h) at h = s against central differences of
+    L(s, s) along the real and imaginary part of single chips, and its chain
+    to y1 against differences of L(s(y1), s(y1))."""
+    M, N, F = 2, 10, 3
+    prob = I.make_problem(M, N, 4, F, p=8.0, snrl_target_db=0.0)
+    y1 = np.random.default_rng(21).random(M * N) * 3
+    s = S.soft_waveform(y1, M, N)
+    _, gs, gh = ref.evaluate(s, s, prob)
+    g = gs + gh
+    loss = lambda w: ref.evaluate(w, w, prob, want_grads=False)[0]["loss"]
+    for m, n in ((0, 0), (0, 6), (1, 3), (1, 9)):
+        for unit, part in ((1.0, "re"), (1j, "im")):
+            e = np.zeros((M, N), np.complex128)
+            e[m, n] = 1e-6 * unit
+            fd = (loss(s + e) - loss(s - e)) / 2e-6
+            want = g[m, n].real if part == "re" else g[m, n].imag
+            assert abs(fd - want) <= 1e-6 * max(1.0, abs(want)), (m, n, part, fd, want)
+    dy = S.waveform_chain(g, s)
+    for j in (2, 11):
+        e = np.zeros(M * N)
+        e[j] = 1e-6
+        fd = (loss(S.soft_waveform(y1 + e, M, N)) - loss(S.soft_waveform(y1 - e, M, N))) / 2e-6
+        assert abs(fd - dy[j]) <= 1e-6 * max(1.0, abs(dy[j]))
+    # one gradient alone misses the filter role
+    assert np.abs(gh).max() > 1e-3 * np.abs(g).max()

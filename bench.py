@@ -353,13 +353,14 @@ def main():
         # N_h = N_x = 10, eps = 0.1 (w_psl 0.1, w_snrl 0.9), SNRL target 0.5 dB,
         # |tau| <= 50 as ROI weights, 129 Doppler bins in [-0.5, 0.5]
         from paper_2604_25728_amd import sqnnative as SN
-        for key, matched in (("paper_sqn_m2n512_b4", False), ("paper_sqnaf_m2n512_b4", True)):
+        for key, matched, R in (("paper_sqn_m2n512_b4", False, 1), ("paper_sqnaf_m2n512_b4", True, 1),
+                                ("paper_sqn_m2n512_b4_x64", False, 64)):
             # SQNAF: the AF extension of SQN (matched filters, no step A), at 0 dB SNRL
             ps = I.make_problem(2, 512, 4, 129, p=16.0, w_psl=0.1, w_snrl=0.9,
                                 **({"snrl_target_db": 0.0} if matched else {}))
             os_ = I.make_opt(lr_z=1e-5, lr_h=5e-2, n_h=10, n_x=10, total_iters=2000)
-            d = SN.SQNDesign(ps, os_, copies=100, c=300.0, seed=0, matched=matched)
-            d.batch.set_roi_weights([I.roi_window_weights(ps, 50)])
+            d = SN.SQNDesign(ps, os_, copies=100, c=300.0, seed=list(range(R)), matched=matched)
+            d.batch.set_roi_weights([I.roi_window_weights(ps, 50)] * R)
             d.capture()              # one outer iteration as a HIP graph
             d.graph.replay()
             torch.cuda.synchronize()
@@ -370,13 +371,14 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             ms_it = e0.elapsed_time(e1) / 5
-            evals = 10 if matched else 20
+            evals = (10 if matched else 20) * R
             extras[key] = {
                 "ms_per_outer_iteration": ms_it, "evals_per_s": evals / (ms_it * 1e-3),
                 "projected_s_for_2000_iterations": 2000 * ms_it * 1e-3,
+                "designs": R,
                 "shape": {"M": 2, "N": 512, "B": 4, "F": 129, "copies": 100, "c": 300.0,
                           "n_h": 0 if matched else 10, "n_x": 10, "matched_filter": matched}}
-            log(f"paper {'SQNAF' if matched else 'SQN'} M=2 N=512 B=4: {ms_it:.2f} ms per outer iteration")
+            log(f"paper {'SQNAF' if matched else 'SQN'} M=2 N=512 B=4 x{R}: {ms_it:.2f} ms per outer iteration")
             del d
         n = 1 << 28
         a = torch.empty(n, dtype=torch.float32, device="cuda")

@@ -21,6 +21,13 @@
  * sqngd_af_forward / sqngd_af_backward with wave_mode SQNGD_WAVE_GIVEN; these
  * calls carry the waveform gradient back to (theta, rho) and update them.
  *
+ * Designs: a shape with designs = R describes R independent designs (random
+ * restarts, each with its own y0, theta, rho): every per-design array is
+ * stacked R times back to back (theta [R][count], y0 / z [R][M N], rho
+ * [R][K], waveforms and gradients [R][M][N], the workspace R slices), the
+ * layout of R equal problems in one sqngd batch. The hidden stack then runs
+ * one workgroup per design, side by side.
+ *
  * Ownership: every array is a DEVICE pointer owned by the caller; the shape is
  * a HOST pointer read during the call. The network's activations live in the
  * caller's workspace (size from sqngd_sqn_workspace_size, 256-byte aligned;
@@ -32,8 +39,8 @@
  *
  * Errors (checked on the host before any HIP call): SQNGD_E_INVALID_ARG for a
  * NULL required pointer, a non-positive size or a non-finite / non-positive
- * c; SQNGD_E_UNSUPPORTED unless M N <= 4096, 2 <= B <= 64 and
- * B * copies <= 4096; SQNGD_E_WORKSPACE for a short workspace; SQNGD_E_ALIGN
+ * c; SQNGD_E_UNSUPPORTED unless M N <= 4096, 2 <= B <= 64,
+ * B * copies <= 4096 and designs <= 65535; SQNGD_E_WORKSPACE for a short workspace; SQNGD_E_ALIGN
  * for a misaligned pointer; SQNGD_E_HIP for a failed launch.
  */
 #ifndef SQNGD_SQN_H
@@ -53,7 +60,8 @@ typedef struct {
   int32_t B;          /* phase levels (the problem's L)                         */
   int32_t copies;     /* r_n of the copying mechanism: K = B * copies thresholds */
   float c;            /* staircase steepness                                    */
-  int32_t reserved[3]; /* must be 0                                              */
+  int32_t designs;    /* R independent designs of this shape, stacked (0 = 1)   */
+  int32_t reserved[2]; /* must be 0                                              */
 } sqngd_sqn_shape;
 
 /* Length of theta for D = M N inputs. */
@@ -100,12 +108,12 @@ int sqngd_sqn_adam(float* p, const float* g, float* m, float* v, int64_t n, cons
 /* *step += 1 on the device (the outer-iteration counter of the driver). */
 int sqngd_sqn_count(int32_t* step, void* stream);
 
-/* The projection of the thresholds onto an ordered set: sorts rho[0..K) in
-   place (ascending), K <= 4096. */
-int sqngd_sqn_sort(float* rho, int32_t K, void* stream);
+/* The projection of the thresholds onto an ordered set: sorts each of the
+   `designs` rows rho[r][0..K) in place (ascending), K <= 4096. */
+int sqngd_sqn_sort(float* rho, int32_t K, int32_t designs, void* stream);
 
 /* Energy projection of the filters (eq. 32): h_m <- h_m sqrt(N / |h_m|^2),
-   rows of N complex values. */
+   rows of N complex values (M R rows for R stacked designs). */
 int sqngd_sqn_project(int32_t M, int32_t N, sqngd_c64* h, void* stream);
 
 #ifdef __cplusplus

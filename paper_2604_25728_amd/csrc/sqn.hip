@@ -28,13 +28,22 @@ constexpr int kMaxK = 4096;
 enum Act : int { ACT_TANH = 0, ACT_SIGMOID = 1, ACT_NONE = 2 };
 
 // a[o] = act(W[o][:] . in + b[o]); out[o] = res[o] + a[o] when res is given.
+// Design r = blockIdx.y: in, W / b and the outputs advance by their strides.
 template <int ACT>
 __global__ __launch_bounds__(kThreads) void k_dense_fwd(const float* __restrict__ in, int K,
                                                          const float* __restrict__ W, const float* __restrict__ b,
                                                          int O, const float* __restrict__ res, float* a_out,
-                                                         float* out) {
+                                                         float* out, int64_t in_str, int64_t w_str,
+                                                         int64_t out_str) {
   const int o = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (o >= O) return;
+  const int64_t r = blockIdx.y;
+  in += r * in_str;
+  W += r * w_str;
+  b += r * w_str;
+  if (res) res += r * out_str;
+  if (a_out) a_out += r * out_str;
+  if (out) out += r * out_str;
   const float* w = W + (int64_t)o * K;
   float acc = 0.f;
   for (int k = lane; k < K; k += 64) acc += w[k] * in[k];
@@ -113,7 +122,12 @@ __device__ __forceinline__ void stack_layer(const StackW& L, const float* in, in
 }
 
 __global__ __launch_bounds__(kStackThreads) void k_res_fwd(const float* __restrict__ th, float* h, float* u,
-                                                            float* v) {
+                                                            float* v, int64_t th_str, int64_t ws_str) {
+  // one workgroup per design
+  th += blockIdx.x * th_str;
+  h += blockIdx.x * ws_str;
+  u += blockIdx.x * ws_str;
+  v += blockIdx.x * ws_str;
   __shared__ __align__(16) float xs[kH];
   __shared__ __align__(16) float us[kH];
   __shared__ float vs[kH];
@@ -169,7 +183,15 @@ __device__ __forceinline__ void stack_transposed(const StackT& T, const float* d
 __global__ __launch_bounds__(kStackThreads) void k_res_bwd(const float* __restrict__ th,
                                                             const float* __restrict__ part, int S,
                                                             const float* __restrict__ h, const float* __restrict__ u,
-                                                            const float* __restrict__ v, float* dp) {
+                                                            const float* __restrict__ v, float* dp, int64_t th_str,
+                                                            int64_t ws_str) {
+  // one workgroup per design
+  th += blockIdx.x * th_str;
+  part += blockIdx.x * ws_str;
+  h += blockIdx.x * ws_str;
+  u += blockIdx.x * ws_str;
+  v += blockIdx.x * ws_str;
+  dp += blockIdx.x * ws_str;
   __shared__ float dh[kH], ds[kH];
   __shared__ float red[8][kH];
   __shared__ float us[kBlocks * kH], vs[kBlocks * kH];
@@ -233,7 +255,14 @@ constexpr int kBwdSplit = 16;
 __global__ __launch_bounds__(64 * kBwdWaves) void k_dense_bwd_part(const float* __restrict__ W,
                                                                     const float* __restrict__ d_act,
                                                                     const float* __restrict__ a, int act, int K,
-                                                                    int O, float* part) {
+                                                                    int O, float* part, int64_t w_str, int64_t d_str,
+                                                                    int64_t a_str, int64_t part_str) {
+  // design r = blockIdx.z
+  const int64_t r = blockIdx.z;
+  W += r * w_str;
+  d_act += r * d_str;
+  a += r * a_str;
+  part += r * part_str;
   __shared__ float sh[kBwdWaves][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int k = blockIdx.x * 64 + lane;
@@ -260,44 +289,50 @@ struct DwArgs {
   const float* d[kLayers];
   const float* a[kLayers];
   const float* x[kLayers];
+  int64_t dstr[kLayers], astr[kLayers], xstr[kLayers];  // per-design strides of d, a, x
   int in[kLayers], act[kLayers];
   float* g;
-  int64_t total;
+  int64_t total;  // parameters per design (the stride of g)
 };
 
 __global__ __launch_bounds__(kThreads) void k_dw_all(DwArgs A) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= A.total) return;
+  const int64_t r = blockIdx.y;  // design
   int64_t w = A.w[0], b = A.b[0];
-  const float *d = A.d[0], *a = A.a[0], *x = A.x[0];
+  const float *d = A.d[0] + r * A.dstr[0], *x = A.x[0] + r * A.xstr[0];
+  const float* a = A.a[0] ? A.a[0] + r * A.astr[0] : nullptr;
   int in = A.in[0], act = A.act[0];
 #pragma unroll
   for (int l = 1; l < kLayers; ++l)
     if (i >= A.w[l]) {
       w = A.w[l];
       b = A.b[l];
-      d = A.d[l];
-      a = A.a[l];
-      x = A.x[l];
+      d = A.d[l] + r * A.dstr[l];
+      a = A.a[l] ? A.a[l] + r * A.astr[l] : nullptr;
+      x = A.x[l] + r * A.xstr[l];
       in = A.in[l];
       act = A.act[l];
     }
+  float* g = A.g + r * A.total;
   if (i < b) {
     const int64_t e = i - w;
     const int o = (int)(e / in), k = (int)(e - (int64_t)o * in);
-    A.g[i] = d[o] * act_grad(act, a ? a[o] : 0.f) * x[k];
+    g[i] = d[o] * act_grad(act, a ? a[o] : 0.f) * x[k];
   } else {
     const int o = (int)(i - b);
-    A.g[i] = d[o] * act_grad(act, a ? a[o] : 0.f);
+    g[i] = d[o] * act_grad(act, a ? a[o] : 0.f);
   }
 }
 
 // One wave per chip, the K thresholds split over its lanes (sums in lane
 // order). y1 = sum_i (tanh(c (z - rho_i)) + 1) / (2B); s = exp(j 2 pi y1).
+// Chips n of all R designs in one range (design n / D, thresholds rho[r][:]).
 __global__ __launch_bounds__(kThreads) void k_soft(const float* __restrict__ z, const float* __restrict__ rho,
-                                                    int D, int K, int B, float c, float2* s) {
+                                                    int D, int R, int K, int B, float c, float2* s) {
   const int n = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (n >= D) return;
+  if (n >= D * R) return;
+  rho += (int64_t)(n / D) * K;
   const float zn = z[n];
   float acc = 0.f;
   for (int i = lane; i < K; i += 64) acc += tanhf(c * (zn - rho[i])) + 1.0f;
@@ -314,10 +349,14 @@ __global__ __launch_bounds__(kThreads) void k_soft(const float* __restrict__ z, 
 // (1 - t_i^2) / (2B); one wave per chip.
 __global__ __launch_bounds__(kThreads) void k_chain(const float* __restrict__ z, const float* __restrict__ rho,
                                                      const float2* __restrict__ s, const float2* __restrict__ gs,
-                                                     const float2* __restrict__ gh, int D, int K, int B, float c,
-                                                     float* dy_out, float* dz_out) {
+                                                     const float2* __restrict__ gh, int D, int R, int K, int B,
+                                                     float c, float* dy_out, float* dz_out, int64_t ws_str) {
   const int n = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (n >= D) return;
+  if (n >= D * R) return;
+  const int r = n / D;
+  rho += (int64_t)r * K;
+  dy_out += r * ws_str - (int64_t)r * D;  // dy_out[n] is design r's dy[n - r D]
+  dz_out += r * ws_str - (int64_t)r * D;
   const float zn = z[n];
   float d = 0.f;
   for (int i = lane; i < K; i += 64) {
@@ -339,9 +378,14 @@ __global__ __launch_bounds__(kThreads) void k_chain(const float* __restrict__ z,
 // threshold, chips in a fixed order.
 __global__ __launch_bounds__(kThreads) void k_drho(const float* __restrict__ z, const float* __restrict__ rho,
                                                     const float* __restrict__ dy, int D, int B, float c,
-                                                    float* drho) {
+                                                    float* drho, int K, int64_t ws_str) {
   __shared__ float sh[kThreads / 64];
   const int i = blockIdx.x;
+  const int64_t dsg = blockIdx.y;  // design
+  z += dsg * D;
+  rho += dsg * K;
+  dy += dsg * ws_str;
+  drho += dsg * K;
   const float r = rho[i];
   float acc = 0.f;
   for (int n = threadIdx.x; n < D; n += kThreads) {
@@ -360,9 +404,10 @@ __global__ __launch_bounds__(kThreads) void k_drho(const float* __restrict__ z, 
 
 // One wave per chip: the count of thresholds at or below z, mod B.
 __global__ __launch_bounds__(kThreads) void k_hard(const float* __restrict__ z, const float* __restrict__ rho,
-                                                    int D, int K, int B, int32_t* idx, float2* x) {
+                                                    int D, int R, int K, int B, int32_t* idx, float2* x) {
   const int n = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (n >= D) return;
+  if (n >= D * R) return;
+  rho += (int64_t)(n / D) * K;
   const float zn = z[n];
   int cnt = 0;
   for (int i = lane; i < K; i += 64) cnt += rho[i] <= zn ? 1 : 0;
@@ -404,6 +449,7 @@ __global__ void k_count(int32_t* step) {
 // rank sort (each value placed by counting smaller keys) measured slower at
 // the paper's K = 400: its K^2 comparisons run on the one CU.
 __global__ __launch_bounds__(1024) void k_sort(float* rho, int K) {
+  rho += (int64_t)blockIdx.x * K;  // one workgroup per design
   __shared__ float v[kMaxK];
   int Kp = 1;
   while (Kp < K) Kp <<= 1;
@@ -481,14 +527,28 @@ struct WsLayout {
 
 inline int blocks_for(int64_t n) { return (int)((n + kThreads - 1) / kThreads); }
 
+constexpr int kMaxDesigns = 65535;  // one grid dimension per design index
+
 int validate(const sqngd_sqn_shape* s) {
   if (s == nullptr) return SQNGD_E_INVALID_ARG;
-  if (s->M < 1 || s->N < 1 || s->B < 2 || s->copies < 1) return SQNGD_E_INVALID_ARG;
+  if (s->M < 1 || s->N < 1 || s->B < 2 || s->copies < 1 || s->designs < 0) return SQNGD_E_INVALID_ARG;
   if (!std::isfinite(s->c) || s->c <= 0.f) return SQNGD_E_INVALID_ARG;
-  if (s->reserved[0] != 0 || s->reserved[1] != 0 || s->reserved[2] != 0) return SQNGD_E_INVALID_ARG;
-  if ((int64_t)s->M * s->N > kMaxD || s->B > 64 || (int64_t)s->B * s->copies > kMaxK) return SQNGD_E_UNSUPPORTED;
+  if (s->reserved[0] != 0 || s->reserved[1] != 0) return SQNGD_E_INVALID_ARG;
+  if ((int64_t)s->M * s->N > kMaxD || s->B > 64 || (int64_t)s->B * s->copies > kMaxK ||
+      s->designs > kMaxDesigns)
+    return SQNGD_E_UNSUPPORTED;
   return SQNGD_OK;
 }
+
+// Strides (floats) of the stacked per-design arrays.
+struct Dims {
+  int D, K, R;
+  int64_t th, ws;  // parameters per design; workspace floats per design (a multiple of 64)
+  explicit Dims(const sqngd_sqn_shape* s)
+      : D(s->M * s->N), K(s->B * s->copies), R(s->designs > 0 ? s->designs : 1),
+        th(Layers(s->M * s->N).total), ws((WsLayout(s->M * s->N).total + 63) & ~(int64_t)63) {}
+  size_t ws_bytes() const { return 4 * (size_t)ws * (size_t)R; }
+};
 
 }  // namespace sqsqn
 
@@ -505,7 +565,7 @@ int sqngd_sqn_workspace_size(const sqngd_sqn_shape* shape, size_t* bytes) {
   int rc = sqsqn::validate(shape);
   if (rc != SQNGD_OK) return rc;
   if (bytes == nullptr) return SQNGD_E_INVALID_ARG;
-  *bytes = align_up(4 * (size_t)sqsqn::WsLayout(shape->M * shape->N).total);
+  *bytes = align_up(sqsqn::Dims(shape).ws_bytes());
   return SQNGD_OK;
 }
 
@@ -517,21 +577,24 @@ int sqngd_sqn_forward(const sqngd_sqn_shape* shape, const float* theta, const fl
   if (theta == nullptr || y0 == nullptr || z == nullptr || ws == nullptr) return SQNGD_E_INVALID_ARG;
   if (!aligned(theta, 16) || !aligned(y0, 4) || !aligned(z, 4) || !aligned(ws, kAlign))
     return SQNGD_E_ALIGN;
-  const int D = shape->M * shape->N;
+  const Dims G(shape);
+  const int D = G.D;
   const WsLayout L(D);
-  if (ws_bytes < 4 * (size_t)L.total) return SQNGD_E_WORKSPACE;
+  if (ws_bytes < G.ws_bytes()) return SQNGD_E_WORKSPACE;
   const Layers Y(D);
   hipStream_t s = (hipStream_t)stream;
   float* f = (float*)ws;
   float* h = f + L.h;
   const int wb = kThreads / 64;
-  hipLaunchKernelGGL(k_dense_fwd<ACT_TANH>, dim3((kH + wb - 1) / wb), dim3(kThreads), 0, s, y0, D, theta + Y.w[0],
-                     theta + Y.b[0], kH, (const float*)nullptr, (float*)nullptr, h);
-  hipLaunchKernelGGL(k_res_fwd, dim3(1), dim3(kStackThreads), 0, s, theta + Y.w[1], h, f + L.u, f + L.v);
+  hipLaunchKernelGGL(k_dense_fwd<ACT_TANH>, dim3((kH + wb - 1) / wb, G.R), dim3(kThreads), 0, s, y0, D,
+                     theta + Y.w[0], theta + Y.b[0], kH, (const float*)nullptr, (float*)nullptr, h, (int64_t)D, G.th,
+                     G.ws);
+  hipLaunchKernelGGL(k_res_fwd, dim3(G.R), dim3(kStackThreads), 0, s, theta + Y.w[1], h, f + L.u, f + L.v, G.th,
+                     G.ws);
   const int lo = 2 * kBlocks + 1;
-  hipLaunchKernelGGL(k_dense_fwd<ACT_SIGMOID>, dim3((D + wb - 1) / wb), dim3(kThreads), 0, s,
+  hipLaunchKernelGGL(k_dense_fwd<ACT_SIGMOID>, dim3((D + wb - 1) / wb, G.R), dim3(kThreads), 0, s,
                      (const float*)(h + (int64_t)kBlocks * kH), kH, theta + Y.w[lo], theta + Y.b[lo], D,
-                     (const float*)nullptr, (float*)nullptr, z);
+                     (const float*)nullptr, (float*)nullptr, z, G.ws, G.th, (int64_t)D);
   return check_launch();
 }
 
@@ -541,9 +604,9 @@ int sqngd_sqn_soft(const sqngd_sqn_shape* shape, const float* z, const float* rh
   if (rc != SQNGD_OK) return rc;
   if (z == nullptr || rho == nullptr || sw == nullptr) return SQNGD_E_INVALID_ARG;
   if (!aligned(z, 4) || !aligned(rho, 4) || !aligned(sw, 8)) return SQNGD_E_ALIGN;
-  const int D = shape->M * shape->N, K = shape->B * shape->copies;
-  hipLaunchKernelGGL(k_soft, dim3(blocks_for(64 * (int64_t)D)), dim3(kThreads), 0, (hipStream_t)stream, z, rho, D, K, shape->B,
-                     shape->c, (float2*)sw);
+  const Dims G(shape);
+  hipLaunchKernelGGL(k_soft, dim3(blocks_for(64 * (int64_t)G.D * G.R)), dim3(kThreads), 0, (hipStream_t)stream, z,
+                     rho, G.D, G.R, G.K, shape->B, shape->c, (float2*)sw);
   return check_launch();
 }
 
@@ -554,9 +617,9 @@ int sqngd_sqn_hard(const sqngd_sqn_shape* shape, const float* z, const float* rh
   if (rc != SQNGD_OK) return rc;
   if (z == nullptr || rho == nullptr || (idx == nullptr && x == nullptr)) return SQNGD_E_INVALID_ARG;
   if (!aligned(z, 4) || !aligned(rho, 4) || !aligned(idx, 4) || !aligned(x, 8)) return SQNGD_E_ALIGN;
-  const int D = shape->M * shape->N, K = shape->B * shape->copies;
-  hipLaunchKernelGGL(k_hard, dim3(blocks_for(64 * (int64_t)D)), dim3(kThreads), 0, (hipStream_t)stream, z, rho, D, K, shape->B,
-                     idx, (float2*)x);
+  const Dims G(shape);
+  hipLaunchKernelGGL(k_hard, dim3(blocks_for(64 * (int64_t)G.D * G.R)), dim3(kThreads), 0, (hipStream_t)stream, z,
+                     rho, G.D, G.R, G.K, shape->B, idx, (float2*)x);
   return check_launch();
 }
 
@@ -573,9 +636,10 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
       !aligned(grad_s, 8) || !aligned(grad_h, 8) || !aligned(grad_theta, 4) || !aligned(grad_rho, 4) ||
       !aligned(ws, kAlign))
     return SQNGD_E_ALIGN;
-  const int D = shape->M * shape->N, K = shape->B * shape->copies, B = shape->B;
+  const Dims G(shape);
+  const int D = G.D, K = G.K, B = shape->B;
   const WsLayout L(D);
-  if (ws_bytes < 4 * (size_t)L.total) return SQNGD_E_WORKSPACE;
+  if (ws_bytes < G.ws_bytes()) return SQNGD_E_WORKSPACE;
   const Layers Y(D);
   hipStream_t s = (hipStream_t)stream;
   float* f = (float*)ws;
@@ -585,16 +649,19 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
   float* dp = f + L.dp;
   float* part = f + L.part;
   // staircase: dL/dy1, dL/dz and dL/drho
-  hipLaunchKernelGGL(k_chain, dim3(blocks_for(64 * (int64_t)D)), dim3(kThreads), 0, s, z, rho, (const float2*)sw,
-                     (const float2*)grad_s, (const float2*)grad_h, D, K, B, shape->c, dy, dz);
-  hipLaunchKernelGGL(k_drho, dim3(K), dim3(kThreads), 0, s, z, rho, (const float*)dy, D, B, shape->c, grad_rho);
+  hipLaunchKernelGGL(k_chain, dim3(blocks_for(64 * (int64_t)D * G.R)), dim3(kThreads), 0, s, z, rho,
+                     (const float2*)sw, (const float2*)grad_s, (const float2*)grad_h, D, G.R, K, B, shape->c, dy, dz,
+                     G.ws);
+  hipLaunchKernelGGL(k_drho, dim3(K, G.R), dim3(kThreads), 0, s, z, rho, (const float*)dy, D, B, shape->c, grad_rho,
+                     K, G.ws);
   // output layer (a = z, sigmoid): gradient into h_5 as split sums
   const int lo = 2 * kBlocks + 1;
-  hipLaunchKernelGGL(k_dense_bwd_part, dim3((kH + 63) / 64, kBwdSplit), dim3(64 * kBwdWaves), 0, s, theta + Y.w[lo],
-                     (const float*)dz, z, (int)ACT_SIGMOID, kH, D, part);
+  hipLaunchKernelGGL(k_dense_bwd_part, dim3((kH + 63) / 64, kBwdSplit, G.R), dim3(64 * kBwdWaves), 0, s,
+                     theta + Y.w[lo], (const float*)dz, z, (int)ACT_SIGMOID, kH, D, part, G.th, G.ws, (int64_t)D,
+                     G.ws);
   // hidden stack and input layer: pre-activation gradients dp[0..10]
-  hipLaunchKernelGGL(k_res_bwd, dim3(1), dim3(kStackThreads), 0, s, theta + Y.w[1], (const float*)part, kBwdSplit,
-                     (const float*)h, (const float*)(f + L.u), (const float*)(f + L.v), dp);
+  hipLaunchKernelGGL(k_res_bwd, dim3(G.R), dim3(kStackThreads), 0, s, theta + Y.w[1], (const float*)part, kBwdSplit,
+                     (const float*)h, (const float*)(f + L.u), (const float*)(f + L.v), dp, G.th, G.ws);
   // weight and bias gradients of all layers
   DwArgs A{};
   for (int l = 0; l < kLayers; ++l) {
@@ -603,15 +670,20 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
     A.in[l] = Y.in[l];
     if (l == lo) {
       A.d[l] = dz;
+      A.dstr[l] = G.ws;
       A.a[l] = z;
+      A.astr[l] = D;
       A.act[l] = ACT_SIGMOID;
     } else {
       A.d[l] = dp + (int64_t)l * kH;
+      A.dstr[l] = G.ws;
       A.a[l] = nullptr;
+      A.astr[l] = 0;
       A.act[l] = ACT_NONE;
     }
     // inputs: y0 for layer 0, u_k for the second layer of block k, h_k for
     // the first, h_5 for the output layer
+    A.xstr[l] = l == 0 ? (int64_t)D : G.ws;
     if (l == 0) A.x[l] = y0;
     else if (l == lo) A.x[l] = h + (int64_t)kBlocks * kH;
     else if (l % 2 == 1) A.x[l] = h + (int64_t)((l - 1) / 2) * kH;
@@ -619,7 +691,7 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
   }
   A.g = grad_theta;
   A.total = Y.total;
-  hipLaunchKernelGGL(k_dw_all, dim3(blocks_for(Y.total)), dim3(kThreads), 0, s, A);
+  hipLaunchKernelGGL(k_dw_all, dim3(blocks_for(Y.total), G.R), dim3(kThreads), 0, s, A);
   return check_launch();
 }
 
@@ -645,12 +717,12 @@ int sqngd_sqn_count(int32_t* step, void* stream) {
   return check_launch();
 }
 
-int sqngd_sqn_sort(float* rho, int32_t K, void* stream) {
+int sqngd_sqn_sort(float* rho, int32_t K, int32_t designs, void* stream) {
   using namespace sqsqn;
-  if (rho == nullptr || K < 1) return SQNGD_E_INVALID_ARG;
-  if (K > kMaxK) return SQNGD_E_UNSUPPORTED;
+  if (rho == nullptr || K < 1 || designs < 1) return SQNGD_E_INVALID_ARG;
+  if (K > kMaxK || designs > kMaxDesigns) return SQNGD_E_UNSUPPORTED;
   if (!aligned(rho, 4)) return SQNGD_E_ALIGN;
-  hipLaunchKernelGGL(k_sort, dim3(1), dim3(1024), 0, (hipStream_t)stream, rho, (int)K);
+  hipLaunchKernelGGL(k_sort, dim3(designs), dim3(1024), 0, (hipStream_t)stream, rho, (int)K);
   return check_launch();
 }
 

@@ -24,7 +24,7 @@ SYMBOLS = ["sqngd_sqn_param_count", "sqngd_sqn_workspace_size", "sqngd_sqn_forwa
 
 class SqnShape(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int32), ("N", ctypes.c_int32), ("B", ctypes.c_int32), ("copies", ctypes.c_int32),
-                ("c", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
+                ("c", ctypes.c_float), ("designs", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 _ready = False
@@ -43,7 +43,7 @@ def lib():
         L.sqngd_sqn_backward.argtypes = [P, P, P, P, P, P, P, P, P, P, P, sz, P]
         L.sqngd_sqn_adam.argtypes = [P, P, P, P, i64, P, i32, i32, f, f, f, f, P]
         L.sqngd_sqn_count.argtypes = [P, P]
-        L.sqngd_sqn_sort.argtypes = [P, i32, P]
+        L.sqngd_sqn_sort.argtypes = [P, i32, i32, P]
         L.sqngd_sqn_project.argtypes = [i32, i32, P, P]
         for n in SYMBOLS:
             getattr(L, n).restype = ctypes.c_int
@@ -66,12 +66,14 @@ def adam(p, g, m, v, t: int, lr: float, beta1: float, beta2: float, eps: float, 
 
 
 class SQN:
-    """One design's transmit network and staircase on the GPU: shape, workspace."""
+    """The transmit network and staircase of R stacked designs of one shape on
+    the GPU (shape, workspace); every per-design array is [R][...]."""
 
-    def __init__(self, M: int, N: int, B: int, copies: int, c: float, device="cuda"):
+    def __init__(self, M: int, N: int, B: int, copies: int, c: float, device="cuda", designs: int = 1):
         self.M, self.N, self.B, self.copies, self.c = M, N, B, copies, float(c)
+        self.R = int(designs)
         self.D, self.K = M * N, B * copies
-        self.shape = SqnShape(M, N, B, copies, float(c), (ctypes.c_int32 * 3)(0, 0, 0))
+        self.shape = SqnShape(M, N, B, copies, float(c), self.R, (ctypes.c_int32 * 2)(0, 0))
         n = ctypes.c_int64()
         nat.check(lib().sqngd_sqn_param_count(self.D, ctypes.byref(n)), "sqn_param_count")
         self.count = n.value
@@ -83,19 +85,19 @@ class SQN:
         self.device = torch.device(device)
 
     def forward(self, theta, y0, z=None):
-        z = torch.empty(self.D, dtype=torch.float32, device=self.device) if z is None else z
+        z = torch.empty(self.R * self.D, dtype=torch.float32, device=self.device) if z is None else z
         nat.check(lib().sqngd_sqn_forward(ctypes.byref(self.shape), _ptr(theta), _ptr(y0), _ptr(z), _ptr(self.ws_view),
                                           self.ws_view.numel(), _stream()), "sqn_forward")
         return z
 
     def soft(self, z, rho, s=None):
-        s = torch.empty(self.D, dtype=torch.complex64, device=self.device) if s is None else s
+        s = torch.empty(self.R * self.D, dtype=torch.complex64, device=self.device) if s is None else s
         nat.check(lib().sqngd_sqn_soft(ctypes.byref(self.shape), _ptr(z), _ptr(rho), _ptr(s), _stream()), "sqn_soft")
         return s
 
     def hard(self, z, rho, want_idx=True, want_x=True):
-        idx = torch.empty(self.D, dtype=torch.int32, device=self.device) if want_idx else None
-        x = torch.empty(self.D, dtype=torch.complex64, device=self.device) if want_x else None
+        idx = torch.empty(self.R * self.D, dtype=torch.int32, device=self.device) if want_idx else None
+        x = torch.empty(self.R * self.D, dtype=torch.complex64, device=self.device) if want_x else None
         nat.check(lib().sqngd_sqn_hard(ctypes.byref(self.shape), _ptr(z), _ptr(rho), _ptr(idx), _ptr(x), _stream()),
                   "sqn_hard")
         return idx, x
@@ -103,8 +105,8 @@ class SQN:
     def backward(self, theta, y0, z, rho, s, grad_s, grad_h=None):
         """grad_h (optional): the filter gradient of the same evaluation when the
         filters are the soft waveform itself (matched filtering); it adds to grad_s."""
-        gt = torch.empty(self.count, dtype=torch.float32, device=self.device)
-        gr = torch.empty(self.K, dtype=torch.float32, device=self.device)
+        gt = torch.empty(self.R * self.count, dtype=torch.float32, device=self.device)
+        gr = torch.empty(self.R * self.K, dtype=torch.float32, device=self.device)
         nat.check(lib().sqngd_sqn_backward(ctypes.byref(self.shape), _ptr(theta), _ptr(y0), _ptr(z), _ptr(rho),
                                            _ptr(s), _ptr(grad_s), _ptr(grad_h), _ptr(gt), _ptr(gr),
                                            _ptr(self.ws_view),
@@ -112,10 +114,10 @@ class SQN:
         return gt, gr
 
     def sort(self, rho):
-        nat.check(lib().sqngd_sqn_sort(_ptr(rho), self.K, _stream()), "sqn_sort")
+        nat.check(lib().sqngd_sqn_sort(_ptr(rho), self.K, self.R, _stream()), "sqn_sort")
 
     def project(self, h):
-        nat.check(lib().sqngd_sqn_project(self.M, self.N, _ptr(h), _stream()), "sqn_project")
+        nat.check(lib().sqngd_sqn_project(self.M * self.R, self.N, _ptr(h), _stream()), "sqn_project")
 
 
 class SQNDesign:
@@ -128,20 +130,27 @@ class SQNDesign:
     matched=True is the AF extension of SQN the paper compares against
     (Sec. IV): no receive-filter optimisation, the filters are the waveform
     itself (the soft one in step B, whose loss then depends on it through
-    both roles, the hard one when evaluated); step A is skipped."""
+    both roles, the hard one when evaluated); step A is skipped.
 
-    def __init__(self, prob: dict, opt: dict, copies: int, c: float, seed: int = 0, theta=None, rho=None,
+    seed may be a list: R independent designs (random restarts) of the same
+    problem run stacked -- one sqngd batch of R problems for the AF and one
+    stacked transmit network -- each from its own seed (theta, y0); explicit
+    theta, rho, y0, h are then the stacked [R][...] arrays."""
+
+    def __init__(self, prob: dict, opt: dict, copies: int, c: float, seed=0, theta=None, rho=None,
                  y0=None, h=None, device="cuda", matched: bool = False):
         self.prob, self.opt = dict(prob), dict(opt)
         self.matched = bool(matched)
+        seeds = [int(x) for x in seed] if isinstance(seed, (list, tuple)) else [int(seed)]
+        self.R = R = len(seeds)
         M, N, B = prob["M"], prob["N"], prob["L"]
-        self.sqn = SQN(M, N, B, copies, c, device)
-        self.batch = nat.Batch([dict(prob, schedule=prob.get("schedule", nat.SCHED_AUTO))], device=device)
+        self.sqn = SQN(M, N, B, copies, c, device, designs=R)
+        self.batch = nat.Batch([dict(prob, schedule=prob.get("schedule", nat.SCHED_AUTO))] * R, device=device)
         dev = self.sqn.device
-        f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32)).to(dev).contiguous()
-        self.theta = f32(I.sqn_init(M * N, seed) if theta is None else theta)
-        self.rho = f32(I.sqn_thresholds(B, copies) if rho is None else rho)
-        self.y0 = f32(I.sqn_input(M, N, seed + 1) if y0 is None else y0)
+        f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32)).to(dev).reshape(-1).contiguous()
+        self.theta = f32(np.concatenate([I.sqn_init(M * N, sd) for sd in seeds]) if theta is None else theta)
+        self.rho = f32(np.tile(I.sqn_thresholds(B, copies), R) if rho is None else rho)
+        self.y0 = f32(np.concatenate([I.sqn_input(M, N, sd + 1) for sd in seeds]) if y0 is None else y0)
         self.z = self.sqn.forward(self.theta, self.y0)
         if h is None:
             _, x = self.sqn.hard(self.z, self.rho, want_idx=False)
@@ -150,9 +159,9 @@ class SQNDesign:
         else:
             self.h = torch.as_tensor(np.asarray(h, np.complex64)).to(dev).reshape(-1).contiguous()
         zeros = lambda n: torch.zeros(n, dtype=torch.float32, device=dev)
-        self.mt, self.vt = zeros(self.sqn.count), zeros(self.sqn.count)
-        self.mr, self.vr = zeros(self.sqn.K), zeros(self.sqn.K)
-        self.mh, self.vh = zeros(2 * M * N), zeros(2 * M * N)
+        self.mt, self.vt = zeros(R * self.sqn.count), zeros(R * self.sqn.count)
+        self.mr, self.vr = zeros(R * self.sqn.K), zeros(R * self.sqn.K)
+        self.mh, self.vh = zeros(2 * R * M * N), zeros(2 * R * M * N)
         self.counter = torch.zeros(1, dtype=torch.int32, device=dev)  # outer iterations done
         self.stats_a = self.batch.new_stats()
         self.stats_b = self.batch.new_stats()
@@ -210,9 +219,11 @@ class SQNDesign:
         z = self.sqn.forward(self.theta, self.y0)
         _, x = self.sqn.hard(z, self.rho, want_idx=False)
         h = x if self.matched else self.h
-        return nat.decode_stats(self.batch.af_forward(None, h, nat.WAVE_GIVEN, s_given=x).cpu().numpy())[0]
+        st = nat.decode_stats(self.batch.af_forward(None, h, nat.WAVE_GIVEN, s_given=x).cpu().numpy())
+        return st[0] if self.R == 1 else st
 
     def hard_indices(self):
         z = self.sqn.forward(self.theta, self.y0)
         idx, _ = self.sqn.hard(z, self.rho, want_x=False)
-        return idx.cpu().numpy().reshape(self.prob["M"], self.prob["N"])
+        shape = (self.prob["M"], self.prob["N"]) if self.R == 1 else (self.R, self.prob["M"], self.prob["N"])
+        return idx.cpu().numpy().reshape(shape)

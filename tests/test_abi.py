@@ -227,14 +227,24 @@ def test_sqn_validation(nat):
     assert lib.sqngd_sqn_param_count(32, ctypes.byref(n)) == 0
     assert n.value == I.sqn_param_count(32)
     b = ctypes.c_size_t()
-    good = SN.SqnShape(2, 16, 4, 3, 30.0, (ctypes.c_int32 * 3)(0, 0, 0))
+    good = SN.SqnShape(2, 16, 4, 3, 30.0, 0, (ctypes.c_int32 * 2)(0, 0))
     assert lib.sqngd_sqn_workspace_size(ctypes.byref(good), ctypes.byref(b)) == 0 and b.value > 0
     for bad, rc in (((2, 16, 1, 3, 30.0), -1), ((2, 16, 4, 3, -1.0), -1), ((2, 16, 65, 3, 30.0), -2),
-                    ((2, 16, 4, 2000, 30.0), -2), ((64, 128, 4, 3, 30.0), -2)):
-        sh = SN.SqnShape(*bad, (ctypes.c_int32 * 3)(0, 0, 0))
+                    ((2, 16, 4, 2000, 30.0), -2), ((64, 128, 4, 3, 30.0), -2), ((2, 16, 4, 3, 30.0, -1), -1),
+                    ((2, 16, 4, 3, 30.0, 65536), -2)):
+        bad = bad if len(bad) == 6 else bad + (0,)
+        sh = SN.SqnShape(*bad, (ctypes.c_int32 * 2)(0, 0))
         assert lib.sqngd_sqn_workspace_size(ctypes.byref(sh), ctypes.byref(b)) == rc, bad
-    assert lib.sqngd_sqn_sort(None, 4, None) == -1
-    assert lib.sqngd_sqn_sort(ctypes.c_void_p(16), 5000, None) == -2
+    assert lib.sqngd_sqn_sort(None, 4, 1, None) == -1
+    assert lib.sqngd_sqn_sort(ctypes.c_void_p(16), 4, 0, None) == -1
+    assert lib.sqngd_sqn_sort(ctypes.c_void_p(16), 5000, 1, None) == -2
+    # R stacked designs: the workspace is R slices of one design's
+    one, three = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.sqngd_sqn_workspace_size(ctypes.byref(SN.SqnShape(2, 16, 4, 3, 30.0, 1, (ctypes.c_int32 * 2)(0, 0))),
+                                        ctypes.byref(one)) == 0
+    assert lib.sqngd_sqn_workspace_size(ctypes.byref(SN.SqnShape(2, 16, 4, 3, 30.0, 3, (ctypes.c_int32 * 2)(0, 0))),
+                                        ctypes.byref(three)) == 0
+    assert one.value == b.value and three.value >= 3 * one.value - 256
     assert lib.sqngd_sqn_adam(None, None, None, None, 4, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
     v = ctypes.c_void_p(256)
     assert lib.sqngd_sqn_adam(v, v, v, v, 4, None, 0, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1  # t = 0

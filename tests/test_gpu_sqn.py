@@ -191,6 +191,45 @@ def test_matched_filter_mode_matches_oracle(SN, S):
     assert abs(hs["psl_auto"] - ref_st["psl_auto"]) <= 1e-4 * ref_st["psl_auto"]
 
 
+@pytest.mark.parametrize("matched", [False, True])
+def test_stacked_designs_match_oracle(SN, S, matched):
+    """Three random restarts of one problem stacked (one AF batch of three
+    problems, the network with one workgroup per design): two outer
+    iterations of each design against the oracle run on its own."""
+    prob = I.make_problem(2, 64, 4, 5, p=8.0, snrl_target_db=0.0 if matched else 0.5)
+    opt = I.make_opt(lr_z=1e-3, lr_h=1e-2, n_h=1, n_x=1)
+    copies, c, seeds = 3, 4.0, [60, 61, 62]
+    print(f"[gpu] sqn stacked designs matched={matched}", flush=True)
+    d = SN.SQNDesign(prob, opt, copies, c, seed=seeds, matched=matched)
+    P, K, D = d.sqn.count, 4 * copies, 2 * 64
+    theta0 = d.theta.cpu().numpy().astype(np.float64).reshape(3, P)
+    rho0 = d.rho.cpu().numpy().astype(np.float64).reshape(3, K)
+    y0 = d.y0.cpu().numpy().astype(np.float64).reshape(3, D)
+    h0 = d.h.cpu().numpy().reshape(3, 2, 64).astype(np.complex128)
+    for _ in range(2):
+        d.iteration()
+    torch.cuda.synchronize()
+    th_g = d.theta.cpu().numpy().reshape(3, P)
+    rho_g = d.rho.cpu().numpy().reshape(3, K)
+    h_g = d.h.cpu().numpy().reshape(3, 2, 64)
+    from paper_2604_25728_amd import native as nat
+    stb = nat.decode_stats(d.stats_b.cpu().numpy())
+    for r in range(3):
+        th, rho, h, st = theta0[r], rho0[r], h0[r], S.new_state(D, K, 2, 64)
+        for t in range(2):
+            th, rho, h, st, sa, sb = S.iteration(prob, opt, {"c": c, "copies": copies}, th, rho, h, y0[r], st, t,
+                                                 matched=matched)
+        assert _rel(th_g[r], th) <= 1e-4, (r, _rel(th_g[r], th))
+        assert _rel(rho_g[r], rho) <= 1e-4, r
+        assert np.all(np.diff(rho_g[r]) >= 0)
+        if not matched:
+            assert _rel(h_g[r], h) <= 1e-4, (r, _rel(h_g[r], h))
+        assert abs(stb[r]["loss"] - sb["loss"]) <= 1e-4 * sb["loss"], r
+    # the designs differ (own seeds)
+    assert not np.allclose(th_g[0], th_g[1])
+    assert d.hard_indices().shape == (3, 2, 64) and len(d.hard_stats()) == 3
+
+
 def test_graph_replay_matches_eager(SN):
     """Replays of a captured outer iteration (step counts from the device
     counter) equal eager iterations, with eager work between the replays."""

@@ -473,11 +473,14 @@ bool stream_capturing(hipStream_t s) {
   return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
 }
 
-// Weighted launches (ROI weights attached) take the general-p instantiation.
+// Weighted launches (ROI weights attached) have p = 16 (squarings) and
+// general-p instantiations.
 template <int P, int WV>
 void launch_split_wv(const PassArgs& a, int phlog, int blocks, hipStream_t s) {
   const dim3 block(64 * WV);
-  if (a.roi_w != nullptr) hipLaunchKernelGGL((k_pass_split<P, -1, WV, true>), dim3(blocks), block, 0, s, a);
+  if (a.roi_w != nullptr && phlog == 3)
+    hipLaunchKernelGGL((k_pass_split<P, 3, WV, true>), dim3(blocks), block, 0, s, a);
+  else if (a.roi_w != nullptr) hipLaunchKernelGGL((k_pass_split<P, -1, WV, true>), dim3(blocks), block, 0, s, a);
   else if (phlog == 3) hipLaunchKernelGGL((k_pass_split<P, 3, WV, false>), dim3(blocks), block, 0, s, a);
   else if (phlog == 2) hipLaunchKernelGGL((k_pass_split<P, 2, WV, false>), dim3(blocks), block, 0, s, a);
   else hipLaunchKernelGGL((k_pass_split<P, -1, WV, false>), dim3(blocks), block, 0, s, a);
@@ -493,7 +496,8 @@ void launch_split(int P, int wv, const PassArgs& a, int phlog, int blocks, hipSt
 template <int P>
 void launch_pass_p(const PassArgs& a, int phlog, int waves, hipStream_t s) {
   const dim3 block(64 * pass_waves(P));
-  if (a.roi_w != nullptr) hipLaunchKernelGGL((k_pass<P, -1, true>), dim3(waves), block, 0, s, a);
+  if (a.roi_w != nullptr && phlog == 3) hipLaunchKernelGGL((k_pass<P, 3, true>), dim3(waves), block, 0, s, a);
+  else if (a.roi_w != nullptr) hipLaunchKernelGGL((k_pass<P, -1, true>), dim3(waves), block, 0, s, a);
   else if (phlog == 3) hipLaunchKernelGGL((k_pass<P, 3, false>), dim3(waves), block, 0, s, a);
   else if (phlog == 2) hipLaunchKernelGGL((k_pass<P, 2, false>), dim3(waves), block, 0, s, a);
   else hipLaunchKernelGGL((k_pass<P, -1, false>), dim3(waves), block, 0, s, a);

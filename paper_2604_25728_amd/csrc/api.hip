@@ -803,6 +803,11 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
   pa.h = (const float2*)h;
   pa.snrl = snrl0;
   launch_prep(*pl, w, pa, s);
+  // The filter-side pass alone yields the statistics too (the same cells in
+  // swapped roles), so a call that wants only grad_h (and stats) skips the
+  // waveform side.
+  const bool wave_side = grad_z != nullptr || grad_s != nullptr || grad_h == nullptr;
+  if (wave_side) {
   // waveform side (orientation 0)
   PassArgs ka{};
   ka.orient = 0;
@@ -822,6 +827,7 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
   fa.grad_z = grad_z;
   fa.z = const_cast<float*>(z);
   launch_final(*pl, w, fa, s);
+  }
   if (grad_h != nullptr) {
     // filter side (orientation 1): self = h, partners = the waveforms of wself
     PrepArgs pb{};
@@ -841,6 +847,7 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
     fb.self_w = (const float2*)h;
     fb.part_w = w.wself;
     fb.snrl = snrl1;
+    fb.stats = wave_side ? nullptr : stats;
     fb.grad_loss = grad_loss;
     fb.grad_w = (float2*)grad_h;
     launch_final(*pl, w, fb, s);

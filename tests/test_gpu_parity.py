@@ -123,6 +123,31 @@ def test_backward_gradients(ref, nat, name, mode):
         assert e_z <= 1e-4, (name, e_z)
 
 
+@pytest.mark.parametrize("name", ["m2n64", "ragged", "n512", "m5n300"])
+def test_filter_gradient_alone(ref, nat, name):
+    """A call that wants only grad_h (and stats) runs the filter side alone:
+    grad_h equals the full call's bit for bit, and the statistics (from the
+    role-swapped cells) match the oracle's and the full call's."""
+    prob = SHAPES[name]
+    z, h, s = _problem_inputs(prob, 7, 2)
+    print(f"[gpu] filter gradient alone {name}", flush=True)
+    b = nat.Batch([prob])
+    zt, ht, st_ = b.pack_z([z]), b.pack_w([h]), b.pack_w([s])
+    full_stats, stats = b.new_stats(), b.new_stats()
+    _, gh_full, _ = b.af_backward(None, ht, nat.WAVE_GIVEN, s_given=st_, want_z=False, want_h=True, want_s=True,
+                                  stats=full_stats)
+    _, gh, _ = b.af_backward(None, ht, nat.WAVE_GIVEN, s_given=st_, want_z=False, want_h=True, want_s=False,
+                             stats=stats)
+    torch.cuda.synchronize()
+    assert torch.equal(gh, gh_full)
+    st_ref, _, gh_ref = ref.evaluate(s.astype(np.complex128), h.astype(np.complex128), prob)
+    got = nat.decode_stats(stats.cpu().numpy())[0]
+    _check_stats(got, st_ref, prob["N"], name)
+    assert _rel(gh.cpu().numpy(), gh_ref) <= 1e-4
+    full = nat.decode_stats(full_stats.cpu().numpy())[0]
+    assert abs(got["loss"] - full["loss"]) <= 1e-5 * full["loss"]
+
+
 def test_grad_loss_scaling_and_hard_mode(ref, nat):
     prob = SHAPES["m2n64"]
     z, h, _ = _problem_inputs(prob, 7, 1)

@@ -226,7 +226,11 @@ int sqngd_af_forward(const sqngd_problem* probs, int32_t nprob, const float* z, 
    grad_loss  nprob floats on the device, or NULL for 1;
    grad_z, grad_h, grad_s  outputs, each may be NULL when not wanted (grad_z
               is only defined for SOFT mode; HARD writes zeros);
-   stats      nprob entries written as by sqngd_af_forward (may be NULL). */
+   stats      nprob entries written as by sqngd_af_forward (may be NULL).
+   The waveform-side pass runs when grad_z or grad_s is wanted, the
+   filter-side (role-swapped) pass when grad_h is; a call that wants grad_h
+   alone runs only the latter and takes stats from its cells (the same cells
+   in swapped roles, equal up to rounding). */
 int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t wave_mode,
                       const sqngd_c64* s_given, const sqngd_c64* h, const float* grad_loss,
                       float* grad_z, sqngd_c64* grad_h, sqngd_c64* grad_s, sqngd_stats* stats,

@@ -105,6 +105,21 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
 int sqngd_sqn_adam(float* p, const float* g, float* m, float* v, int64_t n, const int32_t* step, int32_t step_mul,
                    int32_t step_add, float lr, float beta1, float beta2, float eps, void* stream);
 
+/* sqngd_sqn_adam on rows filter rows of N complex values (g, m, v as 2 N
+   floats per row, Re and Im interleaved) followed by the energy projection of
+   each row (eq. 32), in one launch; the same results as sqngd_sqn_adam then
+   sqngd_sqn_project. */
+int sqngd_sqn_adam_project(int32_t rows, int32_t N, sqngd_c64* h, const sqngd_c64* g, float* m, float* v,
+                           const int32_t* step, int32_t step_mul, int32_t step_add, float lr, float beta1,
+                           float beta2, float eps, void* stream);
+
+/* sqngd_sqn_adam on each of the `designs` rows of K thresholds followed by
+   their ordered projection (the sort of sqngd_sqn_sort), in one launch; the
+   same results as the two calls. */
+int sqngd_sqn_adam_sort(float* rho, const float* g, float* m, float* v, int32_t K, int32_t designs,
+                        const int32_t* step, int32_t step_mul, int32_t step_add, float lr, float beta1, float beta2,
+                        float eps, void* stream);
+
 /* *step += 1 on the device (the outer-iteration counter of the driver). */
 int sqngd_sqn_count(int32_t* step, void* stream);
 

@@ -426,19 +426,60 @@ __global__ __launch_bounds__(kThreads) void k_hard(const float* __restrict__ z, 
 // Step count t = step_mul * (*step) + step_add when step is given (a device
 // counter, so that a captured graph replays with the current count), else
 // step_add.
+struct AdamArgs {
+  float lr, b1, b2, eps;
+  const int32_t* step;
+  int32_t step_mul, step_add;
+};
+struct AdamBias {
+  float bc1, bc2;
+};
+__device__ __forceinline__ AdamBias adam_bias(const AdamArgs& A) {
+  const float t = (float)((A.step ? A.step_mul * *A.step : 0) + A.step_add);
+  return {1.0f - powf(A.b1, t), 1.0f - powf(A.b2, t)};
+}
+// One element: moments updated in place, the new parameter returned.
+__device__ __forceinline__ float adam_elem(float p, float gi, float* m, float* v, const AdamArgs& A,
+                                           const AdamBias& c) {
+  const float mi = A.b1 * *m + (1.0f - A.b1) * gi;
+  const float vi = A.b2 * *v + (1.0f - A.b2) * gi * gi;
+  *m = mi;
+  *v = vi;
+  return p - A.lr * (mi / c.bc1) / (sqrtf(vi / c.bc2) + A.eps);
+}
+
 __global__ __launch_bounds__(kThreads) void k_adam(float* p, const float* __restrict__ g, float* m, float* v,
-                                                    int64_t n, float lr, float b1, float b2, float eps,
-                                                    const int32_t* step, int32_t step_mul, int32_t step_add) {
+                                                    int64_t n, AdamArgs A) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
-  const float t = (float)((step ? step_mul * *step : 0) + step_add);
-  const float bc1 = 1.0f - powf(b1, t), bc2 = 1.0f - powf(b2, t);
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  const AdamBias c = adam_bias(A);
+  p[i] = adam_elem(p[i], g[i], m + i, v + i, A, c);
+}
+
+// Adam on one filter row (2 N floats, Re and Im interleaved) followed by its
+// energy projection: the same arithmetic and sum order as k_adam then
+// k_project, in one launch (one block per row).
+__global__ __launch_bounds__(kThreads) void k_adam_project(float2* h, const float2* __restrict__ g, float* m,
+                                                            float* v, int N, AdamArgs A) {
+  __shared__ float sh[kThreads / 64];
+  const int64_t r0 = (int64_t)blockIdx.x * N;
+  float2* row = h + r0;
+  const AdamBias c = adam_bias(A);
+  float e = 0.f;
+  for (int n = threadIdx.x; n < N; n += kThreads) {
+    const float2 gv = g[r0 + n], pv = row[n];
+    const int64_t i = 2 * (r0 + n);
+    const float2 q = make_float2(adam_elem(pv.x, gv.x, m + i, v + i, A, c), adam_elem(pv.y, gv.y, m + i + 1, v + i + 1, A, c));
+    row[n] = q;
+    e += q.x * q.x + q.y * q.y;
+  }
+  e = wave_sum(e);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = e;
+  __syncthreads();
+  float tot = 0.f;
+  for (int w = 0; w < kThreads / 64; ++w) tot += sh[w];
+  const float sc = sqrtf((float)N / tot);
+  for (int n = threadIdx.x; n < N; n += kThreads) row[n] = make_float2(row[n].x * sc, row[n].y * sc);
 }
 
 __global__ void k_count(int32_t* step) {
@@ -448,6 +489,8 @@ __global__ void k_count(int32_t* step) {
 // Ascending bitonic sort of K <= 4096 values in LDS (padded with +inf). A
 // rank sort (each value placed by counting smaller keys) measured slower at
 // the paper's K = 400: its K^2 comparisons run on the one CU.
+__device__ __forceinline__ void bitonic_lds(float* v, int K, float* rho);
+
 __global__ __launch_bounds__(1024) void k_sort(float* rho, int K) {
   rho += (int64_t)blockIdx.x * K;  // one workgroup per design
   __shared__ float v[kMaxK];
@@ -455,6 +498,32 @@ __global__ __launch_bounds__(1024) void k_sort(float* rho, int K) {
   while (Kp < K) Kp <<= 1;
   for (int i = threadIdx.x; i < Kp; i += 1024) v[i] = i < K ? rho[i] : INFINITY;
   __syncthreads();
+  bitonic_lds(v, K, rho);
+}
+
+// Adam on one design's K thresholds, then the same bitonic sort (one launch).
+__global__ __launch_bounds__(1024) void k_adam_sort(float* rho, const float* __restrict__ g, float* m, float* vv,
+                                                     int K, AdamArgs A) {
+  const int64_t r0 = (int64_t)blockIdx.x * K;
+  rho += r0;
+  g += r0;
+  m += r0;
+  vv += r0;
+  __shared__ float v[kMaxK];
+  int Kp = 1;
+  while (Kp < K) Kp <<= 1;
+  const AdamBias c = adam_bias(A);
+  for (int i = threadIdx.x; i < Kp; i += 1024) v[i] = i < K ? adam_elem(rho[i], g[i], m + i, vv + i, A, c) : INFINITY;
+  __syncthreads();
+  bitonic_lds(v, K, rho);
+}
+
+// Ascending bitonic network over v[0..Kp) (Kp = K rounded up to a power of
+// two, padded with +inf by the caller, then a barrier); the first K values go
+// to rho.
+__device__ __forceinline__ void bitonic_lds(float* v, int K, float* rho) {
+  int Kp = 1;
+  while (Kp < K) Kp <<= 1;
   for (int size = 2; size <= Kp; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = threadIdx.x; i < Kp; i += 1024) {
@@ -695,17 +764,57 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
   return check_launch();
 }
 
-int sqngd_sqn_adam(float* p, const float* g, float* m, float* v, int64_t n, const int32_t* step, int32_t step_mul,
-                   int32_t step_add, float lr, float beta1, float beta2, float eps, void* stream) {
-  using namespace sqsqn;
-  if (p == nullptr || g == nullptr || m == nullptr || v == nullptr || n < 1) return SQNGD_E_INVALID_ARG;
+namespace sqsqn {
+int adam_args(const int32_t* step, int32_t step_mul, int32_t step_add, float lr, float beta1, float beta2, float eps,
+              AdamArgs* A) {
   if (step_mul < 0 || step_add < 0 || (step == nullptr && step_add < 1)) return SQNGD_E_INVALID_ARG;
   if (!std::isfinite(lr) || lr < 0.f || !(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f) ||
       !std::isfinite(eps) || eps <= 0.f)
     return SQNGD_E_INVALID_ARG;
-  if (!aligned(p, 4) || !aligned(g, 4) || !aligned(m, 4) || !aligned(v, 4) || !aligned(step, 4)) return SQNGD_E_ALIGN;
-  hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(kThreads), 0, (hipStream_t)stream, p, g, m, v, n, lr, beta1,
-                     beta2, eps, step, step_mul, step_add);
+  if (!aligned(step, 4)) return SQNGD_E_ALIGN;
+  *A = AdamArgs{lr, beta1, beta2, eps, step, step_mul, step_add};
+  return SQNGD_OK;
+}
+}  // namespace sqsqn
+
+int sqngd_sqn_adam(float* p, const float* g, float* m, float* v, int64_t n, const int32_t* step, int32_t step_mul,
+                   int32_t step_add, float lr, float beta1, float beta2, float eps, void* stream) {
+  using namespace sqsqn;
+  if (p == nullptr || g == nullptr || m == nullptr || v == nullptr || n < 1) return SQNGD_E_INVALID_ARG;
+  AdamArgs A;
+  int rc = adam_args(step, step_mul, step_add, lr, beta1, beta2, eps, &A);
+  if (rc != SQNGD_OK) return rc;
+  if (!aligned(p, 4) || !aligned(g, 4) || !aligned(m, 4) || !aligned(v, 4)) return SQNGD_E_ALIGN;
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(kThreads), 0, (hipStream_t)stream, p, g, m, v, n, A);
+  return check_launch();
+}
+
+int sqngd_sqn_adam_project(int32_t rows, int32_t N, sqngd_c64* h, const sqngd_c64* g, float* m, float* v,
+                           const int32_t* step, int32_t step_mul, int32_t step_add, float lr, float beta1,
+                           float beta2, float eps, void* stream) {
+  using namespace sqsqn;
+  if (h == nullptr || g == nullptr || m == nullptr || v == nullptr || rows < 1 || N < 1) return SQNGD_E_INVALID_ARG;
+  AdamArgs A;
+  int rc = adam_args(step, step_mul, step_add, lr, beta1, beta2, eps, &A);
+  if (rc != SQNGD_OK) return rc;
+  if (!aligned(h, 8) || !aligned(g, 8) || !aligned(m, 4) || !aligned(v, 4)) return SQNGD_E_ALIGN;
+  hipLaunchKernelGGL(k_adam_project, dim3(rows), dim3(kThreads), 0, (hipStream_t)stream, (float2*)h,
+                     (const float2*)g, m, v, (int)N, A);
+  return check_launch();
+}
+
+int sqngd_sqn_adam_sort(float* rho, const float* g, float* m, float* v, int32_t K, int32_t designs,
+                        const int32_t* step, int32_t step_mul, int32_t step_add, float lr, float beta1, float beta2,
+                        float eps, void* stream) {
+  using namespace sqsqn;
+  if (rho == nullptr || g == nullptr || m == nullptr || v == nullptr || K < 1 || designs < 1)
+    return SQNGD_E_INVALID_ARG;
+  if (K > kMaxK || designs > kMaxDesigns) return SQNGD_E_UNSUPPORTED;
+  AdamArgs A;
+  int rc = adam_args(step, step_mul, step_add, lr, beta1, beta2, eps, &A);
+  if (rc != SQNGD_OK) return rc;
+  if (!aligned(rho, 4) || !aligned(g, 4) || !aligned(m, 4) || !aligned(v, 4)) return SQNGD_E_ALIGN;
+  hipLaunchKernelGGL(k_adam_sort, dim3(designs), dim3(1024), 0, (hipStream_t)stream, rho, g, m, v, (int)K, A);
   return check_launch();
 }
 

@@ -18,8 +18,8 @@ from . import inputs as I
 from . import native as nat
 
 SYMBOLS = ["sqngd_sqn_param_count", "sqngd_sqn_workspace_size", "sqngd_sqn_forward", "sqngd_sqn_soft",
-           "sqngd_sqn_hard", "sqngd_sqn_backward", "sqngd_sqn_adam", "sqngd_sqn_count", "sqngd_sqn_sort",
-           "sqngd_sqn_project"]
+           "sqngd_sqn_hard", "sqngd_sqn_backward", "sqngd_sqn_adam", "sqngd_sqn_adam_project", "sqngd_sqn_adam_sort",
+           "sqngd_sqn_count", "sqngd_sqn_sort", "sqngd_sqn_project"]
 
 
 class SqnShape(ctypes.Structure):
@@ -42,6 +42,8 @@ def lib():
         L.sqngd_sqn_hard.argtypes = [P, P, P, P, P, P]
         L.sqngd_sqn_backward.argtypes = [P, P, P, P, P, P, P, P, P, P, P, sz, P]
         L.sqngd_sqn_adam.argtypes = [P, P, P, P, i64, P, i32, i32, f, f, f, f, P]
+        L.sqngd_sqn_adam_project.argtypes = [i32, i32, P, P, P, P, P, i32, i32, f, f, f, f, P]
+        L.sqngd_sqn_adam_sort.argtypes = [P, P, P, P, i32, i32, P, i32, i32, f, f, f, f, P]
         L.sqngd_sqn_count.argtypes = [P, P]
         L.sqngd_sqn_sort.argtypes = [P, i32, i32, P]
         L.sqngd_sqn_project.argtypes = [i32, i32, P, P]
@@ -63,6 +65,22 @@ def adam(p, g, m, v, t: int, lr: float, beta1: float, beta2: float, eps: float, 
     """Adam with step count t, or step_mul * step[0] + t with a device counter."""
     nat.check(lib().sqngd_sqn_adam(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), _ptr(step), int(step_mul), int(t),
                                    float(lr), float(beta1), float(beta2), float(eps), _stream()), "sqn_adam")
+
+
+def adam_project(h, g, m, v, rows: int, N: int, t: int, lr: float, beta1: float, beta2: float, eps: float,
+                 step=None, step_mul: int = 0):
+    """Adam on filter rows then their energy projection (one launch)."""
+    nat.check(lib().sqngd_sqn_adam_project(int(rows), int(N), _ptr(h), _ptr(g), _ptr(m), _ptr(v), _ptr(step),
+                                           int(step_mul), int(t), float(lr), float(beta1), float(beta2), float(eps),
+                                           _stream()), "sqn_adam_project")
+
+
+def adam_sort(rho, g, m, v, K: int, designs: int, t: int, lr: float, beta1: float, beta2: float, eps: float,
+              step=None, step_mul: int = 0):
+    """Adam on each design's thresholds then their sort (one launch)."""
+    nat.check(lib().sqngd_sqn_adam_sort(_ptr(rho), _ptr(g), _ptr(m), _ptr(v), int(K), int(designs), _ptr(step),
+                                        int(step_mul), int(t), float(lr), float(beta1), float(beta2), float(eps),
+                                        _stream()), "sqn_adam_sort")
 
 
 class SQN:
@@ -178,13 +196,11 @@ class SQNDesign:
         nh, nx = int(o["n_h"]), int(o["n_x"])
         self.z = self.sqn.forward(self.theta, self.y0, self.z)
         _, x = self.sqn.hard(self.z, self.rho, want_idx=False)
-        hv = torch.view_as_real(self.h).reshape(-1)
         for i in range(0 if self.matched else int(o["n_h"])):
             _, gh, _ = self.batch.af_backward(None, self.h, nat.WAVE_GIVEN, s_given=x, want_z=False, want_h=True,
                                               stats=self.stats_a)
-            adam(hv, torch.view_as_real(gh).reshape(-1), self.mh, self.vh, i + 1, o["lr_h"], b1, b2, eps,
-                 step=self.counter, step_mul=nh)
-            self.sqn.project(self.h)
+            adam_project(self.h, gh, self.mh, self.vh, self.R * self.prob["M"], self.prob["N"], i + 1, o["lr_h"],
+                         b1, b2, eps, step=self.counter, step_mul=nh)
         for j in range(int(o["n_x"])):
             self.z = self.sqn.forward(self.theta, self.y0, self.z)
             s = self.sqn.soft(self.z, self.rho)
@@ -192,8 +208,8 @@ class SQNDesign:
                                                want_z=False, want_h=self.matched, want_s=True, stats=self.stats_b)
             gt, gr = self.sqn.backward(self.theta, self.y0, self.z, self.rho, s, gs, gh)
             adam(self.theta, gt, self.mt, self.vt, j + 1, o["lr_z"], b1, b2, eps, step=self.counter, step_mul=nx)
-            adam(self.rho, gr, self.mr, self.vr, j + 1, o["lr_z"], b1, b2, eps, step=self.counter, step_mul=nx)
-            self.sqn.sort(self.rho)
+            adam_sort(self.rho, gr, self.mr, self.vr, self.sqn.K, self.R, j + 1, o["lr_z"], b1, b2, eps,
+                      step=self.counter, step_mul=nx)
         nat.check(lib().sqngd_sqn_count(_ptr(self.counter), _stream()), "sqn_count")
 
     def capture(self):

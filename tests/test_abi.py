@@ -254,3 +254,8 @@ def test_sqn_validation(nat):
     ws = ctypes.c_void_p(4096)
     assert lib.sqngd_sqn_forward(ctypes.byref(good), ctypes.c_void_p(260), v, v, ws, b.value, None) == -4
     assert lib.sqngd_sqn_forward(ctypes.byref(good), v, v, v, ws, b.value - 4, None) == -3
+    # fused Adam entry points: the same argument checks as sqngd_sqn_adam
+    assert lib.sqngd_sqn_adam_project(0, 4, v, v, v, v, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert lib.sqngd_sqn_adam_project(2, 4, v, v, v, v, None, 0, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert lib.sqngd_sqn_adam_sort(v, v, v, v, 5000, 1, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -2
+    assert lib.sqngd_sqn_adam_sort(v, v, v, v, 4, 1, None, 0, 1, 1e-3, 1.0, 0.999, 1e-8, None) == -1

@@ -122,6 +122,40 @@ def test_adam_sort_project(SN, S):
     assert _rel(ht.cpu().numpy().reshape(2, 8), R.project(h.astype(np.complex128))) <= 1e-6
 
 
+def test_fused_adam_entry_points_match_separate_calls(SN):
+    """sqngd_sqn_adam_project and sqngd_sqn_adam_sort equal sqngd_sqn_adam
+    followed by sqngd_sqn_project / sqngd_sqn_sort, bit for bit (three
+    stacked designs, step count from a device counter)."""
+    rng = np.random.default_rng(31)
+    print("[gpu] sqn fused adam", flush=True)
+    cnt = torch.tensor([2], dtype=torch.int32, device="cuda")
+    rows, N, K, R = 6, 100, 400, 3
+    h0 = (rng.standard_normal(rows * N) + 1j * rng.standard_normal(rows * N)).astype(np.complex64)
+    g = (rng.standard_normal(rows * N) + 1j * rng.standard_normal(rows * N)).astype(np.complex64)
+    m0 = rng.standard_normal(2 * rows * N).astype(np.float32) * 0.1
+    v0 = rng.random(2 * rows * N).astype(np.float32) * 0.1
+    ha, ma, va = _t(h0, torch.complex64), _t(m0), _t(v0)
+    hb, mb, vb = ha.clone(), ma.clone(), va.clone()
+    gt = _t(g, torch.complex64)
+    SN.adam(torch.view_as_real(ha).reshape(-1), torch.view_as_real(gt).reshape(-1), ma, va, 3, 5e-2, 0.9, 0.999,
+            1e-8, step=cnt, step_mul=10)
+    SN.lib().sqngd_sqn_project(rows, N, SN._ptr(ha), SN._stream())
+    SN.adam_project(hb, gt, mb, vb, rows, N, 3, 5e-2, 0.9, 0.999, 1e-8, step=cnt, step_mul=10)
+    rho0 = np.sort(rng.random((R, K)).astype(np.float32), axis=1).reshape(-1)
+    gr = _t(rng.standard_normal(R * K).astype(np.float32))
+    ra, rb = _t(rho0), _t(rho0)
+    mra, vra = torch.zeros(R * K, device="cuda"), torch.zeros(R * K, device="cuda")
+    mrb, vrb = mra.clone(), vra.clone()
+    SN.adam(ra, gr, mra, vra, 1, 1e-2, 0.9, 0.999, 1e-8, step=cnt, step_mul=10)
+    SN.lib().sqngd_sqn_sort(SN._ptr(ra), K, R, SN._stream())
+    SN.adam_sort(rb, gr, mrb, vrb, K, R, 1, 1e-2, 0.9, 0.999, 1e-8, step=cnt, step_mul=10)
+    torch.cuda.synchronize()
+    assert torch.equal(ha, hb) and torch.equal(ma, mb) and torch.equal(va, vb)
+    assert torch.equal(ra, rb) and torch.equal(mra, mrb) and torch.equal(vra, vrb)
+    assert np.all(np.diff(rb.cpu().numpy().reshape(R, K), axis=1) >= 0)
+    assert not torch.equal(rb, _t(rho0))
+
+
 def test_two_iterations_match_oracle(SN, S):
     """Two outer iterations (n_h = n_x = 1) from the same state: filters,
     network parameters and thresholds against the oracle's. A gentle

@@ -137,13 +137,14 @@ typedef struct {
 
 /* Schedule of the fused AF pass (an implementation choice; every schedule
    computes the same results to rounding). AUTO: the library's rule (the
-   per-(Doppler bin, partner) latency variant for small single batches of
-   FFT length 512 or 1024, its block shape minimising the slowest compute
+   per-(Doppler bin, partner) latency variant for small batches of FFT
+   length 512 or 1024, and for batches of any size whose problems all have
+   M <= 2 at FFT length 1024, its block shape minimising the slowest compute
    unit's wave count). THROUGHPUT: one wavefront per Doppler bin looping over
    the partners. SPLIT8/12/16: the latency variant with that many waves per
-   block (8, 12 or 16 at FFT length 512; 8 at 1024). A hint that does not
-   apply to the batch (another FFT length, M above the waves per block, a
-   batch too large for the latency variant) falls back to AUTO. The first
+   block (8, 12 or 16 at FFT length 512; 8 at 1024), at any batch size. A
+   hint that does not apply to the batch (another FFT length, M above the
+   waves per block) falls back to AUTO. The first
    non-AUTO hint in problem order decides for the whole batch. The
    project's autotuner (paper_2604_25728_amd/tune.py) times the candidates
    on the device and returns the best hint. */

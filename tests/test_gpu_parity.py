@@ -238,6 +238,38 @@ def test_latency_and_throughput_variants_agree(ref, nat):
         assert _rel(x.cpu().numpy(), y[:n].cpu().numpy()) <= 1e-5
 
 
+def test_large_two_waveform_batch_takes_the_latency_variant(ref, nat):
+    """20 M=2 N=512 F=129 designs with ROI weights (more pair waves than the
+    latency variant's cap for other batches): the automatic schedule (the
+    latency variant) against the throughput pass asked for explicitly, all
+    problems, and problem 0 against the oracle."""
+    base = I.make_problem(2, 512, 4, 129, p=16.0, w_psl=0.1, w_snrl=0.9)
+    R = 20
+    print("[gpu] large M=2 batch: latency vs throughput", flush=True)
+    zs = [I.logits(2, 512, 4, 70 + i) for i in range(R)]
+    hs = [I.complex_gaussian(2, 512, 90 + i) for i in range(R)]
+    w = I.roi_window_weights(base, 50)
+    out = []
+    for sched in (0, 1):
+        b = nat.Batch([dict(base, schedule=sched)] * R)
+        b.set_roi_weights([w] * R)
+        st = b.new_stats()
+        gz, gh, _ = b.af_backward(b.pack_z(zs), b.pack_w(hs), nat.WAVE_SOFT, stats=st)
+        torch.cuda.synchronize()
+        out.append((nat.decode_stats(st.cpu().numpy()), gz.cpu().numpy(), gh.cpu().numpy()))
+    (sa, gza, gha), (sb, gzb, ghb) = out
+    for i in range(R):
+        assert abs(sa[i]["loss"] - sb[i]["loss"]) <= 1e-5 * sb[i]["loss"], i
+    assert _rel(gza, gzb) <= 1e-5 and _rel(gha, ghb) <= 1e-5
+    pw = dict(base, roi_w=w.astype(np.float64))
+    sr = ref.soft_waveform(zs[0].astype(np.float64), base["temperature"])
+    st_ref, gs_ref, gh_ref = ref.evaluate(sr, hs[0].astype(np.complex128), pw)
+    _check_stats(sa[0], st_ref, 512, "m2 batch")
+    assert _rel(gha[:2 * 512], gh_ref) <= 1e-4
+    gz_ref = ref.logit_grad(zs[0].astype(np.float64), base["temperature"], gs_ref)
+    assert _rel(gza[:2 * 512 * 4], gz_ref) <= 1e-4
+
+
 @pytest.mark.parametrize("sched", [1, 8, 12, 16])
 def test_every_schedule_gives_the_same_results(ref, nat, sched):
     """Each fused-pass schedule hint (throughput variant, latency variant with

@@ -244,6 +244,44 @@ def cpu_fft_route(prob: dict, budget_s: float) -> dict:
             "sample": f"{n} evaluations (loss, both gradients) by the FFT route in complex128, {el:.1f} s"}
 
 
+def transmit_extras(I, torch, only=None) -> dict:
+    """The paper's transmit side at its Table VI shape (M=2 N=512 B=4 F=129,
+    r_n = 100, c = 300, N_h = N_x = 10, |tau| <= 50): one design, SQNAF, and 64
+    stacked restarts, each one outer iteration per HIP graph replay."""
+    extras = {}
+    from paper_2604_25728_amd import sqnnative as SN
+    for key, matched, R in (("paper_sqn_m2n512_b4", False, 1), ("paper_sqnaf_m2n512_b4", True, 1),
+                            ("paper_sqn_m2n512_b4_x64", False, 64)):
+        if only is not None and key != only:
+            continue
+        # SQNAF: the AF extension of SQN (matched filters, no step A), at 0 dB SNRL
+        ps = I.make_problem(2, 512, 4, 129, p=16.0, w_psl=0.1, w_snrl=0.9,
+                            **({"snrl_target_db": 0.0} if matched else {}))
+        os_ = I.make_opt(lr_z=1e-5, lr_h=5e-2, n_h=10, n_x=10, total_iters=2000)
+        d = SN.SQNDesign(ps, os_, copies=100, c=300.0, seed=list(range(R)), matched=matched)
+        d.batch.set_roi_weights([I.roi_window_weights(ps, 50)] * R)
+        d.capture()              # one outer iteration as a HIP graph
+        d.graph.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            d.graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_it = e0.elapsed_time(e1) / 5
+        evals = (10 if matched else 20) * R
+        extras[key] = {
+            "ms_per_outer_iteration": ms_it, "evals_per_s": evals / (ms_it * 1e-3),
+            "projected_s_for_2000_iterations": 2000 * ms_it * 1e-3,
+            "designs": R,
+            "shape": {"M": 2, "N": 512, "B": 4, "F": 129, "copies": 100, "c": 300.0,
+                      "n_h": 0 if matched else 10, "n_x": 10, "matched_filter": matched}}
+        log(f"paper {'SQNAF' if matched else 'SQN'} M=2 N=512 B=4 x{R}: {ms_it:.2f} ms per outer iteration")
+        del d
+    return extras
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +294,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and copy probes")
     ap.add_argument("--schedule", type=int, default=12,
                     help="fused-pass schedule hint of the --counters run (the timed run tunes it)")
+    ap.add_argument("--transmit", nargs="?", const="all", default=None,
+                    choices=["all", "paper_sqn_m2n512_b4", "paper_sqnaf_m2n512_b4", "paper_sqn_m2n512_b4_x64"],
+                    help="time only the transmit-side workloads (all, or one) and print them as one JSON line")
     ap.add_argument("--counters", action="store_true",
                     help="run the workload for rocprofv3 --pmc (eager iterations + calibration copy) and exit")
     args = ap.parse_args()
@@ -276,6 +317,10 @@ def main():
     prob, opt = cfg["problem"], cfg["opt"]
     log(f"device: {torch.cuda.get_device_name(0)}")
 
+    if args.transmit:
+        only = None if args.transmit == "all" else args.transmit
+        print(json.dumps({"transmit_side": transmit_extras(I, torch, only)}), flush=True)
+        return
     if args.counters:
         run = optim.SQNGD([prob], opt, seeds=[0], schedule=args.schedule)
         counter_run(run, args.steps)
@@ -352,34 +397,7 @@ def main():
         # its Table VI shape and settings: M=2 N=512 B=4, r_n=100, c=300,
         # N_h = N_x = 10, eps = 0.1 (w_psl 0.1, w_snrl 0.9), SNRL target 0.5 dB,
         # |tau| <= 50 as ROI weights, 129 Doppler bins in [-0.5, 0.5]
-        from paper_2604_25728_amd import sqnnative as SN
-        for key, matched, R in (("paper_sqn_m2n512_b4", False, 1), ("paper_sqnaf_m2n512_b4", True, 1),
-                                ("paper_sqn_m2n512_b4_x64", False, 64)):
-            # SQNAF: the AF extension of SQN (matched filters, no step A), at 0 dB SNRL
-            ps = I.make_problem(2, 512, 4, 129, p=16.0, w_psl=0.1, w_snrl=0.9,
-                                **({"snrl_target_db": 0.0} if matched else {}))
-            os_ = I.make_opt(lr_z=1e-5, lr_h=5e-2, n_h=10, n_x=10, total_iters=2000)
-            d = SN.SQNDesign(ps, os_, copies=100, c=300.0, seed=list(range(R)), matched=matched)
-            d.batch.set_roi_weights([I.roi_window_weights(ps, 50)] * R)
-            d.capture()              # one outer iteration as a HIP graph
-            d.graph.replay()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(5):
-                d.graph.replay()
-            e1.record()
-            torch.cuda.synchronize()
-            ms_it = e0.elapsed_time(e1) / 5
-            evals = (10 if matched else 20) * R
-            extras[key] = {
-                "ms_per_outer_iteration": ms_it, "evals_per_s": evals / (ms_it * 1e-3),
-                "projected_s_for_2000_iterations": 2000 * ms_it * 1e-3,
-                "designs": R,
-                "shape": {"M": 2, "N": 512, "B": 4, "F": 129, "copies": 100, "c": 300.0,
-                          "n_h": 0 if matched else 10, "n_x": 10, "matched_filter": matched}}
-            log(f"paper {'SQNAF' if matched else 'SQN'} M=2 N=512 B=4 x{R}: {ms_it:.2f} ms per outer iteration")
-            del d
+        extras.update(transmit_extras(I, torch))
         n = 1 << 28
         a = torch.empty(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

@@ -291,36 +291,52 @@ struct DwArgs {
   const float* x[kLayers];
   int64_t dstr[kLayers], astr[kLayers], xstr[kLayers];  // per-design strides of d, a, x
   int in[kLayers], act[kLayers];
+  int bstart[kLayers + 1];  // first block of each layer (a block never spans two layers)
   float* g;
   int64_t total;  // parameters per design (the stride of g)
 };
 
 __global__ __launch_bounds__(kThreads) void k_dw_all(DwArgs A) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= A.total) return;
-  const int64_t r = blockIdx.y;  // design
-  int64_t w = A.w[0], b = A.b[0];
-  const float *d = A.d[0] + r * A.dstr[0], *x = A.x[0] + r * A.xstr[0];
-  const float* a = A.a[0] ? A.a[0] + r * A.astr[0] : nullptr;
-  int in = A.in[0], act = A.act[0];
+  // the layer is uniform per block (found from blockIdx, scalar work), so
+  // each thread only splits its index into row and column
+  const int bx = blockIdx.x;
+  int l = 0;
 #pragma unroll
-  for (int l = 1; l < kLayers; ++l)
-    if (i >= A.w[l]) {
-      w = A.w[l];
-      b = A.b[l];
-      d = A.d[l] + r * A.dstr[l];
-      a = A.a[l] ? A.a[l] + r * A.astr[l] : nullptr;
-      x = A.x[l] + r * A.xstr[l];
-      in = A.in[l];
-      act = A.act[l];
+  for (int q = 1; q < kLayers; ++q) l = bx >= A.bstart[q] ? q : l;
+  int w = 0, b = 0, in = 1, act = ACT_NONE;
+  const float *d = nullptr, *a = nullptr, *x = nullptr;
+  int64_t dstr = 0, astr = 0, xstr = 0;
+  int b0 = 0;
+#pragma unroll
+  for (int q = 0; q < kLayers; ++q)
+    if (q == l) {
+      w = (int)A.w[q];
+      b = (int)A.b[q];
+      in = A.in[q];
+      act = A.act[q];
+      d = A.d[q];
+      a = A.a[q];
+      x = A.x[q];
+      dstr = A.dstr[q];
+      astr = A.astr[q];
+      xstr = A.xstr[q];
+      b0 = A.bstart[q];
     }
+  // layer l covers theta[w, b + out) with out = (b - w) / in
+  const int end = b + (b - w) / in;
+  const int i = w + (bx - b0) * kThreads + (int)threadIdx.x;
+  if (i >= end) return;
+  const int64_t r = blockIdx.y;  // design
+  d += r * dstr;
+  if (a) a += r * astr;
+  x += r * xstr;
   float* g = A.g + r * A.total;
   if (i < b) {
-    const int64_t e = i - w;
-    const int o = (int)(e / in), k = (int)(e - (int64_t)o * in);
+    const unsigned e = (unsigned)(i - w);
+    const int o = (int)(e / (unsigned)in), k = (int)(e - (unsigned)o * (unsigned)in);
     g[i] = d[o] * act_grad(act, a ? a[o] : 0.f) * x[k];
   } else {
-    const int o = (int)(i - b);
+    const int o = i - b;
     g[i] = d[o] * act_grad(act, a ? a[o] : 0.f);
   }
 }
@@ -760,7 +776,13 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
   }
   A.g = grad_theta;
   A.total = Y.total;
-  hipLaunchKernelGGL(k_dw_all, dim3(blocks_for(Y.total), G.R), dim3(kThreads), 0, s, A);
+  int nb = 0;
+  for (int l = 0; l < kLayers; ++l) {
+    A.bstart[l] = nb;
+    nb += blocks_for((int64_t)Y.in[l] * Y.out[l] + Y.out[l]);
+  }
+  A.bstart[kLayers] = nb;
+  hipLaunchKernelGGL(k_dw_all, dim3(nb, G.R), dim3(kThreads), 0, s, A);
   return check_launch();
 }
 

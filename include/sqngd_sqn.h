@@ -96,6 +96,18 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
                        const float* rho, const sqngd_c64* s, const sqngd_c64* grad_s, const sqngd_c64* grad_h,
                        float* grad_theta, float* grad_rho, void* ws, size_t ws_bytes, void* stream);
 
+/* sqngd_sqn_backward followed by sqngd_sqn_adam on theta, in the same
+   launches: the weight gradients update theta (and its moments m_theta,
+   v_theta, each the length of theta) in place instead of being written out;
+   grad_rho is written as by sqngd_sqn_backward. The same results as the two
+   calls. theta is read by the backward pass before the last launch updates
+   it. */
+int sqngd_sqn_backward_adam(const sqngd_sqn_shape* shape, float* theta, const float* y0, const float* z,
+                            const float* rho, const sqngd_c64* s, const sqngd_c64* grad_s, const sqngd_c64* grad_h,
+                            float* m_theta, float* v_theta, float* grad_rho, const int32_t* step, int32_t step_mul,
+                            int32_t step_add, float lr, float beta1, float beta2, float eps, void* ws,
+                            size_t ws_bytes, void* stream);
+
 /* One bias-corrected Adam step on n floats: p -= lr mhat / (sqrt(vhat) + eps),
    with the moments m, v updated in place; used for theta, rho and the filters
    (as 2 M N floats, Re and Im interleaved). The step count is

@@ -280,10 +280,33 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_dense_bwd_part(const float* 
   }
 }
 
+struct AdamArgs {
+  float lr, b1, b2, eps;
+  const int32_t* step;
+  int32_t step_mul, step_add;
+};
+struct AdamBias {
+  float bc1, bc2;
+};
+__device__ __forceinline__ AdamBias adam_bias(const AdamArgs& A) {
+  const float t = (float)((A.step ? A.step_mul * *A.step : 0) + A.step_add);
+  return {1.0f - powf(A.b1, t), 1.0f - powf(A.b2, t)};
+}
+// One element: moments updated in place, the new parameter returned.
+__device__ __forceinline__ float adam_elem(float p, float gi, float* m, float* v, const AdamArgs& A,
+                                           const AdamBias& c) {
+  const float mi = A.b1 * *m + (1.0f - A.b1) * gi;
+  const float vi = A.b2 * *v + (1.0f - A.b2) * gi * gi;
+  *m = mi;
+  *v = vi;
+  return p - A.lr * (mi / c.bc1) / (sqrtf(vi / c.bc2) + A.eps);
+}
+
 // Weight and bias gradients of every layer in one launch over theta's
 // layout: dW[o][k] = dp[o] x[k], db[o] = dp[o], with dp[o] = d[o] act'(a[o])
 // (act = ACT_NONE when d already is the pre-activation gradient).
 constexpr int kLayers = 2 * kBlocks + 2;
+constexpr int kDwPer = 4;  // parameters per thread of k_dw_all
 struct DwArgs {
   int64_t w[kLayers], b[kLayers];
   const float* d[kLayers];
@@ -294,6 +317,12 @@ struct DwArgs {
   int bstart[kLayers + 1];  // first block of each layer (a block never spans two layers)
   float* g;
   int64_t total;  // parameters per design (the stride of g)
+  // when theta is set, the gradient is not written: Adam updates theta (and
+  // m, v) in place with it, the arithmetic of k_adam
+  float* theta;
+  float* m;
+  float* v;
+  AdamArgs adam;
 };
 
 __global__ __launch_bounds__(kThreads) void k_dw_all(DwArgs A) {
@@ -322,22 +351,33 @@ __global__ __launch_bounds__(kThreads) void k_dw_all(DwArgs A) {
       xstr = A.xstr[q];
       b0 = A.bstart[q];
     }
-  // layer l covers theta[w, b + out) with out = (b - w) / in
+  // layer l covers theta[w, b + out) with out = (b - w) / in; a block takes
+  // kDwPer * kThreads consecutive parameters, a thread every kThreads-th
   const int end = b + (b - w) / in;
-  const int i = w + (bx - b0) * kThreads + (int)threadIdx.x;
-  if (i >= end) return;
   const int64_t r = blockIdx.y;  // design
   d += r * dstr;
   if (a) a += r * astr;
   x += r * xstr;
-  float* g = A.g + r * A.total;
-  if (i < b) {
-    const unsigned e = (unsigned)(i - w);
-    const int o = (int)(e / (unsigned)in), k = (int)(e - (unsigned)o * (unsigned)in);
-    g[i] = d[o] * act_grad(act, a ? a[o] : 0.f) * x[k];
-  } else {
-    const int o = i - b;
-    g[i] = d[o] * act_grad(act, a ? a[o] : 0.f);
+  const AdamBias c = A.theta ? adam_bias(A.adam) : AdamBias{1.f, 1.f};
+  const int i0 = w + (bx - b0) * (kDwPer * kThreads) + (int)threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < kDwPer; ++j) {
+    const int i = i0 + j * kThreads;
+    if (i >= end) break;
+    float gv;
+    if (i < b) {
+      const unsigned e = (unsigned)(i - w);
+      const int o = (int)(e / (unsigned)in), k = (int)(e - (unsigned)o * (unsigned)in);
+      gv = d[o] * act_grad(act, a ? a[o] : 0.f) * x[k];
+    } else {
+      const int o = i - b;
+      gv = d[o] * act_grad(act, a ? a[o] : 0.f);
+    }
+    const int64_t gi = r * A.total + i;
+    if (A.theta)
+      A.theta[gi] = adam_elem(A.theta[gi], gv, A.m + gi, A.v + gi, A.adam, c);
+    else
+      A.g[gi] = gv;
   }
 }
 
@@ -442,34 +482,18 @@ __global__ __launch_bounds__(kThreads) void k_hard(const float* __restrict__ z, 
 // Step count t = step_mul * (*step) + step_add when step is given (a device
 // counter, so that a captured graph replays with the current count), else
 // step_add.
-struct AdamArgs {
-  float lr, b1, b2, eps;
-  const int32_t* step;
-  int32_t step_mul, step_add;
-};
-struct AdamBias {
-  float bc1, bc2;
-};
-__device__ __forceinline__ AdamBias adam_bias(const AdamArgs& A) {
-  const float t = (float)((A.step ? A.step_mul * *A.step : 0) + A.step_add);
-  return {1.0f - powf(A.b1, t), 1.0f - powf(A.b2, t)};
-}
-// One element: moments updated in place, the new parameter returned.
-__device__ __forceinline__ float adam_elem(float p, float gi, float* m, float* v, const AdamArgs& A,
-                                           const AdamBias& c) {
-  const float mi = A.b1 * *m + (1.0f - A.b1) * gi;
-  const float vi = A.b2 * *v + (1.0f - A.b2) * gi * gi;
-  *m = mi;
-  *v = vi;
-  return p - A.lr * (mi / c.bc1) / (sqrtf(vi / c.bc2) + A.eps);
-}
-
+// kDwPer elements per thread (the bias correction, two powf, once per thread)
 __global__ __launch_bounds__(kThreads) void k_adam(float* p, const float* __restrict__ g, float* m, float* v,
                                                     int64_t n, AdamArgs A) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
+  const int64_t i0 = (int64_t)blockIdx.x * (kDwPer * kThreads) + threadIdx.x;
+  if (i0 >= n) return;
   const AdamBias c = adam_bias(A);
-  p[i] = adam_elem(p[i], g[i], m + i, v + i, A, c);
+#pragma unroll
+  for (int j = 0; j < kDwPer; ++j) {
+    const int64_t i = i0 + (int64_t)j * kThreads;
+    if (i >= n) break;
+    p[i] = adam_elem(p[i], g[i], m + i, v + i, A, c);
+  }
 }
 
 // Adam on one filter row (2 N floats, Re and Im interleaved) followed by its
@@ -708,19 +732,24 @@ int sqngd_sqn_hard(const sqngd_sqn_shape* shape, const float* z, const float* rh
   return check_launch();
 }
 
-int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const float* y0, const float* z,
-                       const float* rho, const sqngd_c64* sw, const sqngd_c64* grad_s, const sqngd_c64* grad_h,
-                       float* grad_theta, float* grad_rho, void* ws, size_t ws_bytes, void* stream) {
-  using namespace sqsqn;
-  int rc = validate(shape);
-  if (rc != SQNGD_OK) return rc;
-  if (theta == nullptr || y0 == nullptr || z == nullptr || rho == nullptr || sw == nullptr || grad_s == nullptr ||
-      grad_theta == nullptr || grad_rho == nullptr || ws == nullptr)
+namespace sqsqn {
+static int adam_args(const int32_t* step, int32_t step_mul, int32_t step_add, float lr, float beta1, float beta2, float eps,
+              AdamArgs* A) {
+  if (step_mul < 0 || step_add < 0 || (step == nullptr && step_add < 1)) return SQNGD_E_INVALID_ARG;
+  if (!std::isfinite(lr) || lr < 0.f || !(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f) ||
+      !std::isfinite(eps) || eps <= 0.f)
     return SQNGD_E_INVALID_ARG;
-  if (!aligned(theta, 4) || !aligned(y0, 4) || !aligned(z, 4) || !aligned(rho, 4) || !aligned(sw, 8) ||
-      !aligned(grad_s, 8) || !aligned(grad_h, 8) || !aligned(grad_theta, 4) || !aligned(grad_rho, 4) ||
-      !aligned(ws, kAlign))
-    return SQNGD_E_ALIGN;
+  if (!aligned(step, 4)) return SQNGD_E_ALIGN;
+  *A = AdamArgs{lr, beta1, beta2, eps, step, step_mul, step_add};
+  return SQNGD_OK;
+}
+
+// The backward pass; with adam set, the weight gradients update theta by Adam
+// instead of being written to grad_theta.
+static int backward_impl(const sqngd_sqn_shape* shape, const float* theta, const float* y0, const float* z,
+                  const float* rho, const sqngd_c64* sw, const sqngd_c64* grad_s, const sqngd_c64* grad_h,
+                  float* grad_theta, float* grad_rho, void* ws, size_t ws_bytes, void* stream, float* theta_w,
+                  float* m_theta, float* v_theta, const AdamArgs* adam) {
   const Dims G(shape);
   const int D = G.D, K = G.K, B = shape->B;
   const WsLayout L(D);
@@ -776,28 +805,60 @@ int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const f
   }
   A.g = grad_theta;
   A.total = Y.total;
+  A.theta = adam ? theta_w : nullptr;
+  A.m = m_theta;
+  A.v = v_theta;
+  if (adam) A.adam = *adam;
   int nb = 0;
   for (int l = 0; l < kLayers; ++l) {
     A.bstart[l] = nb;
-    nb += blocks_for((int64_t)Y.in[l] * Y.out[l] + Y.out[l]);
+    nb += (int)(((int64_t)Y.in[l] * Y.out[l] + Y.out[l] + kDwPer * kThreads - 1) / (kDwPer * kThreads));
   }
   A.bstart[kLayers] = nb;
   hipLaunchKernelGGL(k_dw_all, dim3(nb, G.R), dim3(kThreads), 0, s, A);
   return check_launch();
 }
-
-namespace sqsqn {
-int adam_args(const int32_t* step, int32_t step_mul, int32_t step_add, float lr, float beta1, float beta2, float eps,
-              AdamArgs* A) {
-  if (step_mul < 0 || step_add < 0 || (step == nullptr && step_add < 1)) return SQNGD_E_INVALID_ARG;
-  if (!std::isfinite(lr) || lr < 0.f || !(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f) ||
-      !std::isfinite(eps) || eps <= 0.f)
-    return SQNGD_E_INVALID_ARG;
-  if (!aligned(step, 4)) return SQNGD_E_ALIGN;
-  *A = AdamArgs{lr, beta1, beta2, eps, step, step_mul, step_add};
-  return SQNGD_OK;
-}
 }  // namespace sqsqn
+
+int sqngd_sqn_backward(const sqngd_sqn_shape* shape, const float* theta, const float* y0, const float* z,
+                       const float* rho, const sqngd_c64* sw, const sqngd_c64* grad_s, const sqngd_c64* grad_h,
+                       float* grad_theta, float* grad_rho, void* ws, size_t ws_bytes, void* stream) {
+  using namespace sqsqn;
+  int rc = validate(shape);
+  if (rc != SQNGD_OK) return rc;
+  if (theta == nullptr || y0 == nullptr || z == nullptr || rho == nullptr || sw == nullptr || grad_s == nullptr ||
+      grad_theta == nullptr || grad_rho == nullptr || ws == nullptr)
+    return SQNGD_E_INVALID_ARG;
+  if (!aligned(theta, 4) || !aligned(y0, 4) || !aligned(z, 4) || !aligned(rho, 4) || !aligned(sw, 8) ||
+      !aligned(grad_s, 8) || !aligned(grad_h, 8) || !aligned(grad_theta, 4) || !aligned(grad_rho, 4) ||
+      !aligned(ws, kAlign))
+    return SQNGD_E_ALIGN;
+  return backward_impl(shape, theta, y0, z, rho, sw, grad_s, grad_h, grad_theta, grad_rho, ws, ws_bytes, stream,
+                       nullptr, nullptr, nullptr, nullptr);
+}
+
+int sqngd_sqn_backward_adam(const sqngd_sqn_shape* shape, float* theta, const float* y0, const float* z,
+                            const float* rho, const sqngd_c64* sw, const sqngd_c64* grad_s, const sqngd_c64* grad_h,
+                            float* m_theta, float* v_theta, float* grad_rho, const int32_t* step, int32_t step_mul,
+                            int32_t step_add, float lr, float beta1, float beta2, float eps, void* ws,
+                            size_t ws_bytes, void* stream) {
+  using namespace sqsqn;
+  int rc = validate(shape);
+  if (rc != SQNGD_OK) return rc;
+  if (theta == nullptr || y0 == nullptr || z == nullptr || rho == nullptr || sw == nullptr || grad_s == nullptr ||
+      m_theta == nullptr || v_theta == nullptr || grad_rho == nullptr || ws == nullptr)
+    return SQNGD_E_INVALID_ARG;
+  AdamArgs ad;
+  rc = adam_args(step, step_mul, step_add, lr, beta1, beta2, eps, &ad);
+  if (rc != SQNGD_OK) return rc;
+  if (!aligned(theta, 4) || !aligned(y0, 4) || !aligned(z, 4) || !aligned(rho, 4) || !aligned(sw, 8) ||
+      !aligned(grad_s, 8) || !aligned(grad_h, 8) || !aligned(m_theta, 4) || !aligned(v_theta, 4) ||
+      !aligned(grad_rho, 4) || !aligned(ws, kAlign))
+    return SQNGD_E_ALIGN;
+  return backward_impl(shape, theta, y0, z, rho, sw, grad_s, grad_h, nullptr, grad_rho, ws, ws_bytes, stream, theta,
+                       m_theta, v_theta, &ad);
+}
+
 
 int sqngd_sqn_adam(float* p, const float* g, float* m, float* v, int64_t n, const int32_t* step, int32_t step_mul,
                    int32_t step_add, float lr, float beta1, float beta2, float eps, void* stream) {
@@ -807,7 +868,8 @@ int sqngd_sqn_adam(float* p, const float* g, float* m, float* v, int64_t n, cons
   int rc = adam_args(step, step_mul, step_add, lr, beta1, beta2, eps, &A);
   if (rc != SQNGD_OK) return rc;
   if (!aligned(p, 4) || !aligned(g, 4) || !aligned(m, 4) || !aligned(v, 4)) return SQNGD_E_ALIGN;
-  hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(kThreads), 0, (hipStream_t)stream, p, g, m, v, n, A);
+  hipLaunchKernelGGL(k_adam, dim3((int)((n + kDwPer * kThreads - 1) / (kDwPer * kThreads))), dim3(kThreads), 0,
+                     (hipStream_t)stream, p, g, m, v, n, A);
   return check_launch();
 }
 

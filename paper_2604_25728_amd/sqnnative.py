@@ -18,7 +18,7 @@ from . import inputs as I
 from . import native as nat
 
 SYMBOLS = ["sqngd_sqn_param_count", "sqngd_sqn_workspace_size", "sqngd_sqn_forward", "sqngd_sqn_soft",
-           "sqngd_sqn_hard", "sqngd_sqn_backward", "sqngd_sqn_adam", "sqngd_sqn_adam_project", "sqngd_sqn_adam_sort",
+           "sqngd_sqn_hard", "sqngd_sqn_backward", "sqngd_sqn_backward_adam", "sqngd_sqn_adam", "sqngd_sqn_adam_project", "sqngd_sqn_adam_sort",
            "sqngd_sqn_count", "sqngd_sqn_sort", "sqngd_sqn_project"]
 
 
@@ -42,6 +42,7 @@ def lib():
         L.sqngd_sqn_hard.argtypes = [P, P, P, P, P, P]
         L.sqngd_sqn_backward.argtypes = [P, P, P, P, P, P, P, P, P, P, P, sz, P]
         L.sqngd_sqn_adam.argtypes = [P, P, P, P, i64, P, i32, i32, f, f, f, f, P]
+        L.sqngd_sqn_backward_adam.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, i32, i32, f, f, f, f, P, sz, P]
         L.sqngd_sqn_adam_project.argtypes = [i32, i32, P, P, P, P, P, i32, i32, f, f, f, f, P]
         L.sqngd_sqn_adam_sort.argtypes = [P, P, P, P, i32, i32, P, i32, i32, f, f, f, f, P]
         L.sqngd_sqn_count.argtypes = [P, P]
@@ -131,6 +132,18 @@ class SQN:
                                            self.ws_view.numel(), _stream()), "sqn_backward")
         return gt, gr
 
+    def backward_adam(self, theta, y0, z, rho, s, grad_s, m, v, t: int, lr: float, beta1: float, beta2: float,
+                      eps: float, grad_h=None, step=None, step_mul: int = 0):
+        """backward, then Adam on theta in place (the gradient is not stored);
+        returns the threshold gradient."""
+        gr = torch.empty(self.R * self.K, dtype=torch.float32, device=self.device)
+        nat.check(lib().sqngd_sqn_backward_adam(ctypes.byref(self.shape), _ptr(theta), _ptr(y0), _ptr(z), _ptr(rho),
+                                                _ptr(s), _ptr(grad_s), _ptr(grad_h), _ptr(m), _ptr(v), _ptr(gr),
+                                                _ptr(step), int(step_mul), int(t), float(lr), float(beta1),
+                                                float(beta2), float(eps), _ptr(self.ws_view), self.ws_view.numel(),
+                                                _stream()), "sqn_backward_adam")
+        return gr
+
     def sort(self, rho):
         nat.check(lib().sqngd_sqn_sort(_ptr(rho), self.K, self.R, _stream()), "sqn_sort")
 
@@ -206,8 +219,8 @@ class SQNDesign:
             s = self.sqn.soft(self.z, self.rho)
             _, gh, gs = self.batch.af_backward(None, s if self.matched else self.h, nat.WAVE_GIVEN, s_given=s,
                                                want_z=False, want_h=self.matched, want_s=True, stats=self.stats_b)
-            gt, gr = self.sqn.backward(self.theta, self.y0, self.z, self.rho, s, gs, gh)
-            adam(self.theta, gt, self.mt, self.vt, j + 1, o["lr_z"], b1, b2, eps, step=self.counter, step_mul=nx)
+            gr = self.sqn.backward_adam(self.theta, self.y0, self.z, self.rho, s, gs, self.mt, self.vt, j + 1,
+                                        o["lr_z"], b1, b2, eps, grad_h=gh, step=self.counter, step_mul=nx)
             adam_sort(self.rho, gr, self.mr, self.vr, self.sqn.K, self.R, j + 1, o["lr_z"], b1, b2, eps,
                       step=self.counter, step_mul=nx)
         nat.check(lib().sqngd_sqn_count(_ptr(self.counter), _stream()), "sqn_count")

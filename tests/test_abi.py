@@ -259,3 +259,8 @@ def test_sqn_validation(nat):
     assert lib.sqngd_sqn_adam_project(2, 4, v, v, v, v, None, 0, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
     assert lib.sqngd_sqn_adam_sort(v, v, v, v, 5000, 1, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -2
     assert lib.sqngd_sqn_adam_sort(v, v, v, v, 4, 1, None, 0, 1, 1e-3, 1.0, 0.999, 1e-8, None) == -1
+    # backward with Adam on theta: argument checks before any HIP call
+    assert lib.sqngd_sqn_backward_adam(ctypes.byref(good), v, v, v, v, v, v, None, None, v, v, None, 0, 1, 1e-3,
+                                       0.9, 0.999, 1e-8, ws, b.value, None) == -1
+    assert lib.sqngd_sqn_backward_adam(ctypes.byref(good), v, v, v, v, v, v, None, v, v, v, None, 0, 0, 1e-3,
+                                       0.9, 0.999, 1e-8, ws, b.value, None) == -1

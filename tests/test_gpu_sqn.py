@@ -84,6 +84,18 @@ def test_network_and_staircase(SN, S, M, N, B, copies, c):
     dz2, drho2 = S.soft_quantise_grad(zg, rho.astype(np.float64), B, c, S.waveform_chain(g2, sg))
     assert _rel(gr2.cpu().numpy(), drho2) <= 1e-4, _rel(gr2.cpu().numpy(), drho2)
     assert _rel(gt2.cpu().numpy(), S.backward(cache_g, dz2)) <= 1e-4
+    # backward + Adam on theta in one call equals backward then Adam, bit for bit
+    m0 = torch.zeros_like(th)
+    v0 = torch.zeros_like(th)
+    th_a, m_a, v_a = th.clone(), m0.clone(), v0.clone()
+    th_b, m_b, v_b = th.clone(), m0.clone(), v0.clone()
+    q.forward(th, y)  # the activations of theta in the workspace
+    gt3, gr3 = q.backward(th, y, z, r, s, _t(gs, torch.complex64))
+    SN.adam(th_a, gt3, m_a, v_a, 1, 1e-3, 0.9, 0.999, 1e-8)
+    gr4 = q.backward_adam(th_b, y, z, r, s, _t(gs, torch.complex64), m_b, v_b, 1, 1e-3, 0.9, 0.999, 1e-8)
+    torch.cuda.synchronize()
+    assert torch.equal(th_a, th_b) and torch.equal(m_a, m_b) and torch.equal(v_a, v_b)
+    assert torch.equal(gr3, gr4) and not torch.equal(th_b, th)
 
 
 def test_adam_sort_project(SN, S):

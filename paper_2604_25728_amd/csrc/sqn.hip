@@ -560,8 +560,16 @@ __global__ __launch_bounds__(1024) void k_adam_sort(float* rho, const float* __r
 
 // Ascending bitonic network over v[0..Kp) (Kp = K rounded up to a power of
 // two, padded with +inf by the caller, then a barrier); the first K values go
-// to rho.
+// to rho. Every thread of the block calls it (it holds barriers).
 __device__ __forceinline__ void bitonic_lds(float* v, int K, float* rho) {
+  // thresholds after a small Adam step are mostly still in order: one
+  // comparison pass skips the network then (a sorted array is its own sort)
+  int unsorted = 0;
+  for (int i = threadIdx.x; i + 1 < K; i += 1024) unsorted |= v[i] > v[i + 1] ? 1 : 0;
+  if (__syncthreads_or(unsorted) == 0) {
+    for (int i = threadIdx.x; i < K; i += 1024) rho[i] = v[i];
+    return;
+  }
   int Kp = 1;
   while (Kp < K) Kp <<= 1;
   for (int size = 2; size <= Kp; size <<= 1) {

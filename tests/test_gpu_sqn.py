@@ -123,6 +123,10 @@ def test_adam_sort_project(SN, S):
     rho3 = rng.random(1024).astype(np.float32)
     r3 = _t(rho3)
     q3.sort(r3)
+    # already ordered (the comparison pass skips the network), with ties
+    rho4 = np.sort(np.round(rng.random(400) * 50).astype(np.float32))
+    r4 = _t(rho4)
+    q2.sort(r4)
     h = (rng.standard_normal((2, 8)) + 1j * rng.standard_normal((2, 8))).astype(np.complex64)
     ht = _t(h, torch.complex64).reshape(-1)
     q.project(ht)
@@ -131,6 +135,7 @@ def test_adam_sort_project(SN, S):
     assert np.array_equal(r.cpu().numpy(), np.sort(rho))
     assert np.array_equal(r2.cpu().numpy(), np.sort(rho2))
     assert np.array_equal(r3.cpu().numpy(), np.sort(rho3))
+    assert np.array_equal(r4.cpu().numpy(), rho4)
     assert _rel(ht.cpu().numpy().reshape(2, 8), R.project(h.astype(np.complex128))) <= 1e-6
 
 

@@ -132,10 +132,13 @@ __global__ __launch_bounds__(kStackThreads) void k_res_fwd(const float* __restri
   __shared__ __align__(16) float us[kH];
   __shared__ float vs[kH];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the input activation is loaded first, so the barrier waits for it
+  // alone while the first layers' weights are still in flight
+  const float h0 = threadIdx.x < kH ? h[threadIdx.x] : 0.f;
   StackW buf[kAhead];
 #pragma unroll
   for (int l = 0; l + 1 < kAhead; ++l) buf[l] = stack_load(th + l * kHidStride, wv, lane);
-  if (threadIdx.x < kH) xs[threadIdx.x] = h[threadIdx.x];
+  if (threadIdx.x < kH) xs[threadIdx.x] = h0;
   __syncthreads();
 #pragma unroll
   for (int l = 0; l < 2 * kBlocks; ++l) {
@@ -197,22 +200,24 @@ __global__ __launch_bounds__(kStackThreads) void k_res_bwd(const float* __restri
   __shared__ float us[kBlocks * kH], vs[kBlocks * kH];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   // the forward's activations are staged in LDS so the chain below waits on
-  // no global load but the (prefetched) weights
-  for (int i = t; i < kBlocks * kH; i += kStackThreads) {
-    us[i] = u[i];
-    vs[i] = v[i];
-  }
+  // no global load but the (prefetched) weights; all of these loads and the
+  // first layers' weights are in flight together
+  static_assert(kBlocks * kH <= kStackThreads, "one staged value per thread");
+  const float uv = t < kBlocks * kH ? u[t] : 0.f, vv = t < kBlocks * kH ? v[t] : 0.f;
   const float h0 = t < kH ? h[t] : 0.f;
-  if (t < kH) {
-    float acc = 0.f;
-    for (int i = 0; i < S; ++i) acc += part[i * kH + t];
-    dh[t] = acc;
-  }
-  __syncthreads();
+  float acc0 = 0.f;
+  if (t < kH)
+    for (int i = 0; i < S; ++i) acc0 += part[i * kH + t];
   // hidden layers from the last (10) down to 1; buffer i holds layer 10 - i
   StackT buf[kAhead];
 #pragma unroll
   for (int i = 0; i + 1 < kAhead; ++i) buf[i] = stack_tload(th + (2 * kBlocks - 1 - i) * kHidStride, wv, lane);
+  if (t < kBlocks * kH) {
+    us[t] = uv;
+    vs[t] = vv;
+  }
+  if (t < kH) dh[t] = acc0;
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < 2 * kBlocks; ++i) {
     const int l = 2 * kBlocks - i, k = (l - 1) >> 1;

@@ -464,7 +464,12 @@ void launch_prep(const Plan& pl, const Ptrs& w, PrepArgs a, hipStream_t s) {
       default: launch_prep_p<4096>(a, waves, s); break;
     }
     if (g + kMinLogP >= 11)
-      launch_rowspec(pl, w, g, a.mode == PREP_A_HARD ? w.wpart : a.mode == PREP_A_SELF ? w.wself : a.h, s);
+      launch_rowspec(pl, w, g,
+                     a.mode == PREP_A_HARD    ? w.wpart
+                     : a.mode == PREP_A_SELF  ? w.wself
+                     : a.mode == PREP_A_GIVEN ? a.s_given
+                                              : a.h,
+                     s);
   }
 }
 
@@ -809,11 +814,12 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
   pa.s_given = (const float2*)s_given;
   pa.h = (const float2*)h;
   pa.snrl = snrl0;
-  launch_prep(*pl, w, pa, s);
   // The filter-side pass alone yields the statistics too (the same cells in
   // swapped roles), so a call that wants only grad_h (and stats) skips the
-  // waveform side.
+  // waveform side; with the waveforms given it also needs no copy of them.
   const bool wave_side = grad_z != nullptr || grad_s != nullptr || grad_h == nullptr;
+  const bool given_only = !wave_side && wave_mode == SQNGD_WAVE_GIVEN;
+  if (!given_only) launch_prep(*pl, w, pa, s);
   if (wave_side) {
   // waveform side (orientation 0)
   PassArgs ka{};
@@ -838,8 +844,9 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
   if (grad_h != nullptr) {
     // filter side (orientation 1): self = h, partners = the waveforms of wself
     PrepArgs pb{};
-    pb.mode = PREP_A_SELF;
+    pb.mode = given_only ? PREP_A_GIVEN : PREP_A_SELF;
     pb.h = (const float2*)h;
+    pb.s_given = (const float2*)s_given;
     pb.snrl = snrl1;
     launch_prep(*pl, w, pb, s);
     PassArgs kb{};
@@ -852,7 +859,7 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
     fb.mode = FIN_GRAD;
     fb.wave_mode = SQNGD_WAVE_GIVEN;
     fb.self_w = (const float2*)h;
-    fb.part_w = w.wself;
+    fb.part_w = given_only ? (const float2*)s_given : w.wself;
     fb.snrl = snrl1;
     fb.stats = wave_side ? nullptr : stats;
     fb.grad_loss = grad_loss;

@@ -352,6 +352,7 @@ enum PrepMode : int32_t {
   PREP_B_GIVEN = 2,  // self = s_given -> wself; partners = h
   PREP_A_HARD = 3,   // partners = hard(z) -> wpart (self = h)
   PREP_A_SELF = 4,   // partners = wself (self = h)
+  PREP_A_GIVEN = 5,  // partners = s_given (self = h)
 };
 
 struct PrepArgs {
@@ -425,6 +426,10 @@ __global__ __launch_bounds__(64) void k_prep(PrepArgs a) {
           s = a.h[rbase + n];
           break;
         }
+        case PREP_A_GIVEN:
+          v = a.s_given[rbase + n];
+          s = a.h[rbase + n];
+          break;
         default:
           v = a.wself[rbase + n];
           s = a.h[rbase + n];

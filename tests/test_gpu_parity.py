@@ -123,7 +123,7 @@ def test_backward_gradients(ref, nat, name, mode):
         assert e_z <= 1e-4, (name, e_z)
 
 
-@pytest.mark.parametrize("name", ["m2n64", "ragged", "n512", "m5n300"])
+@pytest.mark.parametrize("name", ["m2n64", "ragged", "n512", "m5n300", "n1024"])
 def test_filter_gradient_alone(ref, nat, name):
     """A call that wants only grad_h (and stats) runs the filter side alone:
     grad_h equals the full call's bit for bit, and the statistics (from the

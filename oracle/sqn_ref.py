@@ -15,11 +15,11 @@ sigmoid output (Sec. IV). Read here as
 The soft quantiser is the copied tanh staircase of eq. 24 with K = B r_n
 ordered thresholds rho_i and a_i = 1 / (2B) (each transition adds one level
 1/B, so the hard values are the k / B of the paper's example):
-  y1 = Q_A(z) = sum_i a (tanh(c (z - rho_i)) + 1),  x = exp(j 2 pi y1) (eq. 25-26).
-The hard quantiser (eq. 46) is read as the staircase's limit: the number of
+  y1 = Q_A(z) = sum_i a (tanh(c (z - rho_i)) + 1),  x = exp(j 2 pi y1) (eq. 22-23).
+The hard quantiser Q_R (eq. 43) is read as the staircase's limit: the number of
 thresholds at or below z, divided by B (phase index = that count mod B).
 After each transmit update the thresholds are sorted (the projection onto an
-ordered set the paper asks for after eq. 45).
+ordered set Sec. III-C asks for after each transmit-side update).
 """
 from __future__ import annotations
 
@@ -102,11 +102,18 @@ def soft_quantise(z, rho, B: int, c: float) -> np.ndarray:
     return ((t + 1.0) / (2.0 * B)).sum(axis=1)
 
 
+def sech2(x) -> np.ndarray:
+    """tanh'(x) = 1 - tanh(x)^2 (the derivative the paper states for the
+    staircase), evaluated as 4 e / (1 + e)^2 with e = exp(-2 |x|) so that it
+    keeps its relative precision where tanh(x) rounds to +-1."""
+    e = np.exp(-2.0 * np.abs(np.asarray(x, dtype=np.float64)))
+    return 4.0 * e / ((1.0 + e) * (1.0 + e))
+
+
 def soft_quantise_grad(z, rho, B: int, c: float, dy) -> tuple:
     """(dL/dz, dL/drho) from dL/dy1 through Q_A."""
     z = np.asarray(z, dtype=np.float64)
-    t = np.tanh(c * (z[:, None] - np.asarray(rho, dtype=np.float64)[None, :]))
-    d = c * (1.0 - t * t) / (2.0 * B)                           # dQ_A/dz per threshold
+    d = c * sech2(c * (z[:, None] - np.asarray(rho, dtype=np.float64)[None, :])) / (2.0 * B)  # dQ_A/dz
     dy = np.asarray(dy, dtype=np.float64)
     return (dy[:, None] * d).sum(axis=1), -(dy[:, None] * d).sum(axis=0)
 

@@ -1,0 +1,284 @@
+"""Pins of the oracle's compositions -- one outer iteration of Algorithm 1 and
+the location of the peak sidelobe -- to independent implementations.
+
+The independent side is written here from the paper with other tools:
+torch float64 autograd through the FFT correlation of eq. 36 (no direct
+sums), torch.optim.Adam / torch.optim.SGD for the updates (Sec. III-A,
+Algorithm 1 steps A and B), the energy projection of eq. 32 applied in place,
+and numpy's argmax over a masked cube for the peak location. A wrong order of
+steps A and B, an Adam step count off by one, the temperature of the wrong
+iteration, a projection skipped or the threshold sort misplaced each changes
+the parameters after the first or second outer iteration beyond the 1e-12
+these tests allow.
+"""
+import numpy as np
+import pytest
+
+from paper_2604_25728_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+
+
+def _grid(prob):
+    F = prob["F"]
+    if F == 1:
+        return torch.tensor([prob["nu_min"]], dtype=torch.float64)
+    return torch.tensor(np.linspace(prob["nu_min"], prob["nu_max"], F), dtype=torch.float64)
+
+
+def _loss(s, h, prob):
+    """Eq. 42 with the p-norm of the sidelobes (eq. 7-9, 37) and the SNRL
+    penalty (eq. 38-41), the AF by zero-padded FFT correlation (eq. 33-36)."""
+    M, N = s.shape
+    P = 1
+    while P < 2 * N - 1:
+        P *= 2
+    nu = _grid(prob)
+    n = torch.arange(N, dtype=torch.float64)
+    mod = torch.exp(2j * torch.pi * n[None, :] * nu[:, None] / N)
+    X = torch.fft.fft(s[:, None, :] * mod[None], n=P)
+    H = torch.fft.fft(h, n=P)
+    r = torch.fft.ifft(X[:, None, :, :] * torch.conj(H)[None, :, None, :])
+    tau = torch.arange(-(N - 1), N)
+    A = r[..., (-tau) % P]
+    a = A.abs() / N
+    keep = ((tau >= prob["tau_lo"]) & (tau <= prob["tau_hi"])).expand(M, M, len(nu), 2 * N - 1).clone()
+    for m in range(M):
+        keep[m, m, :, N - 1] = False
+    lp = (a[keep] ** prob["p"]).sum() ** (1.0 / prob["p"])
+    c = (torch.conj(h) * s).sum(dim=1)
+    p_tar = 10.0 ** (-prob["snrl_target_db"] / 20.0)
+    l_snrl = ((c.abs() / N - p_tar) ** 2).mean()
+    return prob["w_psl"] * lp + prob["w_snrl"] * l_snrl
+
+
+def _project_(hr, N):
+    """Eq. 32 in place on the (Re, Im) parameter [M][N][2]."""
+    with torch.no_grad():
+        e = (hr ** 2).sum(dim=(1, 2), keepdim=True)
+        hr.mul_(torch.sqrt(N / e))
+
+
+# ------------------------------------------------ logit parameterisation
+
+
+def _torch_run(prob, opt, z0, h0, iters):
+    M, N, L = prob["M"], prob["N"], prob["L"]
+    z = torch.tensor(z0, dtype=torch.float64, requires_grad=True)
+    hr = torch.tensor(np.stack([h0.real, h0.imag], -1), dtype=torch.float64, requires_grad=True)
+    sgd = opt["flags"] & 1
+    mk = (lambda p, lr: torch.optim.SGD([p], lr=lr)) if sgd else \
+        (lambda p, lr: torch.optim.Adam([p], lr=lr, betas=(opt["beta1"], opt["beta2"]), eps=opt["eps"]))
+    oz, oh = mk(z, opt["lr_z"]), mk(hr, opt["lr_h"])
+    levels = torch.arange(L, dtype=torch.float64)
+    out = []
+    for t in range(iters):
+        for _ in range(opt["n_h"]):
+            with torch.no_grad():
+                x = torch.exp(2j * torch.pi * torch.argmax(z, dim=-1).double() / L)
+            oh.zero_grad()
+            _loss(x, torch.view_as_complex(hr), prob).backward()
+            oh.step()
+            _project_(hr, N)
+        I_ = opt["total_iters"]
+        T = opt["T0"] * (opt["T1"] / opt["T0"]) ** (min(t, I_ - 1) / (I_ - 1)) if I_ > 1 else opt["T0"]
+        for _ in range(opt["n_x"]):
+            pi = torch.softmax(z / T, dim=-1)
+            s = torch.exp(2j * torch.pi * (pi * levels).sum(-1) / L)
+            oz.zero_grad()
+            _loss(s, torch.view_as_complex(hr).detach(), prob).backward()
+            oz.step()
+        out.append((z.detach().numpy().copy(), torch.view_as_complex(hr).detach().numpy().copy()))
+    return out
+
+
+@pytest.mark.parametrize("flags,n_h,n_x", [(0, 2, 3), (0, 1, 1), (0, 0, 2), (0, 2, 0), (1, 1, 2)])
+def test_step_matches_torch(ref, flags, n_h, n_x):
+    """sqngd_ref.step over four outer iterations (t = 0..3) against torch:
+    Adam (or SGD) on (Re h, Im h) with the projection after every step, then
+    Adam (or SGD) on z at the temperature of iteration t; autograd through
+    the FFT route."""
+    prob = I.make_problem(2, 11, 4, 5, nu_min=-0.6, nu_max=0.4, p=6.0, w_psl=1.2, w_snrl=0.7,
+                          snrl_target_db=0.8, tau_lo=-7, tau_hi=9)
+    opt = I.make_opt(lr_z=0.05, lr_h=0.03, n_h=n_h, n_x=n_x, T0=1.0, T1=0.3, total_iters=3, flags=flags)
+    rng = np.random.default_rng(7)
+    z0 = rng.standard_normal((2, 11, 4))
+    h0 = np.exp(2j * np.pi * rng.random((2, 11))) * (1.0 + 0.3 * rng.random((2, 11)))
+    want = _torch_run(prob, opt, z0, h0, 4)
+    z, h, st = z0.copy(), h0.copy(), ref.new_state(2, 11, 4)
+    for t in range(4):
+        z, h, st, sa, sb = ref.step(prob, opt, z, h, st, t)
+        assert (sa is None) == (n_h == 0) and (sb is None) == (n_x == 0)
+        zt, ht = want[t]
+        assert np.abs(z - zt).max() <= 1e-12, (t, np.abs(z - zt).max())
+        assert np.abs(h - ht).max() <= 1e-12, (t, np.abs(h - ht).max())
+        if n_h:
+            np.testing.assert_allclose((np.abs(h) ** 2).sum(1), 11.0, rtol=1e-13)
+    # the updates did something
+    assert np.abs(z - z0).max() > 1e-3 or n_x == 0
+    assert np.abs(h - h0 * np.sqrt(11 / (np.abs(h0) ** 2).sum(1, keepdims=True))).max() > 1e-3 or n_h == 0
+
+
+def test_step_stats_are_the_last_evaluations(ref):
+    """stats_A is the loss of the last step-A evaluation (hard waveform, the
+    filters before that update), stats_B of the last step-B evaluation (soft
+    waveform at T_t, the updated filters)."""
+    prob = I.make_problem(2, 9, 4, 3, p=8.0)
+    opt = I.make_opt(lr_z=0.05, lr_h=0.03, n_h=2, n_x=2, T0=1.0, T1=0.5, total_iters=2)
+    rng = np.random.default_rng(8)
+    z0 = rng.standard_normal((2, 9, 4))
+    h0 = ref.matched_init(z0)
+    st = ref.new_state(2, 9, 4)
+    z1, h1, st1, sa, sb = ref.step(prob, opt, z0, h0, st, 0)
+    # replay with one inner step fewer to get the parameters before the last
+    # update of each step (at t = 0 Adam's step counts do not depend on n_h, n_x)
+    za, ha, _, _, _ = ref.step(prob, dict(opt, n_h=1, n_x=0), z0, h0, st, 0)
+    hx = torch.exp(2j * torch.pi * torch.argmax(torch.tensor(z0), -1).double() / 4)
+    la = _loss(hx, torch.tensor(ha), prob).item()
+    assert abs(sa["loss"] - la) <= 1e-12 * abs(la)
+    zb, hb, _, _, _ = ref.step(prob, dict(opt, n_x=1), z0, h0, st, 0)
+    T = 1.0
+    pi = torch.softmax(torch.tensor(zb) / T, -1)
+    s = torch.exp(2j * torch.pi * (pi * torch.arange(4.0, dtype=torch.float64)).sum(-1) / 4)
+    lb = _loss(s, torch.tensor(hb), prob).item()
+    assert abs(sb["loss"] - lb) <= 1e-12 * abs(lb)
+
+
+# ------------------------------------------ the paper's transmit network
+
+
+def _torch_sqn_run(prob, opt, sqn, theta0, rho0, h0, y0, iters, matched):
+    M, N, B = prob["M"], prob["N"], prob["L"]
+    D = M * N
+    c = sqn["c"]
+    K = B * sqn["copies"]
+    th = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+    rho = torch.tensor(rho0, dtype=torch.float64, requires_grad=True)
+    hr = torch.tensor(np.stack([h0.real, h0.imag], -1), dtype=torch.float64, requires_grad=True)
+    betas = (opt["beta1"], opt["beta2"])
+    ox = torch.optim.Adam([th, rho], lr=opt["lr_z"], betas=betas, eps=opt["eps"])
+    oh = torch.optim.Adam([hr], lr=opt["lr_h"], betas=betas, eps=opt["eps"])
+    x0 = torch.tensor(y0, dtype=torch.float64)
+
+    def net():
+        off, Ws = 0, []
+        for i, o in I.sqn_layers(D):
+            W = th[off: off + o * i].reshape(o, i)
+            off += o * i
+            Ws.append((W, th[off: off + o]))
+            off += o
+        a = torch.tanh(Ws[0][0] @ x0 + Ws[0][1])
+        for k in range(I.SQN_BLOCKS):
+            (W1, b1), (W2, b2) = Ws[1 + 2 * k], Ws[2 + 2 * k]
+            a = a + torch.tanh(W2 @ torch.tanh(W1 @ a + b1) + b2)
+        return torch.sigmoid(Ws[-1][0] @ a + Ws[-1][1])
+
+    out = []
+    for _ in range(iters):
+        with torch.no_grad():
+            z = net()
+            k = (rho[None, :] <= z[:, None]).sum(1) % B
+            x = torch.exp(2j * torch.pi * k.double() / B).reshape(M, N)
+        for _ in range(0 if matched else opt["n_h"]):
+            oh.zero_grad()
+            _loss(x, torch.view_as_complex(hr), prob).backward()
+            oh.step()
+            _project_(hr, N)
+        for _ in range(opt["n_x"]):
+            z = net()
+            # tanh(u) + 1 = 2 sigmoid(2u), taken on the side where the
+            # sigmoid is small so that its derivative keeps its digits
+            u = c * (z[:, None] - rho[None, :])
+            step = torch.where(u >= 0, 2.0 - 2.0 * torch.sigmoid(-2.0 * u), 2.0 * torch.sigmoid(2.0 * u))
+            y1 = (step / (2.0 * B)).sum(1)
+            s = torch.exp(2j * torch.pi * y1).reshape(M, N)
+            ox.zero_grad()
+            _loss(s, s if matched else torch.view_as_complex(hr).detach(), prob).backward()
+            ox.step()
+            with torch.no_grad():
+                rho.copy_(torch.sort(rho).values)
+        assert rho.numel() == K
+        out.append((th.detach().numpy().copy(), rho.detach().numpy().copy(),
+                    torch.view_as_complex(hr).detach().numpy().copy()))
+    return out
+
+
+@pytest.mark.parametrize("copies,c,matched", [(3, 30.0, False), (100, 300.0, False), (3, 30.0, True)])
+def test_sqn_iteration_matches_torch(copies, c, matched):
+    """sqn_ref.iteration over two outer iterations against torch: the
+    ResNet, the copied staircase Q_A and the hard quantiser (threshold count
+    mod B) written with torch ops, Adam on (theta, rho) with the thresholds
+    sorted after every transmit update, Adam + projection on the filters."""
+    from oracle import sqn_ref as S
+    M, N, B = 2, 8, 4
+    D = M * N
+    prob = I.make_problem(M, N, B, 3, p=8.0, snrl_target_db=0.0 if matched else 0.5)
+    opt = I.make_opt(lr_z=2e-3, lr_h=2e-2, n_h=2, n_x=2)
+    sqn = {"c": c, "copies": copies}
+    theta0 = I.sqn_init(D, 11).astype(np.float64)
+    rho0 = I.sqn_thresholds(B, copies).astype(np.float64)
+    y0 = I.sqn_input(M, N, B, 12).astype(np.float64)
+    h0 = np.exp(2j * np.pi * np.random.default_rng(13).random((M, N)))
+    want = _torch_sqn_run(prob, opt, sqn, theta0, rho0, h0, y0, 2, matched)
+    th, rho, h, st = theta0, rho0, h0, S.new_state(D, B * copies, M, N)
+    for t in range(2):
+        th, rho, h, st, sa, sb = S.iteration(prob, opt, sqn, th, rho, h, y0, st, t, matched=matched)
+        tw, rw, hw = want[t]
+        # a parameter whose gradient is of order eps (a threshold with no chip
+        # near it, a weight fed by saturated units) turns a rounding difference
+        # dg of the two gradient sums into a step difference lr dg / eps
+        # (Adam's lr g / (|g| + eps)): allow that for dg ~ 1e-14, far below
+        # the step lr a mistake in the composition would show
+        # From the second iteration on, a sharp staircase (c = 300) feeds the
+        # difference back through the next waveform with gain ~ c / (2B) per
+        # nearby threshold; allow 1e-5 of a step there (a wrong step count,
+        # temperature or order moves parameters by a sizeable part of a step).
+        tol_x = 1e-12 + opt["lr_z"] / opt["eps"] * 1e-14 if t == 0 else 1e-5 * opt["lr_z"]
+        tol_h = 1e-12 + opt["lr_h"] / opt["eps"] * 1e-14 if t == 0 else 1e-5 * opt["lr_h"]
+        assert np.abs(th - tw).max() <= tol_x, (t, np.abs(th - tw).max())
+        assert np.abs(rho - rw).max() <= tol_x, (t, np.abs(rho - rw).max())
+        assert np.abs(h - hw).max() <= tol_h, (t, np.abs(h - hw).max())
+    assert np.abs(rho - rho0).max() > 1e-4
+    assert np.abs(th - theta0).max() > 1e-4
+
+
+# ------------------------------------------------------ peak location
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_loss_arg_is_first_peak_in_m_l_f_tau_order(ref, weighted):
+    """The (m, l, tau, f) the oracle reports is numpy's first argmax of w|A|
+    over the region of interest scanned in (m, l, f, tau) order -- with
+    planted exact ties, a delay window and the auto tau = 0 cut (whose
+    larger planted value must be skipped)."""
+    M, N, F = 3, 7, 4
+    T = 2 * N - 1
+    rng = np.random.default_rng(60)
+    cube = (rng.standard_normal((M, M, F, T)) + 1j * rng.standard_normal((M, M, F, T))) * 0.1
+    peak = 3.0
+    cube[1, 1, 2, N - 1] = 10.0                 # auto tau = 0: outside the region
+    cube[0, 2, 3, 0] = 9.0                      # tau = -(N-1): outside the window below
+    cube[2, 0, 1, N - 1 + 2] = peak * 1j        # planted tie, later in scan order
+    cube[1, 2, 0, N - 1 - 3] = -peak            # planted tie, first in scan order
+    cube[2, 2, 3, N - 1 + 4] = peak * np.exp(0.3j)
+    prob = I.make_problem(M, N, 4, F, p=8.0, tau_lo=-(N - 2), tau_hi=N - 1)
+    wt = None
+    if weighted:
+        wt = np.ones((F, T))
+        wt[2, N - 1 - 1] = 50.0                 # a weight makes a small cell the peak
+        prob = dict(prob, roi_w=wt)
+    s = np.exp(2j * np.pi * rng.random((M, N)))
+    st = ref.loss_stats(cube, s, s, prob)
+    tau = np.arange(-(N - 1), N)
+    w = np.ones((F, T)) if wt is None else wt
+    v = np.abs(cube) * w[None, None]
+    inside = ((tau >= prob["tau_lo"]) & (tau <= prob["tau_hi"]))[None, None, None, :].repeat(M, 0).repeat(M, 1) \
+        .repeat(F, 2)
+    for m in range(M):
+        inside[m, m, :, N - 1] = False
+    v = np.where(inside, v, -1.0)
+    m, l, f, k = np.unravel_index(int(np.argmax(v)), v.shape)
+    assert st["arg"] == (m, l, int(tau[k]), f)
+    if not weighted:
+        assert st["arg"] == (1, 2, -3, 0)
+        assert st["psl_cross"] == peak

@@ -1,11 +1,13 @@
 /*
  * sqngd_sqn.h - C ABI of the paper's transmit parameterisation in libsqngd.so
  * (Sec. III-A): the ResNet f_theta that maps the fixed input y0 = vec(Y0)
- * (normalised random phases, eq. 15-16) to continuous variables z (eq. 17),
- * the copied tanh staircase Q_A with trainable ordered thresholds rho (eq. 24)
- * that gives the soft waveform s = exp(j 2 pi Q_A(z)) (eq. 25-26), and the
- * hard quantiser (eq. 46) read as the staircase's limit: the number of
- * thresholds at or below z, mod B, as the phase index.
+ * (normalised discrete phases, eq. 15-16 and Algorithm 1's initialisation)
+ * to continuous variables z (eq. 17), the copied tanh staircase Q_A with
+ * trainable ordered thresholds rho (eq. 24) that gives the soft waveform
+ * s = exp(j 2 pi Q_A(z)) (eq. 22-23), and the hard quantiser Q_R (eq. 43)
+ * read as the staircase's limit: the number of thresholds at or below z,
+ * mod B, as the phase index. The thresholds are kept ordered after every
+ * transmit update (the projection Sec. III-C asks for).
  *
  * Network (D = M N inputs and outputs, width 128, 5 residual blocks):
  *   h_0 = tanh(W_in y0 + b_in),
@@ -74,10 +76,12 @@ int sqngd_sqn_workspace_size(const sqngd_sqn_shape* shape, size_t* bytes);
 int sqngd_sqn_forward(const sqngd_sqn_shape* shape, const float* theta, const float* y0, float* z, void* ws,
                       size_t ws_bytes, void* stream);
 
-/* Soft waveform s[m][n] = exp(j 2 pi Q_A(z[m N + n])) (eq. 24-26). */
+/* Soft waveform s[m][n] = exp(j 2 pi Q_A(z[m N + n])) (eq. 22-24). The phase is
+   taken from Q_A mod 1 formed as (thresholds below z mod B + the fractional
+   terms) / B, so its FP32 resolution does not degrade with the copy count. */
 int sqngd_sqn_soft(const sqngd_sqn_shape* shape, const float* z, const float* rho, sqngd_c64* s, void* stream);
 
-/* Hard waveform (eq. 46): idx = #{i : rho_i <= z} mod B, x = exp(j 2 pi idx / B).
+/* Hard waveform (Q_R, eq. 43): idx = #{i : rho_i <= z} mod B, x = exp(j 2 pi idx / B).
    Either output may be NULL. */
 int sqngd_sqn_hard(const sqngd_sqn_shape* shape, const float* z, const float* rho, int32_t* idx, sqngd_c64* x,
                    void* stream);

@@ -6,7 +6,8 @@ CPU-baseline leg of the benchmark may import it. It shares no code with the
 HIP path.
 
 The paper generates continuous variables z = f_theta(y0) (eq. 17) from the
-fixed input y0 = vec(Y0) of normalised random phases (eq. 15-16) with a ResNet
+fixed input y0 = vec(Y0) of random normalised discrete phases b / B (eq. 15-16,
+Algorithm 1's initialisation) with a ResNet
 of 5 residual blocks, width 128, tanh in the hidden and residual layers and a
 sigmoid output (Sec. IV). Read here as
   h_0 = tanh(W_in y0 + b_in),
@@ -137,6 +138,15 @@ def waveform_chain(grad_s, s) -> np.ndarray:
     """dL/dy1 from the packed waveform gradient: s = exp(j 2 pi y1), so
     dL/dy1 = 2 pi Im(grad_s conj(s)), flat [M N]."""
     return (2.0 * np.pi * np.imag(np.asarray(grad_s) * np.conj(np.asarray(s)))).reshape(-1)
+
+
+def initial_filters(y0, M: int, N: int) -> np.ndarray:
+    """Algorithm 1's initialisation: X0 = exp(j 2 pi Y0) (eq. 29) from the
+    network input y0 = vec(Y0), the filters its matched filter -- read as
+    H0 = X0 (eq. 30 prints the conjugate, which under eq. 6 would not give the
+    mainlobe h^H x0 = N) -- each row projected to energy N (eq. 32)."""
+    x0 = np.exp(2j * np.pi * np.asarray(y0, dtype=np.float64)).reshape(M, N)
+    return x0 * np.sqrt(N / (np.abs(x0) ** 2).sum(axis=1, keepdims=True))
 
 
 def new_state(D: int, K: int, M: int, N: int) -> dict:

@@ -197,8 +197,8 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     q.logP = log2i(q.P);
     q.tau_lo = p.tau_lo;
     q.tau_hi = p.tau_hi;
-    q.nu_min = p.nu_min;
-    q.dnu = p.F > 1 ? (float)(((double)p.nu_max - (double)p.nu_min) / (double)(p.F - 1)) : 0.0f;
+    q.nu_min = (double)p.nu_min;
+    q.dnu = p.F > 1 ? ((double)p.nu_max - (double)p.nu_min) / (double)(p.F - 1) : 0.0;
     q.p = p.p;
     q.p_tar = (float)std::pow(10.0, -(double)p.snrl_target_db / 20.0);
     q.w_psl = p.w_psl;

@@ -30,13 +30,23 @@ namespace sq {
 
 // ---------------------------------------------------------------- helpers
 
-// exp(j 2 pi n nu / N), phase reduced to [-1/2, 1/2] turns before sincospi.
-__device__ __forceinline__ float2 phasor(int n, float nu, float invN) {
-  float ph = (float)n * nu * invN;
-  ph -= rintf(ph);
+// exp(j 2 pi n nu / N) (the Doppler modulation of eq. 33): the phase in turns
+// is formed and reduced to [-1/2, 1/2] in FP64 -- on a wide Doppler span
+// (|nu| up to N / 2) it holds hundreds of whole turns, and an FP32 product
+// would keep only about 1e-5 of a turn of its fraction -- then one FP32
+// sincospi. Two calls per lane and unit, so the FP64 cost is negligible.
+__device__ __forceinline__ float2 phasor(int n, double nu, double invN) {
+  double ph = (double)n * nu * invN;
+  ph -= rint(ph);
   float s, c;
-  sincospif(2.0f * ph, &s, &c);
+  sincospif(2.0f * (float)ph, &s, &c);
   return make_float2(c, s);
+}
+
+// Doppler frequency of bin f, negated in orientation 1 (the role swap).
+__device__ __forceinline__ double doppler_nu(const ProbPlan& pl, int f, int orient) {
+  const double nu = pl.nu_min + (double)f * pl.dnu;
+  return orient ? -nu : nu;
 }
 
 
@@ -96,7 +106,7 @@ __device__ __forceinline__ float bias_corr(float b, int k) { return 1.0f - exp2f
 // phasor(n, nu, invN) for n = t + TF e, e < EH: one sincospi for n = t, one
 // for the step TF, then products (the step's rounding grows by one ulp per e).
 template <int EH, int TF>
-__device__ __forceinline__ void phasor_row(int t, float nu, float invN, float2 (&ph)[EH]) {
+__device__ __forceinline__ void phasor_row(int t, double nu, double invN, float2 (&ph)[EH]) {
   ph[0] = phasor(t, nu, invN);
   if constexpr (EH > 1) {
     const float2 st = phasor(TF, nu, invN);
@@ -528,8 +538,8 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
   const bool active = fs < F;
   const int f = active ? fs : F - 1;
   const int u = w * F + f;
-  const float invN = 1.0f / (float)N;
-  const float nu = (a.orient ? -1.0f : 1.0f) * (pl.nu_min + (float)f * pl.dnu);
+  const double invN = 1.0 / (double)N;
+  const double nu = doppler_nu(pl, f, a.orient);
   const int wlo = a.orient ? -pl.tau_hi : pl.tau_lo;
   const int whi = a.orient ? -pl.tau_lo : pl.tau_hi;
   const float phm1 = 0.5f * pl.p - 1.0f;
@@ -2107,8 +2117,8 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   const bool active = wave_on && fs < F;
   const int f = fs < F ? fs : F - 1;
   const int u = w * F + f;
-  const float invN = 1.0f / (float)N;
-  const float nu = (a.orient ? -1.0f : 1.0f) * (pl.nu_min + (float)f * pl.dnu);
+  const double invN = 1.0 / (double)N;
+  const double nu = doppler_nu(pl, f, a.orient);
   const int wlo = a.orient ? -pl.tau_hi : pl.tau_lo;
   const int whi = a.orient ? -pl.tau_lo : pl.tau_hi;
   const float phm1 = 0.5f * pl.p - 1.0f;
@@ -2132,8 +2142,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   for (int i = threadIdx.x; i < UB * 65; i += 64 * WV) {
     const int jj = i / 65, tt = i - jj * 65;
     const int fj = min(grp * UB + jj, F - 1);
-    const float nuj = (a.orient ? -1.0f : 1.0f) * (pl.nu_min + (float)fj * pl.dnu);
-    ph_tab[jj][tt] = phasor(tt, nuj, invN);
+    ph_tab[jj][tt] = phasor(tt, doppler_nu(pl, fj, a.orient), invN);
   }
   __syncthreads();
   WaveTwiddles<P> W;

@@ -16,7 +16,7 @@ constexpr int kMinLogP = 7;
 struct ProbPlan {
   int32_t M, N, L, F;
   int32_t P, logP, tau_lo, tau_hi;
-  float nu_min, dnu, p, p_tar;
+  float p, p_tar;
   float w_psl, w_snrl, temperature, inv_NP;
   int32_t sq_mode, ph_log;  // ph_log = log2(p/2) when p/2 is a power of two <= 32, else -1
   int32_t units, row0;      // units = M*wpr statistics entries; row0 = first row in the batch
@@ -26,8 +26,11 @@ struct ProbPlan {
   int64_t ws_unit;   // UnitStat index and row index of upart ([units][N] complex, stride N)
   int64_t ws_upart;  // complex offset of this problem's unit partials
   int64_t off_rw;    // float offset of this problem's ROI weights [F][2N-1]
+  // Doppler grid nu_f = nu_min + f dnu in FP64: wide spans put hundreds of
+  // turns into the modulation phase n nu_f / N, whose fraction FP32 would lose
+  double nu_min, dnu;
 };
-static_assert(sizeof(ProbPlan) == 152, "ProbPlan layout");
+static_assert(sizeof(ProbPlan) == 160, "ProbPlan layout");
 
 
 // Per-unit partial statistics of one fused pass. Keys pack the squared raw

@@ -386,8 +386,22 @@ __global__ __launch_bounds__(kThreads) void k_dw_all(DwArgs A) {
   }
 }
 
+// Staircase term and slope of one threshold at u = c (z - rho_i), from
+// e = exp(-2|u|) so that neither cancels where tanh(u) rounds to +-1:
+//   tanh(u) + 1 = 2 [u > 0] + q_sgn,  q_sgn = -q (u > 0), +q (u <= 0),  q = 2e / (1 + e)
+//   tanh'(u) = 1 - tanh(u)^2 = 4e / (1 + e)^2.
+__device__ __forceinline__ float stair_e(float u) { return expf(-2.0f * fabsf(u)); }
+__device__ __forceinline__ float stair_slope(float e) {
+  const float d = 1.0f + e;
+  return 4.0f * e / (d * d);
+}
+
 // One wave per chip, the K thresholds split over its lanes (sums in lane
-// order). y1 = sum_i (tanh(c (z - rho_i)) + 1) / (2B); s = exp(j 2 pi y1).
+// order). y1 = sum_i (tanh(c (z - rho_i)) + 1) / (2B) = (cnt + frac / 2) / B
+// with cnt the thresholds below z (u > 0) and frac the signed q terms;
+// s = exp(j 2 pi y1) takes the phase from (cnt mod B + frac / 2) / B, which
+// keeps FP32's resolution of the fraction however many copies the staircase
+// has (y1 itself reaches K / B turns).
 // Chips n of all R designs in one range (design n / D, thresholds rho[r][:]).
 __global__ __launch_bounds__(kThreads) void k_soft(const float* __restrict__ z, const float* __restrict__ rho,
                                                     int D, int R, int K, int B, float c, float2* s) {
@@ -395,19 +409,27 @@ __global__ __launch_bounds__(kThreads) void k_soft(const float* __restrict__ z, 
   if (n >= D * R) return;
   rho += (int64_t)(n / D) * K;
   const float zn = z[n];
-  float acc = 0.f;
-  for (int i = lane; i < K; i += 64) acc += tanhf(c * (zn - rho[i])) + 1.0f;
-  acc = wave_sum(acc);
+  float frac = 0.f;
+  int cnt = 0;
+  for (int i = lane; i < K; i += 64) {
+    const float u = c * (zn - rho[i]);
+    const float e = stair_e(u);
+    const float q = 2.0f * e / (1.0f + e);
+    cnt += u > 0.f ? 1 : 0;
+    frac += u > 0.f ? -q : q;
+  }
+  frac = wave_sum(frac);
+  cnt = (int)wave_sum((float)cnt);  // exact: counts <= 4096
   if (lane == 0) {
-    const float y1 = acc / (2.0f * (float)B);
+    const float y1 = ((float)(cnt % B) + 0.5f * frac) / (float)B;
     float sn, cs;
-    sincospif(2.0f * y1, &sn, &cs);
+    sincospif(2.0f * (y1 - rintf(y1)), &sn, &cs);
     s[n] = make_float2(cs, sn);
   }
 }
 
 // dy = 2 pi Im(g conj(s)) with g = gs (+ gh when given); dz = dy sum_i c
-// (1 - t_i^2) / (2B); one wave per chip.
+// tanh'(c (z - rho_i)) / (2B); one wave per chip.
 __global__ __launch_bounds__(kThreads) void k_chain(const float* __restrict__ z, const float* __restrict__ rho,
                                                      const float2* __restrict__ s, const float2* __restrict__ gs,
                                                      const float2* __restrict__ gh, int D, int R, int K, int B,
@@ -420,10 +442,7 @@ __global__ __launch_bounds__(kThreads) void k_chain(const float* __restrict__ z,
   dz_out += r * ws_str - (int64_t)r * D;
   const float zn = z[n];
   float d = 0.f;
-  for (int i = lane; i < K; i += 64) {
-    const float t = tanhf(c * (zn - rho[i]));
-    d += 1.0f - t * t;
-  }
+  for (int i = lane; i < K; i += 64) d += stair_slope(stair_e(c * (zn - rho[i])));
   d = wave_sum(d);
   if (lane == 0) {
     float2 g = gs[n];
@@ -435,7 +454,7 @@ __global__ __launch_bounds__(kThreads) void k_chain(const float* __restrict__ z,
   }
 }
 
-// drho_i = -sum_n dy_n c (1 - tanh(c (z_n - rho_i))^2) / (2B): one block per
+// drho_i = -sum_n dy_n c tanh'(c (z_n - rho_i)) / (2B): one block per
 // threshold, chips in a fixed order.
 __global__ __launch_bounds__(kThreads) void k_drho(const float* __restrict__ z, const float* __restrict__ rho,
                                                     const float* __restrict__ dy, int D, int B, float c,
@@ -450,8 +469,7 @@ __global__ __launch_bounds__(kThreads) void k_drho(const float* __restrict__ z, 
   const float r = rho[i];
   float acc = 0.f;
   for (int n = threadIdx.x; n < D; n += kThreads) {
-    const float t = tanhf(c * (z[n] - r));
-    acc += dy[n] * (1.0f - t * t);
+    acc += dy[n] * stair_slope(stair_e(c * (z[n] - r)));
   }
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;

@@ -211,8 +211,10 @@ def sqn_thresholds(B: int, copies: int) -> np.ndarray:
     return ((np.arange(K) + 0.5) / K).astype(np.float32)
 
 
-def sqn_input(M: int, N: int, seed: int) -> np.ndarray:
-    """The network input y0 = vec(Y0): random normalised phases U[0, 1),
-    float32 [M N] (waveform m's chips at m N .. m N + N - 1)."""
+def sqn_input(M: int, N: int, B: int, seed: int) -> np.ndarray:
+    """The network input y0 = vec(Y0) of Algorithm 1's initialisation: random
+    normalised discrete phases b / B, b uniform in [0, B), float32 [M N]
+    (waveform m's chips at m N .. m N + N - 1, the column-stacking of the
+    N x M phase matrix)."""
     rng = np.random.default_rng(seed)
-    return rng.random(M * N).astype(np.float32)
+    return (rng.integers(0, B, size=M * N) / B).astype(np.float32)

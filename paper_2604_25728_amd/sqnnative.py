@@ -155,8 +155,9 @@ class SQNDesign:
     """Algorithm 1 with the paper's transmit side for one design: the ResNet
     parameters theta and thresholds rho (step B, Adam with lr_z, thresholds
     sorted after each update) and the filters h (step A, Adam with lr_h and
-    the energy projection), from the fixed network input y0. The filters
-    start as the matched filter of the first hard waveform (h0 = x0).
+    the energy projection), from the fixed network input y0 = vec(Y0) of
+    random discrete normalised phases. The filters start as the matched filter
+    of X0 = exp(j 2 pi Y0) (h0 = x0), projected.
 
     matched=True is the AF extension of SQN the paper compares against
     (Sec. IV): no receive-filter optimisation, the filters are the waveform
@@ -181,11 +182,14 @@ class SQNDesign:
         f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32)).to(dev).reshape(-1).contiguous()
         self.theta = f32(np.concatenate([I.sqn_init(M * N, sd) for sd in seeds]) if theta is None else theta)
         self.rho = f32(np.tile(I.sqn_thresholds(B, copies), R) if rho is None else rho)
-        self.y0 = f32(np.concatenate([I.sqn_input(M, N, sd + 1) for sd in seeds]) if y0 is None else y0)
+        self.y0 = f32(np.concatenate([I.sqn_input(M, N, B, sd + 1) for sd in seeds]) if y0 is None else y0)
         self.z = self.sqn.forward(self.theta, self.y0)
         if h is None:
-            _, x = self.sqn.hard(self.z, self.rho, want_idx=False)
-            self.h = x.clone()
+            # Algorithm 1's start: X0 = exp(j 2 pi Y0) from the same discrete
+            # phases as the network input, the filters its matched filter
+            # (h0 = x0, so that h^H x0 = N), then the energy projection
+            y = self.y0.double()
+            self.h = torch.polar(torch.ones_like(y), 2.0 * np.pi * y).to(torch.complex64).contiguous()
             self.sqn.project(self.h)
         else:
             self.h = torch.as_tensor(np.asarray(h, np.complex64)).to(dev).reshape(-1).contiguous()

@@ -53,7 +53,8 @@ def test_step_teacher_forced(ref, mods, cfg, warm):
 
 def test_c1_run_matches_oracle_where_margins_are_clear(ref, mods):
     """The full 200-iteration M=2 N=64 design: final hard indices equal the oracle's
-    wherever the oracle's top-2 logit margin exceeds 1e-3; final PSL agrees."""
+    on every chip whose oracle top-2 logit margin exceeds 1e-3 (the rest is
+    reported); the final hard PSLR agrees within 0.05 dB."""
     nat, optim, _ = mods
     c = I.config("m2n64")
     prob, opt = c["problem"], c["opt"]
@@ -71,11 +72,13 @@ def test_c1_run_matches_oracle_where_margins_are_clear(ref, mods):
     got = run.hard_indices()[0]
     want = ref.hard_indices(z)
     agree = (got == want)[clear].mean()
-    print(f"M=2 N=64 final: {clear.mean():.3f} of chips clear, agreement {agree:.4f}")
-    assert agree >= 0.99
+    print(f"M=2 N=64 final: {clear.mean():.3f} of chips clear, agreement {agree:.4f}, "
+          f"unclear chips agreeing {(got == want)[~clear].mean() if (~clear).any() else 1.0:.3f}")
+    assert np.array_equal(got[clear], want[clear]), np.argwhere((got != want) & clear)
     st_gpu = run.hard_stats()[0]
     st_ref = ref.evaluate(ref.hard_waveform(z), h, prob, False)[0]
     print("final PSLR gpu", st_gpu["pslr_db"], "oracle", st_ref["pslr_db"])
+    assert abs(st_gpu["pslr_db"] - st_ref["pslr_db"]) <= 0.05
     st0 = ref.evaluate(ref.hard_waveform(z0), ref.matched_init(z0), prob, False)[0]
     assert st_gpu["loss"] < st0["loss"]
 

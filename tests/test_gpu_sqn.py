@@ -5,8 +5,10 @@ thresholds), Adam, the threshold sort, the filter projection, and two outer
 iterations of Algorithm 1 with this transmit side.
 
 Tolerances: the network and the staircase run in FP32 against FP64; outputs
-within 1e-5 relative normwise, gradients within 1e-4 (the staircase sums
-K tanh terms); the iteration as in test_gpu_optim (1e-4)."""
+within 1e-5 relative normwise, soft-waveform phases within 1e-4 rad,
+gradients within 1e-4 (the staircase sums K tanh terms); the iteration as in
+test_gpu_optim (1e-4), and at the paper's staircase (c = 300, r_n = 100) the
+parameter updates themselves within 1e-3 of the oracle's."""
 import numpy as np
 import pytest
 
@@ -46,7 +48,7 @@ def test_network_and_staircase(SN, S, M, N, B, copies, c):
     print(f"[gpu] sqn M={M} N={N} B={B} copies={copies}", flush=True)
     q = SN.SQN(M, N, B, copies, c)
     theta = I.sqn_init(D, 20)
-    y0 = I.sqn_input(M, N, 21)
+    y0 = I.sqn_input(M, N, B, 21)
     rho = I.sqn_thresholds(B, copies) + np.random.default_rng(22).normal(0, 1e-4, B * copies).astype(np.float32)
     rho = np.sort(rho).astype(np.float32)
     th, y, r = _t(theta), _t(y0), _t(rho)
@@ -59,7 +61,9 @@ def test_network_and_staircase(SN, S, M, N, B, copies, c):
     # the staircase on the GPU's own z (the FP32 network's rounding stays out of this check)
     zg = z.cpu().numpy().astype(np.float64)
     y1 = S.soft_quantise(zg, rho.astype(np.float64), B, c)
-    assert np.abs(np.angle(s.cpu().numpy() * np.conj(np.exp(2j * np.pi * y1)))).max() <= 2e-4 * copies
+    # (the phase is formed from the threshold count mod B plus the fractional
+    # terms, so FP32 keeps ~1e-6 rad whatever the copy count)
+    assert np.abs(np.angle(s.cpu().numpy() * np.conj(np.exp(2j * np.pi * y1)))).max() <= 1e-4
     k_ref = S.hard_levels(zg, rho.astype(np.float64)) % B
     far = np.min(np.abs(zg[:, None] - rho[None, :].astype(np.float64)), axis=1) > 1e-6
     assert np.array_equal(idx.cpu().numpy()[far], k_ref[far])
@@ -198,6 +202,69 @@ def test_two_iterations_match_oracle(SN, S):
     assert _rel(d.h.cpu().numpy().reshape(2, 64), h) <= 1e-4, _rel(d.h.cpu().numpy().reshape(2, 64), h)
     assert _rel(d.theta.cpu().numpy(), th) <= 1e-4, _rel(d.theta.cpu().numpy(), th)
     assert _rel(d.rho.cpu().numpy(), rho) <= 1e-4
+    assert np.all(np.diff(d.rho.cpu().numpy()) >= 0)
+    from paper_2604_25728_amd import native as nat
+    stb = nat.decode_stats(d.stats_b.cpu().numpy())[0]
+    assert abs(stb["loss"] - sb["loss"]) <= 1e-4 * sb["loss"]
+
+
+def test_initialisation_follows_algorithm_1(SN, S):
+    """Algorithm 1's start: y0 holds discrete normalised phases b / B, and the
+    filters are the projected matched filter of X0 = exp(j 2 pi Y0)."""
+    prob = I.make_problem(2, 64, 4, 5, p=8.0)
+    d = SN.SQNDesign(prob, I.make_opt(), 3, 30.0, seed=[70, 71])
+    y0 = d.y0.cpu().numpy().astype(np.float64).reshape(2, 2 * 64)
+    assert np.array_equal(y0 * 4, np.round(y0 * 4)) and y0.min() >= 0 and y0.max() <= 0.75
+    h = d.h.cpu().numpy().reshape(2, 2, 64)
+    for r in range(2):
+        want = S.initial_filters(y0[r], 2, 64)
+        assert np.abs(h[r] - want).max() <= 1e-6
+        assert np.allclose(np.abs(np.sum(np.conj(h[r]) * np.exp(2j * np.pi * y0[r].reshape(2, 64)), axis=1)), 64)
+
+
+def test_paper_staircase_iterations_match_oracle(SN, S):
+    """Two outer iterations at the paper's transmit settings (r_n = 100 copies,
+    c = 300, B = 4, M = 2, N = 512, eps = 0.1, |tau| <= 50 as ROI weights,
+    N_h = N_x = 2) against the oracle from the same state. At c = 300 most
+    thresholds sit where tanh rounds to +-1 in FP32: their gradients come
+    from the cancellation-free slope 4e / (1 + e)^2, so they move on the GPU
+    as in the oracle. Compared: the updates of theta, rho and h (normwise,
+    1e-3: a handful of parameters whose gradient is within FP32 rounding of
+    zero may take Adam's step with the other sign) and the step-B loss."""
+    prob = I.make_problem(2, 512, 4, 9, p=16.0, w_psl=0.1, w_snrl=0.9)
+    opt = I.make_opt(lr_z=1e-5, lr_h=5e-2, n_h=2, n_x=2)
+    copies, c = 100, 300.0
+    print("[gpu] sqn iterations at c=300 r_n=100", flush=True)
+    d = SN.SQNDesign(prob, opt, copies, c, seed=42)
+    w = I.roi_window_weights(prob, 50)
+    d.batch.set_roi_weights([w])
+    theta0 = d.theta.cpu().numpy().astype(np.float64)
+    rho0 = d.rho.cpu().numpy().astype(np.float64)
+    y0 = d.y0.cpu().numpy().astype(np.float64)
+    h0 = d.h.cpu().numpy().reshape(2, 512).astype(np.complex128)
+    for _ in range(2):
+        d.iteration()
+    torch.cuda.synchronize()
+    pw = dict(prob, roi_w=w.astype(np.float64))
+    th, rho, h, st = theta0, rho0, h0, S.new_state(2 * 512, 4 * copies, 2, 512)
+    for t in range(2):
+        th, rho, h, st, sa, sb = S.iteration(pw, opt, {"c": c, "copies": copies}, th, rho, h, y0, st, t)
+    d_th = _rel(d.theta.cpu().numpy() - theta0, th - theta0)
+    d_rho = _rel(d.rho.cpu().numpy() - rho0, rho - rho0)
+    d_h = _rel(d.h.cpu().numpy().reshape(2, 512) - h0, h - h0)
+    print(f"update errors: theta {d_th:.2e} rho {d_rho:.2e} h {d_h:.2e}", flush=True)
+    # thresholds at least 9 / c from every chip (tanh rounds to +-1 in FP32
+    # there) that still take a sizeable step in the oracle move the same on
+    # the GPU
+    z0, _ = S.forward(theta0, y0)
+    far = np.min(np.abs(z0[:, None] - rho0[None, :]), axis=0) * c > 9.0
+    step_ref, step_gpu = rho - rho0, d.rho.cpu().numpy() - rho0
+    sel = far & (np.abs(step_ref) > 0.1 * opt["lr_z"])
+    print(f"{far.sum()} thresholds in the saturated regime, {sel.sum()} of them moving", flush=True)
+    assert sel.sum() > 0
+    close = np.abs(step_gpu - step_ref)[sel] <= 0.1 * np.abs(step_ref)[sel]
+    assert close.mean() >= 0.99, close.mean()
+    assert d_th <= 1e-3 and d_rho <= 1e-3 and d_h <= 1e-3
     assert np.all(np.diff(d.rho.cpu().numpy()) >= 0)
     from paper_2604_25728_amd import native as nat
     stb = nat.decode_stats(d.stats_b.cpu().numpy())[0]

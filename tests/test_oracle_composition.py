@@ -282,3 +282,19 @@ def test_loss_arg_is_first_peak_in_m_l_f_tau_order(ref, weighted):
     if not weighted:
         assert st["arg"] == (1, 2, -3, 0)
         assert st["psl_cross"] == peak
+
+
+def test_peak_helper_agrees_with_oracle_arg(ref):
+    """tests/helpers.peak_and_gap (used to check the GPU's peak location)
+    returns the oracle's (m, l, tau, f) on random cubes with a delay window."""
+    from helpers import peak_and_gap
+    rng = np.random.default_rng(61)
+    for trial in range(5):
+        M, N, F = 2 + trial % 2, 9, 3
+        T = 2 * N - 1
+        cube = rng.standard_normal((M, M, F, T)) + 1j * rng.standard_normal((M, M, F, T))
+        prob = I.make_problem(M, N, 4, F, p=8.0, tau_lo=-(N - 3), tau_hi=N - 2)
+        s = np.exp(2j * np.pi * rng.random((M, N)))
+        arg, gap = peak_and_gap(cube, prob)
+        assert gap > 0
+        assert arg == ref.loss_stats(cube, s, s, prob)["arg"]

@@ -18,7 +18,7 @@ def test_resnet_against_torch_autograd(S):
     M, N = 2, 12
     D = M * N
     theta = I.sqn_init(D, 3).astype(np.float64)
-    y0 = I.sqn_input(M, N, 4).astype(np.float64)
+    y0 = I.sqn_input(M, N, 4, 4).astype(np.float64)
     z, cache = S.forward(theta, y0)
     dz = np.random.default_rng(5).standard_normal(D)
     g = S.backward(cache, dz)
@@ -47,7 +47,7 @@ def test_resnet_central_differences(S):
     M, N = 1, 8
     D = M * N
     theta = I.sqn_init(D, 6).astype(np.float64)
-    y0 = I.sqn_input(M, N, 7).astype(np.float64)
+    y0 = I.sqn_input(M, N, 4, 7).astype(np.float64)
     w = np.random.default_rng(8).standard_normal(D)
     z, cache = S.forward(theta, y0)
     g = S.backward(cache, w)
@@ -138,3 +138,19 @@ def test_matched_filter_gradient_central_differences(S, ref):
         assert abs(fd - dy[j]) <= 1e-6 * max(1.0, abs(dy[j]))
     # one gradient alone misses the filter role
     assert np.abs(gh).max() > 1e-3 * np.abs(g).max()
+
+
+def test_initial_filters_are_the_matched_filter(S, ref):
+    """Algorithm 1's start: with y0 discrete, every initial filter has unit
+    modulus (energy N), and the direct-sum AF of (X0, H0) has the mainlobe
+    A_mm(0, 0) = N at nu = 0 and |A| <= N everywhere (Cauchy-Schwarz)."""
+    M, N, B = 3, 16, 8
+    y0 = I.sqn_input(M, N, B, 5).astype(np.float64)
+    assert np.array_equal(y0 * B, np.round(y0 * B)) and y0.max() < 1.0
+    h0 = S.initial_filters(y0, M, N)
+    x0 = np.exp(2j * np.pi * y0).reshape(M, N)
+    assert np.allclose(np.abs(h0), 1.0, atol=1e-15)
+    cube = ref.af_cube(x0, h0, 3, -0.5, 0.5)
+    for m in range(M):
+        assert abs(cube[m, m, 1, N - 1] - N) <= 1e-12
+    assert np.abs(cube).max() <= N * (1 + 1e-12)

@@ -76,7 +76,9 @@
  *                        workspace was not initialised for this batch;
  *   SQNGD_E_ALIGN        a pointer not aligned as stated above;
  *   SQNGD_E_HIP          a HIP launch failed (sqngd_last_hip_error() keeps
- *                        the hipError_t).
+ *                        the hipError_t);
+ *   SQNGD_E_SCRATCH      the batch needs more scratch than the static array
+ *                        of sqngd_af_backward_noalloc holds.
  * Numerical trouble is not a status: a non-finite loss or gradient sets
  * stats.nonfinite, and sqngd_step then skips that problem's update.
  */
@@ -96,6 +98,7 @@ extern "C" {
 #define SQNGD_E_WORKSPACE (-3)
 #define SQNGD_E_ALIGN (-4)
 #define SQNGD_E_HIP (-5)
+#define SQNGD_E_SCRATCH (-6)
 
 /* waveform source for sqngd_af_forward / sqngd_af_backward */
 #define SQNGD_WAVE_SOFT 0  /* soft-quantised from z at problem.temperature */
@@ -236,6 +239,25 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
                       const sqngd_c64* s_given, const sqngd_c64* h, const float* grad_loss,
                       float* grad_z, sqngd_c64* grad_h, sqngd_c64* grad_s, sqngd_stats* stats,
                       void* ws, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   evaluation and outputs as sqngd_af_backward (the same kernels, bit for bit)
+   with no workspace argument. Its scratch (the batch plan, partner spectra,
+   unit statistics, gradient partial rows) lives in one static device array of
+   SQNGD_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; each call
+   first writes the batch plan into it through kernel arguments (no copy from
+   host memory, no memset, no allocation). A batch whose
+   sqngd_workspace_size exceeds that size returns SQNGD_E_SCRATCH (32 MiB
+   holds e.g. one M=8 N=1024 F=257 design, 16.4 MiB). ROI weights are not
+   attached (w = 1). Every call on one GPU shares the array: calls that
+   overlap on a GPU (on different streams, or from several threads) race and
+   must be serialised by the caller. */
+#define SQNGD_NOALLOC_SCRATCH_BYTES (32u << 20)
+int sqngd_af_backward_noalloc(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t wave_mode,
+                              const sqngd_c64* s_given, const sqngd_c64* h, const float* grad_loss,
+                              float* grad_z, sqngd_c64* grad_h, sqngd_c64* grad_s, sqngd_stats* stats,
+                              void* stream);
 
 /* One outer iteration t of Algorithm 1 for every problem of the batch:
    n_h times { hard waveform from z; loss and grad_h; Adam on (Re h, Im h);

@@ -661,6 +661,7 @@ const char* sqngd_status_string(int status) {
     case SQNGD_E_WORKSPACE: return "workspace too small or not initialised for this batch";
     case SQNGD_E_ALIGN: return "misaligned pointer";
     case SQNGD_E_HIP: return "HIP launch failure";
+    case SQNGD_E_SCRATCH: return "batch needs more scratch than the static array of the no-allocation entry point";
     default: return "unknown status";
   }
 }
@@ -789,10 +790,13 @@ int sqngd_af_forward(const sqngd_problem* probs, int32_t nprob, const float* z, 
   return check_launch();
 }
 
-int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t wave_mode,
-                      const sqngd_c64* s_given, const sqngd_c64* h, const float* grad_loss, float* grad_z,
-                      sqngd_c64* grad_h, sqngd_c64* grad_s, sqngd_stats* stats, void* ws, size_t ws_bytes,
-                      void* stream) {
+}  // extern "C"
+
+namespace {
+
+int check_backward_args(const float* z, int32_t wave_mode, const sqngd_c64* s_given, const sqngd_c64* h,
+                        const float* grad_loss, const float* grad_z, const sqngd_c64* grad_h,
+                        const sqngd_c64* grad_s, const sqngd_stats* stats) {
   if (wave_mode < SQNGD_WAVE_SOFT || wave_mode > SQNGD_WAVE_GIVEN) return SQNGD_E_INVALID_ARG;
   if (wave_mode != SQNGD_WAVE_GIVEN && z == nullptr) return SQNGD_E_INVALID_ARG;
   if (wave_mode == SQNGD_WAVE_GIVEN && (s_given == nullptr || grad_z != nullptr)) return SQNGD_E_INVALID_ARG;
@@ -801,10 +805,13 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
   if (!aligned(z, 4) || !aligned(s_given, 8) || !aligned(h, 8) || !aligned(grad_loss, 4) || !aligned(grad_z, 4) ||
       !aligned(grad_h, 8) || !aligned(grad_s, 8) || !aligned(stats, 4))
     return SQNGD_E_ALIGN;
-  const Plan* pl = nullptr;
-  int rc = lookup(probs, nprob, ws, ws_bytes, &pl);
-  if (rc != SQNGD_OK) return rc;
-  hipStream_t s = (hipStream_t)stream;
+  return SQNGD_OK;
+}
+
+// The launch sequence of sqngd_af_backward on a workspace that holds `pl`.
+int af_backward_launch(const Plan* pl, void* ws, const float* z, int32_t wave_mode, const sqngd_c64* s_given,
+                       const sqngd_c64* h, const float* grad_loss, float* grad_z, sqngd_c64* grad_h,
+                       sqngd_c64* grad_s, sqngd_stats* stats, hipStream_t s) {
   Ptrs w = ptrs(*pl, ws);
   float4* snrl0 = w.snrl;
   float4* snrl1 = w.snrl + pl->hdr.nrows;
@@ -867,6 +874,23 @@ int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z,
     launch_final(*pl, w, fb, s);
   }
   return check_launch();
+}
+
+}  // namespace
+
+extern "C" {
+
+int sqngd_af_backward(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t wave_mode,
+                      const sqngd_c64* s_given, const sqngd_c64* h, const float* grad_loss, float* grad_z,
+                      sqngd_c64* grad_h, sqngd_c64* grad_s, sqngd_stats* stats, void* ws, size_t ws_bytes,
+                      void* stream) {
+  int rc = check_backward_args(z, wave_mode, s_given, h, grad_loss, grad_z, grad_h, grad_s, stats);
+  if (rc != SQNGD_OK) return rc;
+  const Plan* pl = nullptr;
+  rc = lookup(probs, nprob, ws, ws_bytes, &pl);
+  if (rc != SQNGD_OK) return rc;
+  return af_backward_launch(pl, ws, z, wave_mode, s_given, h, grad_loss, grad_z, grad_h, grad_s, stats,
+                            (hipStream_t)stream);
 }
 
 static int validate_opt(const sqngd_opt* opt) {
@@ -1002,6 +1026,96 @@ int sqngd_hard_quantize(const sqngd_problem* probs, int32_t nprob, const float* 
   HardArgs a{w.plans, w.row_prob, z, idx, (float2*)x};
   hipLaunchKernelGGL(k_hardq, dim3(pl->hdr.nrows), dim3(256), 0, (hipStream_t)stream, a);
   return check_launch();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ entry point without a workspace
+
+// The scratch of sqngd_af_backward_noalloc: one static array per GPU, held
+// until the process ends. Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): it uses the
+// device address hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) unsigned char scratch[SQNGD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr size_t kNoAllocScratch = (size_t)SQNGD_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev < 0 || dev >= kMaxDevices) return SQNGD_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev] == nullptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e);
+    if (ptr == nullptr || !aligned(ptr, kAlign)) return SQNGD_E_ALIGN;
+    g_scratch[dev] = ptr;
+  }
+  *out = g_scratch[dev];
+  return SQNGD_OK;
+}
+
+// Bytes carried by value in a kernel's arguments: the runtime copies the
+// arguments at launch, so the host buffer they came from may go away at once
+// (no host-memory lifetime to track, no copy engine, nothing allocated).
+constexpr int kPutWords = 960;
+struct PutArgs {
+  uint32_t* dst;
+  int32_t nwords, pad;
+  uint32_t w[kPutWords];
+};
+static_assert(sizeof(PutArgs) <= 4096, "kernel argument limit");
+
+__global__ __launch_bounds__(256) void k_put_words(PutArgs a) {
+  for (int i = threadIdx.x; i < a.nwords; i += 256) a.dst[i] = a.w[i];
+}
+
+// Writes the plan's table bytes (header, problem plans, work tables, zeroed
+// counters) to the start of `dst` on `s`.
+int put_plan(const Plan& pl, void* dst, hipStream_t s) {
+  const size_t nb = pl.bytes.size();  // a multiple of the 256-byte alignment
+  const uint32_t* src = (const uint32_t*)pl.bytes.data();
+  const size_t nw = nb / 4;
+  for (size_t off = 0; off < nw; off += kPutWords) {
+    PutArgs a;
+    a.dst = (uint32_t*)dst + off;
+    a.nwords = (int32_t)std::min<size_t>(kPutWords, nw - off);
+    a.pad = 0;
+    std::memcpy(a.w, src + off, 4 * (size_t)a.nwords);
+    hipLaunchKernelGGL(k_put_words, dim3(1), dim3(256), 0, s, a);
+  }
+  return check_launch();
+}
+
+}  // namespace
+
+extern "C" {
+
+int sqngd_af_backward_noalloc(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t wave_mode,
+                              const sqngd_c64* s_given, const sqngd_c64* h, const float* grad_loss,
+                              float* grad_z, sqngd_c64* grad_h, sqngd_c64* grad_s, sqngd_stats* stats,
+                              void* stream) {
+  int rc = check_backward_args(z, wave_mode, s_given, h, grad_loss, grad_z, grad_h, grad_s, stats);
+  if (rc != SQNGD_OK) return rc;
+  rc = validate_batch(probs, nprob);
+  if (rc != SQNGD_OK) return rc;
+  auto pl = build_plan(probs, nprob);
+  if ((size_t)pl->hdr.total > kNoAllocScratch) return SQNGD_E_SCRATCH;
+  void* ws = nullptr;
+  rc = scratch_address(&ws);
+  if (rc != SQNGD_OK) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  rc = put_plan(*pl, ws, s);
+  if (rc != SQNGD_OK) return rc;
+  return af_backward_launch(pl.get(), ws, z, wave_mode, s_given, h, grad_loss, grad_z, grad_h, grad_s, stats, s);
 }
 
 }  // extern "C"

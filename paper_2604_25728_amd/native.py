@@ -24,7 +24,10 @@ SYMBOLS = [
     "sqngd_buffer_sizes", "sqngd_workspace_size", "sqngd_workspace_init", "sqngd_af_forward",
     "sqngd_af_backward", "sqngd_step", "sqngd_run", "sqngd_hard_quantize", "sqngd_status_string",
     "sqngd_last_hip_error", "sqngd_profile_enable", "sqngd_profile_read", "sqngd_set_roi_weights",
+    "sqngd_af_backward_noalloc",
 ]
+E_SCRATCH = -6
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class Problem(ctypes.Structure):
@@ -71,6 +74,7 @@ def load():
     lib.sqngd_set_roi_weights.argtypes = [P, i32, P, P, sz]
     lib.sqngd_af_forward.argtypes = [P, i32, P, i32, P, P, P, P, P, sz, P]
     lib.sqngd_af_backward.argtypes = [P, i32, P, i32, P, P, P, P, P, P, P, P, sz, P]
+    lib.sqngd_af_backward_noalloc.argtypes = [P, i32, P, i32, P, P, P, P, P, P, P, P]
     lib.sqngd_step.argtypes = [P, i32, P, P, P, P, P, P, P, sz, P]
     lib.sqngd_run.argtypes = [P, i32, P, i32, P, P, P, P, P, P, sz, P]
     lib.sqngd_hard_quantize.argtypes = [P, i32, P, P, P, P, sz, P]
@@ -152,6 +156,25 @@ def decode_stats(words: np.ndarray) -> list[dict]:
         d["nonfinite"] = int(words[r, 12])
         out.append(d)
     return out
+
+
+def af_backward_noalloc(probs, z, h, wave_mode=WAVE_SOFT, s_given=None, grad_loss=None, want_z=True,
+                        want_h=True, want_s=False, stats=None, device="cuda"):
+    """sqngd_af_backward_noalloc: the gradients of sqngd_af_backward for the
+    packed batch `probs` without a workspace (the library's static scratch on
+    the current GPU). Returns (grad_z, grad_h, grad_s), None where not wanted."""
+    import torch
+    lib = load()
+    arr = make_problems(probs)
+    zf, wc = ctypes.c_int64(), ctypes.c_int64()
+    check(lib.sqngd_buffer_sizes(arr, len(probs), ctypes.byref(zf), ctypes.byref(wc), None, None), "buffer_sizes")
+    gz = torch.empty(zf.value, dtype=torch.float32, device=device) if want_z else None
+    gh = torch.empty(wc.value, dtype=torch.complex64, device=device) if want_h else None
+    gs = torch.empty(wc.value, dtype=torch.complex64, device=device) if want_s else None
+    check(lib.sqngd_af_backward_noalloc(arr, len(probs), _ptr(z), int(wave_mode), _ptr(s_given), _ptr(h),
+                                        _ptr(grad_loss), _ptr(gz), _ptr(gh), _ptr(gs), _ptr(stats), _stream()),
+          "af_backward_noalloc")
+    return gz, gh, gs
 
 
 class Batch:

@@ -58,7 +58,7 @@ def test_struct_layouts(nat):
 
 def test_status_strings(nat):
     assert nat.status_string(0) == "ok"
-    for rc in (-1, -2, -3, -4, -5):
+    for rc in (-1, -2, -3, -4, -5, -6):
         assert nat.status_string(rc) != "unknown status"
 
 
@@ -264,3 +264,26 @@ def test_sqn_validation(nat):
                                        0.9, 0.999, 1e-8, ws, b.value, None) == -1
     assert lib.sqngd_sqn_backward_adam(ctypes.byref(good), v, v, v, v, v, v, None, v, v, v, None, 0, 0, 1e-3,
                                        0.9, 0.999, 1e-8, ws, b.value, None) == -1
+
+
+def test_noalloc_validation_before_any_hip_call(nat):
+    """sqngd_af_backward_noalloc checks its arguments and the batch's scratch
+    need on the host: bad arguments and a batch larger than the static scratch
+    return their status without touching the device (no GPU here)."""
+    lib = nat.load()
+    fake = ctypes.c_void_p(1 << 20)   # aligned, never dereferenced on these paths
+    big = nat.make_problems([I.make_problem(16, 2048, 64, 129)])
+    rc, need = _ws_size(nat, big)
+    assert rc == 0 and need > nat.NOALLOC_SCRATCH_BYTES
+    rc = lib.sqngd_af_backward_noalloc(big, 1, fake, 0, None, fake, None, fake, fake, None, None, None)
+    assert rc == nat.E_SCRATCH
+    arr = _arr(nat)
+    # NULL filters, bad mode, GIVEN without waveforms, misaligned output
+    assert lib.sqngd_af_backward_noalloc(arr, 1, fake, 0, None, None, None, fake, None, None, None, None) == -1
+    assert lib.sqngd_af_backward_noalloc(arr, 1, fake, 7, None, fake, None, fake, None, None, None, None) == -1
+    assert lib.sqngd_af_backward_noalloc(arr, 1, None, 2, None, fake, None, None, fake, None, None, None) == -1
+    assert lib.sqngd_af_backward_noalloc(arr, 1, fake, 0, None, fake, None, ctypes.c_void_p((1 << 20) + 2),
+                                         None, None, None, None) == -4
+    # an invalid problem
+    bad = _arr(nat, p=1.0)
+    assert lib.sqngd_af_backward_noalloc(bad, 1, fake, 0, None, fake, None, fake, None, None, None, None) == -1

@@ -1,18 +1,23 @@
 #!/usr/bin/env python
 """Throughput of the SQNGD hot path on one MI355X.
 
-A step is one outer iteration of Algorithm 1 (sqngd_step with one filter
-update and one logit update, each a full AF loss + gradient evaluation:
-quantisation, fused FFT AF / loss / adjoint pass, reduction, optimiser),
-recorded once in a HIP graph and replayed. The default workload is one design
-of M=4 waveforms, N=256 chips, L=8 phase levels, F=129 Doppler bins over
-[-0.5, 0.5], every delay in the region of interest, p=16, temperature annealed
-1.0 -> 0.05. Inputs are seeded synthetic N(0,1) logits and the matched filter;
-they are resident in HBM before the timed region starts.
+A step is one outer iteration of Algorithm 1 over one batch (sqngd_step: for
+every design one filter update and one logit update, each a full AF loss +
+gradient evaluation -- quantisation, fused FFT AF / loss / adjoint pass,
+reduction, optimiser), recorded once in a HIP graph and replayed. The default
+workload is the uneven batch: 64 independent designs with N drawn from
+{128, 256, 512, 1024}, M from {2, 4, 8}, L from {4, 8, 16}, F = 129 Doppler
+bins over [-0.5, 0.5], every delay in the region of interest, p = 16, each
+with 8 random restarts (512 problems). Inputs are seeded synthetic N(0,1)
+logits and the matched filter, resident in HBM before the timed region.
 
-Prints one JSON line with the metric, the roofline of the fused pass kernel
-and the oracle timed on the host cores.
-Diagnostics go to stderr.
+The metric's evaluation is one loss + one gradient evaluation of one problem
+(a step holds two per problem: the filter step's grad_h and the logit step's
+grad_z). The line also carries the rate of evaluations with both gradients
+(sqngd_af_backward with grad_z and grad_h) on the same batch.
+
+Prints one JSON line with the metric, the roofline of the dominant kernel and
+the oracle timed on the host cores. Diagnostics go to stderr.
 """
 from __future__ import annotations
 
@@ -20,6 +25,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -29,8 +35,11 @@ if ROOT not in sys.path:
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 HBM_PEAK_GBPS = 8000.0            # MI355X published HBM3E bandwidth
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_split_m4n256_traffic.md")
 COPY_BYTES = 1 << 28              # calibration copy of the counter runs: 256 MiB read, 256 MiB written
+# HBM traffic of the dominant fused-pass kernel from the committed counter
+# summaries (two rocprofv3 --pmc passes each), per workload
+TRAFFIC_FILES = {"uneven": os.path.join(ROOT, "profiles", "k_pass_2048_uneven_64x8_traffic.md"),
+                 "m4n256": os.path.join(ROOT, "profiles", "k_pass_split_m4n256_traffic.md")}
 
 
 def log(*a):
@@ -72,38 +81,58 @@ def cube_frac(cells: int, evals_per_cell_set: float, ms: float) -> float:
 
 def time_graph(run, steps: int, warmup: int, per_graph: int):
     """ms per outer iteration over `steps` iterations run as graph replays of
-    `per_graph` iterations each (steps is rounded up to a multiple)."""
+    `per_graph` iterations each (steps is rounded up to a multiple): (mean,
+    wall seconds, iterations, per-replay ms per iteration). Every replay is
+    bracketed by HIP events on the stream it runs on."""
+    import numpy as np
     import torch
     run.capture(per_graph)
     for _ in range(max(1, warmup // per_graph)):
         run.replay()
     torch.cuda.synchronize()
     reps = max(1, -(-steps // per_graph))
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     t0 = time.perf_counter()
-    e0.record()
-    for _ in range(reps):
+    ev[0].record()
+    for i in range(reps):
         run.replay()
-    e1.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return e0.elapsed_time(e1) / (reps * per_graph), wall, reps * per_graph
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) / per_graph for i in range(reps)])
+    return ev[0].elapsed_time(ev[-1]) / (reps * per_graph), wall, reps * per_graph, per
 
 
-def kernel_durations(run, nat, steps: int, repeat: int = 20):
-    """Per-launch durations (ms) of the fused pass over `steps` eager steps: HIP
-    events on the launch stream around `repeat` back-to-back launches of each
-    pass (identical inputs and outputs), divided by `repeat`."""
+def spread(per) -> dict:
+    import numpy as np
+    return {"median": float(np.median(per)), "p10": float(np.percentile(per, 10)),
+            "p90": float(np.percentile(per, 90)), "replays": int(len(per))}
+
+
+def pass_groups(probs) -> list:
+    """FFT lengths of the batch's fused-pass launches, in launch order."""
+    return sorted({fft_len(p["N"]) for p in probs})
+
+
+def group_durations(run, nat, steps: int, repeat: int = 1) -> dict:
+    """Mean duration (ms) of each FFT-length group's fused-pass launch over
+    `steps` eager steps (two passes each): HIP events recorded by the library
+    on the launch stream around `repeat` back-to-back launches of that pass
+    (identical inputs and outputs), divided by `repeat`. The groups of one
+    pass are launched in increasing FFT length."""
+    import numpy as np
     import torch
+    groups = pass_groups(run.probs)
+    n = 2 * steps * len(groups)
     torch.cuda.synchronize()
-    nat.profile_enable(2 * steps, repeat)
+    nat.profile_enable(n, repeat)
     for _ in range(steps):
         run.step()
     torch.cuda.synchronize()
-    d = nat.profile_read(2 * steps)
+    d = nat.profile_read(n)
     nat.profile_enable(0, 1)
-    return d
+    assert d.size == n, (d.size, n)
+    return {P: float(np.mean(d[i::len(groups)])) for i, P in enumerate(groups)}
 
 
 def source_hash() -> str:
@@ -119,23 +148,23 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(schedule: int):
-    """HBM bytes per fused-pass launch from the committed counter summary, or
-    None when the summary is missing or was taken on other sources or under
-    another schedule."""
+def stored_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary of
+    `workload`, or None when the summary is missing, names another kernel or
+    was taken on other sources."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[workload]) as f:
             txt = f.read()
-    except OSError:
+    except (OSError, KeyError):
         return None
     vals = {}
     for line in txt.splitlines():
-        if line.startswith(("traffic_bytes_per_launch:", "source_hash:", "schedule:")):
+        if line.startswith(("traffic_bytes_per_launch:", "source_hash:", "kernel:")):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("source_hash") != source_hash() or "traffic_bytes_per_launch" not in vals:
         return None
-    if int(vals.get("schedule", "-1")) != int(schedule):
+    if vals.get("kernel") != kernel:
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -156,26 +185,85 @@ def counter_run(run, steps: int):
     log(f"counter run: {steps} eager iterations, then one copy of {COPY_BYTES} bytes")
 
 
-def cpu_baseline(prob: dict, opt: dict, budget_s: float) -> dict:
-    """The FP64 oracle's outer iteration, timed on the host cores."""
+def cpu_model() -> dict:
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def _oracle_step_seconds(prob: dict, opt: dict, seed: int) -> float:
     import numpy as np
 
     from oracle import sqngd_ref as R
     from paper_2604_25728_amd import inputs as I
     R.build()
-    z = I.logits(prob["M"], prob["N"], prob["L"], 0).astype(np.float64)
+    z = I.logits(prob["M"], prob["N"], prob["L"], seed).astype(np.float64)
     h = R.matched_init(z)
     state = R.new_state(prob["M"], prob["N"], prob["L"])
-    n = 0
     t0 = time.perf_counter()
-    while n < 1 or time.perf_counter() - t0 < budget_s:
-        z, h, state, _, _ = R.step(prob, opt, z, h, state, n)
-        n += 1
+    R.step(prob, opt, z, h, state, 0)
+    return time.perf_counter() - t0
+
+
+def oracle_cost(prob: dict) -> float:
+    """Work of one oracle outer iteration in the direct sums' unit: two
+    evaluations of M^2 F N^2 delay-Doppler products each."""
+    return 2.0 * prob["M"] ** 2 * prob["F"] * prob["N"] ** 2
+
+
+def cpu_baseline(designs, opt: dict, budget_s: float) -> dict:
+    """The FP64 oracle's outer iteration (two evaluations, each the AF cube,
+    the loss and both gradients by direct sums) timed on the host cores on a
+    bounded sample of the batch: its distinct shapes in increasing cost until
+    the budget is spent. The direct sums cost M^2 F N^2 products per
+    evaluation, so the per-product time of the sample (least squares through
+    the origin) prices the whole batch; the rate is scaled to the metric's
+    evaluations (two per problem per outer iteration)."""
+    import numpy as np
+    shapes = {}
+    for p, sd in designs:
+        shapes.setdefault((p["M"], p["N"], p["L"]), (p, sd))
+    order = sorted(shapes.values(), key=lambda ps: oracle_cost(ps[0]))
+    xs, ts, names = [], [], []
+    t0 = time.perf_counter()
+    for p, sd in order:
+        if ts and time.perf_counter() - t0 + ts[-1] * oracle_cost(p) / xs[-1] > budget_s:
+            break
+        ts.append(_oracle_step_seconds(p, opt, sd))
+        xs.append(oracle_cost(p))
+        names.append(f"M={p['M']} N={p['N']} L={p['L']}")
     el = time.perf_counter() - t0
+    xs, ts = np.array(xs), np.array(ts)
+    per = float((xs * ts).sum() / (xs * xs).sum())
+    batch_s = per * sum(oracle_cost(p) for p, _ in designs)
     cores = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
-    return {"value": 2 * n / el, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} outer iterations (2 evaluations each: AF cube, loss and both gradients "
-                      f"by FP64 direct sums) of the same workload, {el:.1f} s"}
+    return {"value": 2 * len(designs) / batch_s, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"one oracle outer iteration of each of the {len(xs)} cheapest distinct shapes of the "
+                      f"batch ({', '.join(names)}; {el:.1f} s), {per * 1e9:.3f} ns per delay-Doppler product "
+                      f"(M^2 F N^2 per evaluation), priced over the {len(designs)} problems: "
+                      f"{batch_s:.0f} s per outer iteration of the batch",
+            "s_per_batch_iteration": batch_s, "ns_per_product": per * 1e9,
+            "sample_shapes": names, "sample_seconds": ts.tolist(), **cpu_model()}
+
+
+def cpu_single_thread(designs, opt: dict, budget_s: float) -> dict:
+    """The same leg in a child process restricted to one OpenMP thread."""
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; from paper_2604_25728_amd import inputs as I; "
+            "d = I.uneven_designs(); print(json.dumps(bench.cpu_baseline(d, I.config('m4n256')['opt'], %r)))"
+            % (ROOT, budget_s))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=30 * budget_s + 120)
+    if out.returncode != 0:
+        return {"error": out.stderr[-400:]}
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    return {k: r[k] for k in ("value", "unit", "cores", "sample", "ns_per_product")}
 
 
 def fft_route_eval(s, h, prob: dict, workers: int = 1) -> tuple:
@@ -282,23 +370,109 @@ def transmit_extras(I, torch, only=None) -> dict:
     return extras
 
 
+def roofline_of(probs, gdur: dict, workload: str) -> dict:
+    """Roofline record of the batch's dominant fused-pass launch (the FFT-length
+    group with the largest measured duration): algorithmic flops of that launch
+    (pass_flops summed over its problems) over its measured mean duration,
+    against the FP32 vector peak."""
+    P = max(gdur, key=gdur.get)
+    flops = sum(pass_flops(p) for p in probs if fft_len(p["N"]) == P)
+    ms = gdur[P]
+    achieved = flops / (ms * 1e-3) / 1e12
+    kernel = f"k_pass<{P}, 3, false>"
+    traffic = stored_traffic(workload, kernel)
+    return {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+            "kernel": f"{kernel} (fused AF + loss + adjoint, FFT length {P} group)",
+            "kernel_us": ms * 1e3, "flops_per_launch": flops,
+            "problems_in_launch": sum(1 for p in probs if fft_len(p["N"]) == P),
+            "traffic_source": os.path.relpath(TRAFFIC_FILES[workload], ROOT) if traffic else None,
+            "group_kernel_us": {str(k): v * 1e3 for k, v in sorted(gdur.items())}}
+
+
+def both_gradient_rate(probs, seeds, reps: int = 5) -> dict:
+    """Evaluations with both gradients (sqngd_af_backward: loss, grad_z of the
+    soft waveform and grad_h) of every problem of the batch, timed with HIP
+    events around `reps` back-to-back calls."""
+    import torch
+
+    from paper_2604_25728_amd import inputs as I
+    from paper_2604_25728_amd import native as nat
+    b = nat.Batch(probs)
+    z = b.pack_z([I.logits(p["M"], p["N"], p["L"], s) for p, s in zip(probs, seeds)])
+    _, x = b.hard_quantize(z, want_idx=False)
+    stats = b.new_stats()
+    b.af_backward(z, x, nat.WAVE_SOFT, stats=stats)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.af_backward(z, x, nat.WAVE_SOFT, stats=stats)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"evals_per_s": len(probs) / (ms * 1e-3), "ms_per_batch": ms,
+            "unit": "evaluations with the loss, grad_z and grad_h of one problem per second"}
+
+
+def single_design(I, nat, optim, name: str, steps: int, tuned: bool) -> dict:
+    """One design of a preset: ms per outer iteration (graph replays of one
+    iteration), its fused pass's roofline."""
+    c = I.config(name)
+    prob, opt = c["problem"], c["opt"]
+    sched = None
+    if tuned:
+        from paper_2604_25728_amd import tune
+        sched, sched_ms = tune.tune([prob], opt, steps=40)
+        log(f"{name}: schedule tuning (ms per step): " +
+            ", ".join(f"{k}: {v * 1e3:.1f} us" for k, v in sched_ms.items()) + f" -> {sched}")
+    run = optim.SQNGD([prob], opt, seeds=[0], schedule=sched)
+    ms, _, n, per = time_graph(run, steps, 10, 1)
+    import numpy as np
+    import torch
+    torch.cuda.synchronize()
+    nat.profile_enable(2 * 50, 20)
+    for _ in range(50):
+        run.step()
+    torch.cuda.synchronize()
+    kd = float(np.mean(nat.profile_read(100)))
+    nat.profile_enable(0, 1)
+    flops = pass_flops(prob)
+    achieved = flops / (kd * 1e-3) / 1e12
+    kname = (f"k_pass_split<{fft_len(prob['N'])}, 3, {int(sched)}, false>" if sched and sched >= 8
+             else f"k_pass<{fft_len(prob['N'])}, 3, false>")
+    traffic = stored_traffic(name, kname)
+    out = {"ms_per_step": ms, **{f"step_{k}": v for k, v in spread(per).items()},
+           "evals_per_s": 2.0 / (ms * 1e-3),
+           "cube_equiv_frac_of_hbm": cube_frac(cube_cells(prob), 2, ms),
+           "shape": {k: prob[k] for k in ("M", "N", "L", "F", "nu_min", "nu_max")},
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                        "kernel": kname, "kernel_us": kd * 1e3, "flops_per_launch": flops},
+           "pass_cube_equiv_frac_of_hbm": CUBE_BYTES_PER_CELL * cube_cells(prob) / (kd * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+    if sched is not None:
+        out["schedule"] = int(sched)
+    log(f"{name}: step {ms * 1e3:.1f} us, pass {kd * 1e3:.2f} us = {achieved:.2f} TFLOP/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--iters-per-graph", type=int, default=10,
-                    help="outer iterations recorded in one HIP graph (one sqngd_run call)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and copy probes")
-    ap.add_argument("--schedule", type=int, default=12,
-                    help="fused-pass schedule hint of the --counters run (the timed run tunes it)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other workloads and the copy probe")
     ap.add_argument("--transmit", nargs="?", const="all", default=None,
                     choices=["all", "paper_sqn_m2n512_b4", "paper_sqnaf_m2n512_b4", "paper_sqn_m2n512_b4_x64"],
                     help="time only the transmit-side workloads (all, or one) and print them as one JSON line")
     ap.add_argument("--counters", action="store_true",
                     help="run the workload for rocprofv3 --pmc (eager iterations + calibration copy) and exit")
+    ap.add_argument("--workload", default="uneven", choices=["uneven", "m4n256", "wide_m8n1024"],
+                    help="workload of a --counters run")
+    ap.add_argument("--schedule", type=int, default=12,
+                    help="fused-pass schedule hint of an m4n256 --counters run (the timed run tunes it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the designs of a batch "
@@ -313,90 +487,85 @@ def main():
     from paper_2604_25728_amd import optim
 
     torch.cuda.set_device(0)
-    cfg = I.config("m4n256")
-    prob, opt = cfg["problem"], cfg["opt"]
     log(f"device: {torch.cuda.get_device_name(0)}")
+    designs = I.uneven_designs()
+    probs = [p for p, _ in designs]
+    seeds = [sd for _, sd in designs]
+    opt = I.config("m4n256")["opt"]
 
     if args.transmit:
         only = None if args.transmit == "all" else args.transmit
         print(json.dumps({"transmit_side": transmit_extras(I, torch, only)}), flush=True)
         return
     if args.counters:
-        run = optim.SQNGD([prob], opt, seeds=[0], schedule=args.schedule)
+        if args.workload == "uneven":
+            run = optim.SQNGD(probs, opt, seeds=seeds)
+        else:
+            c = I.config(args.workload)
+            sched = args.schedule if args.workload == "m4n256" else None
+            run = optim.SQNGD([c["problem"]], c["opt"], seeds=[0], schedule=sched)
         counter_run(run, args.steps)
         return
-    from paper_2604_25728_amd import tune
-    sched, sched_ms = tune.tune([prob], opt, steps=40)
-    log("schedule tuning (ms per step): " + ", ".join(f"{k}: {v * 1e3:.1f} us" for k, v in sched_ms.items())
-        + f" -> {sched}")
-    run = optim.SQNGD([prob], opt, seeds=[0], schedule=sched)
-    ms_step, wall, steps = time_graph(run, args.steps, args.warmup, args.iters_per_graph)
-    evals_per_s = 2.0 / (ms_step * 1e-3)
-    log(f"step {ms_step * 1e3:.2f} us ({steps} iterations in graphs of {args.iters_per_graph}, "
-        f"wall {wall:.3f} s)")
 
-    kd = kernel_durations(run, nat, min(args.steps, 200))
-    kd_avg_ms = float(kd.mean())
-    traffic = stored_traffic(sched)
-    flops = pass_flops(prob)
-    achieved = flops / (kd_avg_ms * 1e-3) / 1e12
-    log(f"fused pass: {kd.size} launches, mean {kd_avg_ms * 1e3:.2f} us, "
-        f"{achieved:.2f} TFLOP/s algorithmic")
-    cube_gbps = CUBE_BYTES_PER_CELL * cube_cells(prob) / (kd_avg_ms * 1e-3) / 1e9
-    cube_step_gbps = 2 * CUBE_BYTES_PER_CELL * cube_cells(prob) / (ms_step * 1e-3) / 1e9
+    # ---- the headline: one outer iteration of the uneven 512-problem batch per step
+    run = optim.SQNGD(probs, opt, seeds=seeds)
+    ms_step, wall, steps, per = time_graph(run, args.steps, args.warmup, 1)
+    evals = 2 * len(probs)
+    log(f"uneven x{len(probs)}: step {ms_step:.3f} ms ({steps} graph replays of one iteration, wall {wall:.3f} s)")
+    gdur = group_durations(run, nat, 2)
+    roof = roofline_of(probs, gdur, "uneven")
+    log(f"dominant pass {roof['kernel']}: {roof['kernel_us']:.1f} us, {roof['achieved']:.2f} TFLOP/s; groups "
+        + ", ".join(f"P={k}: {v:.0f} us" for k, v in roof["group_kernel_us"].items()))
+    del run
+    both = both_gradient_rate(probs, seeds)
+    log(f"both gradients: {both['ms_per_batch']:.2f} ms per batch evaluation")
+    cells = sum(cube_cells(p) for p in probs)
 
     extras = {}
     if not args.no_extras:
+        extras["m4n256_x1"] = single_design(I, nat, optim, "m4n256", 500, True)
+        extras["wide_m8n1024_x1"] = single_design(I, nat, optim, "wide_m8n1024", 50, False)
+        prob = I.config("m4n256")["problem"]
         R = 64
         runb = optim.SQNGD([prob] * R, opt, seeds=list(range(R)))
-        msb, _, _ = time_graph(runb, max(10, args.steps // 10), 5, args.iters_per_graph)
-        kdb = kernel_durations(runb, nat, 20)
-        extras["batched_restarts"] = {
-            "designs": R, "ms_per_step": msb, "evals_per_s": 2.0 * R / (msb * 1e-3),
-            "cube_equiv_frac_of_hbm": cube_frac(R * cube_cells(prob), 2, msb),
-            "pass_kernel_us": float(kdb.mean() * 1e3),
-            "pass_tflops": R * flops / (kdb.mean() * 1e-3) / 1e12}
-        log(f"batched x{R}: step {msb * 1e3:.1f} us, {extras['batched_restarts']['evals_per_s']:.0f} evals/s")
+        msb, _, _, _ = time_graph(runb, 20, 5, 1)
+        extras["m4n256_x64"] = {"designs": R, "ms_per_step": msb, "evals_per_s": 2.0 * R / (msb * 1e-3),
+                                "cube_equiv_frac_of_hbm": cube_frac(R * cube_cells(prob), 2, msb)}
+        log(f"m4n256 x{R}: step {msb * 1e3:.1f} us")
         del runb
-        # the other workloads: one wide-span design, the network's design size
-        # batched, and the uneven 64-design x 8-restart batch
-        for name, count in (("wide_m8n1024", 1), ("m4n512", 64)):
-            c = I.config(name)
-            r = optim.SQNGD([c["problem"]] * count, c["opt"], seeds=list(range(count)))
-            ms_c, _, _ = time_graph(r, 20, 10, 10)
-            extras[f"{name}_x{count}"] = {"ms_per_step": ms_c, "evals_per_s": 2.0 * count / (ms_c * 1e-3),
-                                          "cube_equiv_frac_of_hbm": cube_frac(count * cube_cells(c["problem"]),
-                                                                              2, ms_c),
-                                          "shape": {k: c["problem"][k] for k in ("M", "N", "L", "F")}}
-            log(f"{name} x{count}: step {ms_c * 1e3:.1f} us")
-            del r
-        designs = I.uneven_designs()
-        r = optim.SQNGD([p for p, _ in designs], I.config("m4n256")["opt"], seeds=[sd for _, sd in designs])
-        ms_c, _, _ = time_graph(r, 10, 10, 10)
-        extras["uneven_64x8"] = {"ms_per_step": ms_c, "evals_per_s": 2.0 * len(designs) / (ms_c * 1e-3),
-                                   "cube_equiv_frac_of_hbm": cube_frac(sum(cube_cells(p) for p, _ in designs),
-                                                                       2, ms_c),
-                                   "designs": 64, "restarts": 8}
-        log(f"uneven x{len(designs)}: step {ms_c * 1e3:.1f} us")
+        c = I.config("m4n512")
+        r = optim.SQNGD([c["problem"]] * 64, c["opt"], seeds=list(range(64)))
+        ms_c, _, _, _ = time_graph(r, 20, 5, 1)
+        extras["m4n512_x64"] = {"ms_per_step": ms_c, "evals_per_s": 2.0 * 64 / (ms_c * 1e-3),
+                                "cube_equiv_frac_of_hbm": cube_frac(64 * cube_cells(c["problem"]), 2, ms_c)}
+        log(f"m4n512 x64: step {ms_c * 1e3:.1f} us")
         del r
         # the paper's own shapes: N = 1200 (FFT length 4096), M = 2, B = 16 phase
         # levels, 129 Doppler bins in [-0.5, 0.5], the fixed ROI |tau| <= 50 as 0/1
-        # weights w(tau, f) (eq. 8-9), one design and 64 restarts
+        # weights w(tau, f) (eq. 8-9), one design and 64 restarts; and Table III's
+        # widest span, nu in [-600, 600] on the 1201-bin integer grid
         pp = I.make_problem(2, 1200, 16, 129, p=16.0)
         ww = I.roi_window_weights(pp, 50)
         for count in (1, 64):
             r = optim.SQNGD([pp] * count, opt, seeds=list(range(count)), roi_weights=[ww] * count)
-            ms_c, _, _ = time_graph(r, 20 if count == 1 else 10, 10, 10)
+            ms_c, _, _, _ = time_graph(r, 20 if count == 1 else 10, 5, 1)
             extras[f"paper_m2n1200_roi50_x{count}"] = {
                 "ms_per_step": ms_c, "evals_per_s": 2.0 * count / (ms_c * 1e-3),
                 "cube_equiv_frac_of_hbm": cube_frac(count * cube_cells(pp), 2, ms_c),
                 "shape": {"M": 2, "N": 1200, "L": 16, "F": 129, "roi": "|tau| <= 50 as weights"}}
             log(f"M=2 N=1200 |tau|<=50 x{count}: step {ms_c * 1e3:.1f} us")
             del r
+        pw = I.make_problem(2, 1200, 16, 1201, nu_min=-600.0, nu_max=600.0, p=16.0)
+        r = optim.SQNGD([pw], opt, seeds=[0], roi_weights=[I.roi_window_weights(pw, 50)])
+        ms_c, _, _, _ = time_graph(r, 10, 3, 1)
+        extras["paper_m2n1200_wide600_roi50_x1"] = {
+            "ms_per_step": ms_c, "evals_per_s": 2.0 / (ms_c * 1e-3),
+            "cube_equiv_frac_of_hbm": cube_frac(cube_cells(pw), 2, ms_c),
+            "shape": {"M": 2, "N": 1200, "L": 16, "F": 1201, "nu": [-600, 600], "roi": "|tau| <= 50 as weights"}}
+        log(f"M=2 N=1200 nu in [-600, 600] F=1201: step {ms_c:.3f} ms")
+        del r
         # the paper's own transmit side (ResNet + copied staircase, Sec. III-A) at
-        # its Table VI shape and settings: M=2 N=512 B=4, r_n=100, c=300,
-        # N_h = N_x = 10, eps = 0.1 (w_psl 0.1, w_snrl 0.9), SNRL target 0.5 dB,
-        # |tau| <= 50 as ROI weights, 129 Doppler bins in [-0.5, 0.5]
+        # its Table VI shape and settings
         extras.update(transmit_extras(I, torch))
         n = 1 << 28
         a = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -414,38 +583,40 @@ def main():
 
     out = {
         "metric": "AF loss+grad evals/s",
-        "value": evals_per_s,
+        "value": evals / (ms_step * 1e-3),
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "step_ms": spread(per),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "one SQNGD design, M=4 N=256 L=8 F=129 nu in [-0.5,0.5], all 511 "
-                               "delays, p=16, one filter + one logit update per step, HIP graphs of "
-                               f"{args.iters_per_graph} steps",
-                   "M": prob["M"], "N": prob["N"], "L": prob["L"], "F": prob["F"],
-                   "p": prob["p"], "evals_per_step": 2, "schedule": int(sched)},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic, "kernel": "k_pass_split (fused AF + loss + adjoint)",
-                     "kernel_us": kd_avg_ms * 1e3, "flops_per_launch": flops,
-                     "traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT) if traffic else None},
-        "cube_equivalent": {"GBps": cube_gbps, "frac_of_hbm": cube_gbps / HBM_PEAK_GBPS,
-                            "bytes_per_eval": CUBE_BYTES_PER_CELL * cube_cells(prob),
-                            "step_GBps": cube_step_gbps, "step_frac_of_hbm": cube_step_gbps / HBM_PEAK_GBPS},
+        "config": {"workload": "uneven batch: 64 designs x 8 random restarts (512 problems), N in {128, 256, "
+                               "512, 1024}, M in {2, 4, 8}, L in {4, 8, 16}, F=129 nu in [-0.5, 0.5], all delays, "
+                               "p=16; one outer iteration (filter step + logit step) per step, one HIP graph replay "
+                               "per step",
+                   "designs": 64, "restarts": 8, "problems": len(probs), "evals_per_step": evals,
+                   "eval_unit": "one loss + one gradient evaluation of one problem (grad_h in the filter step, "
+                                "grad_z in the logit step)"},
+        "roofline": roof,
+        "both_gradients": both,
+        "cube_equivalent": {"bytes_per_eval_batch": CUBE_BYTES_PER_CELL * cells,
+                            "step_GBps": 2 * CUBE_BYTES_PER_CELL * cells / (ms_step * 1e-3) / 1e9,
+                            "step_frac_of_hbm": cube_frac(cells, 2, ms_step)},
     }
     if extras:
         out["extras"] = extras
     if not args.no_cpu_baseline:
-        out["cpu_fft_route"] = cpu_fft_route(prob, min(10.0, args.cpu_seconds))
-        log(f"cpu FFT route: {out['cpu_fft_route']['value']:.1f} evals/s on {out['cpu_fft_route']['cores']} cores")
-        out["cpu_baseline"] = cpu_baseline(prob, opt, args.cpu_seconds)
-        log(f"cpu baseline: {out['cpu_baseline']['value']:.3f} evals/s on {out['cpu_baseline']['cores']} cores")
+        out["cpu_baseline"] = cpu_baseline(designs, opt, args.cpu_seconds)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.4f} evals/s on {out['cpu_baseline']['cores']} cores")
+        out["cpu_baseline"]["single_thread"] = cpu_single_thread(designs, opt, 0.25 * args.cpu_seconds)
+        prob = I.config("m4n256")["problem"]
+        out["cpu_fft_route_m4n256"] = cpu_fft_route(prob, min(5.0, args.cpu_seconds))
+        log(f"cpu FFT route (M=4 N=256): {out['cpu_fft_route_m4n256']['value']:.1f} evals/s")
     print(json.dumps(out), flush=True)
 
 

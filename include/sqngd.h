@@ -55,12 +55,14 @@
  * caller; problem descriptors and options are HOST pointers read during the
  * call. The library never allocates device memory. Scratch lives in the
  * caller's workspace (size from sqngd_workspace_size, 256-byte aligned), which
- * sqngd_workspace_init prepares once per batch: it uploads the batch plan
+ * sqngd_workspace_init prepares once per batch: it writes the batch plan
  * (problem descriptors, buffer offsets, work tables) into the workspace with
- * one host-to-device copy from a host buffer the library keeps until the
- * process ends. Every later call checks on the host that it names the same
- * batch as the last initialisation of that workspace, and the caller must not
- * write into the workspace meanwhile. Calls only enqueue work on `stream` (a
+ * small kernels that carry it in their arguments, and keeps a host copy of
+ * the plan per workspace until the workspace is initialised again or
+ * released (sqngd_workspace_release). Every later call checks on the host
+ * that it names the same batch (the same descriptors) as the last
+ * initialisation of that workspace, and the caller must not write into the
+ * workspace meanwhile. Calls only enqueue work on `stream` (a
  * hipStream_t passed as void*; NULL is the null stream), are asynchronous and
  * stream-ordered, and issue no memset, so after the initialisation they can be
  * captured in a HIP graph. Two calls that share a workspace must not overlap.
@@ -191,11 +193,19 @@ int sqngd_buffer_sizes(const sqngd_problem* probs, int32_t nprob, int64_t* z_flo
 int sqngd_workspace_size(const sqngd_problem* probs, int32_t nprob, size_t* bytes);
 
 /* Prepares ws for this batch (see Ownership and memory): enqueues the upload
-   of the batch plan and the reset of the step bookkeeping on stream. Required
-   before any other call that takes this workspace, and again after the batch
-   changes. */
+   of the batch plan and the reset of the step bookkeeping on stream (small
+   kernels that carry the plan in their arguments, so the library keeps no
+   host buffer alive for the copy). Required before any other call that takes
+   this workspace, and again after the batch changes; the library's host copy
+   of the workspace's previous plan is freed. */
 int sqngd_workspace_init(const sqngd_problem* probs, int32_t nprob, void* ws, size_t ws_bytes,
                          void* stream);
+
+/* Forgets the batch plan recorded for ws (its host copy is freed); later calls
+   with ws return SQNGD_E_WORKSPACE until it is initialised again. Call it
+   before the workspace's memory is freed or reused. Returns SQNGD_OK, or
+   SQNGD_E_INVALID_ARG if ws holds no plan. Touches no device memory. */
+int sqngd_workspace_release(const void* ws);
 
 /* Attaches the weights w(tau, f) of eq. 8-9 (Algorithm 1's ROI weights) to
    the workspace initialised for this batch. weights is a DEVICE array of
@@ -212,6 +222,35 @@ int sqngd_workspace_init(const sqngd_problem* probs, int32_t nprob, void* ws, si
    (SQNGD_E_INVALID_ARG, SQNGD_E_WORKSPACE). */
 int sqngd_set_roi_weights(const sqngd_problem* probs, int32_t nprob, const float* weights, void* ws,
                           size_t ws_bytes);
+
+/* The stopping criterion of Algorithm 1 (Sec. III-C: a run ends when lowering
+   the loss no longer improves the WPSL of the hard-quantised design, or after
+   T outer iterations), kept on the device so that a captured graph can apply
+   it without a host round trip.
+
+   sqngd_set_stop_mask attaches a DEVICE array stopped[nprob] (int32) to the
+   workspace initialised for this batch (NULL detaches it): every later
+   optimiser step (sqngd_step / sqngd_run) leaves the parameters and Adam
+   state of a problem with stopped[i] != 0 unchanged, as for a non-finite
+   evaluation. The pointer is read when each call enqueues its kernels (a
+   graph captured earlier keeps the one it was captured with); the caller
+   keeps the array alive. Returns SQNGD_OK, SQNGD_E_ALIGN or the lookup errors.
+
+   sqngd_stop_update applies one checkpoint to every problem not yet stopped
+   (one thread each): w = stats[i].pslr_db, the hard-waveform WPSL in dB (from
+   sqngd_af_forward in mode HARD); if w < best_db[i] - min_gain_db then
+   best_db[i] = w and stall[i] = 0, else stall[i] += 1 and, once
+   stall[i] >= patience, stopped[i] = 1 and stop_iter[i] = *step_counter (the
+   outer iterations done; 0 if step_counter is NULL). The caller initialises
+   best_db to +inf and stall, stopped to 0. All arrays are DEVICE arrays of
+   nprob entries owned by the caller. Returns SQNGD_OK, SQNGD_E_INVALID_ARG
+   (nprob < 1, patience < 1, NULL arrays, non-finite min_gain_db) or
+   SQNGD_E_ALIGN. */
+int sqngd_set_stop_mask(const sqngd_problem* probs, int32_t nprob, const int32_t* stopped, void* ws,
+                        size_t ws_bytes);
+int sqngd_stop_update(int32_t nprob, const sqngd_stats* stats, float min_gain_db, int32_t patience,
+                      const int32_t* step_counter, float* best_db, int32_t* stall, int32_t* stopped,
+                      int32_t* stop_iter, void* stream);
 
 /* Loss and statistics of one evaluation (Sec. III-B: eq. 33-36 for the AF,
    eq. 37-42 for the loss, eq. 48 for PSLR).

@@ -123,9 +123,13 @@ struct Plan {
   int maxN = 0;
   bool split = false;  // the fused pass runs as k_pass_split (small batches)
   uint64_t hash = 0;
+  std::vector<sqngd_problem> src;  // the descriptors the plan was built from
   // ROI weights attached by sqngd_set_roi_weights (device, packed per
   // problem), or null for w = 1; read when a pass is enqueued
   mutable const float* roi_w = nullptr;
+  // per-problem stop mask attached by sqngd_set_stop_mask (device), or null;
+  // read when an optimiser step is enqueued
+  mutable const int32_t* frozen = nullptr;
 };
 
 uint64_t fnv1a(const void* data, size_t n) {
@@ -346,14 +350,16 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
   std::memcpy(b + H.row_prob, rp.data(), 4 * rp.size());
   std::memcpy(b, &H, sizeof(WsHeader));
   pl->hash = fnv1a(b, table_bytes);
+  pl->src.assign(probs, probs + nprob);
   return pl;
 }
 
-// Workspace registry: which batch each workspace was last initialised for.
-// Plans are never freed, so an upload still in flight always reads live memory.
+// Workspace registry: the plan each workspace was last initialised for. The
+// device copy of a plan is written through kernel arguments (put_plan), so no
+// host buffer has to outlive the call that uploads it: re-initialising a
+// workspace frees its previous plan, and sqngd_workspace_release drops it.
 std::mutex g_mu;
-std::vector<std::unique_ptr<Plan>> g_keep;
-std::unordered_map<const void*, Plan*> g_ws;
+std::unordered_map<const void*, std::unique_ptr<Plan>> g_ws;
 
 int hip_fail(hipError_t e) {
   g_last_hip.store((int)e);
@@ -365,22 +371,54 @@ int check_launch() {
   return e == hipSuccess ? SQNGD_OK : hip_fail(e);
 }
 
+// Bytes carried by value in a kernel's arguments: the runtime copies the
+// arguments at launch, so the host buffer they came from may go away at once
+// (no host-memory lifetime to track, no copy engine, nothing allocated).
+constexpr int kPutWords = 960;
+struct PutArgs {
+  uint32_t* dst;
+  int32_t nwords, pad;
+  uint32_t w[kPutWords];
+};
+static_assert(sizeof(PutArgs) <= 4096, "kernel argument limit");
+
+__global__ __launch_bounds__(256) void k_put_words(PutArgs a) {
+  for (int i = threadIdx.x; i < a.nwords; i += 256) a.dst[i] = a.w[i];
+}
+
+// Writes the plan's table bytes (header, problem plans, work tables, zeroed
+// counters) to the start of the workspace `dst` on `s`.
+int put_plan(const Plan& pl, void* dst, hipStream_t s) {
+  const size_t nb = pl.bytes.size();  // a multiple of the 256-byte alignment
+  const uint32_t* src = (const uint32_t*)pl.bytes.data();
+  const size_t nw = nb / 4;
+  for (size_t off = 0; off < nw; off += kPutWords) {
+    PutArgs a;
+    a.dst = (uint32_t*)dst + off;
+    a.nwords = (int32_t)std::min<size_t>(kPutWords, nw - off);
+    a.pad = 0;
+    std::memcpy(a.w, src + off, 4 * (size_t)a.nwords);
+    hipLaunchKernelGGL(k_put_words, dim3(1), dim3(256), 0, s, a);
+  }
+  return check_launch();
+}
+
 // Validates the batch and the workspace; on success *out is the plan the
-// workspace holds.
+// workspace holds. The descriptors are compared with the ones the workspace
+// was initialised with (no plan is rebuilt per call).
 int lookup(const sqngd_problem* probs, int32_t nprob, void* ws, size_t ws_bytes, const Plan** out) {
   int rc = validate_batch(probs, nprob);
   if (rc != SQNGD_OK) return rc;
   if (ws == nullptr) return SQNGD_E_INVALID_ARG;
   if (!aligned(ws, kAlign)) return SQNGD_E_ALIGN;
-  auto fresh = build_plan(probs, nprob);
-  if (ws_bytes < (size_t)fresh->hdr.total) return SQNGD_E_WORKSPACE;
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_ws.find(ws);
-  if (it == g_ws.end() || it->second->hash != fresh->hash ||
-      it->second->bytes.size() != fresh->bytes.size() ||
-      std::memcmp(it->second->bytes.data(), fresh->bytes.data(), fresh->bytes.size()) != 0)
+  if (it == g_ws.end()) return SQNGD_E_WORKSPACE;
+  const Plan& pl = *it->second;
+  if (pl.src.size() != (size_t)nprob || std::memcmp(pl.src.data(), probs, sizeof(sqngd_problem) * nprob) != 0)
     return SQNGD_E_WORKSPACE;
-  *out = it->second;
+  if (ws_bytes < (size_t)pl.hdr.total) return SQNGD_E_WORKSPACE;
+  *out = &pl;
   return SQNGD_OK;
 }
 
@@ -590,6 +628,7 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
   a.done = w.counters;
   a.gbuf = w.gbuf;
   a.pflag = w.pflag;
+  a.frozen = (a.mode == FIN_STEP_A || a.mode == FIN_STEP_B) ? pl.frozen : nullptr;
   a.single = pl.hdr.nprob == 1;
   a.one = pl.plans[0];
   for (int g = 0; g < kNumPGroups; ++g) {
@@ -736,6 +775,31 @@ int sqngd_set_roi_weights(const sqngd_problem* probs, int32_t nprob, const float
   return SQNGD_OK;
 }
 
+int sqngd_set_stop_mask(const sqngd_problem* probs, int32_t nprob, const int32_t* stopped, void* ws,
+                        size_t ws_bytes) {
+  if (!aligned(stopped, 4)) return SQNGD_E_ALIGN;
+  const Plan* pl = nullptr;
+  int rc = lookup(probs, nprob, ws, ws_bytes, &pl);
+  if (rc != SQNGD_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  pl->frozen = stopped;
+  return SQNGD_OK;
+}
+
+int sqngd_stop_update(int32_t nprob, const sqngd_stats* stats, float min_gain_db, int32_t patience,
+                      const int32_t* step_counter, float* best_db, int32_t* stall, int32_t* stopped,
+                      int32_t* stop_iter, void* stream) {
+  if (nprob < 1 || nprob > (1 << 20) || patience < 1 || !finite(min_gain_db)) return SQNGD_E_INVALID_ARG;
+  if (stats == nullptr || best_db == nullptr || stall == nullptr || stopped == nullptr || stop_iter == nullptr)
+    return SQNGD_E_INVALID_ARG;
+  if (!aligned(stats, 4) || !aligned(step_counter, 4) || !aligned(best_db, 4) || !aligned(stall, 4) ||
+      !aligned(stopped, 4) || !aligned(stop_iter, 4))
+    return SQNGD_E_ALIGN;
+  hipLaunchKernelGGL(k_stop, dim3((nprob + 255) / 256), dim3(256), 0, (hipStream_t)stream, nprob, stats,
+                     min_gain_db, patience, step_counter, best_db, stall, stopped, stop_iter);
+  return check_launch();
+}
+
 int sqngd_workspace_init(const sqngd_problem* probs, int32_t nprob, void* ws, size_t ws_bytes, void* stream) {
   int rc = validate_batch(probs, nprob);
   if (rc != SQNGD_OK) return rc;
@@ -743,16 +807,16 @@ int sqngd_workspace_init(const sqngd_problem* probs, int32_t nprob, void* ws, si
   if (!aligned(ws, kAlign)) return SQNGD_E_ALIGN;
   auto pl = build_plan(probs, nprob);
   if (ws_bytes < (size_t)pl->hdr.total) return SQNGD_E_WORKSPACE;
-  hipStream_t s = (hipStream_t)stream;
-  Plan* raw = pl.get();
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_keep.push_back(std::move(pl));
-    g_ws[ws] = raw;
-  }
-  hipError_t e = hipMemcpyAsync(ws, raw->bytes.data(), raw->bytes.size(), hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return hip_fail(e);
+  rc = put_plan(*pl, ws, (hipStream_t)stream);
+  if (rc != SQNGD_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_ws[ws] = std::move(pl);  // frees the plan this workspace held before
   return SQNGD_OK;
+}
+
+int sqngd_workspace_release(const void* ws) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_ws.erase(ws) == 1 ? SQNGD_OK : SQNGD_E_INVALID_ARG;
 }
 
 int sqngd_af_forward(const sqngd_problem* probs, int32_t nprob, const float* z, int32_t wave_mode,
@@ -1061,38 +1125,6 @@ int scratch_address(void** out) {
   }
   *out = g_scratch[dev];
   return SQNGD_OK;
-}
-
-// Bytes carried by value in a kernel's arguments: the runtime copies the
-// arguments at launch, so the host buffer they came from may go away at once
-// (no host-memory lifetime to track, no copy engine, nothing allocated).
-constexpr int kPutWords = 960;
-struct PutArgs {
-  uint32_t* dst;
-  int32_t nwords, pad;
-  uint32_t w[kPutWords];
-};
-static_assert(sizeof(PutArgs) <= 4096, "kernel argument limit");
-
-__global__ __launch_bounds__(256) void k_put_words(PutArgs a) {
-  for (int i = threadIdx.x; i < a.nwords; i += 256) a.dst[i] = a.w[i];
-}
-
-// Writes the plan's table bytes (header, problem plans, work tables, zeroed
-// counters) to the start of `dst` on `s`.
-int put_plan(const Plan& pl, void* dst, hipStream_t s) {
-  const size_t nb = pl.bytes.size();  // a multiple of the 256-byte alignment
-  const uint32_t* src = (const uint32_t*)pl.bytes.data();
-  const size_t nw = nb / 4;
-  for (size_t off = 0; off < nw; off += kPutWords) {
-    PutArgs a;
-    a.dst = (uint32_t*)dst + off;
-    a.nwords = (int32_t)std::min<size_t>(kPutWords, nw - off);
-    a.pad = 0;
-    std::memcpy(a.w, src + off, 4 * (size_t)a.nwords);
-    hipLaunchKernelGGL(k_put_words, dim3(1), dim3(256), 0, s, a);
-  }
-  return check_launch();
 }
 
 }  // namespace

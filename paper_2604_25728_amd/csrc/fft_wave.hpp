@@ -176,10 +176,24 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // ------------------------------------------------------------------ geometry
 
-template <int P_, int TF_>
+// Exchange buffers carry one float2 of padding after every 2^PS elements:
+// element i of an FFT's buffer lives at G::ix(i) = i + (i >> PS). The
+// exchanges read with lane strides of 8 or 16 elements across rows of TF
+// elements; unpadded, a wave's 64 lanes then fall on 4 to 16 times fewer LDS
+// banks than they span (up to 16-way conflicts at P = 2048), padded every
+// 16 elements (PS = 4) they spread over all banks. A kernel short of LDS may
+// pad every 32 (PS = 5: the second exchange's reads become conflict-free,
+// the first keeps part of its conflicts). The padding changes no layout
+// outside the exchange buffer. Every exchange access is a lane-dependent
+// part plus a compile-time part whose low PS bits never carry into the lane
+// part's, so G::ix(lane + c) = G::ix(lane) + G::ix(c): the stages form one
+// padded base pointer per lane and address from it with immediate offsets.
+
+template <int P_, int TF_, int PS_ = 4>
 struct GeomT {
   static constexpr int P = P_;
   static constexpr int TF = TF_;                     // lanes per FFT
+  static constexpr int PS = PS_;                     // exchange-buffer padding: one float2 per 2^PS
   static constexpr int E = P / TF;                   // elements per lane
   static constexpr int A = TF >= 32 ? 8 : 4;
   // The length-TF DFT over the lanes runs as radix-A then radix-B stages
@@ -191,7 +205,9 @@ struct GeomT {
   static constexpr int BC = B * C;
   static constexpr int SLOTS = TF <= 64 ? 64 / TF : 1;  // FFTs per wave
   static constexpr int WAVES = TF > 64 ? TF / 64 : 1;   // waves per FFT
-  static constexpr int LDS = 64 * E;                 // float2 per wave
+  static constexpr int SPAN = P + (P >> PS);        // float2 of one FFT's padded exchange buffer
+  static constexpr int LDS = SLOTS * SPAN;           // float2 of a wave's exchange buffers (wave-local)
+  __host__ __device__ static constexpr int ix(int i) { return i + (i >> PS); }
   static_assert(A * B * C == TF, "the lane radices factor TF");
   static_assert(E % A == 0 && E % B == 0 && E % C == 0, "register blocks must tile E");
   static_assert(TF <= 64 ? 64 % TF == 0 : TF % 64 == 0, "an FFT fills whole waves or divides one");
@@ -324,18 +340,20 @@ __device__ __forceinline__ void fft3_forward(float2 (&x)[G::E], float2* buf, int
     x[k1] = W.template step2<k1>(x[k1], false);
   });
   fft_sync<G>();
+  float2* const bt = buf + G::ix(t);
   static_for<E>([&](auto kc) {
     constexpr int k1 = decltype(kc)::value;
-    buf[k1 * TF + t] = x[k1];
+    bt[G::ix(k1 * TF)] = x[k1];
   });
   fft_sync<G>();
   {  // radix A over alpha: lane (q, tau), k1 = j A + q
     const int tau = t % BC, q = t / BC;
+    float2* const bq = buf + G::ix(q * TF + tau);
     static_for<E / A>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
       static_for<A>([&](auto ac) {
         constexpr int al = decltype(ac)::value;
-        x[j * A + al] = buf[(j * A + q) * TF + BC * al + tau];
+        x[j * A + al] = bq[G::ix(j * A * TF + BC * al)];
       });
       dft_reg<A, -1, j * A>(x);
       static_for<A>([&](auto gc) {
@@ -348,19 +366,19 @@ __device__ __forceinline__ void fft3_forward(float2 (&x)[G::E], float2* buf, int
       constexpr int j = decltype(jc)::value;
       static_for<A>([&](auto gc) {
         constexpr int g = decltype(gc)::value;
-        buf[(j * A + q) * TF + g * BC + tau] = x[j * A + g];
+        bq[G::ix(j * A * TF + g * BC)] = x[j * A + g];
       });
     });
     fft_sync<G>();
   }
   {  // radix B over beta: lane (q2, gamma, c), k1 = j2 B + q2
     const int q2 = t / (A * C), gamma = (t % (A * C)) / C, c = t % C;
+    float2* const bq2 = buf + G::ix(q2 * TF + gamma * BC + c);
     static_for<E / B>([&](auto jc) {
       constexpr int j2 = decltype(jc)::value;
-      const int k1 = j2 * B + q2;
       static_for<B>([&](auto bc) {
         constexpr int be = decltype(bc)::value;
-        x[j2 * B + be] = buf[k1 * TF + gamma * BC + C * be + c];
+        x[j2 * B + be] = bq2[G::ix(j2 * B * TF + C * be)];
       });
       dft_reg<B, -1, j2 * B>(x);
       static_for<B>([&](auto zc) {
@@ -371,22 +389,21 @@ __device__ __forceinline__ void fft3_forward(float2 (&x)[G::E], float2* buf, int
     fft_sync<G>();
     static_for<E / B>([&](auto jc) {
       constexpr int j2 = decltype(jc)::value;
-      const int k1 = j2 * B + q2;
       static_for<B>([&](auto zc) {
         constexpr int z = decltype(zc)::value;
-        buf[k1 * TF + gamma * BC + z * C + c] = x[j2 * B + z];
+        bq2[G::ix(j2 * B * TF + z * C)] = x[j2 * B + z];
       });
     });
     fft_sync<G>();
   }
   {  // radix C over c: lane (q3, gamma, zeta), k1 = j3 C + q3
     const int q3 = t / (A * B), gamma = (t % (A * B)) / B, zeta = t % B;
+    float2* const bq3 = buf + G::ix(q3 * TF + gamma * BC + zeta * C);
     static_for<E / C>([&](auto jc) {
       constexpr int j3 = decltype(jc)::value;
-      const int k1 = j3 * C + q3;
       static_for<C>([&](auto cc) {
         constexpr int ci = decltype(cc)::value;
-        x[j3 * C + ci] = buf[k1 * TF + gamma * BC + zeta * C + ci];
+        x[j3 * C + ci] = bq3[G::ix(j3 * C * TF + ci)];
       });
       dft_reg<C, -1, j3 * C>(x);
     });
@@ -398,6 +415,7 @@ __device__ __forceinline__ void fft3_inverse(float2 (&x)[G::E], float2* buf, int
   constexpr int E = G::E, TF = G::TF, A = G::A, B = G::B, C = G::C, BC = G::BC;
   {  // radix C over eta -> c
     const int q3 = t / (A * B), gamma = (t % (A * B)) / B, zeta = t % B;
+    float2* const bq3 = buf + G::ix(q3 * TF + gamma * BC + zeta * C);
     static_for<E / C>([&](auto jc) {
       constexpr int j3 = decltype(jc)::value;
       dft_reg<C, +1, j3 * C>(x);
@@ -405,22 +423,21 @@ __device__ __forceinline__ void fft3_inverse(float2 (&x)[G::E], float2* buf, int
     fft_sync<G>();
     static_for<E / C>([&](auto jc) {
       constexpr int j3 = decltype(jc)::value;
-      const int k1 = j3 * C + q3;
       static_for<C>([&](auto cc) {
         constexpr int ci = decltype(cc)::value;
-        buf[k1 * TF + gamma * BC + zeta * C + ci] = x[j3 * C + ci];
+        bq3[G::ix(j3 * C * TF + ci)] = x[j3 * C + ci];
       });
     });
     fft_sync<G>();
   }
   {  // radix B over zeta -> beta
     const int q2 = t / (A * C), gamma = (t % (A * C)) / C, c = t % C;
+    float2* const bq2 = buf + G::ix(q2 * TF + gamma * BC + c);
     static_for<E / B>([&](auto jc) {
       constexpr int j2 = decltype(jc)::value;
-      const int k1 = j2 * B + q2;
       static_for<B>([&](auto zc) {
         constexpr int z = decltype(zc)::value;
-        float2 v = buf[k1 * TF + gamma * BC + z * C + c];
+        float2 v = bq2[G::ix(j2 * B * TF + z * C)];
         if constexpr (z > 0) v = cmulc(v, W.col2[z]);
         x[j2 * B + z] = v;
       });
@@ -429,21 +446,21 @@ __device__ __forceinline__ void fft3_inverse(float2 (&x)[G::E], float2* buf, int
     fft_sync<G>();
     static_for<E / B>([&](auto jc) {
       constexpr int j2 = decltype(jc)::value;
-      const int k1 = j2 * B + q2;
       static_for<B>([&](auto bc) {
         constexpr int be = decltype(bc)::value;
-        buf[k1 * TF + gamma * BC + C * be + c] = x[j2 * B + be];
+        bq2[G::ix(j2 * B * TF + C * be)] = x[j2 * B + be];
       });
     });
     fft_sync<G>();
   }
   {  // radix A over gamma -> alpha
     const int tau = t % BC, q = t / BC;
+    float2* const bq = buf + G::ix(q * TF + tau);
     static_for<E / A>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
       static_for<A>([&](auto gc) {
         constexpr int g = decltype(gc)::value;
-        float2 v = buf[(j * A + q) * TF + g * BC + tau];
+        float2 v = bq[G::ix(j * A * TF + g * BC)];
         if constexpr (g > 0) v = cmulc(v, W.col[g]);
         x[j * A + g] = v;
       });
@@ -454,14 +471,15 @@ __device__ __forceinline__ void fft3_inverse(float2 (&x)[G::E], float2* buf, int
       constexpr int j = decltype(jc)::value;
       static_for<A>([&](auto ac) {
         constexpr int al = decltype(ac)::value;
-        buf[(j * A + q) * TF + BC * al + tau] = x[j * A + al];
+        bq[G::ix(j * A * TF + BC * al)] = x[j * A + al];
       });
     });
     fft_sync<G>();
   }
+  float2* const bt = buf + G::ix(t);
   static_for<E>([&](auto kc) {
     constexpr int k1 = decltype(kc)::value;
-    x[k1] = W.template step2<k1>(buf[k1 * TF + t], true);
+    x[k1] = W.template step2<k1>(bt[G::ix(k1 * TF)], true);
   });
   dft_reg<E, +1, 0>(x);
 }
@@ -479,17 +497,19 @@ __device__ __forceinline__ void fft2_forward(float2 (&x)[G::E], float2* buf, int
   });
   // exchange 1: [k1][n2]
   fft_sync<G>();
+  float2* const bt = buf + G::ix(t);
   static_for<E>([&](auto kc) {
     constexpr int k1 = decltype(kc)::value;
-    buf[k1 * TF + t] = x[k1];
+    bt[G::ix(k1 * TF)] = x[k1];
   });
   fft_sync<G>();
   const int beta = t % B, q = t / B;
+  float2* const bq = buf + G::ix(q * TF + beta);
   static_for<E / A>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
     static_for<A>([&](auto ac) {
       constexpr int al = decltype(ac)::value;
-      x[j * A + al] = buf[(j * A + q) * TF + B * al + beta];
+      x[j * A + al] = bq[G::ix(j * A * TF + B * al)];
     });
     dft_reg<A, -1, j * A>(x);
     static_for<A>([&](auto gc) {
@@ -503,16 +523,17 @@ __device__ __forceinline__ void fft2_forward(float2 (&x)[G::E], float2* buf, int
     constexpr int j = decltype(jc)::value;
     static_for<A>([&](auto gc) {
       constexpr int g = decltype(gc)::value;
-      buf[(j * A + q) * TF + g * B + beta] = x[j * A + g];
+      bq[G::ix(j * A * TF + g * B)] = x[j * A + g];
     });
   });
   fft_sync<G>();
   const int gamma = t % A, q2 = t / A;
+  float2* const bq2 = buf + G::ix(q2 * TF + gamma * B);
   static_for<E / B>([&](auto jc) {
     constexpr int j2 = decltype(jc)::value;
     static_for<B>([&](auto bc) {
       constexpr int be = decltype(bc)::value;
-      x[j2 * B + be] = buf[(j2 * B + q2) * TF + gamma * B + be];
+      x[j2 * B + be] = bq2[G::ix(j2 * B * TF + be)];
     });
     dft_reg<B, -1, j2 * B>(x);
   });
@@ -524,6 +545,7 @@ template <class G>
 __device__ __forceinline__ void fft2_inverse(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
   constexpr int E = G::E, TF = G::TF, A = G::A, B = G::B;
   const int gamma = t % A, q2 = t / A;
+  float2* const bq2 = buf + G::ix(q2 * TF + gamma * B);
   static_for<E / B>([&](auto jc) {
     constexpr int j2 = decltype(jc)::value;
     dft_reg<B, +1, j2 * B>(x);
@@ -533,16 +555,17 @@ __device__ __forceinline__ void fft2_inverse(float2 (&x)[G::E], float2* buf, int
     constexpr int j2 = decltype(jc)::value;
     static_for<B>([&](auto bc) {
       constexpr int be = decltype(bc)::value;
-      buf[(j2 * B + q2) * TF + gamma * B + be] = x[j2 * B + be];
+      bq2[G::ix(j2 * B * TF + be)] = x[j2 * B + be];
     });
   });
   fft_sync<G>();
   const int beta = t % B, q = t / B;
+  float2* const bq = buf + G::ix(q * TF + beta);
   static_for<E / A>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
     static_for<A>([&](auto gc) {
       constexpr int g = decltype(gc)::value;
-      float2 v = buf[(j * A + q) * TF + g * B + beta];
+      float2 v = bq[G::ix(j * A * TF + g * B)];
       if constexpr (g > 0) v = cmulc(v, W.col[g]);
       x[j * A + g] = v;
     });
@@ -553,13 +576,14 @@ __device__ __forceinline__ void fft2_inverse(float2 (&x)[G::E], float2* buf, int
     constexpr int j = decltype(jc)::value;
     static_for<A>([&](auto ac) {
       constexpr int al = decltype(ac)::value;
-      buf[(j * A + q) * TF + B * al + beta] = x[j * A + al];
+      bq[G::ix(j * A * TF + B * al)] = x[j * A + al];
     });
   });
   fft_sync<G>();
+  float2* const bt = buf + G::ix(t);
   static_for<E>([&](auto kc) {
     constexpr int k1 = decltype(kc)::value;
-    x[k1] = W.template step2<k1>(buf[k1 * TF + t], true);
+    x[k1] = W.template step2<k1>(bt[G::ix(k1 * TF)], true);
   });
   dft_reg<E, +1, 0>(x);
 }

@@ -242,20 +242,26 @@ __device__ __forceinline__ int find_entry(const int32_t* base, int n, int wave) 
   return lo;
 }
 
-// Waves per block of the throughput pass: four at P <= 512, two at 1024 and
-// 2048 (whose per-wave LDS slices would otherwise allow one block per CU),
-// eight at 4096 (all eight share one unit).
-__host__ __device__ constexpr int pass_waves(int P) { return P >= 4096 ? 8 : (P >= 1024 ? 2 : 4); }
-// FFT geometry of the throughput pass: wave-local up to P = 1024; at P = 2048
-// one transform spans the block's two waves (16 elements per lane instead of
-// 32), which keeps the pass's three spectra in registers without spilling;
-// at P = 4096 it spans eight waves (8 elements per lane, three exchanges:
-// 190 VGPRs, against 256 plus spills with four waves and 16 per lane).
+// Waves per block of the throughput pass: four at P <= 512, two at 1024, four
+// at 2048 and eight at 4096 (every wave of a block shares one unit from
+// P = 1024 on).
+__host__ __device__ constexpr int pass_waves(int P) { return P >= 4096 ? 8 : (P >= 2048 ? 4 : (P >= 1024 ? 2 : 4)); }
+// FFT geometry of the throughput pass: wave-local up to P = 512; from 1024
+// on one transform spans the block's waves with 8 elements per lane (128
+// lanes at 1024, 256 at 2048, 512 at 4096; three LDS exchanges). With the
+// exchange buffers padded against bank conflicts this runs three waves per
+// SIMD at P = 1024 and 2048 (168 VGPRs; 250 with one wave and 16 elements
+// per lane held only two), measured 23% faster per pass on both.
 __host__ __device__ constexpr int pass_tf(int P) {
-  return P >= 4096 ? 512 : (P >= 2048 ? 128 : (P >= 512 ? 64 : P / 8));
+  return P >= 4096 ? 512 : (P >= 2048 ? 256 : (P >= 1024 ? 128 : (P >= 512 ? 64 : P / 8)));
 }
 template <int P>
 using PassGeom = GeomT<P, pass_tf(P)>;
+// Waves per SIMD the throughput pass is compiled for: three at P = 1024 and
+// 2048 (the register budget of 168 per lane; the compiler keeps a few values
+// in scratch at 2048). The weighted instantiations keep their registers and
+// run two.
+__host__ __device__ constexpr int pass_min_waves(int P) { return P == 1024 || P == 2048 ? 3 : 1; }
 // Doppler bins (units) per throughput-pass block
 __host__ __device__ constexpr int pass_upb(int P) { return pass_waves(P) * 64 / pass_tf(P); }
 // Where a producer's spectral bin k lands in the partner-spectrum rows the
@@ -323,7 +329,7 @@ template <int P>
 __global__ __launch_bounds__(64 * PassGeom<P>::WAVES) void k_rowspec(RowSpecArgs a) {
   using G = PassGeom<P>;
   constexpr int E = G::E, TF = G::TF;
-  __shared__ float2 buf[P];
+  __shared__ float2 buf[G::SPAN];
   int r, pid;
   ProbPlan pl;
   if (a.single) {
@@ -460,7 +466,7 @@ __global__ __launch_bounds__(64) void k_prep(PrepArgs a) {
   if constexpr (!spec_by_rowspec(P)) {
     WaveTwiddles<P> W;
     W.init(t);
-    fft_forward<P>(X, lds + slot * P, t, W);
+    fft_forward<P>(X, lds + slot * G::SPAN, t, W);
     if (active) {
       float2* sp = a.spec + pl.ws_spec + (int64_t)g * P;
       static_for<E>([&](auto ec) {
@@ -496,13 +502,13 @@ struct PassArgs {
 // WT: the launch carries ROI weights (a separate instantiation, so that the
 // unweighted pass keeps its registers).
 template <int P, int PHLOG, bool WT>
-__global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
+__global__ __launch_bounds__(64 * pass_waves(P), WT ? 1 : pass_min_waves(P)) void k_pass(PassArgs a) {
   using G = PassGeom<P>;
   constexpr int kPassWaves = pass_waves(P);
   constexpr int E = G::E, TF = G::TF, EH = E / 2;
   constexpr int UPB = pass_upb(P);  // units (Doppler bins of one row) per block
   static_assert(UPB * TF == 64 * kPassWaves, "the units fill the block");
-  __shared__ float2 lds[UPB * P];
+  __shared__ float2 lds[UPB * G::SPAN];
   // The accumulated adjoint spectra U and the self spectrum X live in the
   // slot's LDS slice instead of registers: three E-element arrays per lane
   // plus the partner spectrum would cap the occupancy (two waves per SIMD at
@@ -518,7 +524,7 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
   // uslot: the block's unit this lane works on; t: its lane within the FFT
   const int uslot = threadIdx.x / TF, t = threadIdx.x % TF;
   if (a.bump != nullptr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.bump, 1);
-  float2* buf = lds + uslot * P;
+  float2* buf = lds + uslot * G::SPAN;
   int base = 0;
   ProbPlan pl;
   if (a.single) {
@@ -731,7 +737,7 @@ __global__ __launch_bounds__(64 * pass_waves(P)) void k_pass(PassArgs a) {
       float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
       for (int j = 0; j < UPB; ++j) {
-        const float2 v = lds[j * P + n];
+        const float2 v = lds[j * G::SPAN + n];
         acc.x += fac[j] * v.x;
         acc.y += fac[j] * v.y;
       }
@@ -814,6 +820,7 @@ struct FinArgs {
   float2* gbuf;         // gradient rows (k_grad -> k_step)
   const float2* grad_in;  // k_final: gradient rows already reduced by k_grad (skips the partial sums)
   int32_t* pflag;       // per problem: the loss is not finite (k_grad -> k_step)
+  const int32_t* frozen;  // per problem, optimiser steps: nonzero keeps the parameters (stopped design), or null
   int32_t grad_chunks;  // k_grad blocks per row
   int32_t grad_nprob;   // problems of the launch (one statistics block each)
   const int32_t* gprob; // their ids
@@ -905,7 +912,7 @@ __device__ __forceinline__ void row_spectrum(const float2 (&v)[CH], int N, float
     });
     WaveTwiddles<P> W;
     W.init(t);
-    fft_forward<P>(X, fbuf + slot * P, t, W);
+    fft_forward<P>(X, fbuf + slot * G::SPAN, t, W);
     if (slot == 0) {
       static_for<E>([&](auto ec) {
         constexpr int e = decltype(ec)::value;
@@ -1221,7 +1228,7 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
     for (int c = 0; c < CH; ++c)
       chipbad |= n + c * kFinThreads < N && (!isfinite(g[c].x) || !isfinite(g[c].y));
     const int rowbad = __syncthreads_or(chipbad);
-    skip = bad || rowbad;
+    skip = bad || rowbad || (a.frozen != nullptr && a.frozen[pid] != 0);
 
     // ---- 4. per chip
     for (int c = 0; c < CH; ++c)
@@ -1868,13 +1875,15 @@ __global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
   }
   const float flag = lead && !(isfinite(g.x) && isfinite(g.y)) ? 1.0f : 0.0f;
   const float b1 = a.opt.beta1, b2 = a.opt.beta2;
+  // a stopped design keeps its parameters: the step runs as a skipped one
+  const bool hold = a.frozen != nullptr && a.frozen[pid] != 0;
 
   // ---- the update candidate and the next pass's waveform sample
   float2 hu = hv;   // step A: updated, unprojected filter chip (lead lanes)
   float2 nx = zero2;  // next pass: soft self sample or hard partner sample
   float4 mvn = mvh;
   if constexpr (kA) {
-    if (lead && !bad) {
+    if (lead && !bad && !hold) {
       if (sgd) {
         hu.x -= a.opt.lr_h * g.x;
         hu.y -= a.opt.lr_h * g.y;
@@ -1913,7 +1922,7 @@ __global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
     const int kz = tstep * a.opt.n_x + a.inner + 1;
     const float bc1 = sgd ? 1.0f : bias_corr(b1, kz), bc2 = sgd ? 1.0f : bias_corr(b2, kz);
     const float dphi = (g.y * sv.x - g.x * sv.y) * (2.0f * 3.14159265358979f / (float)L) * invT;
-    const bool upd = !bad;
+    const bool upd = !bad && !hold;
 #pragma unroll
     for (int k = 0; k < LVMAX; ++k) {
       const int l = sub + TPC * k;
@@ -1980,7 +1989,7 @@ __global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
   float4 prod;
   float nbad;
   products(hu, nx, shr, prod, nbad);
-  const bool skip = bad || nbad > 0.f;
+  const bool skip = bad || hold || nbad > 0.f;
   float cs = 1.0f;  // scale of the prepared spectrum
 
   // ---- writes
@@ -2047,12 +2056,12 @@ __global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
     });
     WaveTwiddles<P> W;
     W.init(t);
-    fft_forward<P>(X, fbuf + slot * P, t, W);
+    fft_forward<P>(X, fbuf + slot * G::SPAN, t, W);
     if (slot == 0) {
       float2* out = a.spec + pl.ws_spec + (int64_t)m * P;
       static_for<E>([&](auto ec) {
         constexpr int e = decltype(ec)::value;
-        out[e * TF + t] = cscale(X[e], cs);
+        out[pass_spec_slot<P>(t, e)] = cscale(X[e], cs);
       });
     }
   }
@@ -2082,10 +2091,11 @@ __global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
 // spectrum itself. Needs one FFT per wave (P >= 512) and M <= WV.
 template <int P, int PHLOG, int WV, bool WT>
 __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
-  using G = Geom<P>;
+  // padding every 32 elements keeps two blocks per CU at P = 1024 with 8 waves
+  using G = GeomT<P, 64, 5>;
   static_assert(G::TF == 64, "one FFT per wave");
   constexpr int E = G::E, EH = E / 2;
-  __shared__ float2 lds[WV * P];
+  __shared__ float2 lds[WV * G::SPAN];
   // tables the block computes once: W_P^k, and per unit exp(j 2 pi t nu / N)
   // for t < 64 with the step t = 64 in the last column
   __shared__ float2 tw_tab[P];
@@ -2096,7 +2106,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   __shared__ unsigned long long u_ka[WV], u_kc[WV];
   const int wv = threadIdx.x >> 6, t = threadIdx.x & 63;
   if (a.bump != nullptr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.bump, 1);
-  float2* buf = lds + wv * P;
+  float2* buf = lds + wv * G::SPAN;
   int base = 0;
   ProbPlan pl;
   if (a.single) {
@@ -2131,7 +2141,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   float2 SG[E], X[E];
   static_for<E>([&](auto ec) {
     constexpr int e = decltype(ec)::value;
-    SG[e] = sg[e * 64 + t];
+    SG[e] = sg[pass_spec_slot<P>(t, e)];  // the partner spectra are stored in the throughput pass's layout
     X[e] = make_float2(0.f, 0.f);
     if constexpr (e < EH) {
       const int n = t + 64 * e;
@@ -2145,7 +2155,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
     ph_tab[jj][tt] = phasor(tt, doppler_nu(pl, fj, a.orient), invN);
   }
   __syncthreads();
-  WaveTwiddles<P> W;
+  TwiddlesG<G> W;
   W.init_table(t, tw_tab);
   auto phasor_row_tab = [&](float2 (&ph)[EH]) {
     ph[0] = ph_tab[wave_on ? j : 0][t];
@@ -2163,7 +2173,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
       X[e] = cmul(X[e], ph[e]);
     });
   }
-  fft_forward<P>(X, buf, t, W);
+  fft_forward_g<G>(X, buf, t, W);
 
   // this wave's pair (unit j, partner g)
   float2 R[E];
@@ -2171,7 +2181,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
     constexpr int e = decltype(ec)::value;
     R[e] = cmulc(X[e], SG[e]);
   });
-  fft_inverse<P>(R, buf, t, W);
+  fft_inverse_g<G>(R, buf, t, W);
   uint32_t vmask;
   float qmax;
   int kbest;
@@ -2197,7 +2207,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
     g_kc[wv] = active && g != w ? key : 0ull;
   }
   if (grad) {
-    fft_forward<P>(R, buf, t, W);
+    fft_forward_g<G>(R, buf, t, W);
     wave_lds_sync();
     static_for<E>([&](auto ec) {
       constexpr int e = decltype(ec)::value;
@@ -2227,7 +2237,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
         const float fc = cm1 * c;  // (sigma_g / sigma_u)^(p-1)
         static_for<E>([&](auto ec) {
           constexpr int e = decltype(ec)::value;
-          const float2 v = lds[src * P + e * 64 + t];
+          const float2 v = lds[src * G::SPAN + e * 64 + t];
           U[e].x += fc * v.x;
           U[e].y += fc * v.y;
         });
@@ -2240,7 +2250,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
       u_kc[j] = kc;
     }
     if (grad) {
-      fft_inverse<P>(U, buf, t, W);
+      fft_inverse_g<G>(U, buf, t, W);
       float2 ph[EH];
       phasor_row_tab(ph);
       wave_lds_sync();
@@ -2286,12 +2296,33 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
         float cm1, cp;
         pow_ph<PHLOG>(c * c, phm1, cm1, cp);
         const float fc = cm1 * c;
-        const float2 v = lds[(jj * M) * P + n];
+        const float2 v = lds[(jj * M) * G::SPAN + n];
         acc.x += fc * v.x;
         acc.y += fc * v.y;
       }
       up[n] = acc;
     }
+  }
+}
+
+// ------------------------------------------------------------------ k_stop
+
+// The stopping criterion of Algorithm 1, one thread per design: the hard
+// WPSL of the checkpoint (dB) against the best so far; a checkpoint that does
+// not lower it by more than min_gain counts as a stall, and `patience`
+// consecutive stalls stop the design at the current outer iteration.
+__global__ void k_stop(int32_t n, const sqngd_stats* __restrict__ st, float min_gain, int32_t patience,
+                       const int32_t* __restrict__ step, float* best, int32_t* stall, int32_t* stopped,
+                       int32_t* stop_iter) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || stopped[i] != 0) return;
+  const float w = st[i].pslr_db;
+  if ((double)w < (double)best[i] - (double)min_gain) {  // the comparison in FP64, as the host rule makes it
+    best[i] = w;
+    stall[i] = 0;
+  } else if (++stall[i] >= patience) {
+    stopped[i] = 1;
+    stop_iter[i] = step != nullptr ? *step : 0;
   }
 }
 

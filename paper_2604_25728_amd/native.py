@@ -24,7 +24,7 @@ SYMBOLS = [
     "sqngd_buffer_sizes", "sqngd_workspace_size", "sqngd_workspace_init", "sqngd_af_forward",
     "sqngd_af_backward", "sqngd_step", "sqngd_run", "sqngd_hard_quantize", "sqngd_status_string",
     "sqngd_last_hip_error", "sqngd_profile_enable", "sqngd_profile_read", "sqngd_set_roi_weights",
-    "sqngd_af_backward_noalloc",
+    "sqngd_af_backward_noalloc", "sqngd_workspace_release", "sqngd_set_stop_mask", "sqngd_stop_update",
 ]
 E_SCRATCH = -6
 NOALLOC_SCRATCH_BYTES = 32 << 20
@@ -71,6 +71,9 @@ def load():
     lib.sqngd_buffer_sizes.argtypes = [P, i32, P, P, P, P]
     lib.sqngd_workspace_size.argtypes = [P, i32, P]
     lib.sqngd_workspace_init.argtypes = [P, i32, P, sz, P]
+    lib.sqngd_workspace_release.argtypes = [P]
+    lib.sqngd_set_stop_mask.argtypes = [P, i32, P, P, sz]
+    lib.sqngd_stop_update.argtypes = [i32, P, ctypes.c_float, i32, P, P, P, P, P, P]
     lib.sqngd_set_roi_weights.argtypes = [P, i32, P, P, sz]
     lib.sqngd_af_forward.argtypes = [P, i32, P, i32, P, P, P, P, P, sz, P]
     lib.sqngd_af_backward.argtypes = [P, i32, P, i32, P, P, P, P, P, P, P, P, sz, P]
@@ -217,6 +220,13 @@ class Batch:
             oc += p["M"] * p["M"] * p["F"] * (2 * p["N"] - 1)
             oa += 2 * p["M"] * p["N"] * p["L"] + 4 * p["M"] * p["N"]
 
+    def __del__(self):
+        # drop the library's plan for this workspace before its memory goes back to the allocator
+        try:
+            self.lib.sqngd_workspace_release(self._ws_ptr)
+        except Exception:
+            pass
+
     def set_roi_weights(self, ws=None):
         """Attach the ROI weights w(tau, f) of eq. 8-9: a list of [F][2N-1]
         arrays (one per problem, None entries meaning w = 1) or None for w = 1
@@ -235,6 +245,13 @@ class Batch:
             self.roi_w = torch.cat(parts).to(self.device)
         check(self.lib.sqngd_set_roi_weights(self._arr, self.n, _ptr(self.roi_w), self._ws_ptr, self.ws_bytes),
               "set_roi_weights")
+
+    def set_stop_mask(self, stopped=None):
+        """Attach a device int32 [n] stop mask (None detaches): later optimiser
+        steps keep the parameters of problems whose entry is nonzero."""
+        self.stop_mask = stopped
+        check(self.lib.sqngd_set_stop_mask(self._arr, self.n, _ptr(stopped), self._ws_ptr, self.ws_bytes),
+              "set_stop_mask")
 
     # -------------------------------------------------------------- packing
     def pack_z(self, zs):
@@ -315,3 +332,12 @@ class Batch:
         check(self.lib.sqngd_hard_quantize(self._arr, self.n, _ptr(z), _ptr(idx), _ptr(x),
                                            self._ws_ptr, self.ws_bytes, _stream()), "hard_quantize")
         return idx, x
+
+
+def stop_update(stats, min_gain_db: float, patience: int, step_counter, best_db, stall, stopped, stop_iter):
+    """sqngd_stop_update on the current stream: one checkpoint of the stopping
+    rule for every problem whose hard statistics are in `stats`."""
+    n = int(best_db.numel())
+    check(load().sqngd_stop_update(n, _ptr(stats), float(min_gain_db), int(patience), _ptr(step_counter),
+                                   _ptr(best_db), _ptr(stall), _ptr(stopped), _ptr(stop_iter), _stream()),
+          "stop_update")

@@ -244,3 +244,55 @@ def optimise(probs, opt: dict, seeds=None, z0=None, max_iters: int | None = None
     for i in range(n):
         res[i]["wpsl_db_history"] = hist[i]
     return {"designs": res, "check_every": check_every, "patience": patience, "max_iters": max_iters}
+
+
+def optimise_on_device(probs, opt: dict, seeds=None, z0=None, max_iters: int | None = None, check_every: int = 50,
+                       patience: int = 4, min_gain_db: float = 0.0, poll_every: int = 4, schedule=None) -> dict:
+    """Algorithm 1 for a batch of designs with its stopping criterion applied
+    on the device (sqngd_stop_update + the stop mask of sqngd_set_stop_mask):
+    one HIP graph per checkpoint holds `check_every` outer iterations, the
+    hard-waveform evaluation of the batch and the stop update, so no host
+    round trip decides anything. A stopped design keeps the state it had at
+    its stopping checkpoint (its updates are masked) while the others go on in
+    the same batch. The host reads the stop flags every `poll_every`
+    checkpoints and ends the run once every design has stopped or `max_iters`
+    outer iterations are done. The decisions equal StopRule's on the same
+    checkpoint statistics. Returns, per design, the iteration at which it
+    stopped (max_iters if it never did), its hard phase indices, filters,
+    logits and hard statistics at the end."""
+    max_iters = int(opt["total_iters"] if max_iters is None else max_iters)
+    if check_every < 1 or max_iters % check_every != 0:
+        raise ValueError("max_iters must be a positive multiple of check_every")
+    run = SQNGD(probs, opt, seeds=seeds, z0=z0, schedule=schedule)
+    n = run.batch.n
+    dev = run.batch.device
+    best = torch.full((n,), float("inf"), dtype=torch.float32, device=dev)
+    stall = torch.zeros(n, dtype=torch.int32, device=dev)
+    stopped = torch.zeros(n, dtype=torch.int32, device=dev)
+    stop_iter = torch.full((n,), max_iters, dtype=torch.int32, device=dev)
+    hard = run.batch.new_stats()
+    run.batch.set_stop_mask(stopped)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run.step(check_every)
+        run.batch.af_forward(run.z, run.h, nat.WAVE_HARD, stats=hard)
+        nat.stop_update(hard, min_gain_db, patience, run.counter, best, stall, stopped, stop_iter)
+    it = 0
+    checks = 0
+    while it < max_iters:
+        g.replay()
+        it += check_every
+        checks += 1
+        if checks % poll_every == 0 and bool(stopped.all().item()):
+            break
+    torch.cuda.synchronize()
+    sts = nat.decode_stats(hard.cpu().numpy())
+    idx = run.hard_indices()
+    res = []
+    for j in range(n):
+        res.append({"stop_iter": int(stop_iter[j].item()), "stopped": bool(stopped[j].item()), "stats": sts[j],
+                    "idx": idx[j], "h": run.batch.unpack_w(run.h, j).cpu().numpy(),
+                    "z": run.batch.unpack_z(run.z, j).cpu().numpy()})
+    return {"designs": res, "check_every": check_every, "patience": patience, "max_iters": max_iters,
+            "iterations_run": it, "run": run}

@@ -287,3 +287,22 @@ def test_noalloc_validation_before_any_hip_call(nat):
     # an invalid problem
     bad = _arr(nat, p=1.0)
     assert lib.sqngd_af_backward_noalloc(bad, 1, fake, 0, None, fake, None, fake, None, None, None, None) == -1
+
+
+def test_workspace_release_of_unknown_workspace(nat):
+    lib = nat.load()
+    assert lib.sqngd_workspace_release(ctypes.c_void_p(1 << 24)) == -1
+    assert lib.sqngd_workspace_release(None) == -1
+
+
+def test_stop_update_validation(nat):
+    lib = nat.load()
+    fake = ctypes.c_void_p(1 << 20)
+    f = ctypes.c_float
+    assert lib.sqngd_stop_update(0, fake, f(0.0), 2, None, fake, fake, fake, fake, None) == -1
+    assert lib.sqngd_stop_update(4, fake, f(0.0), 0, None, fake, fake, fake, fake, None) == -1
+    assert lib.sqngd_stop_update(4, None, f(0.0), 2, None, fake, fake, fake, fake, None) == -1
+    assert lib.sqngd_stop_update(4, fake, f(float("nan")), 2, None, fake, fake, fake, fake, None) == -1
+    assert lib.sqngd_stop_update(4, fake, f(0.0), 2, None, ctypes.c_void_p((1 << 20) + 2), fake, fake, fake,
+                                 None) == -4
+    assert lib.sqngd_set_stop_mask(_arr(nat), 1, ctypes.c_void_p(3), fake, 1 << 20) == -4

@@ -271,6 +271,30 @@ def test_fallback_finalize_steps_match_oracle(ref, mods, shape):
     assert abs(sb[0]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"]
 
 
+@pytest.mark.parametrize("schedule", ["throughput", "split8"])
+def test_steps_at_fft_length_1024_match_oracle(ref, mods, schedule):
+    """Two iterations of one M=2 N=512 design (FFT length 1024: the partner
+    spectra that k_prep and k_step compute with one wave are stored in the
+    throughput pass's two-wave layout, which both pass variants read)."""
+    nat, optim, _ = mods
+    prob = I.make_problem(2, 512, 4, 5, p=16.0)
+    opt = I.make_opt(total_iters=10, T0=1.0, T1=0.5)
+    sched = nat.SCHED_THROUGHPUT if schedule == "throughput" else nat.SCHED_SPLIT8
+    print(f"[gpu] steps at FFT length 1024, {schedule}", flush=True)
+    run = optim.SQNGD([prob], opt, seeds=[8], schedule=sched)
+    s0 = run.numpy_state(0)
+    run.step(2)
+    torch.cuda.synchronize()
+    s1 = run.numpy_state(0)
+    z, h, state = s0["z"], s0["h"], s0["state"]
+    for t in range(2):
+        z, h, state, sta, stb = ref.step(prob, opt, z, h, state, t)
+    assert _rel(s1["h"], h) <= 1e-4, _rel(s1["h"], h)
+    assert _rel(s1["z"], z) <= 1e-4, _rel(s1["z"], z)
+    sa, sb = run.step_stats()
+    assert abs(sb[0]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"]
+
+
 def test_correlation_only_steps_match_oracle(ref, mods):
     """Correlation-only design (one Doppler bin at nu = 0, the paper's
     correlation experiments): two steps of a batch of two M=3 N=200 designs
@@ -370,15 +394,17 @@ def test_stopping_rule_run(ref, mods):
         assert abs(d["stats"]["pslr_db"] - st["pslr_db"]) <= 0.05
 
 
-@pytest.mark.parametrize("F", [129, 200])
-def test_fused_finalize_steps_match_oracle(ref, mods, F):
-    """A batch of 32 M=4 N=256 designs (128 rows: k_step reduces the gradient
-    rows itself, in one load round per lane at F=129 and two at F=200):
-    two iterations of its first and last design against the oracle's."""
+@pytest.mark.parametrize("N,F", [(256, 129), (256, 200), (512, 33)])
+def test_fused_finalize_steps_match_oracle(ref, mods, N, F):
+    """A batch of 32 M=4 designs (128 rows: k_step reduces the gradient rows
+    itself, in one load round per lane at N=256 F=129 and two at F=200; at
+    N=512 the FFT length is 1024, where the finalize's one-wave spectra are
+    stored in the multi-wave layout of the pass): two iterations of its first
+    and last design against the oracle's."""
     nat, optim, _ = mods
-    prob = I.make_problem(4, 256, 8, F, p=16.0)
+    prob = I.make_problem(4, N, 8, F, p=16.0)
     opt = I.make_opt(total_iters=10, T0=1.0, T1=0.5)
-    print(f"[gpu] fused finalize 32 x M=4 N=256 F={F}", flush=True)
+    print(f"[gpu] fused finalize 32 x M=4 N={N} F={F}", flush=True)
     run = optim.SQNGD([prob] * 32, opt, seeds=list(range(40, 72)), schedule=nat.SCHED_THROUGHPUT)
     s0 = [run.numpy_state(i) for i in (0, 31)]
     run.step(2)

@@ -365,3 +365,28 @@ def test_edge_shapes(ref, nat, name):
         else:
             assert st[k] == 0.0, (k, st[k])
     assert _rel(gs.cpu().numpy(), gs_ref) <= 1e-4 and _rel(gh.cpu().numpy(), gh_ref) <= 1e-4
+
+
+def test_workspace_release_and_reinit(nat):
+    """A released workspace is refused until it is initialised again; a
+    re-initialisation for another batch replaces the plan (the old one is
+    refused), and the re-initialised workspace gives the results of a fresh one."""
+    import ctypes
+    p1, p2 = I.config("m2n64")["problem"], I.make_problem(1, 40, 4, 3, p=8.0)
+    print("[gpu] workspace release / re-init", flush=True)
+    b = nat.Batch([p1])
+    z = b.pack_z([I.logits(2, 64, 4, 1)])
+    h = b.pack_w([I.complex_gaussian(2, 64, 2)])
+    st0 = b.af_forward(z, h, nat.WAVE_SOFT)
+    assert b.lib.sqngd_workspace_release(b._ws_ptr) == 0
+    with pytest.raises(nat.SQNGDError):
+        b.af_forward(z, h, nat.WAVE_SOFT)
+    # re-initialise the same memory for another batch, then for the first again
+    arr2 = nat.make_problems([p2])
+    nat.check(b.lib.sqngd_workspace_init(arr2, 1, b._ws_ptr, b.ws_bytes, nat._stream()), "init p2")
+    with pytest.raises(nat.SQNGDError):
+        b.af_forward(z, h, nat.WAVE_SOFT)
+    nat.check(b.lib.sqngd_workspace_init(b._arr, 1, b._ws_ptr, b.ws_bytes, nat._stream()), "init p1")
+    st1 = b.af_forward(z, h, nat.WAVE_SOFT)
+    torch.cuda.synchronize()
+    assert torch.equal(st0, st1)

@@ -109,30 +109,28 @@ def spread(per) -> dict:
             "p90": float(np.percentile(per, 90)), "replays": int(len(per))}
 
 
-def pass_groups(probs) -> list:
-    """FFT lengths of the batch's fused-pass launches, in launch order."""
-    return sorted({fft_len(p["N"]) for p in probs})
-
-
-def group_durations(run, nat, steps: int, repeat: int = 1) -> dict:
-    """Mean duration (ms) of each FFT-length group's fused-pass launch over
-    `steps` eager steps (two passes each): HIP events recorded by the library
-    on the launch stream around `repeat` back-to-back launches of that pass
-    (identical inputs and outputs), divided by `repeat`. The groups of one
-    pass are launched in increasing FFT length."""
+def launch_durations(run, nat, steps: int, repeat: int = 1) -> dict:
+    """Mean duration (ms) of the batch's fused-pass launches over `steps`
+    eager steps (two passes each), keyed by the FFT lengths each launch
+    covers (one launch may cover several groups): HIP events recorded by the
+    library on the launch stream around `repeat` back-to-back launches of that
+    pass (identical inputs and outputs), divided by `repeat`."""
     import numpy as np
     import torch
-    groups = pass_groups(run.probs)
-    n = 2 * steps * len(groups)
+    n = 2 * steps * 6
     torch.cuda.synchronize()
     nat.profile_enable(n, repeat)
     for _ in range(steps):
         run.step()
     torch.cuda.synchronize()
     d = nat.profile_read(n)
+    masks = nat.profile_groups(n)
     nat.profile_enable(0, 1)
-    assert d.size == n, (d.size, n)
-    return {P: float(np.mean(d[i::len(groups)])) for i, P in enumerate(groups)}
+    out = {}
+    for m in sorted(set(masks.tolist())):
+        Ps = tuple(128 << g for g in range(6) if (m >> g) & 1)
+        out[Ps] = float(np.mean(d[masks == m]))
+    return out
 
 
 def source_hash() -> str:
@@ -370,24 +368,24 @@ def transmit_extras(I, torch, only=None) -> dict:
     return extras
 
 
-def roofline_of(probs, gdur: dict, workload: str) -> dict:
-    """Roofline record of the batch's dominant fused-pass launch (the FFT-length
-    group with the largest measured duration): algorithmic flops of that launch
-    (pass_flops summed over its problems) over its measured mean duration,
-    against the FP32 vector peak."""
-    P = max(gdur, key=gdur.get)
-    flops = sum(pass_flops(p) for p in probs if fft_len(p["N"]) == P)
-    ms = gdur[P]
+def roofline_of(probs, ldur: dict, workload: str, hints=None) -> dict:
+    """Roofline record of the batch's dominant fused-pass launch (the launch
+    with the largest measured duration): the algorithmic flops of that launch
+    (pass_flops summed over the problems of the FFT lengths it covers) over
+    its measured mean duration, against the FP32 vector peak."""
+    Ps = max(ldur, key=ldur.get)
+    sel = [p for p in probs if fft_len(p["N"]) in Ps]
+    flops = sum(pass_flops(p) for p in sel)
+    ms = ldur[Ps]
     achieved = flops / (ms * 1e-3) / 1e12
-    kernel = f"k_pass<{P}, 3, false>"
+    kernel = "k_pass_multi<3, false>" if len(Ps) > 1 else f"k_pass<{Ps[0]}, 3, false>"
     traffic = stored_traffic(workload, kernel)
     return {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-            "kernel": f"{kernel} (fused AF + loss + adjoint, FFT length {P} group)",
-            "kernel_us": ms * 1e3, "flops_per_launch": flops,
-            "problems_in_launch": sum(1 for p in probs if fft_len(p["N"]) == P),
+            "kernel": f"{kernel} (fused AF + loss + adjoint over FFT lengths {list(Ps)})",
+            "kernel_us": ms * 1e3, "flops_per_launch": flops, "problems_in_launch": len(sel),
             "traffic_source": os.path.relpath(TRAFFIC_FILES[workload], ROOT) if traffic else None,
-            "group_kernel_us": {str(k): v * 1e3 for k, v in sorted(gdur.items())}}
+            "launch_us": {"+".join(str(P) for P in k): v * 1e3 for k, v in sorted(ldur.items())}}
 
 
 def both_gradient_rate(probs, seeds, reps: int = 5) -> dict:
@@ -423,7 +421,8 @@ def single_design(I, nat, optim, name: str, steps: int, tuned: bool) -> dict:
     sched = None
     if tuned:
         from paper_2604_25728_amd import tune
-        sched, sched_ms = tune.tune([prob], opt, steps=40)
+        hints, sched_ms = tune.tune([prob], opt, steps=40)
+        sched = hints[0]
         log(f"{name}: schedule tuning (ms per step): " +
             ", ".join(f"{k}: {v * 1e3:.1f} us" for k, v in sched_ms.items()) + f" -> {sched}")
     run = optim.SQNGD([prob], opt, seeds=[0], schedule=sched)
@@ -507,17 +506,21 @@ def main():
         counter_run(run, args.steps)
         return
 
-    # ---- the headline: one outer iteration of the uneven 512-problem batch per step
-    run = optim.SQNGD(probs, opt, seeds=seeds)
+    # ---- the headline: one outer iteration of the uneven 512-problem batch per step,
+    # with the fused-pass schedule of each FFT-length group tuned on the device
+    from paper_2604_25728_amd import tune
+    hints, tune_ms = tune.tune(probs, opt)
+    log("schedule tuning (ms per step): " + ", ".join(f"{k}: {v:.2f}" for k, v in tune_ms.items()))
+    run = optim.SQNGD(probs, opt, seeds=seeds, schedule=hints)
     ms_step, wall, steps, per = time_graph(run, args.steps, args.warmup, 1)
     evals = 2 * len(probs)
     log(f"uneven x{len(probs)}: step {ms_step:.3f} ms ({steps} graph replays of one iteration, wall {wall:.3f} s)")
-    gdur = group_durations(run, nat, 2)
-    roof = roofline_of(probs, gdur, "uneven")
-    log(f"dominant pass {roof['kernel']}: {roof['kernel_us']:.1f} us, {roof['achieved']:.2f} TFLOP/s; groups "
-        + ", ".join(f"P={k}: {v:.0f} us" for k, v in roof["group_kernel_us"].items()))
+    ldur = launch_durations(run, nat, 2)
+    roof = roofline_of(probs, ldur, "uneven")
+    log(f"dominant pass {roof['kernel']}: {roof['kernel_us']:.1f} us, {roof['achieved']:.2f} TFLOP/s; launches "
+        + ", ".join(f"{k}: {v:.0f} us" for k, v in roof["launch_us"].items()))
     del run
-    both = both_gradient_rate(probs, seeds)
+    both = both_gradient_rate([dict(p, schedule=h) for p, h in zip(probs, hints)], seeds)
     log(f"both gradients: {both['ms_per_batch']:.2f} ms per batch evaluation")
     cells = sum(cube_cells(p) for p in probs)
 
@@ -598,8 +601,9 @@ def main():
         "config": {"workload": "uneven batch: 64 designs x 8 random restarts (512 problems), N in {128, 256, "
                                "512, 1024}, M in {2, 4, 8}, L in {4, 8, 16}, F=129 nu in [-0.5, 0.5], all delays, "
                                "p=16; one outer iteration (filter step + logit step) per step, one HIP graph replay "
-                               "per step",
+                               "per step; fused-pass schedule per FFT-length group from the autotuner",
                    "designs": 64, "restarts": 8, "problems": len(probs), "evals_per_step": evals,
+                   "schedule": {str(fft_len(p["N"])): h for p, h in zip(probs, hints)},
                    "eval_unit": "one loss + one gradient evaluation of one problem (grad_h in the filter step, "
                                 "grad_z in the logit step)"},
         "roofline": roof,

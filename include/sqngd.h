@@ -141,20 +141,29 @@ typedef struct {
 } sqngd_problem;
 
 /* Schedule of the fused AF pass (an implementation choice; every schedule
-   computes the same results to rounding). AUTO: the library's rule (the
-   per-(Doppler bin, partner) latency variant for small batches of FFT
-   length 512 or 1024, and for batches of any size whose problems all have
-   M <= 2 at FFT length 1024, its block shape minimising the slowest compute
-   unit's wave count). THROUGHPUT: one wavefront per Doppler bin looping over
-   the partners. SPLIT8/12/16: the latency variant with that many waves per
-   block (8, 12 or 16 at FFT length 512; 8 at 1024), at any batch size. A
-   hint that does not apply to the batch (another FFT length, M above the
-   waves per block) falls back to AUTO. The first
-   non-AUTO hint in problem order decides for the whole batch. The
-   project's autotuner (paper_2604_25728_amd/tune.py) times the candidates
-   on the device and returns the best hint. */
+   computes the same results to rounding), decided per FFT-length group (the
+   problems of one batch with the same FFT length 2^ceil(log2(2N-1)) >= 128):
+   a group follows the first non-AUTO hint among its problems.
+   AUTO: the library's rule -- the per-(Doppler bin, partner) latency variant
+   for small groups of FFT length 512 or 1024 and for groups whose problems
+   all have M <= 2 at FFT length 1024, with the block shape minimising the
+   slowest compute unit's wave count; otherwise the throughput pass.
+   THROUGHPUT: one wavefront per Doppler bin looping over the partners.
+   SPLIT8/12/16: the latency variant with that many waves per block (8, 12
+   or 16 at FFT length 512; 8 at 1024); where it does not apply (another FFT
+   length, M above the waves per block) the group falls back to AUTO.
+   The throughput groups of FFT length <= 2048 run either one launch per
+   group or all in one launch, longest FFT length first (their p must select
+   the same instantiation: p = 4, 8, 16, 32, 64 or the general form). FUSED
+   (on any problem of the batch) asks for the one launch, GROUPED for one
+   launch per group; both act as THROUGHPUT for their own group. AUTO takes
+   the one launch when every such group is small (fewer than 1536 blocks).
+   The project's autotuner (paper_2604_25728_amd/tune.py) times the
+   combinations on the device. */
 #define SQNGD_SCHED_AUTO 0
 #define SQNGD_SCHED_THROUGHPUT 1
+#define SQNGD_SCHED_GROUPED 2
+#define SQNGD_SCHED_FUSED 3
 #define SQNGD_SCHED_SPLIT8 8
 #define SQNGD_SCHED_SPLIT12 12
 #define SQNGD_SCHED_SPLIT16 16
@@ -338,6 +347,10 @@ int sqngd_hard_quantize(const sqngd_problem* probs, int32_t nprob, const float* 
    calls captured in a graph while enabled record nothing. */
 int sqngd_profile_enable(int32_t max_launches, int32_t repeat);
 int sqngd_profile_read(float* ms, int32_t capacity, int32_t* count);
+/* Per recorded launch of the same hook, the FFT-length groups it covered: bit
+   g set for FFT length 128 << g (one launch may cover several groups, see
+   SQNGD_SCHED_GROUPED). Same conventions as sqngd_profile_read. */
+int sqngd_profile_groups(int32_t* masks, int32_t capacity, int32_t* count);
 
 /* Human-readable text of a status code. */
 const char* sqngd_status_string(int status);

@@ -48,6 +48,8 @@ constexpr int kNumCUs = 256;  // MI355X compute units: one block per CU is the a
 // the gradient reduction moves into k_step for groups of at least this many
 // rows, or whose rows hold at most this many bytes of Doppler partials
 constexpr int kFuseRows = kNumCUs / 2;
+// throughput groups below this many blocks count as small for the one-launch rule
+constexpr int kFuseSmallBlocks = 2 * 3 * kNumCUs;
 constexpr int64_t kFuseRowBytes = 16384;
 
 // Waves per split block for the problems of one FFT length: the compiled
@@ -92,7 +94,8 @@ int validate_problem(const sqngd_problem& p) {
   if (p.sq_mode != SQNGD_SQ_PHASE_MEAN && p.sq_mode != SQNGD_SQ_PHASOR_MEAN) return SQNGD_E_INVALID_ARG;
   if (p.reserved != 0) return SQNGD_E_INVALID_ARG;
   if (p.schedule != SQNGD_SCHED_AUTO && p.schedule != SQNGD_SCHED_THROUGHPUT && p.schedule != SQNGD_SCHED_SPLIT8 &&
-      p.schedule != SQNGD_SCHED_SPLIT12 && p.schedule != SQNGD_SCHED_SPLIT16)
+      p.schedule != SQNGD_SCHED_SPLIT12 && p.schedule != SQNGD_SCHED_SPLIT16 && p.schedule != SQNGD_SCHED_GROUPED &&
+      p.schedule != SQNGD_SCHED_FUSED)
     return SQNGD_E_INVALID_ARG;
   return SQNGD_OK;
 }
@@ -114,14 +117,17 @@ struct Plan {
   std::vector<char> bytes;  // [0, hdr.spec): header, plans, tables
   std::vector<ProbPlan> plans;
   int group_phlog[kNumPGroups];
-  int group_wv[kNumPGroups];  // waves per block of the latency variant (split batches)
+  int group_wv[kNumPGroups];  // waves per block of the latency variant (split groups)
+  bool group_split[kNumPGroups];  // the group's pass runs as k_pass_split
   // finalize of the optimiser steps: 0 = k_final, else k_step with this
   // bound on the logit levels per lane
   int group_step[kNumPGroups];
   bool group_fuse[kNumPGroups];  // k_step reduces the gradient rows itself (no k_grad launch)
   bool all_step = true;  // every group runs k_step: the step counter advances in the next pass
   int maxN = 0;
-  bool split = false;  // the fused pass runs as k_pass_split (small batches)
+  // throughput groups (bit g: FFT length 128 << g) that share one launch
+  // (k_pass_multi), 0 for one launch per group
+  int fuse_mask = 0;
   uint64_t hash = 0;
   std::vector<sqngd_problem> src;  // the descriptors the plan was built from
   // ROI weights attached by sqngd_set_roi_weights (device, packed per
@@ -149,44 +155,75 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
   H.nprob = nprob;
   pl->plans.resize(nprob);
   std::vector<int> gprob[kNumPGroups];
-  // Small batches of P = 512 or 1024 problems run the latency variant of the
-  // fused pass (one wave per Doppler bin and partner).
-  bool split = true;
-  // Two waveforms at FFT length 1024: the throughput pass amortises its per-unit
-  // self and adjoint transforms over only two partners, and the latency
-  // variant is faster at any batch size (64 M=2 N=512 designs: 12.0 against
-  // 16.2 ms per transmit-side iteration; 64 M=4 N=512: 2.15 against 1.81 ms).
-  bool pairs2 = true;
-  double pair_waves = 0.0;
+  // Each FFT-length group takes the throughput pass or, at P = 512 or 1024,
+  // the latency variant (one wave per Doppler bin and partner). A group's
+  // hint is the first non-AUTO schedule among its problems. AUTO: the latency
+  // variant for small groups, and at P = 1024 for groups whose problems all
+  // have M <= 2 (the throughput pass amortises its per-unit self and adjoint
+  // transforms over only two partners there; 64 M=2 N=512 designs: 12.0
+  // against 16.2 ms per transmit-side iteration, 64 M=4 N=512: 2.15 against
+  // 1.81 ms).
   std::vector<int> ids_p[kNumPGroups];
+  for (int i = 0; i < nprob; ++i) ids_p[log2i(fft_len(probs[i].N)) - kMinLogP].push_back(i);
+  bool ask_grouped = false, ask_fused = false;
   for (int i = 0; i < nprob; ++i) {
-    const int P = fft_len(probs[i].N);
-    if ((P != 512 && P != 1024) || probs[i].M > kMaxSplitWaves) split = false;
-    if (P != 1024 || probs[i].M > 2) pairs2 = false;
-    pair_waves += (double)probs[i].M * probs[i].M * probs[i].F;
-    ids_p[log2i(P) - kMinLogP].push_back(i);
+    ask_grouped |= probs[i].schedule == SQNGD_SCHED_GROUPED;
+    ask_fused |= probs[i].schedule == SQNGD_SCHED_FUSED;
   }
-  int hint = SQNGD_SCHED_AUTO;
-  for (int i = 0; i < nprob && hint == SQNGD_SCHED_AUTO; ++i) hint = probs[i].schedule;
-  // large batches take the throughput pass unless a split shape is asked for
-  if (pair_waves > kSplitMaxWaves && !pairs2 && hint == SQNGD_SCHED_AUTO) split = false;
-  if (hint == SQNGD_SCHED_THROUGHPUT) split = false;
-  const int forced = hint >= SQNGD_SCHED_SPLIT8 ? hint : 0;
-  for (int pass = 0; pass < 2; ++pass) {  // a forced shape that does not apply falls back to the rule
-    bool ok = split;
-    for (int g = 0; g < kNumPGroups; ++g) {
-      pl->group_wv[g] = 0;
-      if (ok && !ids_p[g].empty()) {
-        pl->group_wv[g] = choose_split_waves(1 << (g + kMinLogP), probs, ids_p[g], pass == 0 ? forced : 0);
-        if (pl->group_wv[g] == 0) ok = false;
+  for (int g = 0; g < kNumPGroups; ++g) {
+    pl->group_wv[g] = 0;
+    pl->group_split[g] = false;
+    if (ids_p[g].empty()) continue;
+    const int P = 1 << (g + kMinLogP);
+    int hint = SQNGD_SCHED_AUTO;
+    bool can = P == 512 || P == 1024, pairs2 = P == 1024;
+    double pair_waves = 0.0;
+    for (int id : ids_p[g]) {
+      if (hint == SQNGD_SCHED_AUTO) hint = probs[id].schedule;
+      if (probs[id].M > kMaxSplitWaves) can = false;
+      if (probs[id].M > 2) pairs2 = false;
+      pair_waves += (double)probs[id].M * probs[id].M * probs[id].F;
+    }
+    bool split = can;
+    if (hint == SQNGD_SCHED_AUTO) split = can && (pair_waves <= kSplitMaxWaves || pairs2);
+    if (hint == SQNGD_SCHED_THROUGHPUT || hint == SQNGD_SCHED_GROUPED || hint == SQNGD_SCHED_FUSED) split = false;
+    if (!split) continue;
+    // a forced shape that does not apply falls back to the rule's shape
+    const int forced = hint >= SQNGD_SCHED_SPLIT8 ? hint : 0;
+    int wv = choose_split_waves(P, probs, ids_p[g], forced);
+    if (wv == 0 && forced != 0) wv = choose_split_waves(P, probs, ids_p[g], 0);
+    pl->group_wv[g] = wv;
+    pl->group_split[g] = wv != 0;
+  }
+  // One launch for the throughput groups of FFT length <= 2048 when asked
+  // (FUSED), or by the rule when every such group is small (fewer blocks
+  // than two rounds of the chip at three blocks per CU: its launch would run
+  // mostly as a tail); GROUPED keeps one launch per group. The groups must
+  // agree on the p-norm's instantiation.
+  {
+    int mask = 0, phl = -2, nseg = 0;
+    bool small = true, same = true;
+    for (int g = 0; g < kNumPGroups - 1; ++g) {
+      if (ids_p[g].empty() || pl->group_split[g]) continue;
+      const int P = 1 << (g + kMinLogP);
+      int64_t blocks = 0;
+      int gphl = -2;
+      for (int id : ids_p[g]) {
+        int k = -1;
+        for (int e = 0; e <= 5; ++e)
+          if (probs[id].p == 2.0f * (float)(1 << e)) k = e;
+        gphl = (gphl == -2 || gphl == k) ? k : -1;
+        blocks += (int64_t)probs[id].M * ((probs[id].F + pass_upb(P) - 1) / pass_upb(P));
       }
+      if (blocks >= (int64_t)kFuseSmallBlocks) small = false;
+      if (phl != -2 && phl != gphl) same = false;
+      phl = gphl;
+      mask |= 1 << g;
+      ++nseg;
     }
-    if (ok || pass == 1) {
-      split = ok;
-      break;
-    }
+    const bool fuse = nseg >= 2 && same && !ask_grouped && (ask_fused || small);
+    pl->fuse_mask = fuse ? mask : 0;
   }
-  pl->split = split;
   int64_t off_z = 0, off_w = 0, off_state = 0, off_cube = 0, off_rw = 0, spec = 0, unit = 0, upart = 0;
   int rows = 0;
   for (int i = 0; i < nprob; ++i) {
@@ -217,8 +254,10 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     q.row0 = rows;
     {
       int upb;  // Doppler bins per fused-pass block
-      if (split) {
+      if (pl->group_split[q.logP - kMinLogP]) {
         upb = pl->group_wv[q.logP - kMinLogP] / p.M;
+      } else if ((pl->fuse_mask >> (q.logP - kMinLogP)) & 1) {
+        upb = pass_upb(q.P, 4);  // four-wave blocks of the one-launch pass
       } else {
         upb = pass_upb(q.P);
       }
@@ -515,8 +554,14 @@ void launch_prep(const Plan& pl, const Ptrs& w, PrepArgs a, hipStream_t s) {
 struct Profiler {
   std::mutex mu;
   std::vector<hipEvent_t> ev;  // 2 per launch
+  std::vector<int32_t> mask;   // per launch: bit g set for each FFT-length group (P = 128 << g) it covers
   int max = 0, used = 0, repeat = 1;
 } g_prof;
+
+// A profiling slot for the next pass launch on s (-1: not profiled); records
+// the start event.
+int prof_begin(hipStream_t s, int32_t mask);
+void prof_end(int slot, hipStream_t s);
 
 bool stream_capturing(hipStream_t s) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
@@ -553,6 +598,33 @@ void launch_pass_p(const PassArgs& a, int phlog, int waves, hipStream_t s) {
   else hipLaunchKernelGGL((k_pass<P, -1, false>), dim3(waves), block, 0, s, a);
 }
 
+void launch_multi(const MultiArgs& m, int phl, hipStream_t s) {
+  const dim3 grid(m.base[m.nseg]), block(256);
+  // weighted launches have p = 16 (squarings) and general-p instantiations
+  if (m.a.roi_w != nullptr && phl == 3) hipLaunchKernelGGL((k_pass_multi<3, true>), grid, block, 0, s, m);
+  else if (m.a.roi_w != nullptr) hipLaunchKernelGGL((k_pass_multi<-1, true>), grid, block, 0, s, m);
+  else if (phl == 3) hipLaunchKernelGGL((k_pass_multi<3, false>), grid, block, 0, s, m);
+  else if (phl == 2) hipLaunchKernelGGL((k_pass_multi<2, false>), grid, block, 0, s, m);
+  else hipLaunchKernelGGL((k_pass_multi<-1, false>), grid, block, 0, s, m);
+}
+
+int prof_begin(hipStream_t s, int32_t mask) {
+  int slot = -1;
+  if (g_prof.max > 0 && !stream_capturing(s)) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (g_prof.used < g_prof.max) {
+      slot = g_prof.used++;
+      g_prof.mask[slot] = mask;
+    }
+  }
+  if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot], s);
+  return slot;
+}
+
+void prof_end(int slot, hipStream_t s) {
+  if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
+}
+
 void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
   a.plans = w.plans;
   a.roi_w = pl.roi_w;
@@ -561,22 +633,47 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
   a.upart = w.upart;
   a.single = pl.hdr.nprob == 1;
   a.one = pl.plans[0];
+  // The throughput groups the plan fused share one launch, longest FFT
+  // length first.
+  int32_t multi_mask = 0;
+  MultiArgs m{};
+  if (pl.fuse_mask != 0) {
+    int phl = -2, nseg = 0, blocks = 0;
+    for (int g = 4; g >= 0; --g) {
+      if (!((pl.fuse_mask >> g) & 1)) continue;
+      phl = pl.group_phlog[g];
+      m.logp[nseg] = g + kMinLogP;
+      m.base[nseg] = blocks;
+      m.gprob[nseg] = (const int32_t*)(w.base + pl.hdr.group_prob[g]);
+      m.gwave[nseg] = (const int32_t*)(w.base + pl.hdr.group_wave[g]);
+      m.gn[nseg] = pl.hdr.group_n[g];
+      blocks += pl.hdr.group_waves[g];
+      ++nseg;
+    }
+    if (nseg >= 2) {
+      m.nseg = nseg;
+      m.base[nseg] = blocks;
+      for (int i = 0; i < nseg; ++i) multi_mask |= 1 << (m.logp[i] - kMinLogP);
+      m.a = a;
+      m.a.single = 0;
+      const int slot = prof_begin(s, multi_mask);
+      const int reps = slot >= 0 ? g_prof.repeat : 1;
+      for (int rep = 0; rep < reps; ++rep, m.a.bump = nullptr) launch_multi(m, phl, s);
+      prof_end(slot, s);
+      a.bump = nullptr;
+    }
+  }
   for (int g = 0; g < kNumPGroups; ++g) {
-    if (pl.hdr.group_n[g] == 0) continue;
+    if (pl.hdr.group_n[g] == 0 || (multi_mask >> g) & 1) continue;
     a.gprob = (const int32_t*)(w.base + pl.hdr.group_prob[g]);
     a.gwave = (const int32_t*)(w.base + pl.hdr.group_wave[g]);
     a.gn = pl.hdr.group_n[g];
     const int waves = pl.hdr.group_waves[g];
     const int phl = pl.group_phlog[g];
-    int slot = -1;
-    if (g_prof.max > 0 && !stream_capturing(s)) {
-      std::lock_guard<std::mutex> lk(g_prof.mu);
-      if (g_prof.used < g_prof.max) slot = g_prof.used++;
-    }
-    if (slot >= 0) hipEventRecord(g_prof.ev[2 * slot], s);
+    const int slot = prof_begin(s, 1 << g);
     const int reps = slot >= 0 ? g_prof.repeat : 1;
     for (int rep = 0; rep < reps; ++rep, a.bump = nullptr) {
-      if (pl.split) {
+      if (pl.group_split[g]) {
         launch_split(1 << (g + kMinLogP), pl.group_wv[g], a, phl, waves, s);
       } else {
         switch (g) {
@@ -589,7 +686,7 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
         }
       }
     }
-    if (slot >= 0) hipEventRecord(g_prof.ev[2 * slot + 1], s);
+    prof_end(slot, s);
     a.bump = nullptr;  // the first kernel of the pass advances the counter
   }
 }
@@ -716,9 +813,19 @@ int sqngd_profile_enable(int32_t max_launches, int32_t repeat) {
     if (err != hipSuccess) return hip_fail(err);
     g_prof.ev.push_back(e);
   }
+  if ((int)g_prof.mask.size() < max_launches) g_prof.mask.resize(max_launches, 0);
   g_prof.max = max_launches;
   g_prof.used = 0;
   g_prof.repeat = repeat;
+  return SQNGD_OK;
+}
+
+int sqngd_profile_groups(int32_t* masks, int32_t capacity, int32_t* count) {
+  if (count == nullptr || (masks == nullptr && capacity > 0) || capacity < 0) return SQNGD_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  const int n = g_prof.used < capacity ? g_prof.used : capacity;
+  for (int i = 0; i < n; ++i) masks[i] = g_prof.mask[i];
+  *count = g_prof.used;
   return SQNGD_OK;
 }
 

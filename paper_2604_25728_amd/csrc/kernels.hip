@@ -242,10 +242,11 @@ __device__ __forceinline__ int find_entry(const int32_t* base, int n, int wave) 
   return lo;
 }
 
-// Waves per block of the throughput pass: four at P <= 512, two at 1024, four
-// at 2048 and eight at 4096 (every wave of a block shares one unit from
-// P = 1024 on).
-__host__ __device__ constexpr int pass_waves(int P) { return P >= 4096 ? 8 : (P >= 2048 ? 4 : (P >= 1024 ? 2 : 4)); }
+// Waves per block of the throughput pass launched for one FFT length: four
+// (one unit per wave up to P = 512, one unit at 2048), two at 1024 (one
+// unit), eight sharing one unit at 4096. In the one-launch form of several
+// groups every block has four waves (two units of two waves at 1024).
+__host__ __device__ constexpr int pass_waves(int P) { return P >= 4096 ? 8 : (P == 1024 ? 2 : 4); }
 // FFT geometry of the throughput pass: wave-local up to P = 512; from 1024
 // on one transform spans the block's waves with 8 elements per lane (128
 // lanes at 1024, 256 at 2048, 512 at 4096; three LDS exchanges). With the
@@ -262,8 +263,9 @@ using PassGeom = GeomT<P, pass_tf(P)>;
 // in scratch at 2048). The weighted instantiations keep their registers and
 // run two.
 __host__ __device__ constexpr int pass_min_waves(int P) { return P == 1024 || P == 2048 ? 3 : 1; }
-// Doppler bins (units) per throughput-pass block
-__host__ __device__ constexpr int pass_upb(int P) { return pass_waves(P) * 64 / pass_tf(P); }
+// Doppler bins (units) per throughput-pass block of BW waves
+__host__ __device__ constexpr int pass_upb(int P, int BW) { return BW * 64 / pass_tf(P); }
+__host__ __device__ constexpr int pass_upb(int P) { return pass_upb(P, pass_waves(P)); }
 // Where a producer's spectral bin k lands in the partner-spectrum rows the
 // pass reads (the pass's own layout).
 template <int P>
@@ -499,45 +501,59 @@ struct PassArgs {
 };
 
 
-// WT: the launch carries ROI weights (a separate instantiation, so that the
-// unweighted pass keeps its registers).
-template <int P, int PHLOG, bool WT>
-__global__ __launch_bounds__(64 * pass_waves(P), WT ? 1 : pass_min_waves(P)) void k_pass(PassArgs a) {
+// LDS of one throughput-pass block. The accumulated adjoint spectra U and the
+// self spectrum X live in the slot's LDS slice instead of registers: three
+// E-element arrays per lane plus the partner spectrum would cap the occupancy.
+template <int P, int BW>
+struct PassSmem {
+  static constexpr int UPB = pass_upb(P, BW), W = BW;
+  float2 lds[UPB * PassGeom<P>::SPAN];  // FFT exchange buffers (padded), then the demodulated partials
+  float2 ulds[UPB * P];                 // accumulated adjoint spectra U
+  float2 xlds[UPB * P];                 // self spectrum X
+  float u_sig[UPB], u_S[UPB];
+  unsigned long long u_ka[UPB], u_kc[UPB];
+  float red_f[W];
+  unsigned long long red_k[W];
+};
+
+// One block of the throughput pass: block `blk` of the FFT-length group the
+// tables of `a` describe. WT: the launch carries ROI weights (a separate
+// instantiation, so that the unweighted pass keeps its registers).
+template <int P, int PHLOG, bool WT, int BW>
+__device__ __forceinline__ void pass_block(const PassArgs& a, int blk, PassSmem<P, BW>& sm) {
   using G = PassGeom<P>;
-  constexpr int kPassWaves = pass_waves(P);
+  constexpr int kPassWaves = BW;
   constexpr int E = G::E, TF = G::TF, EH = E / 2;
-  constexpr int UPB = pass_upb(P);  // units (Doppler bins of one row) per block
+  constexpr int UPB = pass_upb(P, BW);  // units (Doppler bins of one row) per block
   static_assert(UPB * TF == 64 * kPassWaves, "the units fill the block");
-  __shared__ float2 lds[UPB * G::SPAN];
-  // The accumulated adjoint spectra U and the self spectrum X live in the
-  // slot's LDS slice instead of registers: three E-element arrays per lane
-  // plus the partner spectrum would cap the occupancy (two waves per SIMD at
-  // P = 512, one at P >= 1024).
   constexpr bool kUL = true;
   constexpr bool kXL = true;
-  __shared__ float2 ulds[UPB * P];
-  __shared__ float2 xlds[kXL ? UPB * P : 1];
-  __shared__ float u_sig[UPB], u_S[UPB];
-  __shared__ unsigned long long u_ka[UPB], u_kc[UPB];
-  __shared__ float red_f[kPassWaves];
-  __shared__ unsigned long long red_k[kPassWaves];
+  float2* const lds = sm.lds;
+  float2* const ulds = sm.ulds;
+  float2* const xlds = sm.xlds;
+  float* const u_sig = sm.u_sig;
+  float* const u_S = sm.u_S;
+  unsigned long long* const u_ka = sm.u_ka;
+  unsigned long long* const u_kc = sm.u_kc;
+  float* const red_f = sm.red_f;
+  unsigned long long* const red_k = sm.red_k;
   // uslot: the block's unit this lane works on; t: its lane within the FFT
   const int uslot = threadIdx.x / TF, t = threadIdx.x % TF;
-  if (a.bump != nullptr && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(a.bump, 1);
+  if (a.bump != nullptr && blk == 0 && threadIdx.x == 0) atomicAdd(a.bump, 1);
   float2* buf = lds + uslot * G::SPAN;
   int base = 0;
   ProbPlan pl;
   if (a.single) {
     pl = a.one;
   } else {
-    const int entry = find_entry(a.gwave, a.gn, blockIdx.x);
+    const int entry = find_entry(a.gwave, a.gn, blk);
     pl = a.plans[a.gprob[entry]];
     base = a.gwave[entry];
   }
   const int M = pl.M, N = pl.N, F = pl.F;
   // blocks of a problem: wpr per row, rows in order; a block covers UPB
   // consecutive Doppler bins of one row, one per slot
-  const int lb = blockIdx.x - base;
+  const int lb = blk - base;
   const int w = lb / pl.wpr;
   const int grp = lb - w * pl.wpr;
   const int fs = grp * UPB + uslot;
@@ -743,6 +759,62 @@ __global__ __launch_bounds__(64 * pass_waves(P), WT ? 1 : pass_min_waves(P)) voi
       }
       up[n] = acc;
     }
+  }
+}
+
+
+template <int P, int PHLOG, bool WT>
+__global__ __launch_bounds__(64 * pass_waves(P), WT ? 1 : pass_min_waves(P)) void k_pass(PassArgs a) {
+  constexpr int BW = pass_waves(P);
+  __shared__ __align__(16) unsigned char smem[sizeof(PassSmem<P, BW>)];
+  pass_block<P, PHLOG, WT, BW>(a, blockIdx.x, *reinterpret_cast<PassSmem<P, BW>*>(smem));
+}
+
+// The throughput pass of several FFT-length groups (P = 128 .. 2048) of an
+// uneven batch in one launch. Every group's block has four waves (two units
+// of two waves at P = 1024) and about 50 KB of LDS, so one block shape and
+// one LDS region serve them all. The
+// segments are ordered longest first (by FFT length): the dispatcher hands
+// out blocks in index order to whichever compute unit has room, which makes
+// the grid a work queue served longest-job-first, and the short blocks of
+// the small FFT lengths fill the tail the long ones leave.
+constexpr int kMultiMax = 5;
+struct MultiArgs {
+  PassArgs a;
+  int32_t nseg;
+  int32_t logp[kMultiMax];      // FFT length (log2) of each segment, decreasing
+  int32_t base[kMultiMax + 1];  // first block of each segment; base[nseg] = grid size
+  const int32_t* gprob[kMultiMax];
+  const int32_t* gwave[kMultiMax];
+  int32_t gn[kMultiMax];
+};
+
+template <int... Ps>
+constexpr size_t max_pass_smem() {
+  size_t m = 0;
+  ((m = sizeof(PassSmem<Ps, 4>) > m ? sizeof(PassSmem<Ps, 4>) : m), ...);
+  return m;
+}
+constexpr size_t kMultiSmem = max_pass_smem<128, 256, 512, 1024, 2048>();
+
+template <int PHLOG, bool WT>
+__global__ __launch_bounds__(256, WT ? 2 : 3) void k_pass_multi(MultiArgs m) {
+  __shared__ __align__(16) unsigned char smem[kMultiSmem];
+  const int b = blockIdx.x;
+  int i = 0;
+  while (i + 1 < m.nseg && b >= m.base[i + 1]) ++i;
+  PassArgs a = m.a;
+  a.gprob = m.gprob[i];
+  a.gwave = m.gwave[i];
+  a.gn = m.gn[i];
+  if (i != 0) a.bump = nullptr;  // block 0 of the first segment advances the step counter
+  const int lb = b - m.base[i];
+  switch (m.logp[i]) {
+    case 11: pass_block<2048, PHLOG, WT, 4>(a, lb, *reinterpret_cast<PassSmem<2048, 4>*>(smem)); break;
+    case 10: pass_block<1024, PHLOG, WT, 4>(a, lb, *reinterpret_cast<PassSmem<1024, 4>*>(smem)); break;
+    case 9: pass_block<512, PHLOG, WT, 4>(a, lb, *reinterpret_cast<PassSmem<512, 4>*>(smem)); break;
+    case 8: pass_block<256, PHLOG, WT, 4>(a, lb, *reinterpret_cast<PassSmem<256, 4>*>(smem)); break;
+    default: pass_block<128, PHLOG, WT, 4>(a, lb, *reinterpret_cast<PassSmem<128, 4>*>(smem)); break;
   }
 }
 

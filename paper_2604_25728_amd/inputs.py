@@ -19,8 +19,9 @@ implementation is measured and checked on:
                 each, the m4n256 schedule;
   wide_m8n1024  M=8, N=1024, L=16, F=257 over the wide span [-2.5, 2.5],
                 p=16, 5000 iterations;
-  m4n512        M=4, N=512, L=8, F=129 over [-0.5, 0.5], p=16 (the
-                warm-start network's design size).
+  m4n512        M=4, N=512, L=8, F=129 over [-0.5, 0.5], p=16;
+  m4n512_ws     the same design size with eps = 0.1 (w_psl 0.1, w_snrl 0.9)
+                and SNRL target 0.3 dB: the warm-start network's workload.
 
 Every delay is in the region of interest, SNRL target 0.5 dB, loss weights
 w_psl = w_snrl = 1, Adam with beta = (0.9, 0.999), eps = 1e-8 and one step A
@@ -69,6 +70,12 @@ CONFIGS = {
     "wide_m8n1024": {"problem": make_problem(8, 1024, 16, 257, nu_min=-2.5, nu_max=2.5, p=16.0),
            "opt": make_opt(total_iters=5000, T0=1.0, T1=0.05)},
     "m4n512": {"problem": make_problem(4, 512, 8, 129, p=16.0),
+           "opt": make_opt(total_iters=2000, T0=1.0, T1=0.05)},
+    # the warm-start workload: the paper's weighting eps = 0.1 (w_psl 0.1,
+    # w_snrl 0.9) with the SNRL target 0.2 dB inside the 0.5 dB bound the
+    # comparison is held to (the penalty's equilibrium sits past its target
+    # while the sidelobe term pulls against it)
+    "m4n512_ws": {"problem": make_problem(4, 512, 8, 129, p=16.0, w_psl=0.1, w_snrl=0.9, snrl_target_db=0.3),
            "opt": make_opt(total_iters=2000, T0=1.0, T1=0.05)},
 }
 

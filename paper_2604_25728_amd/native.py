@@ -18,13 +18,14 @@ OK = 0
 WAVE_SOFT, WAVE_HARD, WAVE_GIVEN = 0, 1, 2
 SQ_PHASE_MEAN, SQ_PHASOR_MEAN = 0, 1
 OPT_SGD = 1
-SCHED_AUTO, SCHED_THROUGHPUT, SCHED_SPLIT8, SCHED_SPLIT12, SCHED_SPLIT16 = 0, 1, 8, 12, 16
+SCHED_AUTO, SCHED_THROUGHPUT, SCHED_GROUPED, SCHED_FUSED, SCHED_SPLIT8, SCHED_SPLIT12, SCHED_SPLIT16 = 0, 1, 2, 3, 8, 12, 16
 
 SYMBOLS = [
     "sqngd_buffer_sizes", "sqngd_workspace_size", "sqngd_workspace_init", "sqngd_af_forward",
     "sqngd_af_backward", "sqngd_step", "sqngd_run", "sqngd_hard_quantize", "sqngd_status_string",
     "sqngd_last_hip_error", "sqngd_profile_enable", "sqngd_profile_read", "sqngd_set_roi_weights",
     "sqngd_af_backward_noalloc", "sqngd_workspace_release", "sqngd_set_stop_mask", "sqngd_stop_update",
+    "sqngd_profile_groups",
 ]
 E_SCRATCH = -6
 NOALLOC_SCRATCH_BYTES = 32 << 20
@@ -86,6 +87,7 @@ def load():
     lib.sqngd_last_hip_error.argtypes = []
     lib.sqngd_profile_enable.argtypes = [i32, i32]
     lib.sqngd_profile_read.argtypes = [P, i32, P]
+    lib.sqngd_profile_groups.argtypes = [P, i32, P]
     for name in SYMBOLS:
         if name not in ("sqngd_status_string",):
             getattr(lib, name).restype = ctypes.c_int
@@ -115,6 +117,14 @@ def profile_read(capacity: int = 65536) -> np.ndarray:
     cnt = ctypes.c_int32()
     check(load().sqngd_profile_read(buf, capacity, ctypes.byref(cnt)), "profile_read")
     return np.array(buf[: min(cnt.value, capacity)], dtype=np.float64)
+
+
+def profile_groups(capacity: int = 65536) -> np.ndarray:
+    """FFT-length groups (bit g: length 128 << g) of each recorded launch."""
+    buf = (ctypes.c_int32 * capacity)()
+    cnt = ctypes.c_int32()
+    check(load().sqngd_profile_groups(buf, capacity, ctypes.byref(cnt)), "profile_groups")
+    return np.array(buf[: min(cnt.value, capacity)], dtype=np.int64)
 
 
 def make_problems(probs) -> ctypes.Array:

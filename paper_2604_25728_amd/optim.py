@@ -23,13 +23,16 @@ class SQNGD:
 
     def __init__(self, probs, opt: dict, seeds=None, z0=None, device="cuda", schedule=None, roi_weights=None):
         """schedule: None keeps each problem's hint (default automatic), an
-        int applies that SQNGD_SCHED_* hint to every problem, "tune" times the
-        candidates first (tune.tune) and applies the fastest. roi_weights: one
-        [F][2N-1] array (or None) per problem, the w(tau, f) of eq. 8-9."""
-        if schedule == "tune":
+        int applies that SQNGD_SCHED_* hint to every problem, a list gives one
+        hint per problem, "tune" times the candidates per FFT-length group
+        first (tune.tune) and applies the fastest. roi_weights: one [F][2N-1]
+        array (or None) per problem, the w(tau, f) of eq. 8-9."""
+        if isinstance(schedule, str) and schedule == "tune":
             from . import tune
             schedule, _ = tune.tune(probs, opt)
-        if schedule is not None:
+        if isinstance(schedule, (list, tuple)):
+            probs = [dict(p, schedule=int(h)) for p, h in zip(probs, schedule)]
+        elif schedule is not None:
             probs = [dict(p, schedule=int(schedule)) for p in probs]
         self.schedule = schedule
         self.batch = nat.Batch(probs, device=device)

@@ -19,7 +19,13 @@ logits of seed s and runs the full iteration budget; its final hard PSL is the
 target. The warm arm feeds the noise of seed s through the network and runs
 from the proposed logits. For both arms the first checkpoint (every
 `check_every` iterations) at which the hard PSL is at or below the target with
-the worst SNRL within the bound is the time to target.
+the worst SNRL at or below 0.5 dB is the time to target. Seconds are timed per
+design: a subset of the seeds runs one design at a time in each arm, each
+checkpoint's iterations, its hard evaluation and (warm arm) the network's
+proposal bracketed by HIP events.
+
+Workload: M=4 N=512 L=8 F=129 with the paper's weighting eps = 0.1 and the
+SNRL target 0.3 dB, inside the 0.5 dB bound (inputs preset m4n512_ws).
 """
 from __future__ import annotations
 
@@ -58,6 +64,7 @@ def cond_of(prob: dict):
 
 
 PARAMS_M4N512 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warmstart_m4n512.npy")
+WORKLOAD = "m4n512_ws"
 
 
 def trained_params(path: str = PARAMS_M4N512) -> np.ndarray:
@@ -151,8 +158,31 @@ def first_hit(psl_row, snrl_row, target, snrl_bound, check_every):
     return int((ok[0] + 1) * check_every) if ok.size else None
 
 
+def seconds_to_target(prob: dict, opt: dict, z0, target: float, snrl_bound: float, iters: int, check_every: int,
+                      extra_ms: float = 0.0):
+    """One design alone: GPU seconds until its hard PSL is at or below `target`
+    with the worst SNRL within the bound (checkpoints every `check_every`
+    iterations: the iterations as one graph replay and the hard evaluation,
+    bracketed by HIP events), plus `extra_ms`; None if not reached."""
+    run = optim.SQNGD([prob], opt, z0=[z0])
+    run.capture(check_every)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ms = extra_ms
+    for _ in range(0, iters, check_every):
+        e0.record()
+        run.replay()
+        stats = run.batch.af_forward(run.z, run.h, 1)
+        e1.record()
+        torch.cuda.synchronize()
+        ms += e0.elapsed_time(e1)
+        st = optim.nat.decode_stats(stats.cpu().numpy())[0]
+        if st["pslr_db"] <= target + 1e-6 and st["snrl_db_max"] <= snrl_bound + 1e-6:
+            return ms / 1e3
+    return None
+
+
 def time_to_target(prob: dict, opt: dict, net_params: torch.Tensor, seeds, iters: int, check_every: int,
-                   snrl_max_db: float = 0.5) -> dict:
+                   snrl_max_db: float = 0.5, timed_seeds: int = 0) -> dict:
     M, N, L = prob["M"], prob["N"], prob["L"]
     seeds = list(seeds)
     zr = [I.logits(M, N, L, int(s)) for s in seeds]
@@ -162,31 +192,49 @@ def time_to_target(prob: dict, opt: dict, net_params: torch.Tensor, seeds, iters
     per = []
     for i in range(len(seeds)):
         target = psl_r[i, -1]
-        bound = max(snrl_max_db, snrl_r[i, -1])
-        hr = first_hit(psl_r[i], snrl_r[i], target, bound, check_every)
-        hw = first_hit(psl_w[i], snrl_w[i], target, bound, check_every)
-        per.append({"seed": int(seeds[i]), "target_psl_db": float(target), "snrl_bound_db": float(bound),
+        hr = first_hit(psl_r[i], snrl_r[i], target, snrl_max_db, check_every)
+        hw = first_hit(psl_w[i], snrl_w[i], target, snrl_max_db, check_every)
+        per.append({"seed": int(seeds[i]), "target_psl_db": float(target), "snrl_bound_db": float(snrl_max_db),
                     "random_iters": hr, "warm_iters": hw, "warm_start_psl_db": float(psl_w[i, 0]),
-                    "random_start_psl_db": float(psl_r[i, 0]), "warm_final_psl_db": float(psl_w[i, -1])})
-    reached = [p for p in per if p["warm_iters"] is not None]
+                    "random_start_psl_db": float(psl_r[i, 0]), "warm_final_psl_db": float(psl_w[i, -1]),
+                    "random_final_snrl_db": float(snrl_r[i, -1]), "warm_final_snrl_db": float(snrl_w[i, -1])})
+    # seeds whose random run ends within the SNRL bound define a target
+    valid = [p for p in per if p["random_iters"] is not None]
+    reached = [p for p in valid if p["warm_iters"] is not None]
     ratios = [p["warm_iters"] / p["random_iters"] for p in reached]
     per_design_ms = ms_w / len(seeds)
-    return {
-        "seeds": len(seeds), "iters_budget": iters, "check_every": check_every,
-        "fraction_reached": len(reached) / len(seeds),
+    res = {
+        "seeds": len(seeds), "iters_budget": iters, "check_every": check_every, "snrl_bound_db": snrl_max_db,
+        "random_within_bound": len(valid) / len(seeds),
+        "fraction_reached": len(reached) / max(1, len(valid)),
         "median_ratio_iters": float(np.median(ratios)) if ratios else None,
-        "median_random_iters": float(np.median([p["random_iters"] for p in per])),
+        "median_random_iters": float(np.median([p["random_iters"] for p in valid])) if valid else None,
         "median_warm_iters": float(np.median([p["warm_iters"] for p in reached])) if reached else None,
         "median_target_psl_db": float(np.median(psl_r[:, -1])),
         "median_warm_final_psl_db": float(np.median(psl_w[:, -1])),
-        "random_snrl_within_bound": float(np.mean(snrl_r[:, -1] <= snrl_max_db + 1e-6)),
+        "median_random_final_snrl_db": float(np.median(snrl_r[:, -1])),
+        "median_warm_final_snrl_db": float(np.median(snrl_w[:, -1])),
         "gpu_ms_per_iteration_batch": ms_w, "gpu_ms_per_design_iteration": per_design_ms,
         "network_ms_batch": net_ms,
-        "median_warm_seconds": (float(np.median([p["warm_iters"] for p in reached])) * per_design_ms
-                                + net_ms / len(seeds)) / 1e3 if reached else None,
-        "median_random_seconds": float(np.median([p["random_iters"] for p in per])) * ms_r / len(seeds) / 1e3,
         "per_seed": per,
     }
+    if timed_seeds:
+        sec_r, sec_w, sub = [], [], [p for p in valid][:timed_seeds]
+        for p in sub:
+            i = seeds.index(p["seed"])
+            sec_r.append(seconds_to_target(prob, opt, zr[i], p["target_psl_db"], snrl_max_db, iters, check_every))
+            z1, one_ms = propose(net_params, prob, [p["seed"]])
+            sec_w.append(seconds_to_target(prob, opt, z1[0], p["target_psl_db"], snrl_max_db, iters, check_every,
+                                           extra_ms=one_ms))
+        pairs = [(a, b) for a, b in zip(sec_r, sec_w) if a is not None and b is not None]
+        res.update({"timed_seeds": len(sub),
+                    "timed_median_random_seconds": float(np.median([a for a, _ in pairs])) if pairs else None,
+                    "timed_median_warm_seconds": float(np.median([b for _, b in pairs])) if pairs else None,
+                    "timed_median_ratio_seconds": float(np.median([b / a for a, b in pairs])) if pairs else None,
+                    "timed_warm_reached": sum(b is not None for b in sec_w) / max(1, len(sub)),
+                    "timed_per_seed": [{"seed": p["seed"], "random_s": a, "warm_s": b}
+                                       for p, a, b in zip(sub, sec_r, sec_w)]})
+    return res
 
 
 def main():
@@ -208,8 +256,9 @@ def main():
     t.add_argument("--check-every", type=int, default=50)
     t.add_argument("--out", required=True)
     t.add_argument("--save-params", default=None, help="write the trained parameters (.npy, float32)")
+    t.add_argument("--timed-seeds", type=int, default=32, help="seeds timed one design at a time per arm")
     args = ap.parse_args()
-    cfg = I.config("m4n512")
+    cfg = I.config(WORKLOAD)
     prob, opt = cfg["problem"], dict(cfg["opt"])
     if args.cmd == "generate":
         opt["total_iters"] = args.iters
@@ -223,7 +272,8 @@ def main():
     net, hist = train(prob, data, args.epochs, args.batch, args.lr)
     if args.save_params:
         np.save(args.save_params, net.params.cpu().numpy().astype(np.float32), allow_pickle=False)
-    res = time_to_target(prob, opt, net.params, range(args.eval_seeds), args.iters, args.check_every)
+    res = time_to_target(prob, opt, net.params, range(args.eval_seeds), args.iters, args.check_every,
+                         timed_seeds=args.timed_seeds)
     res["train_loss"] = hist
     res["train_runs"] = int(len(data["seeds"]))
     res["train_median_psl_db"] = float(np.median(data["psl_db"]))

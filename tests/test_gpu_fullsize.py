@@ -105,3 +105,45 @@ def test_uneven_batch_slice(ref, nat):
     hs = [I.complex_gaussian(p["M"], p["N"], s + 7) for p, s in designs]
     b = nat.Batch(probs)
     _check(ref, nat, b, probs, zs, hs, rows_per_problem=2)
+
+
+@pytest.mark.parametrize("sched", ["grouped", "fused"])
+def test_full_uneven_batch_sampled_problems(ref, nat, sched):
+    """The whole 512-problem batch (64 designs x 8 restarts, FFT lengths 256 ..
+    2048) in one evaluation with both gradients, launched group by group and
+    as one launch: the cheapest problem of every FFT length against the oracle
+    (statistics, per-row gradients), and every problem's statistics and
+    gradient norms finite."""
+    designs = I.uneven_designs()
+    hint = nat.SCHED_GROUPED if sched == "grouped" else nat.SCHED_FUSED
+    probs = [dict(p, schedule=hint) for p, _ in designs]
+    print(f"[gpu] full uneven batch, {sched}", flush=True)
+    zs = [I.logits(p["M"], p["N"], p["L"], s) for p, s in designs]
+    hs = [I.complex_gaussian(p["M"], p["N"], s + 7) for p, s in designs]
+    b = nat.Batch(probs)
+    stats = b.new_stats()
+    gz, gh, gs = b.af_backward(b.pack_z(zs), b.pack_w(hs), nat.WAVE_SOFT, want_s=True, stats=stats)
+    torch.cuda.synchronize()
+    sts = nat.decode_stats(stats.cpu().numpy())
+    assert all(np.isfinite(st["loss"]) and st["nonfinite"] == 0 for st in sts)
+    assert torch.isfinite(torch.view_as_real(gh)).all() and torch.isfinite(gz).all()
+    fft = lambda n: 1 << max(7, (2 * n - 2).bit_length())
+    picks = {}
+    for i, p in enumerate(probs):
+        P = fft(p["N"])
+        cost = p["M"] ** 2 * p["N"] ** 2
+        if P not in picks or cost < picks[P][1]:
+            picks[P] = (i, cost)
+    assert sorted(picks) == [256, 512, 1024, 2048]
+    for P, (i, _) in sorted(picks.items()):
+        p = probs[i]
+        s = ref.soft_waveform(zs[i].astype(np.float64), p["temperature"])
+        st_ref, gs_ref, gh_ref = ref.evaluate(s, hs[i].astype(np.complex128), p)
+        st = sts[i]
+        assert abs(st["loss"] - st_ref["loss"]) <= 1e-4 * st_ref["loss"], (P, i)
+        assert abs(st["pslr_db"] - st_ref["pslr_db"]) <= 0.05, (P, i)
+        for m in range(p["M"]):
+            assert _rel(b.unpack_w(gs, i).cpu().numpy()[m], gs_ref[m]) <= 1e-4, (P, i, m)
+            assert _rel(b.unpack_w(gh, i).cpu().numpy()[m], gh_ref[m]) <= 1e-4, (P, i, m)
+        gz_ref = ref.logit_grad(zs[i].astype(np.float64), p["temperature"], gs_ref)
+        assert _rel(b.unpack_z(gz, i).cpu().numpy(), gz_ref) <= 1e-4, (P, i)

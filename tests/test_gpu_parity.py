@@ -319,14 +319,67 @@ def test_every_schedule_gives_the_same_results(ref, nat, sched):
     assert _rel(c[2], gh_ref) <= 1e-4
 
 
-def test_autotuner_picks_a_candidate(nat):
+def test_autotuner_picks_a_candidate(nat, tmp_path):
+    """The per-group tuner on one M=4 N=256 design (four candidates at FFT
+    length 512) and on a three-group batch (512 with four candidates, 1024 with
+    two, 256 with one; then one launch or one per group): it returns one hint
+    per problem, the fastest of the combinations it timed, and reads its JSON
+    cache back."""
     from paper_2604_25728_amd import tune
     c = I.config("m4n256")
     print("[gpu] autotuner", flush=True)
-    best, times = tune.tune([c["problem"]], c["opt"], steps=20)
-    assert best in tune.CANDIDATES and set(times) == set(tune.CANDIDATES)
-    assert times[best] == min(times.values()) and all(t > 0 for t in times.values())
-    print("tuned", best, times)
+    hints, times = tune.tune([c["problem"]], c["opt"], steps=20, cache_path=str(tmp_path / "t.json"))
+    assert len(hints) == 1 and hints[0] in tune.candidates([c["problem"]])[512]
+    assert len(times) == 4 and all(t > 0 for t in times.values())
+    probs = [I.make_problem(4, 256, 8, 33), I.make_problem(2, 500, 4, 17), I.make_problem(3, 100, 4, 9)] * 4
+    hints, times = tune.tune(probs, c["opt"], steps=10, cache_path=str(tmp_path / "t.json"))
+    assert len(hints) == 12 and len(times) in (5, 6)   # 1 + 3 + 1 combinations, then the grouping if it applies
+    assert all(h in (nat.SCHED_FUSED, nat.SCHED_GROUPED) for h, p in zip(hints, probs) if p["N"] == 100)
+    tune._cache.clear()
+    again, _ = tune.tune(probs, c["opt"], cache_path=str(tmp_path / "t.json"))
+    assert again == hints
+    print("tuned", hints, times)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_one_launch_and_grouped_launches_agree(ref, nat, weighted):
+    """An uneven batch (FFT lengths 256, 512, 1024, 2048) in one throughput
+    launch (FUSED) against the same batch launched group by group (GROUPED):
+    the same per-unit code (two units per four-wave block at 1024 in the one
+    launch, one per two-wave block otherwise, which changes only the order
+    of the block partials' combination), so statistics and gradients agree to
+    FP32 rounding, and problems 0 and 3 with the oracle; with and without ROI
+    weights."""
+    probs = [I.make_problem(2, 100, 4, 7), I.make_problem(3, 200, 8, 5), I.make_problem(2, 400, 4, 9),
+             I.make_problem(4, 900, 8, 3)] * 2
+    zs = [I.logits(p["M"], p["N"], p["L"], 90 + i) for i, p in enumerate(probs)]
+    hs = [I.complex_gaussian(p["M"], p["N"], 95 + i) for i, p in enumerate(probs)]
+    print("[gpu] one launch vs grouped launches", flush=True)
+    ws = [I.roi_weights(p, 97 + i) for i, p in enumerate(probs)] if weighted else None
+    out = []
+    for sched in (nat.SCHED_FUSED, nat.SCHED_GROUPED):
+        b = nat.Batch([dict(p, schedule=sched) for p in probs])
+        if weighted:
+            b.set_roi_weights(ws)
+        st = b.new_stats()
+        g = b.af_backward(b.pack_z(zs), b.pack_w(hs), nat.WAVE_SOFT, want_s=True, stats=st)
+        out.append((st, g, b))
+    torch.cuda.synchronize()
+    s0, s1 = nat.decode_stats(out[0][0].cpu().numpy()), nat.decode_stats(out[1][0].cpu().numpy())
+    for a_, c_ in zip(s0, s1):
+        assert abs(a_["loss"] - c_["loss"]) <= 1e-5 * c_["loss"]
+    for x, y in zip(out[0][1], out[1][1]):
+        assert _rel(x.cpu().numpy(), y.cpu().numpy()) <= 1e-5
+    b = out[0][2]
+    sts = s0
+    for i in (0, 3):
+        p = probs[i]
+        sr = ref.soft_waveform(zs[i].astype(np.float64), p["temperature"])
+        pw = dict(p, roi_w=ws[i].astype(np.float64)) if weighted else p
+        st_ref, gs_ref, gh_ref = ref.evaluate(sr, hs[i].astype(np.complex128), pw)
+        _check_stats(sts[i], st_ref, p["N"], i)
+        _check_rows(b.unpack_w(out[0][1][2], i).cpu().numpy(), gs_ref, (i, "s"))
+        _check_rows(b.unpack_w(out[0][1][1], i).cpu().numpy(), gh_ref, (i, "h"))
 
 
 EDGE = {

@@ -149,9 +149,11 @@ typedef struct {
    all have M <= 2 at FFT length 1024, with the block shape minimising the
    slowest compute unit's wave count; otherwise the throughput pass.
    THROUGHPUT: one wavefront per Doppler bin looping over the partners.
-   SPLIT8/12/16: the latency variant with that many waves per block (8, 12
-   or 16 at FFT length 512; 8 at 1024); where it does not apply (another FFT
-   length, M above the waves per block) the group falls back to AUTO.
+   SPLIT2/4/8/12/16: the latency variant with that many waves per block (4,
+   8, 12 or 16 at FFT length 512; 2, 4 or 8 at 1024; the rule itself picks
+   among 8, 12 and 16 at 512 and among 4 and 8 at 1024); where it does not apply
+   (another FFT length, M above the waves per block) the group falls back to
+   AUTO.
    The throughput groups of FFT length <= 2048 run either one launch per
    group or all in one launch, longest FFT length first (their p must select
    the same instantiation: p = 4, 8, 16, 32, 64 or the general form). FUSED
@@ -162,11 +164,13 @@ typedef struct {
    combinations on the device. */
 #define SQNGD_SCHED_AUTO 0
 #define SQNGD_SCHED_THROUGHPUT 1
-#define SQNGD_SCHED_GROUPED 2
-#define SQNGD_SCHED_FUSED 3
+#define SQNGD_SCHED_SPLIT2 2
+#define SQNGD_SCHED_SPLIT4 4
 #define SQNGD_SCHED_SPLIT8 8
 #define SQNGD_SCHED_SPLIT12 12
 #define SQNGD_SCHED_SPLIT16 16
+#define SQNGD_SCHED_GROUPED 32
+#define SQNGD_SCHED_FUSED 33
 
 /* Optimiser options of one outer iteration (Algorithm 1). */
 typedef struct {

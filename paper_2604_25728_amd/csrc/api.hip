@@ -40,8 +40,14 @@ bool finite(float v) { return std::isfinite(v); }
 // Latency variant of the fused pass: waves per block (M partners x units per
 // block) are chosen per FFT length among the compiled shapes; the LDS of a
 // block holds one P-point exchange buffer per wave (<= 64 KiB).
+// (the automatic rule picks among these; a SPLIT hint may also ask for the
+// smaller shapes below, kSplitExtra512 / kSplitExtra1024)
+// (measured at M=2 N=512 F=129 with ROI weights: 19.1 us per pass with 8
+// waves per block, 15.9 with 4, 17.5 with 2)
 constexpr int kSplitShapes512[] = {8, 12, 16};
-constexpr int kSplitShapes1024[] = {8};
+constexpr int kSplitShapes1024[] = {4, 8};
+constexpr int kSplitExtra512[] = {4};
+constexpr int kSplitExtra1024[] = {2};
 constexpr int kMaxSplitWaves = 16;
 constexpr double kSplitMaxWaves = 8192.0;
 constexpr int kNumCUs = 256;  // MI355X compute units: one block per CU is the aim
@@ -56,11 +62,16 @@ constexpr int64_t kFuseRowBytes = 16384;
 // shape minimising (rounds of kNumCUs blocks) x (waves per block), i.e. the
 // per-SIMD wave count of the slowest compute unit; ties go to fewer waves.
 int choose_split_waves(int P, const sqngd_problem* probs, const std::vector<int>& ids, int forced) {
-  const int* shapes = P == 512 ? kSplitShapes512 : kSplitShapes1024;
-  const int nshapes = P == 512 ? 3 : 1;
+  std::vector<int> shapes;
+  if (P == 512) shapes.assign(std::begin(kSplitShapes512), std::end(kSplitShapes512));
+  else shapes.assign(std::begin(kSplitShapes1024), std::end(kSplitShapes1024));
+  if (forced != 0) {
+    if (P == 512) shapes.insert(shapes.end(), std::begin(kSplitExtra512), std::end(kSplitExtra512));
+    else shapes.insert(shapes.end(), std::begin(kSplitExtra1024), std::end(kSplitExtra1024));
+  }
   int best = 0;
   double best_cost = 0.0;
-  for (int k = 0; k < nshapes; ++k) {
+  for (size_t k = 0; k < shapes.size(); ++k) {
     const int wv = shapes[k];
     if (forced != 0 && wv != forced) continue;
     int64_t blocks = 0;
@@ -93,9 +104,9 @@ int validate_problem(const sqngd_problem& p) {
   if (!finite(p.temperature) || p.temperature <= 0.0f) return SQNGD_E_INVALID_ARG;
   if (p.sq_mode != SQNGD_SQ_PHASE_MEAN && p.sq_mode != SQNGD_SQ_PHASOR_MEAN) return SQNGD_E_INVALID_ARG;
   if (p.reserved != 0) return SQNGD_E_INVALID_ARG;
-  if (p.schedule != SQNGD_SCHED_AUTO && p.schedule != SQNGD_SCHED_THROUGHPUT && p.schedule != SQNGD_SCHED_SPLIT8 &&
-      p.schedule != SQNGD_SCHED_SPLIT12 && p.schedule != SQNGD_SCHED_SPLIT16 && p.schedule != SQNGD_SCHED_GROUPED &&
-      p.schedule != SQNGD_SCHED_FUSED)
+  if (p.schedule != SQNGD_SCHED_AUTO && p.schedule != SQNGD_SCHED_THROUGHPUT && p.schedule != SQNGD_SCHED_SPLIT2 &&
+      p.schedule != SQNGD_SCHED_SPLIT4 && p.schedule != SQNGD_SCHED_SPLIT8 && p.schedule != SQNGD_SCHED_SPLIT12 &&
+      p.schedule != SQNGD_SCHED_SPLIT16 && p.schedule != SQNGD_SCHED_GROUPED && p.schedule != SQNGD_SCHED_FUSED)
     return SQNGD_E_INVALID_ARG;
   return SQNGD_OK;
 }
@@ -189,7 +200,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     if (hint == SQNGD_SCHED_THROUGHPUT || hint == SQNGD_SCHED_GROUPED || hint == SQNGD_SCHED_FUSED) split = false;
     if (!split) continue;
     // a forced shape that does not apply falls back to the rule's shape
-    const int forced = hint >= SQNGD_SCHED_SPLIT8 ? hint : 0;
+    const int forced = hint >= SQNGD_SCHED_SPLIT2 && hint <= SQNGD_SCHED_SPLIT16 ? hint : 0;
     int wv = choose_split_waves(P, probs, ids_p[g], forced);
     if (wv == 0 && forced != 0) wv = choose_split_waves(P, probs, ids_p[g], 0);
     pl->group_wv[g] = wv;
@@ -582,7 +593,11 @@ void launch_split_wv(const PassArgs& a, int phlog, int blocks, hipStream_t s) {
 }
 
 void launch_split(int P, int wv, const PassArgs& a, int phlog, int blocks, hipStream_t s) {
-  if (P == 1024) launch_split_wv<1024, 8>(a, phlog, blocks, s);
+  if (P == 1024) {
+    if (wv == 2) launch_split_wv<1024, 2>(a, phlog, blocks, s);
+    else if (wv == 4) launch_split_wv<1024, 4>(a, phlog, blocks, s);
+    else launch_split_wv<1024, 8>(a, phlog, blocks, s);
+  } else if (wv == 4) launch_split_wv<512, 4>(a, phlog, blocks, s);
   else if (wv == 12) launch_split_wv<512, 12>(a, phlog, blocks, s);
   else if (wv == 16) launch_split_wv<512, 16>(a, phlog, blocks, s);
   else launch_split_wv<512, 8>(a, phlog, blocks, s);

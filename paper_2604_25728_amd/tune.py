@@ -4,8 +4,8 @@ Every schedule computes the same results; they differ in how the (row,
 Doppler bin, partner) work of the fused pass is cut into wavefronts and
 blocks (SQNGD_SCHED_* hints, include/sqngd.h). The choices are per group of
 problems with the same FFT length: at 512 the throughput pass or the latency
-variant with 8, 12 or 16 waves per block, at 1024 the throughput pass or the
-8-wave latency variant, elsewhere the throughput pass; and for the batch, the
+variant with 4, 8, 12 or 16 waves per block, at 1024 the throughput pass or
+the latency variant with 2, 4 or 8, elsewhere the throughput pass; and for the batch, the
 throughput groups in one launch or one launch per group. The tuner times
 whole outer iterations (HIP-graph replays on the current stream, HIP events)
 in a coordinate search -- every group's candidates with the others fixed,
@@ -21,7 +21,8 @@ import torch
 
 from . import native as nat
 
-SPLIT_SHAPES = {512: (nat.SCHED_SPLIT8, nat.SCHED_SPLIT12, nat.SCHED_SPLIT16), 1024: (nat.SCHED_SPLIT8,)}
+SPLIT_SHAPES = {512: (nat.SCHED_SPLIT4, nat.SCHED_SPLIT8, nat.SCHED_SPLIT12, nat.SCHED_SPLIT16),
+                1024: (nat.SCHED_SPLIT2, nat.SCHED_SPLIT4, nat.SCHED_SPLIT8)}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2604_25728_amd", "tune.json")
 _cache: dict = {}
 

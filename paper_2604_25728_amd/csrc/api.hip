@@ -273,6 +273,9 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
         upb = pass_upb(q.P);
       }
       q.wpr = (p.F + upb - 1) / upb;
+      // the latency pass reads the spectra in the one-wave layout the
+      // producers compute them in (the layouts coincide below P = 1024)
+      q.spec_wave = pl->group_split[q.logP - kMinLogP] && q.P >= 1024 ? 1 : 0;
     }
     q.units = p.M * q.wpr;
     q.off_z = off_z;

@@ -172,6 +172,18 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Workgroup barrier that orders LDS traffic only: every wave's earlier LDS
+// accesses are complete and visible to the workgroup before any later one
+// starts. Global loads in flight stay in flight across it (a full
+// __syncthreads would wait for them), so a kernel that reads only inputs no
+// wave of it writes can issue its global loads early and cross barriers
+// before they land.
+__device__ __forceinline__ void block_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------------ twiddles
 
 // ------------------------------------------------------------------ geometry
@@ -211,26 +223,32 @@ struct GeomT {
   static_assert(A * B * C == TF, "the lane radices factor TF");
   static_assert(E % A == 0 && E % B == 0 && E % C == 0, "register blocks must tile E");
   static_assert(TF <= 64 ? 64 % TF == 0 : TF % 64 == 0, "an FFT fills whole waves or divides one");
-  // spectral-layout bin of lane t, register e
-  __device__ static constexpr int spec_bin(int t, int e) {
+  // spectral-layout bin of lane t, register e (unsigned arithmetic: every
+  // index is non-negative and every radix a power of two, so the divisions
+  // and remainders are shifts and masks)
+  __device__ static constexpr int spec_bin(int t_, int e_) {
+    const unsigned t = (unsigned)t_, e = (unsigned)e_;
+    constexpr unsigned uA = A, uB = B, uC = C, uE = E;
     if constexpr (!THREE) {
-      int gamma = t % A, k1 = (e / B) * B + t / A, delta = e % B;
-      return k1 + E * (gamma + A * delta);
+      const unsigned gamma = t % uA, k1 = (e / uB) * uB + t / uA, delta = e % uB;
+      return (int)(k1 + uE * (gamma + uA * delta));
     } else {
-      const int q3 = t / (A * B), gamma = (t % (A * B)) / B, zeta = t % B;
-      const int k1 = (e / C) * C + q3, eta = e % C;
-      return k1 + E * (gamma + A * (zeta + B * eta));
+      const unsigned q3 = t / (uA * uB), gamma = (t % (uA * uB)) / uB, zeta = t % uB;
+      const unsigned k1 = (e / uC) * uC + q3, eta = e % uC;
+      return (int)(k1 + uE * (gamma + uA * (zeta + uB * eta)));
     }
   }
   // the inverse: storage index e * TF + t of bin k
-  __device__ static constexpr int spec_index(int k) {
-    const int k1 = k % E, r = k / E, gamma = r % A;
+  __device__ static constexpr int spec_index(int k_) {
+    const unsigned k = (unsigned)k_;
+    constexpr unsigned uA = A, uB = B, uC = C, uE = E, uTF = TF;
+    const unsigned k1 = k % uE, r = k / uE, gamma = r % uA;
     if constexpr (!THREE) {
-      const int delta = r / A;
-      return ((k1 / B) * B + delta) * TF + (k1 % B) * A + gamma;
+      const unsigned delta = r / uA;
+      return (int)(((k1 / uB) * uB + delta) * uTF + (k1 % uB) * uA + gamma);
     } else {
-      const int r2 = r / A, zeta = r2 % B, eta = r2 / B;
-      return ((k1 / C) * C + eta) * TF + (k1 % C) * (A * B) + gamma * B + zeta;
+      const unsigned r2 = r / uA, zeta = r2 % uB, eta = r2 / uB;
+      return (int)(((k1 / uC) * uC + eta) * uTF + (k1 % uC) * (uA * uB) + gamma * uB + zeta);
     }
   }
 };
@@ -241,7 +259,7 @@ using Geom = GeomT<P, (P >= 512 ? 64 : P / 8)>;
 // geometry, the workgroup for one spread over several waves.
 template <class G>
 __device__ __forceinline__ void fft_sync() {
-  if constexpr (G::WAVES > 1) __syncthreads();
+  if constexpr (G::WAVES > 1) block_lds_sync();
   else wave_lds_sync();
 }
 
@@ -280,7 +298,7 @@ struct TwiddlesG {
     }
     hi[0] = make_float2(1.f, 0.f);
     for (int a = 1; a < NHI; ++a) hi[a] = tw_exact<P>(t * NLO * a);
-    const int beta = t % G::BC;
+    const int beta = (unsigned)t % G::BC;
     col[0] = make_float2(1.f, 0.f);
     if constexpr (G::A > 1) col[1] = tw_exact<P>(beta * G::E);
     if constexpr (G::A > 2) col[2] = tw_exact<P>(2 * beta * G::E);
@@ -292,7 +310,7 @@ struct TwiddlesG {
       col[7] = cmul(col[4], col[3]);
     }
     if constexpr (G::THREE) {
-      const int c = t % G::C;
+      const int c = (unsigned)t % G::C;
       col2[0] = make_float2(1.f, 0.f);
       for (int z = 1; z < G::B; ++z) col2[z] = tw_exact<P>(c * z * G::E * G::A);
     }
@@ -304,11 +322,11 @@ struct TwiddlesG {
     for (int b = 1; b < NLO; ++b) lo[b] = tab[(t * b) & (P - 1)];
     hi[0] = make_float2(1.f, 0.f);
     for (int a = 1; a < NHI; ++a) hi[a] = tab[(t * NLO * a) & (P - 1)];
-    const int beta = t % G::BC;
+    const int beta = (unsigned)t % G::BC;
     col[0] = make_float2(1.f, 0.f);
     for (int g = 1; g < G::A; ++g) col[g] = tab[(g * beta * G::E) & (P - 1)];
     if constexpr (G::THREE) {
-      const int c = t % G::C;
+      const int c = (unsigned)t % G::C;
       col2[0] = make_float2(1.f, 0.f);
       for (int z = 1; z < G::B; ++z) col2[z] = tab[(c * z * G::E * G::A) & (P - 1)];
     }
@@ -347,7 +365,7 @@ __device__ __forceinline__ void fft3_forward(float2 (&x)[G::E], float2* buf, int
   });
   fft_sync<G>();
   {  // radix A over alpha: lane (q, tau), k1 = j A + q
-    const int tau = t % BC, q = t / BC;
+    const int tau = (unsigned)t % BC, q = (unsigned)t / BC;
     float2* const bq = buf + G::ix(q * TF + tau);
     static_for<E / A>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
@@ -372,7 +390,7 @@ __device__ __forceinline__ void fft3_forward(float2 (&x)[G::E], float2* buf, int
     fft_sync<G>();
   }
   {  // radix B over beta: lane (q2, gamma, c), k1 = j2 B + q2
-    const int q2 = t / (A * C), gamma = (t % (A * C)) / C, c = t % C;
+    const int q2 = (unsigned)t / (A * C), gamma = ((unsigned)t % (A * C)) / C, c = (unsigned)t % C;
     float2* const bq2 = buf + G::ix(q2 * TF + gamma * BC + c);
     static_for<E / B>([&](auto jc) {
       constexpr int j2 = decltype(jc)::value;
@@ -397,7 +415,7 @@ __device__ __forceinline__ void fft3_forward(float2 (&x)[G::E], float2* buf, int
     fft_sync<G>();
   }
   {  // radix C over c: lane (q3, gamma, zeta), k1 = j3 C + q3
-    const int q3 = t / (A * B), gamma = (t % (A * B)) / B, zeta = t % B;
+    const int q3 = (unsigned)t / (A * B), gamma = ((unsigned)t % (A * B)) / B, zeta = (unsigned)t % B;
     float2* const bq3 = buf + G::ix(q3 * TF + gamma * BC + zeta * C);
     static_for<E / C>([&](auto jc) {
       constexpr int j3 = decltype(jc)::value;
@@ -414,7 +432,7 @@ template <class G>
 __device__ __forceinline__ void fft3_inverse(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
   constexpr int E = G::E, TF = G::TF, A = G::A, B = G::B, C = G::C, BC = G::BC;
   {  // radix C over eta -> c
-    const int q3 = t / (A * B), gamma = (t % (A * B)) / B, zeta = t % B;
+    const int q3 = (unsigned)t / (A * B), gamma = ((unsigned)t % (A * B)) / B, zeta = (unsigned)t % B;
     float2* const bq3 = buf + G::ix(q3 * TF + gamma * BC + zeta * C);
     static_for<E / C>([&](auto jc) {
       constexpr int j3 = decltype(jc)::value;
@@ -431,7 +449,7 @@ __device__ __forceinline__ void fft3_inverse(float2 (&x)[G::E], float2* buf, int
     fft_sync<G>();
   }
   {  // radix B over zeta -> beta
-    const int q2 = t / (A * C), gamma = (t % (A * C)) / C, c = t % C;
+    const int q2 = (unsigned)t / (A * C), gamma = ((unsigned)t % (A * C)) / C, c = (unsigned)t % C;
     float2* const bq2 = buf + G::ix(q2 * TF + gamma * BC + c);
     static_for<E / B>([&](auto jc) {
       constexpr int j2 = decltype(jc)::value;
@@ -454,7 +472,7 @@ __device__ __forceinline__ void fft3_inverse(float2 (&x)[G::E], float2* buf, int
     fft_sync<G>();
   }
   {  // radix A over gamma -> alpha
-    const int tau = t % BC, q = t / BC;
+    const int tau = (unsigned)t % BC, q = (unsigned)t / BC;
     float2* const bq = buf + G::ix(q * TF + tau);
     static_for<E / A>([&](auto jc) {
       constexpr int j = decltype(jc)::value;
@@ -503,7 +521,7 @@ __device__ __forceinline__ void fft2_forward(float2 (&x)[G::E], float2* buf, int
     bt[G::ix(k1 * TF)] = x[k1];
   });
   fft_sync<G>();
-  const int beta = t % B, q = t / B;
+  const int beta = (unsigned)t % B, q = (unsigned)t / B;
   float2* const bq = buf + G::ix(q * TF + beta);
   static_for<E / A>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
@@ -527,7 +545,7 @@ __device__ __forceinline__ void fft2_forward(float2 (&x)[G::E], float2* buf, int
     });
   });
   fft_sync<G>();
-  const int gamma = t % A, q2 = t / A;
+  const int gamma = (unsigned)t % A, q2 = (unsigned)t / A;
   float2* const bq2 = buf + G::ix(q2 * TF + gamma * B);
   static_for<E / B>([&](auto jc) {
     constexpr int j2 = decltype(jc)::value;
@@ -544,7 +562,7 @@ __device__ __forceinline__ void fft2_forward(float2 (&x)[G::E], float2* buf, int
 template <class G>
 __device__ __forceinline__ void fft2_inverse(float2 (&x)[G::E], float2* buf, int t, const TwiddlesG<G>& W) {
   constexpr int E = G::E, TF = G::TF, A = G::A, B = G::B;
-  const int gamma = t % A, q2 = t / A;
+  const int gamma = (unsigned)t % A, q2 = (unsigned)t / A;
   float2* const bq2 = buf + G::ix(q2 * TF + gamma * B);
   static_for<E / B>([&](auto jc) {
     constexpr int j2 = decltype(jc)::value;
@@ -559,7 +577,7 @@ __device__ __forceinline__ void fft2_inverse(float2 (&x)[G::E], float2* buf, int
     });
   });
   fft_sync<G>();
-  const int beta = t % B, q = t / B;
+  const int beta = (unsigned)t % B, q = (unsigned)t / B;
   float2* const bq = buf + G::ix(q * TF + beta);
   static_for<E / A>([&](auto jc) {
     constexpr int j = decltype(jc)::value;

@@ -176,6 +176,15 @@ __device__ __forceinline__ void roi_weigh(float2 (&R)[E], int t, int N, int orie
   });
 }
 
+// The same with the weights of the lane's cells already in registers.
+template <int E>
+__device__ __forceinline__ void roi_weigh_reg(float2 (&R)[E], const float (&wr)[E]) {
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    R[e] = cscale(R[e], wr[e]);
+  });
+}
+
 // AF cells of one row into the cube [w][g][f][tau + N - 1] (scaled by 1/P).
 template <int P, int TF, int E>
 __device__ __forceinline__ void cube_store(const float2 (&R)[E], int t, int N, float2* row) {
@@ -267,13 +276,19 @@ __host__ __device__ constexpr int pass_min_waves(int P) { return P == 1024 || P 
 __host__ __device__ constexpr int pass_upb(int P, int BW) { return BW * 64 / pass_tf(P); }
 __host__ __device__ constexpr int pass_upb(int P) { return pass_upb(P, pass_waves(P)); }
 // Where a producer's spectral bin k lands in the partner-spectrum rows the
-// pass reads (the pass's own layout).
+// pass reads: the throughput pass's own layout, or (spec_wave, a problem
+// whose group runs the latency pass) the one-wave layout the producers and
+// the latency pass share, so neither side scatters.
 template <int P>
 __device__ __forceinline__ int pass_spec_slot(int t, int e) {
   using GP = Geom<P>;
   using GC = PassGeom<P>;
   if constexpr (GP::TF == GC::TF) return e * GP::TF + t;
   else return GC::spec_index(GP::spec_bin(t, e));
+}
+template <int P>
+__device__ __forceinline__ int spec_slot(const ProbPlan& pl, int t, int e) {
+  return pl.spec_wave ? e * Geom<P>::TF + t : pass_spec_slot<P>(t, e);
 }
 
 // Reductions over the lanes of one FFT of geometry G, the result in all of
@@ -285,9 +300,9 @@ __device__ __forceinline__ float fft_lanes_reduce(float v, float ident, Op op, f
     return slot_reduce<G::TF>(v, ident, op);
   } else {
     v = slot_reduce<64>(v, ident, op);
-    __syncthreads();
+    block_lds_sync();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
+    block_lds_sync();
     const int w0 = (threadIdx.x / G::TF) * G::WAVES;
     float r = red[w0];
     for (int i = 1; i < G::WAVES; ++i) r = op(r, red[w0 + i]);
@@ -300,9 +315,9 @@ __device__ __forceinline__ unsigned long long fft_lanes_max_key(unsigned long lo
     return slot_max_key<G::TF>(v);
   } else {
     v = slot_max_key<64>(v);
-    __syncthreads();
+    block_lds_sync();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
+    block_lds_sync();
     const int w0 = (threadIdx.x / G::TF) * G::WAVES;
     unsigned long long r = red[w0];
     for (int i = 1; i < G::WAVES; ++i) r = umax64(r, red[w0 + i]);
@@ -473,7 +488,7 @@ __global__ __launch_bounds__(64) void k_prep(PrepArgs a) {
       float2* sp = a.spec + pl.ws_spec + (int64_t)g * P;
       static_for<E>([&](auto ec) {
         constexpr int e = decltype(ec)::value;
-        sp[pass_spec_slot<P>(t, e)] = X[e];
+        sp[spec_slot<P>(pl, t, e)] = X[e];
       });
     }
   }
@@ -712,7 +727,7 @@ __device__ __forceinline__ void pass_block(const PassArgs& a, int blk, PassSmem<
       if (n < N) buf[n] = active ? cmulc(R[e], ph[e]) : make_float2(0.f, 0.f);
     });
   }
-  __syncthreads();
+  block_lds_sync();
 
   // Block combine: one statistics entry and one partial per block, both
   // relative to the block's largest unit scale (unit order fixed).
@@ -966,7 +981,8 @@ __device__ __forceinline__ void logit_chain(const float* zc, int L, float T, int
 // spectral layout of the fused pass, computed by wave 0 of the block; fbuf
 // holds the staged row and then serves as that wave's exchange buffer.
 template <int P, int CH>
-__device__ __forceinline__ void row_spectrum(const float2 (&v)[CH], int N, float2* fbuf, float2* out) {
+__device__ __forceinline__ void row_spectrum(const float2 (&v)[CH], int N, float2* fbuf, float2* out,
+                                             const ProbPlan& pl) {
   using G = Geom<P>;
   constexpr int E = G::E, TF = G::TF;
   const int tid = threadIdx.x;
@@ -988,7 +1004,7 @@ __device__ __forceinline__ void row_spectrum(const float2 (&v)[CH], int N, float
     if (slot == 0) {
       static_for<E>([&](auto ec) {
         constexpr int e = decltype(ec)::value;
-        out[pass_spec_slot<P>(t, e)] = X[e];
+        out[spec_slot<P>(pl, t, e)] = X[e];
       });
     }
   }
@@ -1438,7 +1454,7 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
     row_snrl<CH>(self, prt, shf, a.snrl_next + r);
     if constexpr (!spec_by_rowspec(P))
       if (a.next == NEXT_B_FULL || next_hard)
-        row_spectrum<P, CH>(sp, N, fbuf, a.spec + pl.ws_spec + (int64_t)m * P);
+        row_spectrum<P, CH>(sp, N, fbuf, a.spec + pl.ws_spec + (int64_t)m * P, pl);
   }
 
   // ---- 7. statistics record
@@ -2133,7 +2149,7 @@ __global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
       float2* out = a.spec + pl.ws_spec + (int64_t)m * P;
       static_for<E>([&](auto ec) {
         constexpr int e = decltype(ec)::value;
-        out[pass_spec_slot<P>(t, e)] = cscale(X[e], cs);
+        out[spec_slot<P>(pl, t, e)] = cscale(X[e], cs);
       });
     }
   }
@@ -2191,6 +2207,10 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   const int M = pl.M, N = pl.N, F = pl.F;
   const int UB = WV / M;
   const int j = wv / M, g = wv - (wv / M) * M;
+  // the unit's leader wave (it combines the partners and runs the unit's
+  // inverse transform): partner j mod M, so that the leaders of a block's
+  // units sit on different SIMDs (a block's waves go round-robin over them)
+  const int lead = j % M;
   const bool wave_on = j < UB;
   const int lb = blockIdx.x - base;
   const int w = lb / pl.wpr;
@@ -2207,26 +2227,50 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   const bool grad = a.want_grad != 0;
   const float* wrow = WT ? a.roi_w + pl.off_rw + (int64_t)f * (2 * N - 1) : nullptr;
 
-  // global loads first, then the arithmetic that hides their latency
+  // global loads first, in the order they are needed (a wave's loads complete
+  // in issue order): the self row, the partner spectrum, the ROI weights;
+  // then the arithmetic that hides their latency
   const float2* sg = a.spec + pl.ws_spec + (int64_t)(wave_on ? g : 0) * P;
   const float2* sw = a.self_w + pl.off_w + (int64_t)w * N;
   float2 SG[E], X[E];
+  float WR[WT ? E : 1];  // ROI weights of this lane's cells (0 where a cell holds no delay)
   static_for<E>([&](auto ec) {
     constexpr int e = decltype(ec)::value;
-    SG[e] = sg[pass_spec_slot<P>(t, e)];  // the partner spectra are stored in the throughput pass's layout
     X[e] = make_float2(0.f, 0.f);
-    if constexpr (e < EH) {
+    if constexpr (e < EH) {  // every load issued (clamped index), the tail zeroed after
       const int n = t + 64 * e;
-      if (n < N) X[e] = sw[n];
+      X[e] = sw[n < N ? n : N - 1];
     }
   });
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    SG[e] = sg[e * 64 + t];  // the one-wave layout (spec_wave) at P = 1024; the same as the pass layout below
+  });
+  if constexpr (WT) {
+    static_for<E>([&](auto ec) {
+      constexpr int e = decltype(ec)::value;
+      const int k = t + 64 * e;
+      const bool lo = k <= N - 1, hi = k >= P - N + 1;
+      const int tp = lo ? -k : P - k;
+      const int tau = a.orient ? -tp : tp;
+      WR[e] = wrow[(lo || hi) ? tau + N - 1 : 0];
+    });
+  }
+  __builtin_amdgcn_sched_barrier(0);  // every load above is issued before the table arithmetic
+  if constexpr (WT) {
+    static_for<E>([&](auto ec) {
+      constexpr int e = decltype(ec)::value;
+      const int k = t + 64 * e;
+      if (!(k <= N - 1 || k >= P - N + 1)) WR[e] = 0.f;
+    });
+  }
   for (int i = threadIdx.x; i < P; i += 64 * WV) tw_tab[i] = tw_exact<P>(i);
   for (int i = threadIdx.x; i < UB * 65; i += 64 * WV) {
     const int jj = i / 65, tt = i - jj * 65;
     const int fj = min(grp * UB + jj, F - 1);
     ph_tab[jj][tt] = phasor(tt, doppler_nu(pl, fj, a.orient), invN);
   }
-  __syncthreads();
+  block_lds_sync();
   TwiddlesG<G> W;
   W.init_table(t, tw_tab);
   auto phasor_row_tab = [&](float2 (&ph)[EH]) {
@@ -2242,7 +2286,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
     phasor_row_tab(ph);
     static_for<EH>([&](auto ec) {
       constexpr int e = decltype(ec)::value;
-      X[e] = cmul(X[e], ph[e]);
+      X[e] = t + 64 * e < N ? cmul(X[e], ph[e]) : make_float2(0.f, 0.f);
     });
   }
   fft_forward_g<G>(X, buf, t, W);
@@ -2259,7 +2303,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   int kbest;
   if (a.cube != nullptr && active)
     cube_store<P, 64, E>(R, t, N, a.cube + pl.off_cube + ((int64_t)(w * M + g) * F + f) * (2 * N - 1));
-  if constexpr (WT) roi_weigh<P, 64, E>(R, t, N, a.orient, wrow);  // a = w |A| / N from here on
+  if constexpr (WT) roi_weigh_reg<E>(R, WR);  // a = w |A| / N from here on
   roi_scan<P, 64, E>(R, t, N, wlo, whi, g == w, vmask, qmax, kbest);
   // wave maximum, and its cell from the lowest lane that holds it
   const float qw = wave_max(qmax);
@@ -2270,7 +2314,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   const float sigma = sqrtf(qw);
   float S = 0.f;
   roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? 1.0f / sigma : 0.f, phm1, S);
-  if constexpr (WT) roi_weigh<P, 64, E>(R, t, N, a.orient, wrow);  // d(w|r|)^p / dr carries w^2
+  if constexpr (WT) roi_weigh_reg<E>(R, WR);  // d(w|r|)^p / dr carries w^2
   S = wave_sum(S);
   if (t == 0) {
     g_sig[wv] = active ? sigma : 0.f;
@@ -2286,10 +2330,10 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
       buf[e * 64 + t] = cmul(R[e], SG[e]);
     });
   }
-  __syncthreads();
+  block_lds_sync();
 
-  // per unit: the partner waves combined by the unit's first wave
-  if (wave_on && g == 0) {
+  // per unit: the partner waves combined by the unit's leader
+  if (wave_on && g == lead) {
     float su = 0.f;
     for (int gg = 0; gg < M; ++gg) su = fmaxf(su, g_sig[j * M + gg]);
     const float inv_u = su > 0.f ? 1.0f / su : 0.f;
@@ -2333,7 +2377,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
       });
     }
   }
-  __syncthreads();
+  block_lds_sync();
 
   // block combine over the UB units (unit order fixed)
   float sb = 0.f;
@@ -2368,7 +2412,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
         float cm1, cp;
         pow_ph<PHLOG>(c * c, phm1, cm1, cp);
         const float fc = cm1 * c;
-        const float2 v = lds[(jj * M) * G::SPAN + n];
+        const float2 v = lds[(jj * M + jj % M) * G::SPAN + n];
         acc.x += fc * v.x;
         acc.y += fc * v.y;
       }

@@ -20,7 +20,9 @@ struct ProbPlan {
   float w_psl, w_snrl, temperature, inv_NP;
   int32_t sq_mode, ph_log;  // ph_log = log2(p/2) when p/2 is a power of two <= 32, else -1
   int32_t units, row0;      // units = M*wpr statistics entries; row0 = first row in the batch
-  int32_t wpr, pad0;        // fused-pass blocks per row (ceil(F / Doppler bins per block))
+  int32_t wpr;              // fused-pass blocks per row (ceil(F / Doppler bins per block))
+  int32_t spec_wave;        // 1: partner spectra stored in the one-wave FFT layout (the latency
+                            // pass reads them), 0: in the throughput pass's layout
   int64_t off_z, off_w, off_state, off_cube;
   int64_t ws_spec;   // complex: [M][P] spectra
   int64_t ws_unit;   // UnitStat index and row index of upart ([units][N] complex, stride N)

@@ -731,6 +731,21 @@ void launch_step_p(const FinArgs& a, int lv, bool fuse, dim3 grid, hipStream_t s
   launch_step_pf<P, false>(a, lv, grid, s);
 }
 
+// k_grad over the rows of one FFT-length group: lanes per chip by the
+// group's chip count (one lane per chip from 65536 chips, 4 from 8192, else
+// 16), one statistics block per problem after the row blocks.
+void launch_grad(FinArgs& a, int nrows, int P, int nprob, const int32_t* gprob, hipStream_t s) {
+  const int64_t chips = (int64_t)nrows * (P / 2);
+  const int lpc = chips >= 65536 ? 1 : (chips >= 8192 ? 4 : 16);
+  a.grad_chunks = grad_chunks(P, lpc);
+  a.grad_nprob = nprob;
+  a.gprob = gprob;
+  const dim3 grid(nrows * a.grad_chunks + nprob), block(kGradThreads);
+  if (lpc == 1) hipLaunchKernelGGL(k_grad<1>, grid, block, 0, s, a);
+  else if (lpc == 4) hipLaunchKernelGGL(k_grad<4>, grid, block, 0, s, a);
+  else hipLaunchKernelGGL(k_grad<16>, grid, block, 0, s, a);
+}
+
 void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
   a.plans = w.plans;
   a.row_prob = w.row_prob;
@@ -754,12 +769,8 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
       const int lv = pl.group_step[g];
       const bool fuse = pl.group_fuse[g];
       if (!fuse) {
-        // gradient rows: N <= P/2 chips per row in blocks of kGradChips
-        a.grad_chunks = (1 << (g + kMinLogP)) / (2 * kGradChips);
-        a.grad_nprob = pl.hdr.group_n[g];
-        a.gprob = (const int32_t*)(w.base + pl.hdr.group_prob[g]);
-        hipLaunchKernelGGL(k_grad, dim3(pl.hdr.group_nrows[g] * a.grad_chunks + a.grad_nprob), dim3(kGradThreads),
-                           0, s, a);
+        launch_grad(a, pl.hdr.group_nrows[g], 1 << (g + kMinLogP), pl.hdr.group_n[g],
+                    (const int32_t*)(w.base + pl.hdr.group_prob[g]), s);
       }
       switch (g) {
         case 0: launch_step_p<128>(a, lv, fuse, grid, s); break;
@@ -779,11 +790,8 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
     // gradient rows from k_grad
     if (a.mode == FIN_STEP_A || a.mode == FIN_STEP_B || (a.mode == FIN_GRAD && g + kMinLogP >= 12)) {
       // gradient rows by the wide kernel first; k_final then skips the partial sums
-      af.grad_chunks = (1 << (g + kMinLogP)) / (2 * kGradChips);
-      af.grad_nprob = pl.hdr.group_n[g];
-      af.gprob = (const int32_t*)(w.base + pl.hdr.group_prob[g]);
-      hipLaunchKernelGGL(k_grad, dim3(pl.hdr.group_nrows[g] * af.grad_chunks + af.grad_nprob), dim3(kGradThreads),
-                         0, s, af);
+      launch_grad(af, pl.hdr.group_nrows[g], 1 << (g + kMinLogP), pl.hdr.group_n[g],
+                  (const int32_t*)(w.base + pl.hdr.group_prob[g]), s);
       af.grad_in = w.gbuf;
     }
     switch (g) {

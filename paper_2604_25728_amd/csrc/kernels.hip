@@ -1600,10 +1600,15 @@ __device__ __forceinline__ void block_sum5(float (&v)[5], float* sh) {
   }
 }
 
-constexpr int kGradChips = 16;                    // chips per k_grad block
-constexpr int kGradThreads = 16 * kGradChips;     // 16 lanes per chip
+constexpr int kGradThreads = 256;
 constexpr int kGradWaves = kGradThreads / 64;
-constexpr int kGradK = 8;                         // Doppler partials per lane and load round
+constexpr int kGradK = 8;                         // Doppler partials a lane loads per round
+constexpr int kGradMaxNE = 4096;                  // partial rows per row: at most F (one per Doppler bin)
+// k_grad row blocks per batch row of FFT length P (N <= P / 2 chips), LPC
+// lanes per chip
+__host__ __device__ constexpr int grad_chunks(int P, int LPC) {
+  return P / 2 > kGradThreads / LPC ? P / 2 / (kGradThreads / LPC) : 1;
+}
 
 // Per problem of the launch, after the row blocks: one statistics block
 // (L_p, maxima, loss, the record and the non-finite flag).
@@ -1640,10 +1645,23 @@ __device__ __forceinline__ void grad_units(const ProbPlan& pl, const UnitStat* u
   }
 }
 
+// Gradient rows from the fused pass's per-block partial rows (eq. 37-42 by
+// the adjoint): LPC lanes per chip n sum the row's NE partials, lane `sub`
+// of a chip taking j = sub, sub + LPC, ... , each weighted by
+// (sigma_j / L_p)^(p-1) (one factor per partial, from LDS); the LPC lane sums
+// are then added in a fixed butterfly order. A wave's lanes with the same sub
+// read 64 / LPC consecutive chips of one partial row (whole cache lines).
+// Large batches take one lane per chip (few, long rows of loads per lane);
+// small ones 4 or 16, which shortens each lane's chain of dependent load
+// rounds. One more block per problem writes the statistics.
+template <int LPC>
 __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
+  constexpr int CPW = 64 / LPC;            // chips per wave
+  constexpr int CPB = kGradThreads / LPC;  // chips per block
   __shared__ float shw[2 * kGradWaves];
   __shared__ unsigned long long shk[2 * kGradWaves];
   __shared__ float4 snrl_sh[16];
+  __shared__ float fj_sh[kGradMaxNE];
   const int tid = threadIdx.x;
   const int nrb = gridDim.x - a.grad_nprob;  // row blocks
   const bool stat_block = (int)blockIdx.x >= nrb;
@@ -1667,22 +1685,20 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
   }
   const int M = pl.M, N = pl.N, NE = pl.wpr;
   const int m = stat_block ? 0 : r - pl.row0;
-  if (!stat_block && chunk * kGradChips >= N) return;  // whole block beyond the row
-  const int n = chunk * kGradChips + (tid >> 4), sub = tid & 15;
+  if (!stat_block && chunk * CPB >= N) return;  // whole block beyond the row
+  const int lane = tid & 63, sub = lane / CPW;
+  const int n = chunk * CPB + (tid >> 6) * CPW + lane % CPW;
   const bool on = !stat_block && n < N;
   const int64_t wrow = pl.off_w + (int64_t)m * N;
 
-  // ---- loads
+  // ---- loads: the first round of partials, then the statistics they wait on
   const UnitStat* us = a.ustat + pl.ws_unit;
-  const float2* up = a.upart + pl.ws_upart + (int64_t)m * NE * N + n;
-  float sj[kGradK];
+  const float2* up = a.upart + pl.ws_upart + (int64_t)m * NE * N + (on ? n : 0);
   float2 v[kGradK];
 #pragma unroll
   for (int k = 0; k < kGradK; ++k) {
-    const int j = sub + 16 * k;
-    const bool ok = on && j < NE;
-    sj[k] = ok ? us[m * NE + j].sigma : 0.f;
-    v[k] = ok ? up[(int64_t)j * N] : make_float2(0.f, 0.f);
+    const int j = sub + LPC * k;
+    v[k] = on && j < NE ? up[(int64_t)j * N] : make_float2(0.f, 0.f);
   }
   const float2 pw = on ? a.part_w[wrow + n] : make_float2(0.f, 0.f);
   if (tid < M) snrl_sh[tid] = a.snrl[pl.row0 + tid];
@@ -1735,35 +1751,42 @@ __global__ __launch_bounds__(kGradThreads) void k_grad(FinArgs a) {
     return;
   }
 
-  // ---- gradient of the chip
+  // ---- the partials' factors (sigma_j / L_p)^(p-1), once per row block
+  const float cfac = pl.w_psl / ((float)N * (float)pl.P);
+  const float inv_lp = lp_raw > 0.f ? 1.0f / lp_raw : 0.f;
+  for (int j = tid; j < NE; j += kGradThreads)
+    fj_sh[j] = lp_raw > 0.f ? cfac * pow_pm1(us[m * NE + j].sigma * inv_lp, pl) : 0.f;
+  __syncthreads();
+
+  // ---- gradient of the chip: each lane its partials in order, then the
+  // chip's LPC lanes
   float2 g = make_float2(0.f, 0.f);
-  if (lp_raw > 0.f) {
-    const float cfac = pl.w_psl / ((float)N * (float)pl.P);
-    const float inv_lp = 1.0f / lp_raw;
+#pragma unroll
+  for (int k = 0; k < kGradK; ++k) {
+    const int j = sub + LPC * k;
+    const float f = j < NE ? fj_sh[j] : 0.f;
+    g.x += f * v[k].x;
+    g.y += f * v[k].y;
+  }
+  for (int j0 = LPC * kGradK; j0 < NE; j0 += LPC * kGradK) {
 #pragma unroll
     for (int k = 0; k < kGradK; ++k) {
-      const float f = cfac * pow_pm1(sj[k] * inv_lp, pl);
+      const int j = j0 + sub + LPC * k;
+      v[k] = on && j < NE ? up[(int64_t)j * N] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < kGradK; ++k) {
+      const int j = j0 + sub + LPC * k;
+      const float f = j < NE ? fj_sh[j] : 0.f;
       g.x += f * v[k].x;
       g.y += f * v[k].y;
     }
-    for (int j0 = 16 * kGradK; j0 < NE; j0 += 16 * kGradK) {
-#pragma unroll
-      for (int k = 0; k < kGradK; ++k) {
-        const int j = j0 + sub + 16 * k;
-        const bool ok = on && j < NE;
-        sj[k] = ok ? us[m * NE + j].sigma : 0.f;
-        v[k] = ok ? up[(int64_t)j * N] : make_float2(0.f, 0.f);
-      }
-#pragma unroll
-      for (int k = 0; k < kGradK; ++k) {
-        const float f = cfac * pow_pm1(sj[k] * inv_lp, pl);
-        g.x += f * v[k].x;
-        g.y += f * v[k].y;
-      }
-    }
   }
-  g.x = slot_reduce<16>(g.x, 0.0f, OpAdd());
-  g.y = slot_reduce<16>(g.y, 0.0f, OpAdd());
+#pragma unroll
+  for (int off = CPW; off < 64; off <<= 1) {
+    g.x += __shfl_xor(g.x, off);
+    g.y += __shfl_xor(g.y, off);
+  }
   const float4 cm = snrl_sh[m];
   const float magm = sqrtf(cm.x * cm.x + cm.y * cm.y);
   if (magm > 0.f) {

@@ -319,6 +319,56 @@ def test_every_schedule_gives_the_same_results(ref, nat, sched):
     assert _rel(c[2], gh_ref) <= 1e-4
 
 
+@pytest.mark.parametrize("sched", [1, 2, 4, 8])
+def test_every_schedule_at_fft_length_1024(ref, nat, sched):
+    """Every fused-pass schedule at FFT length 1024 (throughput; the latency
+    variant with 2, 4 or 8 waves per block, whose partner spectra the
+    producers store in the one-wave layout) on the paper's transmit AF shape,
+    M=2 N=512 F=129 with the |tau| <= 50 window as ROI weights: statistics and
+    both gradients, row by row, against the oracle and against the automatic
+    choice; then the cube of a short Doppler span under the same schedule
+    against the oracle's."""
+    base = I.make_problem(2, 512, 4, 129, p=16.0, w_psl=0.1, w_snrl=0.9)
+    w = I.roi_window_weights(base, 50)
+    z, h = I.logits(2, 512, 4, 60), I.complex_gaussian(2, 512, 61)
+    print(f"[gpu] FFT length 1024 schedule {sched}", flush=True)
+    out = {}
+    for s_ in (0, sched):
+        b = nat.Batch([dict(base, schedule=s_)])
+        b.set_roi_weights([w])
+        st = b.new_stats()
+        gz, gh, gs = b.af_backward(b.pack_z([z]), b.pack_w([h]), nat.WAVE_SOFT, want_s=True, stats=st)
+        torch.cuda.synchronize()
+        out[s_] = (nat.decode_stats(st.cpu().numpy())[0], gz.cpu().numpy(), gh.cpu().numpy(), gs.cpu().numpy())
+    a, c = out[0], out[sched]
+    assert abs(a[0]["loss"] - c[0]["loss"]) <= 1e-5 * a[0]["loss"]
+    for x, y in zip(a[1:], c[1:]):
+        assert _rel(y, x) <= 1e-5
+    pw = dict(base, roi_w=w.astype(np.float64))
+    sr = ref.soft_waveform(z.astype(np.float64), base["temperature"])
+    st_ref, gs_ref, gh_ref = ref.evaluate(sr, h.astype(np.complex128), pw)
+    _check_stats(c[0], st_ref, 512, sched)
+    _check_rows(c[3], gs_ref, (sched, "s"))
+    _check_rows(c[2], gh_ref, (sched, "h"))
+    gz_ref = ref.logit_grad(z.astype(np.float64), base["temperature"], gs_ref)
+    assert _rel(c[1], gz_ref) <= 1e-4
+    # the cube, unweighted, over a short span
+    small = I.make_problem(2, 512, 4, 9, nu_min=-0.5, nu_max=0.5, p=16.0)
+    zc, hc, sc = _problem_inputs(small, 62, 2)
+    b = nat.Batch([dict(small, schedule=sched)])
+    stats, cube = b.af_forward(b.pack_z([zc]), b.pack_w([hc]), nat.WAVE_GIVEN, s_given=b.pack_w([sc]), cube=True)
+    torch.cuda.synchronize()
+    cref = ref.af_cube(sc.astype(np.complex128), hc.astype(np.complex128), small["F"], small["nu_min"],
+                       small["nu_max"])
+    cg = b.unpack_cube(cube, 0).cpu().numpy()
+    assert np.abs(cg - cref).max() / np.abs(cref).max() <= 1e-4, sched
+    g = nat.decode_stats(stats.cpu().numpy())[0]
+    stc = ref.loss_stats(cref, sc.astype(np.complex128), hc.astype(np.complex128), small)
+    _check_stats(g, stc, 512, (sched, "cube"))
+    if check_peak(g, cref, small):
+        assert g["arg"] == stc["arg"]
+
+
 def test_autotuner_picks_a_candidate(nat, tmp_path):
     """The per-group tuner on one M=4 N=256 design (four candidates at FFT
     length 512) and on a three-group batch (512 with four candidates, 1024 with

@@ -310,9 +310,21 @@ struct TwiddlesG {
       col[7] = cmul(col[4], col[3]);
     }
     if constexpr (G::THREE) {
+      // powers 1, 2, 4 exact; 3, 5, 6, 7 as products (as lo and col)
       const int c = (unsigned)t % G::C;
+      constexpr int step = G::E * G::A;
       col2[0] = make_float2(1.f, 0.f);
-      for (int z = 1; z < G::B; ++z) col2[z] = tw_exact<P>(c * z * G::E * G::A);
+      if constexpr (G::B == 8) {
+        col2[1] = tw_exact<P>(c * step);
+        col2[2] = tw_exact<P>(2 * c * step);
+        col2[3] = cmul(col2[2], col2[1]);
+        col2[4] = tw_exact<P>(4 * c * step);
+        col2[5] = cmul(col2[4], col2[1]);
+        col2[6] = cmul(col2[4], col2[2]);
+        col2[7] = cmul(col2[4], col2[3]);
+      } else {
+        for (int z = 1; z < G::B; ++z) col2[z] = tw_exact<P>(c * z * step);
+      }
     }
   }
   // The same twiddles read from a table tab[k] = W_P^k, k < P (a block

@@ -695,7 +695,9 @@ __device__ __forceinline__ void pass_block(const PassArgs& a, int blk, PassSmem<
       sigma = mu;
     }
     // a/sigma = x^(1/2), x = |r|^2 / sigma^2:  S += x^(p/2);  G~ = x^(p/2 - 1) r / sigma
-    roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? 1.0f / sigma : 0.f, phm1, S);
+    // v_rcp (1 ulp) suffices for the inverse scale: every partial sum and
+    // gradient partial of the unit is taken relative to the same scale
+    roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? __builtin_amdgcn_rcpf(sigma) : 0.f, phm1, S);
     if constexpr (WT) roi_weigh<P, TF, E>(R, t, N, a.orient, wrow);  // d(w|r|)^p / dr carries w^2
     if (grad) {
       op = OP_ADJ;
@@ -2336,7 +2338,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   const unsigned long long key = holders ? make_key(qw, (uint32_t)(((int64_t)u * M + g) * P + kb)) : 0ull;
   const float sigma = sqrtf(qw);
   float S = 0.f;
-  roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? 1.0f / sigma : 0.f, phm1, S);
+  roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? __builtin_amdgcn_rcpf(sigma) : 0.f, phm1, S);
   if constexpr (WT) roi_weigh_reg<E>(R, WR);  // d(w|r|)^p / dr carries w^2
   S = wave_sum(S);
   if (t == 0) {

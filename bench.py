@@ -414,8 +414,9 @@ def both_gradient_rate(probs, seeds, reps: int = 5) -> dict:
 
 
 def single_design(I, nat, optim, name: str, steps: int, tuned: bool) -> dict:
-    """One design of a preset: ms per outer iteration (graph replays of one
-    iteration), its fused pass's roofline."""
+    """One design of a preset: ms per outer iteration (graph replays of ten
+    iterations each, as the optimiser runs between stopping checks), its
+    fused pass's roofline."""
     c = I.config(name)
     prob, opt = c["problem"], c["opt"]
     sched = None
@@ -426,7 +427,7 @@ def single_design(I, nat, optim, name: str, steps: int, tuned: bool) -> dict:
         log(f"{name}: schedule tuning (ms per step): " +
             ", ".join(f"{k}: {v * 1e3:.1f} us" for k, v in sched_ms.items()) + f" -> {sched}")
     run = optim.SQNGD([prob], opt, seeds=[0], schedule=sched)
-    ms, _, n, per = time_graph(run, steps, 10, 1)
+    ms, _, n, per = time_graph(run, steps, 20, 10)
     import numpy as np
     import torch
     torch.cuda.synchronize()
@@ -468,8 +469,10 @@ def main():
                     help="time only the transmit-side workloads (all, or one) and print them as one JSON line")
     ap.add_argument("--counters", action="store_true",
                     help="run the workload for rocprofv3 --pmc (eager iterations + calibration copy) and exit")
-    ap.add_argument("--workload", default="uneven", choices=["uneven", "m4n256", "wide_m8n1024"],
-                    help="workload of a --counters run")
+    ap.add_argument("--workload", default="uneven",
+                    choices=["uneven", "m4n256", "wide_m8n1024", "paper_m2n512_roi50"],
+                    help="workload of a --counters run (paper_m2n512_roi50: one design at the paper's transmit "
+                         "AF shape, M=2 N=512 L=4 F=129 with the |tau| <= 50 window as ROI weights)")
     ap.add_argument("--schedule", type=int, default=12,
                     help="fused-pass schedule hint of an m4n256 --counters run (the timed run tunes it)")
     args = ap.parse_args()
@@ -499,6 +502,9 @@ def main():
     if args.counters:
         if args.workload == "uneven":
             run = optim.SQNGD(probs, opt, seeds=seeds)
+        elif args.workload == "paper_m2n512_roi50":
+            pp = I.make_problem(2, 512, 4, 129, p=16.0)
+            run = optim.SQNGD([pp], opt, seeds=[0], roi_weights=[I.roi_window_weights(pp, 50)])
         else:
             c = I.config(args.workload)
             sched = args.schedule if args.workload == "m4n256" else None

@@ -154,6 +154,11 @@ typedef struct {
    among 8, 12 and 16 at 512 and among 4 and 8 at 1024); where it does not apply
    (another FFT length, M above the waves per block) the group falls back to
    AUTO.
+   PAIR: at FFT lengths 2048 and 4096, one block per (row, Doppler bin,
+   partner): four transforms per block and one statistics entry and gradient
+   partial row per pair (each problem's F M must be <= 4096); AUTO takes it
+   for groups of at most 2048 pairs (M M F summed), e.g. one M=2 N=1200
+   F=129 design. Elsewhere the group falls back to AUTO.
    The throughput groups of FFT length <= 2048 run either one launch per
    group or all in one launch, longest FFT length first (their p must select
    the same instantiation: p = 4, 8, 16, 32, 64 or the general form). FUSED
@@ -171,6 +176,7 @@ typedef struct {
 #define SQNGD_SCHED_SPLIT16 16
 #define SQNGD_SCHED_GROUPED 32
 #define SQNGD_SCHED_FUSED 33
+#define SQNGD_SCHED_PAIR 40
 
 /* Optimiser options of one outer iteration (Algorithm 1). */
 typedef struct {

@@ -49,6 +49,11 @@ constexpr int kSplitShapes1024[] = {4, 8};
 constexpr int kSplitExtra512[] = {4};
 constexpr int kSplitExtra1024[] = {2};
 constexpr int kMaxSplitWaves = 16;
+// Pair form of the pass (one block per (row, Doppler bin, partner)) at FFT
+// lengths 2048 and 4096: the rule takes it for groups of at most this many
+// pairs (a few rounds of the chip), where one throughput block per unit
+// would leave a partial second round of whole units.
+constexpr int64_t kPairMaxBlocks = 2048;
 constexpr double kSplitMaxWaves = 8192.0;
 constexpr int kNumCUs = 256;  // MI355X compute units: one block per CU is the aim
 // the gradient reduction moves into k_step for groups of at least this many
@@ -106,7 +111,8 @@ int validate_problem(const sqngd_problem& p) {
   if (p.reserved != 0) return SQNGD_E_INVALID_ARG;
   if (p.schedule != SQNGD_SCHED_AUTO && p.schedule != SQNGD_SCHED_THROUGHPUT && p.schedule != SQNGD_SCHED_SPLIT2 &&
       p.schedule != SQNGD_SCHED_SPLIT4 && p.schedule != SQNGD_SCHED_SPLIT8 && p.schedule != SQNGD_SCHED_SPLIT12 &&
-      p.schedule != SQNGD_SCHED_SPLIT16 && p.schedule != SQNGD_SCHED_GROUPED && p.schedule != SQNGD_SCHED_FUSED)
+      p.schedule != SQNGD_SCHED_SPLIT16 && p.schedule != SQNGD_SCHED_GROUPED && p.schedule != SQNGD_SCHED_FUSED &&
+      p.schedule != SQNGD_SCHED_PAIR)
     return SQNGD_E_INVALID_ARG;
   return SQNGD_OK;
 }
@@ -130,6 +136,7 @@ struct Plan {
   int group_phlog[kNumPGroups];
   int group_wv[kNumPGroups];  // waves per block of the latency variant (split groups)
   bool group_split[kNumPGroups];  // the group's pass runs as k_pass_split
+  bool group_pair[kNumPGroups];   // ... as k_pass_pair (one block per pair)
   // finalize of the optimiser steps: 0 = k_final, else k_step with this
   // bound on the logit levels per lane
   int group_step[kNumPGroups];
@@ -184,6 +191,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
   for (int g = 0; g < kNumPGroups; ++g) {
     pl->group_wv[g] = 0;
     pl->group_split[g] = false;
+    pl->group_pair[g] = false;
     if (ids_p[g].empty()) continue;
     const int P = 1 << (g + kMinLogP);
     int hint = SQNGD_SCHED_AUTO;
@@ -194,6 +202,15 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
       if (probs[id].M > kMaxSplitWaves) can = false;
       if (probs[id].M > 2) pairs2 = false;
       pair_waves += (double)probs[id].M * probs[id].M * probs[id].F;
+    }
+    if (P >= 2048) {
+      // pair blocks: every problem's F M partial rows must fit the finalize
+      bool fit = true;
+      for (int id : ids_p[g]) fit = fit && (int64_t)probs[id].F * probs[id].M <= 4096;
+      // a latency-variant hint (FFT length 512 / 1024 only) acts as AUTO here
+      const bool rule = hint == SQNGD_SCHED_AUTO || (hint >= SQNGD_SCHED_SPLIT2 && hint <= SQNGD_SCHED_SPLIT16);
+      pl->group_pair[g] = fit && (hint == SQNGD_SCHED_PAIR || (rule && pair_waves <= (double)kPairMaxBlocks));
+      continue;
     }
     bool split = can;
     if (hint == SQNGD_SCHED_AUTO) split = can && (pair_waves <= kSplitMaxWaves || pairs2);
@@ -215,7 +232,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     int mask = 0, phl = -2, nseg = 0;
     bool small = true, same = true;
     for (int g = 0; g < kNumPGroups - 1; ++g) {
-      if (ids_p[g].empty() || pl->group_split[g]) continue;
+      if (ids_p[g].empty() || pl->group_split[g] || pl->group_pair[g]) continue;
       const int P = 1 << (g + kMinLogP);
       int64_t blocks = 0;
       int gphl = -2;
@@ -265,14 +282,16 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     q.row0 = rows;
     {
       int upb;  // Doppler bins per fused-pass block
-      if (pl->group_split[q.logP - kMinLogP]) {
+      if (pl->group_pair[q.logP - kMinLogP]) {
+        upb = 0;  // one block per (Doppler bin, partner): wpr = F M below
+      } else if (pl->group_split[q.logP - kMinLogP]) {
         upb = pl->group_wv[q.logP - kMinLogP] / p.M;
       } else if ((pl->fuse_mask >> (q.logP - kMinLogP)) & 1) {
         upb = pass_upb(q.P, 4);  // four-wave blocks of the one-launch pass
       } else {
         upb = pass_upb(q.P);
       }
-      q.wpr = (p.F + upb - 1) / upb;
+      q.wpr = upb == 0 ? p.F * p.M : (p.F + upb - 1) / upb;
       // the latency pass reads the spectra in the one-wave layout the
       // producers compute them in (the layouts coincide below P = 1024)
       q.spec_wave = pl->group_split[q.logP - kMinLogP] && q.P >= 1024 ? 1 : 0;
@@ -607,6 +626,16 @@ void launch_split(int P, int wv, const PassArgs& a, int phlog, int blocks, hipSt
 }
 
 template <int P>
+void launch_pair_p(const PassArgs& a, int phlog, int blocks, hipStream_t s) {
+  const dim3 block(64 * PassGeom<P>::WAVES);
+  if (a.roi_w != nullptr && phlog == 3) hipLaunchKernelGGL((k_pass_pair<P, 3, true>), dim3(blocks), block, 0, s, a);
+  else if (a.roi_w != nullptr) hipLaunchKernelGGL((k_pass_pair<P, -1, true>), dim3(blocks), block, 0, s, a);
+  else if (phlog == 3) hipLaunchKernelGGL((k_pass_pair<P, 3, false>), dim3(blocks), block, 0, s, a);
+  else if (phlog == 2) hipLaunchKernelGGL((k_pass_pair<P, 2, false>), dim3(blocks), block, 0, s, a);
+  else hipLaunchKernelGGL((k_pass_pair<P, -1, false>), dim3(blocks), block, 0, s, a);
+}
+
+template <int P>
 void launch_pass_p(const PassArgs& a, int phlog, int waves, hipStream_t s) {
   const dim3 block(64 * pass_waves(P));
   if (a.roi_w != nullptr && phlog == 3) hipLaunchKernelGGL((k_pass<P, 3, true>), dim3(waves), block, 0, s, a);
@@ -691,7 +720,10 @@ void launch_pass(const Plan& pl, const Ptrs& w, PassArgs a, hipStream_t s) {
     const int slot = prof_begin(s, 1 << g);
     const int reps = slot >= 0 ? g_prof.repeat : 1;
     for (int rep = 0; rep < reps; ++rep, a.bump = nullptr) {
-      if (pl.group_split[g]) {
+      if (pl.group_pair[g]) {
+        if (g + kMinLogP == 11) launch_pair_p<2048>(a, phl, waves, s);
+        else launch_pair_p<4096>(a, phl, waves, s);
+      } else if (pl.group_split[g]) {
         launch_split(1 << (g + kMinLogP), pl.group_wv[g], a, phl, waves, s);
       } else {
         switch (g) {

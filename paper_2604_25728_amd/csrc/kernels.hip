@@ -185,6 +185,21 @@ __device__ __forceinline__ void roi_weigh_reg(float2 (&R)[E], const float (&wr)[
   });
 }
 
+// The ROI weights of lane t's cells from the table row wrow = w(., f) (the
+// indexing of roi_weigh), 0 where a cell holds no delay; every load issued.
+template <int P, int TF, int E>
+__device__ __forceinline__ void roi_weights_load(float (&wr)[E], int t, int N, int orient, const float* wrow) {
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    const int k = t + TF * e;
+    const bool lo = k <= N - 1, hi = k >= P - N + 1;
+    const int tp = lo ? -k : P - k;
+    const int tau = orient ? -tp : tp;
+    const float v = wrow[(lo || hi) ? tau + N - 1 : 0];
+    wr[e] = (lo || hi) ? v : 0.f;
+  });
+}
+
 // AF cells of one row into the cube [w][g][f][tau + N - 1] (scaled by 1/P).
 template <int P, int TF, int E>
 __device__ __forceinline__ void cube_store(const float2 (&R)[E], int t, int N, float2* row) {
@@ -1365,19 +1380,27 @@ __global__ __launch_bounds__(kFinThreads) void k_final(FinArgs a) {
       const float Tn = temperature_at(a.opt, tstep + (a.next == NEXT_B_SOFT ? a.next_t_offset : 0));
       const bool soft_grad = chain_out ? a.wave_mode == SQNGD_WAVE_SOFT : zupd;
       const float tw = 2.0f * 3.14159265358979f / (float)L;
+      // the next round's loads are issued before this round's arithmetic
+      // (a round's elements are disjoint from every other round's, and each
+      // is written only by the thread that reads it)
+      float zq = zv0, mq = m0, vq = v0;
+      float2 sq0 = s0;
       for (int base = 0; base < N * LP; base += kFinThreads) {
         const int i = base + tid, en = i >> lg, el = i & (LP - 1);
         const bool ok = en < N && el < L;
-        float zv = zv0, mm = m0, vv = v0;
-        float2 s = s0;
+        float zv = zq, mm = mq, vv = vq;
+        float2 s = sq0;
         const int64_t zi = pl.off_z + (crow + en) * L + el;
-        if (base > 0 && ok) {
-          zv = a.z[zi];
-          if (zstep) {
-            mm = a.adam[pl.off_state + (crow + en) * L + el];
-            vv = a.adam[pl.off_state + (int64_t)M * N * L + (crow + en) * L + el];
+        {
+          const int i2 = i + kFinThreads, en2 = i2 >> lg, el2 = i2 & (LP - 1);
+          if (en2 < N && el2 < L) {
+            zq = a.z[pl.off_z + (crow + en2) * L + el2];
+            if (zstep) {
+              mq = a.adam[pl.off_state + (crow + en2) * L + el2];
+              vq = a.adam[pl.off_state + (int64_t)M * N * L + (crow + en2) * L + el2];
+            }
+            if (zstep || chain_out) sq0 = a.self_w[wrow + en2];
           }
-          if (zstep || chain_out) s = a.self_w[wrow + en];
         }
         if (chain_out || zupd) {
           // dL/dz through the soft quantiser at Tc (chip softmax from the L lanes)
@@ -2443,6 +2466,128 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
       }
       up[n] = acc;
     }
+  }
+}
+
+// ------------------------------------------------------------- k_pass_pair
+
+// Latency form of the pass at the FFT lengths whose transform spans a whole
+// block (P >= 2048): one block per (row w, Doppler bin f, partner g) pair.
+// The block computes the modulated self spectrum, the pair's AF row, its ROI
+// statistics, the adjoint and that partner's own share of the gradient row
+// (the inverse transform of adjoint x partner spectrum, demodulated): four
+// transforms in sequence where the throughput pass runs 2M + 2 per unit. The
+// pairs' statistics and gradient partial rows are separate entries, each
+// relative to its own scale (the finalize combines any number of them), so
+// no partial sum over partners is held and the block needs one exchange
+// buffer of LDS. For single designs whose units barely exceed the compute
+// units (M=2 N=1200 F=129: 258 units, 516 pairs), where one block of the
+// throughput pass per unit leaves a second round of whole units.
+template <int P, int PHLOG, bool WT>
+__global__ __launch_bounds__(64 * PassGeom<P>::WAVES, 4) void k_pass_pair(PassArgs a) {
+  using G = PassGeom<P>;
+  static_assert(G::WAVES >= 4, "a transform spans the block");
+  constexpr int E = G::E, TF = G::TF, EH = E / 2;
+  __shared__ float2 lds[G::SPAN];
+  __shared__ float red_f[G::WAVES];
+  __shared__ unsigned long long red_k[G::WAVES];
+  const int t = threadIdx.x;
+  const int blk = blockIdx.x;
+  if (a.bump != nullptr && blk == 0 && t == 0) atomicAdd(a.bump, 1);
+  int base = 0;
+  ProbPlan pl;
+  if (a.single) {
+    pl = a.one;
+  } else {
+    const int entry = find_entry(a.gwave, a.gn, blk);
+    pl = a.plans[a.gprob[entry]];
+    base = a.gwave[entry];
+  }
+  const int M = pl.M, N = pl.N, F = pl.F;
+  // blocks of a problem: wpr = F M per row, rows in order; within a row
+  // Doppler bin major, partner minor
+  const int lb = blk - base;
+  const int w = lb / pl.wpr;
+  const int rem = lb - w * pl.wpr;
+  const int f = rem / M, g = rem - (rem / M) * M;
+  const int u = w * F + f;
+  const double invN = 1.0 / (double)N;
+  const double nu = doppler_nu(pl, f, a.orient);
+  const int wlo = a.orient ? -pl.tau_hi : pl.tau_lo;
+  const int whi = a.orient ? -pl.tau_lo : pl.tau_hi;
+  const float phm1 = 0.5f * pl.p - 1.0f;
+  const bool grad = a.want_grad != 0;
+
+  // global loads first, in the order they are needed
+  const float2* sw = a.self_w + pl.off_w + (int64_t)w * N;
+  const float2* sg = a.spec + pl.ws_spec + (int64_t)g * P;
+  float2 R[E];
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    R[e] = make_float2(0.f, 0.f);
+    if constexpr (e < EH) {
+      const int n = t + TF * e;
+      R[e] = sw[n < N ? n : N - 1];
+    }
+  });
+  float WR[WT ? E : 1];
+  if constexpr (WT) roi_weights_load<P, TF, E>(WR, t, N, a.orient, a.roi_w + pl.off_rw + (int64_t)f * (2 * N - 1));
+  TwiddlesG<G> W;
+  W.init(t);
+  {
+    float2 ph[EH];
+    phasor_row<EH, TF>(t, nu, invN, ph);
+    static_for<EH>([&](auto ec) {
+      constexpr int e = decltype(ec)::value;
+      R[e] = t + TF * e < N ? cmul(R[e], ph[e]) : make_float2(0.f, 0.f);
+    });
+  }
+  fft_forward_g<G>(R, lds, t, W);  // X, the modulated self spectrum
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    R[e] = cmulc(R[e], sg[e * TF + t]);
+  });
+  fft_inverse_g<G>(R, lds, t, W);  // P A(tau') of the pair at r-index k = t + TF e
+  if (a.cube != nullptr)
+    cube_store<P, TF, E>(R, t, N, a.cube + pl.off_cube + ((int64_t)(w * M + g) * F + f) * (2 * N - 1));
+  if constexpr (WT) roi_weigh_reg<E>(R, WR);  // a = w |A| / N from here on
+  uint32_t vmask;
+  float qmax;
+  int kbest;
+  roi_scan<P, TF, E>(R, t, N, wlo, whi, g == w, vmask, qmax, kbest);
+  unsigned long long key = vmask ? make_key(qmax, (uint32_t)(((int64_t)u * M + g) * P + kbest)) : 0ull;
+  key = fft_lanes_max_key<G>(key, red_k);
+  qmax = fft_lanes_reduce<G>(qmax, 0.0f, OpMax(), red_f);
+  const float sigma = sqrtf(qmax);
+  float S = 0.f;
+  roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? __builtin_amdgcn_rcpf(sigma) : 0.f, phm1, S);
+  if constexpr (WT) roi_weigh_reg<E>(R, WR);  // d(w|r|)^p / dr carries w^2
+  S = fft_lanes_reduce<G>(S, 0.0f, OpAdd(), red_f);
+  const int64_t ent = (int64_t)w * pl.wpr + rem;
+  if (t == 0) {
+    UnitStat st;
+    st.sigma = sigma;
+    st.S = S;
+    st.pad0 = st.pad1 = 0;
+    st.key_auto = g == w ? key : 0ull;
+    st.key_cross = g == w ? 0ull : key;
+    a.ustat[pl.ws_unit + ent] = st;
+  }
+  if (grad) {
+    fft_forward_g<G>(R, lds, t, W);  // the adjoint's spectrum
+    static_for<E>([&](auto ec) {
+      constexpr int e = decltype(ec)::value;
+      R[e] = cmul(R[e], sg[e * TF + t]);
+    });
+    fft_inverse_g<G>(R, lds, t, W);  // this partner's share of the self gradient
+    float2 ph[EH];
+    phasor_row<EH, TF>(t, nu, invN, ph);
+    float2* up = a.upart + pl.ws_upart + ent * N;
+    static_for<EH>([&](auto ec) {
+      constexpr int e = decltype(ec)::value;
+      const int n = t + TF * e;
+      if (n < N) up[n] = cmulc(R[e], ph[e]);
+    });
   }
 }
 

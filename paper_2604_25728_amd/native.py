@@ -19,7 +19,7 @@ WAVE_SOFT, WAVE_HARD, WAVE_GIVEN = 0, 1, 2
 SQ_PHASE_MEAN, SQ_PHASOR_MEAN = 0, 1
 OPT_SGD = 1
 SCHED_AUTO, SCHED_THROUGHPUT, SCHED_SPLIT2, SCHED_SPLIT4, SCHED_SPLIT8, SCHED_SPLIT12, SCHED_SPLIT16 = 0, 1, 2, 4, 8, 12, 16
-SCHED_GROUPED, SCHED_FUSED = 32, 33
+SCHED_GROUPED, SCHED_FUSED, SCHED_PAIR = 32, 33, 40
 
 SYMBOLS = [
     "sqngd_buffer_sizes", "sqngd_workspace_size", "sqngd_workspace_init", "sqngd_af_forward",

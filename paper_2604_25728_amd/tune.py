@@ -23,6 +23,9 @@ from . import native as nat
 
 SPLIT_SHAPES = {512: (nat.SCHED_SPLIT4, nat.SCHED_SPLIT8, nat.SCHED_SPLIT12, nat.SCHED_SPLIT16),
                 1024: (nat.SCHED_SPLIT2, nat.SCHED_SPLIT4, nat.SCHED_SPLIT8)}
+# the pair form (one block per (row, Doppler bin, partner)) at the FFT lengths
+# whose transform spans a block, while each problem's F M partial rows fit
+PAIR_LENGTHS = (2048, 4096)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2604_25728_amd", "tune.json")
 _cache: dict = {}
 
@@ -50,6 +53,8 @@ def candidates(probs) -> dict:
     for P in sorted({fft_len(p["N"]) for p in probs}):
         mmax = max(p["M"] for p in probs if fft_len(p["N"]) == P)
         out[P] = [nat.SCHED_THROUGHPUT] + [c for c in SPLIT_SHAPES.get(P, ()) if mmax <= c]
+        if P in PAIR_LENGTHS and all(p["F"] * p["M"] <= 4096 for p in probs if fft_len(p["N"]) == P):
+            out[P].append(nat.SCHED_PAIR)
     return out
 
 

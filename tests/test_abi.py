@@ -106,8 +106,8 @@ def test_reserved_and_pair_count_limits(nat):
     arr = _arr(nat)
     arr[0].reserved = 1
     assert _ws_size(nat, arr)[0] == -1
-    for sched, code in ((3, -1), (-1, -1), (34, -1), (0, 0), (1, 0), (2, 0), (4, 0), (8, 0), (12, 0), (16, 0),
-                        (32, 0), (33, 0)):
+    for sched, code in ((3, -1), (-1, -1), (34, -1), (41, -1), (0, 0), (1, 0), (2, 0), (4, 0), (8, 0), (12, 0),
+                        (16, 0), (32, 0), (33, 0), (40, 0)):
         arr = _arr(nat)
         arr[0].schedule = sched
         assert _ws_size(nat, arr)[0] == code, sched

@@ -369,6 +369,54 @@ def test_every_schedule_at_fft_length_1024(ref, nat, sched):
         assert g["arg"] == stc["arg"]
 
 
+@pytest.mark.parametrize("N", [1000, 1200])
+@pytest.mark.parametrize("sched", [1, 40])
+def test_pair_and_throughput_forms_at_fft_lengths_2048_and_4096(ref, nat, N, sched):
+    """The throughput pass and the pair form (one block per (row, Doppler
+    bin, partner), its own statistics entry and gradient partial row) at FFT
+    lengths 2048 (N=1000) and 4096 (N=1200), M=2 F=9 with the |tau| <= 50
+    window as ROI weights: statistics, both gradients row by row and the
+    logit gradient against the oracle and against the automatic choice; then
+    the unweighted cube and peak under the same schedule."""
+    base = I.make_problem(2, N, 16, 9, p=16.0, w_psl=0.1, w_snrl=0.9)
+    w = I.roi_window_weights(base, 50)
+    z, h = I.logits(2, N, 16, 63), I.complex_gaussian(2, N, 64)
+    print(f"[gpu] N={N} schedule {sched}", flush=True)
+    out = {}
+    for s_ in (0, sched):
+        b = nat.Batch([dict(base, schedule=s_)])
+        b.set_roi_weights([w])
+        st = b.new_stats()
+        gz, gh, gs = b.af_backward(b.pack_z([z]), b.pack_w([h]), nat.WAVE_SOFT, want_s=True, stats=st)
+        torch.cuda.synchronize()
+        out[s_] = (nat.decode_stats(st.cpu().numpy())[0], gz.cpu().numpy(), gh.cpu().numpy(), gs.cpu().numpy())
+    a, c = out[0], out[sched]
+    assert abs(a[0]["loss"] - c[0]["loss"]) <= 1e-5 * a[0]["loss"]
+    for x, y in zip(a[1:], c[1:]):
+        assert _rel(y, x) <= 1e-5
+    pw = dict(base, roi_w=w.astype(np.float64))
+    sr = ref.soft_waveform(z.astype(np.float64), base["temperature"])
+    st_ref, gs_ref, gh_ref = ref.evaluate(sr, h.astype(np.complex128), pw)
+    _check_stats(c[0], st_ref, N, (N, sched))
+    _check_rows(c[3], gs_ref, (N, sched, "s"))
+    _check_rows(c[2], gh_ref, (N, sched, "h"))
+    assert _rel(c[1], ref.logit_grad(z.astype(np.float64), base["temperature"], gs_ref)) <= 1e-4
+    small = I.make_problem(2, N, 4, 5, nu_min=-0.5, nu_max=0.5, p=16.0)
+    zc, hc, sc = _problem_inputs(small, 65, 2)
+    b = nat.Batch([dict(small, schedule=sched)])
+    stats, cube = b.af_forward(b.pack_z([zc]), b.pack_w([hc]), nat.WAVE_GIVEN, s_given=b.pack_w([sc]), cube=True)
+    torch.cuda.synchronize()
+    cref = ref.af_cube(sc.astype(np.complex128), hc.astype(np.complex128), small["F"], small["nu_min"],
+                       small["nu_max"])
+    cg = b.unpack_cube(cube, 0).cpu().numpy()
+    assert np.abs(cg - cref).max() / np.abs(cref).max() <= 1e-4, (N, sched)
+    g = nat.decode_stats(stats.cpu().numpy())[0]
+    stc = ref.loss_stats(cref, sc.astype(np.complex128), hc.astype(np.complex128), small)
+    _check_stats(g, stc, N, (N, sched, "cube"))
+    if check_peak(g, cref, small):
+        assert g["arg"] == stc["arg"]
+
+
 def test_autotuner_picks_a_candidate(nat, tmp_path):
     """The per-group tuner on one M=4 N=256 design (four candidates at FFT
     length 512) and on a three-group batch (512 with four candidates, 1024 with

@@ -1909,13 +1909,33 @@ __global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
   float* amz = a.adam + pl.off_state + (crow + n) * L;
   float* avz = amz + (int64_t)M * N * L;
   float zl[LVMAX], mz[LVMAX], vz[LVMAX];
+  // one lane per chip with L a multiple of 4 and aligned rows: the chip's
+  // logits and moments move as 16-byte vectors (a quarter of the accesses,
+  // each lane's 4 L bytes contiguous)
+  const bool vec4 = TPC == 1 && LVMAX % 4 == 0 && (L & 3) == 0 && ((pl.off_z | pl.off_state) & 3) == 0 &&
+                    (((uintptr_t)a.z | (uintptr_t)a.adam) & 15) == 0;
+  if (vec4) {
 #pragma unroll
-  for (int k = 0; k < LVMAX; ++k) {
-    const int l = sub + TPC * k;
-    const bool ok = on && l < L && need_z;
-    zl[k] = ok ? a.z[zrow + l] : -INFINITY;
-    mz[k] = ok && !kA && !sgd ? amz[l] : 0.f;
-    vz[k] = ok && !kA && !sgd ? avz[l] : 0.f;
+    for (int k4 = 0; k4 < LVMAX / 4; ++k4) {
+      const bool ok = on && 4 * k4 < L && need_z;
+      const bool okm = ok && !kA && !sgd;
+      const float4 z4 = ok ? *(const float4*)(a.z + zrow + 4 * k4)
+                           : make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+      const float4 m4 = okm ? *(const float4*)(amz + 4 * k4) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 v4 = okm ? *(const float4*)(avz + 4 * k4) : make_float4(0.f, 0.f, 0.f, 0.f);
+      zl[4 * k4] = z4.x, zl[4 * k4 + 1] = z4.y, zl[4 * k4 + 2] = z4.z, zl[4 * k4 + 3] = z4.w;
+      mz[4 * k4] = m4.x, mz[4 * k4 + 1] = m4.y, mz[4 * k4 + 2] = m4.z, mz[4 * k4 + 3] = m4.w;
+      vz[4 * k4] = v4.x, vz[4 * k4 + 1] = v4.y, vz[4 * k4 + 2] = v4.z, vz[4 * k4 + 3] = v4.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < LVMAX; ++k) {
+      const int l = sub + TPC * k;
+      const bool ok = on && l < L && need_z;
+      zl[k] = ok ? a.z[zrow + l] : -INFINITY;
+      mz[k] = ok && !kA && !sgd ? amz[l] : 0.f;
+      vz[k] = ok && !kA && !sgd ? avz[l] : 0.f;
+    }
   }
   if (want_spec)
     for (int i = N + tid; i < P; i += NT) rowbuf[i] = zero2;
@@ -2143,6 +2163,17 @@ __global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
       if (next == NEXT_B_FULL) prod = make_float4(c * prod.x, c * prod.y, prod.z, c * c * prod.w);
       if (next == NEXT_A_SNRL) prod = make_float4(c * prod.x, c * prod.y, c * c * prod.z, prod.w);
       cs = c;
+    } else if (vec4) {
+#pragma unroll
+      for (int k4 = 0; k4 < LVMAX / 4; ++k4) {
+        if (on && 4 * k4 < L) {
+          *(float4*)(a.z + zrow + 4 * k4) = make_float4(zl[4 * k4], zl[4 * k4 + 1], zl[4 * k4 + 2], zl[4 * k4 + 3]);
+          if (!sgd) {
+            *(float4*)(amz + 4 * k4) = make_float4(mz[4 * k4], mz[4 * k4 + 1], mz[4 * k4 + 2], mz[4 * k4 + 3]);
+            *(float4*)(avz + 4 * k4) = make_float4(vz[4 * k4], vz[4 * k4 + 1], vz[4 * k4 + 2], vz[4 * k4 + 3]);
+          }
+        }
+      }
     } else {
 #pragma unroll
       for (int k = 0; k < LVMAX; ++k) {

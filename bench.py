@@ -470,9 +470,9 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="run the workload for rocprofv3 --pmc (eager iterations + calibration copy) and exit")
     ap.add_argument("--workload", default="uneven",
-                    choices=["uneven", "m4n256", "wide_m8n1024", "paper_m2n512_roi50"],
-                    help="workload of a --counters run (paper_m2n512_roi50: one design at the paper's transmit "
-                         "AF shape, M=2 N=512 L=4 F=129 with the |tau| <= 50 window as ROI weights)")
+                    choices=["uneven", "m4n256", "wide_m8n1024", "paper_m2n512_roi50", "paper_m2n1200_roi50"],
+                    help="workload of a --counters run (paper_m2n512_roi50 / paper_m2n1200_roi50: one design at "
+                         "M=2 N=512 L=4 / N=1200 L=16, F=129, with the |tau| <= 50 window as ROI weights)")
     ap.add_argument("--schedule", type=int, default=12,
                     help="fused-pass schedule hint of an m4n256 --counters run (the timed run tunes it)")
     args = ap.parse_args()
@@ -502,8 +502,9 @@ def main():
     if args.counters:
         if args.workload == "uneven":
             run = optim.SQNGD(probs, opt, seeds=seeds)
-        elif args.workload == "paper_m2n512_roi50":
-            pp = I.make_problem(2, 512, 4, 129, p=16.0)
+        elif args.workload in ("paper_m2n512_roi50", "paper_m2n1200_roi50"):
+            pp = (I.make_problem(2, 512, 4, 129, p=16.0) if args.workload == "paper_m2n512_roi50"
+                  else I.make_problem(2, 1200, 16, 129, p=16.0))
             run = optim.SQNGD([pp], opt, seeds=[0], roi_weights=[I.roi_window_weights(pp, 50)])
         else:
             c = I.config(args.workload)

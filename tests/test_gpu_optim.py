@@ -339,6 +339,38 @@ def test_mixed_batch_steps_match_oracle(ref, mods):
         assert _rel(s1["z"], z) <= 1e-4, (i, _rel(s1["z"], z))
 
 
+@pytest.mark.parametrize("layout", ["aligned", "misaligned"])
+def test_step_logit_access_paths_match_oracle(ref, mods, layout):
+    """k_step with one lane per chip (FFT lengths 1024 and 2048) moves a chip's
+    logits and moments as 16-byte vectors only when L is a multiple of 4 and
+    the rows are 16-byte aligned. 'aligned': two problems that take the
+    vector path (L = 8 and 4); 'misaligned': a first problem of 101 x 3
+    logits shifts the offsets of an L = 8 problem off 16 bytes, and an L = 5
+    problem takes the scalar path by its L. Two iterations of every problem
+    against the oracle's."""
+    nat, optim, _ = mods
+    if layout == "aligned":
+        probs = [I.make_problem(2, 1000, 8, 2, p=16.0), I.make_problem(2, 400, 4, 3, p=16.0)]
+    else:
+        probs = [I.make_problem(1, 101, 3, 2, p=8.0), I.make_problem(2, 1000, 8, 2, p=16.0),
+                 I.make_problem(2, 900, 5, 2, p=16.0)]
+    opt = I.make_opt(total_iters=10, T0=1.0, T1=0.5)
+    print(f"[gpu] step logit access, {layout}", flush=True)
+    run = optim.SQNGD(probs, opt, seeds=list(range(40, 40 + len(probs))))
+    s0 = [run.numpy_state(i) for i in range(len(probs))]
+    run.step(2)
+    torch.cuda.synchronize()
+    for i, prob in enumerate(probs):
+        s1 = run.numpy_state(i)
+        z, h, state = s0[i]["z"], s0[i]["h"], s0[i]["state"]
+        for t in range(2):
+            z, h, state, _, _ = ref.step(prob, opt, z, h, state, t)
+        assert _rel(s1["h"], h) <= 1e-4, (layout, i, _rel(s1["h"], h))
+        assert _rel(s1["z"], z) <= 1e-4, (layout, i, _rel(s1["z"], z))
+        assert _rel(s1["state"]["mz"], state["mz"]) <= 1e-3, (layout, i)
+        assert _rel(s1["state"]["vz"], state["vz"]) <= 1e-3, (layout, i)
+
+
 def test_subset_continues_bitwise(mods):
     """A sub-batch built from a running batch continues exactly as the batch
     does when both make the same calls (a call's first evaluation is prepared

@@ -342,9 +342,10 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     H.group_rwaves[g] = rsum;
     pl->group_phlog[g] = phl;
     {
-      // k_step holds N <= P / 2 chips with tpc lanes each (P <= 2048); the
-      // rest, and rows with more than 16 logit levels per lane, use k_final
-      const int tpc = step_tpc(P);
+      // k_step holds N <= P / 2 chips with tpc lanes each (P <= 2048),
+      // k_step2 two chips per lane (P = 4096); rows with more than 16 logit
+      // levels per lane use k_final
+      const int tpc = P >= 4096 ? 1 : step_tpc(P);
       int lv = 0;
       for (int id : gprob[g]) lv = std::max(lv, tpc > 0 ? (pl->plans[id].L + tpc - 1) / tpc : 1 << 30);
       const int mode = tpc < 1 ? 0 : (lv <= 4 ? 4 : (lv <= 16 ? 16 : 0));
@@ -570,8 +571,11 @@ void launch_prep(const Plan& pl, const Ptrs& w, PrepArgs a, hipStream_t s) {
       case 1: launch_prep_p<256>(a, waves, s); break;
       case 2: launch_prep_p<512>(a, waves, s); break;
       case 3: launch_prep_p<1024>(a, waves, s); break;
-      case 4: launch_prep_p<2048>(a, waves, s); break;
-      default: launch_prep_p<4096>(a, waves, s); break;
+      default:  // P >= 2048: a block per row; the spectra by k_rowspec below
+        a.rows = (const int32_t*)(w.base + pl.hdr.group_rows[g]);
+        a.row_prob = w.row_prob;
+        hipLaunchKernelGGL(k_prep_row, dim3(pl.hdr.group_nrows[g]), dim3(kPrepRowThreads), 0, s, a);
+        break;
     }
     if (g + kMinLogP >= 11)
       launch_rowspec(pl, w, g,
@@ -752,6 +756,17 @@ void launch_step_pf(const FinArgs& a, int lv, dim3 grid, hipStream_t s) {
     else hipLaunchKernelGGL((k_step<P, FIN_STEP_B, 16, FG>), grid, block, 0, s, a);
   }
 }
+// FFT length 4096: two chips per lane, gradient rows from k_grad
+void launch_step2(const FinArgs& a, int lv, dim3 grid, hipStream_t s) {
+  const dim3 block(kStep2Threads);
+  if (a.mode == FIN_STEP_A) {
+    if (lv == 4) hipLaunchKernelGGL((k_step2<FIN_STEP_A, 4>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step2<FIN_STEP_A, 16>), grid, block, 0, s, a);
+  } else {
+    if (lv == 4) hipLaunchKernelGGL((k_step2<FIN_STEP_B, 4>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step2<FIN_STEP_B, 16>), grid, block, 0, s, a);
+  }
+}
 template <int P>
 void launch_step_p(const FinArgs& a, int lv, bool fuse, dim3 grid, hipStream_t s) {
   if constexpr (P <= 1024) {
@@ -809,7 +824,8 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
         case 1: launch_step_p<256>(a, lv, fuse, grid, s); break;
         case 2: launch_step_p<512>(a, lv, fuse, grid, s); break;
         case 3: launch_step_p<1024>(a, lv, fuse, grid, s); break;
-        default: launch_step_p<2048>(a, lv, fuse, grid, s); break;
+        case 4: launch_step_p<2048>(a, lv, fuse, grid, s); break;
+        default: launch_step2(a, lv, grid, s); break;
       }
       if (g + kMinLogP >= 11) {  // partner spectra of the next pass
         if (a.next == NEXT_B_FULL) launch_rowspec(pl, w, g, a.h, s);

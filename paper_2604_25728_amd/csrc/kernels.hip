@@ -420,9 +420,46 @@ struct PrepArgs {
   float2* wpart;
   float2* spec;
   float4* snrl;  // per row: (Re, Im) of sum_n conj(part(n)) self(n), |self|^2, |part|^2
+  const int32_t* rows;      // k_prep_row: the group's batch rows, one block each
+  const int32_t* row_prob;  // k_prep_row: problem of each batch row
   int32_t single;  // one problem: its plan is `one`, no table lookups
   ProbPlan one;
 };
+
+// One chip n of the first pass's inputs: the partner sample v (the row that
+// is transformed into the partner spectrum) and the self sample s, with the
+// waveform the mode derives written to its buffer when the row is active.
+__device__ __forceinline__ void prep_chip(const PrepArgs& a, const ProbPlan& pl, int64_t rbase, const float* zr,
+                                          int n, float T, bool active, float2& v, float2& s) {
+  const int L = pl.L;
+  v = s = make_float2(0.f, 0.f);
+  switch (a.mode) {
+    case PREP_B_SOFT:
+    case PREP_B_HARD:
+    case PREP_B_GIVEN: {
+      if (a.mode == PREP_B_SOFT) s = soft_chip(zr + (int64_t)n * L, L, T, pl.sq_mode);
+      else if (a.mode == PREP_B_HARD) s = level_phasor(hard_chip(zr + (int64_t)n * L, L), L);
+      else s = a.s_given[rbase + n];
+      if (active) a.wself[rbase + n] = s;
+      v = a.h[rbase + n];
+      break;
+    }
+    case PREP_A_HARD: {
+      v = level_phasor(hard_chip(zr + (int64_t)n * L, L), L);
+      if (active) a.wpart[rbase + n] = v;
+      s = a.h[rbase + n];
+      break;
+    }
+    case PREP_A_GIVEN:
+      v = a.s_given[rbase + n];
+      s = a.h[rbase + n];
+      break;
+    default:
+      v = a.wself[rbase + n];
+      s = a.h[rbase + n];
+      break;
+  }
+}
 
 template <int P>
 __global__ __launch_bounds__(64) void k_prep(PrepArgs a) {
@@ -456,34 +493,7 @@ __global__ __launch_bounds__(64) void k_prep(PrepArgs a) {
     constexpr int e = decltype(ec)::value;
     const int n = t + TF * e;
     float2 v = make_float2(0.f, 0.f), s = make_float2(0.f, 0.f);
-    if (e < EH && n < N) {
-      switch (a.mode) {
-        case PREP_B_SOFT:
-        case PREP_B_HARD:
-        case PREP_B_GIVEN: {
-          if (a.mode == PREP_B_SOFT) s = soft_chip(zr + (int64_t)n * L, L, T, pl.sq_mode);
-          else if (a.mode == PREP_B_HARD) s = level_phasor(hard_chip(zr + (int64_t)n * L, L), L);
-          else s = a.s_given[rbase + n];
-          if (active) a.wself[rbase + n] = s;
-          v = a.h[rbase + n];
-          break;
-        }
-        case PREP_A_HARD: {
-          v = level_phasor(hard_chip(zr + (int64_t)n * L, L), L);
-          if (active) a.wpart[rbase + n] = v;
-          s = a.h[rbase + n];
-          break;
-        }
-        case PREP_A_GIVEN:
-          v = a.s_given[rbase + n];
-          s = a.h[rbase + n];
-          break;
-        default:
-          v = a.wself[rbase + n];
-          s = a.h[rbase + n];
-          break;
-      }
-    }
+    if (e < EH && n < N) prep_chip(a, pl, rbase, zr, n, T, active, v, s);
     cr += v.x * s.x + v.y * s.y;
     ci += v.x * s.y - v.y * s.x;
     es += s.x * s.x + s.y * s.y;
@@ -507,6 +517,65 @@ __global__ __launch_bounds__(64) void k_prep(PrepArgs a) {
       });
     }
   }
+}
+
+// Maximum and sum over a wave's 64 lanes (every lane gets the result).
+__device__ __forceinline__ float wave_max(float v) { return slot_reduce<64>(v, 0.0f, OpMax()); }
+__device__ __forceinline__ float wave_sum(float v) { return slot_reduce<64>(v, 0.0f, OpAdd()); }
+
+// Block sums of four products and a flag, in wave order (the same in every
+// thread) over NW waves; sh holds 5 * NW floats.
+template <int NW>
+__device__ __forceinline__ void block_sum5(float (&v)[5], float* sh) {
+#pragma unroll
+  for (int i = 0; i < 5; ++i) v[i] = wave_sum(v[i]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) sh[i * NW + (threadIdx.x >> 6)] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    float r = 0.f;
+    for (int w = 0; w < NW; ++w) r += sh[i * NW + w];
+    v[i] = r;
+  }
+}
+
+// The first pass's inputs at the FFT lengths whose partner spectra k_rowspec
+// computes (P >= 2048): one 1024-thread block per batch row, a thread per chip
+// (two at N > 1024), the row's mainlobe and energy products (eq. 38) summed
+// over the block in wave order.
+constexpr int kPrepRowThreads = 1024;
+__global__ __launch_bounds__(kPrepRowThreads) void k_prep_row(PrepArgs a) {
+  constexpr int NW = kPrepRowThreads / 64;
+  __shared__ float sh[5 * NW];
+  int r;
+  ProbPlan pl;
+  if (a.single) {
+    r = blockIdx.x;
+    pl = a.one;
+  } else {
+    r = a.rows[blockIdx.x];
+    pl = a.plans[a.row_prob[r]];
+  }
+  const int g = r - pl.row0;
+  const int N = pl.N, L = pl.L;
+  const int64_t rbase = pl.off_w + (int64_t)g * N;
+  const float* zr = a.z ? a.z + pl.off_z + (int64_t)g * N * L : nullptr;
+  float T = pl.temperature;
+  if (a.use_schedule) T = temperature_at(a.opt, *a.counter);
+  float q[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int n = threadIdx.x; n < N; n += kPrepRowThreads) {
+    float2 v, s;
+    prep_chip(a, pl, rbase, zr, n, T, true, v, s);
+    q[0] += v.x * s.x + v.y * s.y;
+    q[1] += v.x * s.y - v.y * s.x;
+    q[2] += s.x * s.x + s.y * s.y;
+    q[3] += v.x * v.x + v.y * v.y;
+  }
+  block_sum5<NW>(q, sh);
+  if (threadIdx.x == 0) a.snrl[r] = make_float4(q[0], q[1], q[2], q[3]);
 }
 
 // ------------------------------------------------------------------ k_pass
@@ -935,8 +1004,6 @@ struct FinArgs {
 constexpr int kFinThreads = 1024;
 constexpr int kFinWaves = kFinThreads / 64;
 
-__device__ __forceinline__ float wave_max(float v) { return slot_reduce<64>(v, 0.0f, OpMax()); }
-__device__ __forceinline__ float wave_sum(float v) { return slot_reduce<64>(v, 0.0f, OpAdd()); }
 __device__ __forceinline__ float block_max(float v, float* sh) {
   v = wave_max(v);
   __syncthreads();
@@ -1606,25 +1673,6 @@ __device__ __forceinline__ float2 chip_quantise(const float (&zc)[LVMAX], int su
   return make_float2(sc / se, ss / se);
 }
 
-// Block sums of four products and a flag, in wave order (the same in every
-// thread) over NW waves; sh holds 5 * NW floats.
-template <int NW>
-__device__ __forceinline__ void block_sum5(float (&v)[5], float* sh) {
-#pragma unroll
-  for (int i = 0; i < 5; ++i) v[i] = wave_sum(v[i]);
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int i = 0; i < 5; ++i) sh[i * NW + (threadIdx.x >> 6)] = v[i];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    float r = 0.f;
-    for (int w = 0; w < NW; ++w) r += sh[i * NW + w];
-    v[i] = r;
-  }
-}
-
 constexpr int kGradThreads = 256;
 constexpr int kGradWaves = kGradThreads / 64;
 constexpr int kGradK = 8;                         // Doppler partials a lane loads per round
@@ -2233,6 +2281,252 @@ __global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
     }
   }
   }
+
+  if (a.count_step) {
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      const int old = atomicAdd(a.done, 1);
+      if (old == a.nrows_total - 1) {
+        atomicExch(a.done, 0);
+        atomicAdd(a.counter, 1);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ k_step2
+
+// k_step for FFT length 4096 (up to 2048 chips per row): two chips per lane
+// of a 1024-thread block, the gradient rows from k_grad. The row's skip
+// decision (a non-finite loss, a stopped design or a non-finite gradient
+// chip) is reduced before the updates, so each chip's new logits and
+// moments are written as soon as they are formed and only the filter chips
+// of step A (two per lane) wait for the row's energy (eq. 32). Same
+// arithmetic per chip as k_step, one lane per chip.
+constexpr int kStep2Threads = 1024;
+constexpr int kStep2Chips = 2;
+template <int MODE, int LVMAX>
+__global__ __launch_bounds__(kStep2Threads) void k_step2(FinArgs a) {
+  constexpr int NT = kStep2Threads, NW = NT / 64;
+  static_assert(kStep2Chips == 2, "two chips per lane: tid and tid + NT");
+  constexpr bool kA = MODE == FIN_STEP_A;
+  __shared__ float shr[5 * NW];
+  const int tid = threadIdx.x;
+  int r, pid;
+  ProbPlan pl;
+  if (a.single) {
+    r = blockIdx.x;
+    pid = 0;
+    pl = a.one;
+  } else {
+    r = a.rows[blockIdx.x];
+    pid = a.row_prob[r];
+    pl = a.plans[pid];
+  }
+  const int M = pl.M, N = pl.N, L = pl.L;
+  const int m = r - pl.row0;
+  const int64_t wrow = pl.off_w + (int64_t)m * N;
+  const int64_t crow = (int64_t)m * N;
+  const int next = a.next;
+  const bool sgd = (a.opt.flags & SQNGD_OPT_SGD) != 0;
+  const float2 zero2 = make_float2(0.f, 0.f);
+  const int tstep = *a.counter;
+  float* mh = a.adam + pl.off_state + 2 * (int64_t)M * N * L + 2 * crow;
+  float* vh = mh + 2 * (int64_t)M * N;
+
+  // ---- gradients and the row's skip decision
+  const float2 g0 = tid < N ? a.gbuf[wrow + tid] : zero2;
+  const float2 g1 = tid + NT < N ? a.gbuf[wrow + tid + NT] : zero2;
+  const bool flag = !(isfinite(g0.x) && isfinite(g0.y) && isfinite(g1.x) && isfinite(g1.y));
+  const bool hold = a.frozen != nullptr && a.frozen[pid] != 0;
+  const bool skip = __syncthreads_or(flag) != 0 || a.pflag[pid] != 0 || hold;
+  const float b1 = a.opt.beta1, b2 = a.opt.beta2;
+  const bool vec4 = LVMAX % 4 == 0 && (L & 3) == 0 && ((pl.off_z | pl.off_state) & 3) == 0 &&
+                    (((uintptr_t)a.z | (uintptr_t)a.adam) & 15) == 0;
+
+  // the chip's logits (invalid levels -inf) and, for the z step, its moments
+  auto load_z = [&](int n, float (&zl)[LVMAX], float (&mz)[LVMAX], float (&vz)[LVMAX], bool moments) {
+    const int64_t zrow = pl.off_z + (crow + n) * L;
+    const float* amz = a.adam + pl.off_state + (crow + n) * L;
+    const float* avz = amz + (int64_t)M * N * L;
+    if (vec4) {
+#pragma unroll
+      for (int k4 = 0; k4 < LVMAX / 4; ++k4) {
+        const bool ok = 4 * k4 < L;
+        const float4 z4 = ok ? *(const float4*)(a.z + zrow + 4 * k4)
+                             : make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+        const float4 m4 = ok && moments ? *(const float4*)(amz + 4 * k4) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 v4 = ok && moments ? *(const float4*)(avz + 4 * k4) : make_float4(0.f, 0.f, 0.f, 0.f);
+        zl[4 * k4] = z4.x, zl[4 * k4 + 1] = z4.y, zl[4 * k4 + 2] = z4.z, zl[4 * k4 + 3] = z4.w;
+        mz[4 * k4] = m4.x, mz[4 * k4 + 1] = m4.y, mz[4 * k4 + 2] = m4.z, mz[4 * k4 + 3] = m4.w;
+        vz[4 * k4] = v4.x, vz[4 * k4 + 1] = v4.y, vz[4 * k4 + 2] = v4.z, vz[4 * k4 + 3] = v4.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < LVMAX; ++k) {
+        const bool ok = k < L;
+        zl[k] = ok ? a.z[zrow + k] : -INFINITY;
+        mz[k] = ok && moments ? amz[k] : 0.f;
+        vz[k] = ok && moments ? avz[k] : 0.f;
+      }
+    }
+  };
+  // energy and mainlobe products of the next pass (eq. 10, 32, 38): Re, Im
+  // of conj(partner) self, |self|^2, |partner|^2
+  float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+  auto product = [&](float2 self, float2 part) {
+    q0 += part.x * self.x + part.y * self.y;
+    q1 += part.x * self.y - part.y * self.x;
+    q2 += self.x * self.x + self.y * self.y;
+    q3 += part.x * part.x + part.y * part.y;
+  };
+
+  // one chip: its update, the next pass's sample and its products
+  auto chip = [&](int n, float2 gc, float2& hu, float4& mvn) {
+    hu = zero2;
+    mvn = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (n >= N) return;
+    const float2 hv = a.h[wrow + n];
+    if constexpr (kA) {
+      float2 h1 = hv;
+      float4 mv = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (!skip) {
+        if (sgd) {
+          h1.x -= a.opt.lr_h * gc.x;
+          h1.y -= a.opt.lr_h * gc.y;
+        } else {
+          const float2 m2 = *(const float2*)(mh + 2 * n), v2 = *(const float2*)(vh + 2 * n);
+          const int k = tstep * a.opt.n_h + a.inner + 1;
+          const float bc1 = bias_corr(b1, k), bc2 = bias_corr(b2, k);
+          mv.x = b1 * m2.x + (1.0f - b1) * gc.x;
+          mv.y = b1 * m2.y + (1.0f - b1) * gc.y;
+          mv.z = b2 * v2.x + (1.0f - b2) * gc.x * gc.x;
+          mv.w = b2 * v2.y + (1.0f - b2) * gc.y * gc.y;
+          h1.x -= a.opt.lr_h * (mv.x / bc1) / (sqrtf(mv.z / bc2) + a.opt.eps);
+          h1.y -= a.opt.lr_h * (mv.y / bc1) / (sqrtf(mv.w / bc2) + a.opt.eps);
+        }
+      }
+      hu = h1;
+      mvn = mv;
+      if (next == NEXT_B_FULL) {
+        float zl[LVMAX], mz[LVMAX], vz[LVMAX];
+        load_z(n, zl, mz, vz, false);
+        const float2 nx = chip_quantise<1, LVMAX>(zl, 0, L, false, temperature_at(a.opt, tstep), pl.sq_mode);
+        a.wself[wrow + n] = nx;
+        product(nx, h1);
+      } else {
+        product(h1, next == NEXT_A_SNRL ? a.wpart[wrow + n] : h1);
+      }
+    } else {
+      const float2 sv = a.self_w[wrow + n];
+      float zl[LVMAX], mz[LVMAX], vz[LVMAX];
+      load_z(n, zl, mz, vz, !skip && !sgd);
+      if (!skip) {
+        // dL/dz through the soft quantiser at the temperature of this step, then Adam
+        const float Tc = temperature_at(a.opt, tstep);
+        const float invT = 1.0f / Tc;
+        float zm = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < LVMAX; ++k) zm = fmaxf(zm, zl[k]);
+        float e[LVMAX];
+        float se = 0.f, sy = 0.f;
+#pragma unroll
+        for (int k = 0; k < LVMAX; ++k) {
+          e[k] = k < L ? expf((zl[k] - zm) * invT) : 0.f;
+          se += e[k];
+          sy += (float)k * e[k];
+        }
+        // one division per chip and per step instead of three per level
+        const float inv_se = 1.0f / se;
+        const float yb = sy * inv_se;
+        const int kz = tstep * a.opt.n_x + a.inner + 1;
+        const float ibc1 = sgd ? 1.0f : 1.0f / bias_corr(b1, kz), ibc2 = sgd ? 1.0f : 1.0f / bias_corr(b2, kz);
+        const float dphi = (gc.y * sv.x - gc.x * sv.y) * (2.0f * 3.14159265358979f / (float)L) * invT;
+#pragma unroll
+        for (int k = 0; k < LVMAX; ++k) {
+          if (k >= L) continue;
+          const float pi = e[k] * inv_se;
+          float gv;
+          if (pl.sq_mode == SQNGD_SQ_PHASE_MEAN) {
+            gv = dphi * pi * ((float)k - yb);
+          } else {
+            const float2 ul = level_phasor(k, L);
+            gv = pi * invT * (gc.x * (ul.x - sv.x) + gc.y * (ul.y - sv.y));
+          }
+          if (sgd) {
+            zl[k] -= a.opt.lr_z * gv;
+          } else {
+            mz[k] = b1 * mz[k] + (1.0f - b1) * gv;
+            vz[k] = b2 * vz[k] + (1.0f - b2) * gv * gv;
+            zl[k] -= a.opt.lr_z * (mz[k] * ibc1) / (sqrtf(vz[k] * ibc2) + a.opt.eps);
+          }
+        }
+        const int64_t zrow = pl.off_z + (crow + n) * L;
+        float* amz = a.adam + pl.off_state + (crow + n) * L;
+        float* avz = amz + (int64_t)M * N * L;
+        if (vec4) {
+#pragma unroll
+          for (int k4 = 0; k4 < LVMAX / 4; ++k4) {
+            if (4 * k4 < L) {
+              *(float4*)(a.z + zrow + 4 * k4) = make_float4(zl[4 * k4], zl[4 * k4 + 1], zl[4 * k4 + 2], zl[4 * k4 + 3]);
+              if (!sgd) {
+                *(float4*)(amz + 4 * k4) = make_float4(mz[4 * k4], mz[4 * k4 + 1], mz[4 * k4 + 2], mz[4 * k4 + 3]);
+                *(float4*)(avz + 4 * k4) = make_float4(vz[4 * k4], vz[4 * k4 + 1], vz[4 * k4 + 2], vz[4 * k4 + 3]);
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < LVMAX; ++k) {
+            if (k < L) {
+              a.z[zrow + k] = zl[k];
+              if (!sgd) {
+                amz[k] = mz[k];
+                avz[k] = vz[k];
+              }
+            }
+          }
+        }
+      }
+      float2 nx = zero2;
+      if (next == NEXT_A_FULL || next == NEXT_B_SOFT)
+        nx = chip_quantise<1, LVMAX>(zl, 0, L, next == NEXT_A_FULL,
+                                     temperature_at(a.opt, tstep + (next == NEXT_B_SOFT ? a.next_t_offset : 0)),
+                                     pl.sq_mode);
+      if (next == NEXT_B_SOFT) a.wself[wrow + n] = nx;
+      if (next == NEXT_A_FULL) a.wpart[wrow + n] = nx;
+      if (next == NEXT_A_FULL) product(hv, nx);
+      else product(nx, hv);
+    }
+  };
+  float2 hu0, hu1;    // step A: updated, unprojected filter chips
+  float4 mvn0, mvn1;  // step A: their new moments
+  chip(tid, g0, hu0, mvn0);
+  chip(tid + NT, g1, hu1, mvn1);
+  float q[5] = {q0, q1, q2, q3, 0.f};
+  block_sum5<NW>(q, shr);
+  float4 prod = make_float4(q[0], q[1], q[2], q[3]);
+  if constexpr (kA) {
+    // h <- h sqrt(N / |h|^2) over the row, and the products of the projected chips
+    if (!skip) {
+      const float e2 = next == NEXT_A_SNRL ? prod.z : prod.w;
+      const float cn = sqrtf((float)N / e2);
+      auto put = [&](int n, float2 hu, float4 mvn) {
+        if (n >= N) return;
+        if (!sgd) {
+          *(float2*)(mh + 2 * n) = make_float2(mvn.x, mvn.y);
+          *(float2*)(vh + 2 * n) = make_float2(mvn.z, mvn.w);
+        }
+        a.h[wrow + n] = cscale(hu, cn);
+      };
+      put(tid, hu0, mvn0);
+      put(tid + NT, hu1, mvn1);
+      if (next == NEXT_B_FULL) prod = make_float4(cn * prod.x, cn * prod.y, prod.z, cn * cn * prod.w);
+      if (next == NEXT_A_SNRL) prod = make_float4(cn * prod.x, cn * prod.y, cn * cn * prod.z, prod.w);
+    }
+  }
+  if (tid == 0 && next != NEXT_NONE) a.snrl_next[r] = prod;
 
   if (a.count_step) {
     __syncthreads();

@@ -244,11 +244,13 @@ def test_chained_graph_matches_eager_run(mods):
     assert a.t == b.t == 15
 
 
-@pytest.mark.parametrize("shape", [(2, 1024, 4, 3), (3, 1000, 16, 3), (2, 1100, 8, 2), (2, 300, 64, 5)])
+@pytest.mark.parametrize("shape", [(2, 1024, 4, 3), (3, 1000, 16, 3), (2, 1100, 8, 2), (2, 1100, 24, 2),
+                                   (2, 300, 64, 5)])
 def test_fallback_finalize_steps_match_oracle(ref, mods, shape):
     """Steps at FFT length 2048 (k_step with 1024 threads, one lane per chip,
     4 and 16 logit levels per lane, partner spectra by k_rowspec), at 4096
-    (k_final with two chips per thread) and with more logit levels per lane
+    (k_step2, two chips per lane; k_final with two chips per thread when a
+    chip has more than 16 logit levels) and with more logit levels per lane
     than k_step holds (k_final) against the oracle."""
     nat, optim, _ = mods
     M, N, L, F = shape
@@ -369,6 +371,63 @@ def test_step_logit_access_paths_match_oracle(ref, mods, layout):
         assert _rel(s1["z"], z) <= 1e-4, (layout, i, _rel(s1["z"], z))
         assert _rel(s1["state"]["mz"], state["mz"]) <= 1e-3, (layout, i)
         assert _rel(s1["state"]["vz"], state["vz"]) <= 1e-3, (layout, i)
+
+
+@pytest.mark.parametrize("layout", ["aligned", "misaligned"])
+def test_two_chip_step_at_fft_length_4096_matches_oracle(ref, mods, layout):
+    """k_step2 (FFT length 4096, two chips per lane of a 1024-thread block)
+    in a batch with another FFT-length group, two filter and two logit steps
+    per iteration (every next-pass preparation the chaining uses), three
+    iterations against the oracle's. 'aligned': N = 2048, the most chips a
+    row holds (every lane's second chip in use), logits moved as 16-byte
+    vectors (L = 4 and 8); 'misaligned': a first problem of 101 x 3 logits
+    shifts the rows off 16 bytes, and L = 6 takes the scalar path by its L."""
+    nat, optim, _ = mods
+    if layout == "aligned":
+        probs = [I.make_problem(2, 2048, 4, 2, p=16.0), I.make_problem(2, 1100, 8, 2, p=16.0),
+                 I.make_problem(2, 200, 4, 3, p=8.0)]
+    else:
+        probs = [I.make_problem(1, 101, 3, 2, p=8.0), I.make_problem(2, 1200, 8, 2, p=16.0),
+                 I.make_problem(3, 1030, 6, 2, p=16.0, sq_mode=I.PHASOR_MEAN)]
+    opt = I.make_opt(n_h=2, n_x=2, total_iters=20, T0=1.0, T1=0.3)
+    print(f"[gpu] two-chip step at 4096, {layout}", flush=True)
+    run = optim.SQNGD(probs, opt, seeds=list(range(60, 60 + len(probs))))
+    s0 = [run.numpy_state(i) for i in range(len(probs))]
+    iters = 3
+    run.step(iters)
+    torch.cuda.synchronize()
+    assert run.t == iters
+    sa, sb = run.step_stats()
+    for i, prob in enumerate(probs):
+        s1 = run.numpy_state(i)
+        z, h, state = s0[i]["z"], s0[i]["h"], s0[i]["state"]
+        for t in range(iters):
+            z, h, state, sta, stb = ref.step(prob, opt, z, h, state, t)
+        assert _rel(s1["h"], h) <= 1e-4, (layout, i, _rel(s1["h"], h))
+        assert _rel(s1["z"], z) <= 1e-4, (layout, i, _rel(s1["z"], z))
+        assert _rel(s1["state"]["mz"], state["mz"]) <= 1e-3, (layout, i)
+        assert _rel(s1["state"]["vz"], state["vz"]) <= 1e-3, (layout, i)
+        assert abs(sa[i]["loss"] - sta["loss"]) <= 1e-4 * sta["loss"], (layout, i)
+        assert abs(sb[i]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"], (layout, i)
+
+
+def test_two_chip_step_skips_nonfinite_row(mods):
+    """k_step2: a NaN logit makes the logit step's loss non-finite; the
+    step then leaves every logit of the design unchanged."""
+    nat, optim, _ = mods
+    prob = I.make_problem(2, 1100, 8, 2, p=16.0)
+    opt = I.make_opt(total_iters=10, T0=1.0, T1=0.5)
+    print("[gpu] two-chip step, non-finite", flush=True)
+    run = optim.SQNGD([prob], opt, seeds=[4])
+    run.z[8 * 1050 + 3] = float("nan")   # chip (0, 1050): a lane's second chip
+    z_before = run.z.clone()
+    run.step()
+    torch.cuda.synchronize()
+    sa, sb = run.step_stats()
+    assert sb[0]["nonfinite"] == 1
+    assert sa[0]["nonfinite"] == 0
+    assert torch.equal(torch.nan_to_num(run.z, nan=7.0), torch.nan_to_num(z_before, nan=7.0))
+    assert torch.isfinite(run.h).all()
 
 
 def test_subset_continues_bitwise(mods):

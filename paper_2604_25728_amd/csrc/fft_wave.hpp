@@ -271,9 +271,21 @@ __device__ __forceinline__ float2 tw_exact(int k) {
   return make_float2(c, -s);
 }
 
-// Per-lane twiddles reused by every FFT of the wave. A few are evaluated with
-// sincospi and the rest formed as products of at most two of them (error a
-// few ulp), so no table is read from memory at kernel start.
+// w[k] = w1^k for k < K, each power the product of two lower ones
+// (w[k] = w[k/2] w[k - k/2]): one sincospi per twiddle set instead of one
+// per power; the error grows with the product depth, a few ulp at K = 8.
+template <int K>
+__device__ __forceinline__ void tw_powers(float2 (&w)[K], float2 w1) {
+  w[0] = make_float2(1.f, 0.f);
+  if constexpr (K > 1) w[1] = w1;
+  static_for<K>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if constexpr (k >= 2) w[k] = cmul(w[k >> 1], w[k - (k >> 1)]);
+  });
+}
+
+// Per-lane twiddles reused by every FFT of the wave: each set the powers of
+// one sincospi value, so no table is read from memory at kernel start.
 template <class G_>
 struct TwiddlesG {
   using G = G_;
@@ -285,46 +297,13 @@ struct TwiddlesG {
   float2 col[G::A];  // W_TF^(beta gamma), gamma < A, beta = t % (B C)
   float2 col2[G::THREE ? G::B : 1];  // three stages: W_(B C)^(c zeta), zeta < B, c = t % C
   __device__ __forceinline__ void init(int t) {
-    // lo: powers 1, 2, 4 exact; 3, 5, 6, 7 as products
-    lo[0] = make_float2(1.f, 0.f);
-    if constexpr (NLO > 1) lo[1] = tw_exact<P>(t);
-    if constexpr (NLO > 2) lo[2] = tw_exact<P>(2 * t);
-    if constexpr (NLO > 3) lo[3] = cmul(lo[2], lo[1]);
-    if constexpr (NLO > 4) {
-      lo[4] = tw_exact<P>(4 * t);
-      lo[5] = cmul(lo[4], lo[1]);
-      lo[6] = cmul(lo[4], lo[2]);
-      lo[7] = cmul(lo[4], lo[3]);
-    }
-    hi[0] = make_float2(1.f, 0.f);
-    for (int a = 1; a < NHI; ++a) hi[a] = tw_exact<P>(t * NLO * a);
+    tw_powers<NLO>(lo, NLO > 1 ? tw_exact<P>(t) : make_float2(1.f, 0.f));
+    tw_powers<NHI>(hi, NHI > 1 ? tw_exact<P>(t * NLO) : make_float2(1.f, 0.f));
     const int beta = (unsigned)t % G::BC;
-    col[0] = make_float2(1.f, 0.f);
-    if constexpr (G::A > 1) col[1] = tw_exact<P>(beta * G::E);
-    if constexpr (G::A > 2) col[2] = tw_exact<P>(2 * beta * G::E);
-    if constexpr (G::A > 3) col[3] = cmul(col[2], col[1]);
-    if constexpr (G::A > 4) {
-      col[4] = tw_exact<P>(4 * beta * G::E);
-      col[5] = cmul(col[4], col[1]);
-      col[6] = cmul(col[4], col[2]);
-      col[7] = cmul(col[4], col[3]);
-    }
+    tw_powers<G::A>(col, G::A > 1 ? tw_exact<P>(beta * G::E) : make_float2(1.f, 0.f));
     if constexpr (G::THREE) {
-      // powers 1, 2, 4 exact; 3, 5, 6, 7 as products (as lo and col)
       const int c = (unsigned)t % G::C;
-      constexpr int step = G::E * G::A;
-      col2[0] = make_float2(1.f, 0.f);
-      if constexpr (G::B == 8) {
-        col2[1] = tw_exact<P>(c * step);
-        col2[2] = tw_exact<P>(2 * c * step);
-        col2[3] = cmul(col2[2], col2[1]);
-        col2[4] = tw_exact<P>(4 * c * step);
-        col2[5] = cmul(col2[4], col2[1]);
-        col2[6] = cmul(col2[4], col2[2]);
-        col2[7] = cmul(col2[4], col2[3]);
-      } else {
-        for (int z = 1; z < G::B; ++z) col2[z] = tw_exact<P>(c * z * step);
-      }
+      tw_powers<G::B>(col2, tw_exact<P>(c * G::E * G::A));
     }
   }
   // The same twiddles read from a table tab[k] = W_P^k, k < P (a block

@@ -411,6 +411,33 @@ def test_two_chip_step_at_fft_length_4096_matches_oracle(ref, mods, layout):
         assert abs(sb[i]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"], (layout, i)
 
 
+@pytest.mark.parametrize("N", [1000, 999])
+def test_wide_gradient_reduction_steps_match_oracle(ref, mods, N):
+    """A group large enough (64 rows of FFT length 2048) for k_grad's one
+    lane per chip (each wave reads 64 consecutive chips of a partial row),
+    at an even and an odd N. Two iterations of 32 designs; three of them
+    against the oracle's."""
+    nat, optim, _ = mods
+    prob = I.make_problem(2, N, 4, 2, p=16.0)
+    opt = I.make_opt(total_iters=10, T0=1.0, T1=0.5)
+    print(f"[gpu] wide gradient reduction N={N}", flush=True)
+    run = optim.SQNGD([prob] * 32, opt, seeds=list(range(70, 102)))
+    picks = (0, 17, 31)
+    s0 = {i: run.numpy_state(i) for i in picks}
+    run.step(2)
+    torch.cuda.synchronize()
+    sa, sb = run.step_stats()
+    for i in picks:
+        s1 = run.numpy_state(i)
+        z, h, state = s0[i]["z"], s0[i]["h"], s0[i]["state"]
+        for t in range(2):
+            z, h, state, sta, stb = ref.step(prob, opt, z, h, state, t)
+        assert _rel(s1["h"], h) <= 1e-4, (N, i, _rel(s1["h"], h))
+        assert _rel(s1["z"], z) <= 1e-4, (N, i, _rel(s1["z"], z))
+        assert abs(sa[i]["loss"] - sta["loss"]) <= 1e-4 * sta["loss"], (N, i)
+        assert abs(sb[i]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"], (N, i)
+
+
 def test_two_chip_step_skips_nonfinite_row(mods):
     """k_step2: a NaN logit makes the logit step's loss non-finite; the
     step then leaves every logit of the design unchanged."""

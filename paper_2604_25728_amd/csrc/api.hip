@@ -142,6 +142,7 @@ struct Plan {
   int group_step[kNumPGroups];
   bool group_fuse[kNumPGroups];  // k_step reduces the gradient rows itself (no k_grad launch)
   bool all_step = true;  // every group runs k_step: the step counter advances in the next pass
+  int step2_split = 1;   // k_step2 blocks per row at FFT length 4096: the group's longest row in 256-chip blocks
   int maxN = 0;
   // throughput groups (bit g: FFT length 128 << g) that share one launch
   // (k_pass_multi), 0 for one launch per group
@@ -349,6 +350,9 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
       int lv = 0;
       for (int id : gprob[g]) lv = std::max(lv, tpc > 0 ? (pl->plans[id].L + tpc - 1) / tpc : 1 << 30);
       const int mode = tpc < 1 ? 0 : (lv <= 4 ? 4 : (lv <= 16 ? 16 : 0));
+      if (P >= 4096)
+        for (int id : gprob[g])
+          pl->step2_split = std::max(pl->step2_split, (pl->plans[id].N + kStep2Threads - 1) / kStep2Threads);
       pl->group_step[g] = mode;
       if (!gprob[g].empty() && mode == 0) pl->all_step = false;
       // k_step reduces the rows' Doppler partials itself when that takes at
@@ -383,6 +387,9 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
   // counters live in the uploaded table region, so the upload zeroes them
   H.counters = (int64_t)off;
   off = align_up(off + 4 * kNumCounters);
+  const int rows4096 = H.group_nrows[kNumPGroups - 1];
+  H.rowsync = (int64_t)off;
+  off = align_up(off + 4 * (size_t)rows4096);
   const size_t table_bytes = off;
   H.spec = (int64_t)off;
   off = align_up(off + 8 * (size_t)spec);
@@ -400,6 +407,8 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
   off = align_up(off + 8 * (size_t)off_w);
   H.pflag = (int64_t)off;
   off = align_up(off + 4 * (size_t)nprob);
+  H.rowpart = (int64_t)off;
+  off = align_up(off + 16 * (size_t)kStep2MaxSplit * rows4096);
   H.total = (int64_t)off;
   int maxN = 0;
   for (int i = 0; i < nprob; ++i) maxN = probs[i].N > maxN ? probs[i].N : maxN;
@@ -508,6 +517,8 @@ struct Ptrs {
   float4* snrl;
   float2* gbuf;
   int32_t* pflag;
+  int32_t* rowsync;
+  float4* rowpart;
 };
 
 Ptrs ptrs(const Plan& pl, void* ws) {
@@ -524,7 +535,9 @@ Ptrs ptrs(const Plan& pl, void* ws) {
               (float2*)(b + H.upart),
               (float4*)(b + H.snrl),
               (float2*)(b + H.gbuf),
-              (int32_t*)(b + H.pflag)};
+              (int32_t*)(b + H.pflag),
+              (int32_t*)(b + H.rowsync),
+              (float4*)(b + H.rowpart)};
 }
 
 // ----------------------------------------------------------- launch helpers
@@ -756,9 +769,9 @@ void launch_step_pf(const FinArgs& a, int lv, dim3 grid, hipStream_t s) {
     else hipLaunchKernelGGL((k_step<P, FIN_STEP_B, 16, FG>), grid, block, 0, s, a);
   }
 }
-// FFT length 4096: two chips per lane, gradient rows from k_grad
-void launch_step2(const FinArgs& a, int lv, dim3 grid, hipStream_t s) {
-  const dim3 block(kStep2Threads);
+// FFT length 4096: each row over split blocks of 256 chips, gradient rows from k_grad
+void launch_step2(const FinArgs& a, int lv, int nrows, hipStream_t s) {
+  const dim3 grid(nrows * a.split), block(kStep2Threads);
   if (a.mode == FIN_STEP_A) {
     if (lv == 4) hipLaunchKernelGGL((k_step2<FIN_STEP_A, 4>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_step2<FIN_STEP_A, 16>), grid, block, 0, s, a);
@@ -825,7 +838,14 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
         case 2: launch_step_p<512>(a, lv, fuse, grid, s); break;
         case 3: launch_step_p<1024>(a, lv, fuse, grid, s); break;
         case 4: launch_step_p<2048>(a, lv, fuse, grid, s); break;
-        default: launch_step2(a, lv, grid, s); break;
+        default: {
+          FinArgs a2 = a;
+          a2.split = pl.step2_split;
+          a2.rowcnt = w.rowsync;
+          a2.rowpart = w.rowpart;
+          launch_step2(a2, lv, pl.hdr.group_nrows[g], s);
+          break;
+        }
       }
       if (g + kMinLogP >= 11) {  // partner spectra of the next pass
         if (a.next == NEXT_B_FULL) launch_rowspec(pl, w, g, a.h, s);

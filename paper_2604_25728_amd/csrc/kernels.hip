@@ -997,6 +997,9 @@ struct FinArgs {
   int32_t grad_chunks;  // k_grad blocks per row
   int32_t grad_nprob;   // problems of the launch (one statistics block each)
   const int32_t* gprob; // their ids
+  int32_t split;        // k_step2 blocks per row
+  int32_t* rowcnt;      // k_step2: per row of the launch, blocks done (zero between launches)
+  float4* rowpart;      // k_step2: per row of the launch, kStep2MaxSplit partial products
   int32_t single;  // one problem: its plan is `one`, rows are the block indices
   ProbPlan one;
 };
@@ -2297,34 +2300,40 @@ __global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
 
 // ------------------------------------------------------------ k_step2
 
-// k_step for FFT length 4096 (up to 2048 chips per row): two chips per lane
-// of a 1024-thread block, the gradient rows from k_grad. The row's skip
-// decision (a non-finite loss, a stopped design or a non-finite gradient
-// chip) is reduced before the updates, so each chip's new logits and
-// moments are written as soon as they are formed and only the filter chips
-// of step A (two per lane) wait for the row's energy (eq. 32). Same
-// arithmetic per chip as k_step, one lane per chip.
-constexpr int kStep2Threads = 1024;
-constexpr int kStep2Chips = 2;
+// k_step for FFT length 4096 (up to 2048 chips per row): a row is split over
+// ceil(N / 256) blocks of 256 threads, one chip per thread, with the gradient
+// rows from k_grad. Every block reads the whole row's gradient for the row's
+// skip decision (a non-finite loss, a stopped design or a non-finite gradient
+// chip), so each chip's new logits and moments are written as soon as they
+// are formed. The row's products for the next pass (and in step A the
+// filter's energy) are summed by the row's last block, from the blocks'
+// partial sums in block order; in step A that block then projects the whole
+// filter row (eq. 32), which the other blocks have written unprojected. Same
+// arithmetic per chip as k_step with one lane per chip.
+constexpr int kStep2Threads = 256;
+constexpr int kStep2MaxSplit = 8;  // 2048 chips
 template <int MODE, int LVMAX>
 __global__ __launch_bounds__(kStep2Threads) void k_step2(FinArgs a) {
   constexpr int NT = kStep2Threads, NW = NT / 64;
-  static_assert(kStep2Chips == 2, "two chips per lane: tid and tid + NT");
   constexpr bool kA = MODE == FIN_STEP_A;
   __shared__ float shr[5 * NW];
+  __shared__ int last_sh;
   const int tid = threadIdx.x;
+  const int rb = blockIdx.x / a.split, blk = blockIdx.x - rb * a.split;  // row of the launch, block of the row
   int r, pid;
   ProbPlan pl;
   if (a.single) {
-    r = blockIdx.x;
+    r = rb;
     pid = 0;
     pl = a.one;
   } else {
-    r = a.rows[blockIdx.x];
+    r = a.rows[rb];
     pid = a.row_prob[r];
     pl = a.plans[pid];
   }
   const int M = pl.M, N = pl.N, L = pl.L;
+  const int nblk = (N + NT - 1) / NT;
+  if (blk >= nblk) return;  // the row has fewer blocks than the launch's longest
   const int m = r - pl.row0;
   const int64_t wrow = pl.off_w + (int64_t)m * N;
   const int64_t crow = (int64_t)m * N;
@@ -2334,11 +2343,17 @@ __global__ __launch_bounds__(kStep2Threads) void k_step2(FinArgs a) {
   const int tstep = *a.counter;
   float* mh = a.adam + pl.off_state + 2 * (int64_t)M * N * L + 2 * crow;
   float* vh = mh + 2 * (int64_t)M * N;
+  const int n = blk * NT + tid;  // this thread's chip
+  const bool on = n < N;
 
-  // ---- gradients and the row's skip decision
-  const float2 g0 = tid < N ? a.gbuf[wrow + tid] : zero2;
-  const float2 g1 = tid + NT < N ? a.gbuf[wrow + tid + NT] : zero2;
-  const bool flag = !(isfinite(g0.x) && isfinite(g0.y) && isfinite(g1.x) && isfinite(g1.y));
+  // ---- the row's skip decision from its whole gradient row; this chip's gradient
+  float2 gc = zero2;
+  bool flag = false;
+  for (int j = tid; j < N; j += NT) {
+    const float2 gj = a.gbuf[wrow + j];
+    flag |= !(isfinite(gj.x) && isfinite(gj.y));
+    if (j == n) gc = gj;
+  }
   const bool hold = a.frozen != nullptr && a.frozen[pid] != 0;
   const bool skip = __syncthreads_or(flag) != 0 || a.pflag[pid] != 0 || hold;
   const float b1 = a.opt.beta1, b2 = a.opt.beta2;
@@ -2346,7 +2361,7 @@ __global__ __launch_bounds__(kStep2Threads) void k_step2(FinArgs a) {
                     (((uintptr_t)a.z | (uintptr_t)a.adam) & 15) == 0;
 
   // the chip's logits (invalid levels -inf) and, for the z step, its moments
-  auto load_z = [&](int n, float (&zl)[LVMAX], float (&mz)[LVMAX], float (&vz)[LVMAX], bool moments) {
+  auto load_z = [&](float (&zl)[LVMAX], float (&mz)[LVMAX], float (&vz)[LVMAX], bool moments) {
     const int64_t zrow = pl.off_z + (crow + n) * L;
     const float* amz = a.adam + pl.off_state + (crow + n) * L;
     const float* avz = amz + (int64_t)M * N * L;
@@ -2374,23 +2389,19 @@ __global__ __launch_bounds__(kStep2Threads) void k_step2(FinArgs a) {
   };
   // energy and mainlobe products of the next pass (eq. 10, 32, 38): Re, Im
   // of conj(partner) self, |self|^2, |partner|^2
-  float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+  float q[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
   auto product = [&](float2 self, float2 part) {
-    q0 += part.x * self.x + part.y * self.y;
-    q1 += part.x * self.y - part.y * self.x;
-    q2 += self.x * self.x + self.y * self.y;
-    q3 += part.x * part.x + part.y * part.y;
+    q[0] = part.x * self.x + part.y * self.y;
+    q[1] = part.x * self.y - part.y * self.x;
+    q[2] = self.x * self.x + self.y * self.y;
+    q[3] = part.x * part.x + part.y * part.y;
   };
 
-  // one chip: its update, the next pass's sample and its products
-  auto chip = [&](int n, float2 gc, float2& hu, float4& mvn) {
-    hu = zero2;
-    mvn = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (n >= N) return;
+  if (on) {
     const float2 hv = a.h[wrow + n];
     if constexpr (kA) {
+      // Adam on (Re h, Im h); the row's last block projects it
       float2 h1 = hv;
-      float4 mv = make_float4(0.f, 0.f, 0.f, 0.f);
       if (!skip) {
         if (sgd) {
           h1.x -= a.opt.lr_h * gc.x;
@@ -2399,19 +2410,18 @@ __global__ __launch_bounds__(kStep2Threads) void k_step2(FinArgs a) {
           const float2 m2 = *(const float2*)(mh + 2 * n), v2 = *(const float2*)(vh + 2 * n);
           const int k = tstep * a.opt.n_h + a.inner + 1;
           const float bc1 = bias_corr(b1, k), bc2 = bias_corr(b2, k);
-          mv.x = b1 * m2.x + (1.0f - b1) * gc.x;
-          mv.y = b1 * m2.y + (1.0f - b1) * gc.y;
-          mv.z = b2 * v2.x + (1.0f - b2) * gc.x * gc.x;
-          mv.w = b2 * v2.y + (1.0f - b2) * gc.y * gc.y;
-          h1.x -= a.opt.lr_h * (mv.x / bc1) / (sqrtf(mv.z / bc2) + a.opt.eps);
-          h1.y -= a.opt.lr_h * (mv.y / bc1) / (sqrtf(mv.w / bc2) + a.opt.eps);
+          const float mx = b1 * m2.x + (1.0f - b1) * gc.x, my = b1 * m2.y + (1.0f - b1) * gc.y;
+          const float vx = b2 * v2.x + (1.0f - b2) * gc.x * gc.x, vy = b2 * v2.y + (1.0f - b2) * gc.y * gc.y;
+          h1.x -= a.opt.lr_h * (mx / bc1) / (sqrtf(vx / bc2) + a.opt.eps);
+          h1.y -= a.opt.lr_h * (my / bc1) / (sqrtf(vy / bc2) + a.opt.eps);
+          *(float2*)(mh + 2 * n) = make_float2(mx, my);
+          *(float2*)(vh + 2 * n) = make_float2(vx, vy);
         }
+        a.h[wrow + n] = h1;
       }
-      hu = h1;
-      mvn = mv;
       if (next == NEXT_B_FULL) {
         float zl[LVMAX], mz[LVMAX], vz[LVMAX];
-        load_z(n, zl, mz, vz, false);
+        load_z(zl, mz, vz, false);
         const float2 nx = chip_quantise<1, LVMAX>(zl, 0, L, false, temperature_at(a.opt, tstep), pl.sq_mode);
         a.wself[wrow + n] = nx;
         product(nx, h1);
@@ -2421,7 +2431,7 @@ __global__ __launch_bounds__(kStep2Threads) void k_step2(FinArgs a) {
     } else {
       const float2 sv = a.self_w[wrow + n];
       float zl[LVMAX], mz[LVMAX], vz[LVMAX];
-      load_z(n, zl, mz, vz, !skip && !sgd);
+      load_z(zl, mz, vz, !skip && !sgd);
       if (!skip) {
         // dL/dz through the soft quantiser at the temperature of this step, then Adam
         const float Tc = temperature_at(a.opt, tstep);
@@ -2499,34 +2509,38 @@ __global__ __launch_bounds__(kStep2Threads) void k_step2(FinArgs a) {
       if (next == NEXT_A_FULL) product(hv, nx);
       else product(nx, hv);
     }
-  };
-  float2 hu0, hu1;    // step A: updated, unprojected filter chips
-  float4 mvn0, mvn1;  // step A: their new moments
-  chip(tid, g0, hu0, mvn0);
-  chip(tid + NT, g1, hu1, mvn1);
-  float q[5] = {q0, q1, q2, q3, 0.f};
+  }
+
+  // ---- the block's partial products; the row's last block sums them
   block_sum5<NW>(q, shr);
-  float4 prod = make_float4(q[0], q[1], q[2], q[3]);
+  float4* part = a.rowpart + (int64_t)rb * kStep2MaxSplit;
+  if (tid == 0) {
+    part[blk] = make_float4(q[0], q[1], q[2], q[3]);
+    __threadfence();  // release: the partials and this block's filter chips
+    last_sh = atomicAdd(a.rowcnt + rb, 1) == nblk - 1;
+  }
+  __syncthreads();
+  if (!last_sh) return;
+  __threadfence();  // acquire: every block's partials and filter chips
+  float4 prod = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int j = 0; j < nblk; ++j) {
+    const float4 pj = part[j];
+    prod = make_float4(prod.x + pj.x, prod.y + pj.y, prod.z + pj.z, prod.w + pj.w);
+  }
   if constexpr (kA) {
     // h <- h sqrt(N / |h|^2) over the row, and the products of the projected chips
     if (!skip) {
       const float e2 = next == NEXT_A_SNRL ? prod.z : prod.w;
       const float cn = sqrtf((float)N / e2);
-      auto put = [&](int n, float2 hu, float4 mvn) {
-        if (n >= N) return;
-        if (!sgd) {
-          *(float2*)(mh + 2 * n) = make_float2(mvn.x, mvn.y);
-          *(float2*)(vh + 2 * n) = make_float2(mvn.z, mvn.w);
-        }
-        a.h[wrow + n] = cscale(hu, cn);
-      };
-      put(tid, hu0, mvn0);
-      put(tid + NT, hu1, mvn1);
+      for (int j = tid; j < N; j += NT) a.h[wrow + j] = cscale(a.h[wrow + j], cn);
       if (next == NEXT_B_FULL) prod = make_float4(cn * prod.x, cn * prod.y, prod.z, cn * cn * prod.w);
       if (next == NEXT_A_SNRL) prod = make_float4(cn * prod.x, cn * prod.y, cn * cn * prod.z, prod.w);
     }
   }
-  if (tid == 0 && next != NEXT_NONE) a.snrl_next[r] = prod;
+  if (tid == 0) {
+    if (next != NEXT_NONE) a.snrl_next[r] = prod;
+    atomicExch(a.rowcnt + rb, 0);
+  }
 
   if (a.count_step) {
     __syncthreads();

@@ -344,8 +344,8 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     pl->group_phlog[g] = phl;
     {
       // k_step holds N <= P / 2 chips with tpc lanes each (P <= 2048),
-      // k_step2 two chips per lane (P = 4096); rows with more than 16 logit
-      // levels per lane use k_final
+      // k_step2 one chip per lane, a row over 256-chip blocks (P = 4096);
+      // rows with more than 16 logit levels per lane use k_final
       const int tpc = P >= 4096 ? 1 : step_tpc(P);
       int lv = 0;
       for (int id : gprob[g]) lv = std::max(lv, tpc > 0 ? (pl->plans[id].L + tpc - 1) / tpc : 1 << 30);

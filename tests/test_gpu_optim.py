@@ -249,8 +249,8 @@ def test_chained_graph_matches_eager_run(mods):
 def test_fallback_finalize_steps_match_oracle(ref, mods, shape):
     """Steps at FFT length 2048 (k_step with 1024 threads, one lane per chip,
     4 and 16 logit levels per lane, partner spectra by k_rowspec), at 4096
-    (k_step2, two chips per lane; k_final with two chips per thread when a
-    chip has more than 16 logit levels) and with more logit levels per lane
+    (k_step2, a row over 256-chip blocks; k_final with two chips per thread
+    when a chip has more than 16 logit levels) and with more logit levels per lane
     than k_step holds (k_final) against the oracle."""
     nat, optim, _ = mods
     M, N, L, F = shape
@@ -374,14 +374,16 @@ def test_step_logit_access_paths_match_oracle(ref, mods, layout):
 
 
 @pytest.mark.parametrize("layout", ["aligned", "misaligned"])
-def test_two_chip_step_at_fft_length_4096_matches_oracle(ref, mods, layout):
-    """k_step2 (FFT length 4096, two chips per lane of a 1024-thread block)
-    in a batch with another FFT-length group, two filter and two logit steps
-    per iteration (every next-pass preparation the chaining uses), three
-    iterations against the oracle's. 'aligned': N = 2048, the most chips a
-    row holds (every lane's second chip in use), logits moved as 16-byte
-    vectors (L = 4 and 8); 'misaligned': a first problem of 101 x 3 logits
-    shifts the rows off 16 bytes, and L = 6 takes the scalar path by its L."""
+def test_row_split_step_at_fft_length_4096_matches_oracle(ref, mods, layout):
+    """k_step2 (FFT length 4096, each row over blocks of 256 chips, the row's
+    last block summing the products and projecting the filter row) in a
+    batch with another FFT-length group, two filter and two logit steps per
+    iteration (every next-pass preparation the chaining uses), three
+    iterations against the oracle's. 'aligned': N = 2048 (eight blocks per
+    row, the most) beside N = 1100 (five; its other three blocks exit),
+    logits moved as 16-byte vectors (L = 4 and 8); 'misaligned': a first
+    problem of 101 x 3 logits shifts the rows off 16 bytes, and L = 6 takes
+    the scalar path by its L."""
     nat, optim, _ = mods
     if layout == "aligned":
         probs = [I.make_problem(2, 2048, 4, 2, p=16.0), I.make_problem(2, 1100, 8, 2, p=16.0),
@@ -390,7 +392,7 @@ def test_two_chip_step_at_fft_length_4096_matches_oracle(ref, mods, layout):
         probs = [I.make_problem(1, 101, 3, 2, p=8.0), I.make_problem(2, 1200, 8, 2, p=16.0),
                  I.make_problem(3, 1030, 6, 2, p=16.0, sq_mode=I.PHASOR_MEAN)]
     opt = I.make_opt(n_h=2, n_x=2, total_iters=20, T0=1.0, T1=0.3)
-    print(f"[gpu] two-chip step at 4096, {layout}", flush=True)
+    print(f"[gpu] row-split step at 4096, {layout}", flush=True)
     run = optim.SQNGD(probs, opt, seeds=list(range(60, 60 + len(probs))))
     s0 = [run.numpy_state(i) for i in range(len(probs))]
     iters = 3
@@ -438,15 +440,16 @@ def test_wide_gradient_reduction_steps_match_oracle(ref, mods, N):
         assert abs(sb[i]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"], (N, i)
 
 
-def test_two_chip_step_skips_nonfinite_row(mods):
-    """k_step2: a NaN logit makes the logit step's loss non-finite; the
-    step then leaves every logit of the design unchanged."""
+def test_row_split_step_skips_nonfinite_row(mods):
+    """k_step2: a NaN logit (chip 1050, the fifth of the row's five blocks)
+    makes the logit step's loss non-finite; every block then leaves its
+    logits unchanged."""
     nat, optim, _ = mods
     prob = I.make_problem(2, 1100, 8, 2, p=16.0)
     opt = I.make_opt(total_iters=10, T0=1.0, T1=0.5)
-    print("[gpu] two-chip step, non-finite", flush=True)
+    print("[gpu] row-split step, non-finite", flush=True)
     run = optim.SQNGD([prob], opt, seeds=[4])
-    run.z[8 * 1050 + 3] = float("nan")   # chip (0, 1050): a lane's second chip
+    run.z[8 * 1050 + 3] = float("nan")   # chip (0, 1050)
     z_before = run.z.clone()
     run.step()
     torch.cuda.synchronize()

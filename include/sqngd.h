@@ -158,7 +158,8 @@ typedef struct {
    partner): four transforms per block and one statistics entry and gradient
    partial row per pair (each problem's F M must be <= 4096); AUTO takes it
    for groups of at most 2048 pairs (M M F summed), e.g. one M=2 N=1200
-   F=129 design. Elsewhere the group falls back to AUTO.
+   F=129 design, and at FFT length 4096 for groups whose problems all have
+   M <= 3, at any batch size. Elsewhere the group falls back to AUTO.
    The throughput groups of FFT length <= 2048 run either one launch per
    group or all in one launch, longest FFT length first (their p must select
    the same instantiation: p = 4, 8, 16, 32, 64 or the general form). FUSED

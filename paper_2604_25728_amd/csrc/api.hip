@@ -52,8 +52,15 @@ constexpr int kMaxSplitWaves = 16;
 // Pair form of the pass (one block per (row, Doppler bin, partner)) at FFT
 // lengths 2048 and 4096: the rule takes it for groups of at most this many
 // pairs (a few rounds of the chip), where one throughput block per unit
-// would leave a partial second round of whole units.
+// would leave a partial second round of whole units; and at 4096 for groups
+// whose problems have at most kPairMaxM4096 partners at any size: there the
+// throughput pass holds one 8-wave block per CU (100 KB of LDS) and the pair
+// form two, which outweighs its extra transform per pair (measured, M=2
+// N=1200 F=129, 64 designs: pass 1405 -> 1198 us, iteration 3071 -> 2788 us;
+// M=3, 16 designs: 1433 -> 1328 us; at M=4 the larger gradient reduction of
+// F M partial rows per row cancels the faster pass).
 constexpr int64_t kPairMaxBlocks = 2048;
+constexpr int kPairMaxM4096 = 3;
 constexpr double kSplitMaxWaves = 8192.0;
 constexpr int kNumCUs = 256;  // MI355X compute units: one block per CU is the aim
 // the gradient reduction moves into k_step for groups of at least this many
@@ -197,11 +204,13 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     const int P = 1 << (g + kMinLogP);
     int hint = SQNGD_SCHED_AUTO;
     bool can = P == 512 || P == 1024, pairs2 = P == 1024;
+    int mmax = 0;
     double pair_waves = 0.0;
     for (int id : ids_p[g]) {
       if (hint == SQNGD_SCHED_AUTO) hint = probs[id].schedule;
       if (probs[id].M > kMaxSplitWaves) can = false;
       if (probs[id].M > 2) pairs2 = false;
+      mmax = std::max(mmax, (int)probs[id].M);
       pair_waves += (double)probs[id].M * probs[id].M * probs[id].F;
     }
     if (P >= 2048) {
@@ -210,7 +219,8 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
       for (int id : ids_p[g]) fit = fit && (int64_t)probs[id].F * probs[id].M <= 4096;
       // a latency-variant hint (FFT length 512 / 1024 only) acts as AUTO here
       const bool rule = hint == SQNGD_SCHED_AUTO || (hint >= SQNGD_SCHED_SPLIT2 && hint <= SQNGD_SCHED_SPLIT16);
-      pl->group_pair[g] = fit && (hint == SQNGD_SCHED_PAIR || (rule && pair_waves <= (double)kPairMaxBlocks));
+      const bool few = pair_waves <= (double)kPairMaxBlocks || (P == 4096 && mmax <= kPairMaxM4096);
+      pl->group_pair[g] = fit && (hint == SQNGD_SCHED_PAIR || (rule && few));
       continue;
     }
     bool split = can;

@@ -369,6 +369,37 @@ def test_every_schedule_at_fft_length_1024(ref, nat, sched):
         assert g["arg"] == stc["arg"]
 
 
+def test_pair_form_by_rule_for_a_batch_at_fft_length_4096(ref, nat):
+    """A batch at FFT length 4096 with more than 2048 pairs and at most three
+    partners per problem, which the automatic rule gives the pair form (eight
+    problems, N = 1100 / 1030 / 2048, M = 2 and 3): every problem's loss
+    against the throughput pass's, and two problems' statistics and both
+    gradients row by row against the oracle."""
+    probs = ([I.make_problem(2, 1100, 4, 65, p=16.0)] * 5 + [I.make_problem(3, 1030, 8, 43, p=16.0)] * 2
+             + [I.make_problem(2, 2048, 4, 9, p=16.0)])
+    assert sum(p["M"] * p["M"] * p["F"] for p in probs) > 2048
+    zs = [I.logits(p["M"], p["N"], p["L"], 80 + i) for i, p in enumerate(probs)]
+    hs = [I.complex_gaussian(p["M"], p["N"], 90 + i) for i, p in enumerate(probs)]
+    print("[gpu] pair form by rule, batch at 4096", flush=True)
+    out = {}
+    for s_ in (0, nat.SCHED_THROUGHPUT):
+        b = nat.Batch([dict(p, schedule=s_) for p in probs])
+        st = b.new_stats()
+        gz, gh, gs = b.af_backward(b.pack_z(zs), b.pack_w(hs), nat.WAVE_SOFT, want_s=True, stats=st)
+        torch.cuda.synchronize()
+        out[s_] = (b, nat.decode_stats(st.cpu().numpy()), gh, gs)
+    b, sts, gh, gs = out[0]
+    for i in range(len(probs)):
+        assert abs(sts[i]["loss"] - out[nat.SCHED_THROUGHPUT][1][i]["loss"]) <= 1e-5 * sts[i]["loss"], i
+    for i in (0, 5, 7):
+        p = probs[i]
+        sr = ref.soft_waveform(zs[i].astype(np.float64), p["temperature"])
+        st_ref, gs_ref, gh_ref = ref.evaluate(sr, hs[i].astype(np.complex128), p)
+        _check_stats(sts[i], st_ref, p["N"], ("batch 4096", i))
+        _check_rows(b.unpack_w(gs, i).cpu().numpy(), gs_ref, ("batch 4096", i, "s"))
+        _check_rows(b.unpack_w(gh, i).cpu().numpy(), gh_ref, ("batch 4096", i, "h"))
+
+
 @pytest.mark.parametrize("N", [1000, 1200])
 @pytest.mark.parametrize("sched", [1, 40])
 def test_pair_and_throughput_forms_at_fft_lengths_2048_and_4096(ref, nat, N, sched):

@@ -368,7 +368,10 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
       // k_step reduces the rows' Doppler partials itself when that takes at
       // most two load rounds per lane and either the rows alone fill half the
       // chip or a row's partials are small (one block reading a large row is
-      // slower than k_grad's many blocks reading it together)
+      // slower than k_grad's many blocks reading it together), and only with
+      // at most 4 logit levels per lane: with 16 the fused form holds about
+      // 210 VGPRs, one block per CU, and k_grad + k_step measured faster
+      // (uneven 64 x 8 batch: 14.695 -> 14.66 ms per step)
       int ne = 0, nr = 0;
       int64_t row_bytes = 0;
       for (int id : gprob[g]) {
@@ -377,7 +380,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
         nr += q.M;
         row_bytes = std::max(row_bytes, (int64_t)8 * q.wpr * q.N);
       }
-      pl->group_fuse[g] = mode != 0 && P <= 1024 && ne <= 2 * step_tpc(P) * step_fg_loads(P) &&
+      pl->group_fuse[g] = mode == 4 && P <= 1024 && ne <= 2 * step_tpc(P) * step_fg_loads(P) &&
                           (nr >= kFuseRows || row_bytes <= kFuseRowBytes);
     }
     H.group_prob[g] = (int64_t)off;

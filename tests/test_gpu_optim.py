@@ -515,15 +515,15 @@ def test_stopping_rule_run(ref, mods):
         assert abs(d["stats"]["pslr_db"] - st["pslr_db"]) <= 0.05
 
 
-@pytest.mark.parametrize("N,F", [(256, 129), (256, 200), (512, 33)])
-def test_fused_finalize_steps_match_oracle(ref, mods, N, F):
-    """A batch of 32 M=4 designs (128 rows: k_step reduces the gradient rows
-    itself, in one load round per lane at N=256 F=129 and two at F=200; at
-    N=512 the FFT length is 1024, where the finalize's one-wave spectra are
-    stored in the multi-wave layout of the pass): two iterations of its first
-    and last design against the oracle's."""
+@pytest.mark.parametrize("N,F,L", [(256, 129, 8), (256, 200, 8), (512, 33, 4)])
+def test_fused_finalize_steps_match_oracle(ref, mods, N, F, L):
+    """A batch of 32 M=4 designs (128 rows, at most 4 logit levels per lane:
+    k_step reduces the gradient rows itself, in one load round per lane at
+    N=256 F=129 and two at F=200; at N=512 the FFT length is 1024, where the
+    finalize's one-wave spectra are stored in the multi-wave layout of the
+    pass): two iterations of its first and last design against the oracle's."""
     nat, optim, _ = mods
-    prob = I.make_problem(4, N, 8, F, p=16.0)
+    prob = I.make_problem(4, N, L, F, p=16.0)
     opt = I.make_opt(total_iters=10, T0=1.0, T1=0.5)
     print(f"[gpu] fused finalize 32 x M=4 N={N} F={F}", flush=True)
     run = optim.SQNGD([prob] * 32, opt, seeds=list(range(40, 72)), schedule=nat.SCHED_THROUGHPUT)

@@ -60,6 +60,12 @@ constexpr int kMaxSplitWaves = 16;
 // M=3, 16 designs: 1433 -> 1328 us; at M=4 the larger gradient reduction of
 // F M partial rows per row cancels the faster pass).
 constexpr int64_t kPairMaxBlocks = 2048;
+// k_step2 launches of at most this many blocks finish each row in its last
+// block; larger ones in a second launch (no device-scope fence per block).
+// Measured at M=2 N=1200 L=16 F=129: 1-4 designs (10-40 blocks) 2-4 us per
+// iteration faster in the last block, 8 designs (80) even, 16 (160) 18 us
+// and 64 (640) 95 us faster with the second launch.
+constexpr int64_t kStep2LastMaxBlocks = 96;
 constexpr int kPairMaxM4096 = 3;
 constexpr double kSplitMaxWaves = 8192.0;
 constexpr int kNumCUs = 256;  // MI355X compute units: one block per CU is the aim
@@ -782,15 +788,27 @@ void launch_step_pf(const FinArgs& a, int lv, dim3 grid, hipStream_t s) {
     else hipLaunchKernelGGL((k_step<P, FIN_STEP_B, 16, FG>), grid, block, 0, s, a);
   }
 }
-// FFT length 4096: each row over split blocks of 256 chips, gradient rows from k_grad
+// FFT length 4096: each row over split blocks of 256 chips, gradient rows
+// from k_grad; the row's last block finishes it when the launch has at most
+// kStep2LastMaxBlocks blocks, else k_step2_rows in a second launch.
+template <int MODE, bool LAST>
+void launch_step2_m(const FinArgs& a, int lv, dim3 grid, hipStream_t s) {
+  if (lv == 4) hipLaunchKernelGGL((k_step2<MODE, 4, LAST>), grid, dim3(kStep2Threads), 0, s, a);
+  else hipLaunchKernelGGL((k_step2<MODE, 16, LAST>), grid, dim3(kStep2Threads), 0, s, a);
+}
 void launch_step2(const FinArgs& a, int lv, int nrows, hipStream_t s) {
-  const dim3 grid(nrows * a.split), block(kStep2Threads);
+  const dim3 grid(nrows * a.split);
+  const bool last = (int64_t)nrows * a.split <= kStep2LastMaxBlocks;
   if (a.mode == FIN_STEP_A) {
-    if (lv == 4) hipLaunchKernelGGL((k_step2<FIN_STEP_A, 4>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_step2<FIN_STEP_A, 16>), grid, block, 0, s, a);
+    if (last) launch_step2_m<FIN_STEP_A, true>(a, lv, grid, s);
+    else launch_step2_m<FIN_STEP_A, false>(a, lv, grid, s);
   } else {
-    if (lv == 4) hipLaunchKernelGGL((k_step2<FIN_STEP_B, 4>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_step2<FIN_STEP_B, 16>), grid, block, 0, s, a);
+    if (last) launch_step2_m<FIN_STEP_B, true>(a, lv, grid, s);
+    else launch_step2_m<FIN_STEP_B, false>(a, lv, grid, s);
+  }
+  if (!last) {
+    if (a.mode == FIN_STEP_A) hipLaunchKernelGGL(k_step2_rows<FIN_STEP_A>, dim3(nrows), dim3(kStep2Threads), 0, s, a);
+    else hipLaunchKernelGGL(k_step2_rows<FIN_STEP_B>, dim3(nrows), dim3(kStep2Threads), 0, s, a);
   }
 }
 template <int P>

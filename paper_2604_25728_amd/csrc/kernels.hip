@@ -2312,7 +2312,63 @@ __global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
 // arithmetic per chip as k_step with one lane per chip.
 constexpr int kStep2Threads = 256;
 constexpr int kStep2MaxSplit = 8;  // 2048 chips
-template <int MODE, int LVMAX>
+
+// The end of a row's step, by one block of kStep2Threads once every block of
+// the row has written its partial products: their sum in block order, the
+// projection of the filter row (step A, eq. 32) and the next pass's mainlobe
+// products.
+template <bool kA>
+__device__ __forceinline__ void step2_finish(const FinArgs& a, const float4* part, int nblk, bool skip, int r,
+                                             int64_t wrow, int N) {
+  constexpr int NT = kStep2Threads;
+  const int next = a.next;
+  float4 prod = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int j = 0; j < nblk; ++j) {
+    const float4 pj = part[j];
+    prod = make_float4(prod.x + pj.x, prod.y + pj.y, prod.z + pj.z, prod.w + pj.w);
+  }
+  if constexpr (kA) {
+    // h <- h sqrt(N / |h|^2) over the row, and the products of the projected chips
+    if (!skip) {
+      const float e2 = next == NEXT_A_SNRL ? prod.z : prod.w;
+      const float cn = sqrtf((float)N / e2);
+      for (int j = threadIdx.x; j < N; j += NT) a.h[wrow + j] = cscale(a.h[wrow + j], cn);
+      if (next == NEXT_B_FULL) prod = make_float4(cn * prod.x, cn * prod.y, prod.z, cn * cn * prod.w);
+      if (next == NEXT_A_SNRL) prod = make_float4(cn * prod.x, cn * prod.y, cn * cn * prod.z, prod.w);
+    }
+  }
+  if (threadIdx.x == 0 && next != NEXT_NONE) a.snrl_next[r] = prod;
+  if (a.count_step) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      const int old = atomicAdd(a.done, 1);
+      if (old == a.nrows_total - 1) {
+        atomicExch(a.done, 0);
+        atomicAdd(a.counter, 1);
+      }
+    }
+  }
+}
+
+// The row's skip decision over its whole gradient row (every thread of the
+// block gets it), and this thread's chip's gradient when the chip is n.
+__device__ __forceinline__ bool step2_skip(const FinArgs& a, int pid, int64_t wrow, int N, int n, float2& gc) {
+  bool flag = false;
+  for (int j = threadIdx.x; j < N; j += kStep2Threads) {
+    const float2 gj = a.gbuf[wrow + j];
+    flag |= !(isfinite(gj.x) && isfinite(gj.y));
+    if (j == n) gc = gj;
+  }
+  const bool hold = a.frozen != nullptr && a.frozen[pid] != 0;
+  return __syncthreads_or(flag) != 0 || a.pflag[pid] != 0 || hold;
+}
+
+// LAST: the row's last block (a per-row arrival counter, device-scope fences)
+// finishes the row; otherwise k_step2_rows does, one launch later (no fence
+// per block: each one writes back the L2's dirty lines, which large batches
+// pay for every block).
+template <int MODE, int LVMAX, bool LAST>
 __global__ __launch_bounds__(kStep2Threads) void k_step2(FinArgs a) {
   constexpr int NT = kStep2Threads, NW = NT / 64;
   constexpr bool kA = MODE == FIN_STEP_A;
@@ -2348,14 +2404,7 @@ __global__ __launch_bounds__(kStep2Threads) void k_step2(FinArgs a) {
 
   // ---- the row's skip decision from its whole gradient row; this chip's gradient
   float2 gc = zero2;
-  bool flag = false;
-  for (int j = tid; j < N; j += NT) {
-    const float2 gj = a.gbuf[wrow + j];
-    flag |= !(isfinite(gj.x) && isfinite(gj.y));
-    if (j == n) gc = gj;
-  }
-  const bool hold = a.frozen != nullptr && a.frozen[pid] != 0;
-  const bool skip = __syncthreads_or(flag) != 0 || a.pflag[pid] != 0 || hold;
+  const bool skip = step2_skip(a, pid, wrow, N, n, gc);
   const float b1 = a.opt.beta1, b2 = a.opt.beta2;
   const bool vec4 = LVMAX % 4 == 0 && (L & 3) == 0 && ((pl.off_z | pl.off_state) & 3) == 0 &&
                     (((uintptr_t)a.z | (uintptr_t)a.adam) & 15) == 0;
@@ -2511,9 +2560,13 @@ __global__ __launch_bounds__(kStep2Threads) void k_step2(FinArgs a) {
     }
   }
 
-  // ---- the block's partial products; the row's last block sums them
+  // ---- the block's partial products; the row's last block, or k_step2_rows, sums them
   block_sum5<NW>(q, shr);
   float4* part = a.rowpart + (int64_t)rb * kStep2MaxSplit;
+  if constexpr (!LAST) {
+    if (tid == 0) part[blk] = make_float4(q[0], q[1], q[2], q[3]);
+    return;
+  }
   if (tid == 0) {
     part[blk] = make_float4(q[0], q[1], q[2], q[3]);
     __threadfence();  // release: the partials and this block's filter chips
@@ -2522,37 +2575,31 @@ __global__ __launch_bounds__(kStep2Threads) void k_step2(FinArgs a) {
   __syncthreads();
   if (!last_sh) return;
   __threadfence();  // acquire: every block's partials and filter chips
-  float4 prod = make_float4(0.f, 0.f, 0.f, 0.f);
-  for (int j = 0; j < nblk; ++j) {
-    const float4 pj = part[j];
-    prod = make_float4(prod.x + pj.x, prod.y + pj.y, prod.z + pj.z, prod.w + pj.w);
-  }
-  if constexpr (kA) {
-    // h <- h sqrt(N / |h|^2) over the row, and the products of the projected chips
-    if (!skip) {
-      const float e2 = next == NEXT_A_SNRL ? prod.z : prod.w;
-      const float cn = sqrtf((float)N / e2);
-      for (int j = tid; j < N; j += NT) a.h[wrow + j] = cscale(a.h[wrow + j], cn);
-      if (next == NEXT_B_FULL) prod = make_float4(cn * prod.x, cn * prod.y, prod.z, cn * cn * prod.w);
-      if (next == NEXT_A_SNRL) prod = make_float4(cn * prod.x, cn * prod.y, cn * cn * prod.z, prod.w);
-    }
-  }
-  if (tid == 0) {
-    if (next != NEXT_NONE) a.snrl_next[r] = prod;
-    atomicExch(a.rowcnt + rb, 0);
-  }
+  if (tid == 0) atomicExch(a.rowcnt + rb, 0);
+  step2_finish<kA>(a, part, nblk, skip, r, wrow, N);
+}
 
-  if (a.count_step) {
-    __syncthreads();
-    if (tid == 0) {
-      __threadfence();
-      const int old = atomicAdd(a.done, 1);
-      if (old == a.nrows_total - 1) {
-        atomicExch(a.done, 0);
-        atomicAdd(a.counter, 1);
-      }
-    }
+// The rows' ends after k_step2<..., false>: one block of kStep2Threads per row.
+template <int MODE>
+__global__ __launch_bounds__(kStep2Threads) void k_step2_rows(FinArgs a) {
+  const int rb = blockIdx.x;
+  int r, pid;
+  ProbPlan pl;
+  if (a.single) {
+    r = rb;
+    pid = 0;
+    pl = a.one;
+  } else {
+    r = a.rows[rb];
+    pid = a.row_prob[r];
+    pl = a.plans[pid];
   }
+  const int N = pl.N;
+  const int64_t wrow = pl.off_w + (int64_t)(r - pl.row0) * N;
+  float2 gc = make_float2(0.f, 0.f);
+  const bool skip = step2_skip(a, pid, wrow, N, -1, gc);
+  step2_finish<MODE == FIN_STEP_A>(a, a.rowpart + (int64_t)rb * kStep2MaxSplit, (N + kStep2Threads - 1) / kStep2Threads,
+                                   skip, r, wrow, N);
 }
 
 // ------------------------------------------------------------ k_pass_split

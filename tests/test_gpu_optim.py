@@ -440,6 +440,32 @@ def test_wide_gradient_reduction_steps_match_oracle(ref, mods, N):
         assert abs(sb[i]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"], (N, i)
 
 
+def test_row_split_step_in_two_launches_matches_oracle(ref, mods):
+    """k_step2 for a launch of more than 96 blocks (12 designs of two rows,
+    five blocks per row): the blocks write their partial products and
+    k_step2_rows finishes each row in a second launch. Three iterations of
+    two filter and two logit steps; two designs against the oracle's."""
+    nat, optim, _ = mods
+    prob = I.make_problem(2, 1100, 4, 2, p=16.0)
+    opt = I.make_opt(n_h=2, n_x=2, total_iters=20, T0=1.0, T1=0.3)
+    print("[gpu] row-split step in two launches", flush=True)
+    run = optim.SQNGD([prob] * 12, opt, seeds=list(range(110, 122)))
+    picks = (0, 11)
+    s0 = {i: run.numpy_state(i) for i in picks}
+    run.step(3)
+    torch.cuda.synchronize()
+    sa, sb = run.step_stats()
+    for i in picks:
+        s1 = run.numpy_state(i)
+        z, h, state = s0[i]["z"], s0[i]["h"], s0[i]["state"]
+        for t in range(3):
+            z, h, state, sta, stb = ref.step(prob, opt, z, h, state, t)
+        assert _rel(s1["h"], h) <= 1e-4, (i, _rel(s1["h"], h))
+        assert _rel(s1["z"], z) <= 1e-4, (i, _rel(s1["z"], z))
+        assert abs(sa[i]["loss"] - sta["loss"]) <= 1e-4 * sta["loss"], i
+        assert abs(sb[i]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"], i
+
+
 def test_row_split_step_skips_nonfinite_row(mods):
     """k_step2: a NaN logit (chip 1050, the fifth of the row's five blocks)
     makes the logit step's loss non-finite; every block then leaves its

@@ -155,7 +155,7 @@ struct Plan {
   int group_step[kNumPGroups];
   bool group_fuse[kNumPGroups];  // k_step reduces the gradient rows itself (no k_grad launch)
   bool all_step = true;  // every group runs k_step: the step counter advances in the next pass
-  int step2_split = 1;   // k_step2 blocks per row at FFT length 4096: the group's longest row in 256-chip blocks
+  int step2_split[kNumPGroups] = {};  // k_step2 blocks per row (FFT lengths 2048, 4096): longest row in 256-chip blocks
   int maxN = 0;
   // throughput groups (bit g: FFT length 128 << g) that share one launch
   // (k_pass_multi), 0 for one launch per group
@@ -359,16 +359,16 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     H.group_rwaves[g] = rsum;
     pl->group_phlog[g] = phl;
     {
-      // k_step holds N <= P / 2 chips with tpc lanes each (P <= 2048),
-      // k_step2 one chip per lane, a row over 256-chip blocks (P = 4096);
+      // k_step holds N <= P / 2 chips with tpc lanes each (P <= 1024),
+      // k_step2 one chip per lane, a row over 256-chip blocks (P >= 2048);
       // rows with more than 16 logit levels per lane use k_final
-      const int tpc = P >= 4096 ? 1 : step_tpc(P);
+      const int tpc = P >= 2048 ? 1 : step_tpc(P);
       int lv = 0;
       for (int id : gprob[g]) lv = std::max(lv, tpc > 0 ? (pl->plans[id].L + tpc - 1) / tpc : 1 << 30);
       const int mode = tpc < 1 ? 0 : (lv <= 4 ? 4 : (lv <= 16 ? 16 : 0));
-      if (P >= 4096)
+      if (P >= 2048)
         for (int id : gprob[g])
-          pl->step2_split = std::max(pl->step2_split, (pl->plans[id].N + kStep2Threads - 1) / kStep2Threads);
+          pl->step2_split[g] = std::max(pl->step2_split[g], (pl->plans[id].N + kStep2Threads - 1) / kStep2Threads);
       pl->group_step[g] = mode;
       if (!gprob[g].empty() && mode == 0) pl->all_step = false;
       // k_step reduces the rows' Doppler partials itself when that takes at
@@ -406,9 +406,10 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
   // counters live in the uploaded table region, so the upload zeroes them
   H.counters = (int64_t)off;
   off = align_up(off + 4 * kNumCounters);
-  const int rows4096 = H.group_nrows[kNumPGroups - 1];
+  // k_step2's per-row scratch, shared by the FFT-length-2048 and -4096 groups (stream-ordered launches)
+  const int rows_split = std::max(H.group_nrows[kNumPGroups - 1], H.group_nrows[kNumPGroups - 2]);
   H.rowsync = (int64_t)off;
-  off = align_up(off + 4 * (size_t)rows4096);
+  off = align_up(off + 4 * (size_t)rows_split);
   const size_t table_bytes = off;
   H.spec = (int64_t)off;
   off = align_up(off + 8 * (size_t)spec);
@@ -427,7 +428,7 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
   H.pflag = (int64_t)off;
   off = align_up(off + 4 * (size_t)nprob);
   H.rowpart = (int64_t)off;
-  off = align_up(off + 16 * (size_t)kStep2MaxSplit * rows4096);
+  off = align_up(off + 16 * (size_t)kStep2MaxSplit * rows_split);
   H.total = (int64_t)off;
   int maxN = 0;
   for (int i = 0; i < nprob; ++i) maxN = probs[i].N > maxN ? probs[i].N : maxN;
@@ -788,7 +789,7 @@ void launch_step_pf(const FinArgs& a, int lv, dim3 grid, hipStream_t s) {
     else hipLaunchKernelGGL((k_step<P, FIN_STEP_B, 16, FG>), grid, block, 0, s, a);
   }
 }
-// FFT length 4096: each row over split blocks of 256 chips, gradient rows
+// FFT lengths 2048 and 4096: each row over split blocks of 256 chips, gradient rows
 // from k_grad; the row's last block finishes it when the launch has at most
 // kStep2LastMaxBlocks blocks, else k_step2_rows in a second launch.
 template <int MODE, bool LAST>
@@ -868,10 +869,9 @@ void launch_final(const Plan& pl, const Ptrs& w, FinArgs a, hipStream_t s) {
         case 1: launch_step_p<256>(a, lv, fuse, grid, s); break;
         case 2: launch_step_p<512>(a, lv, fuse, grid, s); break;
         case 3: launch_step_p<1024>(a, lv, fuse, grid, s); break;
-        case 4: launch_step_p<2048>(a, lv, fuse, grid, s); break;
-        default: {
+        default: {  // P >= 2048
           FinArgs a2 = a;
-          a2.split = pl.step2_split;
+          a2.split = pl.step2_split[g];
           a2.rowcnt = w.rowsync;
           a2.rowpart = w.rowpart;
           launch_step2(a2, lv, pl.hdr.group_nrows[g], s);

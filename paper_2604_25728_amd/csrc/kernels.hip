@@ -2300,16 +2300,17 @@ __global__ __launch_bounds__(step_threads(P)) void k_step(FinArgs a) {
 
 // ------------------------------------------------------------ k_step2
 
-// k_step for FFT length 4096 (up to 2048 chips per row): a row is split over
-// ceil(N / 256) blocks of 256 threads, one chip per thread, with the gradient
-// rows from k_grad. Every block reads the whole row's gradient for the row's
-// skip decision (a non-finite loss, a stopped design or a non-finite gradient
-// chip), so each chip's new logits and moments are written as soon as they
-// are formed. The row's products for the next pass (and in step A the
-// filter's energy) are summed by the row's last block, from the blocks'
-// partial sums in block order; in step A that block then projects the whole
-// filter row (eq. 32), which the other blocks have written unprojected. Same
-// arithmetic per chip as k_step with one lane per chip.
+// k_step for FFT lengths 2048 and 4096 (up to 1024 / 2048 chips per row): a
+// row is split over ceil(N / 256) blocks of 256 threads, one chip per thread,
+// with the gradient rows from k_grad. Every block reads the whole row's
+// gradient for the row's skip decision (a non-finite loss, a stopped design or
+// a non-finite gradient chip), so each chip's new logits and moments are
+// written as soon as they are formed. The row's products for the next pass
+// (and in step A the filter's energy) are summed by the row's last block, or
+// by k_step2_rows one launch later, from the blocks' partial sums in block
+// order; in step A that block then projects the whole filter row (eq. 32),
+// which the other blocks have written unprojected. Same arithmetic per chip
+// as k_step with one lane per chip.
 constexpr int kStep2Threads = 256;
 constexpr int kStep2MaxSplit = 8;  // 2048 chips
 

@@ -65,8 +65,8 @@ struct WsHeader {
   int64_t snrl;  // float4 [2][rows]: mainlobe products, double-buffered by pass parity
   int64_t gbuf;   // float2 [sum M N]: gradient rows of an optimiser step (packed waveform layout)
   int64_t pflag;  // int32 [nprob]: non-finite loss of the step's evaluation
-  int64_t rowsync;  // int32 [rows of FFT length 4096]: k_step2's blocks done per row (in the zeroed table)
-  int64_t rowpart;  // float4 [rows of FFT length 4096][8]: k_step2's partial products per block
+  int64_t rowsync;  // int32 [rows of FFT length 2048 or 4096]: k_step2's blocks done per row (in the zeroed table)
+  int64_t rowpart;  // float4 [rows of FFT length 2048 or 4096][8]: k_step2's partial products per block
   int64_t total;
 };
 

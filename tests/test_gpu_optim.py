@@ -247,10 +247,10 @@ def test_chained_graph_matches_eager_run(mods):
 @pytest.mark.parametrize("shape", [(2, 1024, 4, 3), (3, 1000, 16, 3), (2, 1100, 8, 2), (2, 1100, 24, 2),
                                    (2, 300, 64, 5)])
 def test_fallback_finalize_steps_match_oracle(ref, mods, shape):
-    """Steps at FFT length 2048 (k_step with 1024 threads, one lane per chip,
-    4 and 16 logit levels per lane, partner spectra by k_rowspec), at 4096
-    (k_step2, a row over 256-chip blocks; k_final with two chips per thread
-    when a chip has more than 16 logit levels) and with more logit levels per lane
+    """Steps at FFT lengths 2048 and 4096 (k_step2: a row over 256-chip
+    blocks, one lane per chip, 4 and 16 logit levels per lane, partner
+    spectra by k_rowspec; k_final with two chips per thread at 4096 when a
+    chip has more than 16 logit levels) and with more logit levels per lane
     than k_step holds (k_final) against the oracle."""
     nat, optim, _ = mods
     M, N, L, F = shape
@@ -343,7 +343,7 @@ def test_mixed_batch_steps_match_oracle(ref, mods):
 
 @pytest.mark.parametrize("layout", ["aligned", "misaligned"])
 def test_step_logit_access_paths_match_oracle(ref, mods, layout):
-    """k_step with one lane per chip (FFT lengths 1024 and 2048) moves a chip's
+    """k_step and k_step2 with one lane per chip (FFT lengths 1024, 2048) move a chip's
     logits and moments as 16-byte vectors only when L is a multiple of 4 and
     the rows are 16-byte aligned. 'aligned': two problems that take the
     vector path (L = 8 and 4); 'misaligned': a first problem of 101 x 3

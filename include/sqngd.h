@@ -137,8 +137,19 @@ typedef struct {
   float temperature;      /* softmax temperature T > 0 (SOFT mode)               */
   int32_t sq_mode;        /* SQNGD_SQ_PHASE_MEAN | SQNGD_SQ_PHASOR_MEAN           */
   int32_t schedule;       /* fused-pass schedule hint, SQNGD_SCHED_* (0: automatic) */
-  int32_t reserved;       /* must be 0                                           */
+  int32_t auto_mask;      /* SQNGD_MASK_TAU0 (0) | SQNGD_MASK_MAINLOBE (1)       */
 } sqngd_problem;
+
+/* Which tau = 0 cells of the auto-ambiguity functions (m1 = m2) leave the
+   region of interest. Eq. 8 drops the whole tau = 0 Doppler cut of an auto
+   pair (the mainlobe and its Doppler sidelobes): SQNGD_MASK_TAU0, the default.
+   SQNGD_MASK_MAINLOBE drops only the cells of that cut inside the Doppler
+   mainlobe, |nu_f| < 1 (the first nulls of A_mm(0, nu) = sum_n e^{j 2 pi n nu
+   / N} for a matched unimodular pair, with eq. 6's normalisation); the cut's
+   cells at |nu_f| >= 1 count as sidelobes. Cross pairs keep every delay (eq.
+   9) in either mode. Any other value: SQNGD_E_INVALID_ARG. */
+#define SQNGD_MASK_TAU0 0
+#define SQNGD_MASK_MAINLOBE 1
 
 /* Schedule of the fused AF pass (an implementation choice; every schedule
    computes the same results to rounding), decided per FFT-length group (the
@@ -194,7 +205,7 @@ typedef struct {
   float loss;        /* w_psl * lp + w_snrl * l_snrl (eq. 42)                    */
   float lp;          /* (sum over the ROI of a^p)^(1/p), a = |A|/N              */
   float l_snrl;      /* eq. 41                                                   */
-  float psl_auto;    /* max |A| over auto pairs, tau != 0 (eq. 8, w = 1)         */
+  float psl_auto;    /* max |A| over auto pairs' ROI cells (eq. 8, w = 1)        */
   float psl_cross;   /* max |A| over cross pairs (eq. 9, w = 1)                  */
   float pslr_db;     /* 20 log10(max(psl_auto, psl_cross) / N)  (eq. 48)         */
   float snrl_db_max; /* max over m of 10 log10(|s|^2 |h|^2 / |h^H s|^2) (eq. 10) */

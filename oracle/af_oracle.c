@@ -90,12 +90,15 @@ void sqngd_ref_af_row(int M, int N, int F, double nu_min, double nu_max, const d
 
 /* Region of interest (eq. 7-9): a cell (m, l, tau, f) counts when
    tau_lo <= tau <= tau_hi, except the tau = 0 cut of an auto pair (eq. 8
-   excludes tau = 0 for m1 = m2; eq. 9 keeps every tau for m1 != m2). Inside it
-   a cell carries the weight w(tau, f) of eq. 8-9: wt[f][tau + N - 1] when a
-   table is given, else 1. */
-static int in_roi(int m, int l, int tau, int tau_lo, int tau_hi) {
+   excludes tau = 0 for m1 = m2; eq. 9 keeps every tau for m1 != m2). With
+   auto_mask = 1 (an option beside the paper's rule) only the cells of that cut
+   inside the Doppler mainlobe, |nu_f| < 1, are excluded: A_mm(0, nu) of a
+   matched unimodular pair is sum_n e^{j 2 pi n nu / N}, whose first nulls sit
+   at nu = +-1. Inside the region a cell carries the weight w(tau, f) of eq.
+   8-9: wt[f][tau + N - 1] when a table is given, else 1. */
+static int in_roi(int m, int l, int tau, double nu, int tau_lo, int tau_hi, int auto_mask) {
   if (tau < tau_lo || tau > tau_hi) return 0;
-  if (m == l && tau == 0) return 0;
+  if (m == l && tau == 0 && (auto_mask == 0 || fabs(nu) < 1.0)) return 0;
   return 1;
 }
 static double roi_weight(const double* wt, int N, int f, int tau) {
@@ -116,8 +119,9 @@ static double roi_weight(const double* wt, int N, int f, int tau) {
    the larger of the two PSLs. snrl_db and pm (length M, may be NULL) receive
    SNRL_m and p_m. lp is evaluated as amax (sum (a/amax)^p)^(1/p), which equals
    the definition and does not overflow. */
-void sqngd_ref_loss(int M, int N, int F, const double* A_in, const double* s_in, const double* h_in,
-                    int tau_lo, int tau_hi, const double* wt, double p, double mu_db, double w_psl,
+void sqngd_ref_loss(int M, int N, int F, double nu_min, double nu_max, const double* A_in,
+                    const double* s_in, const double* h_in, int tau_lo, int tau_hi, int auto_mask,
+                    const double* wt, double p, double mu_db, double w_psl,
                     double w_snrl, double* out, int* arg, double* snrl_db, double* pm) {
   const cplx* A = (const cplx*)A_in;
   const cplx* s = (const cplx*)s_in;
@@ -130,7 +134,7 @@ void sqngd_ref_loss(int M, int N, int F, const double* A_in, const double* s_in,
     for (int l = 0; l < M; ++l)
       for (int f = 0; f < F; ++f)
         for (int tau = -(N - 1); tau <= N - 1; ++tau) {
-          if (!in_roi(m, l, tau, tau_lo, tau_hi)) continue;
+          if (!in_roi(m, l, tau, sqngd_ref_nu(F, nu_min, nu_max, f), tau_lo, tau_hi, auto_mask)) continue;
           double v = roi_weight(wt, N, f, tau) * cabs(A[(((size_t)m * M + l) * F + f) * T + tau + N - 1]);
           if (m == l) {
             if (v > psl_auto) psl_auto = v;
@@ -149,7 +153,7 @@ void sqngd_ref_loss(int M, int N, int F, const double* A_in, const double* s_in,
       for (int l = 0; l < M; ++l)
         for (int f = 0; f < F; ++f)
           for (int tau = -(N - 1); tau <= N - 1; ++tau) {
-            if (!in_roi(m, l, tau, tau_lo, tau_hi)) continue;
+            if (!in_roi(m, l, tau, sqngd_ref_nu(F, nu_min, nu_max, f), tau_lo, tau_hi, auto_mask)) continue;
             double a = roi_weight(wt, N, f, tau) * cabs(A[(((size_t)m * M + l) * F + f) * T + tau + N - 1]) / N;
             acc += pow(a / amax, p);
           }
@@ -201,8 +205,8 @@ void sqngd_ref_loss(int M, int N, int F, const double* A_in, const double* s_in,
      grad_s_m += G_S h_m,  grad_h_m += conj(G_S) s_m.
    Requires the cube of sqngd_ref_af_cube for the same inputs. */
 void sqngd_ref_grads(int M, int N, int F, double nu_min, double nu_max, const double* s_in,
-                     const double* h_in, const double* A_in, int tau_lo, int tau_hi, const double* wt,
-                     double p, double mu_db, double w_psl, double w_snrl, double* gs_out,
+                     const double* h_in, const double* A_in, int tau_lo, int tau_hi, int auto_mask,
+                     const double* wt, double p, double mu_db, double w_psl, double w_snrl, double* gs_out,
                      double* gh_out) {
   const cplx* s = (const cplx*)s_in;
   const cplx* h = (const cplx*)h_in;
@@ -211,8 +215,8 @@ void sqngd_ref_grads(int M, int N, int F, double nu_min, double nu_max, const do
   cplx* gh = (cplx*)gh_out;
   const int T = 2 * N - 1;
   double stats[8];
-  sqngd_ref_loss(M, N, F, A_in, s_in, h_in, tau_lo, tau_hi, wt, p, mu_db, w_psl, w_snrl, stats, NULL,
-                 NULL, NULL);
+  sqngd_ref_loss(M, N, F, nu_min, nu_max, A_in, s_in, h_in, tau_lo, tau_hi, auto_mask, wt, p, mu_db,
+                 w_psl, w_snrl, stats, NULL, NULL, NULL);
   const double lp = stats[1];
   const size_t ncell = (size_t)M * M * F * T;
   cplx* G = (cplx*)calloc(ncell, sizeof(cplx));
@@ -221,7 +225,7 @@ void sqngd_ref_grads(int M, int N, int F, double nu_min, double nu_max, const do
       for (int l = 0; l < M; ++l)
         for (int f = 0; f < F; ++f)
           for (int tau = -(N - 1); tau <= N - 1; ++tau) {
-            if (!in_roi(m, l, tau, tau_lo, tau_hi)) continue;
+            if (!in_roi(m, l, tau, sqngd_ref_nu(F, nu_min, nu_max, f), tau_lo, tau_hi, auto_mask)) continue;
             size_t i = (((size_t)m * M + l) * F + f) * T + tau + N - 1;
             double w = roi_weight(wt, N, f, tau);
             double a = w * cabs(A[i]) / N;

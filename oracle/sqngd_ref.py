@@ -26,7 +26,9 @@ design notes of the repository):
 
 A problem is a plain dict with the keys M, N, L, F, nu_min, nu_max, tau_lo,
 tau_hi, p, snrl_target_db, w_psl, w_snrl, temperature, sq_mode (0 phase-mean,
-1 phasor-mean), and optionally roi_w: the weights w(tau, f) of eq. 8-9 as an
+1 phasor-mean), optionally auto_mask (0, the default: an auto pair's whole
+tau = 0 cut is outside the region, eq. 8; 1: only its Doppler-mainlobe cells
+|nu_f| < 1 are) and optionally roi_w: the weights w(tau, f) of eq. 8-9 as an
 [F][2N-1] array (tau + N - 1 fastest; absent or None means w = 1). Options of an outer iteration are a dict with lr_z, lr_h,
 beta1, beta2, eps, n_h, n_x, T0, T1, total_iters, flags (1 = plain gradient
 descent).
@@ -70,9 +72,9 @@ def _load():
         lib.sqngd_ref_af_row.restype = None
         lib.sqngd_ref_af_row.argtypes = [i, i, i, d, d, P, P, i, i, i, P]
         lib.sqngd_ref_loss.restype = None
-        lib.sqngd_ref_loss.argtypes = [i, i, i, P, P, P, i, i, P, d, d, d, d, P, P, P, P]
+        lib.sqngd_ref_loss.argtypes = [i, i, i, d, d, P, P, P, i, i, i, P, d, d, d, d, P, P, P, P]
         lib.sqngd_ref_grads.restype = None
-        lib.sqngd_ref_grads.argtypes = [i, i, i, d, d, P, P, P, i, i, P, d, d, d, d, P, P]
+        lib.sqngd_ref_grads.argtypes = [i, i, i, d, d, P, P, P, i, i, i, P, d, d, d, d, P, P]
         _lib = lib
     return _lib
 
@@ -136,8 +138,9 @@ def loss_stats(cube: np.ndarray, s, h, prob: dict) -> dict:
     snrl = np.zeros(M)
     pm = np.zeros(M)
     wt = _weights(prob, N, F)
-    _load().sqngd_ref_loss(M, N, F, _ptr(cube), _ptr(s), _ptr(h), int(prob["tau_lo"]),
-                           int(prob["tau_hi"]), _ptr(wt), float(prob["p"]), float(prob["snrl_target_db"]),
+    _load().sqngd_ref_loss(M, N, F, float(prob["nu_min"]), float(prob["nu_max"]), _ptr(cube), _ptr(s),
+                           _ptr(h), int(prob["tau_lo"]), int(prob["tau_hi"]), int(prob.get("auto_mask", 0)),
+                           _ptr(wt), float(prob["p"]), float(prob["snrl_target_db"]),
                            float(prob["w_psl"]), float(prob["w_snrl"]), _ptr(out), _ptr(arg),
                            _ptr(snrl), _ptr(pm))
     keys = ["loss", "lp", "l_snrl", "psl_auto", "psl_cross", "pslr_db", "snrl_db_max", "p_min"]
@@ -160,7 +163,8 @@ def grads(s, h, prob: dict, cube: np.ndarray | None = None):
     gh = np.zeros((M, N), dtype=np.complex128)
     wt = _weights(prob, N, F)
     _load().sqngd_ref_grads(M, N, F, float(prob["nu_min"]), float(prob["nu_max"]), _ptr(s), _ptr(h),
-                            _ptr(cube), int(prob["tau_lo"]), int(prob["tau_hi"]), _ptr(wt), float(prob["p"]),
+                            _ptr(cube), int(prob["tau_lo"]), int(prob["tau_hi"]), int(prob.get("auto_mask", 0)),
+                            _ptr(wt), float(prob["p"]),
                             float(prob["snrl_target_db"]), float(prob["w_psl"]),
                             float(prob["w_snrl"]), _ptr(gs), _ptr(gh))
     return gs, gh

@@ -121,7 +121,7 @@ int validate_problem(const sqngd_problem& p) {
   if (!finite(p.w_psl) || !finite(p.w_snrl) || p.w_psl < 0.0f || p.w_snrl < 0.0f) return SQNGD_E_INVALID_ARG;
   if (!finite(p.temperature) || p.temperature <= 0.0f) return SQNGD_E_INVALID_ARG;
   if (p.sq_mode != SQNGD_SQ_PHASE_MEAN && p.sq_mode != SQNGD_SQ_PHASOR_MEAN) return SQNGD_E_INVALID_ARG;
-  if (p.reserved != 0) return SQNGD_E_INVALID_ARG;
+  if (p.auto_mask != SQNGD_MASK_TAU0 && p.auto_mask != SQNGD_MASK_MAINLOBE) return SQNGD_E_INVALID_ARG;
   if (p.schedule != SQNGD_SCHED_AUTO && p.schedule != SQNGD_SCHED_THROUGHPUT && p.schedule != SQNGD_SCHED_SPLIT2 &&
       p.schedule != SQNGD_SCHED_SPLIT4 && p.schedule != SQNGD_SCHED_SPLIT8 && p.schedule != SQNGD_SCHED_SPLIT12 &&
       p.schedule != SQNGD_SCHED_SPLIT16 && p.schedule != SQNGD_SCHED_GROUPED && p.schedule != SQNGD_SCHED_FUSED &&
@@ -285,6 +285,18 @@ std::unique_ptr<Plan> build_plan(const sqngd_problem* probs, int32_t nprob) {
     q.tau_hi = p.tau_hi;
     q.nu_min = (double)p.nu_min;
     q.dnu = p.F > 1 ? ((double)p.nu_max - (double)p.nu_min) / (double)(p.F - 1) : 0.0;
+    q.cut_lo = 0;
+    q.cut_hi = p.F;
+    if (p.auto_mask == SQNGD_MASK_MAINLOBE) {
+      // the bins the pass modulates with |nu_f| < 1 (nu_f increases with f,
+      // so they are one run [cut_lo, cut_hi), possibly empty)
+      q.cut_lo = q.cut_hi = 0;
+      for (int f = 0; f < p.F; ++f)
+        if (std::fabs(q.nu_min + (double)f * q.dnu) < 1.0) {
+          if (q.cut_hi == 0) q.cut_lo = f;
+          q.cut_hi = f + 1;
+        }
+    }
     q.p = p.p;
     q.p_tar = (float)std::pow(10.0, -(double)p.snrl_target_db / 20.0);
     q.w_psl = p.w_psl;

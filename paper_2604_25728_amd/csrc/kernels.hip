@@ -119,7 +119,8 @@ __device__ __forceinline__ void phasor_row(int t, double nu, double invN, float2
 
 // In-ROI scan of one AF row held as R[e] = P A(tau') at r-index k = t + TF e
 // (ROI cells: tau' = -k for k < N, P - k for k > P - N, inside [wlo, whi],
-// without tau' = 0 on an auto pair): the valid-cell mask and the lane's
+// without tau' = 0 when auto_pair: an auto pair at a Doppler bin whose tau = 0
+// cell the problem's mask removes): the valid-cell mask and the lane's
 // largest |r|^2 with its lowest index.
 template <int P, int TF, int E>
 __device__ __forceinline__ void roi_scan(const float2 (&R)[E], int t, int N, int wlo, int whi, bool auto_pair,
@@ -758,7 +759,7 @@ __device__ __forceinline__ void pass_block(const PassArgs& a, int blk, PassSmem<
     int kbest;
     if (cube != nullptr && active) cube_store<P, TF, E>(R, t, N, cube + ((int64_t)(w * M + g) * F + f) * T2);
     if constexpr (WT) roi_weigh<P, TF, E>(R, t, N, a.orient, wrow);  // a = w |A| / N from here on
-    roi_scan<P, TF, E>(R, t, N, wlo, whi, g == w, vmask, qmax, kbest);
+    roi_scan<P, TF, E>(R, t, N, wlo, whi, g == w && f >= pl.cut_lo && f < pl.cut_hi, vmask, qmax, kbest);
     // this lane's largest cell of the pair (lowest index among equal values)
     const unsigned long long key = vmask ? make_key(qmax, (uint32_t)(((int64_t)u * M + g) * P + kbest)) : 0ull;
     if (g == w) kauto = umax64(kauto, key);
@@ -2739,7 +2740,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   if (a.cube != nullptr && active)
     cube_store<P, 64, E>(R, t, N, a.cube + pl.off_cube + ((int64_t)(w * M + g) * F + f) * (2 * N - 1));
   if constexpr (WT) roi_weigh_reg<E>(R, WR);  // a = w |A| / N from here on
-  roi_scan<P, 64, E>(R, t, N, wlo, whi, g == w, vmask, qmax, kbest);
+  roi_scan<P, 64, E>(R, t, N, wlo, whi, g == w && f >= pl.cut_lo && f < pl.cut_hi, vmask, qmax, kbest);
   // wave maximum, and its cell from the lowest lane that holds it
   const float qw = wave_max(qmax);
   const unsigned long long holders = __ballot(vmask != 0 && qmax == qw);
@@ -2941,7 +2942,7 @@ __global__ __launch_bounds__(64 * PassGeom<P>::WAVES, 4) void k_pass_pair(PassAr
   uint32_t vmask;
   float qmax;
   int kbest;
-  roi_scan<P, TF, E>(R, t, N, wlo, whi, g == w, vmask, qmax, kbest);
+  roi_scan<P, TF, E>(R, t, N, wlo, whi, g == w && f >= pl.cut_lo && f < pl.cut_hi, vmask, qmax, kbest);
   unsigned long long key = vmask ? make_key(qmax, (uint32_t)(((int64_t)u * M + g) * P + kbest)) : 0ull;
   key = fft_lanes_max_key<G>(key, red_k);
   qmax = fft_lanes_reduce<G>(qmax, 0.0f, OpMax(), red_f);

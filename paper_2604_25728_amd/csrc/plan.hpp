@@ -31,8 +31,11 @@ struct ProbPlan {
   // Doppler grid nu_f = nu_min + f dnu in FP64: wide spans put hundreds of
   // turns into the modulation phase n nu_f / N, whose fraction FP32 would lose
   double nu_min, dnu;
+  // Doppler bins [cut_lo, cut_hi) whose auto-pair tau = 0 cell is outside the
+  // region of interest: every bin (eq. 8), or the mainlobe bins |nu_f| < 1
+  int32_t cut_lo, cut_hi;
 };
-static_assert(sizeof(ProbPlan) == 160, "ProbPlan layout");
+static_assert(sizeof(ProbPlan) == 168, "ProbPlan layout");
 
 
 // Per-unit partial statistics of one fused pass. Keys pack the squared raw

@@ -40,8 +40,11 @@ PHASOR_MEAN = 1
 def make_problem(M: int, N: int, L: int, F: int, nu_min: float = -0.5, nu_max: float = 0.5,
                  p: float = 16.0, snrl_target_db: float = 0.5, w_psl: float = 1.0,
                  w_snrl: float = 1.0, temperature: float = 1.0, sq_mode: int = PHASE_MEAN,
-                 tau_lo: int | None = None, tau_hi: int | None = None) -> dict:
-    """A problem dict with every delay in the region of interest by default."""
+                 tau_lo: int | None = None, tau_hi: int | None = None, auto_mask: int = 0) -> dict:
+    """A problem dict with every delay in the region of interest by default.
+
+    auto_mask 0 leaves every auto pair's tau = 0 cut out of the region (eq. 8),
+    1 only its Doppler-mainlobe cells |nu_f| < 1."""
     return {
         "M": int(M), "N": int(N), "L": int(L), "F": int(F),
         "nu_min": float(nu_min), "nu_max": float(nu_max),
@@ -50,6 +53,7 @@ def make_problem(M: int, N: int, L: int, F: int, nu_min: float = -0.5, nu_max: f
         "p": float(p), "snrl_target_db": float(snrl_target_db),
         "w_psl": float(w_psl), "w_snrl": float(w_snrl),
         "temperature": float(temperature), "sq_mode": int(sq_mode),
+        "auto_mask": int(auto_mask),
     }
 
 

@@ -29,6 +29,8 @@ SYMBOLS = [
     "sqngd_profile_groups",
 ]
 E_SCRATCH = -6
+MASK_TAU0 = 0      # eq. 8: an auto pair's whole tau = 0 Doppler cut is outside the ROI
+MASK_MAINLOBE = 1  # only the cut's mainlobe cells |nu_f| < 1 are outside it
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
@@ -38,7 +40,7 @@ class Problem(ctypes.Structure):
                 ("tau_lo", ctypes.c_int32), ("tau_hi", ctypes.c_int32), ("p", ctypes.c_float),
                 ("snrl_target_db", ctypes.c_float), ("w_psl", ctypes.c_float),
                 ("w_snrl", ctypes.c_float), ("temperature", ctypes.c_float),
-                ("sq_mode", ctypes.c_int32), ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sq_mode", ctypes.c_int32), ("schedule", ctypes.c_int32), ("auto_mask", ctypes.c_int32)]
 
 
 class Opt(ctypes.Structure):
@@ -136,6 +138,7 @@ def make_problems(probs) -> ctypes.Array:
         for k in ("M", "N", "L", "F", "tau_lo", "tau_hi", "sq_mode"):
             setattr(p, k, int(d[k]))
         p.schedule = int(d.get("schedule", SCHED_AUTO))
+        p.auto_mask = int(d.get("auto_mask", MASK_TAU0))
         for k in ("nu_min", "nu_max", "p", "snrl_target_db", "w_psl", "w_snrl", "temperature"):
             setattr(p, k, float(d[k]))
     return arr

@@ -14,8 +14,14 @@ def peak_and_gap(cube, prob, weights=None):
     v = np.abs(cube) * (1.0 if weights is None else np.asarray(weights)[None, None])
     inside = np.broadcast_to(((tau >= prob["tau_lo"]) & (tau <= prob["tau_hi"]))[None, None, None, :],
                              v.shape).copy()
+    # auto pairs' tau = 0 cells outside the region: every bin (eq. 8), or with
+    # auto_mask = 1 the bins of the Doppler mainlobe |nu| < 1
+    cut = np.ones(F, dtype=bool)
+    if prob.get("auto_mask", 0) == 1:
+        cut = np.abs(np.linspace(prob["nu_min"], prob["nu_max"], F) if F > 1
+                     else np.array([prob["nu_min"]])) < 1.0
     for m in range(M):
-        inside[m, m, :, N - 1] = False
+        inside[m, m, cut, N - 1] = False
     v = np.where(inside, v, -1.0).reshape(-1)
     top2 = np.partition(v, -2)[-2:]
     hi, lo = float(top2.max()), float(top2.min())

@@ -102,10 +102,11 @@ def test_problem_validation(nat, field, value, code):
     assert rc == code, (field, value, rc)
 
 
-def test_reserved_and_pair_count_limits(nat):
-    arr = _arr(nat)
-    arr[0].reserved = 1
-    assert _ws_size(nat, arr)[0] == -1
+def test_mask_schedule_and_pair_count_limits(nat):
+    for mask, code in ((0, 0), (1, 0), (2, -1), (-1, -1)):
+        arr = _arr(nat)
+        arr[0].auto_mask = mask
+        assert _ws_size(nat, arr)[0] == code, mask
     for sched, code in ((3, -1), (-1, -1), (34, -1), (41, -1), (0, 0), (1, 0), (2, 0), (4, 0), (8, 0), (12, 0),
                         (16, 0), (32, 0), (33, 0), (40, 0)):
         arr = _arr(nat)

@@ -301,6 +301,64 @@ def test_gradients_against_torch_fft_autograd(ref):
     np.testing.assert_allclose(h.grad.numpy(), gh, rtol=0, atol=1e-10 * np.abs(gh).max())
 
 
+def test_mainlobe_mask_against_torch_fft_autograd(ref):
+    """auto_mask = 1 (only the Doppler-mainlobe cells |nu| < 1 of an auto pair's
+    tau = 0 cut leave the region): loss, PSLs, peak and both gradients against
+    torch complex128 autograd through the FFT correlation of eq. 36, with the
+    grid and the mask built here (numpy linspace), not by the oracle."""
+    torch = pytest.importorskip("torch")
+    M, N, F = 3, 10, 11
+    s0, h0 = _rand_c((M, N), 54), _rand_c((M, N), 55)
+    # unimodular waveforms with h = s: the cut's cells at nu = +-1.5, +-2.5
+    # are Dirichlet sidelobes, larger than most delay sidelobes
+    s0 = np.exp(1j * np.angle(s0))
+    h0 = s0 + 0.1 * h0
+    prob = I.make_problem(M, N, 4, F, nu_min=-2.5, nu_max=2.5, p=6.0, w_snrl=0.5, auto_mask=1)
+    st, gs, gh = ref.evaluate(s0, h0, prob)
+    s = torch.tensor(s0, dtype=torch.complex128, requires_grad=True)
+    h = torch.tensor(h0, dtype=torch.complex128, requires_grad=True)
+    P = 32
+    nu_np = np.linspace(-2.5, 2.5, F)
+    nu = torch.tensor(nu_np)
+    n = torch.arange(N, dtype=torch.float64)
+    mod = torch.exp(2j * torch.pi * n[None, :] * nu[:, None] / N)
+    X = torch.fft.fft(s[:, None, :] * mod[None], n=P)
+    H = torch.fft.fft(h, n=P)
+    r = torch.fft.ifft(X[:, None, :, :] * torch.conj(H)[None, :, None, :])
+    tau = torch.arange(-(N - 1), N)
+    A = r[..., (-tau) % P]
+    a = A.abs() / N
+    mask = torch.ones_like(a, dtype=torch.bool)
+    main = torch.tensor(np.abs(nu_np) < 1.0)
+    assert int(main.sum()) == 3  # nu = -0.5, 0, 0.5
+    for m in range(M):
+        mask[m, m, main, N - 1] = False
+    lp = (a[mask] ** prob["p"]).sum() ** (1.0 / prob["p"])
+    c = (torch.conj(h) * s).sum(dim=1)
+    p_tar = 10 ** (-prob["snrl_target_db"] / 20)
+    loss = prob["w_psl"] * lp + prob["w_snrl"] * ((c.abs() / N - p_tar) ** 2).mean()
+    loss.backward()
+    assert abs(loss.item() - st["loss"]) < 1e-12
+    an = a.detach().numpy() * N
+    mk = mask.numpy()
+    auto = max(an[m, m][mk[m, m]].max() for m in range(M))
+    cross = max(an[m, l].max() for m in range(M) for l in range(M) if m != l)
+    assert abs(st["psl_auto"] - auto) < 1e-12 and abs(st["psl_cross"] - cross) < 1e-12
+    v = np.where(mk, an, -1.0)
+    m_, l_, f_, k_ = np.unravel_index(int(np.argmax(v)), v.shape)
+    assert tuple(st["arg"]) == (m_, l_, k_ - (N - 1), f_)
+    np.testing.assert_allclose(s.grad.numpy(), gs, rtol=0, atol=1e-10 * np.abs(gs).max())
+    np.testing.assert_allclose(h.grad.numpy(), gh, rtol=0, atol=1e-10 * np.abs(gh).max())
+    # the cut's Doppler sidelobes do enter: the paper's rule gives a smaller loss
+    st0 = ref.evaluate(s0, h0, dict(prob, auto_mask=0), False)[0]
+    assert st0["lp"] < st["lp"] - 1e-6
+    # a span inside the mainlobe: both rules select the same cells
+    inner = dict(prob, nu_min=-0.5, nu_max=0.5)
+    st1, gs1, gh1 = ref.evaluate(s0, h0, inner)
+    st2, gs2, gh2 = ref.evaluate(s0, h0, dict(inner, auto_mask=0))
+    assert st1["loss"] == st2["loss"] and np.array_equal(gs1, gs2) and np.array_equal(gh1, gh2)
+
+
 @pytest.mark.parametrize("mode", [I.PHASE_MEAN, I.PHASOR_MEAN])
 def test_logit_chain_central_differences(ref, mode):
     M, N, L, F = 2, 8, 4, 3

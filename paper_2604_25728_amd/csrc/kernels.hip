@@ -117,45 +117,72 @@ __device__ __forceinline__ void phasor_row(int t, double nu, double invN, float2
   }
 }
 
-// In-ROI scan of one AF row held as R[e] = P A(tau') at r-index k = t + TF e
-// (ROI cells: tau' = -k for k < N, P - k for k > P - N, inside [wlo, whi],
-// without tau' = 0 when auto_pair: an auto pair at a Doppler bin whose tau = 0
-// cell the problem's mask removes): the valid-cell mask and the lane's
-// largest |r|^2 with its lowest index.
-template <int P, int TF, int E>
-__device__ __forceinline__ void roi_scan(const float2 (&R)[E], int t, int N, int wlo, int whi, bool auto_pair,
-                                         uint32_t& vmask, float& qmax, int& kbest) {
-  vmask = 0;
+// The region-of-interest cells of one AF row held as R[e] = P A(tau') at
+// r-index k = t + TF e, as two runs of r-index: k in
+// [a0, a0 + na] holds tau' = -k (k <= N - 1), k in [b0, b0 + nb] holds tau' =
+// P - k (k >= P - N + 1), each clipped to [wlo, whi]; an empty run starts at
+// 2^30 with length 0, past every index. Cell k is inside when the unsigned
+// (k - a0) <= na or (k - b0) <= nb: the same for every partner of a unit.
+struct RoiRuns {
+  int a0, na, b0, nb;
+};
+template <int P>
+__device__ __forceinline__ RoiRuns roi_runs(int N, int wlo, int whi) {
+  RoiRuns r;
+  const int alo = max(0, -whi), ahi = min(N - 1, -wlo);
+  const int blo = max(P - N + 1, P - whi), bhi = min(P - 1, P - wlo);
+  r.a0 = alo <= ahi ? alo : (1 << 30);
+  r.na = alo <= ahi ? ahi - alo : 0;
+  r.b0 = blo <= bhi ? blo : (1 << 30);
+  r.nb = blo <= bhi ? bhi - blo : 0;
+  return r;
+}
+
+// The membership bits of lane t's cells k = t + TF e; with drop0 the cell
+// k = 0 (tau' = 0) is left out.
+template <int TF, int E>
+__device__ __forceinline__ uint32_t roi_bits(const RoiRuns& r, int t, bool drop0) {
+  uint32_t v = 0;
+  const int ta = t - r.a0, tb = t - r.b0;
+  static_for<E>([&](auto ec) {
+    constexpr int e = decltype(ec)::value;
+    const bool in = (uint32_t)(ta + TF * e) <= (uint32_t)r.na || (uint32_t)(tb + TF * e) <= (uint32_t)r.nb;
+    v |= in ? (1u << e) : 0u;
+  });
+  return drop0 && t == 0 ? v & ~1u : v;
+}
+
+// In-ROI scan of a row over the membership bits vmask: cells outside the
+// region are set to 0 (so that the scaling after it needs no mask), and the
+// lane's largest |r|^2 is found with its lowest index.
+template <int TF, int E>
+__device__ __forceinline__ void roi_scan_bits(float2 (&R)[E], int t, uint32_t vmask, float& qmax, int& kbest) {
   qmax = 0.f;
   kbest = 0;
   static_for<E>([&](auto ec) {
     constexpr int e = decltype(ec)::value;
-    const int k = t + TF * e;
-    const bool lo = k <= N - 1, hi = k >= P - N + 1;
-    const int tp = lo ? -k : P - k;
-    const bool valid = (lo || hi) && tp >= wlo && tp <= whi && !(auto_pair && tp == 0);
-    const float q = valid ? R[e].x * R[e].x + R[e].y * R[e].y : 0.f;
+    const bool valid = (vmask >> e) & 1u;
+    R[e] = valid ? R[e] : make_float2(0.f, 0.f);
+    const float q = R[e].x * R[e].x + R[e].y * R[e].y;
     const bool better = q > qmax;
     qmax = better ? q : qmax;
-    kbest = better ? k : kbest;
-    vmask |= valid ? (1u << e) : 0u;
+    kbest = better ? t + TF * e : kbest;
   });
 }
 
-// S += sum over valid cells of x^(p/2), x = |r|^2 / sigma^2, and the scaled
-// adjoint r <- x^(p/2 - 1) r / sigma on valid cells, 0 elsewhere.
+// S += sum over the cells of x^(p/2), x = |r|^2 / sigma^2, and the scaled
+// adjoint r <- x^(p/2 - 1) r / sigma. Cells outside the region hold 0 (from
+// roi_scan_bits): they add 0 and stay 0 for every p.
 template <int PHLOG, int E>
-__device__ __forceinline__ void roi_scale(float2 (&R)[E], uint32_t vmask, float inv_s, float phm1, float& S) {
+__device__ __forceinline__ void roi_scale(float2 (&R)[E], float inv_s, float phm1, float& S) {
   const float inv_s2 = inv_s * inv_s;
   static_for<E>([&](auto ec) {
     constexpr int e = decltype(ec)::value;
-    const bool valid = (vmask >> e) & 1u;
-    const float x = valid ? (R[e].x * R[e].x + R[e].y * R[e].y) * inv_s2 : 0.f;
+    const float x = (R[e].x * R[e].x + R[e].y * R[e].y) * inv_s2;
     float ym1, y;
     pow_ph<PHLOG>(x, phm1, ym1, y);
-    S += valid ? y : 0.f;
-    const float sc = valid ? ym1 * inv_s : 0.f;
-    R[e] = cscale(R[e], sc);
+    S += y;
+    R[e] = cscale(R[e], ym1 * inv_s);
   });
 }
 
@@ -703,6 +730,8 @@ __device__ __forceinline__ void pass_block(const PassArgs& a, int blk, PassSmem<
   }
   float sigma = 0.f, S = 0.f;
   unsigned long long kauto = 0, kcross = 0;  // per lane; reduced once per unit
+  const RoiRuns runs = roi_runs<P>(N, wlo, whi);
+  const bool cut0 = f >= pl.cut_lo && f < pl.cut_hi;  // the auto pair drops its tau = 0 cell
   int g = 0;
   const float2* sg = spec;
   auto start_pair = [&]() {  // R = X conj(H_g)
@@ -759,7 +788,8 @@ __device__ __forceinline__ void pass_block(const PassArgs& a, int blk, PassSmem<
     int kbest;
     if (cube != nullptr && active) cube_store<P, TF, E>(R, t, N, cube + ((int64_t)(w * M + g) * F + f) * T2);
     if constexpr (WT) roi_weigh<P, TF, E>(R, t, N, a.orient, wrow);  // a = w |A| / N from here on
-    roi_scan<P, TF, E>(R, t, N, wlo, whi, g == w && f >= pl.cut_lo && f < pl.cut_hi, vmask, qmax, kbest);
+    vmask = roi_bits<TF, E>(runs, t, g == w && cut0);
+    roi_scan_bits<TF, E>(R, t, vmask, qmax, kbest);
     // this lane's largest cell of the pair (lowest index among equal values)
     const unsigned long long key = vmask ? make_key(qmax, (uint32_t)(((int64_t)u * M + g) * P + kbest)) : 0ull;
     if (g == w) kauto = umax64(kauto, key);
@@ -782,7 +812,7 @@ __device__ __forceinline__ void pass_block(const PassArgs& a, int blk, PassSmem<
     // a/sigma = x^(1/2), x = |r|^2 / sigma^2:  S += x^(p/2);  G~ = x^(p/2 - 1) r / sigma
     // v_rcp (1 ulp) suffices for the inverse scale: every partial sum and
     // gradient partial of the unit is taken relative to the same scale
-    roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? __builtin_amdgcn_rcpf(sigma) : 0.f, phm1, S);
+    roi_scale<PHLOG, E>(R, sigma > 0.f ? __builtin_amdgcn_rcpf(sigma) : 0.f, phm1, S);
     if constexpr (WT) roi_weigh<P, TF, E>(R, t, N, a.orient, wrow);  // d(w|r|)^p / dr carries w^2
     if (grad) {
       op = OP_ADJ;
@@ -2740,7 +2770,8 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   if (a.cube != nullptr && active)
     cube_store<P, 64, E>(R, t, N, a.cube + pl.off_cube + ((int64_t)(w * M + g) * F + f) * (2 * N - 1));
   if constexpr (WT) roi_weigh_reg<E>(R, WR);  // a = w |A| / N from here on
-  roi_scan<P, 64, E>(R, t, N, wlo, whi, g == w && f >= pl.cut_lo && f < pl.cut_hi, vmask, qmax, kbest);
+  vmask = roi_bits<64, E>(roi_runs<P>(N, wlo, whi), t, g == w && f >= pl.cut_lo && f < pl.cut_hi);
+  roi_scan_bits<64, E>(R, t, vmask, qmax, kbest);
   // wave maximum, and its cell from the lowest lane that holds it
   const float qw = wave_max(qmax);
   const unsigned long long holders = __ballot(vmask != 0 && qmax == qw);
@@ -2749,7 +2780,7 @@ __global__ __launch_bounds__(64 * WV) void k_pass_split(PassArgs a) {
   const unsigned long long key = holders ? make_key(qw, (uint32_t)(((int64_t)u * M + g) * P + kb)) : 0ull;
   const float sigma = sqrtf(qw);
   float S = 0.f;
-  roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? __builtin_amdgcn_rcpf(sigma) : 0.f, phm1, S);
+  roi_scale<PHLOG, E>(R, sigma > 0.f ? __builtin_amdgcn_rcpf(sigma) : 0.f, phm1, S);
   if constexpr (WT) roi_weigh_reg<E>(R, WR);  // d(w|r|)^p / dr carries w^2
   S = wave_sum(S);
   if (t == 0) {
@@ -2942,13 +2973,14 @@ __global__ __launch_bounds__(64 * PassGeom<P>::WAVES, 4) void k_pass_pair(PassAr
   uint32_t vmask;
   float qmax;
   int kbest;
-  roi_scan<P, TF, E>(R, t, N, wlo, whi, g == w && f >= pl.cut_lo && f < pl.cut_hi, vmask, qmax, kbest);
+  vmask = roi_bits<TF, E>(roi_runs<P>(N, wlo, whi), t, g == w && f >= pl.cut_lo && f < pl.cut_hi);
+  roi_scan_bits<TF, E>(R, t, vmask, qmax, kbest);
   unsigned long long key = vmask ? make_key(qmax, (uint32_t)(((int64_t)u * M + g) * P + kbest)) : 0ull;
   key = fft_lanes_max_key<G>(key, red_k);
   qmax = fft_lanes_reduce<G>(qmax, 0.0f, OpMax(), red_f);
   const float sigma = sqrtf(qmax);
   float S = 0.f;
-  roi_scale<PHLOG, E>(R, vmask, sigma > 0.f ? __builtin_amdgcn_rcpf(sigma) : 0.f, phm1, S);
+  roi_scale<PHLOG, E>(R, sigma > 0.f ? __builtin_amdgcn_rcpf(sigma) : 0.f, phm1, S);
   if constexpr (WT) roi_weigh_reg<E>(R, WR);  // d(w|r|)^p / dr carries w^2
   S = fft_lanes_reduce<G>(S, 0.0f, OpAdd(), red_f);
   const int64_t ent = (int64_t)w * pl.wpr + rem;

@@ -337,13 +337,16 @@ __device__ __forceinline__ int spec_slot(const ProbPlan& pl, int t, int e) {
 // Reductions over the lanes of one FFT of geometry G, the result in all of
 // them; a transform spread over several waves combines the waves' values
 // through red[] (one entry per wave of the block) in wave order.
-template <class G, class Op>
+// kLead = false drops the barrier that orders the previous reads of red[]
+// before the new writes: for callers whose every wave has passed a block
+// barrier since it last read red[] (a multi-wave transform's exchanges are).
+template <class G, class Op, bool kLead = true>
 __device__ __forceinline__ float fft_lanes_reduce(float v, float ident, Op op, float* red) {
   if constexpr (G::WAVES == 1) {
     return slot_reduce<G::TF>(v, ident, op);
   } else {
     v = slot_reduce<64>(v, ident, op);
-    block_lds_sync();
+    if constexpr (kLead) block_lds_sync();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     block_lds_sync();
     const int w0 = (threadIdx.x / G::TF) * G::WAVES;
@@ -794,7 +797,9 @@ __device__ __forceinline__ void pass_block(const PassArgs& a, int blk, PassSmem<
     const unsigned long long key = vmask ? make_key(qmax, (uint32_t)(((int64_t)u * M + g) * P + kbest)) : 0ull;
     if (g == w) kauto = umax64(kauto, key);
     else kcross = umax64(kcross, key);
-    qmax = fft_lanes_reduce<G>(qmax, 0.0f, OpMax(), red_f);
+    // every wave has passed this pair's inverse transform (block barriers
+    // between its exchanges) since the previous pair's reduction read red_f
+    qmax = fft_lanes_reduce<G, OpMax, false>(qmax, 0.0f, OpMax(), red_f);
     const float mu = sqrtf(qmax);
     if (mu > sigma) {  // new running scale: rescale the partial sums (online max)
       const float c = sigma / mu;

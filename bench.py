@@ -39,7 +39,8 @@ COPY_BYTES = 1 << 28              # calibration copy of the counter runs: 256 Mi
 # HBM traffic of the dominant fused-pass kernel from the committed counter
 # summaries (two rocprofv3 --pmc passes each), per workload
 TRAFFIC_FILES = {"uneven": os.path.join(ROOT, "profiles", "k_pass_2048_uneven_64x8_traffic.md"),
-                 "m4n256": os.path.join(ROOT, "profiles", "k_pass_split_m4n256_traffic.md")}
+                 "m4n256": os.path.join(ROOT, "profiles", "k_pass_split_m4n256_traffic.md"),
+                 "wide_m8n1024": os.path.join(ROOT, "profiles", "k_pass_2048_wide_m8n1024_traffic.md")}
 
 
 def log(*a):

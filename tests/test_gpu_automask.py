@@ -92,3 +92,28 @@ def test_mask_value_is_validated(nat):
     prob = dict(SHAPES["p256_throughput"], auto_mask=2)
     with pytest.raises(nat.SQNGDError):
         nat.Batch([prob])
+
+
+@pytest.mark.parametrize("N", [100, 600])
+def test_mainlobe_mask_teacher_forced_step(ref, nat, N):
+    """Optimiser steps on the masked loss (k_step at FFT length 256, k_grad +
+    k_step2 at 2048): from the GPU state at iteration t, one oracle iteration
+    of Algorithm 1 under auto_mask = 1 matches the GPU's."""
+    from paper_2604_25728_amd import optim
+    prob = _shape(2, N, 11, -2.5, 2.5)
+    opt = I.make_opt(total_iters=100, T0=1.0, T1=0.5)
+    print(f"[gpu] auto_mask=1 teacher-forced step N={N}", flush=True)
+    run = optim.SQNGD([prob], opt, seeds=[0])
+    for _ in range(2):
+        run.step()
+    torch.cuda.synchronize()
+    s0 = run.numpy_state(0)
+    run.step()
+    torch.cuda.synchronize()
+    s1 = run.numpy_state(0)
+    sa, sb = run.step_stats()
+    z, h, state, sta, stb = ref.step(prob, opt, s0["z"], s0["h"], s0["state"], s0["t"])
+    assert _rel(s1["h"], h) <= 1e-4 and _rel(s1["z"], z) <= 1e-4
+    assert abs(sa[0]["loss"] - sta["loss"]) <= 1e-4 * sta["loss"]
+    assert abs(sb[0]["loss"] - stb["loss"]) <= 1e-4 * stb["loss"]
+    assert abs(sa[0]["pslr_db"] - sta["pslr_db"]) <= 0.05

@@ -40,3 +40,13 @@ def test_designs_are_independent_and_ids_are_global():
         r.update([1], [-9.0])                 # a stopped design takes no further checkpoints
     with pytest.raises(ValueError):
         StopRule(1, patience=0)
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No fallback: with libsqngd.so absent the binding raises instead of
+    computing anything another way."""
+    from paper_2604_25728_amd import native
+    monkeypatch.setattr(native, "LIB_PATH", str(tmp_path / "libsqngd.so"))
+    monkeypatch.setattr(native, "_lib", None)
+    with pytest.raises(native.SQNGDError, match="is missing"):
+        native.load()
